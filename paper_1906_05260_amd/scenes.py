@@ -1,0 +1,251 @@
+"""Seeded synthetic scene generators (inputs only).
+
+This module builds the host-side scene descriptions and skinning meshes that
+both the GPU library and the oracle consume.  It holds none of the solver's
+arithmetic: only rest geometry, per-rod parameters and random draws.  The
+paper's own assets (octopus, anatomical muscles, elastic band; Sec. 7-8) are
+not available, so these seeded scenes stand in for them with the shapes and
+sizes of the paper's workloads.
+
+All lengths are metres, compliances Pa^-1, density kg/m^3.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+DENSITY = 1000.0               # muscle is mostly water (Sec. 1)
+GRAVITY = (0.0, -9.81, 0.0)
+
+
+@dataclass
+class SceneDesc:
+    """Host description of a rod scene (one entry per pill / rod)."""
+    rod_offsets: np.ndarray            # int32 [R+1]
+    rest_pos: np.ndarray               # float64 [P,3]
+    rest_radius: np.ndarray            # float64 [P]
+    pinned: np.ndarray                 # uint8 [P]
+    activation: np.ndarray             # float64 [R]
+    compliance: np.ndarray             # float64 [R,4]: stretch-shear, volume, scale-gradient, bend-twist
+    group: np.ndarray                  # int32 [R]
+    density: float = DENSITY
+    gravity: tuple = GRAVITY
+    collisions: bool = False
+    name: str = ""
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def num_rods(self) -> int:
+        return int(self.rod_offsets.shape[0] - 1)
+
+    @property
+    def num_pills(self) -> int:
+        return int(self.rod_offsets[-1])
+
+    def subset(self, rods) -> "SceneDesc":
+        """Scene made of the given rods only (rods are independent without contacts)."""
+        rods = np.asarray(rods, dtype=np.int64)
+        offs = [0]
+        idx = []
+        for k in rods:
+            a, b = int(self.rod_offsets[k]), int(self.rod_offsets[k + 1])
+            idx.append(np.arange(a, b))
+            offs.append(offs[-1] + b - a)
+        idx = np.concatenate(idx)
+        return SceneDesc(np.asarray(offs, np.int32), self.rest_pos[idx].copy(), self.rest_radius[idx].copy(),
+                         self.pinned[idx].copy(), self.activation[rods].copy(), self.compliance[rods].copy(),
+                         self.group[rods].copy(), self.density, self.gravity, self.collisions,
+                         self.name + "[subset]")
+
+    def pill_index(self, rods):
+        return np.concatenate([np.arange(self.rod_offsets[k], self.rod_offsets[k + 1]) for k in rods])
+
+
+@dataclass
+class SkinMesh:
+    rest_v: np.ndarray     # float32 [V,3]
+    caps: np.ndarray       # int32 [V,4]  capsule id = global index of the capsule's first pill
+    w: np.ndarray          # float32 [V,4], rows sum to 1
+
+
+def _log_uniform(rng, lo, hi, size):
+    return np.exp(rng.uniform(np.log(lo), np.log(hi), size))
+
+
+def straight_rod(n_pills=32, spacing=0.01, radius=0.005, compliance=1e-6) -> SceneDesc:
+    """One straight rod along +x, pill 0 pinned (the 32-pill FP64 single-rod case)."""
+    x = np.zeros((n_pills, 3))
+    x[:, 0] = spacing * np.arange(n_pills)
+    pinned = np.zeros(n_pills, np.uint8)
+    pinned[0] = 1
+    return SceneDesc(np.asarray([0, n_pills], np.int32), x, np.full(n_pills, radius), pinned,
+                     np.ones(1), np.full((1, 4), compliance), np.zeros(1, np.int32), name="single_rod_%d" % n_pills)
+
+
+def helix_rods(num_rods=4096, n_pills=64, seed=1, grid_spacing=0.1, arc=0.01) -> SceneDesc:
+    """Independent random helices along +x on a square grid, pill 0 pinned.
+
+    Helix radius U[0.5,2] cm, pitch U[1,4] cm, pills 1 cm apart in arc length,
+    pill radii U[0.2,0.8] cm, compliances log-uniform 1e-8..1e-4 per type and rod.
+    """
+    rng = np.random.default_rng(seed)
+    side = int(np.ceil(np.sqrt(num_rods)))
+    R = rng.uniform(0.005, 0.02, num_rods)
+    pitch = rng.uniform(0.01, 0.04, num_rods)
+    rbar = rng.uniform(0.002, 0.008, num_rods * n_pills)
+    comp = _log_uniform(rng, 1e-8, 1e-4, (num_rods, 4))
+    phase = rng.uniform(0, 2 * np.pi, num_rods)
+    k = np.arange(num_rods)
+    gy = (k // side) * grid_spacing
+    gz = (k % side) * grid_spacing
+    c = pitch / (2 * np.pi)
+    dt = arc / np.sqrt(R ** 2 + c ** 2)
+    t = dt[:, None] * np.arange(n_pills)[None, :]
+    x = np.empty((num_rods, n_pills, 3))
+    x[:, :, 0] = c[:, None] * t
+    x[:, :, 1] = gy[:, None] + R[:, None] * np.cos(t + phase[:, None])
+    x[:, :, 2] = gz[:, None] + R[:, None] * np.sin(t + phase[:, None])
+    pinned = np.zeros((num_rods, n_pills), np.uint8)
+    pinned[:, 0] = 1
+    offs = np.arange(num_rods + 1, dtype=np.int32) * n_pills
+    return SceneDesc(offs, x.reshape(-1, 3), rbar, pinned.reshape(-1), np.ones(num_rods), comp,
+                     np.arange(num_rods, dtype=np.int32), name="helix_%dx%d" % (num_rods, n_pills))
+
+
+def straight_rods(num_rods=1024, n_pills=32, seed=4, grid_spacing=0.1):
+    """Straight rods along +x (1 cm spacing), random radii, compliances and activations,
+    plus per-rod targets near the free end (the differentiation workload)."""
+    rng = np.random.default_rng(seed)
+    side = int(np.ceil(np.sqrt(num_rods)))
+    rbar = rng.uniform(0.002, 0.008, num_rods * n_pills)
+    comp = _log_uniform(rng, 1e-8, 1e-4, (num_rods, 4))
+    act = rng.uniform(0.8, 1.2, num_rods)
+    k = np.arange(num_rods)
+    x = np.zeros((num_rods, n_pills, 3))
+    x[:, :, 0] = 0.01 * np.arange(n_pills)[None, :]
+    x[:, :, 1] = ((k // side) * grid_spacing)[:, None]
+    x[:, :, 2] = ((k % side) * grid_spacing)[:, None]
+    pinned = np.zeros((num_rods, n_pills), np.uint8)
+    pinned[:, 0] = 1
+    offs = np.arange(num_rods + 1, dtype=np.int32) * n_pills
+    desc = SceneDesc(offs, x.reshape(-1, 3), rbar, pinned.reshape(-1), act, comp,
+                     np.arange(num_rods, dtype=np.int32), name="straight_%dx%d" % (num_rods, n_pills))
+    targets = x[:, -1, :] + rng.normal(0.0, 0.01, (num_rods, 3))
+    return desc, targets
+
+
+def _vogel_disc(n, radius):
+    i = np.arange(n) + 0.5
+    r = radius * np.sqrt(i / n)
+    th = i * np.pi * (3.0 - np.sqrt(5.0))
+    return np.stack([r * np.cos(th), r * np.sin(th)], axis=1)
+
+
+def muscle_scene(num_muscles=64, seed=2, target_pills=(45000, 55000), rods_range=(16, 48), pills_range=(8, 24),
+                 mesh_vertices=200000, spacing=0.01):
+    """Bundles of parallel rods ("muscles") packed side by side so that neighbours touch.
+
+    Each muscle has U{16..48} rods of U{8..24} pills (all rods of a muscle share the
+    pill count, so its cross-sections are aligned).  Sizes are then grown one unit at
+    a time at random muscles until the total lies in ``target_pills`` (the plain
+    draws average ~33k pills; the workload asks for ~50k).  Both rod ends are
+    pinned (bone attachments), activation U[0.8,1.2] per muscle, collision group =
+    muscle.  Returns (desc, mesh) with a skinning mesh of ``mesh_vertices`` vertices
+    on the muscles' envelopes, 4 nearest capsules each, Dirichlet(1,1,1,1) weights.
+    """
+    rng = np.random.default_rng(seed)
+    nr = rng.integers(rods_range[0], rods_range[1] + 1, num_muscles)
+    npl = rng.integers(pills_range[0], pills_range[1] + 1, num_muscles)
+    lo, hi = target_pills
+    if target_pills is not None:
+        while int((nr * npl).sum()) < lo:
+            m = int(rng.integers(num_muscles))
+            if rng.random() < 0.5 and nr[m] < rods_range[1]:
+                nr[m] += 1
+            elif npl[m] < pills_range[1]:
+                npl[m] += 1
+        assert int((nr * npl).sum()) <= hi
+    act = rng.uniform(0.8, 1.2, num_muscles)
+    side = int(np.ceil(np.sqrt(num_muscles)))
+    # per-muscle rod radii and bundle radius
+    xs, rbs, pins, acts, comps, groups, offs = [], [], [], [], [], [], [0]
+    muscle_info = []
+    rmax = 0.008
+    bundle_r = 1.2 * np.sqrt(nr) * 0.005
+    cell = 2.0 * bundle_r.max()
+    for m in range(num_muscles):
+        gy = (m // side) * cell
+        gz = (m % side) * cell
+        centres = _vogel_disc(int(nr[m]), bundle_r[m] - rmax)
+        L = (npl[m] - 1) * spacing
+        x0 = -0.5 * L
+        tilt = rng.normal(0.0, 0.02, 2)
+        rod_ids = []
+        for r in range(int(nr[m])):
+            n = int(npl[m])
+            x = np.zeros((n, 3))
+            x[:, 0] = x0 + spacing * np.arange(n)
+            x[:, 1] = gy + centres[r, 0] + tilt[0] * x[:, 0]
+            x[:, 2] = gz + centres[r, 1] + tilt[1] * x[:, 0]
+            xs.append(x)
+            rbs.append(rng.uniform(0.002, 0.008, n))
+            pn = np.zeros(n, np.uint8)
+            pn[0] = 1
+            pn[-1] = 1
+            pins.append(pn)
+            acts.append(act[m])
+            comps.append(_log_uniform(rng, 1e-8, 1e-4, 4))
+            groups.append(m)
+            rod_ids.append(len(offs) - 1)
+            offs.append(offs[-1] + n)
+        muscle_info.append(dict(rods=rod_ids, centre=(gy, gz), radius=bundle_r[m], x0=x0, L=L, tilt=tilt))
+    desc = SceneDesc(np.asarray(offs, np.int32), np.concatenate(xs), np.concatenate(rbs), np.concatenate(pins),
+                     np.asarray(acts), np.asarray(comps), np.asarray(groups, np.int32), collisions=True,
+                     name="muscles_%d" % num_muscles)
+    mesh = muscle_mesh(desc, muscle_info, mesh_vertices, rng) if mesh_vertices else None
+    desc.extra["muscles"] = muscle_info
+    return desc, mesh
+
+
+def muscle_mesh(desc: SceneDesc, muscle_info, V, rng) -> SkinMesh:
+    """Vertices on each muscle's envelope cylinder (count proportional to its pills);
+    influences = the 4 nearest capsules of that muscle at rest, Dirichlet(1,1,1,1) weights."""
+    offs = desc.rod_offsets
+    pills = np.array([sum(int(offs[k + 1] - offs[k]) for k in mi["rods"]) for mi in muscle_info], dtype=np.float64)
+    counts = np.floor(V * pills / pills.sum()).astype(np.int64)
+    counts[: V - int(counts.sum())] += 1
+    rv, cp, ww = [], [], []
+    for m, mi in enumerate(muscle_info):
+        nv = int(counts[m])
+        if nv == 0:
+            continue
+        caps = np.concatenate([np.arange(offs[k], offs[k + 1] - 1) for k in mi["rods"]])
+        mids = 0.5 * (desc.rest_pos[caps] + desc.rest_pos[caps + 1])
+        u = rng.uniform(0.0, 1.0, nv)
+        th = rng.uniform(0.0, 2 * np.pi, nv)
+        xx = mi["x0"] + u * mi["L"]
+        rr = mi["radius"] + 0.004
+        p = np.stack([xx, mi["centre"][0] + mi["tilt"][0] * xx + rr * np.cos(th),
+                      mi["centre"][1] + mi["tilt"][1] * xx + rr * np.sin(th)], axis=1)
+        for c0 in range(0, nv, 4096):
+            pc = p[c0:c0 + 4096]
+            d2 = ((pc[:, None, :] - mids[None, :, :]) ** 2).sum(-1)
+            nn = np.argsort(d2, axis=1, kind="stable")[:, :4]
+            cp.append(caps[nn])
+        rv.append(p)
+        ww.append(rng.dirichlet(np.ones(4), nv))
+    return SkinMesh(np.concatenate(rv).astype(np.float32), np.concatenate(cp).astype(np.int32),
+                    np.concatenate(ww).astype(np.float32))
+
+
+def scene_of_size(n_pills: int, kind: str, seed: int):
+    """A serving request: helix rods of 64 pills or a muscle scene, about n_pills pills.
+    Returns (desc, mesh or None)."""
+    if kind == "helix":
+        nrods = max(1, int(round(n_pills / 64)))
+        return helix_rods(nrods, 64, seed=seed), None
+    nm = max(1, int(round(n_pills / 512)))
+    desc, mesh = muscle_scene(num_muscles=nm, seed=seed, target_pills=None, mesh_vertices=4 * n_pills)
+    return desc, mesh
