@@ -1,0 +1,165 @@
+#!/usr/bin/env python3
+"""Benchmark: pill-constraint projections per second of the VIPER rod substep on one MI355X.
+
+Workload: 4096 independent rods x 64 pills (random helices, FP32), 20 substeps x 8
+iterations per frame, collision-free; one "step" = one frame of the whole solver
+(prediction, 8 x four colour passes of stretch-shear / volume / scale-gradient /
+bend-twist projections, velocity update) for all rods.  Inputs are resident in HBM
+before timing starts; the timed region holds exactly K frames between
+synchronisations.
+
+Prints one JSON line with the throughput, a roofline object for the dominant kernel
+(timed per launch with HIP events on the launch stream) and the oracle timed on the
+host cores on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# FLOPs per projection / per pill-substep, counted from the closed-form updates in
+# csrc/rod_kernels.hip (add, sub, mul, div, sqrt, rsqrt = 1 each; a fused
+# multiply-add counts as its multiply and its add).
+FLOP = {"ss": 116, "vol": 53, "sg": 16, "bt": 337, "predict": 59, "velocity": 42}
+# Bytes one frame launch moves per pill (FP32): state 15 words read + written,
+# 13 rest words and one flag word read.
+BYTES_PER_PILL_LAUNCH = 4 * (15 + 15 + 13 + 1)
+PEAK_FP32_VALU = 78.6e12     # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz, packed FP32 disabled
+PEAK_HBM = 8.0e12
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("rod_kernels.hip", "viper_dev.h"):
+        with open(os.path.join(ROOT, "paper_1906_05260_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
+    taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_counters.json" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(desc, dt, sub, iters, rods):
+    import oracle
+    sample = desc.subset(range(rods))
+    o = oracle.OracleScene(sample, "f64")
+    t0 = time.perf_counter()
+    n = o.step(dt, sub, iters, threads=1)
+    el = time.perf_counter() - t0
+    return {"value": n / el, "unit": "projections/s", "cores": 1, "kind": "oracle",
+            "sample": "%d of %d rods, 1 frame (%d substeps x %d iterations), serial FP64" %
+                      (rods, desc.num_rods, sub, iters)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--rods", type=int, default=4096)
+    ap.add_argument("--pills", type=int, default=64)
+    ap.add_argument("--substeps", type=int, default=20)
+    ap.add_argument("--iters", type=int, default=8)
+    ap.add_argument("--mode", default="frame", choices=["frame", "substep"])
+    ap.add_argument("--cpu-rods", type=int, default=1024)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the solver runs on a single MI355X "
+              "(rods and scenes are independent; see the sharding note in the design document)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1906_05260_amd import scenes, viper
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    dt, sub, iters = 1.0 / 60.0, args.substeps, args.iters
+    desc = scenes.helix_rods(args.rods, args.pills, seed=1)
+    sc = viper.Scene(desc, "f32", device=dev)
+    mode = viper.MODE_FRAME if args.mode == "frame" else viper.MODE_SUBSTEP
+    for _ in range(args.warmup):
+        sc.step(dt, sub, iters, mode=mode)
+    sc.sync()
+    stream = torch.cuda.current_stream()
+    K = args.steps
+    launches = K if mode == viper.MODE_FRAME else K * sub
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(launches)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K):
+        if mode == viper.MODE_FRAME:
+            ev[k][0].record(stream)
+            sc.step(dt, sub, iters, mode=mode)
+            ev[k][1].record(stream)
+        else:
+            for j in range(sub):
+                e = ev[k * sub + j]
+                e[0].record(stream)
+                sc.step(dt / sub, 1, iters, mode=mode)
+                e[1].record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    sc.sync()
+    kern_ms = sum(a.elapsed_time(b) for a, b in ev) / launches
+
+    P = desc.num_pills
+    edges = P - desc.num_rods
+    bts = P - 2 * desc.num_rods
+    proj_per_frame = sc.projections_per_iteration * iters * sub
+    value = proj_per_frame * K / elapsed
+    flop_sub = iters * (edges * (FLOP["ss"] + FLOP["vol"] + FLOP["sg"]) + bts * FLOP["bt"]) + \
+        P * (FLOP["predict"] + FLOP["velocity"])
+    flop_launch = flop_sub * (sub if mode == viper.MODE_FRAME else 1)
+    bytes_launch = BYTES_PER_PILL_LAUNCH * P
+    achieved = flop_launch / (kern_ms * 1e-3)
+    workload = "helix%dx%d" % (args.rods, args.pills)
+    kname = "rod_frame_kernel"
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_VALU, "traffic": measured_traffic(kname + ("" if mode == viper.MODE_FRAME
+                                                                                 else "_substep"), workload),
+            "kernel": kname, "kernel_ms": kern_ms, "flop_per_launch": flop_launch,
+            "algorithmic_bytes_per_launch": bytes_launch,
+            "algorithmic_hbm_frac": bytes_launch / (kern_ms * 1e-3) / PEAK_HBM}
+    out = {
+        "metric": "pill-constraint projections/sec at fixed iters",
+        "value": value,
+        "unit": "projections/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded random helices)",
+        "config": {"workload": workload, "rods": args.rods, "pills_per_rod": args.pills, "substeps": sub,
+                   "iterations": iters, "frames_timed": K, "collisions": False, "launch": args.mode,
+                   "pill_substeps_per_s": P * sub * K / elapsed},
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(desc, dt, sub, iters, min(args.cpu_rods, desc.num_rods))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

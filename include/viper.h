@@ -1,0 +1,146 @@
+/*
+ * viper.h -- C ABI of the MI355X VIPER rod-solver library (libviper.so).
+ *
+ * The library advances many volume-invariant elastic rods ("VIPER" rods,
+ * Angles et al. 2019) with the position-based substep of Sec. 6: inertial
+ * prediction, coloured Gauss-Seidel projection of the stretch-shear,
+ * volume, scale-gradient and bend-twist constraints (Sec. 5, Sec. 7.5),
+ * pill-pill contacts (Sec. 7.1-7.2) and a velocity update; plus linear-blend
+ * skinning of a mesh onto the rods (Sec. 7.4).
+ *
+ * Conventions (all entry points):
+ *   - Every call returns a viper_status; no C++ exception crosses the ABI.
+ *     On failure viper_last_error() returns a thread-local message.
+ *   - The library never allocates device memory.  The caller allocates one
+ *     device workspace of viper_scene_footprint() bytes (any allocator; the
+ *     Python binding uses a torch uint8 tensor), keeps it alive and
+ *     unmodified until viper_destroy_scene(), and owns it afterwards.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Kernels and
+ *     copies are enqueued asynchronously on it; device-side conditions
+ *     (non-finite state, contact-buffer overflow) surface at viper_sync().
+ *   - Host description arrays are read only during the call that takes them.
+ *   - Indices: pills (vertices) are numbered globally in rod order; rod k owns
+ *     pills [rod_offsets[k], rod_offsets[k+1]).  Edge j of a rod joins its pills
+ *     j and j+1 and is stored in the slot of pill j (the last slot of a rod has
+ *     no edge).  A capsule (the paper's tapered "pill" primitive, Sec. 7) is an
+ *     edge; its id is the global index of its first pill.
+ */
+#ifndef VIPER_H
+#define VIPER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct viper_scene_s* viper_scene;
+
+typedef enum {
+  VIPER_OK = 0,
+  VIPER_ERR_INVALID = 1,      /* bad argument or scene description (nothing enqueued) */
+  VIPER_ERR_NO_CAPACITY = 2,  /* workspace / pool too small */
+  VIPER_ERR_CAPACITY = 3,     /* contact buffer overflowed during a step (reported by viper_sync) */
+  VIPER_ERR_NAN = 4,          /* non-finite state detected (reported by viper_sync) */
+  VIPER_ERR_DEVICE = 5        /* a HIP runtime call failed */
+} viper_status;
+
+typedef enum { VIPER_F32 = 0, VIPER_F64 = 1 } viper_precision;
+
+/* Scene description.  Physical inputs of the problem as the paper states it:
+ * rest centre line and rest radius r (Sec. 3, eq. rest_parametrization), mass
+ * density m (Sec. 4), per-type material compliances = inverse stiffnesses K^-1
+ * (Sec. 5/6), external gravity (Sec. 4, prediction), kinematic pins (Sec. 7),
+ * fibre activation as a rest-length scale (Sec. 8, muscle simulation) and
+ * collision groups (intra-muscle collisions disabled, Sec. 8). */
+typedef struct {
+  int32_t num_rods;
+  const int32_t* rod_offsets;   /* [num_rods+1], increasing, 2 <= pills per rod <= 64 */
+  const double* rest_pos;       /* [P*3] rest vertex positions, m; consecutive pills distinct */
+  const double* rest_radius;    /* [P] rest radius r, m, > 0 */
+  const uint8_t* pinned;        /* [P] nonzero = position fixed (scale, rotation stay free); may be NULL */
+  const double* activation;     /* [num_rods] > 0, scales the stretch rest length; may be NULL (= 1) */
+  const double* compliance;     /* [num_rods*4] Pa^-1 for stretch-shear, volume, scale-gradient,
+                                   bend-twist; >= 0; +inf disables that constraint type for the rod */
+  const int32_t* group;         /* [num_rods] collision group; equal groups never collide; may be NULL */
+  double density;               /* kg/m^3, > 0 */
+  double gravity[3];            /* m/s^2 */
+  int32_t precision;            /* viper_precision: storage and arithmetic type on the device */
+  int32_t collisions;           /* nonzero = pill-pill contacts on */
+  int32_t contact_capacity_per_capsule; /* candidate pairs per capsule reserved (<= 0: 16) */
+} viper_scene_desc;
+
+/* Bytes of device workspace the scene needs (host-only computation; validates the
+ * description).  The workspace must be 256-byte aligned. */
+viper_status viper_scene_footprint(const viper_scene_desc* desc, size_t* bytes);
+
+/* Validate the description, compute rest quantities on the host (rest lengths,
+ * parallel-transported rest frames, rest Darboux vectors, lumped inverse masses and
+ * inertias, compliance scalings) and upload them with the initial state (at rest) into
+ * `workspace` on `stream`.  The returned handle is owned by the caller and released
+ * with viper_destroy_scene(). */
+viper_status viper_create_scene(const viper_scene_desc* desc, void* workspace, size_t bytes, void* stream,
+                                viper_scene* out);
+
+/* Execution strategy for viper_step_ex. */
+typedef enum {
+  VIPER_MODE_AUTO = 0,     /* FRAME without collisions, ITERATION with */
+  VIPER_MODE_FRAME = 1,    /* one launch per call: all substeps with the rod state in registers */
+  VIPER_MODE_SUBSTEP = 2,  /* one launch per substep: state streamed through HBM every substep */
+  VIPER_MODE_ITERATION = 3 /* separate launches per stage and iteration (the contact path) */
+} viper_mode;
+
+/* Advance one frame of length dt (s) in `substeps` substeps of h = dt/substeps, each with
+ * `iterations` constraint iterations (Sec. 6: prediction, then per-constraint dual
+ * updates with lambda reset to 0 each substep, relaxation 1).  dt > 0, substeps >= 1,
+ * iterations >= 0. */
+viper_status viper_step(viper_scene scene, double dt, int32_t substeps, int32_t iterations, void* stream);
+viper_status viper_step_ex(viper_scene scene, double dt, int32_t substeps, int32_t iterations, int32_t mode,
+                           void* stream);
+
+/* State fields for get/set.  Arrays are in the scene's precision (float or double),
+ * pill-major: X, V: [P*3]; S (scale), SDOT: [P]; Q (edge quaternion x,y,z,w), [P*4];
+ * OMEGA (edge angular velocity, world frame) [P*3]; RADIUS (physical radius s*r) [P];
+ * XDET, SDET: positions/scales the last contact detection ran on (read only). */
+typedef enum {
+  VIPER_X = 0, VIPER_V = 1, VIPER_S = 2, VIPER_SDOT = 3, VIPER_Q = 4, VIPER_OMEGA = 5, VIPER_RADIUS = 6,
+  VIPER_XDET = 7, VIPER_SDET = 8
+} viper_field;
+
+/* Copy a state field to `dst` (device or host memory) / from `src` (device or host),
+ * ordered on `stream`.  Slots without an edge read as zero and are ignored on write. */
+viper_status viper_get_state(viper_scene scene, int32_t which, void* dst, void* stream);
+viper_status viper_set_state(viper_scene scene, int32_t which, const void* src, void* stream);
+
+/* Candidate contact pairs of the last substep's detection (Sec. 7.1): sorted (a, b),
+ * a < b, capsule ids; written to device or host `pairs` [cap*2]; *n receives the count
+ * (synchronises `stream`).  VIPER_ERR_NO_CAPACITY if n > cap (nothing written). */
+viper_status viper_get_contacts(viper_scene scene, int32_t* pairs, int32_t cap, int32_t* n, void* stream);
+
+/* Linear-blend skinning (Sec. 7.4): register a mesh of V rest vertices, each with 4
+ * (capsule id, weight) influences.  Device arrays, owned by the caller, read at every
+ * viper_skin call: rest_v [V*3] float, caps [V*4] int32, w [V*4] float. */
+viper_status viper_create_skin(viper_scene scene, int32_t V, const float* rest_v_dev, const int32_t* caps_dev,
+                               const float* w_dev, void* stream, int32_t* skin_id);
+/* out [V*3] float (device): v = sum_k w_k [s R(q) R(q_rest)^T | m - s R(q) R(q_rest)^T m_rest] [v_rest; 1]
+ * per capsule (similarity transform of eq. shapematch, blended as in Sec. 7.4). */
+viper_status viper_skin(viper_scene scene, int32_t skin_id, float* out_dev, void* stream);
+
+/* Wait for `stream` and report device-side conditions raised since the last sync:
+ * VIPER_ERR_NAN, VIPER_ERR_CAPACITY, or VIPER_ERR_DEVICE. Clears them. */
+viper_status viper_sync(viper_scene scene, void* stream);
+
+/* Release the host handle (the workspace stays the caller's). */
+viper_status viper_destroy_scene(viper_scene scene);
+
+/* Numbers of pills, rods, capsules, and rod constraint projections per iteration. */
+viper_status viper_scene_info(viper_scene scene, int64_t* pills, int64_t* rods, int64_t* capsules,
+                              int64_t* projections_per_iteration);
+
+const char* viper_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VIPER_H */

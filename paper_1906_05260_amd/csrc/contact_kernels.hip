@@ -1,0 +1,584 @@
+// Pill-pill contacts for gfx950.
+//
+// Detection (Sec. 7.1, after Green 2010): each capsule (tapered pill primitive)
+// gets a bounding sphere; a uniform grid with cell width equal to the largest
+// sphere diameter guarantees that overlapping spheres sit in neighbouring cells.
+// Cells are hashed into a table and filled by a counting sort; every capsule then
+// counts its candidates in the 27 neighbouring cells, an exclusive scan turns the
+// counts into offsets, and a second pass emits the candidate list in parallel
+// (the parallel count-then-list construction of Sec. 7.1).  Each capsule sorts its
+// own segment, so the list is ordered by (a, b) whatever order the atomics left
+// inside a bucket.  The overlap predicate runs in FP64 with no contraction, so it
+// decides exactly as a serial FP64 evaluation of the same stored values.
+//
+// Handling (Sec. 7.2, App. C): per candidate pair, a 10-step dichotomous search of
+// the largest inter-penetration over the first capsule's barycentric coordinate,
+// with the closed-form projection onto the second capsule; a violated pair gets a
+// hard (zero-compliance) correction of the four end positions and scales.  All
+// pairs read the same state and the corrections are averaged per pill (the Jacobi
+// reduction of Sec. 7), summed in pair order through a per-pill index for a
+// deterministic result.
+
+#include "contact.h"
+
+#include <cmath>
+#include <string>
+
+namespace viper {
+
+namespace {
+
+__device__ __forceinline__ uint32_t cell_hash(int x, int y, int z, int T) {
+  return ((uint32_t)x * 73856093u ^ (uint32_t)y * 19349663u ^ (uint32_t)z * 83492791u) & (uint32_t)(T - 1);
+}
+
+__device__ __forceinline__ int cell_of(double m, double cw) {
+  double f = floor(m / cw);
+  f = fmin(fmax(f, -1073741824.0), 1073741823.0);
+  return (int)f;
+}
+
+// Bounding sphere of capsule p in FP64: centre = midpoint, radius = half length + larger end radius.
+template <class T>
+__device__ void capsule_sphere(const Dev<T>& d, int p, double* out) {
+#pragma clang fp contract(off)
+  const double x0 = (double)d.px[p], y0 = (double)d.py[p], z0 = (double)d.pz[p];
+  const double x1 = (double)d.px[p + 1], y1 = (double)d.py[p + 1], z1 = (double)d.pz[p + 1];
+  out[0] = 0.5 * (x0 + x1);
+  out[1] = 0.5 * (y0 + y1);
+  out[2] = 0.5 * (z0 + z1);
+  const double dx = x1 - x0, dy = y1 - y0, dz = z1 - z0;
+  const double len = __builtin_sqrt((dx * dx + dy * dy) + dz * dz);
+  const double ra = (double)d.s[p] * (double)d.rbar[p];
+  const double rb = (double)d.s[p + 1] * (double)d.rbar[p + 1];
+  out[3] = 0.5 * len + ((ra < rb) ? rb : ra);
+}
+
+__device__ bool spheres_overlap(const double* a, const double* b) {
+#pragma clang fp contract(off)
+  const double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
+  const double d2 = (dx * dx + dy * dy) + dz * dz;
+  const double rr = a[3] + b[3];
+  return d2 < rr * rr;
+}
+
+__global__ void fill_kernel(int32_t* p, int n, int32_t v) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i < n) p[i] = v;
+}
+
+__global__ void clear_max_kernel(unsigned long long* p) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) p[0] = 0ull;
+}
+
+// ---- exclusive scan of n int32 (out[n] = total), 1024 items per block
+__global__ void __launch_bounds__(256) scan_block_kernel(const int32_t* in, int32_t* out, int n, int32_t* bsum) {
+  __shared__ int32_t sh[256];
+  const int t = (int)threadIdx.x;
+  const int base = (int)blockIdx.x * 1024 + 4 * t;
+  int v[4];
+  int s = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) { v[k] = (base + k < n) ? in[base + k] : 0; s += v[k]; }
+  sh[t] = s;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    const int x = (t >= o) ? sh[t - o] : 0;
+    __syncthreads();
+    sh[t] += x;
+    __syncthreads();
+  }
+  int run = sh[t] - s;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (base + k < n) out[base + k] = run;
+    run += v[k];
+  }
+  if (t == 255) bsum[blockIdx.x] = sh[255];
+}
+
+__global__ void __launch_bounds__(1024) scan_sums_kernel(int32_t* bsum, int nb, int32_t* total) {
+  __shared__ int32_t sh[1024];
+  __shared__ int32_t carry;
+  const int t = (int)threadIdx.x;
+  if (t == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < nb; base += 1024) {
+    const int idx = base + t;
+    const int v = (idx < nb) ? bsum[idx] : 0;
+    sh[t] = v;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      const int x = (t >= o) ? sh[t - o] : 0;
+      __syncthreads();
+      sh[t] += x;
+      __syncthreads();
+    }
+    if (idx < nb) bsum[idx] = carry + sh[t] - v;
+    __syncthreads();
+    if (t == 1023) carry += sh[1023];
+    __syncthreads();
+  }
+  if (t == 0) total[0] = carry;
+}
+
+__global__ void __launch_bounds__(256) scan_add_kernel(int32_t* out, int n, const int32_t* bsum) {
+  const int base = (int)blockIdx.x * 1024 + 4 * (int)threadIdx.x;
+  const int add = bsum[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (base + k < n) out[base + k] += add;
+}
+
+hipError_t scan(const int32_t* in, int32_t* out, int n, int32_t* bsum, hipStream_t st) {
+  const int nb = (n + 1023) / 1024;
+  if (nb == 0) {
+    hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, st, out, 1, 0);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(scan_block_kernel, dim3(nb), dim3(256), 0, st, in, out, n, bsum);
+  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(1024), 0, st, bsum, nb, out + n);
+  hipLaunchKernelGGL(scan_add_kernel, dim3(nb), dim3(256), 0, st, out, n, bsum);
+  return hipGetLastError();
+}
+
+// ---- detection
+
+template <class T>
+__global__ void __launch_bounds__(256) sphere_kernel(Dev<T> d, ContactDev c) {
+  __shared__ double sh[256];
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  double R = 0.0;
+  if (i < c.E) {
+    double sp[4];
+    capsule_sphere(d, c.cap_ids[i], sp);
+    c.sph[4 * (size_t)i + 0] = sp[0];
+    c.sph[4 * (size_t)i + 1] = sp[1];
+    c.sph[4 * (size_t)i + 2] = sp[2];
+    c.sph[4 * (size_t)i + 3] = sp[3];
+    R = sp[3];
+  }
+  sh[threadIdx.x] = R;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(c.maxr, (unsigned long long)__double_as_longlong(sh[0]));
+}
+
+template <class T>
+__global__ void det_copy_kernel(Dev<T> d, ContactDev c) {
+  const int p = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (p >= d.P) return;
+  T* xd = (T*)c.xdet;
+  T* sdd = (T*)c.sdet;
+  xd[3 * (size_t)p] = d.px[p]; xd[3 * (size_t)p + 1] = d.py[p]; xd[3 * (size_t)p + 2] = d.pz[p];
+  sdd[p] = d.s[p];
+}
+
+__device__ __forceinline__ double cell_width(const ContactDev& c) {
+  const double R = __longlong_as_double((long long)c.maxr[0]);
+  return (R > 0.0) ? 2.0 * R * (1.0 + 1e-6) : 1.0;
+}
+
+__global__ void __launch_bounds__(256) key_kernel(ContactDev c, int32_t* cell) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i >= c.E) return;
+  const double cw = cell_width(c);
+  const int cx = cell_of(c.sph[4 * (size_t)i], cw), cy = cell_of(c.sph[4 * (size_t)i + 1], cw),
+            cz = cell_of(c.sph[4 * (size_t)i + 2], cw);
+  cell[3 * (size_t)i] = cx; cell[3 * (size_t)i + 1] = cy; cell[3 * (size_t)i + 2] = cz;
+  const uint32_t h = cell_hash(cx, cy, cz, c.T);
+  c.key[i] = (int32_t)h;
+  atomicAdd(&c.cell_cnt[h], 1);
+}
+
+__global__ void __launch_bounds__(256) bucket_scatter_kernel(ContactDev c) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i >= c.E) return;
+  const int h = c.key[i];
+  const int pos = c.cell_start[h] + atomicAdd(&c.cell_cur[h], 1);
+  c.sorted[pos] = i;
+}
+
+// Count (EMIT = false) or emit (EMIT = true) the candidates b > a of capsule a.
+template <bool EMIT>
+__global__ void __launch_bounds__(256) pair_kernel(ContactDev c, const int32_t* cell) {
+  const int a = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (a >= c.E) return;
+  const double sa[4] = {c.sph[4 * (size_t)a], c.sph[4 * (size_t)a + 1], c.sph[4 * (size_t)a + 2], c.sph[4 * (size_t)a + 3]};
+  const int ra = c.cap_rod[a], ga = c.cap_grp[a];
+  const int cx = cell[3 * (size_t)a], cy = cell[3 * (size_t)a + 1], cz = cell[3 * (size_t)a + 2];
+  const int base = EMIT ? c.poff[a] : 0;
+  int cnt = 0;
+  for (int dz = -1; dz <= 1; ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int nx = cx + dx, ny = cy + dy, nz = cz + dz;
+        const uint32_t h = cell_hash(nx, ny, nz, c.T);
+        const int j1 = c.cell_start[h + 1];
+        for (int j = c.cell_start[h]; j < j1; ++j) {
+          const int b = c.sorted[j];
+          if (b <= a) continue;
+          // only the bucket entries that really lie in this neighbour cell
+          if (cell[3 * (size_t)b] != nx || cell[3 * (size_t)b + 1] != ny || cell[3 * (size_t)b + 2] != nz) continue;
+          if (c.cap_rod[b] == ra || c.cap_grp[b] == ga) continue;
+          const double sb[4] = {c.sph[4 * (size_t)b], c.sph[4 * (size_t)b + 1], c.sph[4 * (size_t)b + 2],
+                                c.sph[4 * (size_t)b + 3]};
+          if (!spheres_overlap(sa, sb)) continue;
+          if (EMIT) {
+            const int idx = base + cnt;
+            if (idx < c.cap) c.pairs[2 * (size_t)idx + 1] = b;   // capsule index for now
+          }
+          ++cnt;
+        }
+      }
+  if (!EMIT) {
+    c.pcount[a] = cnt;
+    return;
+  }
+  // sort this capsule's segment by b, then store capsule ids (first pill of each capsule)
+  const int n = min(cnt, c.cap - base);
+  for (int i = 1; i < n; ++i) {
+    const int v = c.pairs[2 * (size_t)(base + i) + 1];
+    int j = i - 1;
+    while (j >= 0 && c.pairs[2 * (size_t)(base + j) + 1] > v) {
+      c.pairs[2 * (size_t)(base + j + 1) + 1] = c.pairs[2 * (size_t)(base + j) + 1];
+      --j;
+    }
+    c.pairs[2 * (size_t)(base + j + 1) + 1] = v;
+  }
+  const int ida = c.cap_ids[a];
+  for (int i = 0; i < n; ++i) {
+    const size_t k = 2 * (size_t)(base + i);
+    c.pairs[k] = ida;
+    c.pairs[k + 1] = c.cap_ids[c.pairs[k + 1]];
+  }
+}
+
+__global__ void finalize_kernel(ContactDev c) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  const int total = c.poff[c.E];
+  c.npairs[0] = min(total, c.cap);
+  if (total > c.cap) c.status[ST_OVERFLOW] = 1;
+}
+
+__global__ void __launch_bounds__(256) csr_count_kernel(ContactDev c) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i >= c.npairs[0]) return;
+  const int a = c.pairs[2 * (size_t)i], b = c.pairs[2 * (size_t)i + 1];
+  atomicAdd(&c.pill_cnt[a], 1);
+  atomicAdd(&c.pill_cnt[a + 1], 1);
+  atomicAdd(&c.pill_cnt[b], 1);
+  atomicAdd(&c.pill_cnt[b + 1], 1);
+}
+
+__global__ void __launch_bounds__(256) csr_fill_kernel(ContactDev c) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i >= c.npairs[0]) return;
+  const int a = c.pairs[2 * (size_t)i], b = c.pairs[2 * (size_t)i + 1];
+  const int pid[4] = {a, a + 1, b, b + 1};
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int slot = c.pill_start[pid[t]] + atomicAdd(&c.pill_cur[pid[t]], 1);
+    c.entries[slot] = 4 * i + t;
+  }
+}
+
+__global__ void __launch_bounds__(256) csr_sort_kernel(ContactDev c) {
+  const int p = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (p >= c.P) return;
+  const int s0 = c.pill_start[p], n = c.pill_start[p + 1] - s0;
+  for (int i = 1; i < n; ++i) {
+    const int v = c.entries[s0 + i];
+    int j = i - 1;
+    while (j >= 0 && c.entries[s0 + j] > v) {
+      c.entries[s0 + j + 1] = c.entries[s0 + j];
+      --j;
+    }
+    c.entries[s0 + j + 1] = v;
+  }
+}
+
+// ---- handling (FP64 arithmetic)
+
+struct D3 { double x, y, z; };
+__device__ __forceinline__ D3 d3(double x, double y, double z) { D3 r; r.x = x; r.y = y; r.z = z; return r; }
+__device__ __forceinline__ D3 sub(D3 a, D3 b) { return d3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ double dotp(D3 a, D3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ D3 lerp(D3 a, D3 b, double t) { return d3(a.x + t * (b.x - a.x), a.y + t * (b.y - a.y), a.z + t * (b.z - a.z)); }
+
+// Barycentric coordinate on capsule (c1,r1)-(c2,r2) of the sphere nearest (in surface
+// distance) to point x: stationary point of |x - c(t)| - r(t) along the axis, clamped
+// (App. C with its sign and square corrected; a capsule whose radii differ by more than
+// its length is its larger end sphere).
+__device__ double pill_param(D3 x, D3 c1, double r1, D3 c2, double r2) {
+  const D3 ax = sub(c2, c1);
+  const double l = sqrt(dotp(ax, ax));
+  if (!(l > 0.0)) return 0.0;
+  const double sn = (r1 - r2) / l;
+  if (sn >= 1.0) return 0.0;
+  if (sn <= -1.0) return 1.0;
+  const D3 e = d3(ax.x / l, ax.y / l, ax.z / l);
+  const D3 rel = sub(x, c1);
+  const double u = dotp(rel, e);
+  const D3 perp = d3(rel.x - u * e.x, rel.y - u * e.y, rel.z - u * e.z);
+  const double dp = sqrt(dotp(perp, perp));
+  const double t = (u - dp * sn / sqrt(1.0 - sn * sn)) / l;
+  return fmin(fmax(t, 0.0), 1.0);
+}
+
+__device__ double gap_at(const D3* c, const double* r, double al) {
+  const D3 ca = lerp(c[0], c[1], al);
+  const double ra = r[0] + al * (r[1] - r[0]);
+  const double be = pill_param(ca, c[2], r[2], c[3], r[3]);
+  const D3 cb = lerp(c[2], c[3], be);
+  const D3 dv = sub(ca, cb);
+  return sqrt(dotp(dv, dv)) - ra - (r[2] + be * (r[3] - r[2]));
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) contact_pair_kernel(Dev<T> d, ContactDev c) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i >= c.npairs[0]) return;
+  const int a = c.pairs[2 * (size_t)i], b = c.pairs[2 * (size_t)i + 1];
+  const int pid[4] = {a, a + 1, b, b + 1};
+  D3 cp[4];
+  double r[4], rb[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int p = pid[t];
+    cp[t] = d3((double)d.px[p], (double)d.py[p], (double)d.pz[p]);
+    rb[t] = (double)d.rbar[p];
+    r[t] = (double)d.s[p] * rb[t];
+  }
+  // dichotomous search over the first capsule's parameter (fixed iteration count)
+  double lo = 0.0, hi = 1.0;
+  for (int k = 0; k < c.search_iters; ++k) {
+    const double m = 0.5 * (lo + hi);
+    const double x1 = m - c.delta, x2 = m + c.delta;
+    if (gap_at(cp, r, x1) < gap_at(cp, r, x2)) hi = x2; else lo = x1;
+  }
+  const double al = 0.5 * (lo + hi);
+  const D3 ca = lerp(cp[0], cp[1], al);
+  const double be = pill_param(ca, cp[2], r[2], cp[3], r[3]);
+  const D3 cb = lerp(cp[2], cp[3], be);
+  const D3 dv = sub(ca, cb);
+  const double dist = sqrt(dotp(dv, dv));
+  const double C = dist - (r[0] + al * (r[1] - r[0])) - (r[2] + be * (r[3] - r[2]));
+  int act = 0;
+  if (C < 0.0 && dist > 0.0) {
+    const D3 n = d3(dv.x / dist, dv.y / dist, dv.z / dist);
+    const double wt[4] = {1.0 - al, al, -(1.0 - be), -be};   // dC/dx_t = wt n, dC/ds_t = -|wt| rbar
+    double den = 0.0;
+    double w[4], ws[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      w[t] = (double)d.winv[pid[t]];
+      ws[t] = (double)d.wsinv[pid[t]];
+      const double gs = fabs(wt[t]) * rb[t];
+      den += w[t] * wt[t] * wt[t] + ws[t] * gs * gs;
+    }
+    if (den > 0.0) {
+      act = 1;
+      const double dl = -C / den;
+      double* o = c.delta_buf + 16 * (size_t)i;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const double k = w[t] * wt[t] * dl;
+        o[4 * t + 0] = k * n.x;
+        o[4 * t + 1] = k * n.y;
+        o[4 * t + 2] = k * n.z;
+        o[4 * t + 3] = -ws[t] * fabs(wt[t]) * rb[t] * dl;
+      }
+    }
+  }
+  c.active[i] = act;
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) contact_gather_kernel(Dev<T> d, ContactDev c) {
+  const int p = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (p >= c.P) return;
+  const int s0 = c.pill_start[p], s1 = c.pill_start[p + 1];
+  if (s0 == s1) return;
+  double ax = 0, ay = 0, az = 0, as = 0;
+  int n = 0;
+  for (int k = s0; k < s1; ++k) {
+    const int e = c.entries[k];
+    const int pr = e >> 2;
+    if (!c.active[pr]) continue;
+    const double* o = c.delta_buf + 16 * (size_t)pr + 4 * (e & 3);
+    ax += o[0]; ay += o[1]; az += o[2]; as += o[3];
+    ++n;
+  }
+  if (n == 0) return;
+  const double inv = 1.0 / (double)n;
+  d.px[p] = (T)((double)d.px[p] + inv * ax);
+  d.py[p] = (T)((double)d.py[p] + inv * ay);
+  d.pz[p] = (T)((double)d.pz[p] + inv * az);
+  d.s[p] = (T)((double)d.s[p] + inv * as);
+}
+
+inline unsigned nblk(int n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+// ----------------------------------------------------------------------------- host side
+
+ContactOffsets contact_layout(size_t start, bool on, int P, int E, int cpc, bool f64) {
+  ContactOffsets o;
+  o.on = on;
+  size_t off = start;
+  auto take = [&](size_t bytes) {
+    size_t r = off;
+    off += (bytes + 255) & ~size_t(255);
+    return r;
+  };
+  if (!on) {
+    o.end = start;
+    return o;
+  }
+  int T = 64;
+  while (T < 2 * E) T <<= 1;
+  const size_t cap = (size_t)cpc * (size_t)E;
+  const size_t ts = f64 ? 8 : 4;
+  const int nb = (std::max(std::max(T, E), P) + 1023) / 1024 + 1;
+  o.cap_ids = take(4 * (size_t)E);
+  o.cap_rod = take(4 * (size_t)E);
+  o.cap_grp = take(4 * (size_t)E);
+  o.sph = take(8 * 4 * (size_t)E);
+  o.maxr = take(8);
+  o.key = take(4 * (size_t)E + 12 * (size_t)E);   // keys followed by cell coordinates
+  o.cell_cnt = take(4 * (size_t)T);
+  o.cell_start = take(4 * (size_t)(T + 1));
+  o.cell_cur = take(4 * (size_t)T);
+  o.sorted = take(4 * (size_t)E);
+  o.pcount = take(4 * (size_t)E);
+  o.poff = take(4 * (size_t)(E + 1));
+  o.pairs = take(8 * cap);
+  o.npairs = take(4);
+  o.pill_cnt = take(4 * (size_t)P);
+  o.pill_start = take(4 * (size_t)(P + 1));
+  o.pill_cur = take(4 * (size_t)P);
+  o.entries = take(16 * cap);
+  o.delta = take(8 * 16 * cap);
+  o.active = take(4 * cap);
+  o.xdet = take(ts * 3 * (size_t)P);
+  o.sdet = take(ts * (size_t)P);
+  o.bsum = take(4 * (size_t)nb);
+  o.end = off;
+  return o;
+}
+
+viper_status contact_init(ContactDev& c, char* ws, const ContactOffsets& o, const viper_scene_desc* d,
+                          const std::vector<int32_t>& off, const std::vector<int32_t>& group, hipStream_t st) {
+  c.on = o.on;
+  if (!o.on) return VIPER_OK;
+  const int R = (int)off.size() - 1;
+  c.P = off[R];
+  std::vector<int32_t> ids, rod, grp;
+  for (int k = 0; k < R; ++k)
+    for (int p = off[k]; p + 1 < off[k + 1]; ++p) { ids.push_back(p); rod.push_back(k); grp.push_back(group[k]); }
+  c.E = (int)ids.size();
+  c.T = 64;
+  while (c.T < 2 * c.E) c.T <<= 1;
+  const int cpc = d->contact_capacity_per_capsule > 0 ? d->contact_capacity_per_capsule : 16;
+  c.cap = cpc * c.E;
+  c.cap_ids = (int32_t*)(ws + o.cap_ids);
+  c.cap_rod = (int32_t*)(ws + o.cap_rod);
+  c.cap_grp = (int32_t*)(ws + o.cap_grp);
+  c.sph = (double*)(ws + o.sph);
+  c.maxr = (unsigned long long*)(ws + o.maxr);
+  c.key = (int32_t*)(ws + o.key);
+  c.cell_cnt = (int32_t*)(ws + o.cell_cnt);
+  c.cell_start = (int32_t*)(ws + o.cell_start);
+  c.cell_cur = (int32_t*)(ws + o.cell_cur);
+  c.sorted = (int32_t*)(ws + o.sorted);
+  c.pcount = (int32_t*)(ws + o.pcount);
+  c.poff = (int32_t*)(ws + o.poff);
+  c.pairs = (int32_t*)(ws + o.pairs);
+  c.npairs = (int32_t*)(ws + o.npairs);
+  c.pill_cnt = (int32_t*)(ws + o.pill_cnt);
+  c.pill_start = (int32_t*)(ws + o.pill_start);
+  c.pill_cur = (int32_t*)(ws + o.pill_cur);
+  c.entries = (int32_t*)(ws + o.entries);
+  c.delta_buf = (double*)(ws + o.delta);
+  c.active = (int32_t*)(ws + o.active);
+  c.xdet = ws + o.xdet;
+  c.sdet = ws + o.sdet;
+  c.bsum = (int32_t*)(ws + o.bsum);
+  if (hipMemcpyAsync(c.cap_ids, ids.data(), 4 * ids.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(c.cap_rod, rod.data(), 4 * rod.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(c.cap_grp, grp.data(), 4 * grp.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemsetAsync(c.npairs, 0, 4, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
+    return VIPER_ERR_DEVICE;
+  return VIPER_OK;
+}
+
+template <class T>
+hipError_t contact_detect(const Dev<T>& d, ContactDev& c, hipStream_t st) {
+  c.status = d.status;
+  const int E = c.E, P = c.P, T_ = c.T;
+  int32_t* cell = c.key + E;
+  hipLaunchKernelGGL(det_copy_kernel<T>, dim3(nblk(P)), dim3(256), 0, st, d, c);
+  hipLaunchKernelGGL(clear_max_kernel, dim3(1), dim3(64), 0, st, c.maxr);
+  hipLaunchKernelGGL(fill_kernel, dim3(nblk(T_)), dim3(256), 0, st, c.cell_cnt, T_, 0);
+  hipLaunchKernelGGL(fill_kernel, dim3(nblk(T_)), dim3(256), 0, st, c.cell_cur, T_, 0);
+  hipLaunchKernelGGL(fill_kernel, dim3(nblk(P)), dim3(256), 0, st, c.pill_cnt, P, 0);
+  hipLaunchKernelGGL(fill_kernel, dim3(nblk(P)), dim3(256), 0, st, c.pill_cur, P, 0);
+  if (E > 0) {
+    hipLaunchKernelGGL(sphere_kernel<T>, dim3(nblk(E)), dim3(256), 0, st, d, c);
+    hipLaunchKernelGGL(key_kernel, dim3(nblk(E)), dim3(256), 0, st, c, cell);
+  }
+  hipError_t e = scan(c.cell_cnt, c.cell_start, T_, c.bsum, st);
+  if (e != hipSuccess) return e;
+  if (E > 0) {
+    hipLaunchKernelGGL(bucket_scatter_kernel, dim3(nblk(E)), dim3(256), 0, st, c);
+    hipLaunchKernelGGL(pair_kernel<false>, dim3(nblk(E)), dim3(256), 0, st, c, (const int32_t*)cell);
+  }
+  e = scan(c.pcount, c.poff, E, c.bsum, st);
+  if (e != hipSuccess) return e;
+  if (E > 0) hipLaunchKernelGGL(pair_kernel<true>, dim3(nblk(E)), dim3(256), 0, st, c, (const int32_t*)cell);
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(64), 0, st, c);
+  if (c.cap > 0) hipLaunchKernelGGL(csr_count_kernel, dim3(nblk(c.cap)), dim3(256), 0, st, c);
+  e = scan(c.pill_cnt, c.pill_start, P, c.bsum, st);
+  if (e != hipSuccess) return e;
+  if (c.cap > 0) hipLaunchKernelGGL(csr_fill_kernel, dim3(nblk(c.cap)), dim3(256), 0, st, c);
+  hipLaunchKernelGGL(csr_sort_kernel, dim3(nblk(P)), dim3(256), 0, st, c);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t contact_project(const Dev<T>& d, ContactDev& c, hipStream_t st) {
+  if (c.cap > 0) hipLaunchKernelGGL(contact_pair_kernel<T>, dim3(nblk(c.cap)), dim3(256), 0, st, d, c);
+  hipLaunchKernelGGL(contact_gather_kernel<T>, dim3(nblk(c.P)), dim3(256), 0, st, d, c);
+  return hipGetLastError();
+}
+
+hipError_t contact_copy_det(ContactDev& c, bool x, void* dst, int P, size_t ts, hipStream_t st) {
+  return hipMemcpyAsync(dst, x ? c.xdet : c.sdet, (x ? 3 : 1) * ts * (size_t)P, hipMemcpyDeviceToDevice, st);
+}
+
+viper_status contact_get_pairs(ContactDev& c, int32_t* pairs, int32_t cap, int32_t* n, hipStream_t st) {
+  int32_t h = 0;
+  if (hipMemcpyAsync(&h, c.npairs, 4, hipMemcpyDeviceToHost, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
+    return VIPER_ERR_DEVICE;
+  *n = h;
+  if (h > cap) return VIPER_ERR_NO_CAPACITY;
+  if (h > 0) {
+    if (!pairs) return VIPER_ERR_INVALID;
+    if (hipMemcpyAsync(pairs, c.pairs, 8 * (size_t)h, hipMemcpyDefault, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return VIPER_ERR_DEVICE;
+  }
+  return VIPER_OK;
+}
+
+template hipError_t contact_detect<float>(const Dev<float>&, ContactDev&, hipStream_t);
+template hipError_t contact_detect<double>(const Dev<double>&, ContactDev&, hipStream_t);
+template hipError_t contact_project<float>(const Dev<float>&, ContactDev&, hipStream_t);
+template hipError_t contact_project<double>(const Dev<double>&, ContactDev&, hipStream_t);
+
+}  // namespace viper

@@ -1,0 +1,574 @@
+// VIPER rod substep kernels for gfx950 (CDNA4, wave64).
+//
+// One wavefront owns a contiguous run of whole rods (<= 64 pills); lane l holds
+// pill wave_start+l: its vertex state (position, velocity, scale and rate) and
+// the edge that starts at it (quaternion, angular velocity).  Constraints are
+// projected in four colour passes per iteration (even/odd edges for stretch-
+// shear + volume + scale-gradient, even/odd vertices for bend-twist), so inside
+// a pass every constraint touches disjoint state.  The lane owning the left end
+// of a constraint reads its right neighbour's values with a cross-lane shuffle,
+// applies the closed-form update of Sec. 6 (per-constraint dual update, XPBD
+// form, relaxation 1), and hands the right neighbour its new values back.
+//
+// The closed forms used here (derived from the generic update
+//   S = sum_b J_b W_b J_b^T + alpha~,  dl = S^-1(-C - alpha~ lambda),  dX_b = W_b J_b^T dl)
+// are:
+//  stretch-shear (eq. stretch_z):  C = (x1-x0)/lbar - d3(q),
+//      S = k1 d3 d3^T + k2 (I - d3 d3^T),  k1 = (w0+w1)/lbar^2 + a~,  k2 = k1 + 1/I_bend
+//  volume (eq. vol, tangential):   C = s_m^2 |x1-x0| / l0 - 1   (scalar)
+//  scale gradient (eq. surface_stretch): C = (s1-s0)/l0         (scalar)
+//  bend-twist (eq. bending_twist, Darboux vector of Sec. 7.5):
+//      C = s1 c Im(r) - Omega_rest,  r = conj(q0) q1 (shortest arc), c = 4/(l0_0+l0_1),
+//      J_q1 = -J_q0 = (s1 c / 2)(r_w I - [r_v]x) R0^T, solved as a symmetric 3x3 in frame 0.
+
+#include "viper_dev.h"
+
+namespace viper {
+
+template <class T> __device__ __forceinline__ T rsq(T a);
+template <> __device__ __forceinline__ float rsq<float>(float a) { return rsqrtf(a); }
+template <> __device__ __forceinline__ double rsq<double>(double a) { return rsqrt(a); }
+
+template <class T> __device__ __forceinline__ T dn(T v) { return __shfl_down(v, 1); }  // from lane+1
+template <class T> __device__ __forceinline__ T up(T v) { return __shfl_up(v, 1); }    // from lane-1
+
+// q <- normalize(q + 1/2 [t, 0] (x) q): rotate by the world-frame vector t.
+template <class T>
+__device__ __forceinline__ void qrot_world(T& x, T& y, T& z, T& w, T t0, T t1, T t2) {
+  const T a0 = T(0.5) * t0, a1 = T(0.5) * t1, a2 = T(0.5) * t2;
+  const T nx = x + (w * a0 + (a1 * z - a2 * y));
+  const T ny = y + (w * a1 + (a2 * x - a0 * z));
+  const T nz = z + (w * a2 + (a0 * y - a1 * x));
+  const T nw = w - (a0 * x + a1 * y + a2 * z);
+  const T in = rsq(nx * nx + ny * ny + nz * nz + nw * nw);
+  x = nx * in; y = ny * in; z = nz * in; w = nw * in;
+}
+
+template <class T>
+struct Lane {
+  T x0, x1, x2, v0, v1, v2, s, sd;
+  T q0, q1, q2, q3, o0, o1, o2;
+  T xp0, xp1, xp2, sp, qp0, qp1, qp2, qp3;
+  T l[8];
+  T w, ws, wR, wsR;            // inverse masses of this pill and the right neighbour
+  T ilb, il0, cbt, inert;      // edge constants
+  T db0, db1, db2;             // rest Darboux
+  T css, cvol, csg, cbtc;      // scaled compliances (per edge)
+  T ass, avol, asg, abt;       // compliance / h^2
+  T I1, I1R;                   // inverse bending inertia of own / right edge (this substep)
+  uint32_t f;
+};
+
+// ---------------------------------------------------------------- per-lane stages
+
+template <class T>
+__device__ __forceinline__ void predict_lane(Lane<T>& L, T h, T gx, T gy, T gz) {
+  L.xp0 = L.x0; L.xp1 = L.x1; L.xp2 = L.x2; L.sp = L.s;
+  if (L.w > T(0)) {
+    const T h2 = h * h;
+    L.x0 = L.x0 + h * L.v0 + h2 * gx;
+    L.x1 = L.x1 + h * L.v1 + h2 * gy;
+    L.x2 = L.x2 + h * L.v2 + h2 * gz;
+  }
+  L.s = L.s + h * L.sd;
+  L.qp0 = L.q0; L.qp1 = L.q1; L.qp2 = L.q2; L.qp3 = L.q3;
+  if (L.f & F_EDGE) qrot_world(L.q0, L.q1, L.q2, L.q3, h * L.o0, h * L.o1, h * L.o2);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) L.l[i] = T(0);
+}
+
+// Inverse bending inertia of the own edge from the substep-start midpoint scale
+// (rotational weight rho s^2 l pi r^4 / 4, App. B) and of the right neighbour's edge.
+template <class T>
+__device__ __forceinline__ void inertia_lane(Lane<T>& L) {
+  const T spR = dn(L.sp);
+  T I1 = T(0);
+  if (L.f & F_EDGE) {
+    const T sm = T(0.5) * (L.sp + spR);
+    I1 = T(4) / (L.inert * sm * sm);
+  }
+  L.I1 = I1;
+  L.I1R = dn(I1);
+}
+
+template <class T>
+__device__ __forceinline__ void velocity_lane(Lane<T>& L, T h) {
+  const T ih = T(1) / h;
+  if (L.w > T(0)) {
+    L.v0 = (L.x0 - L.xp0) * ih; L.v1 = (L.x1 - L.xp1) * ih; L.v2 = (L.x2 - L.xp2) * ih;
+  } else {
+    L.v0 = T(0); L.v1 = T(0); L.v2 = T(0);
+  }
+  L.sd = (L.s - L.sp) * ih;
+  if (L.f & F_EDGE) {
+    // r = q (x) conj(q_prev), shortest arc; omega = 2 Im(r) / h
+    T rx = -L.q3 * L.qp0 + L.q0 * L.qp3 - L.q1 * L.qp2 + L.q2 * L.qp1;
+    T ry = -L.q3 * L.qp1 + L.q0 * L.qp2 + L.q1 * L.qp3 - L.q2 * L.qp0;
+    T rz = -L.q3 * L.qp2 - L.q0 * L.qp1 + L.q1 * L.qp0 + L.q2 * L.qp3;
+    T rw = L.q3 * L.qp3 + L.q0 * L.qp0 + L.q1 * L.qp1 + L.q2 * L.qp2;
+    const T sg = (rw < T(0)) ? T(-2) * ih : T(2) * ih;
+    L.o0 = sg * rx; L.o1 = sg * ry; L.o2 = sg * rz;
+  }
+}
+
+// Stretch-shear, volume and scale-gradient of the own edge (left end = this lane),
+// for the lanes whose edge parity equals `colour`.
+template <class T>
+__device__ __forceinline__ void pass_edges(Lane<T>& L, int colour) {
+  T b0 = dn(L.x0), b1 = dn(L.x1), b2 = dn(L.x2), sb = dn(L.s);
+  const bool odd = (L.f & F_ODD) != 0;
+  const bool act = (L.f & F_EDGE) && (odd == (colour != 0));
+  if (act) {
+    T a0 = L.x0, a1 = L.x1, a2 = L.x2, sa = L.s;
+    const T wa = L.w, wb = L.wR;
+    if (L.f & F_SS) {
+      const T q0 = L.q0, q1 = L.q1, q2 = L.q2, q3 = L.q3;
+      const T d0 = T(2) * (q0 * q2 + q3 * q1);
+      const T d1 = T(2) * (q1 * q2 - q3 * q0);
+      const T d2 = T(1) - T(2) * (q0 * q0 + q1 * q1);
+      const T ilb = L.ilb, at = L.ass;
+      const T c0 = (b0 - a0) * ilb - d0, c1 = (b1 - a1) * ilb - d1, c2 = (b2 - a2) * ilb - d2;
+      const T k1 = (wa + wb) * ilb * ilb + at;
+      const T ik1 = T(1) / k1, ik2 = T(1) / (k1 + L.I1);
+      const T r0 = -c0 - at * L.l[0], r1 = -c1 - at * L.l[1], r2 = -c2 - at * L.l[2];
+      const T dr = d0 * r0 + d1 * r1 + d2 * r2;
+      const T e = dr * (ik1 - ik2);
+      const T g0 = r0 * ik2 + e * d0, g1 = r1 * ik2 + e * d1, g2 = r2 * ik2 + e * d2;
+      L.l[0] += g0; L.l[1] += g1; L.l[2] += g2;
+      const T fa = wa * ilb, fb = wb * ilb;
+      a0 -= fa * g0; a1 -= fa * g1; a2 -= fa * g2;
+      b0 += fb * g0; b1 += fb * g1; b2 += fb * g2;
+      const T nI = -L.I1;   // dtheta = -(d3 x dl) / I_bend
+      qrot_world(L.q0, L.q1, L.q2, L.q3, nI * (d1 * g2 - d2 * g1), nI * (d2 * g0 - d0 * g2), nI * (d0 * g1 - d1 * g0));
+    }
+    if (L.f & F_VOL) {
+      const T e0 = b0 - a0, e1 = b1 - a1, e2 = b2 - a2;
+      const T ilen = rsq(e0 * e0 + e1 * e1 + e2 * e2);
+      const T len = (e0 * e0 + e1 * e1 + e2 * e2) * ilen;
+      const T sm = T(0.5) * (sa + sb);
+      const T sm2 = sm * sm;
+      const T C = sm2 * len * L.il0 - T(1);
+      const T gx = sm2 * L.il0, gs = sm * len * L.il0;
+      const T at = L.avol;
+      const T S = (wa + wb) * gx * gx + (L.ws + L.wsR) * gs * gs + at;
+      const T dl = (-C - at * L.l[3]) / S;
+      L.l[3] += dl;
+      const T k = gx * dl * ilen;
+      a0 -= wa * k * e0; a1 -= wa * k * e1; a2 -= wa * k * e2;
+      b0 += wb * k * e0; b1 += wb * k * e1; b2 += wb * k * e2;
+      sa += L.ws * gs * dl;
+      sb += L.wsR * gs * dl;
+    }
+    if (L.f & F_SG) {
+      const T il0 = L.il0, at = L.asg;
+      const T C = (sb - sa) * il0;
+      const T S = (L.ws + L.wsR) * il0 * il0 + at;
+      const T dl = (-C - at * L.l[4]) / S;
+      L.l[4] += dl;
+      sa -= L.ws * il0 * dl;
+      sb += L.wsR * il0 * dl;
+    }
+    L.x0 = a0; L.x1 = a1; L.x2 = a2; L.s = sa;
+  }
+  // hand the right end back to its owner
+  b0 = up(b0); b1 = up(b1); b2 = up(b2); sb = up(sb);
+  const bool recv = (L.f & F_VALID) && !(L.f & F_FIRST) && (odd == (colour == 0));
+  if (recv) { L.x0 = b0; L.x1 = b1; L.x2 = b2; L.s = sb; }
+}
+
+// Bend-twist at vertex p+1 between the own edge (a) and the right edge (b), for
+// lanes whose parity equals `colour`.
+template <class T>
+__device__ __forceinline__ void pass_bt(Lane<T>& L, int colour) {
+  T b0 = dn(L.q0), b1 = dn(L.q1), b2 = dn(L.q2), b3 = dn(L.q3), sb = dn(L.s);
+  const bool odd = (L.f & F_ODD) != 0;
+  const bool act = (L.f & F_BT) && (L.f & F_BTEN) && (odd == (colour != 0));
+  if (act) {
+    const T a0 = L.q0, a1 = L.q1, a2 = L.q2, a3 = L.q3;
+    // r = conj(qa) (x) qb
+    const T rx = a3 * b0 - a0 * b3 - a1 * b2 + a2 * b1;
+    const T ry = a3 * b1 + a0 * b2 - a1 * b3 - a2 * b0;
+    const T rz = a3 * b2 - a0 * b1 + a1 * b0 - a2 * b3;
+    const T rw = a3 * b3 + a0 * b0 + a1 * b1 + a2 * b2;
+    const T sg = (rw < T(0)) ? T(-1) : T(1);
+    const T v0 = sg * rx, v1 = sg * ry, v2 = sg * rz, w = sg * rw;
+    const T c = L.cbt;
+    const T sc = sb * c;
+    const T C0 = sc * v0 - L.db0, C1 = sc * v1 - L.db1, C2 = sc * v2 - L.db2;
+    // tangent of edge b in frame a: t = R(r) e_z;  u = B e_z, y = B t with B = w I - [v]x
+    const T t0 = T(2) * (v0 * v2 + w * v1);
+    const T t1 = T(2) * (v1 * v2 - w * v0);
+    const T t2 = T(1) - T(2) * (v0 * v0 + v1 * v1);
+    const T u0 = -v1, u1 = v0, u2 = w;
+    const T y0 = w * t0 - (v1 * t2 - v2 * t1);
+    const T y1 = w * t1 - (v2 * t0 - v0 * t2);
+    const T y2 = w * t2 - (v0 * t1 - v1 * t0);
+    // S = K[(Ia+Ib)(I - v v^T) - Ia/2 u u^T - Ib/2 y y^T] + wsb c^2 v v^T + diag(a, a, a/2)
+    const T Ia = L.I1, Ib = L.I1R;
+    const T K = T(0.25) * sc * sc;
+    const T m = K * (Ia + Ib);
+    const T ha = T(0.5) * K * Ia, hb = T(0.5) * K * Ib;
+    const T qv = L.wsR * c * c - m;
+    const T at = L.abt;
+    const T S00 = m + qv * v0 * v0 - ha * u0 * u0 - hb * y0 * y0 + at;
+    const T S11 = m + qv * v1 * v1 - ha * u1 * u1 - hb * y1 * y1 + at;
+    const T S22 = m + qv * v2 * v2 - ha * u2 * u2 - hb * y2 * y2 + T(0.5) * at;
+    const T S01 = qv * v0 * v1 - ha * u0 * u1 - hb * y0 * y1;
+    const T S02 = qv * v0 * v2 - ha * u0 * u2 - hb * y0 * y2;
+    const T S12 = qv * v1 * v2 - ha * u1 * u2 - hb * y1 * y2;
+    const T r0 = -C0 - at * L.l[5], r1 = -C1 - at * L.l[6], r2 = -C2 - T(0.5) * at * L.l[7];
+    const T A00 = S11 * S22 - S12 * S12, A01 = S02 * S12 - S01 * S22, A02 = S01 * S12 - S02 * S11;
+    const T A11 = S00 * S22 - S02 * S02, A12 = S01 * S02 - S00 * S12, A22 = S00 * S11 - S01 * S01;
+    const T idet = T(1) / (S00 * A00 + S01 * A01 + S02 * A02);
+    const T g0 = (A00 * r0 + A01 * r1 + A02 * r2) * idet;
+    const T g1 = (A01 * r0 + A11 * r1 + A12 * r2) * idet;
+    const T g2 = (A02 * r0 + A12 * r1 + A22 * r2) * idet;
+    L.l[5] += g0; L.l[6] += g1; L.l[7] += g2;
+    // B^T dl = w dl + v x dl   (frame a)
+    const T e0 = w * g0 + (v1 * g2 - v2 * g1);
+    const T e1 = w * g1 + (v2 * g0 - v0 * g2);
+    const T e2 = w * g2 + (v0 * g1 - v1 * g0);
+    const T hs = T(0.5) * sc;
+    // body-frame (a) rotation of edge a: -hs Ia (e - e_z e_z/2)
+    const T ka = -hs * Ia;
+    const T da0 = ka * e0, da1 = ka * e1, da2 = T(0.5) * ka * e2;
+    // frame-a rotation of edge b: hs Ib (e - (t.e) t / 2)
+    const T te = T(0.5) * (t0 * e0 + t1 * e1 + t2 * e2);
+    const T kb = hs * Ib;
+    const T dB0 = kb * (e0 - te * t0), dB1 = kb * (e1 - te * t1), dB2 = kb * (e2 - te * t2);
+    // q_a <- normalize(q_a + 1/2 q_a (x) [da, 0])
+    {
+      const T h0 = T(0.5) * da0, h1 = T(0.5) * da1, h2 = T(0.5) * da2;
+      const T nx = a0 + (a3 * h0 + (a1 * h2 - a2 * h1));
+      const T ny = a1 + (a3 * h1 + (a2 * h0 - a0 * h2));
+      const T nz = a2 + (a3 * h2 + (a0 * h1 - a1 * h0));
+      const T nw = a3 - (a0 * h0 + a1 * h1 + a2 * h2);
+      const T in = rsq(nx * nx + ny * ny + nz * nz + nw * nw);
+      L.q0 = nx * in; L.q1 = ny * in; L.q2 = nz * in; L.q3 = nw * in;
+    }
+    // q_b <- normalize(q_b + 1/2 q_a (x) [dB, 0] (x) r_true),  r_true = sg (v, w)
+    {
+      const T h0 = T(0.5) * sg * dB0, h1 = T(0.5) * sg * dB1, h2 = T(0.5) * sg * dB2;
+      // p = [h, 0] (x) (v, w)
+      const T p0 = w * h0 + (h1 * v2 - h2 * v1);
+      const T p1 = w * h1 + (h2 * v0 - h0 * v2);
+      const T p2 = w * h2 + (h0 * v1 - h1 * v0);
+      const T p3 = -(h0 * v0 + h1 * v1 + h2 * v2);
+      // q_a (x) p
+      const T nx = b0 + (a3 * p0 + a0 * p3 + a1 * p2 - a2 * p1);
+      const T ny = b1 + (a3 * p1 - a0 * p2 + a1 * p3 + a2 * p0);
+      const T nz = b2 + (a3 * p2 + a0 * p1 - a1 * p0 + a2 * p3);
+      const T nw = b3 + (a3 * p3 - a0 * p0 - a1 * p1 - a2 * p2);
+      const T in = rsq(nx * nx + ny * ny + nz * nz + nw * nw);
+      b0 = nx * in; b1 = ny * in; b2 = nz * in; b3 = nw * in;
+    }
+    sb += L.wsR * c * (v0 * g0 + v1 * g1 + v2 * g2);
+  }
+  b0 = up(b0); b1 = up(b1); b2 = up(b2); b3 = up(b3); sb = up(sb);
+  const bool recv = (L.f & F_EDGE) && !(L.f & F_FIRST) && (L.f & F_BTEN) && (odd == (colour == 0));
+  if (recv) { L.q0 = b0; L.q1 = b1; L.q2 = b2; L.q3 = b3; L.s = sb; }
+}
+
+template <class T>
+__device__ __forceinline__ void iteration_lane(Lane<T>& L) {
+  pass_edges(L, 0);
+  pass_edges(L, 1);
+  pass_bt(L, 0);
+  pass_bt(L, 1);
+}
+
+// ---------------------------------------------------------------- load / store
+
+template <class T>
+__device__ __forceinline__ int lane_setup(const Dev<T>& d, Lane<T>& L, int& p, bool& valid) {
+  const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int lane = (int)(threadIdx.x & 63);
+  if (wave >= d.W) return -1;
+  const int p0 = d.wave_start[wave];
+  const int n = d.wave_start[wave + 1] - p0;
+  valid = lane < n;
+  p = p0 + (valid ? lane : 0);
+  L.f = valid ? d.flags[p] : 0u;
+  return wave;
+}
+
+template <class T>
+__device__ __forceinline__ void load_state(const Dev<T>& d, Lane<T>& L, int p) {
+  L.x0 = d.px[p]; L.x1 = d.py[p]; L.x2 = d.pz[p];
+  L.v0 = d.vx[p]; L.v1 = d.vy[p]; L.v2 = d.vz[p];
+  L.s = d.s[p]; L.sd = d.sd[p];
+  L.q0 = d.qx[p]; L.q1 = d.qy[p]; L.q2 = d.qz[p]; L.q3 = d.qw[p];
+  L.o0 = d.ox[p]; L.o1 = d.oy[p]; L.o2 = d.oz[p];
+}
+
+template <class T>
+__device__ __forceinline__ void load_consts(const Dev<T>& d, Lane<T>& L, int p, T ih2) {
+  L.w = d.winv[p]; L.ws = d.wsinv[p];
+  L.wR = dn(L.w); L.wsR = dn(L.ws);
+  L.ilb = d.ilb[p]; L.il0 = d.il0[p]; L.cbt = d.cbt[p]; L.inert = d.inert[p];
+  L.db0 = d.dbx[p]; L.db1 = d.dby[p]; L.db2 = d.dbz[p];
+  L.ass = d.css[p] * ih2; L.avol = d.cvol[p] * ih2; L.asg = d.csg[p] * ih2; L.abt = d.cbtc[p] * ih2;
+}
+
+template <class T>
+__device__ __forceinline__ void store_state(const Dev<T>& d, Lane<T>& L, int p) {
+  d.px[p] = L.x0; d.py[p] = L.x1; d.pz[p] = L.x2;
+  d.vx[p] = L.v0; d.vy[p] = L.v1; d.vz[p] = L.v2;
+  d.s[p] = L.s; d.sd[p] = L.sd;
+  if (L.f & F_EDGE) {
+    d.qx[p] = L.q0; d.qy[p] = L.q1; d.qz[p] = L.q2; d.qw[p] = L.q3;
+    d.ox[p] = L.o0; d.oy[p] = L.o1; d.oz[p] = L.o2;
+  }
+}
+
+template <class T>
+__device__ __forceinline__ void check_finite(const Dev<T>& d, const Lane<T>& L) {
+  const T acc = L.x0 + L.x1 + L.x2 + L.s + L.q0 + L.q1 + L.q2 + L.q3;
+  if (!isfinite(acc)) d.status[ST_NAN] = 1;
+}
+
+// ---------------------------------------------------------------- kernels
+
+// FRAME / SUBSTEP mode: nsub substeps with the rod state in registers.
+template <class T>
+__global__ void __launch_bounds__(256) rod_frame_kernel(Dev<T> d, int nsub, T h, int iters) {
+  Lane<T> L;
+  int p;
+  bool valid;
+  if (lane_setup(d, L, p, valid) < 0) return;
+  load_state(d, L, p);
+  const T ih2 = T(1) / (h * h);
+  load_consts(d, L, p, ih2);
+  for (int sub = 0; sub < nsub; ++sub) {
+    predict_lane(L, h, d.gx, d.gy, d.gz);
+    inertia_lane(L);
+    for (int it = 0; it < iters; ++it) iteration_lane(L);
+    velocity_lane(L, h);
+  }
+  if (valid) {
+    store_state(d, L, p);
+    check_finite(d, L);
+  }
+}
+
+// ITERATION mode, stage 1: prediction of every pill and edge, saving the substep-start
+// state and resetting the multipliers.
+template <class T>
+__global__ void __launch_bounds__(256) predict_kernel(Dev<T> d, T h) {
+  Lane<T> L;
+  int p;
+  bool valid;
+  if (lane_setup(d, L, p, valid) < 0) return;
+  load_state(d, L, p);
+  L.w = d.winv[p];
+  L.inert = d.inert[p];
+  predict_lane(L, h, d.gx, d.gy, d.gz);
+  inertia_lane(L);
+  if (valid) {
+    d.px[p] = L.x0; d.py[p] = L.x1; d.pz[p] = L.x2; d.s[p] = L.s;
+    d.qx[p] = L.q0; d.qy[p] = L.q1; d.qz[p] = L.q2; d.qw[p] = L.q3;
+    d.xpx[p] = L.xp0; d.xpy[p] = L.xp1; d.xpz[p] = L.xp2; d.spv[p] = L.sp;
+    d.qpx[p] = L.qp0; d.qpy[p] = L.qp1; d.qpz[p] = L.qp2; d.qpw[p] = L.qp3;
+    d.i1[p] = L.I1;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) d.lam[(size_t)i * d.P + p] = T(0);
+  }
+}
+
+// ITERATION mode, stage 2: one constraint iteration (four colour passes) with the
+// state and multipliers streamed from and back to memory.
+template <class T>
+__global__ void __launch_bounds__(256) rod_iteration_kernel(Dev<T> d, T h) {
+  Lane<T> L;
+  int p;
+  bool valid;
+  if (lane_setup(d, L, p, valid) < 0) return;
+  L.x0 = d.px[p]; L.x1 = d.py[p]; L.x2 = d.pz[p]; L.s = d.s[p];
+  L.q0 = d.qx[p]; L.q1 = d.qy[p]; L.q2 = d.qz[p]; L.q3 = d.qw[p];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) L.l[i] = d.lam[(size_t)i * d.P + p];
+  load_consts(d, L, p, T(1) / (h * h));
+  L.I1 = d.i1[p];
+  L.I1R = dn(L.I1);
+  iteration_lane(L);
+  if (valid) {
+    d.px[p] = L.x0; d.py[p] = L.x1; d.pz[p] = L.x2; d.s[p] = L.s;
+    d.qx[p] = L.q0; d.qy[p] = L.q1; d.qz[p] = L.q2; d.qw[p] = L.q3;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) d.lam[(size_t)i * d.P + p] = L.l[i];
+  }
+}
+
+// ITERATION mode, stage 3: velocity update.
+template <class T>
+__global__ void __launch_bounds__(256) velocity_kernel(Dev<T> d, T h) {
+  Lane<T> L;
+  int p;
+  bool valid;
+  if (lane_setup(d, L, p, valid) < 0) return;
+  if (!valid) return;
+  L.x0 = d.px[p]; L.x1 = d.py[p]; L.x2 = d.pz[p]; L.s = d.s[p];
+  L.q0 = d.qx[p]; L.q1 = d.qy[p]; L.q2 = d.qz[p]; L.q3 = d.qw[p];
+  L.o0 = d.ox[p]; L.o1 = d.oy[p]; L.o2 = d.oz[p];
+  L.xp0 = d.xpx[p]; L.xp1 = d.xpy[p]; L.xp2 = d.xpz[p]; L.sp = d.spv[p];
+  L.qp0 = d.qpx[p]; L.qp1 = d.qpy[p]; L.qp2 = d.qpz[p]; L.qp3 = d.qpw[p];
+  L.w = d.winv[p];
+  velocity_lane(L, h);
+  d.vx[p] = L.v0; d.vy[p] = L.v1; d.vz[p] = L.v2; d.sd[p] = L.sd;
+  if (L.f & F_EDGE) { d.ox[p] = L.o0; d.oy[p] = L.o1; d.oz[p] = L.o2; }
+  check_finite(d, L);
+}
+
+// Field gather/scatter between the SoA layout and a pill-major array.
+template <class T>
+__global__ void gather_kernel(Dev<T> d, int which, T* out) {
+  const int p = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (p >= d.P) return;
+  const bool edge = (d.flags[p] & F_EDGE) != 0;
+  switch (which) {
+    case 0: case 7: out[3 * p] = d.px[p]; out[3 * p + 1] = d.py[p]; out[3 * p + 2] = d.pz[p]; break;
+    case 1: out[3 * p] = d.vx[p]; out[3 * p + 1] = d.vy[p]; out[3 * p + 2] = d.vz[p]; break;
+    case 2: case 8: out[p] = d.s[p]; break;
+    case 3: out[p] = d.sd[p]; break;
+    case 4:
+      out[4 * p] = edge ? d.qx[p] : T(0); out[4 * p + 1] = edge ? d.qy[p] : T(0);
+      out[4 * p + 2] = edge ? d.qz[p] : T(0); out[4 * p + 3] = edge ? d.qw[p] : T(0);
+      break;
+    case 5:
+      out[3 * p] = edge ? d.ox[p] : T(0); out[3 * p + 1] = edge ? d.oy[p] : T(0); out[3 * p + 2] = edge ? d.oz[p] : T(0);
+      break;
+    case 6: out[p] = d.s[p] * d.rbar[p]; break;
+    default: break;
+  }
+}
+
+template <class T>
+__global__ void scatter_kernel(Dev<T> d, int which, const T* in) {
+  const int p = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (p >= d.P) return;
+  const bool edge = (d.flags[p] & F_EDGE) != 0;
+  switch (which) {
+    case 0: d.px[p] = in[3 * p]; d.py[p] = in[3 * p + 1]; d.pz[p] = in[3 * p + 2]; break;
+    case 1: d.vx[p] = in[3 * p]; d.vy[p] = in[3 * p + 1]; d.vz[p] = in[3 * p + 2]; break;
+    case 2: d.s[p] = in[p]; break;
+    case 3: d.sd[p] = in[p]; break;
+    case 4:
+      if (edge) { d.qx[p] = in[4 * p]; d.qy[p] = in[4 * p + 1]; d.qz[p] = in[4 * p + 2]; d.qw[p] = in[4 * p + 3]; }
+      break;
+    case 5:
+      if (edge) { d.ox[p] = in[3 * p]; d.oy[p] = in[3 * p + 1]; d.oz[p] = in[3 * p + 2]; }
+      break;
+    default: break;
+  }
+}
+
+// ---------------------------------------------------------------- skinning (Sec. 7.4)
+
+// Per capsule: M = [ s R(q) R(q_rest)^T | m - s R(q) R(q_rest)^T m_rest ] as 12 floats.
+template <class T>
+__global__ void __launch_bounds__(256) skin_transform_kernel(Dev<T> d, float* xf) {
+  const int p = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (p >= d.P) return;
+  if (!(d.flags[p] & F_EDGE)) return;
+  // relative rotation q (x) conj(q_rest)
+  const T a0 = d.qx[p], a1 = d.qy[p], a2 = d.qz[p], a3 = d.qw[p];
+  const T b0 = -d.qrx[p], b1 = -d.qry[p], b2 = -d.qrz[p], b3 = d.qrw[p];
+  const T x = a3 * b0 + a0 * b3 + a1 * b2 - a2 * b1;
+  const T y = a3 * b1 - a0 * b2 + a1 * b3 + a2 * b0;
+  const T z = a3 * b2 + a0 * b1 - a1 * b0 + a2 * b3;
+  const T w = a3 * b3 - a0 * b0 - a1 * b1 - a2 * b2;
+  const T sm = T(0.5) * (d.s[p] + d.s[p + 1]);
+  const T R00 = T(1) - T(2) * (y * y + z * z), R01 = T(2) * (x * y - w * z), R02 = T(2) * (x * z + w * y);
+  const T R10 = T(2) * (x * y + w * z), R11 = T(1) - T(2) * (x * x + z * z), R12 = T(2) * (y * z - w * x);
+  const T R20 = T(2) * (x * z - w * y), R21 = T(2) * (y * z + w * x), R22 = T(1) - T(2) * (x * x + y * y);
+  const T m0 = T(0.5) * (d.px[p] + d.px[p + 1]), m1 = T(0.5) * (d.py[p] + d.py[p + 1]), m2 = T(0.5) * (d.pz[p] + d.pz[p + 1]);
+  const T r0 = d.mrx[p], r1 = d.mry[p], r2 = d.mrz[p];
+  float* o = xf + (size_t)12 * p;
+  o[0] = (float)(sm * R00); o[1] = (float)(sm * R01); o[2] = (float)(sm * R02);
+  o[3] = (float)(m0 - sm * (R00 * r0 + R01 * r1 + R02 * r2));
+  o[4] = (float)(sm * R10); o[5] = (float)(sm * R11); o[6] = (float)(sm * R12);
+  o[7] = (float)(m1 - sm * (R10 * r0 + R11 * r1 + R12 * r2));
+  o[8] = (float)(sm * R20); o[9] = (float)(sm * R21); o[10] = (float)(sm * R22);
+  o[11] = (float)(m2 - sm * (R20 * r0 + R21 * r1 + R22 * r2));
+}
+
+// Per vertex: 4 gathers of the transform table (L2-resident), one blended affine map.
+__global__ void __launch_bounds__(256) lbs_kernel(int V, const float* __restrict__ rest_v, const int4* __restrict__ caps,
+                                                  const float4* __restrict__ w, const float4* __restrict__ xf,
+                                                  float* __restrict__ out) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i >= V) return;
+  const float vx = rest_v[3 * i], vy = rest_v[3 * i + 1], vz = rest_v[3 * i + 2];
+  const int4 c = caps[i];
+  const float4 wt = w[i];
+  const int ci[4] = {c.x, c.y, c.z, c.w};
+  const float wk[4] = {wt.x, wt.y, wt.z, wt.w};
+  float o0 = 0.f, o1 = 0.f, o2 = 0.f;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const float4 r0 = xf[3 * (size_t)ci[k] + 0];
+    const float4 r1 = xf[3 * (size_t)ci[k] + 1];
+    const float4 r2 = xf[3 * (size_t)ci[k] + 2];
+    o0 += wk[k] * (r0.x * vx + r0.y * vy + r0.z * vz + r0.w);
+    o1 += wk[k] * (r1.x * vx + r1.y * vy + r1.z * vz + r1.w);
+    o2 += wk[k] * (r2.x * vx + r2.y * vy + r2.z * vz + r2.w);
+  }
+  out[3 * i] = o0; out[3 * i + 1] = o1; out[3 * i + 2] = o2;
+}
+
+// ---------------------------------------------------------------- launchers
+
+static inline unsigned wave_blocks(int W) { return (unsigned)((W + 3) / 4); }
+
+template <class T> hipError_t launch_rod_frame(const Dev<T>& d, int nsub, double h, int iters, hipStream_t st) {
+  if (d.W == 0) return hipSuccess;
+  hipLaunchKernelGGL(rod_frame_kernel<T>, dim3(wave_blocks(d.W)), dim3(256), 0, st, d, nsub, (T)h, iters);
+  return hipGetLastError();
+}
+template <class T> hipError_t launch_predict(const Dev<T>& d, double h, hipStream_t st) {
+  if (d.W == 0) return hipSuccess;
+  hipLaunchKernelGGL(predict_kernel<T>, dim3(wave_blocks(d.W)), dim3(256), 0, st, d, (T)h);
+  return hipGetLastError();
+}
+template <class T> hipError_t launch_rod_iteration(const Dev<T>& d, double h, hipStream_t st) {
+  if (d.W == 0) return hipSuccess;
+  hipLaunchKernelGGL(rod_iteration_kernel<T>, dim3(wave_blocks(d.W)), dim3(256), 0, st, d, (T)h);
+  return hipGetLastError();
+}
+template <class T> hipError_t launch_velocity(const Dev<T>& d, double h, hipStream_t st) {
+  if (d.W == 0) return hipSuccess;
+  hipLaunchKernelGGL(velocity_kernel<T>, dim3(wave_blocks(d.W)), dim3(256), 0, st, d, (T)h);
+  return hipGetLastError();
+}
+template <class T> hipError_t launch_gather_field(const Dev<T>& d, int which, T* out, hipStream_t st) {
+  if (d.P == 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_kernel<T>, dim3((d.P + 255) / 256), dim3(256), 0, st, d, which, out);
+  return hipGetLastError();
+}
+template <class T> hipError_t launch_scatter_field(const Dev<T>& d, int which, const T* in, hipStream_t st) {
+  if (d.P == 0) return hipSuccess;
+  hipLaunchKernelGGL(scatter_kernel<T>, dim3((d.P + 255) / 256), dim3(256), 0, st, d, which, in);
+  return hipGetLastError();
+}
+template <class T> hipError_t launch_skin(const Dev<T>& d, int V, const float* rest_v, const int32_t* caps,
+                                          const float* w, float* out, float* xform, hipStream_t st) {
+  if (d.P > 0) hipLaunchKernelGGL(skin_transform_kernel<T>, dim3((d.P + 255) / 256), dim3(256), 0, st, d, xform);
+  if (V > 0)
+    hipLaunchKernelGGL(lbs_kernel, dim3((V + 255) / 256), dim3(256), 0, st, V, rest_v, (const int4*)caps,
+                       (const float4*)w, (const float4*)xform, out);
+  return hipGetLastError();
+}
+
+#define VIPER_INST(T)                                                                                         \
+  template hipError_t launch_rod_frame<T>(const Dev<T>&, int, double, int, hipStream_t);                     \
+  template hipError_t launch_predict<T>(const Dev<T>&, double, hipStream_t);                                 \
+  template hipError_t launch_rod_iteration<T>(const Dev<T>&, double, hipStream_t);                           \
+  template hipError_t launch_velocity<T>(const Dev<T>&, double, hipStream_t);                                \
+  template hipError_t launch_gather_field<T>(const Dev<T>&, int, T*, hipStream_t);                           \
+  template hipError_t launch_scatter_field<T>(const Dev<T>&, int, const T*, hipStream_t);                    \
+  template hipError_t launch_skin<T>(const Dev<T>&, int, const float*, const int32_t*, const float*, float*, \
+                                     float*, hipStream_t);
+VIPER_INST(float)
+VIPER_INST(double)
+
+}  // namespace viper

@@ -1,0 +1,567 @@
+// Host runtime of libviper.so: the C ABI declared in include/viper.h.
+//
+// Scene creation validates the description, computes the rest quantities on
+// the host in FP64 (rest lengths, parallel-transported rest frames, rest
+// Darboux vectors, lumped inverse masses, inertias and compliance scalings),
+// and packs them with the initial state into the caller's workspace as
+// structure-of-arrays.  Steps only enqueue kernels on the caller's stream.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/viper.h"
+#include "viper_dev.h"
+#include "contact.h"
+
+using namespace viper;
+
+namespace {
+
+thread_local std::string g_err;
+
+viper_status fail(viper_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return fail(VIPER_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+const double kPi = 3.14159265358979323846;
+const int kMaxPills = 64;
+
+// ----------------------------------------------------------------------------- layout
+
+struct Layout {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    size_t o = off;
+    off += (bytes + 255) & ~size_t(255);
+    return o;
+  }
+};
+
+// Offsets of every array inside the workspace.
+struct Offsets {
+  size_t state[15];        // px py pz vx vy vz s sd qx qy qz qw ox oy oz
+  size_t pill_rest[3];     // winv wsinv rbar
+  size_t edge_rest[18];    // ilb il0 cbt inert dbx dby dbz css cvol csg cbtc qrx qry qrz qrw mrx mry mrz
+  size_t scratch[10];      // xpx xpy xpz spv qpx qpy qpz qpw i1 lam(8P)
+  size_t flags, wave_start, status, stage, xform;
+  ContactOffsets contact;
+  size_t total;
+};
+
+struct Host {
+  int R = 0, P = 0, W = 0, E = 0;
+  int64_t proj_per_iter = 0;
+  std::vector<int32_t> off, wave_start, group;
+  std::vector<uint32_t> flags;
+  // rest data (FP64)
+  std::vector<double> x, rbar, winv, wsinv;
+  std::vector<double> ilb, il0, cbt, inert, db[3], cs[4], qr[4], mr[3];
+};
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0; }
+
+viper_status validate(const viper_scene_desc* d) {
+  if (!d) return fail(VIPER_ERR_INVALID, "desc is NULL");
+  if (d->num_rods < 0) return fail(VIPER_ERR_INVALID, "num_rods < 0");
+  if (d->num_rods > 0 && (!d->rod_offsets || !d->rest_pos || !d->rest_radius || !d->compliance))
+    return fail(VIPER_ERR_INVALID, "rod_offsets, rest_pos, rest_radius and compliance are required");
+  if (d->precision != VIPER_F32 && d->precision != VIPER_F64) return fail(VIPER_ERR_INVALID, "unknown precision");
+  if (!finite_pos(d->density)) return fail(VIPER_ERR_INVALID, "density must be finite and > 0");
+  for (int i = 0; i < 3; ++i)
+    if (!std::isfinite(d->gravity[i])) return fail(VIPER_ERR_INVALID, "gravity must be finite");
+  if (d->num_rods == 0) return VIPER_OK;
+  if (d->rod_offsets[0] != 0) return fail(VIPER_ERR_INVALID, "rod_offsets[0] must be 0");
+  for (int k = 0; k < d->num_rods; ++k) {
+    int n = d->rod_offsets[k + 1] - d->rod_offsets[k];
+    if (n < 2 || n > kMaxPills)
+      return fail(VIPER_ERR_INVALID, "rod " + std::to_string(k) + " has " + std::to_string(n) +
+                                         " pills; each rod needs 2..64 pills");
+    if (d->activation && !finite_pos(d->activation[k])) return fail(VIPER_ERR_INVALID, "activation must be > 0");
+    for (int t = 0; t < 4; ++t) {
+      double c = d->compliance[4 * k + t];
+      if (std::isnan(c) || c < 0) return fail(VIPER_ERR_INVALID, "compliance must be >= 0 or +inf");
+    }
+  }
+  const int P = d->rod_offsets[d->num_rods];
+  if (P > (1 << 27)) return fail(VIPER_ERR_INVALID, "too many pills");
+  for (int p = 0; p < P; ++p) {
+    if (!finite_pos(d->rest_radius[p])) return fail(VIPER_ERR_INVALID, "rest_radius must be finite and > 0");
+    for (int i = 0; i < 3; ++i)
+      if (!std::isfinite(d->rest_pos[3 * p + i])) return fail(VIPER_ERR_INVALID, "rest_pos must be finite");
+  }
+  for (int k = 0; k < d->num_rods; ++k)
+    for (int p = d->rod_offsets[k]; p + 1 < d->rod_offsets[k + 1]; ++p) {
+      double dx = d->rest_pos[3 * p + 3] - d->rest_pos[3 * p], dy = d->rest_pos[3 * p + 4] - d->rest_pos[3 * p + 1],
+             dz = d->rest_pos[3 * p + 5] - d->rest_pos[3 * p + 2];
+      if (!(dx * dx + dy * dy + dz * dz > 0)) return fail(VIPER_ERR_INVALID, "consecutive rest pills coincide");
+    }
+  return VIPER_OK;
+}
+
+int pack_waves(const viper_scene_desc* d, std::vector<int32_t>& ws) {
+  ws.clear();
+  int start = 0, n = 0;
+  for (int k = 0; k < d->num_rods; ++k) {
+    int len = d->rod_offsets[k + 1] - d->rod_offsets[k];
+    if (n + len > kMaxPills) {
+      ws.push_back(start);
+      start = d->rod_offsets[k];
+      n = 0;
+    }
+    n += len;
+  }
+  if (d->num_rods > 0) ws.push_back(start);
+  ws.push_back(d->num_rods > 0 ? d->rod_offsets[d->num_rods] : 0);
+  return (int)ws.size() - 1;
+}
+
+Offsets make_layout(const viper_scene_desc* d, int P, int W, int E, int cap) {
+  const size_t ts = d->precision == VIPER_F64 ? 8 : 4;
+  Layout L;
+  Offsets o;
+  for (auto& v : o.state) v = L.take(ts * P);
+  for (auto& v : o.pill_rest) v = L.take(ts * P);
+  for (auto& v : o.edge_rest) v = L.take(ts * P);
+  for (int i = 0; i < 9; ++i) o.scratch[i] = L.take(ts * P);
+  o.scratch[9] = L.take(ts * 8 * (size_t)P);
+  o.flags = L.take(4 * (size_t)P);
+  o.wave_start = L.take(4 * (size_t)(W + 1));
+  o.status = L.take(4 * ST_WORDS);
+  o.stage = L.take(ts * 4 * (size_t)P);      // gather/scatter staging
+  o.xform = L.take(4 * 12 * (size_t)P);      // skinning transforms
+  o.contact = contact_layout(L.off, d->collisions != 0, P, E, cap, d->precision == VIPER_F64);
+  L.off = o.contact.end;
+  o.total = L.off;
+  return o;
+}
+
+// Shortest-arc rotation taking unit a onto unit b (x, y, z, w).
+void shortest_arc(const double a[3], const double b[3], double q[4]) {
+  double c = a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+  if (c < -1.0 + 1e-12) {
+    double ax[3];
+    if (std::fabs(a[0]) < 0.9) { ax[0] = 0; ax[1] = a[2]; ax[2] = -a[1]; }   // a x e_x
+    else { ax[0] = -a[2]; ax[1] = 0; ax[2] = a[0]; }                          // a x e_y
+    double n = std::sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
+    q[0] = ax[0] / n; q[1] = ax[1] / n; q[2] = ax[2] / n; q[3] = 0;
+    return;
+  }
+  double x = a[1] * b[2] - a[2] * b[1], y = a[2] * b[0] - a[0] * b[2], z = a[0] * b[1] - a[1] * b[0], w = 1.0 + c;
+  double n = std::sqrt(x * x + y * y + z * z + w * w);
+  q[0] = x / n; q[1] = y / n; q[2] = z / n; q[3] = w / n;
+}
+
+void qmul(const double a[4], const double b[4], double r[4]) {
+  r[0] = a[3] * b[0] + a[0] * b[3] + a[1] * b[2] - a[2] * b[1];
+  r[1] = a[3] * b[1] - a[0] * b[2] + a[1] * b[3] + a[2] * b[0];
+  r[2] = a[3] * b[2] + a[0] * b[1] - a[1] * b[0] + a[2] * b[3];
+  r[3] = a[3] * b[3] - a[0] * b[0] - a[1] * b[1] - a[2] * b[2];
+}
+
+void build_host(const viper_scene_desc* d, Host& H) {
+  H.R = d->num_rods;
+  H.off.assign(d->rod_offsets, d->rod_offsets + H.R + 1);
+  H.P = H.off[H.R];
+  const int P = H.P;
+  H.group.resize(H.R);
+  for (int k = 0; k < H.R; ++k) H.group[k] = d->group ? d->group[k] : k;
+  H.W = pack_waves(d, H.wave_start);
+  H.x.assign(d->rest_pos, d->rest_pos + 3 * (size_t)P);
+  H.rbar.assign(d->rest_radius, d->rest_radius + P);
+  H.flags.assign(P, 0);
+  std::vector<double> M(P, 0.0), Ms(P, 0.0);
+  H.ilb.assign(P, 0); H.il0.assign(P, 0); H.cbt.assign(P, 0); H.inert.assign(P, 0);
+  for (int i = 0; i < 3; ++i) { H.db[i].assign(P, 0); H.mr[i].assign(P, 0); }
+  for (int i = 0; i < 4; ++i) { H.cs[i].assign(P, 0); H.qr[i].assign(P, 0); }
+  for (int p = 0; p < P; ++p) H.qr[3][p] = 1.0;
+  const double rho = d->density;
+  H.E = 0;
+  H.proj_per_iter = 0;
+  std::vector<double> l0(P, 0.0);
+  for (int k = 0; k < H.R; ++k) {
+    const int a = H.off[k], b = H.off[k + 1];
+    const double act = d->activation ? d->activation[k] : 1.0;
+    bool en[4];
+    for (int t = 0; t < 4; ++t) en[t] = std::isfinite(d->compliance[4 * k + t]);
+    uint32_t ef = (en[0] ? F_SS : 0u) | (en[1] ? F_VOL : 0u) | (en[2] ? F_SG : 0u) | (en[3] ? F_BTEN : 0u);
+    double tprev[3] = {0, 0, 1}, qcur[4] = {0, 0, 0, 1};
+    for (int p = a; p < b; ++p) {
+      uint32_t f = F_VALID | ef;
+      if (p == a) f |= F_FIRST;
+      if ((p - a) & 1) f |= F_ODD;
+      if (p + 1 < b) f |= F_EDGE;
+      if (p + 2 < b) f |= F_BT;
+      H.flags[p] = f;
+    }
+    for (int p = a; p + 1 < b; ++p) {
+      double e[3] = {H.x[3 * p + 3] - H.x[3 * p], H.x[3 * p + 4] - H.x[3 * p + 1], H.x[3 * p + 5] - H.x[3 * p + 2]};
+      double len = std::sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+      double t[3] = {e[0] / len, e[1] / len, e[2] / len};
+      double sa[4], qn[4];
+      shortest_arc(tprev, t, sa);
+      qmul(sa, qcur, qn);
+      double n = std::sqrt(qn[0] * qn[0] + qn[1] * qn[1] + qn[2] * qn[2] + qn[3] * qn[3]);
+      for (int i = 0; i < 4; ++i) { qcur[i] = qn[i] / n; H.qr[i][p] = qcur[i]; }
+      for (int i = 0; i < 3; ++i) { tprev[i] = t[i]; H.mr[i][p] = 0.5 * (H.x[3 * p + i] + H.x[3 * p + 3 + i]); }
+      l0[p] = len;
+      H.il0[p] = 1.0 / len;
+      H.ilb[p] = 1.0 / (act * len);
+      const double rm = 0.5 * (H.rbar[p] + H.rbar[p + 1]);
+      const double r2 = rm * rm, r4 = r2 * r2;
+      const double Me = rho * kPi * r2 * len, Mse = rho * kPi * r4 * len / 2.0;
+      M[p] += 0.5 * Me; M[p + 1] += 0.5 * Me;
+      Ms[p] += 0.5 * Mse; Ms[p + 1] += 0.5 * Mse;
+      H.inert[p] = rho * kPi * r4 * len;
+      if (en[0]) H.cs[0][p] = d->compliance[4 * k + 0] / (kPi * r2 * len);
+      if (en[1]) H.cs[1][p] = d->compliance[4 * k + 1] / (kPi * r2 * len);
+      if (en[2]) H.cs[2][p] = d->compliance[4 * k + 2] / (kPi * r4 / 2.0 * len);
+      H.E += 1;
+      H.proj_per_iter += (int64_t)en[0] + en[1] + en[2];
+    }
+    for (int p = a; p + 2 < b; ++p) {
+      const double rv = H.rbar[p + 1], r4 = rv * rv * rv * rv;
+      const double lv = 0.5 * (l0[p] + l0[p + 1]);
+      if (en[3]) H.cs[3][p] = d->compliance[4 * k + 3] / (kPi * r4 / 4.0 * lv);
+      const double c = 4.0 / (l0[p] + l0[p + 1]);
+      H.cbt[p] = c;
+      const double qa[4] = {-H.qr[0][p], -H.qr[1][p], -H.qr[2][p], H.qr[3][p]};
+      const double qb[4] = {H.qr[0][p + 1], H.qr[1][p + 1], H.qr[2][p + 1], H.qr[3][p + 1]};
+      double r[4];
+      qmul(qa, qb, r);
+      const double sg = r[3] < 0 ? -1.0 : 1.0;
+      for (int i = 0; i < 3; ++i) H.db[i][p] = c * sg * r[i];
+      H.proj_per_iter += (int64_t)en[3];
+    }
+  }
+  H.winv.assign(P, 0); H.wsinv.assign(P, 0);
+  for (int p = 0; p < P; ++p) {
+    bool pin = d->pinned && d->pinned[p];
+    H.winv[p] = pin ? 0.0 : 1.0 / M[p];
+    H.wsinv[p] = 1.0 / Ms[p];
+  }
+}
+
+template <class T>
+std::vector<T> cvt(const std::vector<double>& v) {
+  std::vector<T> o(v.size());
+  for (size_t i = 0; i < v.size(); ++i) o[i] = (T)v[i];
+  return o;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------- scene
+
+struct Skin {
+  int V;
+  const float* rest_v;
+  const int32_t* caps;
+  const float* w;
+};
+
+struct viper_scene_s {
+  int precision = 0;
+  int collisions = 0;
+  int cap = 16;
+  int R = 0, P = 0, W = 0, E = 0;
+  int64_t proj_per_iter = 0;
+  char* ws = nullptr;
+  size_t bytes = 0;
+  Offsets o;
+  Dev<float> df;
+  Dev<double> dd;
+  ContactDev cd;
+  std::vector<Skin> skins;
+  std::vector<int32_t> off;  // rod offsets (host copy)
+};
+
+namespace {
+
+template <class T>
+void fill_dev(viper_scene_s* S, Dev<T>& d) {
+  char* b = S->ws;
+  auto P_ = [&](size_t off) { return (T*)(b + off); };
+  d.P = S->P;
+  d.W = S->W;
+  d.wave_start = (const int32_t*)(b + S->o.wave_start);
+  d.flags = (const uint32_t*)(b + S->o.flags);
+  T** st[15] = {&d.px, &d.py, &d.pz, &d.vx, &d.vy, &d.vz, &d.s, &d.sd, &d.qx, &d.qy, &d.qz, &d.qw, &d.ox, &d.oy, &d.oz};
+  for (int i = 0; i < 15; ++i) *st[i] = P_(S->o.state[i]);
+  const T** pr[3] = {&d.winv, &d.wsinv, &d.rbar};
+  for (int i = 0; i < 3; ++i) *pr[i] = P_(S->o.pill_rest[i]);
+  const T** er[18] = {&d.ilb, &d.il0, &d.cbt, &d.inert, &d.dbx, &d.dby, &d.dbz, &d.css, &d.cvol,
+                      &d.csg, &d.cbtc, &d.qrx, &d.qry, &d.qrz, &d.qrw, &d.mrx, &d.mry, &d.mrz};
+  for (int i = 0; i < 18; ++i) *er[i] = P_(S->o.edge_rest[i]);
+  T** sc[9] = {&d.xpx, &d.xpy, &d.xpz, &d.spv, &d.qpx, &d.qpy, &d.qpz, &d.qpw, &d.i1};
+  for (int i = 0; i < 9; ++i) *sc[i] = P_(S->o.scratch[i]);
+  d.lam = P_(S->o.scratch[9]);
+  d.status = (int32_t*)(b + S->o.status);
+}
+
+template <class T>
+viper_status upload(viper_scene_s* S, const Host& H, hipStream_t st) {
+  char* b = S->ws;
+  const int P = H.P;
+  auto put = [&](size_t off, const std::vector<double>& v) -> hipError_t {
+    std::vector<T> t = cvt<T>(v);
+    return hipMemcpyAsync(b + off, t.data(), t.size() * sizeof(T), hipMemcpyHostToDevice, st);
+  };
+  // hipMemcpyAsync from pageable host memory returns after the data is staged, so
+  // the temporaries above may go out of scope.
+  std::vector<double> comp[3];
+  for (int i = 0; i < 3; ++i) {
+    comp[i].resize(P);
+    for (int p = 0; p < P; ++p) comp[i][p] = H.x[3 * (size_t)p + i];
+  }
+  std::vector<double> zero(P, 0.0), one(P, 1.0);
+  for (int i = 0; i < 3; ++i) HIP_TRY(put(S->o.state[i], comp[i]));
+  for (int i = 3; i < 6; ++i) HIP_TRY(put(S->o.state[i], zero));
+  HIP_TRY(put(S->o.state[6], one));
+  HIP_TRY(put(S->o.state[7], zero));
+  for (int i = 0; i < 4; ++i) HIP_TRY(put(S->o.state[8 + i], H.qr[i]));
+  for (int i = 12; i < 15; ++i) HIP_TRY(put(S->o.state[i], zero));
+  HIP_TRY(put(S->o.pill_rest[0], H.winv));
+  HIP_TRY(put(S->o.pill_rest[1], H.wsinv));
+  HIP_TRY(put(S->o.pill_rest[2], H.rbar));
+  const std::vector<double>* er[18] = {&H.ilb, &H.il0, &H.cbt, &H.inert, &H.db[0], &H.db[1], &H.db[2], &H.cs[0],
+                                       &H.cs[1], &H.cs[2], &H.cs[3], &H.qr[0], &H.qr[1], &H.qr[2], &H.qr[3],
+                                       &H.mr[0], &H.mr[1], &H.mr[2]};
+  for (int i = 0; i < 18; ++i) HIP_TRY(put(S->o.edge_rest[i], *er[i]));
+  HIP_TRY(hipMemcpyAsync(b + S->o.flags, H.flags.data(), 4 * (size_t)P, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(b + S->o.wave_start, H.wave_start.data(), 4 * H.wave_start.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemsetAsync(b + S->o.status, 0, 4 * ST_WORDS, st));
+  HIP_TRY(hipStreamSynchronize(st));   // the host staging vectors die with this frame
+  return VIPER_OK;
+}
+
+template <class T> Dev<T>& dev(viper_scene_s* S);
+template <> Dev<float>& dev<float>(viper_scene_s* S) { return S->df; }
+template <> Dev<double>& dev<double>(viper_scene_s* S) { return S->dd; }
+
+template <class T>
+viper_status step_t(viper_scene_s* S, double dt, int sub, int iters, int mode, hipStream_t st) {
+  Dev<T>& d = dev<T>(S);
+  const double h = dt / sub;
+  if (mode == VIPER_MODE_AUTO) mode = S->collisions ? VIPER_MODE_ITERATION : VIPER_MODE_FRAME;
+  if (S->collisions && mode != VIPER_MODE_ITERATION)
+    return fail(VIPER_ERR_INVALID, "scenes with collisions step in VIPER_MODE_ITERATION");
+  if (mode == VIPER_MODE_FRAME) {
+    HIP_TRY(launch_rod_frame<T>(d, sub, h, iters, st));
+  } else if (mode == VIPER_MODE_SUBSTEP) {
+    for (int i = 0; i < sub; ++i) HIP_TRY(launch_rod_frame<T>(d, 1, h, iters, st));
+  } else if (mode == VIPER_MODE_ITERATION) {
+    for (int i = 0; i < sub; ++i) {
+      HIP_TRY(launch_predict<T>(d, h, st));
+      if (S->collisions) HIP_TRY(contact_detect<T>(d, S->cd, st));
+      for (int it = 0; it < iters; ++it) {
+        HIP_TRY(launch_rod_iteration<T>(d, h, st));
+        if (S->collisions) HIP_TRY(contact_project<T>(d, S->cd, st));
+      }
+      HIP_TRY(launch_velocity<T>(d, h, st));
+    }
+  } else {
+    return fail(VIPER_ERR_INVALID, "unknown mode");
+  }
+  return VIPER_OK;
+}
+
+}  // namespace
+
+// ============================================================================= C ABI
+
+extern "C" {
+
+const char* viper_last_error(void) { return g_err.c_str(); }
+
+viper_status viper_scene_footprint(const viper_scene_desc* desc, size_t* bytes) {
+  viper_status s = validate(desc);
+  if (s != VIPER_OK) return s;
+  if (!bytes) return fail(VIPER_ERR_INVALID, "bytes is NULL");
+  std::vector<int32_t> ws;
+  int W = pack_waves(desc, ws);
+  int P = desc->num_rods ? desc->rod_offsets[desc->num_rods] : 0;
+  int E = P - desc->num_rods;
+  int cap = desc->contact_capacity_per_capsule > 0 ? desc->contact_capacity_per_capsule : 16;
+  *bytes = make_layout(desc, P, W, E, cap).total;
+  return VIPER_OK;
+}
+
+viper_status viper_create_scene(const viper_scene_desc* desc, void* workspace, size_t bytes, void* stream,
+                                viper_scene* out) {
+  viper_status s = validate(desc);
+  if (s != VIPER_OK) return s;
+  if (!out) return fail(VIPER_ERR_INVALID, "out is NULL");
+  if (!workspace) return fail(VIPER_ERR_INVALID, "workspace is NULL");
+  if (((uintptr_t)workspace) & 255) return fail(VIPER_ERR_INVALID, "workspace must be 256-byte aligned");
+  Host H;
+  build_host(desc, H);
+  int cap = desc->contact_capacity_per_capsule > 0 ? desc->contact_capacity_per_capsule : 16;
+  Offsets o = make_layout(desc, H.P, H.W, H.E, cap);
+  if (bytes < o.total)
+    return fail(VIPER_ERR_NO_CAPACITY, "workspace too small: need " + std::to_string(o.total) + " bytes");
+  viper_scene_s* S = new viper_scene_s();
+  S->precision = desc->precision;
+  S->collisions = desc->collisions != 0;
+  S->cap = cap;
+  S->R = H.R; S->P = H.P; S->W = H.W; S->E = H.E;
+  S->proj_per_iter = H.proj_per_iter;
+  S->ws = (char*)workspace;
+  S->bytes = bytes;
+  S->o = o;
+  S->off = H.off;
+  hipStream_t st = (hipStream_t)stream;
+  viper_status r;
+  if (S->precision == VIPER_F64) {
+    fill_dev(S, S->dd);
+    S->dd.gx = desc->gravity[0]; S->dd.gy = desc->gravity[1]; S->dd.gz = desc->gravity[2];
+    r = upload<double>(S, H, st);
+  } else {
+    fill_dev(S, S->df);
+    S->df.gx = (float)desc->gravity[0]; S->df.gy = (float)desc->gravity[1]; S->df.gz = (float)desc->gravity[2];
+    r = upload<float>(S, H, st);
+  }
+  if (r == VIPER_OK) r = contact_init(S->cd, S->ws, o.contact, desc, H.off, H.group, st);
+  if (r != VIPER_OK) {
+    delete S;
+    return r;
+  }
+  *out = S;
+  return VIPER_OK;
+}
+
+viper_status viper_step_ex(viper_scene S, double dt, int32_t substeps, int32_t iterations, int32_t mode, void* stream) {
+  if (!S) return fail(VIPER_ERR_INVALID, "scene is NULL");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(VIPER_ERR_INVALID, "dt must be finite and > 0");
+  if (substeps < 1 || iterations < 0) return fail(VIPER_ERR_INVALID, "substeps >= 1 and iterations >= 0 required");
+  hipStream_t st = (hipStream_t)stream;
+  return S->precision == VIPER_F64 ? step_t<double>(S, dt, substeps, iterations, mode, st)
+                                   : step_t<float>(S, dt, substeps, iterations, mode, st);
+}
+
+viper_status viper_step(viper_scene S, double dt, int32_t substeps, int32_t iterations, void* stream) {
+  return viper_step_ex(S, dt, substeps, iterations, VIPER_MODE_AUTO, stream);
+}
+
+static int field_width(int which) {
+  switch (which) {
+    case VIPER_X: case VIPER_V: case VIPER_OMEGA: case VIPER_XDET: return 3;
+    case VIPER_Q: return 4;
+    case VIPER_S: case VIPER_SDOT: case VIPER_RADIUS: case VIPER_SDET: return 1;
+    default: return 0;
+  }
+}
+
+viper_status viper_get_state(viper_scene S, int32_t which, void* dst, void* stream) {
+  if (!S || !dst) return fail(VIPER_ERR_INVALID, "scene and dst are required");
+  int wdt = field_width(which);
+  if (!wdt) return fail(VIPER_ERR_INVALID, "unknown field");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t ts = S->precision == VIPER_F64 ? 8 : 4;
+  void* stage = S->ws + S->o.stage;
+  if (which == VIPER_XDET || which == VIPER_SDET) {
+    if (!S->collisions) return fail(VIPER_ERR_INVALID, "XDET/SDET exist only for scenes with collisions");
+    HIP_TRY(contact_copy_det(S->cd, which == VIPER_XDET, stage, S->P, ts, st));
+  } else if (S->precision == VIPER_F64) {
+    HIP_TRY(launch_gather_field<double>(S->dd, which, (double*)stage, st));
+  } else {
+    HIP_TRY(launch_gather_field<float>(S->df, which, (float*)stage, st));
+  }
+  HIP_TRY(hipMemcpyAsync(dst, stage, ts * wdt * (size_t)S->P, hipMemcpyDefault, st));
+  return VIPER_OK;
+}
+
+viper_status viper_set_state(viper_scene S, int32_t which, const void* src, void* stream) {
+  if (!S || !src) return fail(VIPER_ERR_INVALID, "scene and src are required");
+  int wdt = field_width(which);
+  if (!wdt || which == VIPER_RADIUS || which == VIPER_XDET || which == VIPER_SDET)
+    return fail(VIPER_ERR_INVALID, "field is not writable");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t ts = S->precision == VIPER_F64 ? 8 : 4;
+  void* stage = S->ws + S->o.stage;
+  HIP_TRY(hipMemcpyAsync(stage, src, ts * wdt * (size_t)S->P, hipMemcpyDefault, st));
+  if (S->precision == VIPER_F64) HIP_TRY(launch_scatter_field<double>(S->dd, which, (const double*)stage, st));
+  else HIP_TRY(launch_scatter_field<float>(S->df, which, (const float*)stage, st));
+  return VIPER_OK;
+}
+
+viper_status viper_get_contacts(viper_scene S, int32_t* pairs, int32_t cap, int32_t* n, void* stream) {
+  if (!S || !n) return fail(VIPER_ERR_INVALID, "scene and n are required");
+  if (!S->collisions) { *n = 0; return VIPER_OK; }
+  return contact_get_pairs(S->cd, pairs, cap, n, (hipStream_t)stream);
+}
+
+viper_status viper_create_skin(viper_scene S, int32_t V, const float* rest_v, const int32_t* caps, const float* w,
+                               void* stream, int32_t* skin_id) {
+  if (!S || !skin_id || V < 0) return fail(VIPER_ERR_INVALID, "scene, skin_id and V >= 0 are required");
+  if (V > 0 && (!rest_v || !caps || !w)) return fail(VIPER_ERR_INVALID, "rest_v, caps and w are required");
+  if ((((uintptr_t)caps) & 15) || (((uintptr_t)w) & 15)) return fail(VIPER_ERR_INVALID, "caps and w must be 16-byte aligned");
+  if (V > 0) {
+    std::vector<int32_t> hc(4 * (size_t)V);
+    HIP_TRY(hipMemcpyAsync(hc.data(), caps, hc.size() * 4, hipMemcpyDefault, (hipStream_t)stream));
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    std::vector<uint8_t> is_cap(S->P, 0);
+    for (int k = 0; k < S->R; ++k)
+      for (int p = S->off[k]; p + 1 < S->off[k + 1]; ++p) is_cap[p] = 1;
+    for (size_t i = 0; i < hc.size(); ++i)
+      if (hc[i] < 0 || hc[i] >= S->P || !is_cap[hc[i]])
+        return fail(VIPER_ERR_INVALID, "skin influence " + std::to_string(i) + " is not a capsule id");
+  }
+  S->skins.push_back(Skin{V, rest_v, caps, w});
+  *skin_id = (int32_t)S->skins.size() - 1;
+  return VIPER_OK;
+}
+
+viper_status viper_skin(viper_scene S, int32_t skin_id, float* out, void* stream) {
+  if (!S || skin_id < 0 || skin_id >= (int32_t)S->skins.size()) return fail(VIPER_ERR_INVALID, "bad skin id");
+  const Skin& k = S->skins[skin_id];
+  if (k.V > 0 && !out) return fail(VIPER_ERR_INVALID, "out is NULL");
+  float* xf = (float*)(S->ws + S->o.xform);
+  hipStream_t st = (hipStream_t)stream;
+  if (S->precision == VIPER_F64) HIP_TRY(launch_skin<double>(S->dd, k.V, k.rest_v, k.caps, k.w, out, xf, st));
+  else HIP_TRY(launch_skin<float>(S->df, k.V, k.rest_v, k.caps, k.w, out, xf, st));
+  return VIPER_OK;
+}
+
+viper_status viper_sync(viper_scene S, void* stream) {
+  if (!S) return fail(VIPER_ERR_INVALID, "scene is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  int32_t h[ST_WORDS];
+  HIP_TRY(hipMemcpyAsync(h, S->ws + S->o.status, sizeof(h), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(hipGetLastError());
+  if (h[ST_NAN] || h[ST_OVERFLOW]) {
+    HIP_TRY(hipMemsetAsync(S->ws + S->o.status, 0, sizeof(h), st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (h[ST_NAN]) return fail(VIPER_ERR_NAN, "non-finite state detected");
+    return fail(VIPER_ERR_CAPACITY, "contact buffer overflow: raise contact_capacity_per_capsule");
+  }
+  return VIPER_OK;
+}
+
+viper_status viper_destroy_scene(viper_scene S) {
+  delete S;
+  return VIPER_OK;
+}
+
+viper_status viper_scene_info(viper_scene S, int64_t* pills, int64_t* rods, int64_t* capsules, int64_t* ppi) {
+  if (!S) return fail(VIPER_ERR_INVALID, "scene is NULL");
+  if (pills) *pills = S->P;
+  if (rods) *rods = S->R;
+  if (capsules) *capsules = S->E;
+  if (ppi) *ppi = S->proj_per_iter;
+  return VIPER_OK;
+}
+
+}  // extern "C"

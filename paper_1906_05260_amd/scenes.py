@@ -158,8 +158,8 @@ def muscle_scene(num_muscles=64, seed=2, target_pills=(45000, 55000), rods_range
     rng = np.random.default_rng(seed)
     nr = rng.integers(rods_range[0], rods_range[1] + 1, num_muscles)
     npl = rng.integers(pills_range[0], pills_range[1] + 1, num_muscles)
-    lo, hi = target_pills
     if target_pills is not None:
+        lo, hi = target_pills
         while int((nr * npl).sum()) < lo:
             m = int(rng.integers(num_muscles))
             if rng.random() < 0.5 and nr[m] < rods_range[1]:

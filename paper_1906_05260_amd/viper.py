@@ -1,0 +1,235 @@
+"""ctypes binding of libviper.so (include/viper.h): argument marshalling only.
+
+Every step of the solver runs in the HIP kernels of ``csrc/``; PyTorch only
+provides the device workspace and the stream.  Importing this module on a
+machine where the library is missing raises immediately -- there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libviper.so")
+
+OK, ERR_INVALID, ERR_NO_CAPACITY, ERR_CAPACITY, ERR_NAN, ERR_DEVICE = range(6)
+F32, F64 = 0, 1
+MODE_AUTO, MODE_FRAME, MODE_SUBSTEP, MODE_ITERATION = range(4)
+X, V, S, SDOT, Q, OMEGA, RADIUS, XDET, SDET = range(9)
+FIELD_WIDTH = {X: 3, V: 3, S: 1, SDOT: 1, Q: 4, OMEGA: 3, RADIUS: 1, XDET: 3, SDET: 1}
+FIELD_NAMES = {"x": X, "v": V, "s": S, "sd": SDOT, "q": Q, "om": OMEGA, "radius": RADIUS, "xdet": XDET,
+               "sdet": SDET}
+
+# Every symbol declared in include/viper.h.
+ABI_SYMBOLS = [
+    "viper_scene_footprint", "viper_create_scene", "viper_step", "viper_step_ex", "viper_get_state",
+    "viper_set_state", "viper_get_contacts", "viper_create_skin", "viper_skin", "viper_sync",
+    "viper_destroy_scene", "viper_scene_info", "viper_last_error",
+]
+
+
+class ViperError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("viper status %d: %s" % (status, msg))
+        self.status = status
+
+
+class SceneDescC(ctypes.Structure):
+    _fields_ = [
+        ("num_rods", ctypes.c_int32),
+        ("rod_offsets", ctypes.c_void_p),
+        ("rest_pos", ctypes.c_void_p),
+        ("rest_radius", ctypes.c_void_p),
+        ("pinned", ctypes.c_void_p),
+        ("activation", ctypes.c_void_p),
+        ("compliance", ctypes.c_void_p),
+        ("group", ctypes.c_void_p),
+        ("density", ctypes.c_double),
+        ("gravity", ctypes.c_double * 3),
+        ("precision", ctypes.c_int32),
+        ("collisions", ctypes.c_int32),
+        ("contact_capacity_per_capsule", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libviper.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+        for name in ABI_SYMBOLS:
+            getattr(L, name).restype = ctypes.c_int
+        L.viper_last_error.restype = ctypes.c_char_p
+        L.viper_scene_footprint.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
+        L.viper_create_scene.argtypes = [P, P, ctypes.c_size_t, P, ctypes.POINTER(P)]
+        L.viper_step.argtypes = [P, D, I32, I32, P]
+        L.viper_step_ex.argtypes = [P, D, I32, I32, I32, P]
+        L.viper_get_state.argtypes = [P, I32, P, P]
+        L.viper_set_state.argtypes = [P, I32, P, P]
+        L.viper_get_contacts.argtypes = [P, P, I32, ctypes.POINTER(I32), P]
+        L.viper_create_skin.argtypes = [P, I32, P, P, P, P, ctypes.POINTER(I32)]
+        L.viper_skin.argtypes = [P, I32, P, P]
+        L.viper_sync.argtypes = [P, P]
+        L.viper_destroy_scene.argtypes = [P]
+        L.viper_scene_info.argtypes = [P] + [ctypes.POINTER(ctypes.c_int64)] * 4
+        _lib = L
+    return _lib
+
+
+def check(status):
+    if status != OK:
+        raise ViperError(status, lib().viper_last_error().decode())
+
+
+class _DescHolder:
+    """Keeps the numpy arrays behind a SceneDescC alive."""
+
+    def __init__(self, desc, precision, collisions=None, capacity=16):
+        self.arrays = dict(
+            off=np.ascontiguousarray(desc.rod_offsets, np.int32),
+            pos=np.ascontiguousarray(desc.rest_pos, np.float64).reshape(-1),
+            rad=np.ascontiguousarray(desc.rest_radius, np.float64),
+            pin=np.ascontiguousarray(desc.pinned, np.uint8),
+            act=np.ascontiguousarray(desc.activation, np.float64),
+            comp=np.ascontiguousarray(desc.compliance, np.float64).reshape(-1),
+            grp=np.ascontiguousarray(desc.group, np.int32),
+        )
+        a = self.arrays
+        c = SceneDescC()
+        c.num_rods = int(desc.num_rods)
+        c.rod_offsets = a["off"].ctypes.data
+        c.rest_pos = a["pos"].ctypes.data
+        c.rest_radius = a["rad"].ctypes.data
+        c.pinned = a["pin"].ctypes.data
+        c.activation = a["act"].ctypes.data
+        c.compliance = a["comp"].ctypes.data
+        c.group = a["grp"].ctypes.data
+        c.density = float(desc.density)
+        for i in range(3):
+            c.gravity[i] = float(desc.gravity[i])
+        c.precision = F64 if precision in ("f64", F64) else F32
+        c.collisions = int(bool(desc.collisions if collisions is None else collisions))
+        c.contact_capacity_per_capsule = int(capacity)
+        self.c = c
+
+
+def footprint(desc, precision="f32", collisions=None, capacity=16) -> int:
+    h = _DescHolder(desc, precision, collisions, capacity)
+    n = ctypes.c_size_t(0)
+    check(lib().viper_scene_footprint(ctypes.byref(h.c), ctypes.byref(n)))
+    return int(n.value)
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Scene:
+    """A VIPER scene resident in one device workspace (a torch uint8 tensor)."""
+
+    def __init__(self, desc, precision="f32", device="cuda:0", collisions=None, capacity=16, stream=None,
+                 workspace=None):
+        import torch
+        self.desc = desc
+        self.precision = F64 if precision in ("f64", F64) else F32
+        self.dtype = torch.float64 if self.precision == F64 else torch.float32
+        self.device = torch.device(device)
+        h = _DescHolder(desc, precision, collisions, capacity)
+        nbytes = ctypes.c_size_t(0)
+        check(lib().viper_scene_footprint(ctypes.byref(h.c), ctypes.byref(nbytes)))
+        self.nbytes = int(nbytes.value)
+        if workspace is None:
+            workspace = torch.empty(max(self.nbytes, 256), dtype=torch.uint8, device=self.device)
+        self.workspace = workspace
+        handle = ctypes.c_void_p()
+        check(lib().viper_create_scene(ctypes.byref(h.c), ctypes.c_void_p(workspace.data_ptr()),
+                                       ctypes.c_size_t(workspace.numel()), _stream_ptr(stream),
+                                       ctypes.byref(handle)))
+        self.handle = handle
+        self.P = int(desc.num_pills)
+        self.num_rods = int(desc.num_rods)
+        self._skins = []
+        pills, rods, caps, ppi = (ctypes.c_int64() for _ in range(4))
+        check(lib().viper_scene_info(self.handle, ctypes.byref(pills), ctypes.byref(rods), ctypes.byref(caps),
+                                     ctypes.byref(ppi)))
+        self.capsules = int(caps.value)
+        self.projections_per_iteration = int(ppi.value)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            try:
+                lib().viper_destroy_scene(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    def step(self, dt, substeps, iterations, mode=MODE_AUTO, stream=None):
+        check(lib().viper_step_ex(self.handle, float(dt), int(substeps), int(iterations), int(mode),
+                                  _stream_ptr(stream)))
+
+    def get(self, which, stream=None):
+        import torch
+        which = FIELD_NAMES.get(which, which)
+        out = torch.empty((self.P, FIELD_WIDTH[which]), dtype=self.dtype, device=self.device)
+        check(lib().viper_get_state(self.handle, int(which), ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out if FIELD_WIDTH[which] > 1 else out.view(-1)
+
+    def set(self, which, values, stream=None):
+        import torch
+        which = FIELD_NAMES.get(which, which)
+        t = torch.as_tensor(values).to(device=self.device, dtype=self.dtype).contiguous()
+        assert t.numel() == self.P * FIELD_WIDTH[which]
+        check(lib().viper_set_state(self.handle, int(which), ctypes.c_void_p(t.data_ptr()), _stream_ptr(stream)))
+        self._keep_alive = t
+
+    def state(self):
+        """All state fields as float64 numpy arrays (synchronises)."""
+        import torch
+        out = {k: self.get(k) for k in ("x", "v", "s", "sd", "q", "om")}
+        torch.cuda.synchronize(self.device)
+        return {k: v.double().cpu().numpy() for k, v in out.items()}
+
+    def contacts(self, stream=None):
+        n = ctypes.c_int32(0)
+        st = lib().viper_get_contacts(self.handle, None, 0, ctypes.byref(n), _stream_ptr(stream))
+        if st not in (OK, ERR_NO_CAPACITY):
+            check(st)
+        out = np.zeros((max(int(n.value), 1), 2), np.int32)
+        check(lib().viper_get_contacts(self.handle, ctypes.c_void_p(out.ctypes.data), int(out.shape[0]),
+                                       ctypes.byref(n), _stream_ptr(stream)))
+        return out[: int(n.value)].copy()
+
+    def create_skin(self, rest_v, caps, w, stream=None):
+        import torch
+        rv = torch.as_tensor(rest_v, dtype=torch.float32).to(self.device).contiguous()
+        cp = torch.as_tensor(caps, dtype=torch.int32).to(self.device).contiguous()
+        ww = torch.as_tensor(w, dtype=torch.float32).to(self.device).contiguous()
+        sid = ctypes.c_int32(-1)
+        check(lib().viper_create_skin(self.handle, int(rv.shape[0]), ctypes.c_void_p(rv.data_ptr()),
+                                      ctypes.c_void_p(cp.data_ptr()), ctypes.c_void_p(ww.data_ptr()),
+                                      _stream_ptr(stream), ctypes.byref(sid)))
+        self._skins.append((rv, cp, ww))
+        return int(sid.value)
+
+    def skin(self, skin_id, out=None, stream=None):
+        import torch
+        V = int(self._skins[skin_id][0].shape[0])
+        if out is None:
+            out = torch.empty((V, 3), dtype=torch.float32, device=self.device)
+        check(lib().viper_skin(self.handle, int(skin_id), ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out
+
+    def sync(self, stream=None):
+        check(lib().viper_sync(self.handle, _stream_ptr(stream)))

@@ -1,0 +1,94 @@
+"""Host-only checks of the C ABI: the library loads, exports every declared symbol, and
+validates descriptions / computes footprints without touching a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1906_05260_amd import scenes, viper
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "viper.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(viper_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = viper.lib()
+    names = declared_symbols()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(viper.ABI_SYMBOLS) == names
+
+
+def test_footprint_scales_and_validates():
+    d = scenes.helix_rods(16, 64, seed=1)
+    f32 = viper.footprint(d, "f32")
+    f64 = viper.footprint(d, "f64")
+    assert f64 > f32 > 16 * 64 * 4 * 30
+    d2 = scenes.helix_rods(32, 64, seed=1)
+    assert viper.footprint(d2, "f32") > f32
+    # collisions add the contact buffers
+    assert viper.footprint(d, "f32", collisions=True) > f32
+
+
+@pytest.mark.parametrize("mutate,msg", [
+    (lambda d: d.rest_radius.__setitem__(3, 0.0), "rest_radius"),
+    (lambda d: d.rest_radius.__setitem__(3, np.nan), "rest_radius"),
+    (lambda d: d.compliance.__setitem__((0, 1), -1.0), "compliance"),
+    (lambda d: d.activation.__setitem__(0, 0.0), "activation"),
+    (lambda d: d.rest_pos.__setitem__(1, d.rest_pos[0]), "coincide"),
+])
+def test_invalid_descriptions_rejected(mutate, msg):
+    d = scenes.helix_rods(4, 8, seed=2)
+    mutate(d)
+    with pytest.raises(viper.ViperError) as ei:
+        viper.footprint(d)
+    assert ei.value.status == viper.ERR_INVALID
+    assert msg in str(ei.value)
+
+
+def test_rod_length_limits():
+    ok = scenes.straight_rod(64)
+    viper.footprint(ok)
+    for n in (1, 65):
+        d = scenes.straight_rod(max(n, 2))
+        if n == 1:
+            d.rod_offsets = np.asarray([0, 1], np.int32)
+            d.rest_pos = d.rest_pos[:1]
+        else:
+            d = scenes.straight_rod(65)
+        with pytest.raises(viper.ViperError) as ei:
+            viper.footprint(d)
+        assert ei.value.status == viper.ERR_INVALID
+
+
+def test_infinite_compliance_disables_type():
+    d = scenes.helix_rods(4, 8, seed=2)
+    d.compliance[:, 3] = np.inf
+    viper.footprint(d)
+
+
+def test_create_requires_workspace_and_alignment():
+    L = viper.lib()
+    d = scenes.helix_rods(2, 8, seed=2)
+    h = viper._DescHolder(d, "f32")
+    out = ctypes.c_void_p()
+    assert L.viper_create_scene(ctypes.byref(h.c), None, 0, None, ctypes.byref(out)) == viper.ERR_INVALID
+    assert L.viper_create_scene(ctypes.byref(h.c), ctypes.c_void_p(0x1001), 1 << 30, None,
+                                ctypes.byref(out)) == viper.ERR_INVALID
+    assert L.viper_create_scene(ctypes.byref(h.c), ctypes.c_void_p(0x100000), 16, None,
+                                ctypes.byref(out)) == viper.ERR_NO_CAPACITY
+    assert b"workspace" in L.viper_last_error()
+
+
+def test_step_rejects_bad_arguments_without_gpu():
+    L = viper.lib()
+    assert L.viper_step(None, 1 / 60, 1, 1, None) == viper.ERR_INVALID
+    assert L.viper_sync(None, None) == viper.ERR_INVALID
