@@ -102,7 +102,10 @@ viper_status viper_step_ex(viper_scene scene, double dt, int32_t substeps, int32
 /* State fields for get/set.  Arrays are in the scene's precision (float or double),
  * pill-major: X, V: [P*3]; S (scale), SDOT: [P]; Q (edge quaternion x,y,z,w), [P*4];
  * OMEGA (edge angular velocity, world frame) [P*3]; RADIUS (physical radius s*r) [P];
- * XDET, SDET: positions/scales the last contact detection ran on (read only). */
+ * XDET, SDET: positions/scales the last contact detection ran on (read only; XDET is
+ * always FP64 world coordinates, exactly the values the FP64 candidate test used).
+ * Positions are stored on the device relative to a per-rod anchor (the rest position
+ * of the rod's first pill) and converted to world coordinates in FP64 at this boundary. */
 typedef enum {
   VIPER_X = 0, VIPER_V = 1, VIPER_S = 2, VIPER_SDOT = 3, VIPER_Q = 4, VIPER_OMEGA = 5, VIPER_RADIUS = 6,
   VIPER_XDET = 7, VIPER_SDET = 8

@@ -150,9 +150,15 @@ template <class R> struct Block {
   R out[3];        // resulting correction W J^T dl
 };
 
-// Solve the m x m system S y = b by Cramer's rule (m = 1 or 3).
-template <class R> void solve_small(int m, const R S[3][3], const R b[3], R y[3]) {
-  if (m == 1) { y[0] = b[0] / S[0][0]; return; }
+// Solve the m x m system S y = b by Cramer's rule (m = 1 or 3).  The system is
+// first divided by its largest entry (same solution) so that the cubic
+// determinants stay inside the float range when R = float.
+template <class R> void solve_small(int m, const R S0[3][3], const R b0[3], R y[3]) {
+  if (m == 1) { y[0] = b0[0] / S0[0][0]; return; }
+  R big(0.0);
+  for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) { R a = S0[i][j] < R(0.0) ? -S0[i][j] : S0[i][j]; big = rmax(big, a); }
+  R S[3][3], b[3];
+  for (int i = 0; i < 3; ++i) { b[i] = b0[i] / big; for (int j = 0; j < 3; ++j) S[i][j] = S0[i][j] / big; }
   R det = S[0][0] * (S[1][1] * S[2][2] - S[1][2] * S[2][1]) - S[0][1] * (S[1][0] * S[2][2] - S[1][2] * S[2][0]) +
           S[0][2] * (S[1][0] * S[2][1] - S[1][1] * S[2][0]);
   for (int c = 0; c < 3; ++c) {

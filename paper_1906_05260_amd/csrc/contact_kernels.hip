@@ -38,12 +38,25 @@ __device__ __forceinline__ int cell_of(double m, double cw) {
   return (int)f;
 }
 
+// World position of pill p in FP64: anchor of its rod + stored local offset.
+template <class T>
+__device__ __forceinline__ void world_pos(const Dev<T>& d, int p, double* w) {
+#pragma clang fp contract(off)
+  const double* an = d.anchor + 3 * (size_t)d.rod_of[p];
+  w[0] = an[0] + (double)d.px[p];
+  w[1] = an[1] + (double)d.py[p];
+  w[2] = an[2] + (double)d.pz[p];
+}
+
 // Bounding sphere of capsule p in FP64: centre = midpoint, radius = half length + larger end radius.
 template <class T>
 __device__ void capsule_sphere(const Dev<T>& d, int p, double* out) {
 #pragma clang fp contract(off)
-  const double x0 = (double)d.px[p], y0 = (double)d.py[p], z0 = (double)d.pz[p];
-  const double x1 = (double)d.px[p + 1], y1 = (double)d.py[p + 1], z1 = (double)d.pz[p + 1];
+  double w0[3], w1[3];
+  world_pos(d, p, w0);
+  world_pos(d, p + 1, w1);
+  const double x0 = w0[0], y0 = w0[1], z0 = w0[2];
+  const double x1 = w1[0], y1 = w1[1], z1 = w1[2];
   out[0] = 0.5 * (x0 + x1);
   out[1] = 0.5 * (y0 + y1);
   out[2] = 0.5 * (z0 + z1);
@@ -171,9 +184,9 @@ template <class T>
 __global__ void det_copy_kernel(Dev<T> d, ContactDev c) {
   const int p = (int)(blockIdx.x * blockDim.x + threadIdx.x);
   if (p >= d.P) return;
-  T* xd = (T*)c.xdet;
+  double* xd = (double*)c.xdet;
   T* sdd = (T*)c.sdet;
-  xd[3 * (size_t)p] = d.px[p]; xd[3 * (size_t)p + 1] = d.py[p]; xd[3 * (size_t)p + 2] = d.pz[p];
+  world_pos(d, p, xd + 3 * (size_t)p);
   sdd[p] = d.s[p];
 }
 
@@ -349,7 +362,9 @@ __global__ void __launch_bounds__(256) contact_pair_kernel(Dev<T> d, ContactDev 
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     const int p = pid[t];
-    cp[t] = d3((double)d.px[p], (double)d.py[p], (double)d.pz[p]);
+    double w[3];
+    world_pos(d, p, w);
+    cp[t] = d3(w[0], w[1], w[2]);
     rb[t] = (double)d.rbar[p];
     r[t] = (double)d.s[p] * rb[t];
   }
@@ -465,7 +480,7 @@ ContactOffsets contact_layout(size_t start, bool on, int P, int E, int cpc, bool
   o.entries = take(16 * cap);
   o.delta = take(8 * 16 * cap);
   o.active = take(4 * cap);
-  o.xdet = take(ts * 3 * (size_t)P);
+  o.xdet = take(8 * 3 * (size_t)P);   // FP64 world positions
   o.sdet = take(ts * (size_t)P);
   o.bsum = take(4 * (size_t)nb);
   o.end = off;
@@ -558,7 +573,7 @@ hipError_t contact_project(const Dev<T>& d, ContactDev& c, hipStream_t st) {
 }
 
 hipError_t contact_copy_det(ContactDev& c, bool x, void* dst, int P, size_t ts, hipStream_t st) {
-  return hipMemcpyAsync(dst, x ? c.xdet : c.sdet, (x ? 3 : 1) * ts * (size_t)P, hipMemcpyDeviceToDevice, st);
+  return hipMemcpyAsync(dst, x ? c.xdet : c.sdet, (x ? 3 * 8 : ts) * (size_t)P, hipMemcpyDefault, st);
 }
 
 viper_status contact_get_pairs(ContactDev& c, int32_t* pairs, int32_t cap, int32_t* n, hipStream_t st) {

@@ -217,9 +217,13 @@ __device__ __forceinline__ void pass_bt(Lane<T>& L, int colour) {
     const T S02 = qv * v0 * v2 - ha * u0 * u2 - hb * y0 * y2;
     const T S12 = qv * v1 * v2 - ha * u1 * u2 - hb * y1 * y2;
     const T r0 = -C0 - at * L.l[5], r1 = -C1 - at * L.l[6], r2 = -C2 - T(0.5) * at * L.l[7];
-    const T A00 = S11 * S22 - S12 * S12, A01 = S02 * S12 - S01 * S22, A02 = S01 * S12 - S02 * S11;
-    const T A11 = S00 * S22 - S02 * S02, A12 = S01 * S02 - S00 * S12, A22 = S00 * S11 - S01 * S01;
-    const T idet = T(1) / (S00 * A00 + S01 * A01 + S02 * A02);
+    // The entries reach ~1e14 for thin rods; equilibrate by the trace so that the
+    // cubic determinant stays inside the FP32 range.  S^-1 = adj(sS) s / det(sS).
+    const T sgm = T(1) / (S00 + S11 + S22);
+    const T s00 = S00 * sgm, s11 = S11 * sgm, s22 = S22 * sgm, s01 = S01 * sgm, s02 = S02 * sgm, s12 = S12 * sgm;
+    const T A00 = s11 * s22 - s12 * s12, A01 = s02 * s12 - s01 * s22, A02 = s01 * s12 - s02 * s11;
+    const T A11 = s00 * s22 - s02 * s02, A12 = s01 * s02 - s00 * s12, A22 = s00 * s11 - s01 * s01;
+    const T idet = sgm / (s00 * A00 + s01 * A01 + s02 * A02);
     const T g0 = (A00 * r0 + A01 * r1 + A02 * r2) * idet;
     const T g1 = (A01 * r0 + A11 * r1 + A12 * r2) * idet;
     const T g2 = (A02 * r0 + A12 * r1 + A22 * r2) * idet;
@@ -425,10 +429,15 @@ __global__ void gather_kernel(Dev<T> d, int which, T* out) {
   const int p = (int)(blockIdx.x * blockDim.x + threadIdx.x);
   if (p >= d.P) return;
   const bool edge = (d.flags[p] & F_EDGE) != 0;
+  const double* an = d.anchor + 3 * (size_t)d.rod_of[p];
   switch (which) {
-    case 0: case 7: out[3 * p] = d.px[p]; out[3 * p + 1] = d.py[p]; out[3 * p + 2] = d.pz[p]; break;
+    case 0:
+      out[3 * p] = (T)(an[0] + (double)d.px[p]);
+      out[3 * p + 1] = (T)(an[1] + (double)d.py[p]);
+      out[3 * p + 2] = (T)(an[2] + (double)d.pz[p]);
+      break;
     case 1: out[3 * p] = d.vx[p]; out[3 * p + 1] = d.vy[p]; out[3 * p + 2] = d.vz[p]; break;
-    case 2: case 8: out[p] = d.s[p]; break;
+    case 2: out[p] = d.s[p]; break;
     case 3: out[p] = d.sd[p]; break;
     case 4:
       out[4 * p] = edge ? d.qx[p] : T(0); out[4 * p + 1] = edge ? d.qy[p] : T(0);
@@ -447,8 +456,13 @@ __global__ void scatter_kernel(Dev<T> d, int which, const T* in) {
   const int p = (int)(blockIdx.x * blockDim.x + threadIdx.x);
   if (p >= d.P) return;
   const bool edge = (d.flags[p] & F_EDGE) != 0;
+  const double* an = d.anchor + 3 * (size_t)d.rod_of[p];
   switch (which) {
-    case 0: d.px[p] = in[3 * p]; d.py[p] = in[3 * p + 1]; d.pz[p] = in[3 * p + 2]; break;
+    case 0:
+      d.px[p] = (T)((double)in[3 * p] - an[0]);
+      d.py[p] = (T)((double)in[3 * p + 1] - an[1]);
+      d.pz[p] = (T)((double)in[3 * p + 2] - an[2]);
+      break;
     case 1: d.vx[p] = in[3 * p]; d.vy[p] = in[3 * p + 1]; d.vz[p] = in[3 * p + 2]; break;
     case 2: d.s[p] = in[p]; break;
     case 3: d.sd[p] = in[p]; break;
@@ -481,15 +495,20 @@ __global__ void __launch_bounds__(256) skin_transform_kernel(Dev<T> d, float* xf
   const T R00 = T(1) - T(2) * (y * y + z * z), R01 = T(2) * (x * y - w * z), R02 = T(2) * (x * z + w * y);
   const T R10 = T(2) * (x * y + w * z), R11 = T(1) - T(2) * (x * x + z * z), R12 = T(2) * (y * z - w * x);
   const T R20 = T(2) * (x * z - w * y), R21 = T(2) * (y * z + w * x), R22 = T(1) - T(2) * (x * x + y * y);
-  const T m0 = T(0.5) * (d.px[p] + d.px[p + 1]), m1 = T(0.5) * (d.py[p] + d.py[p + 1]), m2 = T(0.5) * (d.pz[p] + d.pz[p + 1]);
-  const T r0 = d.mrx[p], r1 = d.mry[p], r2 = d.mrz[p];
+  // translation m - s R m_rest in world coordinates (FP64): anchor + local midpoints
+  const double* an = d.anchor + 3 * (size_t)d.rod_of[p];
+  const double m0 = an[0] + 0.5 * ((double)d.px[p] + (double)d.px[p + 1]);
+  const double m1 = an[1] + 0.5 * ((double)d.py[p] + (double)d.py[p + 1]);
+  const double m2 = an[2] + 0.5 * ((double)d.pz[p] + (double)d.pz[p + 1]);
+  const double r0 = an[0] + (double)d.mrx[p], r1 = an[1] + (double)d.mry[p], r2 = an[2] + (double)d.mrz[p];
+  const double s0 = (double)sm;
   float* o = xf + (size_t)12 * p;
   o[0] = (float)(sm * R00); o[1] = (float)(sm * R01); o[2] = (float)(sm * R02);
-  o[3] = (float)(m0 - sm * (R00 * r0 + R01 * r1 + R02 * r2));
+  o[3] = (float)(m0 - s0 * ((double)R00 * r0 + (double)R01 * r1 + (double)R02 * r2));
   o[4] = (float)(sm * R10); o[5] = (float)(sm * R11); o[6] = (float)(sm * R12);
-  o[7] = (float)(m1 - sm * (R10 * r0 + R11 * r1 + R12 * r2));
+  o[7] = (float)(m1 - s0 * ((double)R10 * r0 + (double)R11 * r1 + (double)R12 * r2));
   o[8] = (float)(sm * R20); o[9] = (float)(sm * R21); o[10] = (float)(sm * R22);
-  o[11] = (float)(m2 - sm * (R20 * r0 + R21 * r1 + R22 * r2));
+  o[11] = (float)(m2 - s0 * ((double)R20 * r0 + (double)R21 * r1 + (double)R22 * r2));
 }
 
 // Per vertex: 4 gathers of the transform table (L2-resident), one blended affine map.

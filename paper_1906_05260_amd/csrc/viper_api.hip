@@ -8,6 +8,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -55,7 +56,7 @@ struct Offsets {
   size_t pill_rest[3];     // winv wsinv rbar
   size_t edge_rest[18];    // ilb il0 cbt inert dbx dby dbz css cvol csg cbtc qrx qry qrz qrw mrx mry mrz
   size_t scratch[10];      // xpx xpy xpz spv qpx qpy qpz qpw i1 lam(8P)
-  size_t flags, wave_start, status, stage, xform;
+  size_t flags, wave_start, status, stage, xform, anchor, rod_of;
   ContactOffsets contact;
   size_t total;
 };
@@ -66,7 +67,8 @@ struct Host {
   std::vector<int32_t> off, wave_start, group;
   std::vector<uint32_t> flags;
   // rest data (FP64)
-  std::vector<double> x, rbar, winv, wsinv;
+  std::vector<double> x, rbar, winv, wsinv, anchor, xloc;
+  std::vector<int32_t> rod_of;
   std::vector<double> ilb, il0, cbt, inert, db[3], cs[4], qr[4], mr[3];
 };
 
@@ -139,8 +141,10 @@ Offsets make_layout(const viper_scene_desc* d, int P, int W, int E, int cap) {
   o.flags = L.take(4 * (size_t)P);
   o.wave_start = L.take(4 * (size_t)(W + 1));
   o.status = L.take(4 * ST_WORDS);
-  o.stage = L.take(ts * 4 * (size_t)P);      // gather/scatter staging
+  o.stage = L.take(std::max(ts * 4, (size_t)24) * (size_t)P);   // gather/scatter staging (FP64 XDET: 24 B/pill)
   o.xform = L.take(4 * 12 * (size_t)P);      // skinning transforms
+  o.anchor = L.take(8 * 3 * (size_t)std::max(d->num_rods, 1));
+  o.rod_of = L.take(4 * (size_t)P);
   o.contact = contact_layout(L.off, d->collisions != 0, P, E, cap, d->precision == VIPER_F64);
   L.off = o.contact.end;
   o.total = L.off;
@@ -179,6 +183,17 @@ void build_host(const viper_scene_desc* d, Host& H) {
   for (int k = 0; k < H.R; ++k) H.group[k] = d->group ? d->group[k] : k;
   H.W = pack_waves(d, H.wave_start);
   H.x.assign(d->rest_pos, d->rest_pos + 3 * (size_t)P);
+  H.anchor.assign(3 * (size_t)H.R, 0.0);
+  H.xloc.assign(3 * (size_t)P, 0.0);
+  H.rod_of.assign(P, 0);
+  for (int k = 0; k < H.R; ++k) {
+    const int a = H.off[k];
+    for (int i = 0; i < 3; ++i) H.anchor[3 * k + i] = H.x[3 * (size_t)a + i];
+    for (int p = a; p < H.off[k + 1]; ++p) {
+      H.rod_of[p] = k;
+      for (int i = 0; i < 3; ++i) H.xloc[3 * (size_t)p + i] = H.x[3 * (size_t)p + i] - H.anchor[3 * k + i];
+    }
+  }
   H.rbar.assign(d->rest_radius, d->rest_radius + P);
   H.flags.assign(P, 0);
   std::vector<double> M(P, 0.0), Ms(P, 0.0);
@@ -214,7 +229,7 @@ void build_host(const viper_scene_desc* d, Host& H) {
       qmul(sa, qcur, qn);
       double n = std::sqrt(qn[0] * qn[0] + qn[1] * qn[1] + qn[2] * qn[2] + qn[3] * qn[3]);
       for (int i = 0; i < 4; ++i) { qcur[i] = qn[i] / n; H.qr[i][p] = qcur[i]; }
-      for (int i = 0; i < 3; ++i) { tprev[i] = t[i]; H.mr[i][p] = 0.5 * (H.x[3 * p + i] + H.x[3 * p + 3 + i]); }
+      for (int i = 0; i < 3; ++i) { tprev[i] = t[i]; H.mr[i][p] = 0.5 * (H.xloc[3 * p + i] + H.xloc[3 * p + 3 + i]); }
       l0[p] = len;
       H.il0[p] = 1.0 / len;
       H.ilb[p] = 1.0 / (act * len);
@@ -308,22 +323,26 @@ void fill_dev(viper_scene_s* S, Dev<T>& d) {
   for (int i = 0; i < 9; ++i) *sc[i] = P_(S->o.scratch[i]);
   d.lam = P_(S->o.scratch[9]);
   d.status = (int32_t*)(b + S->o.status);
+  d.anchor = (const double*)(b + S->o.anchor);
+  d.rod_of = (const int32_t*)(b + S->o.rod_of);
 }
 
 template <class T>
 viper_status upload(viper_scene_s* S, const Host& H, hipStream_t st) {
   char* b = S->ws;
   const int P = H.P;
+  // converted host copies stay alive until the stream has drained (end of this function)
+  std::vector<std::vector<T>> keep;
+  keep.reserve(64);
   auto put = [&](size_t off, const std::vector<double>& v) -> hipError_t {
-    std::vector<T> t = cvt<T>(v);
+    keep.push_back(cvt<T>(v));
+    const std::vector<T>& t = keep.back();
     return hipMemcpyAsync(b + off, t.data(), t.size() * sizeof(T), hipMemcpyHostToDevice, st);
   };
-  // hipMemcpyAsync from pageable host memory returns after the data is staged, so
-  // the temporaries above may go out of scope.
   std::vector<double> comp[3];
   for (int i = 0; i < 3; ++i) {
     comp[i].resize(P);
-    for (int p = 0; p < P; ++p) comp[i][p] = H.x[3 * (size_t)p + i];
+    for (int p = 0; p < P; ++p) comp[i][p] = H.xloc[3 * (size_t)p + i];
   }
   std::vector<double> zero(P, 0.0), one(P, 1.0);
   for (int i = 0; i < 3; ++i) HIP_TRY(put(S->o.state[i], comp[i]));
@@ -340,6 +359,8 @@ viper_status upload(viper_scene_s* S, const Host& H, hipStream_t st) {
                                        &H.mr[0], &H.mr[1], &H.mr[2]};
   for (int i = 0; i < 18; ++i) HIP_TRY(put(S->o.edge_rest[i], *er[i]));
   HIP_TRY(hipMemcpyAsync(b + S->o.flags, H.flags.data(), 4 * (size_t)P, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(b + S->o.anchor, H.anchor.data(), 8 * H.anchor.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(b + S->o.rod_of, H.rod_of.data(), 4 * (size_t)P, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(b + S->o.wave_start, H.wave_start.data(), 4 * H.wave_start.size(), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemsetAsync(b + S->o.status, 0, 4 * ST_WORDS, st));
   HIP_TRY(hipStreamSynchronize(st));   // the host staging vectors die with this frame
@@ -478,7 +499,8 @@ viper_status viper_get_state(viper_scene S, int32_t which, void* dst, void* stre
   } else {
     HIP_TRY(launch_gather_field<float>(S->df, which, (float*)stage, st));
   }
-  HIP_TRY(hipMemcpyAsync(dst, stage, ts * wdt * (size_t)S->P, hipMemcpyDefault, st));
+  const size_t es = (which == VIPER_XDET) ? 8 : ts;   // XDET is FP64 in both precisions
+  HIP_TRY(hipMemcpyAsync(dst, stage, es * wdt * (size_t)S->P, hipMemcpyDefault, st));
   return VIPER_OK;
 }
 

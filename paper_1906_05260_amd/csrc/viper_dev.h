@@ -45,6 +45,11 @@ struct Dev {
   T *lam;                    // [8*P] accumulated multipliers: ss(3) vol sg bt(3)
   T *i1;                     // [P] inverse bending inertia of the edge for this substep
   int32_t* status;           // [ST_WORDS]
+  // Positions are stored relative to a per-rod anchor (the rest position of the rod's
+  // first pill), so that FP32 resolves edge vectors independently of where the rod
+  // sits in the world; world = anchor[rod] + local, formed in FP64 where needed.
+  const double* anchor;      // [3*R]
+  const int32_t* rod_of;     // [P]
   T gx, gy, gz;
 };
 

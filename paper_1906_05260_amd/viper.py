@@ -182,7 +182,8 @@ class Scene:
     def get(self, which, stream=None):
         import torch
         which = FIELD_NAMES.get(which, which)
-        out = torch.empty((self.P, FIELD_WIDTH[which]), dtype=self.dtype, device=self.device)
+        dtype = torch.float64 if which == XDET else self.dtype
+        out = torch.empty((self.P, FIELD_WIDTH[which]), dtype=dtype, device=self.device)
         check(lib().viper_get_state(self.handle, int(which), ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
         return out if FIELD_WIDTH[which] > 1 else out.view(-1)
 
