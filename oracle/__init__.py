@@ -106,7 +106,10 @@ class OracleScene:
 
     def __del__(self):
         if getattr(self, "h", None):
-            lib().orc_destroy(self.h)
+            try:
+                lib().orc_destroy(self.h)
+            except Exception:      # interpreter shutdown
+                pass
             self.h = None
 
     def set_state(self, x=None, v=None, s=None, sd=None, q=None, om=None):

