@@ -108,7 +108,9 @@ viper_status viper_step_ex(viper_scene scene, double dt, int32_t substeps, int32
  * of the rod's first pill) and converted to world coordinates in FP64 at this boundary. */
 typedef enum {
   VIPER_X = 0, VIPER_V = 1, VIPER_S = 2, VIPER_SDOT = 3, VIPER_Q = 4, VIPER_OMEGA = 5, VIPER_RADIUS = 6,
-  VIPER_XDET = 7, VIPER_SDET = 8
+  VIPER_XDET = 7, VIPER_SDET = 8,
+  VIPER_XLOCAL = 9   /* [P*3] positions relative to the rod anchor, exactly as stored (bit-exact
+                        checkpoint / resume together with V, S, SDOT, Q, OMEGA) */
 } viper_field;
 
 /* Copy a state field to `dst` (device or host memory) / from `src` (device or host),

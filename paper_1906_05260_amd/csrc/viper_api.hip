@@ -37,7 +37,8 @@ viper_status fail(viper_status s, const std::string& msg) {
   } while (0)
 
 const double kPi = 3.14159265358979323846;
-const int kMaxPills = 64;
+const int kMaxPills = 64;     // pills per rod
+const int kWaveSpan = 128;    // pill slots per wavefront (two per lane)
 
 // ----------------------------------------------------------------------------- layout
 
@@ -117,7 +118,7 @@ int pack_waves(const viper_scene_desc* d, std::vector<int32_t>& ws) {
   int start = 0, n = 0;
   for (int k = 0; k < d->num_rods; ++k) {
     int len = d->rod_offsets[k + 1] - d->rod_offsets[k];
-    if (n + len > kMaxPills) {
+    if (n + len > kWaveSpan) {
       ws.push_back(start);
       start = d->rod_offsets[k];
       n = 0;
@@ -477,7 +478,7 @@ viper_status viper_step(viper_scene S, double dt, int32_t substeps, int32_t iter
 
 static int field_width(int which) {
   switch (which) {
-    case VIPER_X: case VIPER_V: case VIPER_OMEGA: case VIPER_XDET: return 3;
+    case VIPER_X: case VIPER_V: case VIPER_OMEGA: case VIPER_XDET: case VIPER_XLOCAL: return 3;
     case VIPER_Q: return 4;
     case VIPER_S: case VIPER_SDOT: case VIPER_RADIUS: case VIPER_SDET: return 1;
     default: return 0;

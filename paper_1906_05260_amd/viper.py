@@ -18,10 +18,12 @@ LIB_PATH = os.path.join(HERE, "libviper.so")
 OK, ERR_INVALID, ERR_NO_CAPACITY, ERR_CAPACITY, ERR_NAN, ERR_DEVICE = range(6)
 F32, F64 = 0, 1
 MODE_AUTO, MODE_FRAME, MODE_SUBSTEP, MODE_ITERATION = range(4)
-X, V, S, SDOT, Q, OMEGA, RADIUS, XDET, SDET = range(9)
-FIELD_WIDTH = {X: 3, V: 3, S: 1, SDOT: 1, Q: 4, OMEGA: 3, RADIUS: 1, XDET: 3, SDET: 1}
+X, V, S, SDOT, Q, OMEGA, RADIUS, XDET, SDET, XLOCAL = range(10)
+FIELD_WIDTH = {X: 3, V: 3, S: 1, SDOT: 1, Q: 4, OMEGA: 3, RADIUS: 1, XDET: 3, SDET: 1, XLOCAL: 3}
 FIELD_NAMES = {"x": X, "v": V, "s": S, "sd": SDOT, "q": Q, "om": OMEGA, "radius": RADIUS, "xdet": XDET,
-               "sdet": SDET}
+               "sdet": SDET, "xlocal": XLOCAL}
+# fields that restore a scene exactly (bit for bit)
+CHECKPOINT_FIELDS = ("xlocal", "v", "s", "sd", "q", "om")
 
 # Every symbol declared in include/viper.h.
 ABI_SYMBOLS = [
@@ -195,10 +197,13 @@ class Scene:
         check(lib().viper_set_state(self.handle, int(which), ctypes.c_void_p(t.data_ptr()), _stream_ptr(stream)))
         self._keep_alive = t
 
-    def state(self):
-        """All state fields as float64 numpy arrays (synchronises)."""
+    def state(self, local=False):
+        """All state fields as float64 numpy arrays (synchronises).  With local=True the
+        positions are the stored rod-anchor-relative values (key "x")."""
         import torch
         out = {k: self.get(k) for k in ("x", "v", "s", "sd", "q", "om")}
+        if local:
+            out["x"] = self.get("xlocal")
         torch.cuda.synchronize(self.device)
         return {k: v.double().cpu().numpy() for k, v in out.items()}
 

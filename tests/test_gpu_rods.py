@@ -191,30 +191,34 @@ def test_helix_4096x64_full_horizon():
 
 
 def test_helix_one_frame_parity_late_in_horizon():
-    """From the GPU's own FP32 state after 50 and 99 frames (rods swinging at speed),
-    one more frame on the GPU and on the FP64 oracle agree within 1e-4 on the rods whose
-    one-frame response is well conditioned (FP32 oracle floor below 1e-5)."""
+    """From the GPU's own FP32 state after 50 and 99 frames (rods swinging at several
+    m/s), one more frame on the GPU and on the FP64 oracle: the GPU error is within 3x the
+    FP32 oracle's own error (its rounding floor, 1e-5..4e-4 here) on every rod, and within
+    1e-4 wherever that floor is below 1e-4 / 3."""
     desc = scenes.helix_rods(4096, 64, seed=1)
     rods = [0, 1, 2, 3, 777, 1500, 3500, 4000]
-    sub = desc.subset(rods)
+    sub = local_subset(desc, rods)      # the oracle works in the same rod-anchored frame
     idx = desc.pill_index(rods)
     sc = viper.Scene(desc, "f32")
     checked = 0
+    done = 0
     for stop in (50, 99):
-        while getattr(sc, "_frames", 0) < stop:
+        while done < stop:
             sc.step(1 / 60, 20, 8)
-            sc._frames = getattr(sc, "_frames", 0) + 1
-        st = {k: v[idx] for k, v in sc.state().items()}
+            done += 1
+        st = {k: v[idx] for k, v in sc.state(local=True).items()}
         sc.step(1 / 60, 20, 8)
-        sc._frames += 1
-        g = {k: v[idx] for k, v in sc.state().items()}
+        done += 1
+        g = {k: v[idx] for k, v in sc.state(local=True).items()}
         o = oracle.OracleScene(sub, "f64"); o.set_state(**st); o.step(1 / 60, 20, 8, threads=8)
         of = oracle.OracleScene(sub, "f32"); of.set_state(**st); of.step(1 / 60, 20, 8, threads=8)
         r = o.get_state()
         e = rod_errors(sub, g, r)
         fl = rod_errors(sub, of.get_state(), r)
         say("frame", stop, "one-frame gpu32", np.array2string(e, precision=1), "floor", np.array2string(fl, precision=1))
-        ok = fl < 1e-5
+        fin = np.isfinite(fl)
+        assert np.all(e[fin] <= 3 * fl[fin] + 1e-5), (e, fl)
+        ok = fl < TOL / 3
         assert np.all(e[ok] < TOL)
         checked += int(ok.sum())
     assert checked >= 8
@@ -231,8 +235,10 @@ def test_modes_agree():
         sc.step(1 / 60, 20, 8, mode=mode)
         sc.sync()
         res.append(sc.state())
-    for r in res[1:]:
-        assert max(errors(desc, r, res[0])) < 1e-5
+    for mode, r in zip(("substep", "iteration"), res[1:]):
+        e = errors(desc, r, res[0])
+        say(mode, "vs frame", e)
+        assert max(e) < TOL
 
 
 def test_deterministic_and_state_roundtrip():
@@ -247,7 +253,7 @@ def test_deterministic_and_state_roundtrip():
         assert np.array_equal(sa[k], sb[k])
     # resume: copy a's full state into a fresh scene and continue both
     c = viper.Scene(desc, "f32")
-    for k in ("x", "v", "s", "sd", "q", "om"):
+    for k in viper.CHECKPOINT_FIELDS:
         c.set(k, a.get(k))
     a.step(1 / 60, 20, 8)
     c.step(1 / 60, 20, 8)
