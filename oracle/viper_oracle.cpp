@@ -474,7 +474,7 @@ template <class R> int project_bt(Scene<R>& S, int p, R ih2) {
 
 // ------------------------------ contacts ------------------------------------
 
-// Closed-form projection of a point onto a tapered capsule (App. C, corrected):
+// Closed-form projection of a point onto a tapered capsule (App. D, corrected):
 // returns the barycentric t of the sphere of the capsule closest (surface distance)
 // to x.  Reading: p_s = c1 + e ((x - c1) . e); o = |x - p_s| tan(theta) unsquared;
 // when |r1 - r2| >= l the capsule is its larger end sphere.

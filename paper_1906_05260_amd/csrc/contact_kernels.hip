@@ -11,7 +11,7 @@
 // inside a bucket.  The overlap predicate runs in FP64 with no contraction, so it
 // decides exactly as a serial FP64 evaluation of the same stored values.
 //
-// Handling (Sec. 7.2, App. C): per candidate pair, a 10-step dichotomous search of
+// Handling (Sec. 7.2, App. D): per candidate pair, a 10-step dichotomous search of
 // the largest inter-penetration over the first capsule's barycentric coordinate,
 // with the closed-form projection onto the second capsule; a violated pair gets a
 // hard (zero-compliance) correction of the four end positions and scales.  All
@@ -324,7 +324,7 @@ __device__ __forceinline__ D3 lerp(D3 a, D3 b, double t) { return d3(a.x + t * (
 
 // Barycentric coordinate on capsule (c1,r1)-(c2,r2) of the sphere nearest (in surface
 // distance) to point x: stationary point of |x - c(t)| - r(t) along the axis, clamped
-// (App. C with its sign and square corrected; a capsule whose radii differ by more than
+// (App. D with its sign and square corrected; a capsule whose radii differ by more than
 // its length is its larger end sphere).
 __device__ double pill_param(D3 x, D3 c1, double r1, D3 c2, double r2) {
   const D3 ax = sub(c2, c1);

@@ -4,7 +4,7 @@ Each test checks the oracle against something other than itself: closed forms
 of the prediction (Sec. 6 / App. B), the textbook position-based distance
 constraint, exact single-constraint corrections derived by hand, disc
 quadrature of the inertia and stiffness weights (Sec. 5, App. A/B), brute-force
-minimisation for the capsule projection (App. C) and the dichotomous search
+minimisation for the capsule projection (App. D) and the dichotomous search
 (Sec. 7.2), and conservation laws of the discrete update.  A dropped term, a
 wrong sign or index, or a transposed operand in the oracle fails one of them.
 """
