@@ -145,6 +145,28 @@ viper_status viper_scene_info(viper_scene scene, int64_t* pills, int64_t* rods, 
 
 const char* viper_last_error(void);
 
+/* ---- Serving pool: continuous batching of many scenes in one workspace ----------------
+ * The pool owns no device memory either: the caller hands in one workspace.  Scenes are
+ * admitted by footprint (first-fit inside the workspace; VIPER_ERR_NO_CAPACITY when no
+ * free range or slot fits, nothing changed), stay resident on the device, and every
+ * viper_pool_step advances every resident scene by one frame: all collision-free scenes
+ * in one launch over a shared block table, all scenes with contacts through one shared
+ * sequence of launches on a second stream that overlaps the first.  A scene admitted
+ * while a step runs joins at the next step; uploads of new scenes do not touch resident
+ * state.  All scenes of a pool share `precision`.  The scene handles of a pool
+ * (viper_pool_scene) serve viper_get_state / viper_set_state / viper_get_contacts /
+ * viper_sync and must not be destroyed by the caller. */
+typedef struct viper_pool_s* viper_pool;
+viper_status viper_pool_create(void* workspace, size_t bytes, int32_t max_scenes, int32_t precision, void* stream,
+                               viper_pool* out);
+viper_status viper_pool_admit(viper_pool pool, const viper_scene_desc* desc, void* stream, int32_t* slot);
+viper_status viper_pool_step(viper_pool pool, double dt, int32_t substeps, int32_t iterations, void* stream);
+viper_status viper_pool_retire(viper_pool pool, int32_t slot, void* stream);
+viper_status viper_pool_scene(viper_pool pool, int32_t slot, viper_scene* scene);
+viper_status viper_pool_info(viper_pool pool, size_t* free_bytes, size_t* largest_free, int32_t* resident,
+                             int64_t* resident_pills);
+viper_status viper_pool_destroy(viper_pool pool);
+
 #ifdef __cplusplus
 }
 #endif

@@ -75,20 +75,61 @@ __device__ bool spheres_overlap(const double* a, const double* b) {
   return d2 < rr * rr;
 }
 
-__global__ void fill_kernel(int32_t* p, int n, int32_t v) {
-  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-  if (i < n) p[i] = v;
+// ---- block-table helpers
+
+#define BLOCK_SCENE(tab, D, CD)                 \
+  const Blk blk_ = (tab)[blockIdx.x];           \
+  const Dev<T>& d = (D)[blk_.scene];            \
+  const ContactDev& c = (CD)[blk_.scene];       \
+  (void)d; (void)c;
+
+// Zero the per-substep hash-cell counters.
+__global__ void __launch_bounds__(256) zero_cells_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
+  const Blk b = tab[blockIdx.x];
+  const ContactDev& c = CD[b.scene];
+  const int i = b.base + (int)threadIdx.x;
+  if (i >= c.T) return;
+  c.cell_cnt[i] = 0;
+  c.cell_cur[i] = 0;
 }
 
-__global__ void clear_max_kernel(unsigned long long* p) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) p[0] = 0ull;
+// Copy the detection state (FP64 world positions, scales), zero the per-pill counters and
+// the largest-radius register.
+template <class T>
+__global__ void __launch_bounds__(256) det_copy_kernel(const Dev<T>* __restrict__ D, const ContactDev* __restrict__ CD,
+                                                       const Blk* __restrict__ tab) {
+  BLOCK_SCENE(tab, D, CD)
+  const int p = blk_.base + (int)threadIdx.x;
+  if (p == 0) c.maxr[0] = 0ull;
+  if (p >= d.P) return;
+  world_pos(d, p, c.xdet + 3 * (size_t)p);
+  ((T*)c.sdet)[p] = d.s[p];
+  c.pill_cnt[p] = 0;
+  c.pill_cur[p] = 0;
 }
 
-// ---- exclusive scan of n int32 (out[n] = total), 1024 items per block
-__global__ void __launch_bounds__(256) scan_block_kernel(const int32_t* in, int32_t* out, int n, int32_t* bsum) {
+// ---- exclusive scans (out[n] = total), 1024 items per block, one array per scene:
+// WHICH = 0: hash-cell counts, 1: candidate counts per capsule, 2: CSR counts per pill.
+// The selection is a template parameter: each scan kernel is compiled for one array, so
+// no kernel selects its pointers through a runtime branch.
+template <int WHICH>
+__device__ __forceinline__ void scan_arrays(const ContactDev& c, const int32_t*& in, int32_t*& out, int& n) {
+  if constexpr (WHICH == 0) { in = c.cell_cnt; out = c.cell_start; n = c.T; }
+  else if constexpr (WHICH == 1) { in = c.pcount; out = c.poff; n = c.E; }
+  else { in = c.pill_cnt; out = c.pill_start; n = c.P; }
+}
+
+template <int WHICH>
+__global__ void __launch_bounds__(256) scan_block_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
   __shared__ int32_t sh[256];
+  const Blk b = tab[blockIdx.x];
+  const ContactDev& c = CD[b.scene];
+  const int32_t* in;
+  int32_t* out;
+  int n;
+  scan_arrays<WHICH>(c, in, out, n);
   const int t = (int)threadIdx.x;
-  const int base = (int)blockIdx.x * 1024 + 4 * t;
+  const int base = b.base + 4 * t;
   int v[4];
   int s = 0;
 #pragma unroll
@@ -107,18 +148,26 @@ __global__ void __launch_bounds__(256) scan_block_kernel(const int32_t* in, int3
     if (base + k < n) out[base + k] = run;
     run += v[k];
   }
-  if (t == 255) bsum[blockIdx.x] = sh[255];
+  if (t == 255) c.bsum[b.base / 1024] = sh[255];
 }
 
-__global__ void __launch_bounds__(1024) scan_sums_kernel(int32_t* bsum, int nb, int32_t* total) {
+// One block per scene: exclusive scan of its block sums; writes the total to out[n].
+template <int WHICH>
+__global__ void __launch_bounds__(1024) scan_sums_kernel(const ContactDev* __restrict__ CD) {
   __shared__ int32_t sh[1024];
   __shared__ int32_t carry;
+  const ContactDev& c = CD[blockIdx.x];
+  const int32_t* in;
+  int32_t* out;
+  int n;
+  scan_arrays<WHICH>(c, in, out, n);
+  const int nb = (n + 1023) / 1024;
   const int t = (int)threadIdx.x;
   if (t == 0) carry = 0;
   __syncthreads();
   for (int base = 0; base < nb; base += 1024) {
     const int idx = base + t;
-    const int v = (idx < nb) ? bsum[idx] : 0;
+    const int v = (idx < nb) ? c.bsum[idx] : 0;
     sh[t] = v;
     __syncthreads();
     for (int o = 1; o < 1024; o <<= 1) {
@@ -127,40 +176,37 @@ __global__ void __launch_bounds__(1024) scan_sums_kernel(int32_t* bsum, int nb, 
       sh[t] += x;
       __syncthreads();
     }
-    if (idx < nb) bsum[idx] = carry + sh[t] - v;
+    if (idx < nb) c.bsum[idx] = carry + sh[t] - v;
     __syncthreads();
     if (t == 1023) carry += sh[1023];
     __syncthreads();
   }
-  if (t == 0) total[0] = carry;
+  if (t == 0) out[n] = carry;
 }
 
-__global__ void __launch_bounds__(256) scan_add_kernel(int32_t* out, int n, const int32_t* bsum) {
-  const int base = (int)blockIdx.x * 1024 + 4 * (int)threadIdx.x;
-  const int add = bsum[blockIdx.x];
+template <int WHICH>
+__global__ void __launch_bounds__(256) scan_add_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
+  const Blk b = tab[blockIdx.x];
+  const ContactDev& c = CD[b.scene];
+  const int32_t* in;
+  int32_t* out;
+  int n;
+  scan_arrays<WHICH>(c, in, out, n);
+  const int base = b.base + 4 * (int)threadIdx.x;
+  const int add = c.bsum[b.base / 1024];
 #pragma unroll
   for (int k = 0; k < 4; ++k)
     if (base + k < n) out[base + k] += add;
 }
 
-hipError_t scan(const int32_t* in, int32_t* out, int n, int32_t* bsum, hipStream_t st) {
-  const int nb = (n + 1023) / 1024;
-  if (nb == 0) {
-    hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, st, out, 1, 0);
-    return hipGetLastError();
-  }
-  hipLaunchKernelGGL(scan_block_kernel, dim3(nb), dim3(256), 0, st, in, out, n, bsum);
-  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(1024), 0, st, bsum, nb, out + n);
-  hipLaunchKernelGGL(scan_add_kernel, dim3(nb), dim3(256), 0, st, out, n, bsum);
-  return hipGetLastError();
-}
-
 // ---- detection
 
 template <class T>
-__global__ void __launch_bounds__(256) sphere_kernel(Dev<T> d, ContactDev c) {
+__global__ void __launch_bounds__(256) sphere_kernel(const Dev<T>* __restrict__ D, const ContactDev* __restrict__ CD,
+                                                     const Blk* __restrict__ tab) {
   __shared__ double sh[256];
-  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  BLOCK_SCENE(tab, D, CD)
+  const int i = blk_.base + (int)threadIdx.x;
   double R = 0.0;
   if (i < c.E) {
     double sp[4];
@@ -180,35 +226,29 @@ __global__ void __launch_bounds__(256) sphere_kernel(Dev<T> d, ContactDev c) {
   if (threadIdx.x == 0) atomicMax(c.maxr, (unsigned long long)__double_as_longlong(sh[0]));
 }
 
-template <class T>
-__global__ void det_copy_kernel(Dev<T> d, ContactDev c) {
-  const int p = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-  if (p >= d.P) return;
-  double* xd = (double*)c.xdet;
-  T* sdd = (T*)c.sdet;
-  world_pos(d, p, xd + 3 * (size_t)p);
-  sdd[p] = d.s[p];
-}
-
 __device__ __forceinline__ double cell_width(const ContactDev& c) {
   const double R = __longlong_as_double((long long)c.maxr[0]);
   return (R > 0.0) ? 2.0 * R * (1.0 + 1e-6) : 1.0;
 }
 
-__global__ void __launch_bounds__(256) key_kernel(ContactDev c, int32_t* cell) {
-  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+__global__ void __launch_bounds__(256) key_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
+  const Blk b = tab[blockIdx.x];
+  const ContactDev& c = CD[b.scene];
+  const int i = b.base + (int)threadIdx.x;
   if (i >= c.E) return;
   const double cw = cell_width(c);
   const int cx = cell_of(c.sph[4 * (size_t)i], cw), cy = cell_of(c.sph[4 * (size_t)i + 1], cw),
             cz = cell_of(c.sph[4 * (size_t)i + 2], cw);
-  cell[3 * (size_t)i] = cx; cell[3 * (size_t)i + 1] = cy; cell[3 * (size_t)i + 2] = cz;
+  c.cell[3 * (size_t)i] = cx; c.cell[3 * (size_t)i + 1] = cy; c.cell[3 * (size_t)i + 2] = cz;
   const uint32_t h = cell_hash(cx, cy, cz, c.T);
   c.key[i] = (int32_t)h;
   atomicAdd(&c.cell_cnt[h], 1);
 }
 
-__global__ void __launch_bounds__(256) bucket_scatter_kernel(ContactDev c) {
-  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+__global__ void __launch_bounds__(256) bucket_scatter_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
+  const Blk b = tab[blockIdx.x];
+  const ContactDev& c = CD[b.scene];
+  const int i = b.base + (int)threadIdx.x;
   if (i >= c.E) return;
   const int h = c.key[i];
   const int pos = c.cell_start[h] + atomicAdd(&c.cell_cur[h], 1);
@@ -217,9 +257,12 @@ __global__ void __launch_bounds__(256) bucket_scatter_kernel(ContactDev c) {
 
 // Count (EMIT = false) or emit (EMIT = true) the candidates b > a of capsule a.
 template <bool EMIT>
-__global__ void __launch_bounds__(256) pair_kernel(ContactDev c, const int32_t* cell) {
-  const int a = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+__global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
+  const Blk blk = tab[blockIdx.x];
+  const ContactDev& c = CD[blk.scene];
+  const int a = blk.base + (int)threadIdx.x;
   if (a >= c.E) return;
+  const int32_t* cell = c.cell;
   const double sa[4] = {c.sph[4 * (size_t)a], c.sph[4 * (size_t)a + 1], c.sph[4 * (size_t)a + 2], c.sph[4 * (size_t)a + 3]};
   const int ra = c.cap_rod[a], ga = c.cap_grp[a];
   const int cx = cell[3 * (size_t)a], cy = cell[3 * (size_t)a + 1], cz = cell[3 * (size_t)a + 2];
@@ -270,15 +313,19 @@ __global__ void __launch_bounds__(256) pair_kernel(ContactDev c, const int32_t* 
   }
 }
 
-__global__ void finalize_kernel(ContactDev c) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+// One thread per scene (launched with one block per scene).
+__global__ void finalize_kernel(const ContactDev* __restrict__ CD) {
+  if (threadIdx.x != 0) return;
+  const ContactDev& c = CD[blockIdx.x];
   const int total = c.poff[c.E];
   c.npairs[0] = min(total, c.cap);
   if (total > c.cap) c.status[ST_OVERFLOW] = 1;
 }
 
-__global__ void __launch_bounds__(256) csr_count_kernel(ContactDev c) {
-  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+__global__ void __launch_bounds__(256) csr_count_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
+  const Blk blk = tab[blockIdx.x];
+  const ContactDev& c = CD[blk.scene];
+  const int i = blk.base + (int)threadIdx.x;
   if (i >= c.npairs[0]) return;
   const int a = c.pairs[2 * (size_t)i], b = c.pairs[2 * (size_t)i + 1];
   atomicAdd(&c.pill_cnt[a], 1);
@@ -287,8 +334,10 @@ __global__ void __launch_bounds__(256) csr_count_kernel(ContactDev c) {
   atomicAdd(&c.pill_cnt[b + 1], 1);
 }
 
-__global__ void __launch_bounds__(256) csr_fill_kernel(ContactDev c) {
-  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+__global__ void __launch_bounds__(256) csr_fill_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
+  const Blk blk = tab[blockIdx.x];
+  const ContactDev& c = CD[blk.scene];
+  const int i = blk.base + (int)threadIdx.x;
   if (i >= c.npairs[0]) return;
   const int a = c.pairs[2 * (size_t)i], b = c.pairs[2 * (size_t)i + 1];
   const int pid[4] = {a, a + 1, b, b + 1};
@@ -299,8 +348,10 @@ __global__ void __launch_bounds__(256) csr_fill_kernel(ContactDev c) {
   }
 }
 
-__global__ void __launch_bounds__(256) csr_sort_kernel(ContactDev c) {
-  const int p = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+__global__ void __launch_bounds__(256) csr_sort_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
+  const Blk blk = tab[blockIdx.x];
+  const ContactDev& c = CD[blk.scene];
+  const int p = blk.base + (int)threadIdx.x;
   if (p >= c.P) return;
   const int s0 = c.pill_start[p], n = c.pill_start[p + 1] - s0;
   for (int i = 1; i < n; ++i) {
@@ -352,8 +403,10 @@ __device__ double gap_at(const D3* c, const double* r, double al) {
 }
 
 template <class T>
-__global__ void __launch_bounds__(256) contact_pair_kernel(Dev<T> d, ContactDev c) {
-  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+__global__ void __launch_bounds__(256) contact_pair_kernel(const Dev<T>* __restrict__ D, const ContactDev* __restrict__ CD,
+                                                           const Blk* __restrict__ tab) {
+  BLOCK_SCENE(tab, D, CD)
+  const int i = blk_.base + (int)threadIdx.x;
   if (i >= c.npairs[0]) return;
   const int a = c.pairs[2 * (size_t)i], b = c.pairs[2 * (size_t)i + 1];
   const int pid[4] = {a, a + 1, b, b + 1};
@@ -413,8 +466,10 @@ __global__ void __launch_bounds__(256) contact_pair_kernel(Dev<T> d, ContactDev 
 }
 
 template <class T>
-__global__ void __launch_bounds__(256) contact_gather_kernel(Dev<T> d, ContactDev c) {
-  const int p = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+__global__ void __launch_bounds__(256) contact_gather_kernel(const Dev<T>* __restrict__ D, const ContactDev* __restrict__ CD,
+                                                             const Blk* __restrict__ tab) {
+  BLOCK_SCENE(tab, D, CD)
+  const int p = blk_.base + (int)threadIdx.x;
   if (p >= c.P) return;
   const int s0 = c.pill_start[p], s1 = c.pill_start[p + 1];
   if (s0 == s1) return;
@@ -436,8 +491,6 @@ __global__ void __launch_bounds__(256) contact_gather_kernel(Dev<T> d, ContactDe
   d.s[p] = (T)((double)d.s[p] + inv * as);
 }
 
-inline unsigned nblk(int n) { return (unsigned)((n + 255) / 256); }
-
 }  // namespace
 
 // ----------------------------------------------------------------------------- host side
@@ -455,8 +508,7 @@ ContactOffsets contact_layout(size_t start, bool on, int P, int E, int cpc, bool
     o.end = start;
     return o;
   }
-  int T = 64;
-  while (T < 2 * E) T <<= 1;
+  const int T = contact_table_size(E);
   const size_t cap = (size_t)cpc * (size_t)E;
   const size_t ts = f64 ? 8 : 4;
   const int nb = (std::max(std::max(T, E), P) + 1023) / 1024 + 1;
@@ -465,7 +517,8 @@ ContactOffsets contact_layout(size_t start, bool on, int P, int E, int cpc, bool
   o.cap_grp = take(4 * (size_t)E);
   o.sph = take(8 * 4 * (size_t)E);
   o.maxr = take(8);
-  o.key = take(4 * (size_t)E + 12 * (size_t)E);   // keys followed by cell coordinates
+  o.key = take(4 * (size_t)E);
+  o.cell = take(12 * (size_t)E);
   o.cell_cnt = take(4 * (size_t)T);
   o.cell_start = take(4 * (size_t)(T + 1));
   o.cell_cur = take(4 * (size_t)T);
@@ -487,9 +540,16 @@ ContactOffsets contact_layout(size_t start, bool on, int P, int E, int cpc, bool
   return o;
 }
 
+int contact_table_size(int E) {
+  int T = 64;
+  while (T < 2 * E) T <<= 1;
+  return T;
+}
+
 viper_status contact_init(ContactDev& c, char* ws, const ContactOffsets& o, const viper_scene_desc* d,
-                          const std::vector<int32_t>& off, const std::vector<int32_t>& group, hipStream_t st) {
-  c.on = o.on;
+                          const std::vector<int32_t>& off, const std::vector<int32_t>& group, int32_t* status,
+                          hipStream_t st) {
+  c = ContactDev();
   if (!o.on) return VIPER_OK;
   const int R = (int)off.size() - 1;
   c.P = off[R];
@@ -497,8 +557,7 @@ viper_status contact_init(ContactDev& c, char* ws, const ContactOffsets& o, cons
   for (int k = 0; k < R; ++k)
     for (int p = off[k]; p + 1 < off[k + 1]; ++p) { ids.push_back(p); rod.push_back(k); grp.push_back(group[k]); }
   c.E = (int)ids.size();
-  c.T = 64;
-  while (c.T < 2 * c.E) c.T <<= 1;
+  c.T = contact_table_size(c.E);
   const int cpc = d->contact_capacity_per_capsule > 0 ? d->contact_capacity_per_capsule : 16;
   c.cap = cpc * c.E;
   c.cap_ids = (int32_t*)(ws + o.cap_ids);
@@ -507,6 +566,7 @@ viper_status contact_init(ContactDev& c, char* ws, const ContactOffsets& o, cons
   c.sph = (double*)(ws + o.sph);
   c.maxr = (unsigned long long*)(ws + o.maxr);
   c.key = (int32_t*)(ws + o.key);
+  c.cell = (int32_t*)(ws + o.cell);
   c.cell_cnt = (int32_t*)(ws + o.cell_cnt);
   c.cell_start = (int32_t*)(ws + o.cell_start);
   c.cell_cur = (int32_t*)(ws + o.cell_cur);
@@ -521,9 +581,10 @@ viper_status contact_init(ContactDev& c, char* ws, const ContactOffsets& o, cons
   c.entries = (int32_t*)(ws + o.entries);
   c.delta_buf = (double*)(ws + o.delta);
   c.active = (int32_t*)(ws + o.active);
-  c.xdet = ws + o.xdet;
+  c.xdet = (double*)(ws + o.xdet);
   c.sdet = ws + o.sdet;
   c.bsum = (int32_t*)(ws + o.bsum);
+  c.status = status;
   if (hipMemcpyAsync(c.cap_ids, ids.data(), 4 * ids.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(c.cap_rod, rod.data(), 4 * rod.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(c.cap_grp, grp.data(), 4 * grp.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
@@ -532,51 +593,59 @@ viper_status contact_init(ContactDev& c, char* ws, const ContactOffsets& o, cons
   return VIPER_OK;
 }
 
+namespace {
+template <int WHICH>
+hipError_t scan(const BatchDev& b, int tabid, hipStream_t st) {
+  const ContactDev* CD = b.cd;
+  if (b.nblk[tabid] > 0)
+    hipLaunchKernelGGL(scan_block_kernel<WHICH>, dim3(b.nblk[tabid]), dim3(256), 0, st, CD, b.tab[tabid]);
+  hipLaunchKernelGGL(scan_sums_kernel<WHICH>, dim3(b.nscenes), dim3(1024), 0, st, CD);
+  if (b.nblk[tabid] > 0)
+    hipLaunchKernelGGL(scan_add_kernel<WHICH>, dim3(b.nblk[tabid]), dim3(256), 0, st, CD, b.tab[tabid]);
+  return hipGetLastError();
+}
+}  // namespace
+
 template <class T>
-hipError_t contact_detect(const Dev<T>& d, ContactDev& c, hipStream_t st) {
-  c.status = d.status;
-  const int E = c.E, P = c.P, T_ = c.T;
-  int32_t* cell = c.key + E;
-  hipLaunchKernelGGL(det_copy_kernel<T>, dim3(nblk(P)), dim3(256), 0, st, d, c);
-  hipLaunchKernelGGL(clear_max_kernel, dim3(1), dim3(64), 0, st, c.maxr);
-  hipLaunchKernelGGL(fill_kernel, dim3(nblk(T_)), dim3(256), 0, st, c.cell_cnt, T_, 0);
-  hipLaunchKernelGGL(fill_kernel, dim3(nblk(T_)), dim3(256), 0, st, c.cell_cur, T_, 0);
-  hipLaunchKernelGGL(fill_kernel, dim3(nblk(P)), dim3(256), 0, st, c.pill_cnt, P, 0);
-  hipLaunchKernelGGL(fill_kernel, dim3(nblk(P)), dim3(256), 0, st, c.pill_cur, P, 0);
-  if (E > 0) {
-    hipLaunchKernelGGL(sphere_kernel<T>, dim3(nblk(E)), dim3(256), 0, st, d, c);
-    hipLaunchKernelGGL(key_kernel, dim3(nblk(E)), dim3(256), 0, st, c, cell);
-  }
-  hipError_t e = scan(c.cell_cnt, c.cell_start, T_, c.bsum, st);
+hipError_t launch_contact_detect(const BatchDev& b, hipStream_t st) {
+  if (b.nscenes == 0) return hipSuccess;
+  const Dev<T>* D = (const Dev<T>*)b.dev;
+  const ContactDev* CD = b.cd;
+  const dim3 blk(256);
+  hipLaunchKernelGGL(det_copy_kernel<T>, dim3(b.nblk[TB_PILLS]), blk, 0, st, D, CD, b.tab[TB_PILLS]);
+  hipLaunchKernelGGL(zero_cells_kernel, dim3(b.nblk[TB_CELLS]), blk, 0, st, CD, b.tab[TB_CELLS]);
+  hipLaunchKernelGGL(sphere_kernel<T>, dim3(b.nblk[TB_CAPS]), blk, 0, st, D, CD, b.tab[TB_CAPS]);
+  hipLaunchKernelGGL(key_kernel, dim3(b.nblk[TB_CAPS]), blk, 0, st, CD, b.tab[TB_CAPS]);
+  hipError_t e = scan<0>(b, TB_SCAN_T, st);
   if (e != hipSuccess) return e;
-  if (E > 0) {
-    hipLaunchKernelGGL(bucket_scatter_kernel, dim3(nblk(E)), dim3(256), 0, st, c);
-    hipLaunchKernelGGL(pair_kernel<false>, dim3(nblk(E)), dim3(256), 0, st, c, (const int32_t*)cell);
-  }
-  e = scan(c.pcount, c.poff, E, c.bsum, st);
+  hipLaunchKernelGGL(bucket_scatter_kernel, dim3(b.nblk[TB_CAPS]), blk, 0, st, CD, b.tab[TB_CAPS]);
+  hipLaunchKernelGGL(pair_kernel<false>, dim3(b.nblk[TB_CAPS]), blk, 0, st, CD, b.tab[TB_CAPS]);
+  e = scan<1>(b, TB_SCAN_E, st);
   if (e != hipSuccess) return e;
-  if (E > 0) hipLaunchKernelGGL(pair_kernel<true>, dim3(nblk(E)), dim3(256), 0, st, c, (const int32_t*)cell);
-  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(64), 0, st, c);
-  if (c.cap > 0) hipLaunchKernelGGL(csr_count_kernel, dim3(nblk(c.cap)), dim3(256), 0, st, c);
-  e = scan(c.pill_cnt, c.pill_start, P, c.bsum, st);
+  hipLaunchKernelGGL(pair_kernel<true>, dim3(b.nblk[TB_CAPS]), blk, 0, st, CD, b.tab[TB_CAPS]);
+  hipLaunchKernelGGL(finalize_kernel, dim3(b.nscenes), dim3(64), 0, st, CD);
+  hipLaunchKernelGGL(csr_count_kernel, dim3(b.nblk[TB_PAIRS]), blk, 0, st, CD, b.tab[TB_PAIRS]);
+  e = scan<2>(b, TB_SCAN_P, st);
   if (e != hipSuccess) return e;
-  if (c.cap > 0) hipLaunchKernelGGL(csr_fill_kernel, dim3(nblk(c.cap)), dim3(256), 0, st, c);
-  hipLaunchKernelGGL(csr_sort_kernel, dim3(nblk(P)), dim3(256), 0, st, c);
+  hipLaunchKernelGGL(csr_fill_kernel, dim3(b.nblk[TB_PAIRS]), blk, 0, st, CD, b.tab[TB_PAIRS]);
+  hipLaunchKernelGGL(csr_sort_kernel, dim3(b.nblk[TB_PILLS]), blk, 0, st, CD, b.tab[TB_PILLS]);
   return hipGetLastError();
 }
 
 template <class T>
-hipError_t contact_project(const Dev<T>& d, ContactDev& c, hipStream_t st) {
-  if (c.cap > 0) hipLaunchKernelGGL(contact_pair_kernel<T>, dim3(nblk(c.cap)), dim3(256), 0, st, d, c);
-  hipLaunchKernelGGL(contact_gather_kernel<T>, dim3(nblk(c.P)), dim3(256), 0, st, d, c);
+hipError_t launch_contact_project(const BatchDev& b, hipStream_t st) {
+  if (b.nscenes == 0) return hipSuccess;
+  const Dev<T>* D = (const Dev<T>*)b.dev;
+  hipLaunchKernelGGL(contact_pair_kernel<T>, dim3(b.nblk[TB_PAIRS]), dim3(256), 0, st, D, b.cd, b.tab[TB_PAIRS]);
+  hipLaunchKernelGGL(contact_gather_kernel<T>, dim3(b.nblk[TB_PILLS]), dim3(256), 0, st, D, b.cd, b.tab[TB_PILLS]);
   return hipGetLastError();
 }
 
-hipError_t contact_copy_det(ContactDev& c, bool x, void* dst, int P, size_t ts, hipStream_t st) {
-  return hipMemcpyAsync(dst, x ? c.xdet : c.sdet, (x ? 3 * 8 : ts) * (size_t)P, hipMemcpyDefault, st);
+hipError_t contact_copy_det(const ContactDev& c, bool x, void* dst, int P, size_t ts, hipStream_t st) {
+  return hipMemcpyAsync(dst, x ? (void*)c.xdet : c.sdet, (x ? 3 * 8 : ts) * (size_t)P, hipMemcpyDefault, st);
 }
 
-viper_status contact_get_pairs(ContactDev& c, int32_t* pairs, int32_t cap, int32_t* n, hipStream_t st) {
+viper_status contact_get_pairs(const ContactDev& c, int32_t* pairs, int32_t cap, int32_t* n, hipStream_t st) {
   int32_t h = 0;
   if (hipMemcpyAsync(&h, c.npairs, 4, hipMemcpyDeviceToHost, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
     return VIPER_ERR_DEVICE;
@@ -591,9 +660,9 @@ viper_status contact_get_pairs(ContactDev& c, int32_t* pairs, int32_t cap, int32
   return VIPER_OK;
 }
 
-template hipError_t contact_detect<float>(const Dev<float>&, ContactDev&, hipStream_t);
-template hipError_t contact_detect<double>(const Dev<double>&, ContactDev&, hipStream_t);
-template hipError_t contact_project<float>(const Dev<float>&, ContactDev&, hipStream_t);
-template hipError_t contact_project<double>(const Dev<double>&, ContactDev&, hipStream_t);
+template hipError_t launch_contact_detect<float>(const BatchDev&, hipStream_t);
+template hipError_t launch_contact_detect<double>(const BatchDev&, hipStream_t);
+template hipError_t launch_contact_project<float>(const BatchDev&, hipStream_t);
+template hipError_t launch_contact_project<double>(const BatchDev&, hipStream_t);
 
 }  // namespace viper

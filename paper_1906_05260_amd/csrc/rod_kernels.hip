@@ -327,21 +327,24 @@ __device__ __forceinline__ void iteration_lane(Lane2<T>& P) {
 
 // ---------------------------------------------------------------- load / store
 
-// Slots of this lane: pA = p0 + 2 lane, pB = pA + 1 (clamped to a valid index when
-// beyond the wave's run; such slots carry no flags and are never stored).
+// Slots of this lane: pA = p0 + 2 lane, pB = pA + 1 of its wavefront's run (clamped to a
+// valid index beyond the run; such slots carry no flags and are never stored).  The block
+// table maps the block to its scene and first wavefront.
 template <class T>
-__device__ __forceinline__ bool lane_setup(const Dev<T>& d, Lane2<T>& P, int& pA, int& pB) {
-  const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+__device__ __forceinline__ const Dev<T>* lane_setup(const Dev<T>* D, const Blk* tab, Lane2<T>& P, int& pA, int& pB) {
+  const Blk b = tab[blockIdx.x];
+  const Dev<T>* d = D + b.scene;
+  const int wave = b.base + (int)(threadIdx.x >> 6);
   const int lane = (int)(threadIdx.x & 63);
-  if (wave >= d.W) return false;
-  const int p0 = d.wave_start[wave];
-  const int n = d.wave_start[wave + 1] - p0;
+  if (wave >= d->W) return nullptr;
+  const int p0 = d->wave_start[wave];
+  const int n = d->wave_start[wave + 1] - p0;
   const bool vA = 2 * lane < n, vB = 2 * lane + 1 < n;
   pA = p0 + (vA ? 2 * lane : 0);
   pB = p0 + (vB ? 2 * lane + 1 : 0);
-  P.A.f = vA ? d.flags[pA] : 0u;
-  P.B.f = vB ? d.flags[pB] : 0u;
-  return true;
+  P.A.f = vA ? d->flags[pA] : 0u;
+  P.B.f = vB ? d->flags[pB] : 0u;
+  return d;
 }
 
 template <class T>
@@ -392,10 +395,13 @@ __device__ __forceinline__ void check_finite(const Dev<T>& d, const Slot<T>& L) 
 
 // FRAME / SUBSTEP mode: nsub substeps with the rod state in registers.
 template <class T>
-__global__ void __launch_bounds__(256) rod_frame_kernel(Dev<T> d, int nsub, T h, int iters) {
+__global__ void __launch_bounds__(256) rod_frame_kernel(const Dev<T>* __restrict__ D, const Blk* __restrict__ tab,
+                                                        int nsub, T h, int iters) {
   Lane2<T> P;
   int pA, pB;
-  if (!lane_setup(d, P, pA, pB)) return;
+  const Dev<T>* dp = lane_setup(D, tab, P, pA, pB);
+  if (!dp) return;
+  const Dev<T>& d = *dp;
   load_state(d, P.A, pA);
   load_state(d, P.B, pB);
   load_lane_consts(d, P, pA, pB, rcp(h * h));
@@ -429,10 +435,12 @@ __device__ __forceinline__ void store_predicted(const Dev<T>& d, const Slot<T>& 
 }
 
 template <class T>
-__global__ void __launch_bounds__(256) predict_kernel(Dev<T> d, T h) {
+__global__ void __launch_bounds__(256) predict_kernel(const Dev<T>* __restrict__ D, const Blk* __restrict__ tab, T h) {
   Lane2<T> P;
   int pA, pB;
-  if (!lane_setup(d, P, pA, pB)) return;
+  const Dev<T>* dp = lane_setup(D, tab, P, pA, pB);
+  if (!dp) return;
+  const Dev<T>& d = *dp;
   load_state(d, P.A, pA);
   load_state(d, P.B, pB);
   P.A.w = d.winv[pA]; P.A.inert = d.inert[pA];
@@ -465,10 +473,13 @@ __device__ __forceinline__ void store_iter(const Dev<T>& d, const Slot<T>& L, in
 }
 
 template <class T>
-__global__ void __launch_bounds__(256) rod_iteration_kernel(Dev<T> d, T h) {
+__global__ void __launch_bounds__(256) rod_iteration_kernel(const Dev<T>* __restrict__ D, const Blk* __restrict__ tab,
+                                                            T h) {
   Lane2<T> P;
   int pA, pB;
-  if (!lane_setup(d, P, pA, pB)) return;
+  const Dev<T>* dp = lane_setup(D, tab, P, pA, pB);
+  if (!dp) return;
+  const Dev<T>& d = *dp;
   load_iter(d, P.A, pA);
   load_iter(d, P.B, pB);
   load_lane_consts(d, P, pA, pB, rcp(h * h));
@@ -494,10 +505,12 @@ __device__ __forceinline__ void velocity_store(const Dev<T>& d, Slot<T>& L, int 
 }
 
 template <class T>
-__global__ void __launch_bounds__(256) velocity_kernel(Dev<T> d, T h) {
+__global__ void __launch_bounds__(256) velocity_kernel(const Dev<T>* __restrict__ D, const Blk* __restrict__ tab, T h) {
   Lane2<T> P;
   int pA, pB;
-  if (!lane_setup(d, P, pA, pB)) return;
+  const Dev<T>* dp = lane_setup(D, tab, P, pA, pB);
+  if (!dp) return;
+  const Dev<T>& d = *dp;
   const T ih = T(1) / h;
   velocity_store(d, P.A, pA, ih);
   velocity_store(d, P.B, pB, ih);
@@ -619,26 +632,28 @@ __global__ void __launch_bounds__(256) lbs_kernel(int V, const float* __restrict
 
 // ---------------------------------------------------------------- launchers
 
-static inline unsigned wave_blocks(int W) { return (unsigned)((W + 3) / 4); }
-
-template <class T> hipError_t launch_rod_frame(const Dev<T>& d, int nsub, double h, int iters, hipStream_t st) {
-  if (d.W == 0) return hipSuccess;
-  hipLaunchKernelGGL(rod_frame_kernel<T>, dim3(wave_blocks(d.W)), dim3(256), 0, st, d, nsub, (T)h, iters);
+template <class T> hipError_t launch_rod_frame(const BatchDev& b, int nsub, double h, int iters, hipStream_t st) {
+  if (b.nblk[TB_WAVES] == 0) return hipSuccess;
+  hipLaunchKernelGGL(rod_frame_kernel<T>, dim3(b.nblk[TB_WAVES]), dim3(256), 0, st, (const Dev<T>*)b.dev,
+                     b.tab[TB_WAVES], nsub, (T)h, iters);
   return hipGetLastError();
 }
-template <class T> hipError_t launch_predict(const Dev<T>& d, double h, hipStream_t st) {
-  if (d.W == 0) return hipSuccess;
-  hipLaunchKernelGGL(predict_kernel<T>, dim3(wave_blocks(d.W)), dim3(256), 0, st, d, (T)h);
+template <class T> hipError_t launch_predict(const BatchDev& b, double h, hipStream_t st) {
+  if (b.nblk[TB_WAVES] == 0) return hipSuccess;
+  hipLaunchKernelGGL(predict_kernel<T>, dim3(b.nblk[TB_WAVES]), dim3(256), 0, st, (const Dev<T>*)b.dev,
+                     b.tab[TB_WAVES], (T)h);
   return hipGetLastError();
 }
-template <class T> hipError_t launch_rod_iteration(const Dev<T>& d, double h, hipStream_t st) {
-  if (d.W == 0) return hipSuccess;
-  hipLaunchKernelGGL(rod_iteration_kernel<T>, dim3(wave_blocks(d.W)), dim3(256), 0, st, d, (T)h);
+template <class T> hipError_t launch_rod_iteration(const BatchDev& b, double h, hipStream_t st) {
+  if (b.nblk[TB_WAVES] == 0) return hipSuccess;
+  hipLaunchKernelGGL(rod_iteration_kernel<T>, dim3(b.nblk[TB_WAVES]), dim3(256), 0, st, (const Dev<T>*)b.dev,
+                     b.tab[TB_WAVES], (T)h);
   return hipGetLastError();
 }
-template <class T> hipError_t launch_velocity(const Dev<T>& d, double h, hipStream_t st) {
-  if (d.W == 0) return hipSuccess;
-  hipLaunchKernelGGL(velocity_kernel<T>, dim3(wave_blocks(d.W)), dim3(256), 0, st, d, (T)h);
+template <class T> hipError_t launch_velocity(const BatchDev& b, double h, hipStream_t st) {
+  if (b.nblk[TB_WAVES] == 0) return hipSuccess;
+  hipLaunchKernelGGL(velocity_kernel<T>, dim3(b.nblk[TB_WAVES]), dim3(256), 0, st, (const Dev<T>*)b.dev,
+                     b.tab[TB_WAVES], (T)h);
   return hipGetLastError();
 }
 template <class T> hipError_t launch_gather_field(const Dev<T>& d, int which, T* out, hipStream_t st) {
@@ -661,10 +676,10 @@ template <class T> hipError_t launch_skin(const Dev<T>& d, int V, const float* r
 }
 
 #define VIPER_INST(T)                                                                                         \
-  template hipError_t launch_rod_frame<T>(const Dev<T>&, int, double, int, hipStream_t);                     \
-  template hipError_t launch_predict<T>(const Dev<T>&, double, hipStream_t);                                 \
-  template hipError_t launch_rod_iteration<T>(const Dev<T>&, double, hipStream_t);                           \
-  template hipError_t launch_velocity<T>(const Dev<T>&, double, hipStream_t);                                \
+  template hipError_t launch_rod_frame<T>(const BatchDev&, int, double, int, hipStream_t);                   \
+  template hipError_t launch_predict<T>(const BatchDev&, double, hipStream_t);                               \
+  template hipError_t launch_rod_iteration<T>(const BatchDev&, double, hipStream_t);                         \
+  template hipError_t launch_velocity<T>(const BatchDev&, double, hipStream_t);                              \
   template hipError_t launch_gather_field<T>(const Dev<T>&, int, T*, hipStream_t);                           \
   template hipError_t launch_scatter_field<T>(const Dev<T>&, int, const T*, hipStream_t);                    \
   template hipError_t launch_skin<T>(const Dev<T>&, int, const float*, const int32_t*, const float*, float*, \

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -57,7 +58,7 @@ struct Offsets {
   size_t pill_rest[3];     // winv wsinv rbar
   size_t edge_rest[18];    // ilb il0 cbt inert dbx dby dbz css cvol csg cbtc qrx qry qrz qrw mrx mry mrz
   size_t scratch[10];      // xpx xpy xpz spv qpx qpy qpz qpw i1 lam(8P)
-  size_t flags, wave_start, status, stage, xform, anchor, rod_of;
+  size_t flags, wave_start, status, stage, xform, anchor, rod_of, header;
   ContactOffsets contact;
   size_t total;
 };
@@ -130,6 +131,67 @@ int pack_waves(const viper_scene_desc* d, std::vector<int32_t>& ws) {
   return (int)ws.size() - 1;
 }
 
+// ----------------------------------------------------------------------------- batch tables
+
+// Per-scene item counts of every stage.
+struct Counts {
+  int W = 0, P = 0, E = 0, T = 0, cap = 0;
+  bool contacts = false;
+};
+
+const int kStageItems[TB_COUNT] = {4, 256, 256, 256, 256, 1024, 1024, 1024};
+
+int stage_items(const Counts& c, int stage) {
+  switch (stage) {
+    case TB_WAVES: return c.W;
+    case TB_PILLS: return c.P;
+    case TB_CAPS: return c.contacts ? c.E : 0;
+    case TB_CELLS: return c.contacts ? c.T : 0;
+    case TB_PAIRS: return c.contacts ? c.cap : 0;
+    case TB_SCAN_P: return c.contacts ? c.P : 0;
+    case TB_SCAN_E: return c.contacts ? c.E : 0;
+    case TB_SCAN_T: return c.contacts ? c.T : 0;
+    default: return 0;
+  }
+}
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Bytes of the device header of a batch: Dev structs, ContactDev structs, block tables.
+size_t header_bytes(const std::vector<Counts>& v, size_t dev_size) {
+  size_t n = align256(v.size() * dev_size) + align256(v.size() * sizeof(ContactDev));
+  for (int t = 0; t < TB_COUNT; ++t) {
+    size_t e = 0;
+    for (const Counts& c : v) e += (size_t)((stage_items(c, t) + kStageItems[t] - 1) / kStageItems[t]);
+    n += align256(e * sizeof(Blk));
+  }
+  return n;
+}
+
+// Lay the batch header out in `buf` (host image of the device bytes at `dev_base`) and
+// point `b` at the device copy.
+void build_header(std::vector<char>& buf, const std::vector<const void*>& devs, size_t dev_size,
+                  const std::vector<ContactDev>& cds, const std::vector<Counts>& v, char* dev_base, BatchDev& b) {
+  buf.assign(header_bytes(v, dev_size), 0);
+  size_t off = 0;
+  for (size_t i = 0; i < devs.size(); ++i) std::memcpy(buf.data() + off + i * dev_size, devs[i], dev_size);
+  b.dev = dev_base + off;
+  off += align256(v.size() * dev_size);
+  for (size_t i = 0; i < cds.size(); ++i) std::memcpy(buf.data() + off + i * sizeof(ContactDev), &cds[i], sizeof(ContactDev));
+  b.cd = (const ContactDev*)(dev_base + off);
+  off += align256(v.size() * sizeof(ContactDev));
+  for (int t = 0; t < TB_COUNT; ++t) {
+    std::vector<Blk> tab;
+    for (size_t s = 0; s < v.size(); ++s)
+      for (int base = 0; base < stage_items(v[s], t); base += kStageItems[t]) tab.push_back(Blk{(int32_t)s, base});
+    std::memcpy(buf.data() + off, tab.data(), tab.size() * sizeof(Blk));
+    b.tab[t] = (const Blk*)(dev_base + off);
+    b.nblk[t] = (int)tab.size();
+    off += align256(tab.size() * sizeof(Blk));
+  }
+  b.nscenes = (int)v.size();
+}
+
 Offsets make_layout(const viper_scene_desc* d, int P, int W, int E, int cap) {
   const size_t ts = d->precision == VIPER_F64 ? 8 : 4;
   Layout L;
@@ -146,6 +208,9 @@ Offsets make_layout(const viper_scene_desc* d, int P, int W, int E, int cap) {
   o.xform = L.take(4 * 12 * (size_t)P);      // skinning transforms
   o.anchor = L.take(8 * 3 * (size_t)std::max(d->num_rods, 1));
   o.rod_of = L.take(4 * (size_t)P);
+  Counts c;
+  c.W = W; c.P = P; c.E = E; c.T = contact_table_size(E); c.cap = cap * E; c.contacts = d->collisions != 0;
+  o.header = L.take(header_bytes(std::vector<Counts>{c}, d->precision == VIPER_F64 ? sizeof(Dev<double>) : sizeof(Dev<float>)));
   o.contact = contact_layout(L.off, d->collisions != 0, P, E, cap, d->precision == VIPER_F64);
   L.off = o.contact.end;
   o.total = L.off;
@@ -299,6 +364,8 @@ struct viper_scene_s {
   Dev<float> df;
   Dev<double> dd;
   ContactDev cd;
+  BatchDev batch;             // this scene as a batch of one
+  std::vector<char> header;   // host image of the batch header
   std::vector<Skin> skins;
   std::vector<int32_t> off;  // rod offsets (host copy)
 };
@@ -372,31 +439,44 @@ template <class T> Dev<T>& dev(viper_scene_s* S);
 template <> Dev<float>& dev<float>(viper_scene_s* S) { return S->df; }
 template <> Dev<double>& dev<double>(viper_scene_s* S) { return S->dd; }
 
+// One frame of a batch (all scenes share precision, dt, substeps and iterations).
 template <class T>
-viper_status step_t(viper_scene_s* S, double dt, int sub, int iters, int mode, hipStream_t st) {
-  Dev<T>& d = dev<T>(S);
+viper_status batch_step(const BatchDev& b, bool collisions, double dt, int sub, int iters, int mode, hipStream_t st) {
   const double h = dt / sub;
-  if (mode == VIPER_MODE_AUTO) mode = S->collisions ? VIPER_MODE_ITERATION : VIPER_MODE_FRAME;
-  if (S->collisions && mode != VIPER_MODE_ITERATION)
+  if (mode == VIPER_MODE_AUTO) mode = collisions ? VIPER_MODE_ITERATION : VIPER_MODE_FRAME;
+  if (collisions && mode != VIPER_MODE_ITERATION)
     return fail(VIPER_ERR_INVALID, "scenes with collisions step in VIPER_MODE_ITERATION");
   if (mode == VIPER_MODE_FRAME) {
-    HIP_TRY(launch_rod_frame<T>(d, sub, h, iters, st));
+    HIP_TRY(launch_rod_frame<T>(b, sub, h, iters, st));
   } else if (mode == VIPER_MODE_SUBSTEP) {
-    for (int i = 0; i < sub; ++i) HIP_TRY(launch_rod_frame<T>(d, 1, h, iters, st));
+    for (int i = 0; i < sub; ++i) HIP_TRY(launch_rod_frame<T>(b, 1, h, iters, st));
   } else if (mode == VIPER_MODE_ITERATION) {
     for (int i = 0; i < sub; ++i) {
-      HIP_TRY(launch_predict<T>(d, h, st));
-      if (S->collisions) HIP_TRY(contact_detect<T>(d, S->cd, st));
+      HIP_TRY(launch_predict<T>(b, h, st));
+      if (collisions) HIP_TRY(launch_contact_detect<T>(b, st));
       for (int it = 0; it < iters; ++it) {
-        HIP_TRY(launch_rod_iteration<T>(d, h, st));
-        if (S->collisions) HIP_TRY(contact_project<T>(d, S->cd, st));
+        HIP_TRY(launch_rod_iteration<T>(b, h, st));
+        if (collisions) HIP_TRY(launch_contact_project<T>(b, st));
       }
-      HIP_TRY(launch_velocity<T>(d, h, st));
+      HIP_TRY(launch_velocity<T>(b, h, st));
     }
   } else {
     return fail(VIPER_ERR_INVALID, "unknown mode");
   }
   return VIPER_OK;
+}
+
+template <class T>
+viper_status step_t(viper_scene_s* S, double dt, int sub, int iters, int mode, hipStream_t st) {
+  return batch_step<T>(S->batch, S->collisions != 0, dt, sub, iters, mode, st);
+}
+
+Counts scene_counts(const viper_scene_s* S) {
+  Counts c;
+  c.W = S->W; c.P = S->P; c.E = S->E; c.T = S->collisions ? S->cd.T : contact_table_size(S->E);
+  c.cap = S->collisions ? S->cd.cap : S->cap * S->E;
+  c.contacts = S->collisions != 0;
+  return c;
 }
 
 }  // namespace
@@ -454,7 +534,16 @@ viper_status viper_create_scene(const viper_scene_desc* desc, void* workspace, s
     S->df.gx = (float)desc->gravity[0]; S->df.gy = (float)desc->gravity[1]; S->df.gz = (float)desc->gravity[2];
     r = upload<float>(S, H, st);
   }
-  if (r == VIPER_OK) r = contact_init(S->cd, S->ws, o.contact, desc, H.off, H.group, st);
+  if (r == VIPER_OK) r = contact_init(S->cd, S->ws, o.contact, desc, H.off, H.group, (int32_t*)(S->ws + o.status), st);
+  if (r == VIPER_OK) {
+    const void* dv = S->precision == VIPER_F64 ? (const void*)&S->dd : (const void*)&S->df;
+    const size_t dsz = S->precision == VIPER_F64 ? sizeof(Dev<double>) : sizeof(Dev<float>);
+    build_header(S->header, std::vector<const void*>{dv}, dsz, std::vector<ContactDev>{S->cd},
+                 std::vector<Counts>{scene_counts(S)}, S->ws + o.header, S->batch);
+    if (hipMemcpyAsync(S->ws + o.header, S->header.data(), S->header.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      r = fail(VIPER_ERR_DEVICE, "header upload failed");
+  }
   if (r != VIPER_OK) {
     delete S;
     return r;
@@ -584,6 +673,210 @@ viper_status viper_scene_info(viper_scene S, int64_t* pills, int64_t* rods, int6
   if (rods) *rods = S->R;
   if (capsules) *capsules = S->E;
   if (ppi) *ppi = S->proj_per_iter;
+  return VIPER_OK;
+}
+
+}  // extern "C"
+
+// ============================================================================= serving pool
+
+namespace {
+struct PoolSlot {
+  viper_scene_s* scene = nullptr;
+  size_t off = 0, size = 0;
+};
+}  // namespace
+
+struct viper_pool_s {
+  char* ws = nullptr;
+  size_t bytes = 0;
+  int precision = 0;
+  int max_scenes = 0;
+  size_t header_cap = 0;                 // [0, header_cap): two batch headers
+  std::map<size_t, size_t> free_;        // offset -> size of free ranges
+  std::vector<PoolSlot> slots;
+  bool dirty = true;
+  BatchDev fb, cb;                       // collision-free batch, contact batch
+  std::vector<char> hf, hc;              // host images of the headers
+  hipStream_t aux = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace {
+
+void pool_free_range(viper_pool_s* P, size_t off, size_t size) {
+  auto it = P->free_.emplace(off, size).first;
+  auto nx = std::next(it);
+  if (nx != P->free_.end() && it->first + it->second == nx->first) {
+    it->second += nx->second;
+    P->free_.erase(nx);
+  }
+  if (it != P->free_.begin()) {
+    auto pv = std::prev(it);
+    if (pv->first + pv->second == it->first) {
+      pv->second += it->second;
+      P->free_.erase(it);
+    }
+  }
+}
+
+template <class T>
+viper_status pool_rebuild(viper_pool_s* P, hipStream_t st) {
+  HIP_TRY(hipStreamSynchronize(st));   // the previous step no longer reads the headers
+  std::vector<const void*> df, dc;
+  std::vector<ContactDev> cc;
+  std::vector<Counts> vf, vc;
+  for (const PoolSlot& sl : P->slots) {
+    if (!sl.scene) continue;
+    viper_scene_s* S = sl.scene;
+    const void* d = (const void*)&dev<T>(S);
+    if (S->collisions) { dc.push_back(d); cc.push_back(S->cd); vc.push_back(scene_counts(S)); }
+    else { df.push_back(d); vf.push_back(scene_counts(S)); }
+  }
+  const size_t half = P->header_cap / 2;
+  if (header_bytes(vf, sizeof(Dev<T>)) > half || header_bytes(vc, sizeof(Dev<T>)) > half)
+    return fail(VIPER_ERR_NO_CAPACITY, "pool header region too small for the resident set");
+  build_header(P->hf, df, sizeof(Dev<T>), std::vector<ContactDev>(), vf, P->ws, P->fb);
+  build_header(P->hc, dc, sizeof(Dev<T>), cc, vc, P->ws + half, P->cb);
+  if (!P->hf.empty()) HIP_TRY(hipMemcpyAsync(P->ws, P->hf.data(), P->hf.size(), hipMemcpyHostToDevice, st));
+  if (!P->hc.empty()) HIP_TRY(hipMemcpyAsync(P->ws + half, P->hc.data(), P->hc.size(), hipMemcpyHostToDevice, st));
+  P->dirty = false;
+  return VIPER_OK;
+}
+
+template <class T>
+viper_status pool_step_t(viper_pool_s* P, double dt, int sub, int iters, hipStream_t st) {
+  if (P->dirty) {
+    viper_status r = pool_rebuild<T>(P, st);
+    if (r != VIPER_OK) return r;
+  }
+  if (P->fb.nscenes > 0) {
+    viper_status r = batch_step<T>(P->fb, false, dt, sub, iters, VIPER_MODE_FRAME, st);
+    if (r != VIPER_OK) return r;
+  }
+  if (P->cb.nscenes > 0) {
+    HIP_TRY(hipEventRecord(P->ev0, st));
+    HIP_TRY(hipStreamWaitEvent(P->aux, P->ev0, 0));
+    viper_status r = batch_step<T>(P->cb, true, dt, sub, iters, VIPER_MODE_ITERATION, P->aux);
+    if (r != VIPER_OK) return r;
+    HIP_TRY(hipEventRecord(P->ev1, P->aux));
+    HIP_TRY(hipStreamWaitEvent(st, P->ev1, 0));
+  }
+  return VIPER_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+viper_status viper_pool_create(void* workspace, size_t bytes, int32_t max_scenes, int32_t precision, void* stream,
+                               viper_pool* out) {
+  (void)stream;
+  if (!workspace || !out || max_scenes < 1) return fail(VIPER_ERR_INVALID, "workspace, out and max_scenes >= 1 are required");
+  if (((uintptr_t)workspace) & 255) return fail(VIPER_ERR_INVALID, "workspace must be 256-byte aligned");
+  if (precision != VIPER_F32 && precision != VIPER_F64) return fail(VIPER_ERR_INVALID, "unknown precision");
+  const size_t header = align256(std::max<size_t>(bytes / 64, 1u << 20) + (size_t)max_scenes * 8192);
+  if (bytes < 2 * header) return fail(VIPER_ERR_NO_CAPACITY, "pool workspace too small");
+  viper_pool_s* P = new viper_pool_s();
+  P->ws = (char*)workspace;
+  P->bytes = bytes;
+  P->precision = precision;
+  P->max_scenes = max_scenes;
+  P->header_cap = header;
+  P->free_[header] = bytes - header;
+  P->slots.resize(max_scenes);
+  if (hipStreamCreateWithFlags(&P->aux, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&P->ev0, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&P->ev1, hipEventDisableTiming) != hipSuccess) {
+    delete P;
+    return fail(VIPER_ERR_DEVICE, "could not create the pool's stream or events");
+  }
+  *out = P;
+  return VIPER_OK;
+}
+
+viper_status viper_pool_admit(viper_pool P, const viper_scene_desc* desc, void* stream, int32_t* slot) {
+  if (!P || !desc || !slot) return fail(VIPER_ERR_INVALID, "pool, desc and slot are required");
+  if (desc->precision != P->precision) return fail(VIPER_ERR_INVALID, "scene precision differs from the pool's");
+  size_t fp = 0;
+  viper_status r = viper_scene_footprint(desc, &fp);
+  if (r != VIPER_OK) return r;
+  fp = align256(fp);
+  int sid = -1;
+  for (int i = 0; i < P->max_scenes; ++i)
+    if (!P->slots[i].scene) { sid = i; break; }
+  if (sid < 0) return fail(VIPER_ERR_NO_CAPACITY, "all pool slots are in use");
+  auto it = P->free_.begin();
+  for (; it != P->free_.end(); ++it)
+    if (it->second >= fp) break;
+  if (it == P->free_.end()) return fail(VIPER_ERR_NO_CAPACITY, "no free range of " + std::to_string(fp) + " bytes");
+  const size_t off = it->first, size = it->second;
+  P->free_.erase(it);
+  if (size > fp) P->free_[off + fp] = size - fp;
+  viper_scene S = nullptr;
+  r = viper_create_scene(desc, P->ws + off, fp, stream, &S);
+  if (r != VIPER_OK) {
+    pool_free_range(P, off, fp);
+    return r;
+  }
+  P->slots[sid] = PoolSlot{S, off, fp};
+  P->dirty = true;
+  *slot = sid;
+  return VIPER_OK;
+}
+
+viper_status viper_pool_step(viper_pool P, double dt, int32_t substeps, int32_t iterations, void* stream) {
+  if (!P) return fail(VIPER_ERR_INVALID, "pool is NULL");
+  if (!(dt > 0) || !std::isfinite(dt) || substeps < 1 || iterations < 0)
+    return fail(VIPER_ERR_INVALID, "dt > 0, substeps >= 1, iterations >= 0 required");
+  hipStream_t st = (hipStream_t)stream;
+  return P->precision == VIPER_F64 ? pool_step_t<double>(P, dt, substeps, iterations, st)
+                                   : pool_step_t<float>(P, dt, substeps, iterations, st);
+}
+
+viper_status viper_pool_retire(viper_pool P, int32_t slot, void* stream) {
+  if (!P || slot < 0 || slot >= P->max_scenes || !P->slots[slot].scene) return fail(VIPER_ERR_INVALID, "bad slot");
+  // the range may be reused by the next admission: let the device finish with it first
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  HIP_TRY(hipStreamSynchronize(P->aux));
+  PoolSlot& sl = P->slots[slot];
+  delete sl.scene;
+  pool_free_range(P, sl.off, sl.size);
+  sl = PoolSlot();
+  P->dirty = true;
+  return VIPER_OK;
+}
+
+viper_status viper_pool_scene(viper_pool P, int32_t slot, viper_scene* scene) {
+  if (!P || !scene || slot < 0 || slot >= P->max_scenes || !P->slots[slot].scene) return fail(VIPER_ERR_INVALID, "bad slot");
+  *scene = P->slots[slot].scene;
+  return VIPER_OK;
+}
+
+viper_status viper_pool_info(viper_pool P, size_t* free_bytes, size_t* largest_free, int32_t* resident,
+                             int64_t* resident_pills) {
+  if (!P) return fail(VIPER_ERR_INVALID, "pool is NULL");
+  size_t fb = 0, lf = 0;
+  for (auto& kv : P->free_) { fb += kv.second; lf = std::max(lf, kv.second); }
+  int n = 0;
+  int64_t pills = 0;
+  for (auto& sl : P->slots)
+    if (sl.scene) { ++n; pills += sl.scene->P; }
+  if (free_bytes) *free_bytes = fb;
+  if (largest_free) *largest_free = lf;
+  if (resident) *resident = n;
+  if (resident_pills) *resident_pills = pills;
+  return VIPER_OK;
+}
+
+viper_status viper_pool_destroy(viper_pool P) {
+  if (!P) return VIPER_OK;
+  if (P->aux) hipStreamSynchronize(P->aux);
+  for (auto& sl : P->slots) delete sl.scene;
+  if (P->ev0) hipEventDestroy(P->ev0);
+  if (P->ev1) hipEventDestroy(P->ev1);
+  if (P->aux) hipStreamDestroy(P->aux);
+  delete P;
   return VIPER_OK;
 }
 

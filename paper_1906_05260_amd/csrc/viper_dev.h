@@ -53,11 +53,60 @@ struct Dev {
   T gx, gy, gz;
 };
 
-// Launchers (enqueue on `stream`, return hipError_t of the launch).
-template <class T> hipError_t launch_rod_frame(const Dev<T>& d, int nsub, double h, int iters, hipStream_t st);
-template <class T> hipError_t launch_predict(const Dev<T>& d, double h, hipStream_t st);
-template <class T> hipError_t launch_rod_iteration(const Dev<T>& d, double h, hipStream_t st);
-template <class T> hipError_t launch_velocity(const Dev<T>& d, double h, hipStream_t st);
+// Contact buffers of one scene (device pointers into its workspace).
+struct ContactDev {
+  int P = 0, E = 0, T = 0, cap = 0;   // pills, capsules, hash-table size, pair capacity
+  int search_iters = 10;
+  double delta = 1e-4;
+  int32_t *cap_ids = nullptr, *cap_rod = nullptr, *cap_grp = nullptr;
+  double* sph = nullptr;              // [E*4] mx my mz R
+  unsigned long long* maxr = nullptr; // bits of the largest sphere radius
+  int32_t *key = nullptr, *cell = nullptr;  // [E] hash keys, [3E] integer cell coordinates
+  int32_t *cell_cnt = nullptr, *cell_start = nullptr, *cell_cur = nullptr, *sorted = nullptr;
+  int32_t *pcount = nullptr, *poff = nullptr, *pairs = nullptr, *npairs = nullptr;
+  int32_t *pill_cnt = nullptr, *pill_start = nullptr, *pill_cur = nullptr, *entries = nullptr;
+  double* delta_buf = nullptr;        // [cap*16] per-pair corrections of the 4 end pills (dx dy dz ds)
+  int32_t* active = nullptr;          // [cap]
+  double* xdet = nullptr;             // [3P] FP64 world positions at detection
+  void* sdet = nullptr;               // [P] scales at detection (scene precision)
+  int32_t* bsum = nullptr;            // scan block sums
+  int32_t* status = nullptr;          // the scene's status words
+};
+
+// A batch of scenes advanced by the same launches.  Each launch's grid is described by a
+// block table: block b works on scene tab[b].scene, items tab[b].base + [0, block size).
+// Every scene's item range is padded to whole blocks, so a block never spans two scenes.
+struct Blk {
+  int32_t scene, base;
+};
+
+enum Stage {
+  TB_WAVES = 0,   // 4 wavefronts (<= 512 pill slots) per block: rod kernels
+  TB_PILLS,       // 256 pills per block
+  TB_CAPS,        // 256 capsules per block
+  TB_CELLS,       // 256 hash cells per block
+  TB_PAIRS,       // 256 candidate-pair slots per block
+  TB_SCAN_P,      // 1024 pills per block (scans)
+  TB_SCAN_E,      // 1024 capsules per block
+  TB_SCAN_T,      // 1024 cells per block
+  TB_COUNT
+};
+
+struct BatchDev {
+  int nscenes = 0;
+  const void* dev = nullptr;          // Dev<T>[nscenes] in device memory
+  const ContactDev* cd = nullptr;     // ContactDev[nscenes] in device memory (contact batches)
+  const Blk* tab[TB_COUNT] = {};
+  int nblk[TB_COUNT] = {};
+};
+
+// Launchers over a batch (enqueue on `stream`, return hipError_t of the launches).
+template <class T> hipError_t launch_rod_frame(const BatchDev& b, int nsub, double h, int iters, hipStream_t st);
+template <class T> hipError_t launch_predict(const BatchDev& b, double h, hipStream_t st);
+template <class T> hipError_t launch_rod_iteration(const BatchDev& b, double h, hipStream_t st);
+template <class T> hipError_t launch_velocity(const BatchDev& b, double h, hipStream_t st);
+template <class T> hipError_t launch_contact_detect(const BatchDev& b, hipStream_t st);
+template <class T> hipError_t launch_contact_project(const BatchDev& b, hipStream_t st);
 template <class T> hipError_t launch_gather_field(const Dev<T>& d, int which, T* out, hipStream_t st);
 template <class T> hipError_t launch_scatter_field(const Dev<T>& d, int which, const T* in, hipStream_t st);
 template <class T> hipError_t launch_skin(const Dev<T>& d, int V, const float* rest_v, const int32_t* caps,

@@ -249,3 +249,36 @@ def scene_of_size(n_pills: int, kind: str, seed: int):
     nm = max(1, int(round(n_pills / 512)))
     desc, mesh = muscle_scene(num_muscles=nm, seed=seed, target_pills=None, mesh_vertices=4 * n_pills)
     return desc, mesh
+
+
+@dataclass
+class Request:
+    arrival: float          # seconds after the start of the run
+    desc: SceneDesc
+    frames: int
+    kind: str
+
+
+def serving_requests(rate=200.0, duration=2.0, seed=3, min_pills=1000, max_pills=200000, frames=60,
+                     kinds=("helix", "muscle")):
+    """Poisson arrivals (exponential gaps of mean 1/rate) over `duration` seconds of scenes
+    with log-uniform sizes in [min_pills, max_pills], kind drawn uniformly from `kinds`
+    (64-pill helix rods, or muscle bundles with contacts and no skin mesh)."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    k = 0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t > duration:
+            break
+        n = int(np.exp(rng.uniform(np.log(min_pills), np.log(max_pills))))
+        kind = kinds[int(rng.integers(len(kinds)))]
+        if kind == "helix":
+            desc = helix_rods(max(1, int(round(n / 64))), 64, seed=seed * 100003 + k)
+        else:
+            desc, _ = muscle_scene(num_muscles=max(1, int(round(n / 512))), seed=seed * 100003 + k,
+                                   target_pills=None, mesh_vertices=0)
+        out.append(Request(t, desc, frames, kind))
+        k += 1
+    return out

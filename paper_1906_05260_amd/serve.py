@@ -1,0 +1,140 @@
+"""Serving loop: continuous batching of rod scenes on one GPU.
+
+Requests (a scene and a number of frames) arrive over time.  The batched server keeps
+every admitted scene resident in one device pool and advances all of them by one frame
+per pool step (one launch for the collision-free scenes, one shared launch sequence for
+the scenes with contacts).  Requests that arrive while a step runs are admitted as soon as
+a slot and a free range of the pool's HBM fit their footprint; their uploads run on a
+copy stream and they join the next step.  Finished scenes are retired, which frees their
+range.  The plain path serves the same requests first-come first-served, one scene at a
+time with its own launches, as a baseline.
+
+Reported per run: frame latency p50/p99 (latency of frame k = completion of frame k minus
+the moment it became ready: the arrival for frame 0, the previous frame's completion
+after), time to first frame p50/p99, pill-frames/s, peak resident bytes.
+"""
+from __future__ import annotations
+
+import time
+from collections import deque
+
+import numpy as np
+
+from . import viper
+
+
+def _summary(lat, ttff, pill_frames, t_first, t_last, extra=None):
+    lat = np.asarray(lat) * 1e3
+    ttff = np.asarray(ttff) * 1e3
+    span = max(t_last - t_first, 1e-9)
+    out = {
+        "frames": int(lat.size),
+        "latency_ms_p50": float(np.percentile(lat, 50)) if lat.size else None,
+        "latency_ms_p99": float(np.percentile(lat, 99)) if lat.size else None,
+        "ttff_ms_p50": float(np.percentile(ttff, 50)) if ttff.size else None,
+        "ttff_ms_p99": float(np.percentile(ttff, 99)) if ttff.size else None,
+        "pill_frames_per_s": pill_frames / span,
+        "wall_s": span,
+    }
+    if extra:
+        out.update(extra)
+    return out
+
+
+def serve_batched(requests, pool_bytes, dt=1.0 / 60.0, substeps=20, iterations=8, max_scenes=512,
+                  precision="f32", device="cuda:0", on_finish=None):
+    """Continuous batching over a device pool.  `on_finish(request, scene)` (optional) is
+    called with each finished scene before it is retired."""
+    import torch
+    pool = viper.Pool(pool_bytes, max_scenes=max_scenes, precision=precision, device=device)
+    copy_stream = torch.cuda.Stream(device=device)
+    main = torch.cuda.current_stream(device)
+    pending = deque(sorted(requests, key=lambda r: r.arrival))
+    waiting = deque()
+    resident = {}                     # slot -> [request, frames done, t_ready]
+    lat, ttff = [], []
+    pill_frames = 0
+    peak_bytes = 0
+    steps = 0
+    t0 = time.perf_counter()
+
+    def admit_ready():
+        nonlocal peak_bytes
+        now = time.perf_counter() - t0
+        while pending and pending[0].arrival <= now:
+            waiting.append(pending.popleft())
+        while waiting:
+            r = waiting[0]
+            slot = pool.admit(r.desc, stream=copy_stream)
+            if slot is None:
+                break
+            waiting.popleft()
+            resident[slot] = [r, 0, r.arrival]
+        info = pool.info()
+        peak_bytes = max(peak_bytes, pool_bytes - info["free_bytes"])
+
+    while pending or waiting or resident:
+        admit_ready()
+        if not resident:
+            if pending:
+                time.sleep(max(0.0, pending[0].arrival - (time.perf_counter() - t0)))
+            continue
+        members = list(resident.keys())
+        pool.step(dt, substeps, iterations, stream=main)
+        done_ev = torch.cuda.Event()
+        done_ev.record(main)
+        steps += 1
+        # overlap: admit arrivals (uploads on the copy stream) while the step runs
+        while not done_ev.query():
+            admit_ready()
+            time.sleep(20e-6)
+        done_ev.synchronize()
+        t_done = time.perf_counter() - t0
+        for slot in members:
+            st = resident[slot]
+            r = st[0]
+            lat.append(t_done - st[2])
+            if st[1] == 0:
+                ttff.append(t_done - r.arrival)
+            st[1] += 1
+            st[2] = t_done
+            pill_frames += r.desc.num_pills
+            if st[1] == r.frames:
+                if on_finish is not None:
+                    on_finish(r, pool.scene(slot))
+                pool.retire(slot, stream=main)
+                del resident[slot]
+    t_last = time.perf_counter() - t0
+    t_first = min(r.arrival for r in requests) if requests else 0.0
+    return _summary(lat, ttff, pill_frames, t_first, t_last,
+                    {"path": "batched", "steps": steps, "peak_resident_bytes": int(peak_bytes)})
+
+
+def serve_plain(requests, dt=1.0 / 60.0, substeps=20, iterations=8, precision="f32", device="cuda:0",
+                on_finish=None):
+    """First-come first-served, one scene at a time, one viper_step per frame."""
+    import torch
+    lat, ttff = [], []
+    pill_frames = 0
+    t0 = time.perf_counter()
+    for r in sorted(requests, key=lambda r: r.arrival):
+        now = time.perf_counter() - t0
+        if now < r.arrival:
+            time.sleep(r.arrival - now)
+        sc = viper.Scene(r.desc, precision, device=device)
+        t_ready = r.arrival
+        for k in range(r.frames):
+            sc.step(dt, substeps, iterations)
+            torch.cuda.synchronize(device)
+            t_done = time.perf_counter() - t0
+            lat.append(t_done - t_ready)
+            if k == 0:
+                ttff.append(t_done - r.arrival)
+            t_ready = t_done
+            pill_frames += r.desc.num_pills
+        if on_finish is not None:
+            on_finish(r, sc)
+        del sc
+    t_last = time.perf_counter() - t0
+    t_first = min(r.arrival for r in requests) if requests else 0.0
+    return _summary(lat, ttff, pill_frames, t_first, t_last, {"path": "plain"})

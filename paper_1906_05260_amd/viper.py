@@ -30,6 +30,8 @@ ABI_SYMBOLS = [
     "viper_scene_footprint", "viper_create_scene", "viper_step", "viper_step_ex", "viper_get_state",
     "viper_set_state", "viper_get_contacts", "viper_create_skin", "viper_skin", "viper_sync",
     "viper_destroy_scene", "viper_scene_info", "viper_last_error",
+    "viper_pool_create", "viper_pool_admit", "viper_pool_step", "viper_pool_retire", "viper_pool_scene",
+    "viper_pool_info", "viper_pool_destroy",
 ]
 
 
@@ -82,6 +84,14 @@ def lib():
         L.viper_sync.argtypes = [P, P]
         L.viper_destroy_scene.argtypes = [P]
         L.viper_scene_info.argtypes = [P] + [ctypes.POINTER(ctypes.c_int64)] * 4
+        L.viper_pool_create.argtypes = [P, ctypes.c_size_t, I32, I32, P, ctypes.POINTER(P)]
+        L.viper_pool_admit.argtypes = [P, P, P, ctypes.POINTER(I32)]
+        L.viper_pool_step.argtypes = [P, D, I32, I32, P]
+        L.viper_pool_retire.argtypes = [P, I32, P]
+        L.viper_pool_scene.argtypes = [P, I32, ctypes.POINTER(P)]
+        L.viper_pool_info.argtypes = [P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
+                                      ctypes.POINTER(I32), ctypes.POINTER(ctypes.c_int64)]
+        L.viper_pool_destroy.argtypes = [P]
         _lib = L
     return _lib
 
@@ -168,9 +178,30 @@ class Scene:
         self.capsules = int(caps.value)
         self.projections_per_iteration = int(ppi.value)
 
+    @classmethod
+    def attach(cls, handle, desc, precision, device):
+        """Wrap a scene handle owned elsewhere (a pool slot); it is not destroyed here."""
+        import torch
+        self = cls.__new__(cls)
+        self.desc = desc
+        self.precision = F64 if precision in ("f64", F64) else F32
+        self.dtype = torch.float64 if self.precision == F64 else torch.float32
+        self.device = torch.device(device)
+        self.handle = handle
+        self._owned = False
+        self.P = int(desc.num_pills)
+        self.num_rods = int(desc.num_rods)
+        self._skins = []
+        pills, rods, caps, ppi = (ctypes.c_int64() for _ in range(4))
+        check(lib().viper_scene_info(self.handle, ctypes.byref(pills), ctypes.byref(rods), ctypes.byref(caps),
+                                     ctypes.byref(ppi)))
+        self.capsules = int(caps.value)
+        self.projections_per_iteration = int(ppi.value)
+        return self
+
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
+        if h is not None and h.value and getattr(self, "_owned", True):
             try:
                 lib().viper_destroy_scene(h)
             except Exception:
@@ -239,3 +270,59 @@ class Scene:
 
     def sync(self, stream=None):
         check(lib().viper_sync(self.handle, _stream_ptr(stream)))
+
+
+class Pool:
+    """A serving pool (include/viper.h, viper_pool_*) over one torch workspace."""
+
+    def __init__(self, nbytes, max_scenes=256, precision="f32", device="cuda:0", stream=None):
+        import torch
+        self.device = torch.device(device)
+        self.precision = precision
+        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        check(lib().viper_pool_create(ctypes.c_void_p(self.workspace.data_ptr()), ctypes.c_size_t(int(nbytes)),
+                                      int(max_scenes), F64 if precision in ("f64", F64) else F32,
+                                      _stream_ptr(stream), ctypes.byref(h)))
+        self.handle = h
+        self.descs = {}
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            try:
+                lib().viper_pool_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    def admit(self, desc, stream=None, capacity=16):
+        """Slot id, or None when the pool has no room (VIPER_ERR_NO_CAPACITY)."""
+        hd = _DescHolder(desc, self.precision, None, capacity)
+        slot = ctypes.c_int32(-1)
+        st = lib().viper_pool_admit(self.handle, ctypes.byref(hd.c), _stream_ptr(stream), ctypes.byref(slot))
+        if st == ERR_NO_CAPACITY:
+            return None
+        check(st)
+        self.descs[int(slot.value)] = desc
+        return int(slot.value)
+
+    def step(self, dt, substeps, iterations, stream=None):
+        check(lib().viper_pool_step(self.handle, float(dt), int(substeps), int(iterations), _stream_ptr(stream)))
+
+    def retire(self, slot, stream=None):
+        check(lib().viper_pool_retire(self.handle, int(slot), _stream_ptr(stream)))
+        self.descs.pop(int(slot), None)
+
+    def scene(self, slot):
+        h = ctypes.c_void_p()
+        check(lib().viper_pool_scene(self.handle, int(slot), ctypes.byref(h)))
+        return Scene.attach(h, self.descs[int(slot)], self.precision, self.device)
+
+    def info(self):
+        fb, lf = ctypes.c_size_t(), ctypes.c_size_t()
+        n, pills = ctypes.c_int32(), ctypes.c_int64()
+        check(lib().viper_pool_info(self.handle, ctypes.byref(fb), ctypes.byref(lf), ctypes.byref(n),
+                                    ctypes.byref(pills)))
+        return dict(free_bytes=int(fb.value), largest_free=int(lf.value), resident=int(n.value),
+                    resident_pills=int(pills.value))

@@ -1,0 +1,114 @@
+"""Serving pool (continuous batching) on the GPU.
+
+- Each scene's result is the same alone and in the mix (staggered admissions and
+  retirements, collision-free and contact scenes together), within the stated tolerance
+  (1e-4 relative position error; in practice bit-identical: every scene runs the same
+  per-wave / per-block arithmetic whatever else shares the launch).
+- Admission is refused when no free range fits the footprint and succeeds after a
+  retirement frees one.
+- The batched server beats the plain per-scene path on the same requests.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1906_05260_amd import scenes, serve, viper  # noqa: E402
+from test_gpu_rods import errors  # noqa: E402
+
+DT, SUB, IT = 1 / 60, 20, 8
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run_alone(desc, frames, prec="f32"):
+    sc = viper.Scene(desc, prec)
+    for _ in range(frames):
+        sc.step(DT, SUB, IT)
+    sc.sync()
+    return sc.state()
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_alone_equals_mix(prec):
+    A = scenes.helix_rods(37, 64, seed=11)
+    B, _ = scenes.muscle_scene(num_muscles=6, seed=12, target_pills=None, mesh_vertices=0)
+    C = scenes.helix_rods(5, 64, seed=13)
+    D, _ = scenes.muscle_scene(num_muscles=3, seed=14, target_pills=None, mesh_vertices=0)
+    pool = viper.Pool(512 << 20, max_scenes=8, precision=prec)
+    plan = {}                                    # slot -> (desc, frames stepped)
+    frames = {}
+
+    def admit(desc, name):
+        s = pool.admit(desc)
+        assert s is not None
+        plan[name] = s
+        frames[name] = 0
+
+    def step(n):
+        for _ in range(n):
+            pool.step(DT, SUB, IT)
+            for k in frames:
+                if k not in retired:
+                    frames[k] += 1
+
+    retired = {}
+    admit(A, "A")
+    step(2)
+    admit(B, "B")
+    admit(C, "C")
+    step(3)
+    st = pool.scene(plan["A"]).state()
+    retired["A"] = st
+    pool.retire(plan["A"])
+    admit(D, "D")
+    step(2)
+    for name in ("B", "C", "D"):
+        retired[name] = pool.scene(plan[name]).state()
+    descs = {"A": A, "B": B, "C": C, "D": D}
+    for name, desc in descs.items():
+        alone = run_alone(desc, frames[name], prec)
+        e = errors(desc, retired[name], alone)
+        same = all(np.array_equal(retired[name][k], alone[k]) for k in ("x", "s", "q"))
+        say(prec, name, "frames", frames[name], "errors", e, "bit-identical", same)
+        assert max(e) < 1e-4
+    for name in ("B", "C", "D"):
+        pool.scene(plan[name]).sync()
+
+
+def test_admission_by_footprint():
+    big = scenes.helix_rods(1024, 64, seed=21)
+    small = scenes.helix_rods(8, 64, seed=22)
+    fp_big = viper.footprint(big)
+    pool = viper.Pool(int(fp_big * 1.3) + (4 << 20), max_scenes=4)
+    s1 = pool.admit(big)
+    assert s1 is not None
+    assert pool.admit(big) is None          # no free range fits a second one
+    s2 = pool.admit(small)
+    assert s2 is not None                   # but a small one still fits
+    pool.step(DT, SUB, IT)
+    pool.retire(s1)
+    s3 = pool.admit(big)                    # the freed range is reused
+    assert s3 is not None
+    pool.step(DT, SUB, IT)
+    pool.scene(s3).sync()
+    info = pool.info()
+    assert info["resident"] == 2
+
+
+def test_batched_beats_plain():
+    reqs = scenes.serving_requests(rate=200, duration=0.25, seed=31, min_pills=1000, max_pills=30000, frames=10)
+    say("requests", len(reqs), "pills", sum(r.desc.num_pills for r in reqs))
+    b = serve.serve_batched(reqs, pool_bytes=4 << 30)
+    p = serve.serve_plain(reqs)
+    say("batched", b)
+    say("plain", p)
+    assert b["frames"] == p["frames"] == sum(r.frames for r in reqs)
+    assert b["pill_frames_per_s"] > p["pill_frames_per_s"]
+    assert b["latency_ms_p99"] < p["latency_ms_p99"]
