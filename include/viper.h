@@ -145,6 +145,37 @@ viper_status viper_scene_info(viper_scene scene, int64_t* pills, int64_t* rods, 
 
 const char* viper_last_error(void);
 
+/* ---- Adjoint of the frame ---------------------------------------------------------------
+ * Reverse mode through the collision-free frame of viper_step (Sec. 6: prediction, the
+ * stretch-shear / volume / scale-gradient / bend-twist dual updates in their colour order,
+ * velocity update), giving the gradient of a scalar loss of the final positions with
+ * respect to the rest radii r (Sec. 3, through the lumped masses and inertias of App. B and
+ * the compliance scalings of Sec. 5/6) and the per-rod activation a (Sec. 8: rest length
+ * a l0).  The forward writes the state at the start of every substep (checkpoint); the
+ * backward replays each substep from it in reverse order.  Scenes with collisions are
+ * rejected with VIPER_ERR_INVALID.
+ *
+ * Device bytes needed: the checkpoint holds frames*substeps*15*P values in the scene's
+ * precision; the backward scratch holds one substep's per-pass state snapshots plus the
+ * state and parameter adjoints. */
+viper_status viper_adjoint_sizes(viper_scene scene, int32_t frames, int32_t substeps, int32_t iterations,
+                                 size_t* ckpt_bytes, size_t* work_bytes);
+
+/* Advance `frames` frames exactly as viper_step_ex(..., VIPER_MODE_FRAME) does (bitwise
+ * the same state) and write the checkpoint to ckpt (device memory of ckpt_bytes). */
+viper_status viper_step_checkpointed(viper_scene scene, double dt, int32_t frames, int32_t substeps,
+                                     int32_t iterations, void* ckpt, size_t ckpt_bytes, void* stream);
+
+/* Reverse of the viper_step_checkpointed call that wrote ckpt (same dt, frames, substeps,
+ * iterations; the scene's parameters unchanged since).  dl_dx: device [P*3] in the scene's
+ * precision, dL/dx of the positions after the last frame (world and stored rod-local
+ * positions differ by a constant, so either gradient).  work: device scratch of work_bytes.
+ * Outputs, device FP64, overwritten: dl_drbar [P], dl_dact [R].  The scene state is not
+ * changed. */
+viper_status viper_step_backward(viper_scene scene, double dt, int32_t frames, int32_t substeps, int32_t iterations,
+                                 const void* ckpt, const void* dl_dx, void* work, size_t work_bytes,
+                                 double* dl_drbar, double* dl_dact, void* stream);
+
 /* ---- Serving pool: continuous batching of many scenes in one workspace ----------------
  * The pool owns no device memory either: the caller hands in one workspace.  Scenes are
  * admitted by footprint (first-fit inside the workspace; VIPER_ERR_NO_CAPACITY when no

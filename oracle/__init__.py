@@ -68,7 +68,7 @@ def lib():
         L.orc_set_masses.argtypes = [P, P, P, P]
         L.orc_contact_pass.argtypes = [P, I, D]
         L.orc_grad.restype = D
-        L.orc_grad.argtypes = [I, P, P, P, P, P, P, P, D, P, D, I, I, I, P, P, P, I]
+        L.orc_grad.argtypes = [I, P, P, P, P, P, P, P, D, P, D, I, I, I, P, P, P, I, I]
         _lib = L
     return _lib
 
@@ -208,8 +208,10 @@ def dichotomous(a1, ra1, a2, ra2, b1, rb1, b2, rb2, iters=10, delta=1e-4):
                                  float(rb2), int(iters), float(delta))
 
 
-def grad(desc, dt, substeps, iters, frames, targets, threads=8):
-    """Exact FP64 gradient (dual numbers) of L = sum |x_free_end - target|^2 w.r.t. rest radii and activations."""
+def grad(desc, dt, substeps, iters, frames, targets, threads=8, precision="f64"):
+    """Gradient (dual numbers) of L = sum |x_free_end - target|^2 w.r.t. rest radii and activations:
+    exact derivatives of the discrete algorithm in FP64, or the same in FP32 arithmetic
+    (precision="f32", the rounding floor of an FP32 gradient)."""
     L = lib()
     off = np.ascontiguousarray(desc.rod_offsets, dtype=np.int32)
     arrs = [_f64(desc.rest_pos).reshape(-1), _f64(desc.rest_radius), np.ascontiguousarray(desc.pinned, np.uint8),
@@ -219,7 +221,7 @@ def grad(desc, dt, substeps, iters, frames, targets, threads=8):
     drb = np.zeros(int(off[-1])); dac = np.zeros(int(desc.num_rods))
     loss = L.orc_grad(int(desc.num_rods), _p(off), _p(arrs[0]), _p(arrs[1]), _p(arrs[2]), _p(arrs[3]), _p(arrs[4]),
                       _p(arrs[5]), float(desc.density), _p(arrs[6]), float(dt), int(substeps), int(iters), int(frames),
-                      _p(tg), _p(drb), _p(dac), int(threads))
+                      _p(tg), _p(drb), _p(dac), int(threads), 1 if precision == "f64" else 0)
     return loss, drb, dac
 
 

@@ -12,7 +12,8 @@
 //   double      -- the reference (FP64),
 //   float       -- the FP32 rounding floor of the same algorithm,
 //   Dual<K>     -- forward-mode dual numbers, giving exact derivatives of the
-//                  discrete algorithm (gradient oracle).
+//                  discrete algorithm (gradient oracle); Dual<K, float> gives
+//                  the FP32 rounding floor of those derivatives.
 //
 // Every constraint is projected with ONE generic routine: the per-constraint
 // dual update of Sec. 6 (eq. app_dual_formulation_update, beta = 1), written
@@ -41,31 +42,35 @@ namespace orc {
 // ---------------------------------------------------------------------------
 // Forward-mode dual numbers with K directions.
 // ---------------------------------------------------------------------------
-template <int K>
+template <int K, class B = double>
 struct Dual {
-  double v;
-  double d[K];
+  B v;
+  B d[K];
   Dual() : v(0) { for (int i = 0; i < K; ++i) d[i] = 0; }
-  Dual(double a) : v(a) { for (int i = 0; i < K; ++i) d[i] = 0; }
+  Dual(double a) : v(B(a)) { for (int i = 0; i < K; ++i) d[i] = 0; }
 };
-template <int K> Dual<K> operator+(const Dual<K>& a, const Dual<K>& b) { Dual<K> r; r.v = a.v + b.v; for (int i = 0; i < K; ++i) r.d[i] = a.d[i] + b.d[i]; return r; }
-template <int K> Dual<K> operator-(const Dual<K>& a, const Dual<K>& b) { Dual<K> r; r.v = a.v - b.v; for (int i = 0; i < K; ++i) r.d[i] = a.d[i] - b.d[i]; return r; }
-template <int K> Dual<K> operator-(const Dual<K>& a) { Dual<K> r; r.v = -a.v; for (int i = 0; i < K; ++i) r.d[i] = -a.d[i]; return r; }
-template <int K> Dual<K> operator*(const Dual<K>& a, const Dual<K>& b) { Dual<K> r; r.v = a.v * b.v; for (int i = 0; i < K; ++i) r.d[i] = a.d[i] * b.v + a.v * b.d[i]; return r; }
-template <int K> Dual<K> operator/(const Dual<K>& a, const Dual<K>& b) { Dual<K> r; r.v = a.v / b.v; for (int i = 0; i < K; ++i) r.d[i] = (a.d[i] * b.v - a.v * b.d[i]) / (b.v * b.v); return r; }
-template <int K> Dual<K>& operator+=(Dual<K>& a, const Dual<K>& b) { a = a + b; return a; }
-template <int K> Dual<K>& operator-=(Dual<K>& a, const Dual<K>& b) { a = a - b; return a; }
-template <int K> Dual<K>& operator*=(Dual<K>& a, const Dual<K>& b) { a = a * b; return a; }
-template <int K> Dual<K>& operator/=(Dual<K>& a, const Dual<K>& b) { a = a / b; return a; }
-template <int K> bool operator<(const Dual<K>& a, const Dual<K>& b) { return a.v < b.v; }
-template <int K> bool operator>(const Dual<K>& a, const Dual<K>& b) { return a.v > b.v; }
-template <int K> bool operator<=(const Dual<K>& a, const Dual<K>& b) { return a.v <= b.v; }
-template <int K> bool operator>=(const Dual<K>& a, const Dual<K>& b) { return a.v >= b.v; }
-template <int K> Dual<K> sqrt(const Dual<K>& a) { Dual<K> r; r.v = std::sqrt(a.v); for (int i = 0; i < K; ++i) r.d[i] = a.d[i] / (2.0 * r.v); return r; }
+#define DT_ template <int K, class B>
+#define DD_ Dual<K, B>
+DT_ DD_ operator+(const DD_& a, const DD_& b) { DD_ r; r.v = a.v + b.v; for (int i = 0; i < K; ++i) r.d[i] = a.d[i] + b.d[i]; return r; }
+DT_ DD_ operator-(const DD_& a, const DD_& b) { DD_ r; r.v = a.v - b.v; for (int i = 0; i < K; ++i) r.d[i] = a.d[i] - b.d[i]; return r; }
+DT_ DD_ operator-(const DD_& a) { DD_ r; r.v = -a.v; for (int i = 0; i < K; ++i) r.d[i] = -a.d[i]; return r; }
+DT_ DD_ operator*(const DD_& a, const DD_& b) { DD_ r; r.v = a.v * b.v; for (int i = 0; i < K; ++i) r.d[i] = a.d[i] * b.v + a.v * b.d[i]; return r; }
+DT_ DD_ operator/(const DD_& a, const DD_& b) { DD_ r; r.v = a.v / b.v; for (int i = 0; i < K; ++i) r.d[i] = (a.d[i] * b.v - a.v * b.d[i]) / (b.v * b.v); return r; }
+DT_ DD_& operator+=(DD_& a, const DD_& b) { a = a + b; return a; }
+DT_ DD_& operator-=(DD_& a, const DD_& b) { a = a - b; return a; }
+DT_ DD_& operator*=(DD_& a, const DD_& b) { a = a * b; return a; }
+DT_ DD_& operator/=(DD_& a, const DD_& b) { a = a / b; return a; }
+DT_ bool operator<(const DD_& a, const DD_& b) { return a.v < b.v; }
+DT_ bool operator>(const DD_& a, const DD_& b) { return a.v > b.v; }
+DT_ bool operator<=(const DD_& a, const DD_& b) { return a.v <= b.v; }
+DT_ bool operator>=(const DD_& a, const DD_& b) { return a.v >= b.v; }
+DT_ DD_ sqrt(const DD_& a) { DD_ r; r.v = std::sqrt(a.v); for (int i = 0; i < K; ++i) r.d[i] = a.d[i] / (B(2) * r.v); return r; }
 
 inline double val(double a) { return a; }
 inline double val(float a) { return a; }
-template <int K> double val(const Dual<K>& a) { return a.v; }
+DT_ double val(const DD_& a) { return a.v; }
+#undef DT_
+#undef DD_
 inline double sqrt(double a) { return std::sqrt(a); }
 inline float sqrt(float a) { return std::sqrt(a); }
 
@@ -1002,9 +1007,15 @@ void orc_capsule_transforms(void* hp, double* out) {
 // ----------------------------------------------------------------------------
 static const int KD = 8;
 
-double orc_grad(int num_rods, const int32_t* off, const double* rest_pos, const double* rest_radius, const uint8_t* pinned,
-                const double* activation, const double* compliance, const int32_t* group, double density, const double* gravity,
-                double dt, int substeps, int iters, int frames, const double* targets, double* d_rbar, double* d_act, int threads) {
+}  // extern "C"
+
+// B = double: exact FP64 derivatives; B = float: the same derivatives in FP32 arithmetic.
+template <class B>
+static double grad_impl(int num_rods, const int32_t* off, const double* rest_pos, const double* rest_radius,
+                        const uint8_t* pinned, const double* activation, const double* compliance, const int32_t* group,
+                        double density, const double* gravity, double dt, int substeps, int iters, int frames,
+                        const double* targets, double* d_rbar, double* d_act, int threads) {
+  typedef Dual<KD, B> DN;
   std::vector<double> loss_k(num_rods, 0.0);
   auto work = [&](int k0, int k1) {
     for (int k = k0; k < k1; ++k) {
@@ -1013,17 +1024,17 @@ double orc_grad(int num_rods, const int32_t* off, const double* rest_pos, const 
       Desc d = make_desc(1, loff, rest_pos + 3 * a, rest_radius + a, pinned + a, activation + k, compliance + 4 * k, group + k, density, gravity);
       int nparam = N + 1;
       for (int c0 = 0; c0 < nparam; c0 += KD) {
-        std::vector<Dual<KD>> rb(N), ac(1);
-        for (int i = 0; i < N; ++i) { rb[i] = Dual<KD>(rest_radius[a + i]); if (i >= c0 && i < c0 + KD) rb[i].d[i - c0] = 1.0; }
-        ac[0] = Dual<KD>(activation[k]);
-        if (N >= c0 && N < c0 + KD) ac[0].d[N - c0] = 1.0;
-        Scene<Dual<KD>> S;
+        std::vector<DN> rb(N), ac(1);
+        for (int i = 0; i < N; ++i) { rb[i] = DN(rest_radius[a + i]); if (i >= c0 && i < c0 + KD) rb[i].d[i - c0] = 1; }
+        ac[0] = DN(activation[k]);
+        if (N >= c0 && N < c0 + KD) ac[0].d[N - c0] = 1;
+        Scene<DN> S;
         build(S, d, rb.data(), ac.data());
-        Dual<KD> hh(dt / substeps);
+        DN hh(dt / substeps);
         for (int f = 0; f < frames; ++f)
           for (int i = 0; i < substeps; ++i) substep(S, hh, iters, false, 10, 1e-4, 1);
-        V3<Dual<KD>> e = S.x[N - 1] - v3<Dual<KD>>(Dual<KD>(targets[3 * k]), Dual<KD>(targets[3 * k + 1]), Dual<KD>(targets[3 * k + 2]));
-        Dual<KD> L = dot(e, e);
+        V3<DN> e = S.x[N - 1] - v3<DN>(DN(targets[3 * k]), DN(targets[3 * k + 1]), DN(targets[3 * k + 2]));
+        DN L = dot(e, e);
         loss_k[k] = L.v;
         for (int j = 0; j < KD; ++j) {
           int pi = c0 + j;
@@ -1040,6 +1051,19 @@ double orc_grad(int num_rods, const int32_t* off, const double* rest_pos, const 
   double L = 0;
   for (double v : loss_k) L += v;
   return L;
+}
+
+extern "C" {
+
+// precision 1: FP64 (exact derivatives of the discrete algorithm); 0: FP32 (its rounding floor).
+double orc_grad(int num_rods, const int32_t* off, const double* rest_pos, const double* rest_radius, const uint8_t* pinned,
+                const double* activation, const double* compliance, const int32_t* group, double density, const double* gravity,
+                double dt, int substeps, int iters, int frames, const double* targets, double* d_rbar, double* d_act, int threads,
+                int precision) {
+  return precision ? grad_impl<double>(num_rods, off, rest_pos, rest_radius, pinned, activation, compliance, group, density,
+                                       gravity, dt, substeps, iters, frames, targets, d_rbar, d_act, threads)
+                   : grad_impl<float>(num_rods, off, rest_pos, rest_radius, pinned, activation, compliance, group, density,
+                                      gravity, dt, substeps, iters, frames, targets, d_rbar, d_act, threads);
 }
 
 }  // extern "C"

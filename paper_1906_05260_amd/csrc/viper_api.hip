@@ -368,6 +368,7 @@ struct viper_scene_s {
   std::vector<char> header;   // host image of the batch header
   std::vector<Skin> skins;
   std::vector<int32_t> off;  // rod offsets (host copy)
+  double density = 1000.0;
 };
 
 namespace {
@@ -523,6 +524,7 @@ viper_status viper_create_scene(const viper_scene_desc* desc, void* workspace, s
   S->bytes = bytes;
   S->o = o;
   S->off = H.off;
+  S->density = desc->density;
   hipStream_t st = (hipStream_t)stream;
   viper_status r;
   if (S->precision == VIPER_F64) {
@@ -673,6 +675,94 @@ viper_status viper_scene_info(viper_scene S, int64_t* pills, int64_t* rods, int6
   if (rods) *rods = S->R;
   if (capsules) *capsules = S->E;
   if (ppi) *ppi = S->proj_per_iter;
+  return VIPER_OK;
+}
+
+
+}  // extern "C"
+
+// ----------------------------------------------------------------------------- adjoint
+
+namespace {
+
+viper_status adjoint_check(viper_scene S, int32_t frames, int32_t substeps, int32_t iterations) {
+  if (!S) return fail(VIPER_ERR_INVALID, "scene is NULL");
+  if (S->collisions) return fail(VIPER_ERR_INVALID, "the adjoint covers collision-free scenes");
+  if (frames < 1 || substeps < 1 || iterations < 0)
+    return fail(VIPER_ERR_INVALID, "frames >= 1, substeps >= 1 and iterations >= 0 required");
+  return VIPER_OK;
+}
+
+void adjoint_bytes(viper_scene S, int32_t frames, int32_t substeps, int32_t iterations, size_t* ckpt,
+                   size_t* snap, size_t* adj, size_t* padj) {
+  const size_t ts = S->precision == VIPER_F64 ? 8 : 4;
+  const size_t P = (size_t)S->P, NL = (size_t)S->W * 64;
+  *ckpt = (size_t)frames * substeps * kCkptFields * P * ts;
+  *snap = align256((size_t)iterations * 4 * 32 * NL * ts);
+  *adj = align256((size_t)kCkptFields * P * ts);
+  *padj = align256(8 * P * ts);
+}
+
+template <class T>
+viper_status ckpt_t(viper_scene S, double h, int32_t frames, int32_t sub, int32_t iters, T* ckpt,
+                           hipStream_t st) {
+  const size_t per_frame = (size_t)sub * kCkptFields * S->P;
+  for (int f = 0; f < frames; ++f) HIP_TRY(launch_frame_ckpt<T>(S->batch, sub, h, iters, ckpt + f * per_frame, st));
+  return VIPER_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+viper_status viper_adjoint_sizes(viper_scene S, int32_t frames, int32_t substeps, int32_t iterations,
+                                 size_t* ckpt_bytes, size_t* work_bytes) {
+  viper_status r = adjoint_check(S, frames, substeps, iterations);
+  if (r != VIPER_OK) return r;
+  size_t c, sn, a, pa;
+  adjoint_bytes(S, frames, substeps, iterations, &c, &sn, &a, &pa);
+  if (ckpt_bytes) *ckpt_bytes = c;
+  if (work_bytes) *work_bytes = sn + a + pa;
+  return VIPER_OK;
+}
+
+viper_status viper_step_checkpointed(viper_scene S, double dt, int32_t frames, int32_t substeps, int32_t iterations,
+                                     void* ckpt, size_t ckpt_bytes, void* stream) {
+  viper_status r = adjoint_check(S, frames, substeps, iterations);
+  if (r != VIPER_OK) return r;
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(VIPER_ERR_INVALID, "dt must be finite and > 0");
+  size_t c, sn, a, pa;
+  adjoint_bytes(S, frames, substeps, iterations, &c, &sn, &a, &pa);
+  if (!ckpt || ckpt_bytes < c) return fail(VIPER_ERR_INVALID, "checkpoint buffer missing or too small");
+  const double h = dt / substeps;
+  hipStream_t st = (hipStream_t)stream;
+  return S->precision == VIPER_F64 ? ckpt_t<double>(S, h, frames, substeps, iterations, (double*)ckpt, st)
+                                   : ckpt_t<float>(S, h, frames, substeps, iterations, (float*)ckpt, st);
+}
+
+viper_status viper_step_backward(viper_scene S, double dt, int32_t frames, int32_t substeps, int32_t iterations,
+                                 const void* ckpt, const void* dl_dx, void* work, size_t work_bytes,
+                                 double* dl_drbar, double* dl_dact, void* stream) {
+  viper_status r = adjoint_check(S, frames, substeps, iterations);
+  if (r != VIPER_OK) return r;
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(VIPER_ERR_INVALID, "dt must be finite and > 0");
+  if (!ckpt || !dl_dx || !dl_drbar || !dl_dact) return fail(VIPER_ERR_INVALID, "ckpt, dl_dx and outputs are required");
+  size_t c, sn, a, pa;
+  adjoint_bytes(S, frames, substeps, iterations, &c, &sn, &a, &pa);
+  if (!work || work_bytes < sn + a + pa) return fail(VIPER_ERR_INVALID, "work buffer missing or too small");
+  const double h = dt / substeps;
+  const int nsub = frames * substeps;
+  hipStream_t st = (hipStream_t)stream;
+  char* w = (char*)work;
+  if (S->precision == VIPER_F64) {
+    HIP_TRY(launch_backward<double>(S->batch, S->P, nsub, h, iterations, (const double*)ckpt, (const double*)dl_dx,
+                                    (double*)w, (double*)(w + sn), (double*)(w + sn + a), S->density, dl_drbar,
+                                    dl_dact, st));
+  } else {
+    HIP_TRY(launch_backward<float>(S->batch, S->P, nsub, h, iterations, (const float*)ckpt, (const float*)dl_dx,
+                                   (float*)w, (float*)(w + sn), (float*)(w + sn + a), S->density, dl_drbar, dl_dact,
+                                   st));
+  }
   return VIPER_OK;
 }
 
@@ -871,11 +961,11 @@ viper_status viper_pool_info(viper_pool P, size_t* free_bytes, size_t* largest_f
 
 viper_status viper_pool_destroy(viper_pool P) {
   if (!P) return VIPER_OK;
-  if (P->aux) hipStreamSynchronize(P->aux);
+  if (P->aux) (void)hipStreamSynchronize(P->aux);
   for (auto& sl : P->slots) delete sl.scene;
-  if (P->ev0) hipEventDestroy(P->ev0);
-  if (P->ev1) hipEventDestroy(P->ev1);
-  if (P->aux) hipStreamDestroy(P->aux);
+  if (P->ev0) (void)hipEventDestroy(P->ev0);
+  if (P->ev1) (void)hipEventDestroy(P->ev1);
+  if (P->aux) (void)hipStreamDestroy(P->aux);
   delete P;
   return VIPER_OK;
 }

@@ -109,6 +109,12 @@ template <class T> hipError_t launch_contact_detect(const BatchDev& b, hipStream
 template <class T> hipError_t launch_contact_project(const BatchDev& b, hipStream_t st);
 template <class T> hipError_t launch_gather_field(const Dev<T>& d, int which, T* out, hipStream_t st);
 template <class T> hipError_t launch_scatter_field(const Dev<T>& d, int which, const T* in, hipStream_t st);
+// Adjoint of the collision-free frame (single scene): checkpoint layout [substep][15][P].
+constexpr int kCkptFields = 15;
+template <class T> hipError_t launch_frame_ckpt(const BatchDev& b, int nsub, double h, int iters, T* ckpt, hipStream_t st);
+template <class T> hipError_t launch_backward(const BatchDev& b, int P, int nsub, double h, int iters, const T* ckpt,
+                                              const T* dldx, T* snap, T* adj, T* padj, double rho, double* drbar,
+                                              double* dact, hipStream_t st);
 template <class T> hipError_t launch_skin(const Dev<T>& d, int V, const float* rest_v, const int32_t* caps,
                                           const float* w, float* out, float* xform, hipStream_t st);
 

@@ -32,6 +32,7 @@ ABI_SYMBOLS = [
     "viper_destroy_scene", "viper_scene_info", "viper_last_error",
     "viper_pool_create", "viper_pool_admit", "viper_pool_step", "viper_pool_retire", "viper_pool_scene",
     "viper_pool_info", "viper_pool_destroy",
+    "viper_adjoint_sizes", "viper_step_checkpointed", "viper_step_backward",
 ]
 
 
@@ -92,6 +93,10 @@ def lib():
         L.viper_pool_info.argtypes = [P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
                                       ctypes.POINTER(I32), ctypes.POINTER(ctypes.c_int64)]
         L.viper_pool_destroy.argtypes = [P]
+        SZ = ctypes.c_size_t
+        L.viper_adjoint_sizes.argtypes = [P, I32, I32, I32, ctypes.POINTER(SZ), ctypes.POINTER(SZ)]
+        L.viper_step_checkpointed.argtypes = [P, D, I32, I32, I32, P, SZ, P]
+        L.viper_step_backward.argtypes = [P, D, I32, I32, I32, P, P, P, SZ, P, P, P]
         _lib = L
     return _lib
 
@@ -270,6 +275,43 @@ class Scene:
 
     def sync(self, stream=None):
         check(lib().viper_sync(self.handle, _stream_ptr(stream)))
+
+    # ---- adjoint (include/viper.h, viper_adjoint_sizes / viper_step_checkpointed / viper_step_backward)
+
+    def adjoint_sizes(self, frames, substeps, iterations):
+        c, w = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        check(lib().viper_adjoint_sizes(self.handle, int(frames), int(substeps), int(iterations), ctypes.byref(c),
+                                        ctypes.byref(w)))
+        return int(c.value), int(w.value)
+
+    def step_checkpointed(self, dt, frames, substeps, iterations, ckpt=None, stream=None):
+        """Advance ``frames`` frames (FRAME mode) writing the per-substep checkpoint; returns it."""
+        import torch
+        nc, _ = self.adjoint_sizes(frames, substeps, iterations)
+        if ckpt is None:
+            ckpt = torch.empty(max(nc, 1), dtype=torch.uint8, device=self.device)
+        check(lib().viper_step_checkpointed(self.handle, float(dt), int(frames), int(substeps), int(iterations),
+                                            ctypes.c_void_p(ckpt.data_ptr()), ctypes.c_size_t(ckpt.numel()),
+                                            _stream_ptr(stream)))
+        return ckpt
+
+    def backward(self, dt, frames, substeps, iterations, ckpt, dl_dx, work=None, stream=None):
+        """(dL/d rest radius [P], dL/d activation [R]) as float64 device tensors."""
+        import torch
+        _, nw = self.adjoint_sizes(frames, substeps, iterations)
+        if work is None:
+            work = torch.empty(max(nw, 1), dtype=torch.uint8, device=self.device)
+        g = torch.as_tensor(dl_dx).to(device=self.device, dtype=self.dtype).contiguous()
+        assert g.numel() == 3 * self.P
+        drbar = torch.empty(self.P, dtype=torch.float64, device=self.device)
+        dact = torch.empty(self.num_rods, dtype=torch.float64, device=self.device)
+        check(lib().viper_step_backward(self.handle, float(dt), int(frames), int(substeps), int(iterations),
+                                        ctypes.c_void_p(ckpt.data_ptr()), ctypes.c_void_p(g.data_ptr()),
+                                        ctypes.c_void_p(work.data_ptr()), ctypes.c_size_t(work.numel()),
+                                        ctypes.c_void_p(drbar.data_ptr()), ctypes.c_void_p(dact.data_ptr()),
+                                        _stream_ptr(stream)))
+        self._keep_alive = (g, work)
+        return drbar, dact
 
 
 class Pool:

@@ -193,10 +193,10 @@ def test_helix_4096x64_full_horizon():
 def test_helix_one_frame_parity_late_in_horizon():
     """From the GPU's own FP32 state after 50 and 99 frames (rods swinging at several
     m/s), one more frame on the GPU and on the FP64 oracle: the GPU error is within 3x the
-    FP32 oracle's own error (its rounding floor, 1e-5..4e-4 here) on every rod, and within
+    FP32 oracle's own error (its rounding floor: 1e-5 up to O(0.1) on a rod in a chaotic phase) on every rod, and within
     1e-4 wherever that floor is below 1e-4 / 3."""
     desc = scenes.helix_rods(4096, 64, seed=1)
-    rods = [0, 1, 2, 3, 777, 1500, 3500, 4000]
+    rods = [0, 1, 2, 3] + list(range(171, 4096, 171))     # 27 rods spread over the scene
     sub = local_subset(desc, rods)      # the oracle works in the same rod-anchored frame
     idx = desc.pill_index(rods)
     sc = viper.Scene(desc, "f32")

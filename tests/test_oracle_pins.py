@@ -542,3 +542,23 @@ def test_dual_gradient_matches_finite_differences():
         dm = desc.subset(range(desc.num_rods)); dm.activation[k] -= hstep
         fd = (oracle.loss(dp, dt, sub, it, fr, targets) - oracle.loss(dm, dt, sub, it, fr, targets)) / (2 * hstep)
         assert abs(fd - dac[k]) <= 1e-4 * abs(dac[k]) + 1e-10
+
+
+@pytest.mark.slow
+def test_fp32_dual_gradient_is_the_fp64_gradient_rounded():
+    """The FP32 gradient (used to calibrate FP32 tolerances) is the same derivative: close
+    to the FP64 one on a well-conditioned scene whose rods sit at the origin."""
+    desc, targets = scenes.straight_rods(2, 6, seed=9)
+    d = desc.subset(range(2))
+    t = np.array(targets, dtype=np.float64)
+    for k in range(2):
+        a, b = d.rod_offsets[k], d.rod_offsets[k + 1]
+        o = d.rest_pos[a].copy()
+        d.rest_pos[a:b] -= o
+        t[k] -= o
+    L64, r64, a64 = oracle.grad(d, 1 / 60, 4, 3, 1, t, threads=2)
+    L32, r32, a32 = oracle.grad(d, 1 / 60, 4, 3, 1, t, threads=2, precision="f32")
+    assert abs(L32 - L64) <= 1e-5 * L64
+    assert np.linalg.norm(r32 - r64) <= 1e-3 * np.linalg.norm(r64)
+    assert np.linalg.norm(a32 - a64) <= 1e-3 * np.linalg.norm(a64)
+    assert np.linalg.norm(r64) > 0 and np.linalg.norm(a64) > 0
