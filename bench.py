@@ -68,6 +68,81 @@ def cpu_baseline(desc, dt, sub, iters, rods):
                       (rods, desc.num_rods, sub, iters)}
 
 
+def copy_reference(torch, dev, mib, steps):
+    """A plain elementwise copy kernel (read n bytes, write n bytes) of known size."""
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        torch.neg(a, out=b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    print(json.dumps({"kernel": "neg (elementwise copy)", "bytes_read": 4 * n, "bytes_written": 4 * n,
+                      "ms_per_launch": ms, "GB_per_s": 8 * n / (ms * 1e-3) / 1e9}), flush=True)
+
+
+def adjoint_timing(torch, viper, scenes, dev, reps=5):
+    """Forward with per-substep checkpoints and backward of one frame on 1024 straight rods x
+    32 pills (FP32, 20 substeps x 8 iterations), L = sum |x_free_end - target|^2."""
+    desc, targets = scenes.straight_rods(1024, 32, seed=4)
+    dt, sub, iters = 1.0 / 60.0, 20, 8
+    st = torch.cuda.current_stream()
+    times = {"plain": [], "forward": [], "backward": []}
+    last = torch.as_tensor(desc.rod_offsets[1:] - 1, device=dev, dtype=torch.long)
+    tg = torch.as_tensor(targets, device=dev, dtype=torch.float32)
+    for r in range(reps + 1):
+        sc = viper.Scene(desc, "f32", device=dev)
+        nc, nw = sc.adjoint_sizes(1, sub, iters)
+        ckpt = torch.empty(nc, dtype=torch.uint8, device=dev)
+        work = torch.empty(nw, dtype=torch.uint8, device=dev)
+        ref = viper.Scene(desc, "f32", device=dev)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+        ev[0].record(st)
+        ref.step(dt, sub, iters, mode=viper.MODE_FRAME)
+        ev[1].record(st)
+        ev[2].record(st)
+        sc.step_checkpointed(dt, 1, sub, iters, ckpt=ckpt)
+        ev[3].record(st)
+        x = sc.get("x")
+        g = torch.zeros_like(x)
+        g[last] = 2.0 * (x[last] - tg)
+        ev[4].record(st)
+        sc.backward(dt, 1, sub, iters, ckpt, g, work=work)
+        ev[5].record(st)
+        torch.cuda.synchronize()
+        sc.sync()
+        if r > 0:
+            times["plain"].append(ev[0].elapsed_time(ev[1]))
+            times["forward"].append(ev[2].elapsed_time(ev[3]))
+            times["backward"].append(ev[4].elapsed_time(ev[5]))
+    med = {k: float(sorted(v)[len(v) // 2]) for k, v in times.items()}
+    return {"workload": "straight1024x32", "frames": 1, "substeps": sub, "iterations": iters, "dtype": "f32",
+            "plain_frame_ms": med["plain"], "forward_checkpointed_ms": med["forward"],
+            "backward_ms": med["backward"], "backward_over_forward": med["backward"] / med["plain"],
+            "checkpoint_bytes": nc, "backward_scratch_bytes": nw,
+            "params": desc.num_pills + desc.num_rods}
+
+
+def serving_run(torch, scenes, serve, seconds):
+    """Poisson arrivals (200/s) of helix and muscle scenes of 1k-200k pills (log-uniform),
+    60 frames each; continuous batching vs the plain per-scene path on the same requests."""
+    reqs = scenes.serving_requests(rate=200, duration=seconds, seed=3)
+    b = serve.serve_batched(reqs, pool_bytes=32 << 30)
+    torch.cuda.synchronize()
+    p = serve.serve_plain(reqs)
+    keep = ("frames", "latency_ms_p50", "latency_ms_p99", "ttff_ms_p50", "ttff_ms_p99", "pill_frames_per_s", "wall_s")
+    return {"workload": "poisson200x%.2fs_1k-200k_60frames" % seconds, "requests": len(reqs),
+            "pills": int(sum(r.desc.num_pills for r in reqs)),
+            "contact_requests": int(sum(r.kind == "muscle" for r in reqs)),
+            "batched": {k: b[k] for k in keep + ("steps", "peak_resident_bytes")},
+            "plain": {k: p[k] for k in keep}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +155,13 @@ def main():
     ap.add_argument("--mode", default="frame", choices=["frame", "substep"])
     ap.add_argument("--cpu-rods", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=0.5,
+                    help="arrival window of the serving workload (Poisson, 200 requests/s)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="instead of the solver, time a plain device copy of this many MiB (the "
+                         "reference kernel for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the solver runs on a single MI355X "
@@ -91,6 +173,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_mib:
+        copy_reference(torch, dev, args.copy_mib, args.steps)
+        return
     dt, sub, iters = 1.0 / 60.0, args.substeps, args.iters
     desc = scenes.helix_rods(args.rods, args.pills, seed=1)
     sc = viper.Scene(desc, "f32", device=dev)
@@ -139,7 +224,7 @@ def main():
             "algorithmic_bytes_per_launch": bytes_launch,
             "algorithmic_hbm_frac": bytes_launch / (kern_ms * 1e-3) / PEAK_HBM}
     out = {
-        "metric": "pill-constraint projections/sec at fixed iters",
+        "metric": "pill-constraint projections/sec at fixed iters; served p50/p99 frame latency",
         "value": value,
         "unit": "projections/s",
         "n_gpus": 1,
@@ -156,6 +241,13 @@ def main():
                    "pill_substeps_per_s": P * sub * K / elapsed},
         "roofline": roof,
     }
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_timing(torch, viper, scenes, dev)
+    if not args.no_serve:
+        from paper_1906_05260_amd import serve
+        out["serving"] = serving_run(torch, scenes, serve, args.serve_seconds)
+        out["latency_ms_p50"] = out["serving"]["batched"]["latency_ms_p50"]
+        out["latency_ms_p99"] = out["serving"]["batched"]["latency_ms_p99"]
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(desc, dt, sub, iters, min(args.cpu_rods, desc.num_rods))
     print(json.dumps(out), flush=True)
