@@ -128,6 +128,52 @@ def adjoint_timing(torch, viper, scenes, dev, reps=5):
             "params": desc.num_pills + desc.num_rods}
 
 
+def contact_skin_timing(torch, viper, scenes, dev, frames=10):
+    """The muscle scene (64 muscles, ~45k pills, FP32, uniform-grid pill-pill contacts,
+    20 substeps x 8 iterations) and LBS skinning of its 200k-vertex mesh: ms per frame
+    and per skinning pass, timed with HIP events on the launch stream."""
+    desc, mesh = scenes.muscle_scene(64, seed=2)
+    sc = viper.Scene(desc, "f32", device=dev, collisions=True)
+    sid = sc.create_skin(mesh.rest_v, mesh.caps, mesh.w)
+    dt, sub, iters = 1.0 / 60.0, 20, 8
+    for _ in range(2):
+        sc.step(dt, sub, iters)
+    sc.sync()
+    st = torch.cuda.current_stream()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    out = torch.empty((mesh.rest_v.shape[0], 3), dtype=torch.float32, device=dev)
+    e3, e4 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(frames):
+        sc.step(dt, sub, iters)                       # GRAPH: the captured frame replayed
+    e1.record(st)
+    for _ in range(frames):
+        sc.skin(sid, out=out)
+    e2.record(st)
+    for _ in range(frames):
+        sc.step(dt, sub, iters, mode=viper.MODE_ITERATION)   # the same launches, eager
+    e3.record(st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(frames):
+        sc.step(dt, sub, iters)
+    torch.cuda.synchronize()
+    wall_graph = (time.perf_counter() - t0) * 1e3 / frames
+    sc.sync()
+    frame_ms = e0.elapsed_time(e1) / frames
+    skin_ms = e1.elapsed_time(e2) / frames
+    eager_ms = e2.elapsed_time(e3) / frames
+    V = int(mesh.rest_v.shape[0])
+    skin_bytes = 56 * V + 48 * sc.capsules     # rest vertex 12 + 4 ids 16 + 4 weights 16 + out 12; transforms
+    return {"workload": "muscle64_%dpills" % desc.num_pills, "pills": desc.num_pills, "capsules": sc.capsules,
+            "contact_pairs_last_substep": int(len(sc.contacts())), "frame_ms": frame_ms,
+            "frame_ms_eager_launches": eager_ms, "frame_ms_wall_graph": wall_graph,
+            "pill_substeps_per_s": desc.num_pills * sub / (frame_ms * 1e-3),
+            "launches_per_frame": sub * (2 + 20 + 3 * iters),
+            "skin_vertices": V, "skin_ms": skin_ms,
+            "skin_algorithmic_GB_per_s": skin_bytes / (skin_ms * 1e-3) / 1e9}
+
+
 def serving_run(torch, scenes, serve, seconds):
     """Poisson arrivals (200/s) of helix and muscle scenes of 1k-200k pills (log-uniform),
     60 frames each; continuous batching vs the plain per-scene path on the same requests."""
@@ -141,6 +187,10 @@ def serving_run(torch, scenes, serve, seconds):
             "contact_requests": int(sum(r.kind == "muscle" for r in reqs)),
             "batched": {k: b[k] for k in keep + ("steps", "peak_resident_bytes")},
             "plain": {k: p[k] for k in keep}}
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
 def main():
@@ -157,6 +207,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-contacts", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=0.5,
                     help="arrival window of the serving workload (Poisson, 200 requests/s)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -241,11 +292,17 @@ def main():
                    "pill_substeps_per_s": P * sub * K / elapsed},
         "roofline": roof,
     }
+    log("headline: %.3f ms/frame, rod kernel %.3f ms" % (elapsed * 1e3 / K, kern_ms))
+    if not args.no_contacts:
+        out["contacts_skinning"] = contact_skin_timing(torch, viper, scenes, dev)
+        log("contacts and skinning done")
     if not args.no_adjoint:
         out["adjoint"] = adjoint_timing(torch, viper, scenes, dev)
+        log("adjoint done")
     if not args.no_serve:
         from paper_1906_05260_amd import serve
         out["serving"] = serving_run(torch, scenes, serve, args.serve_seconds)
+        log("serving done")
         out["latency_ms_p50"] = out["serving"]["batched"]["latency_ms_p50"]
         out["latency_ms_p99"] = out["serving"]["batched"]["latency_ms_p99"]
     if not args.no_cpu:

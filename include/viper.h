@@ -85,10 +85,13 @@ viper_status viper_create_scene(const viper_scene_desc* desc, void* workspace, s
 
 /* Execution strategy for viper_step_ex. */
 typedef enum {
-  VIPER_MODE_AUTO = 0,     /* FRAME without collisions, ITERATION with */
-  VIPER_MODE_FRAME = 1,    /* one launch per call: all substeps with the rod state in registers */
-  VIPER_MODE_SUBSTEP = 2,  /* one launch per substep: state streamed through HBM every substep */
-  VIPER_MODE_ITERATION = 3 /* separate launches per stage and iteration (the contact path) */
+  VIPER_MODE_AUTO = 0,      /* FRAME without collisions, GRAPH with */
+  VIPER_MODE_FRAME = 1,     /* one launch per call: all substeps with the rod state in registers */
+  VIPER_MODE_SUBSTEP = 2,   /* one launch per substep: state streamed through HBM every substep */
+  VIPER_MODE_ITERATION = 3, /* separate launches per stage and iteration (the contact path) */
+  VIPER_MODE_GRAPH = 4      /* the ITERATION launches of one frame captured once into a HIP graph
+                               (per scene and dt, substeps, iterations) and replayed: same kernels,
+                               same results, one submission per frame */
 } viper_mode;
 
 /* Advance one frame of length dt (s) in `substeps` substeps of h = dt/substeps, each with

@@ -369,6 +369,15 @@ struct viper_scene_s {
   std::vector<Skin> skins;
   std::vector<int32_t> off;  // rod offsets (host copy)
   double density = 1000.0;
+  // GRAPH mode: one captured frame, valid for (h, substeps, iterations) of its capture
+  hipStream_t capture = nullptr;
+  hipGraphExec_t graph = nullptr;
+  double graph_h = 0.0;
+  int graph_sub = 0, graph_iters = 0;
+  ~viper_scene_s() {
+    if (graph) (void)hipGraphExecDestroy(graph);
+    if (capture) (void)hipStreamDestroy(capture);
+  }
 };
 
 namespace {
@@ -467,9 +476,46 @@ viper_status batch_step(const BatchDev& b, bool collisions, double dt, int sub, 
   return VIPER_OK;
 }
 
+// Capture one ITERATION-mode frame of the scene into a graph (on a private stream, so
+// that any caller stream, the legacy default stream included, can replay it).
+template <class T>
+viper_status capture_frame(viper_scene_s* S, double dt, int sub, int iters) {
+  if (S->graph) {
+    HIP_TRY(hipGraphExecDestroy(S->graph));
+    S->graph = nullptr;
+  }
+  if (!S->capture) HIP_TRY(hipStreamCreateWithFlags(&S->capture, hipStreamNonBlocking));
+  HIP_TRY(hipStreamBeginCapture(S->capture, hipStreamCaptureModeThreadLocal));
+  viper_status r = batch_step<T>(S->batch, S->collisions != 0, dt, sub, iters, VIPER_MODE_ITERATION, S->capture);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(S->capture, &g);
+  if (r != VIPER_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return r;
+  }
+  if (e != hipSuccess) return fail(VIPER_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(&S->graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    S->graph = nullptr;
+    return fail(VIPER_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+  }
+  S->graph_h = dt / sub;
+  S->graph_sub = sub;
+  S->graph_iters = iters;
+  return VIPER_OK;
+}
+
 template <class T>
 viper_status step_t(viper_scene_s* S, double dt, int sub, int iters, int mode, hipStream_t st) {
-  return batch_step<T>(S->batch, S->collisions != 0, dt, sub, iters, mode, st);
+  if (mode == VIPER_MODE_AUTO && S->collisions) mode = VIPER_MODE_GRAPH;
+  if (mode != VIPER_MODE_GRAPH) return batch_step<T>(S->batch, S->collisions != 0, dt, sub, iters, mode, st);
+  if (!S->graph || S->graph_h != dt / sub || S->graph_sub != sub || S->graph_iters != iters) {
+    viper_status r = capture_frame<T>(S, dt, sub, iters);
+    if (r != VIPER_OK) return r;
+  }
+  HIP_TRY(hipGraphLaunch(S->graph, st));
+  return VIPER_OK;
 }
 
 Counts scene_counts(const viper_scene_s* S) {

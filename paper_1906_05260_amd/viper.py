@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libviper.so")
 
 OK, ERR_INVALID, ERR_NO_CAPACITY, ERR_CAPACITY, ERR_NAN, ERR_DEVICE = range(6)
 F32, F64 = 0, 1
-MODE_AUTO, MODE_FRAME, MODE_SUBSTEP, MODE_ITERATION = range(4)
+MODE_AUTO, MODE_FRAME, MODE_SUBSTEP, MODE_ITERATION, MODE_GRAPH = range(5)
 X, V, S, SDOT, Q, OMEGA, RADIUS, XDET, SDET, XLOCAL = range(10)
 FIELD_WIDTH = {X: 3, V: 3, S: 1, SDOT: 1, Q: 4, OMEGA: 3, RADIUS: 1, XDET: 3, SDET: 1, XLOCAL: 3}
 FIELD_NAMES = {"x": X, "v": V, "s": S, "sd": SDOT, "q": Q, "om": OMEGA, "radius": RADIUS, "xdet": XDET,

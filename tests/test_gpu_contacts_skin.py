@@ -136,3 +136,23 @@ def test_skin_rejects_bad_capsule():
     caps[3, 2] = int(desc.rod_offsets[1]) - 1     # last pill of rod 0 has no capsule
     with pytest.raises(viper.ViperError):
         sc.create_skin(mesh.rest_v, caps, mesh.w)
+
+
+def test_graph_replay_equals_eager_launches():
+    """GRAPH mode (one captured frame replayed) gives bit-for-bit the eager ITERATION
+    launches' results on every replay, with eager work and synchronisations between the
+    replays; a change of substeps or iterations re-captures."""
+    desc, _ = small_muscles(seed=8)
+    say("case: graph vs eager", desc.num_pills)
+    for prec in ("f32", "f64"):
+        a = viper.Scene(desc, prec)
+        b = viper.Scene(desc, prec)
+        for frame, (sub, it) in enumerate([(8, 4)] * 4 + [(6, 3)] * 2 + [(8, 4)]):
+            a.step(1 / 60, sub, it, mode=viper.MODE_ITERATION)
+            b.step(1 / 60, sub, it, mode=viper.MODE_GRAPH)
+            sa, sb = a.state(local=True), b.state(local=True)
+            for k in ("x", "v", "s", "sd", "q", "om"):
+                assert np.array_equal(sa[k], sb[k]), (prec, frame, k)
+            assert np.array_equal(a.contacts(), b.contacts())
+        a.sync()
+        b.sync()
