@@ -56,16 +56,30 @@ def measured_traffic(kernel, workload):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(desc, dt, sub, iters, rods):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(desc, dt, sub, iters, rods, threads):
+    """The oracle (FP64, rods split across threads; rods are independent without
+    contacts, so the result equals the serial run) on a bounded sample of the workload."""
     import oracle
     sample = desc.subset(range(rods))
     o = oracle.OracleScene(sample, "f64")
     t0 = time.perf_counter()
-    n = o.step(dt, sub, iters, threads=1)
+    n = o.step(dt, sub, iters, threads=threads)
     el = time.perf_counter() - t0
-    return {"value": n / el, "unit": "projections/s", "cores": 1, "kind": "oracle",
-            "sample": "%d of %d rods, 1 frame (%d substeps x %d iterations), serial FP64" %
-                      (rods, desc.num_rods, sub, iters)}
+    return {"value": n / el, "unit": "projections/s", "cores": threads, "kind": "oracle",
+            "sample": "%d of %d rods, 1 frame (%d substeps x %d iterations), FP64, %d threads on %s" %
+                      (rods, desc.num_rods, sub, iters, threads, cpu_model()),
+            "seconds": el, "pill_substeps_per_s": sample.num_pills * sub / el}
 
 
 def copy_reference(torch, dev, mib, steps):
@@ -203,7 +217,8 @@ def main():
     ap.add_argument("--substeps", type=int, default=20)
     ap.add_argument("--iters", type=int, default=8)
     ap.add_argument("--mode", default="frame", choices=["frame", "substep"])
-    ap.add_argument("--cpu-rods", type=int, default=1024)
+    ap.add_argument("--cpu-rods", type=int, default=4096)
+    ap.add_argument("--cpu-threads", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
@@ -306,7 +321,10 @@ def main():
         out["latency_ms_p50"] = out["serving"]["batched"]["latency_ms_p50"]
         out["latency_ms_p99"] = out["serving"]["batched"]["latency_ms_p99"]
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(desc, dt, sub, iters, min(args.cpu_rods, desc.num_rods))
+        threads = max(1, min(args.cpu_threads, os.cpu_count() or 1))
+        out["cpu_baseline"] = cpu_baseline(desc, dt, sub, iters, min(args.cpu_rods, desc.num_rods), threads)
+        out["cpu_baseline"]["serial"] = cpu_baseline(desc, dt, sub, iters, min(256, desc.num_rods), 1)
+        log("cpu baseline done")
     print(json.dumps(out), flush=True)
 
 
