@@ -142,6 +142,34 @@ def adjoint_timing(torch, viper, scenes, dev, reps=5):
             "params": desc.num_pills + desc.num_rods}
 
 
+def single_rod_timing(torch, viper, scenes, dev, frames=120):
+    """One 32-pill rod in FP64, 10 substeps x 4 iterations, 120 frames: launch/latency-bound;
+    GPU microseconds per frame (one frame kernel each) next to the oracle's."""
+    import oracle
+    desc = scenes.straight_rod(32)
+    dt, sub, iters = 1.0 / 60.0, 10, 4
+    sc = viper.Scene(desc, "f64", device=dev)
+    sc.step(dt, sub, iters)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(st)
+    for _ in range(frames):
+        sc.step(dt, sub, iters)
+    e1.record(st)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e6 / frames
+    o = oracle.OracleScene(desc, "f64")
+    t1 = time.perf_counter()
+    for _ in range(frames):
+        o.step(dt, sub, iters)
+    cpu = (time.perf_counter() - t1) * 1e6 / frames
+    return {"workload": "single_rod32_f64", "frames": frames, "substeps": sub, "iterations": iters,
+            "gpu_us_per_frame": e0.elapsed_time(e1) * 1e3 / frames, "gpu_wall_us_per_frame": wall,
+            "oracle_us_per_frame_1core": cpu}
+
+
 def contact_skin_timing(torch, viper, scenes, dev, frames=10):
     """The muscle scene (64 muscles, ~45k pills, FP32, uniform-grid pill-pill contacts,
     20 substeps x 8 iterations) and LBS skinning of its 200k-vertex mesh: ms per frame
@@ -308,6 +336,7 @@ def main():
         "roofline": roof,
     }
     log("headline: %.3f ms/frame, rod kernel %.3f ms" % (elapsed * 1e3 / K, kern_ms))
+    out["single_rod"] = single_rod_timing(torch, viper, scenes, dev)
     if not args.no_contacts:
         out["contacts_skinning"] = contact_skin_timing(torch, viper, scenes, dev)
         log("contacts and skinning done")

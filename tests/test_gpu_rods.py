@@ -225,20 +225,23 @@ def test_helix_one_frame_parity_late_in_horizon():
 
 
 def test_modes_agree():
-    """One launch per frame, one per substep, and per-stage launches compute the same
-    substep (results agree to FP32 rounding after one frame)."""
+    """One launch per frame, one per substep, per-stage launches and their captured graph
+    compute the same substep (results agree to FP32 rounding after one frame; the graph
+    bit for bit with the per-stage launches)."""
     desc = scenes.helix_rods(64, 64, seed=5)
     res = []
-    for mode in (viper.MODE_FRAME, viper.MODE_SUBSTEP, viper.MODE_ITERATION):
+    for mode in (viper.MODE_FRAME, viper.MODE_SUBSTEP, viper.MODE_ITERATION, viper.MODE_GRAPH):
         say("case: mode", mode)
         sc = viper.Scene(desc, "f32")
         sc.step(1 / 60, 20, 8, mode=mode)
         sc.sync()
         res.append(sc.state())
-    for mode, r in zip(("substep", "iteration"), res[1:]):
+    for mode, r in zip(("substep", "iteration", "graph"), res[1:]):
         e = errors(desc, r, res[0])
         say(mode, "vs frame", e)
         assert max(e) < TOL
+    for k in res[2]:      # the graph replays exactly the ITERATION launches
+        assert np.array_equal(res[2][k], res[3][k]), k
 
 
 def test_deterministic_and_state_roundtrip():
