@@ -220,14 +220,14 @@ def serving_run(torch, scenes, serve, seconds):
     """Poisson arrivals (200/s) of helix and muscle scenes of 1k-200k pills (log-uniform),
     60 frames each; continuous batching vs the plain per-scene path on the same requests."""
     reqs = scenes.serving_requests(rate=200, duration=seconds, seed=3)
-    b = serve.serve_batched(reqs, pool_bytes=32 << 30)
+    b = serve.serve_batched(reqs, pool_bytes=32 << 30, progress=log)
     torch.cuda.synchronize()
-    p = serve.serve_plain(reqs)
+    p = serve.serve_plain(reqs, progress=log)
     keep = ("frames", "latency_ms_p50", "latency_ms_p99", "ttff_ms_p50", "ttff_ms_p99", "pill_frames_per_s", "wall_s")
     return {"workload": "poisson200x%.2fs_1k-200k_60frames" % seconds, "requests": len(reqs),
             "pills": int(sum(r.desc.num_pills for r in reqs)),
             "contact_requests": int(sum(r.kind == "muscle" for r in reqs)),
-            "batched": {k: b[k] for k in keep + ("steps", "peak_resident_bytes")},
+            "batched": {k: b[k] for k in keep + ("steps", "peak_resident_bytes", "host_s")},
             "plain": {k: p[k] for k in keep}}
 
 
@@ -251,7 +251,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-contacts", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=0.5,
+    ap.add_argument("--serve-seconds", type=float, default=0.25,
                     help="arrival window of the serving workload (Poisson, 200 requests/s)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="instead of the solver, time a plain device copy of this many MiB (the "

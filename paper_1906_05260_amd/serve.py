@@ -42,9 +42,10 @@ def _summary(lat, ttff, pill_frames, t_first, t_last, extra=None):
 
 
 def serve_batched(requests, pool_bytes, dt=1.0 / 60.0, substeps=20, iterations=8, max_scenes=512,
-                  precision="f32", device="cuda:0", on_finish=None):
+                  precision="f32", device="cuda:0", on_finish=None, progress=None):
     """Continuous batching over a device pool.  `on_finish(request, scene)` (optional) is
-    called with each finished scene before it is retired."""
+    called with each finished scene before it is retired; `progress(msg)` (optional)
+    receives a line every 50 steps."""
     import torch
     pool = viper.Pool(pool_bytes, max_scenes=max_scenes, precision=precision, device=device)
     copy_stream = torch.cuda.Stream(device=device)
@@ -56,11 +57,13 @@ def serve_batched(requests, pool_bytes, dt=1.0 / 60.0, substeps=20, iterations=8
     pill_frames = 0
     peak_bytes = 0
     steps = 0
+    host = {"admit_s": 0.0, "step_enqueue_s": 0.0, "gpu_wait_s": 0.0, "retire_s": 0.0}
     t0 = time.perf_counter()
 
     def admit_ready():
         nonlocal peak_bytes
-        now = time.perf_counter() - t0
+        ta = time.perf_counter()
+        now = ta - t0
         while pending and pending[0].arrival <= now:
             waiting.append(pending.popleft())
         while waiting:
@@ -72,6 +75,7 @@ def serve_batched(requests, pool_bytes, dt=1.0 / 60.0, substeps=20, iterations=8
             resident[slot] = [r, 0, r.arrival]
         info = pool.info()
         peak_bytes = max(peak_bytes, pool_bytes - info["free_bytes"])
+        host["admit_s"] += time.perf_counter() - ta
 
     while pending or waiting or resident:
         admit_ready()
@@ -80,16 +84,23 @@ def serve_batched(requests, pool_bytes, dt=1.0 / 60.0, substeps=20, iterations=8
                 time.sleep(max(0.0, pending[0].arrival - (time.perf_counter() - t0)))
             continue
         members = list(resident.keys())
+        ts = time.perf_counter()
         pool.step(dt, substeps, iterations, stream=main)
         done_ev = torch.cuda.Event()
         done_ev.record(main)
+        host["step_enqueue_s"] += time.perf_counter() - ts
         steps += 1
         # overlap: admit arrivals (uploads on the copy stream) while the step runs
         while not done_ev.query():
             admit_ready()
             time.sleep(20e-6)
+        tw = time.perf_counter()
         done_ev.synchronize()
         t_done = time.perf_counter() - t0
+        host["gpu_wait_s"] += time.perf_counter() - tw
+        if progress is not None and steps % 50 == 0:
+            progress("batched: step %d, %d resident, %d waiting, %d pending, t=%.2fs" %
+                     (steps, len(resident), len(waiting), len(pending), t_done))
         for slot in members:
             st = resident[slot]
             r = st[0]
@@ -102,16 +113,19 @@ def serve_batched(requests, pool_bytes, dt=1.0 / 60.0, substeps=20, iterations=8
             if st[1] == r.frames:
                 if on_finish is not None:
                     on_finish(r, pool.scene(slot))
+                tr = time.perf_counter()
                 pool.retire(slot, stream=main)
+                host["retire_s"] += time.perf_counter() - tr
                 del resident[slot]
     t_last = time.perf_counter() - t0
     t_first = min(r.arrival for r in requests) if requests else 0.0
     return _summary(lat, ttff, pill_frames, t_first, t_last,
-                    {"path": "batched", "steps": steps, "peak_resident_bytes": int(peak_bytes)})
+                    {"path": "batched", "steps": steps, "peak_resident_bytes": int(peak_bytes),
+                     "host_s": {k: round(v, 4) for k, v in host.items()}})
 
 
 def serve_plain(requests, dt=1.0 / 60.0, substeps=20, iterations=8, precision="f32", device="cuda:0",
-                on_finish=None):
+                on_finish=None, progress=None):
     """First-come first-served, one scene at a time, one viper_step per frame."""
     import torch
     lat, ttff = [], []
@@ -135,6 +149,8 @@ def serve_plain(requests, dt=1.0 / 60.0, substeps=20, iterations=8, precision="f
         if on_finish is not None:
             on_finish(r, sc)
         del sc
+        if progress is not None:
+            progress("plain: request done (%d pills), t=%.2fs" % (r.desc.num_pills, time.perf_counter() - t0))
     t_last = time.perf_counter() - t0
     t_first = min(r.arrival for r in requests) if requests else 0.0
     return _summary(lat, ttff, pill_frames, t_first, t_last, {"path": "plain"})

@@ -145,8 +145,8 @@ def test_graph_replay_equals_eager_launches():
     desc, _ = small_muscles(seed=8)
     say("case: graph vs eager", desc.num_pills)
     for prec in ("f32", "f64"):
-        a = viper.Scene(desc, prec)
-        b = viper.Scene(desc, prec)
+        a = viper.Scene(desc, prec, capacity=64)
+        b = viper.Scene(desc, prec, capacity=64)
         for frame, (sub, it) in enumerate([(8, 4)] * 4 + [(6, 3)] * 2 + [(8, 4)]):
             a.step(1 / 60, sub, it, mode=viper.MODE_ITERATION)
             b.step(1 / 60, sub, it, mode=viper.MODE_GRAPH)

