@@ -16,8 +16,9 @@
 // with the closed-form projection onto the second capsule; a violated pair gets a
 // hard (zero-compliance) correction of the four end positions and scales.  All
 // pairs read the same state and the corrections are averaged per pill (the Jacobi
-// reduction of Sec. 7), summed in pair order through a per-pill index for a
-// deterministic result.
+// reduction of Sec. 7).  The per-pill sums are accumulated with 64-bit integer atomics
+// in fixed point (2^-44 m resolution): integer addition is associative, so the sum does
+// not depend on the order in which pairs arrive and the result is deterministic.
 
 #include "contact.h"
 
@@ -75,6 +76,13 @@ __device__ bool spheres_overlap(const double* a, const double* b) {
   return d2 < rr * rr;
 }
 
+// Fixed-point accumulation (2^-44 m per unit; a single term is clamped to +-2^12 m so
+// that no sum of a pass can wrap): deterministic whatever the order of the atomics.
+__device__ __forceinline__ void acc_add(unsigned long long* a, double v) {
+  const double s = fmin(fmax(v * 0x1p44, -0x1p56), 0x1p56);
+  atomicAdd(a, (unsigned long long)(long long)rint(s));
+}
+
 // ---- block-table helpers
 
 #define BLOCK_SCENE(tab, D, CD)                 \
@@ -93,8 +101,8 @@ __global__ void __launch_bounds__(256) zero_cells_kernel(const ContactDev* __res
   c.cell_cur[i] = 0;
 }
 
-// Copy the detection state (FP64 world positions, scales), zero the per-pill counters and
-// the largest-radius register.
+// Copy the detection state (FP64 world positions, scales) and zero the largest-radius
+// register.
 template <class T>
 __global__ void __launch_bounds__(256) det_copy_kernel(const Dev<T>* __restrict__ D, const ContactDev* __restrict__ CD,
                                                        const Blk* __restrict__ tab) {
@@ -104,19 +112,17 @@ __global__ void __launch_bounds__(256) det_copy_kernel(const Dev<T>* __restrict_
   if (p >= d.P) return;
   world_pos(d, p, c.xdet + 3 * (size_t)p);
   ((T*)c.sdet)[p] = d.s[p];
-  c.pill_cnt[p] = 0;
-  c.pill_cur[p] = 0;
 }
 
 // ---- exclusive scans (out[n] = total), 1024 items per block, one array per scene:
-// WHICH = 0: hash-cell counts, 1: candidate counts per capsule, 2: CSR counts per pill.
-// The selection is a template parameter: each scan kernel is compiled for one array, so
-// no kernel selects its pointers through a runtime branch.
+// WHICH = 0: hash-cell counts, 1: candidate counts per capsule.  The selection is a
+// template parameter: each scan kernel is compiled for one array, so no kernel selects
+// its pointers through a runtime branch.
 template <int WHICH>
 __device__ __forceinline__ void scan_arrays(const ContactDev& c, const int32_t*& in, int32_t*& out, int& n) {
+  static_assert(WHICH == 0 || WHICH == 1, "scan array");
   if constexpr (WHICH == 0) { in = c.cell_cnt; out = c.cell_start; n = c.T; }
-  else if constexpr (WHICH == 1) { in = c.pcount; out = c.poff; n = c.E; }
-  else { in = c.pill_cnt; out = c.pill_start; n = c.P; }
+  else { in = c.pcount; out = c.poff; n = c.E; }
 }
 
 template <int WHICH>
@@ -255,6 +261,28 @@ __global__ void __launch_bounds__(256) bucket_scatter_kernel(const ContactDev* _
   c.sorted[pos] = i;
 }
 
+// Exact cell of a capsule packed into 63 bits (21 per axis).  Two cells that alias after
+// packing are >= 2^21 cells apart, so no sphere of one overlaps a sphere of the other: the
+// filter below may admit an aliased bucket entry, the exact overlap test then rejects it.
+__device__ __forceinline__ long long pack_cell(int x, int y, int z) {
+  return (long long)(x & 0x1FFFFF) | ((long long)(y & 0x1FFFFF) << 21) | ((long long)(z & 0x1FFFFF) << 42);
+}
+
+// Copy each capsule's sphere, packed cell and rod/group into bucket order, so that the
+// neighbour search below reads every cell's entries contiguously.
+__global__ void __launch_bounds__(256) reorder_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
+  const Blk blk = tab[blockIdx.x];
+  const ContactDev& c = CD[blk.scene];
+  const int j = blk.base + (int)threadIdx.x;
+  if (j >= c.E) return;
+  const int b = c.sorted[j];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) c.ssph[4 * (size_t)j + k] = c.sph[4 * (size_t)b + k];
+  c.skey[j] = pack_cell(c.cell[3 * (size_t)b], c.cell[3 * (size_t)b + 1], c.cell[3 * (size_t)b + 2]);
+  c.srg[2 * (size_t)j] = c.cap_rod[b];
+  c.srg[2 * (size_t)j + 1] = c.cap_grp[b];
+}
+
 // Count (EMIT = false) or emit (EMIT = true) the candidates b > a of capsule a.
 template <bool EMIT>
 __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
@@ -273,15 +301,15 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
       for (int dx = -1; dx <= 1; ++dx) {
         const int nx = cx + dx, ny = cy + dy, nz = cz + dz;
         const uint32_t h = cell_hash(nx, ny, nz, c.T);
+        const long long nk = pack_cell(nx, ny, nz);
         const int j1 = c.cell_start[h + 1];
         for (int j = c.cell_start[h]; j < j1; ++j) {
           const int b = c.sorted[j];
           if (b <= a) continue;
-          // only the bucket entries that really lie in this neighbour cell
-          if (cell[3 * (size_t)b] != nx || cell[3 * (size_t)b + 1] != ny || cell[3 * (size_t)b + 2] != nz) continue;
-          if (c.cap_rod[b] == ra || c.cap_grp[b] == ga) continue;
-          const double sb[4] = {c.sph[4 * (size_t)b], c.sph[4 * (size_t)b + 1], c.sph[4 * (size_t)b + 2],
-                                c.sph[4 * (size_t)b + 3]};
+          if (c.skey[j] != nk) continue;     // a bucket entry of another cell (hash collision)
+          if (c.srg[2 * (size_t)j] == ra || c.srg[2 * (size_t)j + 1] == ga) continue;
+          const double sb[4] = {c.ssph[4 * (size_t)j], c.ssph[4 * (size_t)j + 1], c.ssph[4 * (size_t)j + 2],
+                                c.ssph[4 * (size_t)j + 3]};
           if (!spheres_overlap(sa, sb)) continue;
           if (EMIT) {
             const int idx = base + cnt;
@@ -320,49 +348,6 @@ __global__ void finalize_kernel(const ContactDev* __restrict__ CD) {
   const int total = c.poff[c.E];
   c.npairs[0] = min(total, c.cap);
   if (total > c.cap) c.status[ST_OVERFLOW] = 1;
-}
-
-__global__ void __launch_bounds__(256) csr_count_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
-  const Blk blk = tab[blockIdx.x];
-  const ContactDev& c = CD[blk.scene];
-  const int i = blk.base + (int)threadIdx.x;
-  if (i >= c.npairs[0]) return;
-  const int a = c.pairs[2 * (size_t)i], b = c.pairs[2 * (size_t)i + 1];
-  atomicAdd(&c.pill_cnt[a], 1);
-  atomicAdd(&c.pill_cnt[a + 1], 1);
-  atomicAdd(&c.pill_cnt[b], 1);
-  atomicAdd(&c.pill_cnt[b + 1], 1);
-}
-
-__global__ void __launch_bounds__(256) csr_fill_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
-  const Blk blk = tab[blockIdx.x];
-  const ContactDev& c = CD[blk.scene];
-  const int i = blk.base + (int)threadIdx.x;
-  if (i >= c.npairs[0]) return;
-  const int a = c.pairs[2 * (size_t)i], b = c.pairs[2 * (size_t)i + 1];
-  const int pid[4] = {a, a + 1, b, b + 1};
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int slot = c.pill_start[pid[t]] + atomicAdd(&c.pill_cur[pid[t]], 1);
-    c.entries[slot] = 4 * i + t;
-  }
-}
-
-__global__ void __launch_bounds__(256) csr_sort_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
-  const Blk blk = tab[blockIdx.x];
-  const ContactDev& c = CD[blk.scene];
-  const int p = blk.base + (int)threadIdx.x;
-  if (p >= c.P) return;
-  const int s0 = c.pill_start[p], n = c.pill_start[p + 1] - s0;
-  for (int i = 1; i < n; ++i) {
-    const int v = c.entries[s0 + i];
-    int j = i - 1;
-    while (j >= 0 && c.entries[s0 + j] > v) {
-      c.entries[s0 + j + 1] = c.entries[s0 + j];
-      --j;
-    }
-    c.entries[s0 + j + 1] = v;
-  }
 }
 
 // ---- handling (FP64 arithmetic)
@@ -435,7 +420,6 @@ __global__ void __launch_bounds__(256) contact_pair_kernel(const Dev<T>* __restr
   const D3 dv = sub(ca, cb);
   const double dist = sqrt(dotp(dv, dv));
   const double C = dist - (r[0] + al * (r[1] - r[0])) - (r[2] + be * (r[3] - r[2]));
-  int act = 0;
   if (C < 0.0 && dist > 0.0) {
     const D3 n = d3(dv.x / dist, dv.y / dist, dv.z / dist);
     const double wt[4] = {1.0 - al, al, -(1.0 - be), -be};   // dC/dx_t = wt n, dC/ds_t = -|wt| rbar
@@ -449,46 +433,40 @@ __global__ void __launch_bounds__(256) contact_pair_kernel(const Dev<T>* __restr
       den += w[t] * wt[t] * wt[t] + ws[t] * gs * gs;
     }
     if (den > 0.0) {
-      act = 1;
       const double dl = -C / den;
-      double* o = c.delta_buf + 16 * (size_t)i;
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const double k = w[t] * wt[t] * dl;
-        o[4 * t + 0] = k * n.x;
-        o[4 * t + 1] = k * n.y;
-        o[4 * t + 2] = k * n.z;
-        o[4 * t + 3] = -ws[t] * fabs(wt[t]) * rb[t] * dl;
+        unsigned long long* o = c.acc + 4 * (size_t)pid[t];
+        acc_add(o + 0, k * n.x);
+        acc_add(o + 1, k * n.y);
+        acc_add(o + 2, k * n.z);
+        acc_add(o + 3, -ws[t] * fabs(wt[t]) * rb[t] * dl);
+        atomicAdd(&c.acnt[pid[t]], 1);
       }
     }
   }
-  c.active[i] = act;
 }
 
+// Apply the averaged corrections of the pass and clear the accumulators for the next one.
 template <class T>
 __global__ void __launch_bounds__(256) contact_gather_kernel(const Dev<T>* __restrict__ D, const ContactDev* __restrict__ CD,
                                                              const Blk* __restrict__ tab) {
   BLOCK_SCENE(tab, D, CD)
   const int p = blk_.base + (int)threadIdx.x;
   if (p >= c.P) return;
-  const int s0 = c.pill_start[p], s1 = c.pill_start[p + 1];
-  if (s0 == s1) return;
-  double ax = 0, ay = 0, az = 0, as = 0;
-  int n = 0;
-  for (int k = s0; k < s1; ++k) {
-    const int e = c.entries[k];
-    const int pr = e >> 2;
-    if (!c.active[pr]) continue;
-    const double* o = c.delta_buf + 16 * (size_t)pr + 4 * (e & 3);
-    ax += o[0]; ay += o[1]; az += o[2]; as += o[3];
-    ++n;
-  }
+  const int n = c.acnt[p];
   if (n == 0) return;
+  unsigned long long* a = c.acc + 4 * (size_t)p;
   const double inv = 1.0 / (double)n;
+  const double ax = (double)(long long)a[0] * 0x1p-44, ay = (double)(long long)a[1] * 0x1p-44;
+  const double az = (double)(long long)a[2] * 0x1p-44, as = (double)(long long)a[3] * 0x1p-44;
   d.px[p] = (T)((double)d.px[p] + inv * ax);
   d.py[p] = (T)((double)d.py[p] + inv * ay);
   d.pz[p] = (T)((double)d.pz[p] + inv * az);
   d.s[p] = (T)((double)d.s[p] + inv * as);
+  a[0] = 0ull; a[1] = 0ull; a[2] = 0ull; a[3] = 0ull;
+  c.acnt[p] = 0;
 }
 
 }  // namespace
@@ -527,12 +505,11 @@ ContactOffsets contact_layout(size_t start, bool on, int P, int E, int cpc, bool
   o.poff = take(4 * (size_t)(E + 1));
   o.pairs = take(8 * cap);
   o.npairs = take(4);
-  o.pill_cnt = take(4 * (size_t)P);
-  o.pill_start = take(4 * (size_t)(P + 1));
-  o.pill_cur = take(4 * (size_t)P);
-  o.entries = take(16 * cap);
-  o.delta = take(8 * 16 * cap);
-  o.active = take(4 * cap);
+  o.ssph = take(8 * 4 * (size_t)E);
+  o.skey = take(8 * (size_t)E);
+  o.srg = take(8 * (size_t)E);
+  o.acc = take(8 * 4 * (size_t)P);
+  o.acnt = take(4 * (size_t)P);
   o.xdet = take(8 * 3 * (size_t)P);   // FP64 world positions
   o.sdet = take(ts * (size_t)P);
   o.bsum = take(4 * (size_t)nb);
@@ -575,12 +552,11 @@ viper_status contact_init(ContactDev& c, char* ws, const ContactOffsets& o, cons
   c.poff = (int32_t*)(ws + o.poff);
   c.pairs = (int32_t*)(ws + o.pairs);
   c.npairs = (int32_t*)(ws + o.npairs);
-  c.pill_cnt = (int32_t*)(ws + o.pill_cnt);
-  c.pill_start = (int32_t*)(ws + o.pill_start);
-  c.pill_cur = (int32_t*)(ws + o.pill_cur);
-  c.entries = (int32_t*)(ws + o.entries);
-  c.delta_buf = (double*)(ws + o.delta);
-  c.active = (int32_t*)(ws + o.active);
+  c.ssph = (double*)(ws + o.ssph);
+  c.skey = (long long*)(ws + o.skey);
+  c.srg = (int32_t*)(ws + o.srg);
+  c.acc = (unsigned long long*)(ws + o.acc);
+  c.acnt = (int32_t*)(ws + o.acnt);
   c.xdet = (double*)(ws + o.xdet);
   c.sdet = ws + o.sdet;
   c.bsum = (int32_t*)(ws + o.bsum);
@@ -588,7 +564,9 @@ viper_status contact_init(ContactDev& c, char* ws, const ContactOffsets& o, cons
   if (hipMemcpyAsync(c.cap_ids, ids.data(), 4 * ids.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(c.cap_rod, rod.data(), 4 * rod.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(c.cap_grp, grp.data(), 4 * grp.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
-      hipMemsetAsync(c.npairs, 0, 4, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
+      hipMemsetAsync(c.npairs, 0, 4, st) != hipSuccess ||
+      hipMemsetAsync(c.acc, 0, 8 * 4 * (size_t)c.P, st) != hipSuccess ||
+      hipMemsetAsync(c.acnt, 0, 4 * (size_t)c.P, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
     return VIPER_ERR_DEVICE;
   return VIPER_OK;
 }
@@ -619,16 +597,12 @@ hipError_t launch_contact_detect(const BatchDev& b, hipStream_t st) {
   hipError_t e = scan<0>(b, TB_SCAN_T, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(bucket_scatter_kernel, dim3(b.nblk[TB_CAPS]), blk, 0, st, CD, b.tab[TB_CAPS]);
+  hipLaunchKernelGGL(reorder_kernel, dim3(b.nblk[TB_CAPS]), blk, 0, st, CD, b.tab[TB_CAPS]);
   hipLaunchKernelGGL(pair_kernel<false>, dim3(b.nblk[TB_CAPS]), blk, 0, st, CD, b.tab[TB_CAPS]);
   e = scan<1>(b, TB_SCAN_E, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(pair_kernel<true>, dim3(b.nblk[TB_CAPS]), blk, 0, st, CD, b.tab[TB_CAPS]);
   hipLaunchKernelGGL(finalize_kernel, dim3(b.nscenes), dim3(64), 0, st, CD);
-  hipLaunchKernelGGL(csr_count_kernel, dim3(b.nblk[TB_PAIRS]), blk, 0, st, CD, b.tab[TB_PAIRS]);
-  e = scan<2>(b, TB_SCAN_P, st);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(csr_fill_kernel, dim3(b.nblk[TB_PAIRS]), blk, 0, st, CD, b.tab[TB_PAIRS]);
-  hipLaunchKernelGGL(csr_sort_kernel, dim3(b.nblk[TB_PILLS]), blk, 0, st, CD, b.tab[TB_PILLS]);
   return hipGetLastError();
 }
 

@@ -139,7 +139,7 @@ struct Counts {
   bool contacts = false;
 };
 
-const int kStageItems[TB_COUNT] = {4, 256, 256, 256, 256, 1024, 1024, 1024};
+const int kStageItems[TB_COUNT] = {4, 256, 256, 256, 256, 1024, 1024};
 
 int stage_items(const Counts& c, int stage) {
   switch (stage) {
@@ -148,7 +148,6 @@ int stage_items(const Counts& c, int stage) {
     case TB_CAPS: return c.contacts ? c.E : 0;
     case TB_CELLS: return c.contacts ? c.T : 0;
     case TB_PAIRS: return c.contacts ? c.cap : 0;
-    case TB_SCAN_P: return c.contacts ? c.P : 0;
     case TB_SCAN_E: return c.contacts ? c.E : 0;
     case TB_SCAN_T: return c.contacts ? c.T : 0;
     default: return 0;

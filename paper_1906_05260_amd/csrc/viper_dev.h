@@ -64,9 +64,11 @@ struct ContactDev {
   int32_t *key = nullptr, *cell = nullptr;  // [E] hash keys, [3E] integer cell coordinates
   int32_t *cell_cnt = nullptr, *cell_start = nullptr, *cell_cur = nullptr, *sorted = nullptr;
   int32_t *pcount = nullptr, *poff = nullptr, *pairs = nullptr, *npairs = nullptr;
-  int32_t *pill_cnt = nullptr, *pill_start = nullptr, *pill_cur = nullptr, *entries = nullptr;
-  double* delta_buf = nullptr;        // [cap*16] per-pair corrections of the 4 end pills (dx dy dz ds)
-  int32_t* active = nullptr;          // [cap]
+  double* ssph = nullptr;             // [E*4] spheres in bucket (cell) order
+  long long* skey = nullptr;          // [E] packed exact cell coordinates in bucket order
+  int32_t* srg = nullptr;             // [E*2] rod, group in bucket order
+  unsigned long long* acc = nullptr;  // [P*4] fixed-point sums of contact corrections (dx dy dz ds)
+  int32_t* acnt = nullptr;            // [P] active contacts per pill this pass
   double* xdet = nullptr;             // [3P] FP64 world positions at detection
   void* sdet = nullptr;               // [P] scales at detection (scene precision)
   int32_t* bsum = nullptr;            // scan block sums
@@ -86,8 +88,7 @@ enum Stage {
   TB_CAPS,        // 256 capsules per block
   TB_CELLS,       // 256 hash cells per block
   TB_PAIRS,       // 256 candidate-pair slots per block
-  TB_SCAN_P,      // 1024 pills per block (scans)
-  TB_SCAN_E,      // 1024 capsules per block
+  TB_SCAN_E,      // 1024 capsules per block (scans)
   TB_SCAN_T,      // 1024 cells per block
   TB_COUNT
 };

@@ -142,7 +142,7 @@ def test_graph_replay_equals_eager_launches():
     """GRAPH mode (one captured frame replayed) gives bit-for-bit the eager ITERATION
     launches' results on every replay, with eager work and synchronisations between the
     replays; a change of substeps or iterations re-captures."""
-    desc, _ = small_muscles(seed=8)
+    desc, _ = small_muscles(seed=3)      # stays bounded over this sequence (oracle: <= ~800 pairs)
     say("case: graph vs eager", desc.num_pills)
     for prec in ("f32", "f64"):
         a = viper.Scene(desc, prec, capacity=64)
@@ -150,9 +150,9 @@ def test_graph_replay_equals_eager_launches():
         for frame, (sub, it) in enumerate([(8, 4)] * 4 + [(6, 3)] * 2 + [(8, 4)]):
             a.step(1 / 60, sub, it, mode=viper.MODE_ITERATION)
             b.step(1 / 60, sub, it, mode=viper.MODE_GRAPH)
+            a.sync()                    # raises on contact-buffer overflow
+            b.sync()
             sa, sb = a.state(local=True), b.state(local=True)
             for k in ("x", "v", "s", "sd", "q", "om"):
                 assert np.array_equal(sa[k], sb[k]), (prec, frame, k)
             assert np.array_equal(a.contacts(), b.contacts())
-        a.sync()
-        b.sync()
