@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 # FLOPs per projection / per pill-substep, counted from the closed-form updates in
 # csrc/rod_kernels.hip (add, sub, mul, div, sqrt, rsqrt = 1 each; a fused
 # multiply-add counts as its multiply and its add).
-FLOP = {"ss": 116, "vol": 53, "sg": 16, "bt": 337, "predict": 59, "velocity": 42}
+FLOP = {"ss": 122, "vol": 53, "sg": 16, "bt": 337, "predict": 59, "velocity": 42}
 # Bytes one frame launch moves per pill (FP32): state 15 words read + written,
 # 13 rest words and one flag word read.
 BYTES_PER_PILL_LAUNCH = 4 * (15 + 15 + 13 + 1)

@@ -134,9 +134,15 @@ __device__ __forceinline__ void edge_update(Slot<T>& L, T& b0, T& b1, T& b2, T& 
   const T wa = L.w;
   if (L.f & F_SS) {
     const T q0 = L.q0, q1 = L.q1, q2 = L.q2, q3 = L.q3;
-    const T d0 = T(2) * (q0 * q2 + q3 * q1);
-    const T d1 = T(2) * (q1 * q2 - q3 * q0);
-    const T d2 = T(1) - T(2) * (q0 * q0 + q1 * q1);
+    // director d3 = q e_z conj(q) / |q|^2: exactly unit whatever rounding left in |q|.  The
+    // unit-quaternion form 1 - 2(q0^2 + q1^2) turns a 1e-7 norm error into an edge-length
+    // bias that a stiff stretch-shear constraint enforces, and gradients of stiff FP32 rods
+    // amplify it by orders of magnitude.
+    const T na = q0 * q0 + q1 * q1, nb = q2 * q2 + q3 * q3;
+    const T tw = T(2) * rcp(na + nb);
+    const T d0 = (q0 * q2 + q3 * q1) * tw;
+    const T d1 = (q1 * q2 - q3 * q0) * tw;
+    const T d2 = (nb - na) * (T(0.5) * tw);
     const T ilb = L.ilb, at = L.ass;
     const T c0 = (b0 - a0) * ilb - d0, c1 = (b1 - a1) * ilb - d1, c2 = (b2 - a2) * ilb - d2;
     const T k1 = (wa + wb) * ilb * ilb + at;
