@@ -251,7 +251,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-contacts", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=0.25,
+    ap.add_argument("--serve-seconds", type=float, default=0.15,
                     help="arrival window of the serving workload (Poisson, 200 requests/s)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="instead of the solver, time a plain device copy of this many MiB (the "
