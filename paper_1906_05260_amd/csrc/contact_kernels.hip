@@ -29,6 +29,11 @@ namespace viper {
 
 namespace {
 
+// Neighbour search: 9 threads per capsule, one per (dz, dy) column of its 27 neighbour
+// cells; 28 capsules (252 threads) per block.
+constexpr int kSearchSub = 9;
+constexpr int kSearchCaps = 28;
+
 __device__ __forceinline__ uint32_t cell_hash(int x, int y, int z, int T) {
   return ((uint32_t)x * 73856093u ^ (uint32_t)y * 19349663u ^ (uint32_t)z * 83492791u) & (uint32_t)(T - 1);
 }
@@ -122,7 +127,7 @@ template <int WHICH>
 __device__ __forceinline__ void scan_arrays(const ContactDev& c, const int32_t*& in, int32_t*& out, int& n) {
   static_assert(WHICH == 0 || WHICH == 1, "scan array");
   if constexpr (WHICH == 0) { in = c.cell_cnt; out = c.cell_start; n = c.T; }
-  else { in = c.pcount; out = c.poff; n = c.E; }
+  else { in = c.pcount; out = c.poff; n = kSearchSub * c.E; }
 }
 
 template <int WHICH>
@@ -283,61 +288,70 @@ __global__ void __launch_bounds__(256) reorder_kernel(const ContactDev* __restri
   c.srg[2 * (size_t)j + 1] = c.cap_grp[b];
 }
 
-// Count (EMIT = false) or emit (EMIT = true) the candidates b > a of capsule a.
+// Count (EMIT = false) or emit (EMIT = true) the candidates b > a of capsule a.  Threads
+// follow bucket order, so the lanes of a wave mostly share a home cell and walk the same
+// neighbour entries (their loads coalesce); each of a capsule's 9 threads covers one
+// (dz, dy) column of 3 cells.  Counts are per (capsule, column) so that an exclusive scan
+// gives every thread its output offset; after the emit pass the capsule's first thread
+// sorts the capsule's segment by b and stores capsule ids.
 template <bool EMIT>
 __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
   const Blk blk = tab[blockIdx.x];
   const ContactDev& c = CD[blk.scene];
-  const int a = blk.base + (int)threadIdx.x;
-  if (a >= c.E) return;
-  const int32_t* cell = c.cell;
-  const double sa[4] = {c.sph[4 * (size_t)a], c.sph[4 * (size_t)a + 1], c.sph[4 * (size_t)a + 2], c.sph[4 * (size_t)a + 3]};
-  const int ra = c.cap_rod[a], ga = c.cap_grp[a];
-  const int cx = cell[3 * (size_t)a], cy = cell[3 * (size_t)a + 1], cz = cell[3 * (size_t)a + 2];
-  const int base = EMIT ? c.poff[a] : 0;
-  int cnt = 0;
-  for (int dz = -1; dz <= 1; ++dz)
-    for (int dy = -1; dy <= 1; ++dy)
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int nx = cx + dx, ny = cy + dy, nz = cz + dz;
-        const uint32_t h = cell_hash(nx, ny, nz, c.T);
-        const long long nk = pack_cell(nx, ny, nz);
-        const int j1 = c.cell_start[h + 1];
-        for (int j = c.cell_start[h]; j < j1; ++j) {
-          const int b = c.sorted[j];
-          if (b <= a) continue;
-          if (c.skey[j] != nk) continue;     // a bucket entry of another cell (hash collision)
-          if (c.srg[2 * (size_t)j] == ra || c.srg[2 * (size_t)j + 1] == ga) continue;
-          const double sb[4] = {c.ssph[4 * (size_t)j], c.ssph[4 * (size_t)j + 1], c.ssph[4 * (size_t)j + 2],
-                                c.ssph[4 * (size_t)j + 3]};
-          if (!spheres_overlap(sa, sb)) continue;
-          if (EMIT) {
-            const int idx = base + cnt;
-            if (idx < c.cap) c.pairs[2 * (size_t)idx + 1] = b;   // capsule index for now
-          }
-          ++cnt;
+  const int q = (int)threadIdx.x / kSearchSub, sub = (int)threadIdx.x % kSearchSub;
+  const int jh = blk.base + q;                      // bucket position of the home capsule
+  const bool live = q < kSearchCaps && jh < c.E;
+  int a = 0;
+  if (live) {
+    a = c.sorted[jh];
+    const double sa[4] = {c.ssph[4 * (size_t)jh], c.ssph[4 * (size_t)jh + 1], c.ssph[4 * (size_t)jh + 2],
+                          c.ssph[4 * (size_t)jh + 3]};
+    const int ra = c.srg[2 * (size_t)jh], ga = c.srg[2 * (size_t)jh + 1];
+    const int cx = c.cell[3 * (size_t)a], cy = c.cell[3 * (size_t)a + 1], cz = c.cell[3 * (size_t)a + 2];
+    const int ny = cy + sub % 3 - 1, nz = cz + sub / 3 - 1;
+    const int base = EMIT ? c.poff[kSearchSub * (size_t)a + sub] : 0;
+    int cnt = 0;
+    for (int dx = -1; dx <= 1; ++dx) {
+      const int nx = cx + dx;
+      const uint32_t h = cell_hash(nx, ny, nz, c.T);
+      const long long nk = pack_cell(nx, ny, nz);
+      const int j1 = c.cell_start[h + 1];
+      for (int j = c.cell_start[h]; j < j1; ++j) {
+        const int b = c.sorted[j];
+        if (b <= a) continue;
+        if (c.skey[j] != nk) continue;     // a bucket entry of another cell (hash collision)
+        if (c.srg[2 * (size_t)j] == ra || c.srg[2 * (size_t)j + 1] == ga) continue;
+        const double sb[4] = {c.ssph[4 * (size_t)j], c.ssph[4 * (size_t)j + 1], c.ssph[4 * (size_t)j + 2],
+                              c.ssph[4 * (size_t)j + 3]};
+        if (!spheres_overlap(sa, sb)) continue;
+        if (EMIT) {
+          const int idx = base + cnt;
+          if (idx < c.cap) c.pairs[2 * (size_t)idx + 1] = b;   // capsule index for now
         }
+        ++cnt;
       }
-  if (!EMIT) {
-    c.pcount[a] = cnt;
-    return;
+    }
+    if (!EMIT) c.pcount[kSearchSub * (size_t)a + sub] = cnt;
   }
+  if (!EMIT) return;
+  __syncthreads();
+  if (!live || sub != 0) return;
   // sort this capsule's segment by b, then store capsule ids (first pill of each capsule)
-  const int n = min(cnt, c.cap - base);
-  for (int i = 1; i < n; ++i) {
-    const int v = c.pairs[2 * (size_t)(base + i) + 1];
+  const int s0 = min(c.poff[kSearchSub * (size_t)a], c.cap);
+  const int s1 = min(c.poff[kSearchSub * (size_t)a + kSearchSub], c.cap);
+  for (int i = s0 + 1; i < s1; ++i) {
+    const int v = c.pairs[2 * (size_t)i + 1];
     int j = i - 1;
-    while (j >= 0 && c.pairs[2 * (size_t)(base + j) + 1] > v) {
-      c.pairs[2 * (size_t)(base + j + 1) + 1] = c.pairs[2 * (size_t)(base + j) + 1];
+    while (j >= s0 && c.pairs[2 * (size_t)j + 1] > v) {
+      c.pairs[2 * (size_t)(j + 1) + 1] = c.pairs[2 * (size_t)j + 1];
       --j;
     }
-    c.pairs[2 * (size_t)(base + j + 1) + 1] = v;
+    c.pairs[2 * (size_t)(j + 1) + 1] = v;
   }
   const int ida = c.cap_ids[a];
-  for (int i = 0; i < n; ++i) {
-    const size_t k = 2 * (size_t)(base + i);
-    c.pairs[k] = ida;
-    c.pairs[k + 1] = c.cap_ids[c.pairs[k + 1]];
+  for (int i = s0; i < s1; ++i) {
+    c.pairs[2 * (size_t)i] = ida;
+    c.pairs[2 * (size_t)i + 1] = c.cap_ids[c.pairs[2 * (size_t)i + 1]];
   }
 }
 
@@ -345,7 +359,7 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
 __global__ void finalize_kernel(const ContactDev* __restrict__ CD) {
   if (threadIdx.x != 0) return;
   const ContactDev& c = CD[blockIdx.x];
-  const int total = c.poff[c.E];
+  const int total = c.poff[kSearchSub * (size_t)c.E];
   c.npairs[0] = min(total, c.cap);
   if (total > c.cap) c.status[ST_OVERFLOW] = 1;
 }
@@ -489,7 +503,7 @@ ContactOffsets contact_layout(size_t start, bool on, int P, int E, int cpc, bool
   const int T = contact_table_size(E);
   const size_t cap = (size_t)cpc * (size_t)E;
   const size_t ts = f64 ? 8 : 4;
-  const int nb = (std::max(std::max(T, E), P) + 1023) / 1024 + 1;
+  const int nb = (std::max(std::max(T, kSearchSub * E), P) + 1023) / 1024 + 1;
   o.cap_ids = take(4 * (size_t)E);
   o.cap_rod = take(4 * (size_t)E);
   o.cap_grp = take(4 * (size_t)E);
@@ -501,8 +515,8 @@ ContactOffsets contact_layout(size_t start, bool on, int P, int E, int cpc, bool
   o.cell_start = take(4 * (size_t)(T + 1));
   o.cell_cur = take(4 * (size_t)T);
   o.sorted = take(4 * (size_t)E);
-  o.pcount = take(4 * (size_t)E);
-  o.poff = take(4 * (size_t)(E + 1));
+  o.pcount = take(4 * (size_t)kSearchSub * E);
+  o.poff = take(4 * ((size_t)kSearchSub * E + 1));
   o.pairs = take(8 * cap);
   o.npairs = take(4);
   o.ssph = take(8 * 4 * (size_t)E);
@@ -598,10 +612,10 @@ hipError_t launch_contact_detect(const BatchDev& b, hipStream_t st) {
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(bucket_scatter_kernel, dim3(b.nblk[TB_CAPS]), blk, 0, st, CD, b.tab[TB_CAPS]);
   hipLaunchKernelGGL(reorder_kernel, dim3(b.nblk[TB_CAPS]), blk, 0, st, CD, b.tab[TB_CAPS]);
-  hipLaunchKernelGGL(pair_kernel<false>, dim3(b.nblk[TB_CAPS]), blk, 0, st, CD, b.tab[TB_CAPS]);
+  hipLaunchKernelGGL(pair_kernel<false>, dim3(b.nblk[TB_SEARCH]), blk, 0, st, CD, b.tab[TB_SEARCH]);
   e = scan<1>(b, TB_SCAN_E, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(pair_kernel<true>, dim3(b.nblk[TB_CAPS]), blk, 0, st, CD, b.tab[TB_CAPS]);
+  hipLaunchKernelGGL(pair_kernel<true>, dim3(b.nblk[TB_SEARCH]), blk, 0, st, CD, b.tab[TB_SEARCH]);
   hipLaunchKernelGGL(finalize_kernel, dim3(b.nscenes), dim3(64), 0, st, CD);
   return hipGetLastError();
 }

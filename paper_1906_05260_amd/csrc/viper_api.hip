@@ -139,16 +139,17 @@ struct Counts {
   bool contacts = false;
 };
 
-const int kStageItems[TB_COUNT] = {4, 256, 256, 256, 256, 1024, 1024};
+const int kStageItems[TB_COUNT] = {4, 256, 256, 28, 256, 256, 1024, 1024};
 
 int stage_items(const Counts& c, int stage) {
   switch (stage) {
     case TB_WAVES: return c.W;
     case TB_PILLS: return c.P;
     case TB_CAPS: return c.contacts ? c.E : 0;
+    case TB_SEARCH: return c.contacts ? c.E : 0;
     case TB_CELLS: return c.contacts ? c.T : 0;
     case TB_PAIRS: return c.contacts ? c.cap : 0;
-    case TB_SCAN_E: return c.contacts ? c.E : 0;
+    case TB_SCAN_E: return c.contacts ? 9 * c.E : 0;
     case TB_SCAN_T: return c.contacts ? c.T : 0;
     default: return 0;
   }

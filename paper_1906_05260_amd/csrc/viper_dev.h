@@ -63,7 +63,8 @@ struct ContactDev {
   unsigned long long* maxr = nullptr; // bits of the largest sphere radius
   int32_t *key = nullptr, *cell = nullptr;  // [E] hash keys, [3E] integer cell coordinates
   int32_t *cell_cnt = nullptr, *cell_start = nullptr, *cell_cur = nullptr, *sorted = nullptr;
-  int32_t *pcount = nullptr, *poff = nullptr, *pairs = nullptr, *npairs = nullptr;
+  int32_t *pcount = nullptr, *poff = nullptr;  // [9E], [9E+1] candidates per (capsule, column)
+  int32_t *pairs = nullptr, *npairs = nullptr;
   double* ssph = nullptr;             // [E*4] spheres in bucket (cell) order
   long long* skey = nullptr;          // [E] packed exact cell coordinates in bucket order
   int32_t* srg = nullptr;             // [E*2] rod, group in bucket order
@@ -86,9 +87,10 @@ enum Stage {
   TB_WAVES = 0,   // 4 wavefronts (<= 512 pill slots) per block: rod kernels
   TB_PILLS,       // 256 pills per block
   TB_CAPS,        // 256 capsules per block
+  TB_SEARCH,      // 28 capsules per block, 9 threads each: neighbour search
   TB_CELLS,       // 256 hash cells per block
   TB_PAIRS,       // 256 candidate-pair slots per block
-  TB_SCAN_E,      // 1024 capsules per block (scans)
+  TB_SCAN_E,      // 1024 (capsule, neighbour column) counts per block (scans)
   TB_SCAN_T,      // 1024 cells per block
   TB_COUNT
 };
