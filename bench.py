@@ -37,7 +37,7 @@ PEAK_HBM = 8.0e12
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("rod_kernels.hip", "rod_device.h", "viper_dev.h"):
+    for f in ("rod_kernels.hip", "rod_device.h"):
         with open(os.path.join(ROOT, "paper_1906_05260_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
