@@ -96,7 +96,7 @@ __device__ __forceinline__ void acc_add(unsigned long long* a, double v) {
   const ContactDev& c = (CD)[blk_.scene];       \
   (void)d; (void)c;
 
-// Zero the per-substep hash-cell counters.
+// Reset the per-substep hash-bucket counters and group ranges.
 __global__ void __launch_bounds__(256) zero_cells_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
   const Blk b = tab[blockIdx.x];
   const ContactDev& c = CD[b.scene];
@@ -104,6 +104,8 @@ __global__ void __launch_bounds__(256) zero_cells_kernel(const ContactDev* __res
   if (i >= c.T) return;
   c.cell_cnt[i] = 0;
   c.cell_cur[i] = 0;
+  c.cgmin[i] = 0x7fffffff;
+  c.cgmax[i] = -0x7fffffff - 1;
 }
 
 // Copy the detection state (FP64 world positions, scales) and zero the largest-radius
@@ -254,6 +256,8 @@ __global__ void __launch_bounds__(256) key_kernel(const ContactDev* __restrict__
   const uint32_t h = cell_hash(cx, cy, cz, c.T);
   c.key[i] = (int32_t)h;
   atomicAdd(&c.cell_cnt[h], 1);
+  atomicMin(&c.cgmin[h], c.cap_grp[i]);
+  atomicMax(&c.cgmax[h], c.cap_grp[i]);
 }
 
 __global__ void __launch_bounds__(256) bucket_scatter_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
@@ -293,7 +297,8 @@ __global__ void __launch_bounds__(256) reorder_kernel(const ContactDev* __restri
 // neighbour entries (their loads coalesce); each of a capsule's 9 threads covers one
 // (dz, dy) column of 3 cells.  Counts are per (capsule, column) so that an exclusive scan
 // gives every thread its output offset; after the emit pass the capsule's first thread
-// sorts the capsule's segment by b and stores capsule ids.
+// sorts the capsule's segment by b and stores capsule ids.  A bucket whose entries all
+// share the capsule's collision group (the interior of a muscle) is skipped unread.
 template <bool EMIT>
 __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
   const Blk blk = tab[blockIdx.x];
@@ -314,6 +319,7 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
     for (int dx = -1; dx <= 1; ++dx) {
       const int nx = cx + dx;
       const uint32_t h = cell_hash(nx, ny, nz, c.T);
+      if (c.cgmin[h] == ga && c.cgmax[h] == ga) continue;   // every entry is in this capsule's group
       const long long nk = pack_cell(nx, ny, nz);
       const int j1 = c.cell_start[h + 1];
       for (int j = c.cell_start[h]; j < j1; ++j) {
@@ -515,6 +521,8 @@ ContactOffsets contact_layout(size_t start, bool on, int P, int E, int cpc, bool
   o.cell_start = take(4 * (size_t)(T + 1));
   o.cell_cur = take(4 * (size_t)T);
   o.sorted = take(4 * (size_t)E);
+  o.cgmin = take(4 * (size_t)T);
+  o.cgmax = take(4 * (size_t)T);
   o.pcount = take(4 * (size_t)kSearchSub * E);
   o.poff = take(4 * ((size_t)kSearchSub * E + 1));
   o.pairs = take(8 * cap);
@@ -562,6 +570,8 @@ viper_status contact_init(ContactDev& c, char* ws, const ContactOffsets& o, cons
   c.cell_start = (int32_t*)(ws + o.cell_start);
   c.cell_cur = (int32_t*)(ws + o.cell_cur);
   c.sorted = (int32_t*)(ws + o.sorted);
+  c.cgmin = (int32_t*)(ws + o.cgmin);
+  c.cgmax = (int32_t*)(ws + o.cgmax);
   c.pcount = (int32_t*)(ws + o.pcount);
   c.poff = (int32_t*)(ws + o.poff);
   c.pairs = (int32_t*)(ws + o.pairs);

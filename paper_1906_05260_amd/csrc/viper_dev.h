@@ -63,6 +63,7 @@ struct ContactDev {
   unsigned long long* maxr = nullptr; // bits of the largest sphere radius
   int32_t *key = nullptr, *cell = nullptr;  // [E] hash keys, [3E] integer cell coordinates
   int32_t *cell_cnt = nullptr, *cell_start = nullptr, *cell_cur = nullptr, *sorted = nullptr;
+  int32_t *cgmin = nullptr, *cgmax = nullptr;  // [T] smallest / largest group id in each bucket
   int32_t *pcount = nullptr, *poff = nullptr;  // [9E], [9E+1] candidates per (capsule, column)
   int32_t *pairs = nullptr, *npairs = nullptr;
   double* ssph = nullptr;             // [E*4] spheres in bucket (cell) order
