@@ -116,14 +116,36 @@ __device__ __forceinline__ void gather_vjp(const DT<T> (&out)[M], const T (&yb)[
 
 // ---------------------------------------------------------------- local VJPs
 
+// The backward kernel runs every logical lane in kReps replica waves of one block: all
+// replicas recompute the same state, and the input-direction chunks of each local VJP are
+// split between them (chunk c on replica c % kReps); share_chunks then gives every replica
+// the full result through LDS.  Called by all threads of the block (it has barriers).
+constexpr int kReps = 4;
+
+template <class T, int N>
+__device__ __forceinline__ void share_chunks(T (&xb)[N], int rep, T* X, int lane) {
+  constexpr int KD = KDim<T>::v;
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+    if ((i / KD) % kReps == rep) X[i * 64 + lane] = xb[i];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < N; ++i) xb[i] = X[i * 64 + lane];
+  __syncthreads();
+}
+
 // Stretch-shear + volume + scale gradient of slot L's edge (edge_update).
 // Inputs (26): x0 x1 x2 s q0 q1 q2 q3 l0..l4 | b0 b1 b2 sb | w ws ilb ass avol asg I1 | wb wsb
 // Outputs (17): x0 x1 x2 s q0..q3 l0..l4 | b0 b1 b2 sb
 template <class T>
-__device__ void edge_vjp(const Slot<T>& L, T b0, T b1, T b2, T sb, T wb, T wsb, const T (&yb)[17], T (&xb)[26]) {
+__device__ void edge_vjp(const Slot<T>& L, T b0, T b1, T b2, T sb, T wb, T wsb, const T (&yb)[17], T (&xb)[26],
+                         int rep, T* X, int lane) {
+  constexpr int KD = KDim<T>::v;
   const T v[26] = {L.x0, L.x1, L.x2, L.s, L.q0, L.q1, L.q2, L.q3, L.l[0], L.l[1], L.l[2], L.l[3], L.l[4],
                    b0, b1, b2, sb, L.w, L.ws, L.ilb, L.ass, L.avol, L.asg, L.I1, wb, wsb};
-  for (int c0 = 0; c0 < 26; c0 += KDim<T>::v) {
+#pragma unroll
+  for (int i = 0; i < 26; ++i) xb[i] = T(0);
+  for (int c0 = rep * KD; c0 < 26; c0 += kReps * KD) {
     DT<T> in[26];
     seed(in, v, c0);
     Slot<DT<T>> S;
@@ -139,14 +161,19 @@ __device__ void edge_vjp(const Slot<T>& L, T b0, T b1, T b2, T sb, T wb, T wsb, 
                            c0_, c1_, c2_, cs_};
     gather_vjp(out, yb, c0, xb);
   }
+  share_chunks(xb, rep, X, lane);
 }
 
 // Bend-twist between slot L's edge and the next edge (bt_update).
 // Inputs (16): q0..q3 l5 l6 l7 | b0..b3 sb | Ia Ib wsb abt      Outputs (12): q0..q3 l5..l7 | b0..b3 sb
 template <class T>
-__device__ void bt_vjp(const Slot<T>& L, T b0, T b1, T b2, T b3, T sb, T Ib, T wsb, const T (&yb)[12], T (&xb)[16]) {
+__device__ void bt_vjp(const Slot<T>& L, T b0, T b1, T b2, T b3, T sb, T Ib, T wsb, const T (&yb)[12], T (&xb)[16],
+                       int rep, T* X, int lane) {
+  constexpr int KD = KDim<T>::v;
   const T v[16] = {L.q0, L.q1, L.q2, L.q3, L.l[5], L.l[6], L.l[7], b0, b1, b2, b3, sb, L.I1, Ib, wsb, L.abt};
-  for (int c0 = 0; c0 < 16; c0 += KDim<T>::v) {
+#pragma unroll
+  for (int i = 0; i < 16; ++i) xb[i] = T(0);
+  for (int c0 = rep * KD; c0 < 16; c0 += kReps * KD) {
     DT<T> in[16];
     seed(in, v, c0);
     Slot<DT<T>> S;
@@ -160,6 +187,7 @@ __device__ void bt_vjp(const Slot<T>& L, T b0, T b1, T b2, T b3, T sb, T Ib, T w
     const DT<T> out[12] = {S.q0, S.q1, S.q2, S.q3, S.l[5], S.l[6], S.l[7], e0, e1, e2, e3, es};
     gather_vjp(out, yb, c0, xb);
   }
+  share_chunks(xb, rep, X, lane);
 }
 
 // Angular velocity from the quaternions after / before the substep (omega_of).
@@ -228,27 +256,32 @@ __device__ __forceinline__ void snap_io(T* base, size_t NL, Slot<T>& A, Slot<T>&
 
 // ---------------------------------------------------------------- reverse passes
 
+// Every lane calls the local VJP once per pass (the call has block barriers): on its A edge,
+// its B edge, or on a dummy whose result it discards.
 template <class T>
-__device__ void pass_edges_vjp(Lane2<T>& P, SAdj<T>& aA, SAdj<T>& aB, int colour) {
+__device__ void pass_edges_vjp(Lane2<T>& P, SAdj<T>& aA, SAdj<T>& aB, int colour, int rep, T* X, int lane) {
   const T n0 = dn(P.A.x0), n1 = dn(P.A.x1), n2 = dn(P.A.x2), ns = dn(P.A.s);       // pre-pass next slot A
   const T g0 = dn(aA.x0), g1 = dn(aA.x1), g2 = dn(aA.x2), gs = dn(aA.s);            // adjoint of its post-pass value
+  const bool useA = (P.A.f & F_EDGE) && colour_is(P.A.f, colour);
+  const bool useB = !useA && (P.B.f & F_EDGE) && colour_is(P.B.f, colour);
+  const Slot<T> L = useB ? P.B : P.A;
+  const T yb[17] = {useB ? aB.x0 : aA.x0, useB ? aB.x1 : aA.x1, useB ? aB.x2 : aA.x2, useB ? aB.s : aA.s,
+                    useB ? aB.q0 : aA.q0, useB ? aB.q1 : aA.q1, useB ? aB.q2 : aA.q2, useB ? aB.q3 : aA.q3,
+                    useB ? aB.l[0] : aA.l[0], useB ? aB.l[1] : aA.l[1], useB ? aB.l[2] : aA.l[2],
+                    useB ? aB.l[3] : aA.l[3], useB ? aB.l[4] : aA.l[4],
+                    useB ? g0 : aB.x0, useB ? g1 : aB.x1, useB ? g2 : aB.x2, useB ? gs : aB.s};
+  T xb[26];
+  edge_vjp(L, useB ? n0 : P.B.x0, useB ? n1 : P.B.x1, useB ? n2 : P.B.x2, useB ? ns : P.B.s,
+           useB ? P.wN : P.B.w, useB ? P.wsN : P.B.ws, yb, xb, rep, X, lane);
   T r0 = T(0), r1 = T(0), r2 = T(0), rs = T(0), rw = T(0), rws = T(0);
-  if ((P.A.f & F_EDGE) && colour_is(P.A.f, colour)) {
-    const T yb[17] = {aA.x0, aA.x1, aA.x2, aA.s, aA.q0, aA.q1, aA.q2, aA.q3, aA.l[0], aA.l[1], aA.l[2], aA.l[3], aA.l[4],
-                      aB.x0, aB.x1, aB.x2, aB.s};
-    T xb[26];
-    edge_vjp(P.A, P.B.x0, P.B.x1, P.B.x2, P.B.s, P.B.w, P.B.ws, yb, xb);
+  if (useA) {
     aA.x0 = xb[0]; aA.x1 = xb[1]; aA.x2 = xb[2]; aA.s = xb[3];
     aA.q0 = xb[4]; aA.q1 = xb[5]; aA.q2 = xb[6]; aA.q3 = xb[7];
     aA.l[0] = xb[8]; aA.l[1] = xb[9]; aA.l[2] = xb[10]; aA.l[3] = xb[11]; aA.l[4] = xb[12];
     aB.x0 = xb[13]; aB.x1 = xb[14]; aB.x2 = xb[15]; aB.s = xb[16];
     aA.w += xb[17]; aA.ws += xb[18]; aA.ilb += xb[19]; aA.ass += xb[20]; aA.avol += xb[21]; aA.asg += xb[22];
     aA.I1 += xb[23]; aB.w += xb[24]; aB.ws += xb[25];
-  } else if ((P.B.f & F_EDGE) && colour_is(P.B.f, colour)) {
-    const T yb[17] = {aB.x0, aB.x1, aB.x2, aB.s, aB.q0, aB.q1, aB.q2, aB.q3, aB.l[0], aB.l[1], aB.l[2], aB.l[3], aB.l[4],
-                      g0, g1, g2, gs};
-    T xb[26];
-    edge_vjp(P.B, n0, n1, n2, ns, P.wN, P.wsN, yb, xb);
+  } else if (useB) {
     aB.x0 = xb[0]; aB.x1 = xb[1]; aB.x2 = xb[2]; aB.s = xb[3];
     aB.q0 = xb[4]; aB.q1 = xb[5]; aB.q2 = xb[6]; aB.q3 = xb[7];
     aB.l[0] = xb[8]; aB.l[1] = xb[9]; aB.l[2] = xb[10]; aB.l[3] = xb[11]; aB.l[4] = xb[12];
@@ -263,22 +296,25 @@ __device__ void pass_edges_vjp(Lane2<T>& P, SAdj<T>& aA, SAdj<T>& aB, int colour
 }
 
 template <class T>
-__device__ void pass_bt_vjp(Lane2<T>& P, SAdj<T>& aA, SAdj<T>& aB, int colour) {
+__device__ void pass_bt_vjp(Lane2<T>& P, SAdj<T>& aA, SAdj<T>& aB, int colour, int rep, T* X, int lane) {
   const T n0 = dn(P.A.q0), n1 = dn(P.A.q1), n2 = dn(P.A.q2), n3 = dn(P.A.q3), ns = dn(P.A.s);
   const T g0 = dn(aA.q0), g1 = dn(aA.q1), g2 = dn(aA.q2), g3 = dn(aA.q3), gs = dn(aA.s);
+  const bool useA = (P.A.f & F_BT) && (P.A.f & F_BTEN) && colour_is(P.A.f, colour);
+  const bool useB = !useA && (P.B.f & F_BT) && (P.B.f & F_BTEN) && colour_is(P.B.f, colour);
+  const Slot<T> L = useB ? P.B : P.A;
+  const T yb[12] = {useB ? aB.q0 : aA.q0, useB ? aB.q1 : aA.q1, useB ? aB.q2 : aA.q2, useB ? aB.q3 : aA.q3,
+                    useB ? aB.l[5] : aA.l[5], useB ? aB.l[6] : aA.l[6], useB ? aB.l[7] : aA.l[7],
+                    useB ? g0 : aB.q0, useB ? g1 : aB.q1, useB ? g2 : aB.q2, useB ? g3 : aB.q3, useB ? gs : aB.s};
+  T xb[16];
+  bt_vjp(L, useB ? n0 : P.B.q0, useB ? n1 : P.B.q1, useB ? n2 : P.B.q2, useB ? n3 : P.B.q3, useB ? ns : P.B.s,
+         useB ? P.I1N : P.B.I1, useB ? P.wsN : P.B.ws, yb, xb, rep, X, lane);
   T r0 = T(0), r1 = T(0), r2 = T(0), r3 = T(0), rs = T(0), rI = T(0), rws = T(0);
-  if ((P.A.f & F_BT) && (P.A.f & F_BTEN) && colour_is(P.A.f, colour)) {
-    const T yb[12] = {aA.q0, aA.q1, aA.q2, aA.q3, aA.l[5], aA.l[6], aA.l[7], aB.q0, aB.q1, aB.q2, aB.q3, aB.s};
-    T xb[16];
-    bt_vjp(P.A, P.B.q0, P.B.q1, P.B.q2, P.B.q3, P.B.s, P.B.I1, P.B.ws, yb, xb);
+  if (useA) {
     aA.q0 = xb[0]; aA.q1 = xb[1]; aA.q2 = xb[2]; aA.q3 = xb[3];
     aA.l[5] = xb[4]; aA.l[6] = xb[5]; aA.l[7] = xb[6];
     aB.q0 = xb[7]; aB.q1 = xb[8]; aB.q2 = xb[9]; aB.q3 = xb[10]; aB.s = xb[11];
     aA.I1 += xb[12]; aB.I1 += xb[13]; aB.ws += xb[14]; aA.abt += xb[15];
-  } else if ((P.B.f & F_BT) && (P.B.f & F_BTEN) && colour_is(P.B.f, colour)) {
-    const T yb[12] = {aB.q0, aB.q1, aB.q2, aB.q3, aB.l[5], aB.l[6], aB.l[7], g0, g1, g2, g3, gs};
-    T xb[16];
-    bt_vjp(P.B, n0, n1, n2, n3, ns, P.I1N, P.wsN, yb, xb);
+  } else if (useB) {
     aB.q0 = xb[0]; aB.q1 = xb[1]; aB.q2 = xb[2]; aB.q3 = xb[3];
     aB.l[5] = xb[4]; aB.l[6] = xb[5]; aB.l[7] = xb[6];
     r0 = xb[7]; r1 = xb[8]; r2 = xb[9]; r3 = xb[10]; rs = xb[11];
@@ -369,17 +405,42 @@ __global__ void __launch_bounds__(256) rod_frame_ckpt_kernel(const Dev<T>* __res
 // at the end of the substep on entry and at its start on exit; padj ([8][pill]) accumulates
 // the parameter adjoints: 1/M, 1/M_s, 1/lbar, rho pi r^4 l0, and the four compliance
 // scalings; snap is this lane's pass-snapshot scratch.
+// Block b works on logical wavefront tab[b / 4].base + b % 4 (the forward's lane layout),
+// replicated in its 4 waves: replica r = wave index within the block.  A whole block is
+// inactive or active, so the early return never splits a barrier.
+template <class T>
+__device__ __forceinline__ const Dev<T>* lane_setup_rep(const Dev<T>* D, const Blk* tab, Lane2<T>& P, int& pA,
+                                                        int& pB, int& wave) {
+  const Blk b = tab[blockIdx.x >> 2];
+  const Dev<T>* d = D + b.scene;
+  wave = b.base + (int)(blockIdx.x & 3);
+  const int lane = (int)(threadIdx.x & 63);
+  if (wave >= d->W) return nullptr;
+  const int p0 = d->wave_start[wave];
+  const int n = d->wave_start[wave + 1] - p0;
+  const bool vA = 2 * lane < n, vB = 2 * lane + 1 < n;
+  pA = p0 + (vA ? 2 * lane : 0);
+  pB = p0 + (vB ? 2 * lane + 1 : 0);
+  P.A.f = vA ? d->flags[pA] : 0u;
+  P.B.f = vB ? d->flags[pB] : 0u;
+  return d;
+}
+
 template <class T>
 __global__ void __launch_bounds__(256) rod_backward_kernel(const Dev<T>* __restrict__ D, const Blk* __restrict__ tab,
                                                            T h, int iters, const T* __restrict__ ckpt, T* __restrict__ snap,
                                                            T* __restrict__ adj, T* __restrict__ padj) {
+  __shared__ T X[26 * 64];                 // chunk exchange between the replicas
   Lane2<T> P;
-  int pA, pB;
-  const Dev<T>* dp = lane_setup(D, tab, P, pA, pB);
+  int pA, pB, wave;
+  const Dev<T>* dp = lane_setup_rep(D, tab, P, pA, pB, wave);
   if (!dp) return;
   const Dev<T>& d = *dp;
+  const int lane = (int)(threadIdx.x & 63);
+  const int rep = (int)(threadIdx.x >> 6);
+  const bool writer = rep == 0;
   const size_t NL = (size_t)d.W * 64;
-  const size_t lg = (size_t)(tab[blockIdx.x].base + (int)(threadIdx.x >> 6)) * 64 + (threadIdx.x & 63);
+  const size_t lg = (size_t)wave * 64 + lane;
   T* cbase = const_cast<T*>(ckpt);
   ckpt_io(cbase, d.P, pA, P.A, false);
   ckpt_io(cbase, d.P, pB, P.B, false);
@@ -392,12 +453,13 @@ __global__ void __launch_bounds__(256) rod_backward_kernel(const Dev<T>* __restr
   inertia_lane(P);
   for (int it = 0; it < iters; ++it) {
     for (int k = 0; k < 4; ++k) {
-      snap_io(snap + ((size_t)(it * 4 + k) * 32) * NL + lg, NL, P.A, P.B, true);
+      if (writer) snap_io(snap + ((size_t)(it * 4 + k) * 32) * NL + lg, NL, P.A, P.B, true);
       if (k < 2) pass_edges(P, k); else pass_bt(P, k - 2);
     }
   }
   velocity_slot(P.A, ih);
   velocity_slot(P.B, ih);
+  __syncthreads();                         // the snapshots of replica 0 are read by all
   // adjoint of the substep-end state
   SAdj<T> aA, aB;
   zero_adj(aA);
@@ -419,7 +481,7 @@ __global__ void __launch_bounds__(256) rod_backward_kernel(const Dev<T>* __restr
   for (int it = iters - 1; it >= 0; --it) {
     for (int k = 3; k >= 0; --k) {
       snap_io(snap + ((size_t)(it * 4 + k) * 32) * NL + lg, NL, P.A, P.B, false);
-      if (k < 2) pass_edges_vjp(P, aA, aB, k); else pass_bt_vjp(P, aA, aB, k - 2);
+      if (k < 2) pass_edges_vjp(P, aA, aB, k, rep, X, lane); else pass_bt_vjp(P, aA, aB, k - 2, rep, X, lane);
     }
   }
   // substep-start inertia of both edges (the B edge's right end is the next lane's A)
@@ -455,6 +517,7 @@ __global__ void __launch_bounds__(256) rod_backward_kernel(const Dev<T>* __restr
       out.q0 = T(0); out.q1 = T(0); out.q2 = T(0); out.q3 = T(0);
       out.o0 = T(0); out.o1 = T(0); out.o2 = T(0);
     }
+    if (!writer) continue;
     ckpt_io(adj, d.P, ps[j], out, true);
     const int p = ps[j];
     padj[0 * (size_t)d.P + p] += a.w;
@@ -544,7 +607,7 @@ hipError_t launch_backward(const BatchDev& b, int P, int nsub, double h, int ite
   if (P == 0) return hipSuccess;
   hipLaunchKernelGGL(adjoint_seed_kernel<T>, dim3((P + 255) / 256), dim3(256), 0, st, P, dldx, adj, padj);
   for (int sub = nsub - 1; sub >= 0; --sub)
-    hipLaunchKernelGGL(rod_backward_kernel<T>, dim3(b.nblk[TB_WAVES]), dim3(256), 0, st, (const Dev<T>*)b.dev,
+    hipLaunchKernelGGL(rod_backward_kernel<T>, dim3(4 * b.nblk[TB_WAVES]), dim3(64 * kReps), 0, st, (const Dev<T>*)b.dev,
                        b.tab[TB_WAVES], (T)h, iters, ckpt + (size_t)sub * kCkptFields * P, snap, adj, padj);
   hipLaunchKernelGGL(adjoint_chain_kernel<T>, dim3((P + 255) / 256), dim3(256), 0, st, (const Dev<T>*)b.dev,
                      (const T*)padj, rho, drbar, dact);

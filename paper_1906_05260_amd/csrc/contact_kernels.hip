@@ -33,6 +33,7 @@ namespace {
 // cells; 28 capsules (252 threads) per block.
 constexpr int kSearchSub = 9;
 constexpr int kSearchCaps = 28;
+constexpr int kStage = 4;       // candidates per (capsule, column) kept by the count pass
 
 __device__ __forceinline__ uint32_t cell_hash(int x, int y, int z, int T) {
   return ((uint32_t)x * 73856093u ^ (uint32_t)y * 19349663u ^ (uint32_t)z * 83492791u) & (uint32_t)(T - 1);
@@ -296,8 +297,9 @@ __global__ void __launch_bounds__(256) reorder_kernel(const ContactDev* __restri
 // follow bucket order, so the lanes of a wave mostly share a home cell and walk the same
 // neighbour entries (their loads coalesce); each of a capsule's 9 threads covers one
 // (dz, dy) column of 3 cells.  Counts are per (capsule, column) so that an exclusive scan
-// gives every thread its output offset; after the emit pass the capsule's first thread
-// sorts the capsule's segment by b and stores capsule ids.  A bucket whose entries all
+// gives every thread its output offset.  The count pass keeps a column's first 4
+// candidates, so the emit pass re-walks only the columns that had more.  After the emit
+// pass the capsule's first thread sorts the capsule's segment by b and stores capsule ids.  A bucket whose entries all
 // share the capsule's collision group (the interior of a muscle) is skipped unread.
 template <bool EMIT>
 __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
@@ -307,8 +309,19 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
   const int jh = blk.base + q;                      // bucket position of the home capsule
   const bool live = q < kSearchCaps && jh < c.E;
   int a = 0;
+  int32_t* stg = nullptr;
+  int have = 0;
   if (live) {
     a = c.sorted[jh];
+    stg = c.stage + (size_t)kStage * (kSearchSub * (size_t)a + sub);
+    if (EMIT) have = c.pcount[kSearchSub * (size_t)a + sub];
+  }
+  if (EMIT && live && have <= kStage) {
+    // the count pass kept every candidate of this column: copy them
+    const int base = c.poff[kSearchSub * (size_t)a + sub];
+    for (int k = 0; k < have; ++k)
+      if (base + k < c.cap) c.pairs[2 * (size_t)(base + k) + 1] = stg[k];
+  } else if (live) {
     const double sa[4] = {c.ssph[4 * (size_t)jh], c.ssph[4 * (size_t)jh + 1], c.ssph[4 * (size_t)jh + 2],
                           c.ssph[4 * (size_t)jh + 3]};
     const int ra = c.srg[2 * (size_t)jh], ga = c.srg[2 * (size_t)jh + 1];
@@ -333,6 +346,8 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
         if (EMIT) {
           const int idx = base + cnt;
           if (idx < c.cap) c.pairs[2 * (size_t)idx + 1] = b;   // capsule index for now
+        } else if (cnt < kStage) {
+          stg[cnt] = b;
         }
         ++cnt;
       }
@@ -525,6 +540,7 @@ ContactOffsets contact_layout(size_t start, bool on, int P, int E, int cpc, bool
   o.cgmax = take(4 * (size_t)T);
   o.pcount = take(4 * (size_t)kSearchSub * E);
   o.poff = take(4 * ((size_t)kSearchSub * E + 1));
+  o.stage = take(4 * (size_t)kStage * kSearchSub * E);
   o.pairs = take(8 * cap);
   o.npairs = take(4);
   o.ssph = take(8 * 4 * (size_t)E);
@@ -574,6 +590,7 @@ viper_status contact_init(ContactDev& c, char* ws, const ContactOffsets& o, cons
   c.cgmax = (int32_t*)(ws + o.cgmax);
   c.pcount = (int32_t*)(ws + o.pcount);
   c.poff = (int32_t*)(ws + o.poff);
+  c.stage = (int32_t*)(ws + o.stage);
   c.pairs = (int32_t*)(ws + o.pairs);
   c.npairs = (int32_t*)(ws + o.npairs);
   c.ssph = (double*)(ws + o.ssph);

@@ -65,6 +65,7 @@ struct ContactDev {
   int32_t *cell_cnt = nullptr, *cell_start = nullptr, *cell_cur = nullptr, *sorted = nullptr;
   int32_t *cgmin = nullptr, *cgmax = nullptr;  // [T] smallest / largest group id in each bucket
   int32_t *pcount = nullptr, *poff = nullptr;  // [9E], [9E+1] candidates per (capsule, column)
+  int32_t* stage = nullptr;           // [9E*4] first candidates of each (capsule, column)
   int32_t *pairs = nullptr, *npairs = nullptr;
   double* ssph = nullptr;             // [E*4] spheres in bucket (cell) order
   long long* skey = nullptr;          // [E] packed exact cell coordinates in bucket order
