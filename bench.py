@@ -216,6 +216,36 @@ def contact_skin_timing(torch, viper, scenes, dev, frames=10):
             "skin_algorithmic_GB_per_s": skin_bytes / (skin_ms * 1e-3) / 1e9}
 
 
+def paper_shaped_timing(torch, viper, scenes, dev, frames=10):
+    """The paper's octopus-sized scene (100 models x 37 pills, inter-model collisions, each
+    skinned to 6.5k vertices): ms per frame at 20 x 8 and per skinning pass, beside the
+    paper's ~7 ms per frame on one GTX 1080 (its substeps and iterations are unstated)."""
+    desc, mesh = scenes.octopus_scene()
+    sc = viper.Scene(desc, "f32", device=dev, collisions=True)
+    sid = sc.create_skin(mesh.rest_v, mesh.caps, mesh.w)
+    out = torch.empty((mesh.rest_v.shape[0], 3), dtype=torch.float32, device=dev)
+    res = {"workload": "octopus100x37", "pills": desc.num_pills, "skin_vertices": int(mesh.rest_v.shape[0])}
+    st = torch.cuda.current_stream()
+    for sub, it in ((20, 8), (4, 4)):
+        for _ in range(2):
+            sc.step(1.0 / 60.0, sub, it)
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record(st)
+        for _ in range(frames):
+            sc.step(1.0 / 60.0, sub, it)
+        e1.record(st)
+        for _ in range(frames):
+            sc.step(1.0 / 60.0, sub, it)
+            sc.skin(sid, out=out)
+        e2.record(st)
+        torch.cuda.synchronize()
+        res["frame_ms_%dx%d" % (sub, it)] = e0.elapsed_time(e1) / frames
+        res["frame_plus_skin_ms_%dx%d" % (sub, it)] = e1.elapsed_time(e2) / frames
+    sc.sync()
+    res["paper_ms_gtx1080"] = 7.0
+    return res
+
+
 def serving_run(torch, scenes, serve, seconds):
     """Poisson arrivals (200/s) of helix and muscle scenes of 1k-200k pills (log-uniform),
     60 frames each; continuous batching vs the plain per-scene path on the same requests."""
@@ -339,6 +369,7 @@ def main():
     out["single_rod"] = single_rod_timing(torch, viper, scenes, dev)
     if not args.no_contacts:
         out["contacts_skinning"] = contact_skin_timing(torch, viper, scenes, dev)
+        out["paper_shaped"] = paper_shaped_timing(torch, viper, scenes, dev)
         log("contacts and skinning done")
     if not args.no_adjoint:
         out["adjoint"] = adjoint_timing(torch, viper, scenes, dev)

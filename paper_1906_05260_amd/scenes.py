@@ -240,6 +240,82 @@ def muscle_mesh(desc: SceneDesc, muscle_info, V, rng) -> SkinMesh:
                     np.concatenate(ww).astype(np.float32))
 
 
+def octopus_scene(num_models=100, seed=5, mesh_vertices_per_model=6500, spacing=0.2):
+    """Models shaped like the paper's octopus example (Sec. 8): a 5-pill body hanging from
+    a pinned top pill and 8 arms of 4 pills leaving the body's lowest pill, 37 pills per
+    model, on a square grid close enough for neighbouring arms to collide (collision group =
+    model).  The body's top pill and each arm's root are pinned.  Radii 1.5 cm (body) and
+    1.2 -> 0.6 cm (arms); compliances 1e-7 (stretch-shear), 1e-8 (volume, scale gradient),
+    1e-5 (bend-twist): stiff enough in volume that scales stay near 1 (with the log-uniform
+    compliances of the helix scene, the soft volume and scale-gradient terms let bend-twist
+    drive scales through zero within a frame); activation 1.  Each model gets a skinning mesh of ``mesh_vertices_per_model``
+    vertices on its capsules' surfaces, influences = its 4 nearest capsules at rest with
+    Dirichlet(1,1,1,1) weights.  Returns (desc, mesh)."""
+    rng = np.random.default_rng(seed)
+    side = int(np.ceil(np.sqrt(num_models)))
+    pos, rad, pin, offs, grp, comp = [], [], [], [0], [], []
+    model_rods = []
+    for m in range(num_models):
+        base = np.array([(m % side) * spacing, 0.5, (m // side) * spacing])
+        rods = []
+        body = base + np.outer(np.arange(5), [0.0, -0.025, 0.0])
+        pos.append(body)
+        rad.append(np.full(5, 0.015))
+        pn = np.zeros(5, np.uint8)
+        pn[0] = 1
+        pin.append(pn)
+        rods.append(len(offs) - 1)
+        offs.append(offs[-1] + 5)
+        grp.append(m)
+        foot = body[-1]
+        for a in range(8):
+            th = 2 * np.pi * a / 8 + rng.uniform(-0.1, 0.1)
+            d = np.array([np.cos(th), -0.35, np.sin(th)])
+            d /= np.linalg.norm(d)
+            arm = foot + np.outer(np.arange(1, 5), 0.03 * d)
+            pos.append(arm)
+            rad.append(np.linspace(0.012, 0.006, 4))
+            pa = np.zeros(4, np.uint8)
+            pa[0] = 1                     # the arm's root is held at the body
+            pin.append(pa)
+            rods.append(len(offs) - 1)
+            offs.append(offs[-1] + 4)
+            grp.append(m)
+        model_rods.append(rods)
+    R = len(grp)
+    comp = np.tile([1e-7, 1e-8, 1e-8, 1e-5], (R, 1))
+    desc = SceneDesc(np.asarray(offs, np.int32), np.concatenate(pos), np.concatenate(rad), np.concatenate(pin),
+                     np.ones(R), comp, np.asarray(grp, np.int32), collisions=True,
+                     name="octopus%dx37" % num_models)
+    rv, cp, ww = [], [], []
+    V = int(mesh_vertices_per_model)
+    for m in range(num_models if V > 0 else 0):
+        caps = np.concatenate([np.arange(offs[k], offs[k + 1] - 1) for k in model_rods[m]])
+        a, b = desc.rest_pos[caps], desc.rest_pos[caps + 1]
+        ra, rb = desc.rest_radius[caps], desc.rest_radius[caps + 1]
+        L = np.linalg.norm(b - a, axis=1)
+        pick = rng.choice(len(caps), V, p=L / L.sum())
+        t = rng.uniform(0.0, 1.0, V)
+        axis = (b - a)[pick] / L[pick, None]
+        helper = np.where(np.abs(axis[:, 1:2]) < 0.9, [[0.0, 1.0, 0.0]], [[1.0, 0.0, 0.0]])
+        e1 = np.cross(axis, helper)
+        e1 /= np.linalg.norm(e1, axis=1, keepdims=True)
+        e2 = np.cross(axis, e1)
+        th = rng.uniform(0.0, 2 * np.pi, V)
+        r = (1 - t) * ra[pick] + t * rb[pick] + 0.002
+        p = a[pick] + t[:, None] * (b - a)[pick] + r[:, None] * (np.cos(th)[:, None] * e1 + np.sin(th)[:, None] * e2)
+        mids = 0.5 * (a + b)
+        d2 = ((p[:, None, :] - mids[None, :, :]) ** 2).sum(-1)
+        cp.append(caps[np.argsort(d2, axis=1, kind="stable")[:, :4]])
+        rv.append(p)
+        ww.append(rng.dirichlet(np.ones(4), V))
+    mesh = None
+    if rv:
+        mesh = SkinMesh(np.concatenate(rv).astype(np.float32), np.concatenate(cp).astype(np.int32),
+                        np.concatenate(ww).astype(np.float32))
+    return desc, mesh
+
+
 def scene_of_size(n_pills: int, kind: str, seed: int):
     """A serving request: helix rods of 64 pills or a muscle scene, about n_pills pills.
     Returns (desc, mesh or None)."""
