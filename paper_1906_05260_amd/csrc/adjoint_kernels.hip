@@ -120,7 +120,7 @@ __device__ __forceinline__ void gather_vjp(const DT<T> (&out)[M], const T (&yb)[
 // replicas recompute the same state, and the input-direction chunks of each local VJP are
 // split between them (chunk c on replica c % kReps); share_chunks then gives every replica
 // the full result through LDS.  Called by all threads of the block (it has barriers).
-constexpr int kReps = 4;
+constexpr int kReps = 8;
 
 template <class T, int N>
 __device__ __forceinline__ void share_chunks(T (&xb)[N], int rep, T* X, int lane) {
@@ -406,7 +406,7 @@ __global__ void __launch_bounds__(256) rod_frame_ckpt_kernel(const Dev<T>* __res
 // the parameter adjoints: 1/M, 1/M_s, 1/lbar, rho pi r^4 l0, and the four compliance
 // scalings; snap is this lane's pass-snapshot scratch.
 // Block b works on logical wavefront tab[b / 4].base + b % 4 (the forward's lane layout),
-// replicated in its 4 waves: replica r = wave index within the block.  A whole block is
+// replicated in its kReps waves: replica r = wave index within the block.  A whole block is
 // inactive or active, so the early return never splits a barrier.
 template <class T>
 __device__ __forceinline__ const Dev<T>* lane_setup_rep(const Dev<T>* D, const Blk* tab, Lane2<T>& P, int& pA,
@@ -427,7 +427,7 @@ __device__ __forceinline__ const Dev<T>* lane_setup_rep(const Dev<T>* D, const B
 }
 
 template <class T>
-__global__ void __launch_bounds__(256) rod_backward_kernel(const Dev<T>* __restrict__ D, const Blk* __restrict__ tab,
+__global__ void __launch_bounds__(64 * kReps) rod_backward_kernel(const Dev<T>* __restrict__ D, const Blk* __restrict__ tab,
                                                            T h, int iters, const T* __restrict__ ckpt, T* __restrict__ snap,
                                                            T* __restrict__ adj, T* __restrict__ padj) {
   __shared__ T X[26 * 64];                 // chunk exchange between the replicas
