@@ -120,7 +120,7 @@ __device__ __forceinline__ void gather_vjp(const DT<T> (&out)[M], const T (&yb)[
 // replicas recompute the same state, and the input-direction chunks of each local VJP are
 // split between them (chunk c on replica c % kReps); share_chunks then gives every replica
 // the full result through LDS.  Called by all threads of the block (it has barriers).
-constexpr int kReps = 8;
+constexpr int kReps = 4;
 
 template <class T, int N>
 __device__ __forceinline__ void share_chunks(T (&xb)[N], int rep, T* X, int lane) {
