@@ -195,6 +195,15 @@ viper_status viper_pool_create(void* workspace, size_t bytes, int32_t max_scenes
                                viper_pool* out);
 viper_status viper_pool_admit(viper_pool pool, const viper_scene_desc* desc, void* stream, int32_t* slot);
 viper_status viper_pool_step(viper_pool pool, double dt, int32_t substeps, int32_t iterations, void* stream);
+/* One frame of one class of resident scenes, enqueued on `stream`: classes = 1 the
+ * collision-free scenes (one launch), 2 the scenes with contacts (their shared launch
+ * sequence), 3 both on the same stream.  The classes are independent: a caller may keep a
+ * step of each in flight on its own stream (a collision-free frame then does not wait for
+ * the contact scenes' much longer one).  A class whose membership changed since its last
+ * step first waits for `stream` and rebuilds its header.  Retire a scene only after its
+ * class's last step has completed. */
+viper_status viper_pool_step_ex(viper_pool pool, double dt, int32_t substeps, int32_t iterations, int32_t classes,
+                                void* stream);
 viper_status viper_pool_retire(viper_pool pool, int32_t slot, void* stream);
 viper_status viper_pool_scene(viper_pool pool, int32_t slot, viper_scene* scene);
 viper_status viper_pool_info(viper_pool pool, size_t* free_bytes, size_t* largest_free, int32_t* resident,

@@ -831,7 +831,7 @@ struct viper_pool_s {
   size_t header_cap = 0;                 // [0, header_cap): two batch headers
   std::map<size_t, size_t> free_;        // offset -> size of free ranges
   std::vector<PoolSlot> slots;
-  bool dirty = true;
+  bool dirty_f = true, dirty_c = true;   // membership of a class changed since its header was built
   BatchDev fb, cb;                       // collision-free batch, contact batch
   std::vector<char> hf, hc;              // host images of the headers
   hipStream_t aux = nullptr;
@@ -856,44 +856,56 @@ void pool_free_range(viper_pool_s* P, size_t off, size_t size) {
   }
 }
 
+// Rebuild the header of one class (collision-free or with contacts) in its own half of
+// the header region.  `st` is the stream that stepped that class last: it is synchronised
+// first, so that no step still reads the header being replaced.
 template <class T>
-viper_status pool_rebuild(viper_pool_s* P, hipStream_t st) {
-  HIP_TRY(hipStreamSynchronize(st));   // the previous step no longer reads the headers
-  std::vector<const void*> df, dc;
+viper_status pool_rebuild(viper_pool_s* P, bool contact, hipStream_t st) {
+  HIP_TRY(hipStreamSynchronize(st));
+  std::vector<const void*> dv;
   std::vector<ContactDev> cc;
-  std::vector<Counts> vf, vc;
+  std::vector<Counts> vc;
   for (const PoolSlot& sl : P->slots) {
-    if (!sl.scene) continue;
+    if (!sl.scene || (sl.scene->collisions != 0) != contact) continue;
     viper_scene_s* S = sl.scene;
-    const void* d = (const void*)&dev<T>(S);
-    if (S->collisions) { dc.push_back(d); cc.push_back(S->cd); vc.push_back(scene_counts(S)); }
-    else { df.push_back(d); vf.push_back(scene_counts(S)); }
+    dv.push_back((const void*)&dev<T>(S));
+    if (contact) cc.push_back(S->cd);
+    vc.push_back(scene_counts(S));
   }
   const size_t half = P->header_cap / 2;
-  if (header_bytes(vf, sizeof(Dev<T>)) > half || header_bytes(vc, sizeof(Dev<T>)) > half)
+  if (header_bytes(vc, sizeof(Dev<T>)) > half)
     return fail(VIPER_ERR_NO_CAPACITY, "pool header region too small for the resident set");
-  build_header(P->hf, df, sizeof(Dev<T>), std::vector<ContactDev>(), vf, P->ws, P->fb);
-  build_header(P->hc, dc, sizeof(Dev<T>), cc, vc, P->ws + half, P->cb);
-  if (!P->hf.empty()) HIP_TRY(hipMemcpyAsync(P->ws, P->hf.data(), P->hf.size(), hipMemcpyHostToDevice, st));
-  if (!P->hc.empty()) HIP_TRY(hipMemcpyAsync(P->ws + half, P->hc.data(), P->hc.size(), hipMemcpyHostToDevice, st));
-  P->dirty = false;
+  std::vector<char>& img = contact ? P->hc : P->hf;
+  char* at = P->ws + (contact ? half : 0);
+  build_header(img, dv, sizeof(Dev<T>), cc, vc, at, contact ? P->cb : P->fb);
+  if (!img.empty()) {
+    HIP_TRY(hipMemcpyAsync(at, img.data(), img.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));   // the host image may change before the next rebuild
+  }
+  (contact ? P->dirty_c : P->dirty_f) = false;
   return VIPER_OK;
 }
 
 template <class T>
+viper_status pool_step_class(viper_pool_s* P, bool contact, double dt, int sub, int iters, hipStream_t st) {
+  if (contact ? P->dirty_c : P->dirty_f) {
+    viper_status r = pool_rebuild<T>(P, contact, st);
+    if (r != VIPER_OK) return r;
+  }
+  const BatchDev& b = contact ? P->cb : P->fb;
+  if (b.nscenes == 0) return VIPER_OK;
+  return batch_step<T>(b, contact, dt, sub, iters, contact ? VIPER_MODE_ITERATION : VIPER_MODE_FRAME, st);
+}
+
+// Both classes: collision-free on `st`, contacts on the pool's second stream, joined.
+template <class T>
 viper_status pool_step_t(viper_pool_s* P, double dt, int sub, int iters, hipStream_t st) {
-  if (P->dirty) {
-    viper_status r = pool_rebuild<T>(P, st);
-    if (r != VIPER_OK) return r;
-  }
-  if (P->fb.nscenes > 0) {
-    viper_status r = batch_step<T>(P->fb, false, dt, sub, iters, VIPER_MODE_FRAME, st);
-    if (r != VIPER_OK) return r;
-  }
-  if (P->cb.nscenes > 0) {
+  viper_status r = pool_step_class<T>(P, false, dt, sub, iters, st);
+  if (r != VIPER_OK) return r;
+  if (P->dirty_c || P->cb.nscenes > 0) {
     HIP_TRY(hipEventRecord(P->ev0, st));
     HIP_TRY(hipStreamWaitEvent(P->aux, P->ev0, 0));
-    viper_status r = batch_step<T>(P->cb, true, dt, sub, iters, VIPER_MODE_ITERATION, P->aux);
+    r = pool_step_class<T>(P, true, dt, sub, iters, P->aux);
     if (r != VIPER_OK) return r;
     HIP_TRY(hipEventRecord(P->ev1, P->aux));
     HIP_TRY(hipStreamWaitEvent(st, P->ev1, 0));
@@ -956,7 +968,7 @@ viper_status viper_pool_admit(viper_pool P, const viper_scene_desc* desc, void* 
     return r;
   }
   P->slots[sid] = PoolSlot{S, off, fp};
-  P->dirty = true;
+  (S->collisions ? P->dirty_c : P->dirty_f) = true;
   *slot = sid;
   return VIPER_OK;
 }
@@ -970,16 +982,31 @@ viper_status viper_pool_step(viper_pool P, double dt, int32_t substeps, int32_t 
                                    : pool_step_t<float>(P, dt, substeps, iterations, st);
 }
 
+viper_status viper_pool_step_ex(viper_pool P, double dt, int32_t substeps, int32_t iterations, int32_t classes,
+                                void* stream) {
+  if (!P) return fail(VIPER_ERR_INVALID, "pool is NULL");
+  if (!(dt > 0) || !std::isfinite(dt) || substeps < 1 || iterations < 0)
+    return fail(VIPER_ERR_INVALID, "dt > 0, substeps >= 1, iterations >= 0 required");
+  if (classes < 1 || classes > 3) return fail(VIPER_ERR_INVALID, "classes must be 1, 2 or 3");
+  hipStream_t st = (hipStream_t)stream;
+  viper_status r = VIPER_OK;
+  for (int c = 0; c < 2 && r == VIPER_OK; ++c)
+    if (classes & (1 << c))
+      r = P->precision == VIPER_F64 ? pool_step_class<double>(P, c == 1, dt, substeps, iterations, st)
+                                    : pool_step_class<float>(P, c == 1, dt, substeps, iterations, st);
+  return r;
+}
+
 viper_status viper_pool_retire(viper_pool P, int32_t slot, void* stream) {
   if (!P || slot < 0 || slot >= P->max_scenes || !P->slots[slot].scene) return fail(VIPER_ERR_INVALID, "bad slot");
   // the range may be reused by the next admission: let the device finish with it first
   HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
   HIP_TRY(hipStreamSynchronize(P->aux));
   PoolSlot& sl = P->slots[slot];
+  (sl.scene->collisions ? P->dirty_c : P->dirty_f) = true;
   delete sl.scene;
   pool_free_range(P, sl.off, sl.size);
   sl = PoolSlot();
-  P->dirty = true;
   return VIPER_OK;
 }
 

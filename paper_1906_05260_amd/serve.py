@@ -1,11 +1,11 @@
 """Serving loop: continuous batching of rod scenes on one GPU.
 
 Requests (a scene and a number of frames) arrive over time.  The batched server keeps
-every admitted scene resident in one device pool and advances all of them by one frame
-per pool step (one launch for the collision-free scenes, one shared launch sequence for
-the scenes with contacts).  Requests that arrive while a step runs are admitted as soon as
-a slot and a free range of the pool's HBM fit their footprint; their uploads run on a
-copy stream and they join the next step.  Finished scenes are retired, which frees their
+every admitted scene resident in one device pool and advances them frame by frame in two
+independent classes (one launch for all collision-free scenes, one shared launch sequence
+for all scenes with contacts), each class on its own stream.  Requests that arrive while
+a step runs are admitted as soon as a slot and a free range of the pool's HBM fit their
+footprint; their uploads run on a copy stream and they join their class's next step.  Finished scenes are retired, which frees their
 range.  The plain path serves the same requests first-come first-served, one scene at a
 time with its own launches, as a baseline.
 
@@ -43,16 +43,24 @@ def _summary(lat, ttff, pill_frames, t_first, t_last, extra=None):
 
 def serve_batched(requests, pool_bytes, dt=1.0 / 60.0, substeps=20, iterations=8, max_scenes=512,
                   precision="f32", device="cuda:0", on_finish=None, progress=None):
-    """Continuous batching over a device pool.  `on_finish(request, scene)` (optional) is
-    called with each finished scene before it is retired; `progress(msg)` (optional)
-    receives a line every 50 steps."""
+    """Continuous batching over a device pool.
+
+    The collision-free scenes and the scenes with contacts are two classes, each stepped
+    one frame at a time on its own stream (viper_pool_step_ex), each with at most one step
+    in flight: a collision-free frame (one launch for all of them) does not wait for the
+    contact scenes' longer launch sequence.  Arrivals are admitted while steps run (uploads
+    on a copy stream) and join their class's next step; a finished scene is retired as soon
+    as its class's step completes.  `on_finish(request, scene)` (optional) is called with
+    each finished scene before it is retired; `progress(msg)` (optional) receives a line
+    every 100 class steps."""
     import torch
     pool = viper.Pool(pool_bytes, max_scenes=max_scenes, precision=precision, device=device)
     copy_stream = torch.cuda.Stream(device=device)
-    main = torch.cuda.current_stream(device)
+    lanes = {1: {"stream": torch.cuda.Stream(device=device), "event": None, "members": []},
+             2: {"stream": torch.cuda.Stream(device=device), "event": None, "members": []}}
     pending = deque(sorted(requests, key=lambda r: r.arrival))
     waiting = deque()
-    resident = {}                     # slot -> [request, frames done, t_ready]
+    resident = {}                     # slot -> [request, frames done, t_ready, class]
     lat, ttff = [], []
     pill_frames = 0
     peak_bytes = 0
@@ -72,36 +80,33 @@ def serve_batched(requests, pool_bytes, dt=1.0 / 60.0, substeps=20, iterations=8
             if slot is None:
                 break
             waiting.popleft()
-            resident[slot] = [r, 0, r.arrival]
+            resident[slot] = [r, 0, r.arrival, 2 if r.desc.collisions else 1]
         info = pool.info()
         peak_bytes = max(peak_bytes, pool_bytes - info["free_bytes"])
         host["admit_s"] += time.perf_counter() - ta
 
-    while pending or waiting or resident:
-        admit_ready()
-        if not resident:
-            if pending:
-                time.sleep(max(0.0, pending[0].arrival - (time.perf_counter() - t0)))
-            continue
-        members = list(resident.keys())
+    def launch(cls):
+        nonlocal steps
+        lane = lanes[cls]
+        members = [k for k, v in resident.items() if v[3] == cls]
+        if not members:
+            return
         ts = time.perf_counter()
-        pool.step(dt, substeps, iterations, stream=main)
-        done_ev = torch.cuda.Event()
-        done_ev.record(main)
+        pool.step(dt, substeps, iterations, stream=lane["stream"], classes=cls)
+        ev = torch.cuda.Event()
+        ev.record(lane["stream"])
         host["step_enqueue_s"] += time.perf_counter() - ts
+        lane["event"], lane["members"] = ev, members
         steps += 1
-        # overlap: admit arrivals (uploads on the copy stream) while the step runs
-        while not done_ev.query():
-            admit_ready()
-            time.sleep(20e-6)
-        tw = time.perf_counter()
-        done_ev.synchronize()
+        if progress is not None and steps % 100 == 0:
+            progress("batched: %d class steps, %d resident, %d waiting, %d pending, t=%.2fs" %
+                     (steps, len(resident), len(waiting), len(pending), time.perf_counter() - t0))
+
+    def complete(cls):
+        nonlocal pill_frames
+        lane = lanes[cls]
         t_done = time.perf_counter() - t0
-        host["gpu_wait_s"] += time.perf_counter() - tw
-        if progress is not None and steps % 50 == 0:
-            progress("batched: step %d, %d resident, %d waiting, %d pending, t=%.2fs" %
-                     (steps, len(resident), len(waiting), len(pending), t_done))
-        for slot in members:
+        for slot in lane["members"]:
             st = resident[slot]
             r = st[0]
             lat.append(t_done - st[2])
@@ -114,9 +119,29 @@ def serve_batched(requests, pool_bytes, dt=1.0 / 60.0, substeps=20, iterations=8
                 if on_finish is not None:
                     on_finish(r, pool.scene(slot))
                 tr = time.perf_counter()
-                pool.retire(slot, stream=main)
+                pool.retire(slot, stream=lane["stream"])
                 host["retire_s"] += time.perf_counter() - tr
                 del resident[slot]
+        lane["event"], lane["members"] = None, []
+
+    while pending or waiting or resident:
+        admit_ready()
+        for cls in (1, 2):
+            if lanes[cls]["event"] is None:
+                launch(cls)
+        busy = [c for c in (1, 2) if lanes[c]["event"] is not None]
+        if not busy:
+            if pending:
+                time.sleep(max(0.0, pending[0].arrival - (time.perf_counter() - t0)))
+            continue
+        done = [c for c in busy if lanes[c]["event"].query()]
+        if not done:
+            tw = time.perf_counter()
+            time.sleep(20e-6)
+            host["gpu_wait_s"] += time.perf_counter() - tw
+            continue
+        for c in done:
+            complete(c)
     t_last = time.perf_counter() - t0
     t_first = min(r.arrival for r in requests) if requests else 0.0
     return _summary(lat, ttff, pill_frames, t_first, t_last,

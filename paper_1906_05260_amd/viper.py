@@ -32,7 +32,7 @@ ABI_SYMBOLS = [
     "viper_destroy_scene", "viper_scene_info", "viper_last_error",
     "viper_pool_create", "viper_pool_admit", "viper_pool_step", "viper_pool_retire", "viper_pool_scene",
     "viper_pool_info", "viper_pool_destroy",
-    "viper_adjoint_sizes", "viper_step_checkpointed", "viper_step_backward",
+    "viper_adjoint_sizes", "viper_step_checkpointed", "viper_step_backward", "viper_pool_step_ex",
 ]
 
 
@@ -88,6 +88,7 @@ def lib():
         L.viper_pool_create.argtypes = [P, ctypes.c_size_t, I32, I32, P, ctypes.POINTER(P)]
         L.viper_pool_admit.argtypes = [P, P, P, ctypes.POINTER(I32)]
         L.viper_pool_step.argtypes = [P, D, I32, I32, P]
+        L.viper_pool_step_ex.argtypes = [P, D, I32, I32, I32, P]
         L.viper_pool_retire.argtypes = [P, I32, P]
         L.viper_pool_scene.argtypes = [P, I32, ctypes.POINTER(P)]
         L.viper_pool_info.argtypes = [P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
@@ -349,8 +350,14 @@ class Pool:
         self.descs[int(slot.value)] = desc
         return int(slot.value)
 
-    def step(self, dt, substeps, iterations, stream=None):
-        check(lib().viper_pool_step(self.handle, float(dt), int(substeps), int(iterations), _stream_ptr(stream)))
+    def step(self, dt, substeps, iterations, stream=None, classes=None):
+        """One frame of every resident scene (classes=None), or of one class: 1 = collision-free,
+        2 = with contacts, 3 = both on `stream`."""
+        if classes is None:
+            check(lib().viper_pool_step(self.handle, float(dt), int(substeps), int(iterations), _stream_ptr(stream)))
+        else:
+            check(lib().viper_pool_step_ex(self.handle, float(dt), int(substeps), int(iterations), int(classes),
+                                           _stream_ptr(stream)))
 
     def retire(self, slot, stream=None):
         check(lib().viper_pool_retire(self.handle, int(slot), _stream_ptr(stream)))

@@ -35,8 +35,10 @@ def run_alone(desc, frames, prec="f32"):
     return sc.state()
 
 
-@pytest.mark.parametrize("prec", ["f32", "f64"])
-def test_alone_equals_mix(prec):
+@pytest.mark.parametrize("prec,split", [("f32", False), ("f64", False), ("f32", True)])
+def test_alone_equals_mix(prec, split):
+    """split: the two classes (collision-free, with contacts) stepped separately on two
+    streams, as the serving loop does, instead of one joint pool step."""
     A = scenes.helix_rods(37, 64, seed=11)
     B, _ = scenes.muscle_scene(num_muscles=6, seed=12, target_pills=None, mesh_vertices=0)
     C = scenes.helix_rods(5, 64, seed=13)
@@ -51,9 +53,16 @@ def test_alone_equals_mix(prec):
         plan[name] = s
         frames[name] = 0
 
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+
     def step(n):
         for _ in range(n):
-            pool.step(DT, SUB, IT)
+            if split:
+                pool.step(DT, SUB, IT, stream=s1, classes=1)
+                pool.step(DT, SUB, IT, stream=s2, classes=2)
+                torch.cuda.synchronize()
+            else:
+                pool.step(DT, SUB, IT)
             for k in frames:
                 if k not in retired:
                     frames[k] += 1
@@ -76,7 +85,7 @@ def test_alone_equals_mix(prec):
         alone = run_alone(desc, frames[name], prec)
         e = errors(desc, retired[name], alone)
         same = all(np.array_equal(retired[name][k], alone[k]) for k in ("x", "s", "q"))
-        say(prec, name, "frames", frames[name], "errors", e, "bit-identical", same)
+        say(prec, "split" if split else "joint", name, "frames", frames[name], "errors", e, "bit-identical", same)
         assert max(e) < 1e-4
     for name in ("B", "C", "D"):
         pool.scene(plan[name]).sync()
