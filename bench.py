@@ -257,7 +257,7 @@ def serving_run(torch, scenes, serve, seconds):
     return {"workload": "poisson200x%.2fs_1k-200k_60frames" % seconds, "requests": len(reqs),
             "pills": int(sum(r.desc.num_pills for r in reqs)),
             "contact_requests": int(sum(r.kind == "muscle" for r in reqs)),
-            "batched": {k: b[k] for k in keep + ("steps", "peak_resident_bytes", "host_s")},
+            "batched": {k: b[k] for k in keep + ("steps", "peak_resident_bytes", "per_class", "host_s")},
             "plain": {k: p[k] for k in keep}}
 
 

@@ -903,6 +903,7 @@ viper_status pool_step_t(viper_pool_s* P, double dt, int sub, int iters, hipStre
   viper_status r = pool_step_class<T>(P, false, dt, sub, iters, st);
   if (r != VIPER_OK) return r;
   if (P->dirty_c || P->cb.nscenes > 0) {
+    if (!P->aux) HIP_TRY(hipStreamCreateWithFlags(&P->aux, hipStreamNonBlocking));
     HIP_TRY(hipEventRecord(P->ev0, st));
     HIP_TRY(hipStreamWaitEvent(P->aux, P->ev0, 0));
     r = pool_step_class<T>(P, true, dt, sub, iters, P->aux);
@@ -933,11 +934,12 @@ viper_status viper_pool_create(void* workspace, size_t bytes, int32_t max_scenes
   P->header_cap = header;
   P->free_[header] = bytes - header;
   P->slots.resize(max_scenes);
-  if (hipStreamCreateWithFlags(&P->aux, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&P->ev0, hipEventDisableTiming) != hipSuccess ||
+  // the second stream of the joint step is created at its first use (callers that step the
+  // classes on their own streams never need it, and every stream takes a hardware queue)
+  if (hipEventCreateWithFlags(&P->ev0, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&P->ev1, hipEventDisableTiming) != hipSuccess) {
     delete P;
-    return fail(VIPER_ERR_DEVICE, "could not create the pool's stream or events");
+    return fail(VIPER_ERR_DEVICE, "could not create the pool's events");
   }
   *out = P;
   return VIPER_OK;
@@ -1001,7 +1003,7 @@ viper_status viper_pool_retire(viper_pool P, int32_t slot, void* stream) {
   if (!P || slot < 0 || slot >= P->max_scenes || !P->slots[slot].scene) return fail(VIPER_ERR_INVALID, "bad slot");
   // the range may be reused by the next admission: let the device finish with it first
   HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
-  HIP_TRY(hipStreamSynchronize(P->aux));
+  if (P->aux) HIP_TRY(hipStreamSynchronize(P->aux));
   PoolSlot& sl = P->slots[slot];
   (sl.scene->collisions ? P->dirty_c : P->dirty_f) = true;
   delete sl.scene;

@@ -56,8 +56,11 @@ def serve_batched(requests, pool_bytes, dt=1.0 / 60.0, substeps=20, iterations=8
     import torch
     pool = viper.Pool(pool_bytes, max_scenes=max_scenes, precision=precision, device=device)
     copy_stream = torch.cuda.Stream(device=device)
-    lanes = {1: {"stream": torch.cuda.Stream(device=device), "event": None, "members": []},
+    # the collision-free class steps on the caller's current stream, the contact class on one
+    # more: few streams, so that each keeps a hardware queue of its own
+    lanes = {1: {"stream": torch.cuda.current_stream(device), "event": None, "members": []},
              2: {"stream": torch.cuda.Stream(device=device), "event": None, "members": []}}
+    lat_cls = {1: [], 2: []}
     pending = deque(sorted(requests, key=lambda r: r.arrival))
     waiting = deque()
     resident = {}                     # slot -> [request, frames done, t_ready, class]
@@ -110,6 +113,7 @@ def serve_batched(requests, pool_bytes, dt=1.0 / 60.0, substeps=20, iterations=8
             st = resident[slot]
             r = st[0]
             lat.append(t_done - st[2])
+            lat_cls[cls].append(t_done - st[2])
             if st[1] == 0:
                 ttff.append(t_done - r.arrival)
             st[1] += 1
@@ -144,9 +148,15 @@ def serve_batched(requests, pool_bytes, dt=1.0 / 60.0, substeps=20, iterations=8
             complete(c)
     t_last = time.perf_counter() - t0
     t_first = min(r.arrival for r in requests) if requests else 0.0
+    per_class = {}
+    for cls, name in ((1, "collision_free"), (2, "contacts")):
+        v = np.asarray(lat_cls[cls]) * 1e3
+        per_class[name] = {"frames": int(v.size),
+                           "latency_ms_p50": float(np.percentile(v, 50)) if v.size else None,
+                           "latency_ms_p99": float(np.percentile(v, 99)) if v.size else None}
     return _summary(lat, ttff, pill_frames, t_first, t_last,
                     {"path": "batched", "steps": steps, "peak_resident_bytes": int(peak_bytes),
-                     "host_s": {k: round(v, 4) for k, v in host.items()}})
+                     "per_class": per_class, "host_s": {k: round(v, 4) for k, v in host.items()}})
 
 
 def serve_plain(requests, dt=1.0 / 60.0, substeps=20, iterations=8, precision="f32", device="cuda:0",
