@@ -21,6 +21,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -207,13 +209,38 @@ def contact_skin_timing(torch, viper, scenes, dev, frames=10):
     eager_ms = e2.elapsed_time(e3) / frames
     V = int(mesh.rest_v.shape[0])
     skin_bytes = 56 * V + 48 * sc.capsules     # rest vertex 12 + 4 ids 16 + 4 weights 16 + out 12; transforms
+    # the same skinning with a mesh far beyond the caches: 16M vertices (0.9 GB of vertex data),
+    # influences drawn uniformly over the scene's capsules, Dirichlet(1,1,1,1) weights
+    rng = np.random.default_rng(7)
+    VL = 16 << 20
+    last = set((np.asarray(desc.rod_offsets[1:]) - 1).tolist())
+    capsule_ids = np.array([p for p in range(desc.num_pills) if p not in last], dtype=np.int32)
+    big_caps = capsule_ids[rng.integers(0, len(capsule_ids), (VL, 4))]
+    g = rng.gamma(1.0, 1.0, (VL, 4)).astype(np.float32)
+    big_w = g / g.sum(1, keepdims=True)
+    big_v = rng.uniform(-1.0, 1.0, (VL, 3)).astype(np.float32)
+    sid_l = sc.create_skin(big_v, big_caps, big_w)
+    del big_caps, big_w, big_v
+    out_l = torch.empty((VL, 3), dtype=torch.float32, device=dev)
+    sc.skin(sid_l, out=out_l)
+    e5, e6 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e5.record(st)
+    for _ in range(frames):
+        sc.skin(sid_l, out=out_l)
+    e6.record(st)
+    torch.cuda.synchronize()
+    skin_l_ms = e5.elapsed_time(e6) / frames
+    skin_l_bytes = 56 * VL + 48 * sc.capsules
     return {"workload": "muscle64_%dpills" % desc.num_pills, "pills": desc.num_pills, "capsules": sc.capsules,
             "contact_pairs_last_substep": int(len(sc.contacts())), "frame_ms": frame_ms,
             "frame_ms_eager_launches": eager_ms, "frame_ms_wall_graph": wall_graph,
             "pill_substeps_per_s": desc.num_pills * sub / (frame_ms * 1e-3),
             "launches_per_frame": sub * (2 + 20 + 3 * iters),
             "skin_vertices": V, "skin_ms": skin_ms,
-            "skin_algorithmic_GB_per_s": skin_bytes / (skin_ms * 1e-3) / 1e9}
+            "skin_algorithmic_GB_per_s": skin_bytes / (skin_ms * 1e-3) / 1e9,
+            "skin_large": {"vertices": VL, "ms": skin_l_ms, "algorithmic_bytes": skin_l_bytes,
+                           "GB_per_s": skin_l_bytes / (skin_l_ms * 1e-3) / 1e9,
+                           "hbm_frac": skin_l_bytes / (skin_l_ms * 1e-3) / PEAK_HBM}}
 
 
 def paper_shaped_timing(torch, viper, scenes, dev, frames=10):
