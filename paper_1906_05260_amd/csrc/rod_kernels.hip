@@ -247,9 +247,12 @@ __global__ void __launch_bounds__(256) lbs_kernel(int V, const float* __restrict
                                                   float* __restrict__ out) {
   const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
   if (i >= V) return;
-  const float vx = rest_v[3 * i], vy = rest_v[3 * i + 1], vz = rest_v[3 * i + 2];
   const int4 c = caps[i];
   const float4 wt = w[i];
+  const float vx = rest_v[3 * i], vy = rest_v[3 * i + 1], vz = rest_v[3 * i + 2];
+  // Issue every streamed load before the gathers: left alone, the scheduler sinks the
+  // weight load below them and each wave pays a second HBM round trip.
+  __builtin_amdgcn_sched_barrier(0);
   const int ci[4] = {c.x, c.y, c.z, c.w};
   const float wk[4] = {wt.x, wt.y, wt.z, wt.w};
   float o0 = 0.f, o1 = 0.f, o2 = 0.f;

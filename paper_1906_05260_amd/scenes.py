@@ -210,8 +210,9 @@ def muscle_scene(num_muscles=64, seed=2, target_pills=(45000, 55000), rods_range
 
 
 def muscle_mesh(desc: SceneDesc, muscle_info, V, rng) -> SkinMesh:
-    """Vertices on each muscle's envelope cylinder (count proportional to its pills);
-    influences = the 4 nearest capsules of that muscle at rest, Dirichlet(1,1,1,1) weights."""
+    """Vertices on each muscle's envelope cylinder (count proportional to its pills), in
+    order along the muscle's axis; influences = the 4 nearest capsules of that muscle at
+    rest, Dirichlet(1,1,1,1) weights."""
     offs = desc.rod_offsets
     pills = np.array([sum(int(offs[k + 1] - offs[k]) for k in mi["rods"]) for mi in muscle_info], dtype=np.float64)
     counts = np.floor(V * pills / pills.sum()).astype(np.int64)
@@ -223,7 +224,7 @@ def muscle_mesh(desc: SceneDesc, muscle_info, V, rng) -> SkinMesh:
             continue
         caps = np.concatenate([np.arange(offs[k], offs[k + 1] - 1) for k in mi["rods"]])
         mids = 0.5 * (desc.rest_pos[caps] + desc.rest_pos[caps + 1])
-        u = rng.uniform(0.0, 1.0, nv)
+        u = np.sort(rng.uniform(0.0, 1.0, nv))      # vertex order runs along the axis, as a mesh's rings do
         th = rng.uniform(0.0, 2 * np.pi, nv)
         xx = mi["x0"] + u * mi["L"]
         rr = mi["radius"] + 0.004
