@@ -143,8 +143,11 @@ def _vogel_disc(n, radius):
     return np.stack([r * np.cos(th), r * np.sin(th)], axis=1)
 
 
+MUSCLE_COMPLIANCE = (1e-7, 1e-8, 1e-8, 1e-5)     # stretch-shear, volume, scale gradient, bend-twist
+
+
 def muscle_scene(num_muscles=64, seed=2, target_pills=(45000, 55000), rods_range=(16, 48), pills_range=(8, 24),
-                 mesh_vertices=200000, spacing=0.01):
+                 mesh_vertices=200000, spacing=0.01, compliance=MUSCLE_COMPLIANCE):
     """Bundles of parallel rods ("muscles") packed side by side so that neighbours touch.
 
     Each muscle has U{16..48} rods of U{8..24} pills (all rods of a muscle share the
@@ -152,7 +155,11 @@ def muscle_scene(num_muscles=64, seed=2, target_pills=(45000, 55000), rods_range
     a time at random muscles until the total lies in ``target_pills`` (the plain
     draws average ~33k pills; the workload asks for ~50k).  Both rod ends are
     pinned (bone attachments), activation U[0.8,1.2] per muscle, collision group =
-    muscle.  Returns (desc, mesh) with a skinning mesh of ``mesh_vertices`` vertices
+    muscle.  Compliances default to ``MUSCLE_COMPLIANCE`` for every rod: a muscle keeps
+    its volume, and with volume or scale-gradient compliances near 1e-4 the activation
+    step drives some scales through zero (negative radii) within the first frames;
+    ``compliance="loguniform"`` draws them log-uniform 1e-8..1e-4 per type and rod as
+    in the helix scene.  Returns (desc, mesh) with a skinning mesh of ``mesh_vertices`` vertices
     on the muscles' envelopes, 4 nearest capsules each, Dirichlet(1,1,1,1) weights.
     """
     rng = np.random.default_rng(seed)
@@ -196,7 +203,9 @@ def muscle_scene(num_muscles=64, seed=2, target_pills=(45000, 55000), rods_range
             pn[-1] = 1
             pins.append(pn)
             acts.append(act[m])
-            comps.append(_log_uniform(rng, 1e-8, 1e-4, 4))
+            drawn = _log_uniform(rng, 1e-8, 1e-4, 4)       # drawn either way: the other draws stay put
+            comps.append(drawn if isinstance(compliance, str) and compliance == "loguniform"
+                         else np.asarray(compliance, dtype=np.float64))
             groups.append(m)
             rod_ids.append(len(offs) - 1)
             offs.append(offs[-1] + n)

@@ -25,7 +25,11 @@ def say(*a):
 
 
 def small_muscles(seed=2, n=8):
-    desc, mesh = scenes.muscle_scene(num_muscles=n, seed=seed, target_pills=None, mesh_vertices=4000)
+    # Log-uniform compliances: these cases step coarsely (4 substeps, or one 1/60 s substep),
+    # where the stiff default muscle compliances drive the light scale DOFs unstable in the
+    # FP64 oracle too (scales of -48..18 after the single substep from a 4x4 state).
+    desc, mesh = scenes.muscle_scene(num_muscles=n, seed=seed, target_pills=None, mesh_vertices=4000,
+                                     compliance="loguniform")
     return desc, mesh
 
 
