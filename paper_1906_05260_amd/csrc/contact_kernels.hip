@@ -34,6 +34,7 @@ namespace {
 constexpr int kSearchSub = 9;
 constexpr int kSearchCaps = 28;
 constexpr int kStage = 4;       // candidates per (capsule, column) kept by the count pass
+constexpr int kSortMax = 64;    // longest per-capsule candidate segment sorted in LDS
 
 __device__ __forceinline__ uint32_t cell_hash(int x, int y, int z, int T) {
   return ((uint32_t)x * 73856093u ^ (uint32_t)y * 19349663u ^ (uint32_t)z * 83492791u) & (uint32_t)(T - 1);
@@ -355,11 +356,34 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
     if (!EMIT) c.pcount[kSearchSub * (size_t)a + sub] = cnt;
   }
   if (!EMIT) return;
+  // Sort each capsule's segment by b and store capsule ids (first pill of each capsule).
+  // A segment of up to kSortMax entries is ranked in LDS by the capsule's 9 threads: its
+  // entries are distinct capsules, so rank = number of smaller entries is a permutation.
+  __shared__ int seg[kSearchCaps][kSortMax];
+  __syncthreads();                        // every column of the block's capsules has emitted
+  int s0 = 0, n = 0;
+  if (live) {
+    s0 = min(c.poff[kSearchSub * (size_t)a], c.cap);
+    n = min(c.poff[kSearchSub * (size_t)a + kSearchSub], c.cap) - s0;
+    if (n <= kSortMax)
+      for (int i = sub; i < n; i += kSearchSub) seg[q][i] = c.pairs[2 * (size_t)(s0 + i) + 1];
+  }
   __syncthreads();
-  if (!live || sub != 0) return;
-  // sort this capsule's segment by b, then store capsule ids (first pill of each capsule)
-  const int s0 = min(c.poff[kSearchSub * (size_t)a], c.cap);
-  const int s1 = min(c.poff[kSearchSub * (size_t)a + kSearchSub], c.cap);
+  if (!live) return;
+  const int ida = c.cap_ids[a];
+  if (n <= kSortMax) {
+    for (int i = sub; i < n; i += kSearchSub) {
+      const int v = seg[q][i];
+      int r = 0;
+      for (int k = 0; k < n; ++k) r += seg[q][k] < v;
+      c.pairs[2 * (size_t)(s0 + r)] = ida;
+      c.pairs[2 * (size_t)(s0 + r) + 1] = c.cap_ids[v];
+    }
+    return;
+  }
+  if (sub != 0) return;
+  // longer segments (rare): one thread, insertion sort in place
+  const int s1 = s0 + n;
   for (int i = s0 + 1; i < s1; ++i) {
     const int v = c.pairs[2 * (size_t)i + 1];
     int j = i - 1;
@@ -369,7 +393,6 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
     }
     c.pairs[2 * (size_t)(j + 1) + 1] = v;
   }
-  const int ida = c.cap_ids[a];
   for (int i = s0; i < s1; ++i) {
     c.pairs[2 * (size_t)i] = ida;
     c.pairs[2 * (size_t)i + 1] = c.cap_ids[c.pairs[2 * (size_t)i + 1]];
