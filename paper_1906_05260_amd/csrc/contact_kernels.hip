@@ -35,6 +35,7 @@ constexpr int kSearchSub = 9;
 constexpr int kSearchCaps = 28;
 constexpr int kStage = 4;       // candidates per (capsule, column) kept by the count pass
 constexpr int kSortMax = 64;    // longest per-capsule candidate segment sorted in LDS
+constexpr int kChunk = 4;       // bucket entries whose loads are issued together
 
 __device__ __forceinline__ uint32_t cell_hash(int x, int y, int z, int T) {
   return ((uint32_t)x * 73856093u ^ (uint32_t)y * 19349663u ^ (uint32_t)z * 83492791u) & (uint32_t)(T - 1);
@@ -329,28 +330,54 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
     const int cx = c.cell[3 * (size_t)a], cy = c.cell[3 * (size_t)a + 1], cz = c.cell[3 * (size_t)a + 2];
     const int ny = cy + sub % 3 - 1, nz = cz + sub / 3 - 1;
     const int base = EMIT ? c.poff[kSearchSub * (size_t)a + sub] : 0;
+    // The three cells of this column: bucket, group bounds and range, loaded together.
+    uint32_t hc[3];
+    int gmn[3], gmx[3], js[3], je[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) hc[d] = cell_hash(cx + d - 1, ny, nz, c.T);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      gmn[d] = c.cgmin[hc[d]]; gmx[d] = c.cgmax[hc[d]];
+      js[d] = c.cell_start[hc[d]]; je[d] = c.cell_start[hc[d] + 1];
+    }
     int cnt = 0;
-    for (int dx = -1; dx <= 1; ++dx) {
-      const int nx = cx + dx;
-      const uint32_t h = cell_hash(nx, ny, nz, c.T);
-      if (c.cgmin[h] == ga && c.cgmax[h] == ga) continue;   // every entry is in this capsule's group
-      const long long nk = pack_cell(nx, ny, nz);
-      const int j1 = c.cell_start[h + 1];
-      for (int j = c.cell_start[h]; j < j1; ++j) {
-        const int b = c.sorted[j];
-        if (b <= a) continue;
-        if (c.skey[j] != nk) continue;     // a bucket entry of another cell (hash collision)
-        if (c.srg[2 * (size_t)j] == ra || c.srg[2 * (size_t)j + 1] == ga) continue;
-        const double sb[4] = {c.ssph[4 * (size_t)j], c.ssph[4 * (size_t)j + 1], c.ssph[4 * (size_t)j + 2],
-                              c.ssph[4 * (size_t)j + 3]};
-        if (!spheres_overlap(sa, sb)) continue;
-        if (EMIT) {
-          const int idx = base + cnt;
-          if (idx < c.cap) c.pairs[2 * (size_t)idx + 1] = b;   // capsule index for now
-        } else if (cnt < kStage) {
-          stg[cnt] = b;
+    for (int d = 0; d < 3; ++d) {
+      if (gmn[d] == ga && gmx[d] == ga) continue;   // every entry is in this capsule's group
+      const long long nk = pack_cell(cx + d - 1, ny, nz);
+      const int j1 = je[d];
+      // kChunk bucket entries per round: every load of the chunk is issued before any test
+      // (indices past the end re-read the last entry and are masked), in ascending j order.
+      for (int j = js[d]; j < j1; j += kChunk) {
+        int bb[kChunk], rr[kChunk], gg[kChunk];
+        long long kk[kChunk];
+        double2 s01[kChunk], s23[kChunk];
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) {
+          const size_t jj = (size_t)min(j + u, j1 - 1);
+          bb[u] = c.sorted[jj];
+          kk[u] = c.skey[jj];
+          const int2 rg = ((const int2*)c.srg)[jj];
+          rr[u] = rg.x; gg[u] = rg.y;
+          s01[u] = ((const double2*)c.ssph)[2 * jj];
+          s23[u] = ((const double2*)c.ssph)[2 * jj + 1];
         }
-        ++cnt;
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) {
+          if (j + u >= j1) break;
+          const int b = bb[u];
+          if (b <= a) continue;
+          if (kk[u] != nk) continue;     // a bucket entry of another cell (hash collision)
+          if (rr[u] == ra || gg[u] == ga) continue;
+          const double sb[4] = {s01[u].x, s01[u].y, s23[u].x, s23[u].y};
+          if (!spheres_overlap(sa, sb)) continue;
+          if (EMIT) {
+            const int idx = base + cnt;
+            if (idx < c.cap) c.pairs[2 * (size_t)idx + 1] = b;   // capsule index for now
+          } else if (cnt < kStage) {
+            stg[cnt] = b;
+          }
+          ++cnt;
+        }
       }
     }
     if (!EMIT) c.pcount[kSearchSub * (size_t)a + sub] = cnt;
