@@ -99,31 +99,6 @@ __device__ __forceinline__ void acc_add(unsigned long long* a, double v) {
   const ContactDev& c = (CD)[blk_.scene];       \
   (void)d; (void)c;
 
-// Reset the per-substep hash-bucket counters and group ranges.
-__global__ void __launch_bounds__(256) zero_cells_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
-  const Blk b = tab[blockIdx.x];
-  const ContactDev& c = CD[b.scene];
-  const int i = b.base + (int)threadIdx.x;
-  if (i >= c.T) return;
-  c.cell_cnt[i] = 0;
-  c.cell_cur[i] = 0;
-  c.cgmin[i] = 0x7fffffff;
-  c.cgmax[i] = -0x7fffffff - 1;
-}
-
-// Copy the detection state (FP64 world positions, scales) and zero the largest-radius
-// register.
-template <class T>
-__global__ void __launch_bounds__(256) det_copy_kernel(const Dev<T>* __restrict__ D, const ContactDev* __restrict__ CD,
-                                                       const Blk* __restrict__ tab) {
-  BLOCK_SCENE(tab, D, CD)
-  const int p = blk_.base + (int)threadIdx.x;
-  if (p == 0) c.maxr[0] = 0ull;
-  if (p >= d.P) return;
-  world_pos(d, p, c.xdet + 3 * (size_t)p);
-  ((T*)c.sdet)[p] = d.s[p];
-}
-
 // ---- exclusive scans (out[n] = total), 1024 items per block, one array per scene:
 // WHICH = 0: hash-cell counts, 1: candidate counts per capsule.  The selection is a
 // template parameter: each scan kernel is compiled for one array, so no kernel selects
@@ -217,14 +192,27 @@ __global__ void __launch_bounds__(256) scan_add_kernel(const ContactDev* __restr
 
 // ---- detection
 
+// Start of detection, one launch over max(pills, cells, capsules) items of each scene:
+// copy the detection state, reset the hash buckets, and form every capsule's bounding
+// sphere with a max-reduction of the radii (the cell width of Sec. 7.1's grid).
 template <class T>
-__global__ void __launch_bounds__(256) sphere_kernel(const Dev<T>* __restrict__ D, const ContactDev* __restrict__ CD,
-                                                     const Blk* __restrict__ tab) {
+__global__ void __launch_bounds__(256) det_kernel(const Dev<T>* __restrict__ D, const ContactDev* __restrict__ CD,
+                                                  const Blk* __restrict__ tab) {
   __shared__ double sh[256];
   BLOCK_SCENE(tab, D, CD)
   const int i = blk_.base + (int)threadIdx.x;
+  if (i < d.P) {                       // detection state: FP64 world positions, scales
+    world_pos(d, i, c.xdet + 3 * (size_t)i);
+    ((T*)c.sdet)[i] = d.s[i];
+  }
+  if (i < c.T) {                       // per-substep hash-bucket counters and group ranges
+    c.cell_cnt[i] = 0;
+    c.cell_cur[i] = 0;
+    c.cgmin[i] = 0x7fffffff;
+    c.cgmax[i] = -0x7fffffff - 1;
+  }
   double R = 0.0;
-  if (i < c.E) {
+  if (i < c.E) {                       // bounding sphere of each capsule
     double sp[4];
     capsule_sphere(d, c.cap_ids[i], sp);
     c.sph[4 * (size_t)i + 0] = sp[0];
@@ -239,6 +227,7 @@ __global__ void __launch_bounds__(256) sphere_kernel(const Dev<T>* __restrict__ 
     if ((int)threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
     __syncthreads();
   }
+  // maxr is zero here: set at scene set-up, cleared again by the end of every detection
   if (threadIdx.x == 0) atomicMax(c.maxr, (unsigned long long)__double_as_longlong(sh[0]));
 }
 
@@ -263,16 +252,6 @@ __global__ void __launch_bounds__(256) key_kernel(const ContactDev* __restrict__
   atomicMax(&c.cgmax[h], c.cap_grp[i]);
 }
 
-__global__ void __launch_bounds__(256) bucket_scatter_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
-  const Blk b = tab[blockIdx.x];
-  const ContactDev& c = CD[b.scene];
-  const int i = b.base + (int)threadIdx.x;
-  if (i >= c.E) return;
-  const int h = c.key[i];
-  const int pos = c.cell_start[h] + atomicAdd(&c.cell_cur[h], 1);
-  c.sorted[pos] = i;
-}
-
 // Exact cell of a capsule packed into 63 bits (21 per axis).  Two cells that alias after
 // packing are >= 2^21 cells apart, so no sphere of one overlaps a sphere of the other: the
 // filter below may admit an aliased bucket entry, the exact overlap test then rejects it.
@@ -280,20 +259,22 @@ __device__ __forceinline__ long long pack_cell(int x, int y, int z) {
   return (long long)(x & 0x1FFFFF) | ((long long)(y & 0x1FFFFF) << 21) | ((long long)(z & 0x1FFFFF) << 42);
 }
 
-// Copy each capsule's sphere, packed cell and rod/group into bucket order, so that the
-// neighbour search below reads every cell's entries contiguously.
-__global__ void __launch_bounds__(256) reorder_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
-  const Blk blk = tab[blockIdx.x];
-  const ContactDev& c = CD[blk.scene];
-  const int j = blk.base + (int)threadIdx.x;
-  if (j >= c.E) return;
-  const int b = c.sorted[j];
+__global__ void __launch_bounds__(256) bucket_scatter_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
+  const Blk b = tab[blockIdx.x];
+  const ContactDev& c = CD[b.scene];
+  const int i = b.base + (int)threadIdx.x;
+  if (i >= c.E) return;
+  const int h = c.key[i];
+  const int pos = c.cell_start[h] + atomicAdd(&c.cell_cur[h], 1);
+  // the capsule's search data goes straight to its bucket slot: sphere, exact cell, rod, group
+  c.sorted[pos] = i;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) c.ssph[4 * (size_t)j + k] = c.sph[4 * (size_t)b + k];
-  c.skey[j] = pack_cell(c.cell[3 * (size_t)b], c.cell[3 * (size_t)b + 1], c.cell[3 * (size_t)b + 2]);
-  c.srg[2 * (size_t)j] = c.cap_rod[b];
-  c.srg[2 * (size_t)j + 1] = c.cap_grp[b];
+  for (int k = 0; k < 4; ++k) c.ssph[4 * (size_t)pos + k] = c.sph[4 * (size_t)i + k];
+  c.skey[pos] = pack_cell(c.cell[3 * (size_t)i], c.cell[3 * (size_t)i + 1], c.cell[3 * (size_t)i + 2]);
+  c.srg[2 * (size_t)pos] = c.cap_rod[i];
+  c.srg[2 * (size_t)pos + 1] = c.cap_grp[i];
 }
+
 
 // Count (EMIT = false) or emit (EMIT = true) the candidates b > a of capsule a.  Threads
 // follow bucket order, so the lanes of a wave mostly share a home cell and walk the same
@@ -307,6 +288,13 @@ template <bool EMIT>
 __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
   const Blk blk = tab[blockIdx.x];
   const ContactDev& c = CD[blk.scene];
+  if (EMIT && blk.base == 0 && threadIdx.x == 0) {
+    // the scene's pair count and overflow flag; the largest radius has had its last reader
+    const int total = c.poff[kSearchSub * (size_t)c.E];
+    c.npairs[0] = min(total, c.cap);
+    if (total > c.cap) c.status[ST_OVERFLOW] = 1;
+    c.maxr[0] = 0ull;
+  }
   const int q = (int)threadIdx.x / kSearchSub, sub = (int)threadIdx.x % kSearchSub;
   const int jh = blk.base + q;                      // bucket position of the home capsule
   const bool live = q < kSearchCaps && jh < c.E;
@@ -426,15 +414,6 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
   }
 }
 
-// One thread per scene (launched with one block per scene).
-__global__ void finalize_kernel(const ContactDev* __restrict__ CD) {
-  if (threadIdx.x != 0) return;
-  const ContactDev& c = CD[blockIdx.x];
-  const int total = c.poff[kSearchSub * (size_t)c.E];
-  c.npairs[0] = min(total, c.cap);
-  if (total > c.cap) c.status[ST_OVERFLOW] = 1;
-}
-
 // ---- handling (FP64 arithmetic)
 
 struct D3 { double x, y, z; };
@@ -531,27 +510,6 @@ __global__ void __launch_bounds__(256) contact_pair_kernel(const Dev<T>* __restr
       }
     }
   }
-}
-
-// Apply the averaged corrections of the pass and clear the accumulators for the next one.
-template <class T>
-__global__ void __launch_bounds__(256) contact_gather_kernel(const Dev<T>* __restrict__ D, const ContactDev* __restrict__ CD,
-                                                             const Blk* __restrict__ tab) {
-  BLOCK_SCENE(tab, D, CD)
-  const int p = blk_.base + (int)threadIdx.x;
-  if (p >= c.P) return;
-  const int n = c.acnt[p];
-  if (n == 0) return;
-  unsigned long long* a = c.acc + 4 * (size_t)p;
-  const double inv = 1.0 / (double)n;
-  const double ax = (double)(long long)a[0] * 0x1p-44, ay = (double)(long long)a[1] * 0x1p-44;
-  const double az = (double)(long long)a[2] * 0x1p-44, as = (double)(long long)a[3] * 0x1p-44;
-  d.px[p] = (T)((double)d.px[p] + inv * ax);
-  d.py[p] = (T)((double)d.py[p] + inv * ay);
-  d.pz[p] = (T)((double)d.pz[p] + inv * az);
-  d.s[p] = (T)((double)d.s[p] + inv * as);
-  a[0] = 0ull; a[1] = 0ull; a[2] = 0ull; a[3] = 0ull;
-  c.acnt[p] = 0;
 }
 
 }  // namespace
@@ -655,7 +613,7 @@ viper_status contact_init(ContactDev& c, char* ws, const ContactOffsets& o, cons
   if (hipMemcpyAsync(c.cap_ids, ids.data(), 4 * ids.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(c.cap_rod, rod.data(), 4 * rod.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(c.cap_grp, grp.data(), 4 * grp.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
-      hipMemsetAsync(c.npairs, 0, 4, st) != hipSuccess ||
+      hipMemsetAsync(c.npairs, 0, 4, st) != hipSuccess || hipMemsetAsync(c.maxr, 0, 8, st) != hipSuccess ||
       hipMemsetAsync(c.acc, 0, 8 * 4 * (size_t)c.P, st) != hipSuccess ||
       hipMemsetAsync(c.acnt, 0, 4 * (size_t)c.P, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
     return VIPER_ERR_DEVICE;
@@ -681,19 +639,15 @@ hipError_t launch_contact_detect(const BatchDev& b, hipStream_t st) {
   const Dev<T>* D = (const Dev<T>*)b.dev;
   const ContactDev* CD = b.cd;
   const dim3 blk(256);
-  hipLaunchKernelGGL(det_copy_kernel<T>, dim3(b.nblk[TB_PILLS]), blk, 0, st, D, CD, b.tab[TB_PILLS]);
-  hipLaunchKernelGGL(zero_cells_kernel, dim3(b.nblk[TB_CELLS]), blk, 0, st, CD, b.tab[TB_CELLS]);
-  hipLaunchKernelGGL(sphere_kernel<T>, dim3(b.nblk[TB_CAPS]), blk, 0, st, D, CD, b.tab[TB_CAPS]);
+  hipLaunchKernelGGL(det_kernel<T>, dim3(b.nblk[TB_DET]), blk, 0, st, D, CD, b.tab[TB_DET]);
   hipLaunchKernelGGL(key_kernel, dim3(b.nblk[TB_CAPS]), blk, 0, st, CD, b.tab[TB_CAPS]);
   hipError_t e = scan<0>(b, TB_SCAN_T, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(bucket_scatter_kernel, dim3(b.nblk[TB_CAPS]), blk, 0, st, CD, b.tab[TB_CAPS]);
-  hipLaunchKernelGGL(reorder_kernel, dim3(b.nblk[TB_CAPS]), blk, 0, st, CD, b.tab[TB_CAPS]);
   hipLaunchKernelGGL(pair_kernel<false>, dim3(b.nblk[TB_SEARCH]), blk, 0, st, CD, b.tab[TB_SEARCH]);
   e = scan<1>(b, TB_SCAN_E, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(pair_kernel<true>, dim3(b.nblk[TB_SEARCH]), blk, 0, st, CD, b.tab[TB_SEARCH]);
-  hipLaunchKernelGGL(finalize_kernel, dim3(b.nscenes), dim3(64), 0, st, CD);
   return hipGetLastError();
 }
 
@@ -702,7 +656,6 @@ hipError_t launch_contact_project(const BatchDev& b, hipStream_t st) {
   if (b.nscenes == 0) return hipSuccess;
   const Dev<T>* D = (const Dev<T>*)b.dev;
   hipLaunchKernelGGL(contact_pair_kernel<T>, dim3(b.nblk[TB_PAIRS]), dim3(256), 0, st, D, b.cd, b.tab[TB_PAIRS]);
-  hipLaunchKernelGGL(contact_gather_kernel<T>, dim3(b.nblk[TB_PILLS]), dim3(256), 0, st, D, b.cd, b.tab[TB_PILLS]);
   return hipGetLastError();
 }
 

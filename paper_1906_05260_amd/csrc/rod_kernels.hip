@@ -109,7 +109,7 @@ __device__ __forceinline__ void store_iter(const Dev<T>& d, const Slot<T>& L, in
 
 template <class T>
 __global__ void __launch_bounds__(256) rod_iteration_kernel(const Dev<T>* __restrict__ D, const Blk* __restrict__ tab,
-                                                            T h) {
+                                                            T h, const ContactDev* __restrict__ CD) {
   Lane2<T> P;
   int pA, pB;
   const Dev<T>* dp = lane_setup(D, tab, P, pA, pB);
@@ -117,6 +117,11 @@ __global__ void __launch_bounds__(256) rod_iteration_kernel(const Dev<T>* __rest
   const Dev<T>& d = *dp;
   load_iter(d, P.A, pA);
   load_iter(d, P.B, pB);
+  if (CD) {   // the previous contact pass's corrections come first
+    const ContactDev& c = CD[dp - D];
+    if (P.A.f & F_VALID) contact_apply(c, pA, P.A.x0, P.A.x1, P.A.x2, P.A.s);
+    if (P.B.f & F_VALID) contact_apply(c, pB, P.B.x0, P.B.x1, P.B.x2, P.B.s);
+  }
   load_lane_consts(d, P, pA, pB, rcp(h * h));
   P.I1N = dn(P.A.I1);
   iteration_lane(P);
@@ -126,9 +131,12 @@ __global__ void __launch_bounds__(256) rod_iteration_kernel(const Dev<T>* __rest
 
 // ITERATION mode, stage 3: velocity update.
 template <class T>
-__device__ __forceinline__ void velocity_store(const Dev<T>& d, Slot<T>& L, int p, T ih) {
+__device__ __forceinline__ void velocity_store(const Dev<T>& d, Slot<T>& L, int p, T ih, const ContactDev* c) {
   if (!(L.f & F_VALID)) return;
   L.x0 = d.px[p]; L.x1 = d.py[p]; L.x2 = d.pz[p]; L.s = d.s[p];
+  if (c && contact_apply(*c, p, L.x0, L.x1, L.x2, L.s)) {   // the last contact pass's corrections
+    d.px[p] = L.x0; d.py[p] = L.x1; d.pz[p] = L.x2; d.s[p] = L.s;
+  }
   L.q0 = d.qx[p]; L.q1 = d.qy[p]; L.q2 = d.qz[p]; L.q3 = d.qw[p];
   L.xp0 = d.xpx[p]; L.xp1 = d.xpy[p]; L.xp2 = d.xpz[p]; L.sp = d.spv[p];
   L.qp0 = d.qpx[p]; L.qp1 = d.qpy[p]; L.qp2 = d.qpz[p]; L.qp3 = d.qpw[p];
@@ -140,15 +148,17 @@ __device__ __forceinline__ void velocity_store(const Dev<T>& d, Slot<T>& L, int 
 }
 
 template <class T>
-__global__ void __launch_bounds__(256) velocity_kernel(const Dev<T>* __restrict__ D, const Blk* __restrict__ tab, T h) {
+__global__ void __launch_bounds__(256) velocity_kernel(const Dev<T>* __restrict__ D, const Blk* __restrict__ tab, T h,
+                                                       const ContactDev* __restrict__ CD) {
   Lane2<T> P;
   int pA, pB;
   const Dev<T>* dp = lane_setup(D, tab, P, pA, pB);
   if (!dp) return;
   const Dev<T>& d = *dp;
   const T ih = T(1) / h;
-  velocity_store(d, P.A, pA, ih);
-  velocity_store(d, P.B, pB, ih);
+  const ContactDev* c = CD ? CD + (dp - D) : nullptr;
+  velocity_store(d, P.A, pA, ih, c);
+  velocity_store(d, P.B, pB, ih, c);
 }
 
 // Field gather/scatter between the SoA layout and a pill-major array.
@@ -282,16 +292,16 @@ template <class T> hipError_t launch_predict(const BatchDev& b, double h, hipStr
                      b.tab[TB_WAVES], (T)h);
   return hipGetLastError();
 }
-template <class T> hipError_t launch_rod_iteration(const BatchDev& b, double h, hipStream_t st) {
+template <class T> hipError_t launch_rod_iteration(const BatchDev& b, double h, const ContactDev* cd, hipStream_t st) {
   if (b.nblk[TB_WAVES] == 0) return hipSuccess;
   hipLaunchKernelGGL(rod_iteration_kernel<T>, dim3(b.nblk[TB_WAVES]), dim3(256), 0, st, (const Dev<T>*)b.dev,
-                     b.tab[TB_WAVES], (T)h);
+                     b.tab[TB_WAVES], (T)h, cd);
   return hipGetLastError();
 }
-template <class T> hipError_t launch_velocity(const BatchDev& b, double h, hipStream_t st) {
+template <class T> hipError_t launch_velocity(const BatchDev& b, double h, const ContactDev* cd, hipStream_t st) {
   if (b.nblk[TB_WAVES] == 0) return hipSuccess;
   hipLaunchKernelGGL(velocity_kernel<T>, dim3(b.nblk[TB_WAVES]), dim3(256), 0, st, (const Dev<T>*)b.dev,
-                     b.tab[TB_WAVES], (T)h);
+                     b.tab[TB_WAVES], (T)h, cd);
   return hipGetLastError();
 }
 template <class T> hipError_t launch_gather_field(const Dev<T>& d, int which, T* out, hipStream_t st) {
@@ -316,8 +326,8 @@ template <class T> hipError_t launch_skin(const Dev<T>& d, int V, const float* r
 #define VIPER_INST(T)                                                                                         \
   template hipError_t launch_rod_frame<T>(const BatchDev&, int, double, int, hipStream_t);                   \
   template hipError_t launch_predict<T>(const BatchDev&, double, hipStream_t);                               \
-  template hipError_t launch_rod_iteration<T>(const BatchDev&, double, hipStream_t);                         \
-  template hipError_t launch_velocity<T>(const BatchDev&, double, hipStream_t);                              \
+  template hipError_t launch_rod_iteration<T>(const BatchDev&, double, const ContactDev*, hipStream_t);      \
+  template hipError_t launch_velocity<T>(const BatchDev&, double, const ContactDev*, hipStream_t);           \
   template hipError_t launch_gather_field<T>(const Dev<T>&, int, T*, hipStream_t);                           \
   template hipError_t launch_scatter_field<T>(const Dev<T>&, int, const T*, hipStream_t);                    \
   template hipError_t launch_skin<T>(const Dev<T>&, int, const float*, const int32_t*, const float*, float*, \

@@ -139,18 +139,17 @@ struct Counts {
   bool contacts = false;
 };
 
-const int kStageItems[TB_COUNT] = {4, 256, 256, 28, 256, 256, 1024, 1024};
+const int kStageItems[TB_COUNT] = {4, 256, 28, 256, 1024, 1024, 256};
 
 int stage_items(const Counts& c, int stage) {
   switch (stage) {
     case TB_WAVES: return c.W;
-    case TB_PILLS: return c.P;
     case TB_CAPS: return c.contacts ? c.E : 0;
     case TB_SEARCH: return c.contacts ? c.E : 0;
-    case TB_CELLS: return c.contacts ? c.T : 0;
     case TB_PAIRS: return c.contacts ? c.cap : 0;
     case TB_SCAN_E: return c.contacts ? 9 * c.E : 0;
     case TB_SCAN_T: return c.contacts ? c.T : 0;
+    case TB_DET: return c.contacts ? std::max(c.P, std::max(c.T, c.E)) : 0;
     default: return 0;
   }
 }
@@ -464,11 +463,12 @@ viper_status batch_step(const BatchDev& b, bool collisions, double dt, int sub, 
     for (int i = 0; i < sub; ++i) {
       HIP_TRY(launch_predict<T>(b, h, st));
       if (collisions) HIP_TRY(launch_contact_detect<T>(b, st));
+      const ContactDev* cd = collisions ? b.cd : nullptr;
       for (int it = 0; it < iters; ++it) {
-        HIP_TRY(launch_rod_iteration<T>(b, h, st));
+        HIP_TRY(launch_rod_iteration<T>(b, h, cd, st));
         if (collisions) HIP_TRY(launch_contact_project<T>(b, st));
       }
-      HIP_TRY(launch_velocity<T>(b, h, st));
+      HIP_TRY(launch_velocity<T>(b, h, cd, st));
     }
   } else {
     return fail(VIPER_ERR_INVALID, "unknown mode");

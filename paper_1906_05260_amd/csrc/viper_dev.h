@@ -78,6 +78,26 @@ struct ContactDev {
   int32_t* status = nullptr;          // the scene's status words
 };
 
+// End of a Jacobi contact pass, for pill p: add the average of the fixed-point sums of its
+// contact corrections (position and scale, 2^-44 per unit) and clear the sums.  Returns
+// whether the pill had an active contact.
+template <class T>
+__device__ __forceinline__ bool contact_apply(const ContactDev& c, int p, T& x0, T& x1, T& x2, T& s) {
+  const int n = c.acnt[p];
+  if (n == 0) return false;
+  unsigned long long* a = c.acc + 4 * (size_t)p;
+  const double inv = 1.0 / (double)n;
+  const double ax = (double)(long long)a[0] * 0x1p-44, ay = (double)(long long)a[1] * 0x1p-44;
+  const double az = (double)(long long)a[2] * 0x1p-44, as = (double)(long long)a[3] * 0x1p-44;
+  x0 = (T)((double)x0 + inv * ax);
+  x1 = (T)((double)x1 + inv * ay);
+  x2 = (T)((double)x2 + inv * az);
+  s = (T)((double)s + inv * as);
+  a[0] = 0ull; a[1] = 0ull; a[2] = 0ull; a[3] = 0ull;
+  c.acnt[p] = 0;
+  return true;
+}
+
 // A batch of scenes advanced by the same launches.  Each launch's grid is described by a
 // block table: block b works on scene tab[b].scene, items tab[b].base + [0, block size).
 // Every scene's item range is padded to whole blocks, so a block never spans two scenes.
@@ -87,13 +107,12 @@ struct Blk {
 
 enum Stage {
   TB_WAVES = 0,   // 4 wavefronts (<= 512 pill slots) per block: rod kernels
-  TB_PILLS,       // 256 pills per block
   TB_CAPS,        // 256 capsules per block
   TB_SEARCH,      // 28 capsules per block, 9 threads each: neighbour search
-  TB_CELLS,       // 256 hash cells per block
   TB_PAIRS,       // 256 candidate-pair slots per block
   TB_SCAN_E,      // 1024 (capsule, neighbour column) counts per block (scans)
   TB_SCAN_T,      // 1024 cells per block
+  TB_DET,         // 256 of max(pills, cells, capsules) per block: start of contact detection
   TB_COUNT
 };
 
@@ -108,8 +127,10 @@ struct BatchDev {
 // Launchers over a batch (enqueue on `stream`, return hipError_t of the launches).
 template <class T> hipError_t launch_rod_frame(const BatchDev& b, int nsub, double h, int iters, hipStream_t st);
 template <class T> hipError_t launch_predict(const BatchDev& b, double h, hipStream_t st);
-template <class T> hipError_t launch_rod_iteration(const BatchDev& b, double h, hipStream_t st);
-template <class T> hipError_t launch_velocity(const BatchDev& b, double h, hipStream_t st);
+// With contacts (cd non-null) the rod iteration and the velocity update first apply each
+// pill's averaged corrections of the preceding contact pass (contact_apply).
+template <class T> hipError_t launch_rod_iteration(const BatchDev& b, double h, const ContactDev* cd, hipStream_t st);
+template <class T> hipError_t launch_velocity(const BatchDev& b, double h, const ContactDev* cd, hipStream_t st);
 template <class T> hipError_t launch_contact_detect(const BatchDev& b, hipStream_t st);
 template <class T> hipError_t launch_contact_project(const BatchDev& b, hipStream_t st);
 template <class T> hipError_t launch_gather_field(const Dev<T>& d, int which, T* out, hipStream_t st);
