@@ -38,9 +38,18 @@ PEAK_HBM = 8.0e12
 
 
 def kernel_source_hash():
+    """Hash of what the frame kernel is compiled from: its own definition in rod_kernels.hip,
+    the device headers it includes and the build flags (edits to other kernels of
+    rod_kernels.hip leave it unchanged)."""
+    csrc = os.path.join(ROOT, "paper_1906_05260_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("rod_kernels.hip", "rod_device.h"):
-        with open(os.path.join(ROOT, "paper_1906_05260_amd", "csrc", f), "rb") as fh:
+    with open(os.path.join(csrc, "rod_kernels.hip")) as fh:
+        src = fh.read()
+    i = src.index(" rod_frame_kernel(")
+    h.update(src[src.rfind("template <class T>", 0, i):src.index("\n}\n", i) + 3].encode())
+    for f in (os.path.join(csrc, "rod_device.h"), os.path.join(csrc, "viper_dev.h"),
+              os.path.join(ROOT, "paper_1906_05260_amd", "build.py")):
+        with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
