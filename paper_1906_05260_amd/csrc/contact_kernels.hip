@@ -35,7 +35,10 @@ constexpr int kSearchSub = 9;
 constexpr int kSearchCaps = 28;
 constexpr int kStage = 4;       // candidates per (capsule, column) kept by the count pass
 constexpr int kSortMax = 64;    // longest per-capsule candidate segment sorted in LDS
-constexpr int kChunk = 4;       // bucket entries whose loads are issued together
+constexpr int kWalkItems = 4;   // bucket entries per lane whose loads are issued together
+constexpr int kWaves = 4;       // wavefronts per search block
+constexpr int kCapsPerWave = 7; // capsules per wavefront (7 x 9 columns = 63 lanes)
+static_assert(kWaves * kCapsPerWave == kSearchCaps, "search block layout");
 
 __device__ __forceinline__ uint32_t cell_hash(int x, int y, int z, int T) {
   return ((uint32_t)x * 73856093u ^ (uint32_t)y * 19349663u ^ (uint32_t)z * 83492791u) & (uint32_t)(T - 1);
@@ -295,82 +298,131 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
     if (total > c.cap) c.status[ST_OVERFLOW] = 1;
     c.maxr[0] = 0ull;
   }
-  const int q = (int)threadIdx.x / kSearchSub, sub = (int)threadIdx.x % kSearchSub;
+  // Each wavefront holds 7 whole capsules x 9 columns (lane 63 idles): a capsule's columns
+  // and the balanced walk below stay inside one wavefront.
+  const int wv = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+  const int q = wv * kCapsPerWave + lane / kSearchSub, sub = lane % kSearchSub;
   const int jh = blk.base + q;                      // bucket position of the home capsule
-  const bool live = q < kSearchCaps && jh < c.E;
-  int a = 0;
-  int32_t* stg = nullptr;
-  int have = 0;
+  const bool live = lane < kCapsPerWave * kSearchSub && jh < c.E;
+  int a = 0, have = 0;
   if (live) {
     a = c.sorted[jh];
-    stg = c.stage + (size_t)kStage * (kSearchSub * (size_t)a + sub);
     if (EMIT) have = c.pcount[kSearchSub * (size_t)a + sub];
   }
+  const int col = kSearchSub * a + sub;             // this lane's (capsule, column) slot
   if (EMIT && live && have <= kStage) {
     // the count pass kept every candidate of this column: copy them
-    const int base = c.poff[kSearchSub * (size_t)a + sub];
+    const int32_t* stg = c.stage + (size_t)kStage * col;
+    const int base = c.poff[col];
     for (int k = 0; k < have; ++k)
       if (base + k < c.cap) c.pairs[2 * (size_t)(base + k) + 1] = stg[k];
-  } else if (live) {
-    const double sa[4] = {c.ssph[4 * (size_t)jh], c.ssph[4 * (size_t)jh + 1], c.ssph[4 * (size_t)jh + 2],
-                          c.ssph[4 * (size_t)jh + 3]};
-    const int ra = c.srg[2 * (size_t)jh], ga = c.srg[2 * (size_t)jh + 1];
-    const int cx = c.cell[3 * (size_t)a], cy = c.cell[3 * (size_t)a + 1], cz = c.cell[3 * (size_t)a + 2];
-    const int ny = cy + sub % 3 - 1, nz = cz + sub / 3 - 1;
-    const int base = EMIT ? c.poff[kSearchSub * (size_t)a + sub] : 0;
-    // The three cells of this column: bucket, group bounds and range, loaded together.
-    uint32_t hc[3];
-    int gmn[3], gmx[3], js[3], je[3];
+  }
+  // Columns to walk: all of them in the count pass, those with more than kStage candidates
+  // in the emit pass.  A lane lists its column's three cells (a bucket whose entries all
+  // share the capsule's group is left out) ...
+  __shared__ int s_off[kWaves][65];
+  __shared__ int s_cnt[kWaves][64];
+  __shared__ int s_col[kWaves][64][12];   // js0 js1 js2, cum1 cum2, cx ny nz, a ra ga, out
+  __shared__ double s_sph[kWaves][64][4];
+  int w = 0;
+  {
+    int js[3] = {0, 0, 0}, ln[3] = {0, 0, 0}, cx = 0, ny = 0, nz = 0, ra = 0, ga = 0;
+    double sa[4] = {0.0, 0.0, 0.0, 0.0};
+    if (live && (!EMIT || have > kStage)) {
 #pragma unroll
-    for (int d = 0; d < 3; ++d) hc[d] = cell_hash(cx + d - 1, ny, nz, c.T);
+      for (int k = 0; k < 4; ++k) sa[k] = c.ssph[4 * (size_t)jh + k];
+      ra = c.srg[2 * (size_t)jh]; ga = c.srg[2 * (size_t)jh + 1];
+      cx = c.cell[3 * (size_t)a];
+      ny = c.cell[3 * (size_t)a + 1] + sub % 3 - 1;
+      nz = c.cell[3 * (size_t)a + 2] + sub / 3 - 1;
+      uint32_t hc[3];
+      int gmn[3], gmx[3], je[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      gmn[d] = c.cgmin[hc[d]]; gmx[d] = c.cgmax[hc[d]];
-      js[d] = c.cell_start[hc[d]]; je[d] = c.cell_start[hc[d] + 1];
+      for (int d = 0; d < 3; ++d) hc[d] = cell_hash(cx + d - 1, ny, nz, c.T);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        gmn[d] = c.cgmin[hc[d]]; gmx[d] = c.cgmax[hc[d]];
+        js[d] = c.cell_start[hc[d]]; je[d] = c.cell_start[hc[d] + 1];
+      }
+#pragma unroll
+      for (int d = 0; d < 3; ++d) ln[d] = (gmn[d] == ga && gmx[d] == ga) ? 0 : je[d] - js[d];
     }
-    int cnt = 0;
-    for (int d = 0; d < 3; ++d) {
-      if (gmn[d] == ga && gmx[d] == ga) continue;   // every entry is in this capsule's group
-      const long long nk = pack_cell(cx + d - 1, ny, nz);
-      const int j1 = je[d];
-      // kChunk bucket entries per round: every load of the chunk is issued before any test
-      // (indices past the end re-read the last entry and are masked), in ascending j order.
-      for (int j = js[d]; j < j1; j += kChunk) {
-        int bb[kChunk], rr[kChunk], gg[kChunk];
-        long long kk[kChunk];
-        double2 s01[kChunk], s23[kChunk];
+    w = ln[0] + ln[1] + ln[2];
+    int* sc = s_col[wv][lane];
+    sc[0] = js[0]; sc[1] = js[1]; sc[2] = js[2]; sc[3] = ln[0]; sc[4] = ln[0] + ln[1];
+    sc[5] = cx; sc[6] = ny; sc[7] = nz; sc[8] = a; sc[9] = ra; sc[10] = ga;
+    sc[11] = EMIT ? (live ? c.poff[col] : 0) : col;
 #pragma unroll
-        for (int u = 0; u < kChunk; ++u) {
-          const size_t jj = (size_t)min(j + u, j1 - 1);
-          bb[u] = c.sorted[jj];
-          kk[u] = c.skey[jj];
-          const int2 rg = ((const int2*)c.srg)[jj];
-          rr[u] = rg.x; gg[u] = rg.y;
-          s01[u] = ((const double2*)c.ssph)[2 * jj];
-          s23[u] = ((const double2*)c.ssph)[2 * jj + 1];
-        }
+    for (int k = 0; k < 4; ++k) s_sph[wv][lane][k] = sa[k];
+    s_cnt[wv][lane] = 0;
+  }
+  // ... and the wavefront walks the concatenation of its lanes' lists 64 entries at a time
+  // (a lane finds the column of its entry by binary search over the exclusive prefix sums),
+  // so that lanes stay busy however unevenly the entries fall on columns.
+  int incl = w;
 #pragma unroll
-        for (int u = 0; u < kChunk; ++u) {
-          if (j + u >= j1) break;
-          const int b = bb[u];
-          if (b <= a) continue;
-          if (kk[u] != nk) continue;     // a bucket entry of another cell (hash collision)
-          if (rr[u] == ra || gg[u] == ga) continue;
-          const double sb[4] = {s01[u].x, s01[u].y, s23[u].x, s23[u].y};
-          if (!spheres_overlap(sa, sb)) continue;
-          if (EMIT) {
-            const int idx = base + cnt;
-            if (idx < c.cap) c.pairs[2 * (size_t)idx + 1] = b;   // capsule index for now
-          } else if (cnt < kStage) {
-            stg[cnt] = b;
-          }
-          ++cnt;
-        }
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(incl, o);
+    if (lane >= o) incl += t;
+  }
+  s_off[wv][lane] = incl - w;
+  if (lane == 63) s_off[wv][64] = incl;
+  __syncthreads();
+  const int W = s_off[wv][64];
+  for (int g0 = 0; g0 < W; g0 += 64 * kWalkItems) {
+    int own[kWalkItems], jj[kWalkItems], dd[kWalkItems], bb[kWalkItems], rr[kWalkItems], gg[kWalkItems];
+    long long kk[kWalkItems];
+    double2 s01[kWalkItems], s23[kWalkItems];
+#pragma unroll
+    for (int u = 0; u < kWalkItems; ++u) {
+      const int g = g0 + 64 * u + lane;
+      int lo = 0, hi = 64;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (s_off[wv][mid] <= g) lo = mid; else hi = mid;
+      }
+      const int* sc = s_col[wv][lo];
+      const int k = g - s_off[wv][lo];
+      own[u] = g < W ? lo : -1;
+      dd[u] = k < sc[3] ? 0 : (k < sc[4] ? 1 : 2);
+      jj[u] = dd[u] == 0 ? sc[0] + k : (dd[u] == 1 ? sc[1] + k - sc[3] : sc[2] + k - sc[4]);
+      if (g >= W) jj[u] = 0;          // past the end: a harmless in-bounds read, masked below
+    }
+#pragma unroll
+    for (int u = 0; u < kWalkItems; ++u) {
+      const size_t j = (size_t)jj[u];
+      bb[u] = c.sorted[j];
+      kk[u] = c.skey[j];
+      const int2 rg = ((const int2*)c.srg)[j];
+      rr[u] = rg.x; gg[u] = rg.y;
+      s01[u] = ((const double2*)c.ssph)[2 * j];
+      s23[u] = ((const double2*)c.ssph)[2 * j + 1];
+    }
+#pragma unroll
+    for (int u = 0; u < kWalkItems; ++u) {
+      const int o = own[u];
+      if (o < 0) continue;
+      const int* sc = s_col[wv][o];
+      const int b = bb[u];
+      if (b <= sc[8]) continue;
+      if (kk[u] != pack_cell(sc[5] + dd[u] - 1, sc[6], sc[7])) continue;   // another cell (hash collision)
+      if (rr[u] == sc[9] || gg[u] == sc[10]) continue;
+      const double sb[4] = {s01[u].x, s01[u].y, s23[u].x, s23[u].y};
+      if (!spheres_overlap(s_sph[wv][o], sb)) continue;
+      const int pos = atomicAdd(&s_cnt[wv][o], 1);
+      if (EMIT) {
+        const int idx = sc[11] + pos;
+        if (idx < c.cap) c.pairs[2 * (size_t)idx + 1] = b;   // capsule index for now
+      } else if (pos < kStage) {
+        c.stage[(size_t)kStage * sc[11] + pos] = b;
       }
     }
-    if (!EMIT) c.pcount[kSearchSub * (size_t)a + sub] = cnt;
   }
-  if (!EMIT) return;
+  __syncthreads();
+  if (!EMIT) {
+    if (live) c.pcount[col] = s_cnt[wv][lane];
+    return;
+  }
   // Sort each capsule's segment by b and store capsule ids (first pill of each capsule).
   // A segment of up to kSortMax entries is ranked in LDS by the capsule's 9 threads: its
   // entries are distinct capsules, so rank = number of smaller entries is a permutation.

@@ -95,6 +95,44 @@ def test_contact_substep_parity_fp32():
     assert ex < 1e-4 and es < 1e-4 and eq < 1e-4
 
 
+def crowd_scene(seed=11):
+    """80 two-pill rods through one point (every pair of their capsules overlaps) plus 40
+    scattered rods; every rod is its own collision group except every tenth pair of
+    neighbours, which share one."""
+    rng = np.random.default_rng(seed)
+    centre = np.array([0.1, 0.2, -0.05])
+    pos = []
+    for k in range(120):
+        u = rng.normal(size=3)
+        u /= np.linalg.norm(u)
+        m = centre + (rng.normal(0.0, 3e-4, 3) if k < 80 else rng.uniform(-0.03, 0.03, 3))
+        pos += [m + 0.005 * u, m - 0.005 * u]
+    R = 120
+    group = np.arange(R, dtype=np.int32)
+    group[1::10] = group[0::10]
+    desc = scenes.SceneDesc(np.arange(0, 2 * R + 1, 2, dtype=np.int32), np.asarray(pos), np.full(2 * R, 0.003),
+                            np.zeros(2 * R, np.uint8), np.ones(R), np.full((R, 4), 1e-6), group, collisions=True,
+                            name="crowd")
+    return desc
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_crowded_cell_pair_set(prec):
+    """Capsules whose neighbour columns hold far more than the staged candidates, and home
+    capsules with more than the 64 candidates ranked in LDS: the exact brute-force set."""
+    desc = crowd_scene()
+    say("case: crowd", prec, desc.num_pills)
+    sc = viper.Scene(desc, prec, capacity=64)
+    sc.step(1e-3, 1, 1)
+    sc.sync()
+    got = sc.contacts()
+    ref = oracle_pairs(desc, sc)
+    per_a = np.bincount(ref[:, 0]) if len(ref) else np.zeros(1)
+    say("pairs", len(got), len(ref), "most candidates of one capsule", int(per_a.max()))
+    assert per_a.max() > 64
+    assert np.array_equal(got, ref)
+
+
 def test_full_muscle_scene_pair_set_and_overflow_flag():
     """The ~50k-pill muscle scene: exact candidate set after a frame; a tiny capacity
     raises the overflow status instead of writing out of bounds."""
