@@ -299,10 +299,13 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
     c.maxr[0] = 0ull;
   }
   // Each wavefront holds 7 whole capsules x 9 columns (lane 63 idles): a capsule's columns
-  // and the balanced walk below stay inside one wavefront.
+  // and the balanced walk below stay inside one wavefront.  Wavefront w of the scene takes
+  // bucket positions w, w + n, ..., w + 6n (n = the scene's wavefronts): capsules of one
+  // crowded cell, adjacent in bucket order, land in different wavefronts.
   const int wv = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
   const int q = wv * kCapsPerWave + lane / kSearchSub, sub = lane % kSearchSub;
-  const int jh = blk.base + q;                      // bucket position of the home capsule
+  const int nwave = kWaves * ((c.E + kSearchCaps - 1) / kSearchCaps);
+  const int jh = blk.base / kCapsPerWave + wv + nwave * (lane / kSearchSub);   // home capsule's bucket position
   const bool live = lane < kCapsPerWave * kSearchSub && jh < c.E;
   int a = 0, have = 0;
   if (live) {
