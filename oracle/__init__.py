@@ -67,6 +67,10 @@ def lib():
         L.orc_capsule_transforms.argtypes = [P, P]
         L.orc_set_masses.argtypes = [P, P, P, P]
         L.orc_contact_pass.argtypes = [P, I, D]
+        L.orc_set_sections.argtypes = [P, I, P, P]
+        L.orc_section_fit.argtypes = [P, I, P]
+        L.orc_bundle.argtypes = [P]
+        L.orc_extract_rotation.argtypes = [P, P, P]
         L.orc_grad.restype = D
         L.orc_grad.argtypes = [I, P, P, P, P, P, P, P, D, P, D, I, I, I, P, P, P, I, I]
         _lib = L
@@ -80,6 +84,15 @@ def _p(a):
 def _f64(a, n=None):
     a = np.ascontiguousarray(a, dtype=np.float64)
     return a
+
+
+def extract_rotation(A, q0=(0.0, 0.0, 0.0, 1.0)):
+    """The oracle's rotation extraction (Mueller et al. 2016 iteration) of a 3x3 matrix."""
+    A = np.ascontiguousarray(A, dtype=np.float64).reshape(9)
+    q0 = np.ascontiguousarray(q0, dtype=np.float64)
+    q = np.zeros(4)
+    lib().orc_extract_rotation(_p(A), _p(q0), _p(q))
+    return q
 
 
 class OracleScene:
@@ -103,6 +116,21 @@ class OracleScene:
         self.num_rods = int(desc.num_rods)
         self.h = L.orc_create(1 if precision == "f64" else 0, self.num_rods, _p(off), _p(rp), _p(rr), _p(pn),
                               _p(ac), _p(co), _p(gr), float(desc.density), _p(g))
+
+        if getattr(desc, "section_offsets", None) is not None:
+            self._sec = (np.ascontiguousarray(desc.section_offsets, dtype=np.int32),
+                         np.ascontiguousarray(desc.section_pills, dtype=np.int32))
+            L.orc_set_sections(self.h, int(self._sec[0].shape[0] - 1), _p(self._sec[0]), _p(self._sec[1]))
+
+    def section_fit(self, k):
+        """Bundling fit of section k at the current state (Sec. 7.3): (R*, s*, c*, q*)."""
+        out = np.zeros(17)
+        lib().orc_section_fit(self.h, int(k), _p(out))
+        return out[:9].reshape(3, 3), float(out[9]), out[10:13].copy(), out[13:17].copy()
+
+    def bundle(self):
+        """One bundling projection of every section at the current state."""
+        lib().orc_bundle(self.h)
 
     def __del__(self):
         if getattr(self, "h", None):

@@ -35,6 +35,7 @@
 #include <cstring>
 #include <limits>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 namespace orc {
@@ -248,6 +249,10 @@ template <class R> struct Scene {
   std::vector<Q4<R>> qprev;
   std::vector<R> lam;          // [slot*8]: ss(3) vol(1) sg(1) bt(3)
   // contacts
+  // bundling (Sec. 7.3): cross-sections as lists of pills, and each section's rotation of the
+  // previous substep (the start of the next rotation extraction)
+  std::vector<int> sec_off, sec_pill;
+  std::vector<Q4<double>> sec_q;
   std::vector<int32_t> pairs;  // sorted (a, b), a < b, capsule id = first pill of the edge
   std::vector<int> active_count; // number of active contacts in the last contact pass
   int64_t projections = 0;     // count of rod + active contact projections performed
@@ -687,9 +692,125 @@ template <class R> void velocity_rods(Scene<R>& S, R h, int r0, int r1) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Scale-invariant shape matching of a muscle cross-section ("bundling", Sec. 7.3).
+// Each pill i of a section carries a similarity transform T_i = [s_i R_i | x_i]; the
+// section is fitted with one global similarity T* of its rest transforms (Umeyama),
+// and then every T_i is set to T* Tbar_i.  Readings (the paper gives the energy and the
+// fit, not where the step sits or what a rod's last pill contributes):
+//   - the projection runs once per substep, after the constraint iterations and before
+//     the velocity update; every section is fitted from the same state, then applied;
+//   - R_i is the rotation of the edge that starts at pill i; the last pill of a rod
+//     (no edge of its own) contributes the rotation of its incoming edge, and only its
+//     position and scale are set;
+//   - rest transforms: scale 1, rest frames qrest, rest positions;
+//   - pinned pills keep their position (pins fix position only); scale and rotation
+//     are set as for any pill;
+//   - the optimal rotation is extracted with the iteration of Mueller et al. 2016,
+//     started from the section's rotation of the previous substep (identity at first),
+//     at most 20 steps, stopping when the update angle falls below 1e-9.
+// ---------------------------------------------------------------------------
+struct SectionFit { M3<double> R; Q4<double> q; double s; V3<double> c; };
+
+inline M3<double> qmat_d(const Q4<double>& q) { return qmat(q); }
+
+// Rotation that maximises trace(R^T A) (= argmin_R |R - A|_F over SO(3)), by the
+// iteration of Mueller et al. 2016: rotate by the axis-angle vector
+// sum_k r_k x a_k / (|sum_k r_k . a_k| + 1e-9) (r_k, a_k the columns of R and A).
+inline Q4<double> extract_rotation(const M3<double>& A, Q4<double> q) {
+  for (int it = 0; it < 20; ++it) {
+    M3<double> Rm = qmat(q);
+    V3<double> num = v3<double>(0, 0, 0);
+    double den = 0;
+    for (int k = 0; k < 3; ++k) {
+      V3<double> r = v3<double>(Rm.m[0][k], Rm.m[1][k], Rm.m[2][k]);
+      V3<double> a = v3<double>(A.m[0][k], A.m[1][k], A.m[2][k]);
+      num = num + cross(r, a);
+      den += dot(r, a);
+    }
+    V3<double> om = (1.0 / (std::fabs(den) + 1e-9)) * num;
+    double w = norm(om);
+    if (w < 1e-9) break;
+    double sh = std::sin(0.5 * w) / w;
+    q = qnormalize(qmul(q4<double>(sh * om.x, sh * om.y, sh * om.z, std::cos(0.5 * w)), q));
+  }
+  return q;
+}
+
+// The pill's transform: rotation of its edge, or of its incoming edge for a rod's last pill.
+template <class R> int section_edge(const Scene<R>& S, int p) { return S.has_edge(p) ? p : p - 1; }
+
+template <class R> SectionFit fit_section(const Scene<R>& S, int k) {
+  const int i0 = S.sec_off[k], i1 = S.sec_off[k + 1];
+  const double n = double(i1 - i0);
+  V3<double> mu = v3<double>(0, 0, 0), mub = v3<double>(0, 0, 0);
+  for (int i = i0; i < i1; ++i) {
+    const int p = S.sec_pill[i];
+    mu = mu + v3<double>(val(S.x[p].x), val(S.x[p].y), val(S.x[p].z));
+    mub = mub + S.xrest[p];
+  }
+  mu = (1.0 / n) * mu;
+  mub = (1.0 / n) * mub;
+  // A = sum_i [s_i R_i | x_i - mu] [sbar_i Rbar_i | xbar_i - mubar]^T,
+  // D = sum_i |[sbar_i Rbar_i | xbar_i - mubar]|_F^2
+  M3<double> A = mzero<double>();
+  double D = 0;
+  for (int i = i0; i < i1; ++i) {
+    const int p = S.sec_pill[i], e = section_edge(S, p);
+    const Q4<double> qe = q4<double>(val(S.q[e].x), val(S.q[e].y), val(S.q[e].z), val(S.q[e].w));
+    const Q4<double> qb = q4<double>(val(S.qrest[e].x), val(S.qrest[e].y), val(S.qrest[e].z), val(S.qrest[e].w));
+    const M3<double> Ri = qmat(qe), Rb = qmat(qb);
+    const double si = val(S.s[p]), sb = 1.0;
+    const V3<double> d = v3<double>(val(S.x[p].x), val(S.x[p].y), val(S.x[p].z)) - mu;
+    const V3<double> db = S.xrest[p] - mub;
+    const double dv[3] = {d.x, d.y, d.z}, dbv[3] = {db.x, db.y, db.z};
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        double acc = dv[r] * dbv[c];
+        for (int t = 0; t < 3; ++t) acc += (si * Ri.m[r][t]) * (sb * Rb.m[c][t]);
+        A.m[r][c] += acc;
+      }
+    D += 3.0 * sb * sb + dot(db, db);
+  }
+  SectionFit F;
+  F.q = extract_rotation(A, S.sec_q[k]);
+  F.R = qmat(F.q);
+  // s* = sum_i <R* Bbar_i, B_i>_F / D  =  trace(R*^T A) / D
+  double num = 0;
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) num += F.R.m[r][c] * A.m[r][c];
+  F.s = num / D;
+  F.c = mu - F.s * mvec(F.R, mub);
+  return F;
+}
+
+template <class R> void bundle(Scene<R>& S) {
+  const int ns = int(S.sec_off.size()) - 1;
+  if (ns <= 0) return;
+  std::vector<SectionFit> fits(ns);
+  for (int k = 0; k < ns; ++k) fits[k] = fit_section(S, k);
+  for (int k = 0; k < ns; ++k) {
+    const SectionFit& F = fits[k];
+    S.sec_q[k] = F.q;
+    for (int i = S.sec_off[k]; i < S.sec_off[k + 1]; ++i) {
+      const int p = S.sec_pill[i];
+      if (S.winv[p] > R(0.0)) {
+        const V3<double> y = F.s * mvec(F.R, S.xrest[p]) + F.c;
+        S.x[p] = v3<R>(R(y.x), R(y.y), R(y.z));
+      }
+      S.s[p] = R(F.s * 1.0);
+      if (S.has_edge(p)) {
+        const Q4<double> qb = q4<double>(val(S.qrest[p].x), val(S.qrest[p].y), val(S.qrest[p].z), val(S.qrest[p].w));
+        const Q4<double> qn = qnormalize(qmul(F.q, qb));
+        S.q[p] = q4<R>(R(qn.x), R(qn.y), R(qn.z), R(qn.w));
+      }
+    }
+  }
+}
+
 template <class R> void substep(Scene<R>& S, R h, int iters, bool collide, int search_iters, double delta, int threads) {
   R ih2 = R(1.0) / (h * h);
-  if (!collide && threads > 1 && S.nrods > 1) {
+  if (!collide && threads > 1 && S.nrods > 1 && S.sec_off.size() < 2) {
     int nt = std::min(threads, S.nrods);
     std::vector<std::thread> pool;
     std::vector<int64_t> proj(nt, 0);
@@ -712,6 +833,7 @@ template <class R> void substep(Scene<R>& S, R h, int iters, bool collide, int s
     S.projections += solve_colours(S, ih2, 0, S.nrods);
     if (collide) project_contacts(S, search_iters, delta);
   }
+  if constexpr (std::is_floating_point<R>::value) bundle(S);
   velocity_rods(S, h, 0, S.nrods);
 }
 
@@ -804,6 +926,12 @@ template <class R> static void get_state_t(const Scene<R>& S, double* x, double*
   }
 }
 
+template <class R> static void set_sections_t(Scene<R>& S, int nsec, const int32_t* off, const int32_t* pill) {
+  S.sec_off.assign(off, off + nsec + 1);
+  S.sec_pill.assign(pill, pill + off[nsec]);
+  S.sec_q.assign(nsec, q4<double>(0, 0, 0, 1));
+}
+
 static Desc make_desc(int num_rods, const int32_t* off, const double* rest_pos, const double* rest_radius, const uint8_t* pinned,
                       const double* activation, const double* compliance, const int32_t* group, double density, const double* gravity) {
   Desc d;
@@ -846,6 +974,34 @@ void orc_set_state(void* hp, const double* x, const double* v, const double* s, 
 void orc_get_state(void* hp, double* x, double* v, double* s, double* sd, double* q, double* om) {
   Handle* h = (Handle*)hp;
   if (h->d) get_state_t(*h->d, x, v, s, sd, q, om); else get_state_t(*h->f, x, v, s, sd, q, om);
+}
+
+// Bundling cross-sections (Sec. 7.3): nsec sections, section k = pills sec_pill[sec_off[k]..sec_off[k+1]).
+void orc_set_sections(void* hp, int nsec, const int32_t* off, const int32_t* pill) {
+  Handle* h = (Handle*)hp;
+  if (h->d) set_sections_t(*h->d, nsec, off, pill); else set_sections_t(*h->f, nsec, off, pill);
+}
+// The fit of section k at the current state: R* (row-major 9), s*, c* (3), q* (4).
+void orc_section_fit(void* hp, int k, double* out) {
+  Handle* h = (Handle*)hp;
+  SectionFit F = h->d ? fit_section(*h->d, k) : fit_section(*h->f, k);
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) out[3 * r + c] = F.R.m[r][c];
+  out[9] = F.s; out[10] = F.c.x; out[11] = F.c.y; out[12] = F.c.z;
+  out[13] = F.q.x; out[14] = F.q.y; out[15] = F.q.z; out[16] = F.q.w;
+}
+// One bundling projection of every section at the current state.
+void orc_bundle(void* hp) {
+  Handle* h = (Handle*)hp;
+  if (h->d) bundle(*h->d); else bundle(*h->f);
+}
+// Rotation extraction alone (A row-major, q0 = start quaternion x y z w): q out.
+void orc_extract_rotation(const double* A, const double* q0, double* q) {
+  M3<double> M;
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) M.m[r][c] = A[3 * r + c];
+  Q4<double> o = extract_rotation(M, q4<double>(q0[0], q0[1], q0[2], q0[3]));
+  q[0] = o.x; q[1] = o.y; q[2] = o.z; q[3] = o.w;
 }
 
 // One frame = `substeps` substeps of h = dt / substeps.  Returns projections performed.

@@ -35,6 +35,9 @@ class SceneDesc:
     collisions: bool = False
     name: str = ""
     extra: dict = field(default_factory=dict)
+    # bundling cross-sections (Sec. 7.3): section k = pills section_pills[section_offsets[k]:section_offsets[k+1]]
+    section_offsets: np.ndarray = None  # int32 [S+1]
+    section_pills: np.ndarray = None    # int32
 
     @property
     def num_rods(self) -> int:
@@ -147,7 +150,7 @@ MUSCLE_COMPLIANCE = (1e-7, 1e-8, 1e-8, 1e-5)     # stretch-shear, volume, scale 
 
 
 def muscle_scene(num_muscles=64, seed=2, target_pills=(45000, 55000), rods_range=(16, 48), pills_range=(8, 24),
-                 mesh_vertices=200000, spacing=0.01, compliance=MUSCLE_COMPLIANCE):
+                 mesh_vertices=200000, spacing=0.01, compliance=MUSCLE_COMPLIANCE, bundling=False):
     """Bundles of parallel rods ("muscles") packed side by side so that neighbours touch.
 
     Each muscle has U{16..48} rods of U{8..24} pills (all rods of a muscle share the
@@ -159,7 +162,8 @@ def muscle_scene(num_muscles=64, seed=2, target_pills=(45000, 55000), rods_range
     its volume, and with volume or scale-gradient compliances near 1e-4 the activation
     step drives some scales through zero (negative radii) within the first frames;
     ``compliance="loguniform"`` draws them log-uniform 1e-8..1e-4 per type and rod as
-    in the helix scene.  Returns (desc, mesh) with a skinning mesh of ``mesh_vertices`` vertices
+    in the helix scene.  With ``bundling`` every muscle gets one cross-section per pill
+    index (that pill of each of its rods) for the shape matching of Sec. 7.3.  Returns (desc, mesh) with a skinning mesh of ``mesh_vertices`` vertices
     on the muscles' envelopes, 4 nearest capsules each, Dirichlet(1,1,1,1) weights.
     """
     rng = np.random.default_rng(seed)
@@ -215,6 +219,16 @@ def muscle_scene(num_muscles=64, seed=2, target_pills=(45000, 55000), rods_range
                      name="muscles_%d" % num_muscles)
     mesh = muscle_mesh(desc, muscle_info, mesh_vertices, rng) if mesh_vertices else None
     desc.extra["muscles"] = muscle_info
+    if bundling:
+        # one cross-section per pill index of each muscle: pill k of every rod of the muscle
+        offs = np.asarray(desc.rod_offsets)
+        so, sp = [0], []
+        for mi in muscle_info:
+            for k in range(int(offs[mi["rods"][0] + 1] - offs[mi["rods"][0]])):
+                sp.extend(int(offs[r]) + k for r in mi["rods"])
+                so.append(len(sp))
+        desc.section_offsets = np.asarray(so, np.int32)
+        desc.section_pills = np.asarray(sp, np.int32)
     return desc, mesh
 
 

@@ -562,3 +562,177 @@ def test_fp32_dual_gradient_is_the_fp64_gradient_rounded():
     assert np.linalg.norm(r32 - r64) <= 1e-3 * np.linalg.norm(r64)
     assert np.linalg.norm(a32 - a64) <= 1e-3 * np.linalg.norm(a64)
     assert np.linalg.norm(r64) > 0 and np.linalg.norm(a64) > 0
+
+
+# ----------------------------------------------------------------------------- bundling (Sec. 7.3)
+
+def _qmat(q):
+    x, y, z, w = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+def _qmul(a, b):
+    ax, ay, az, aw = a
+    bx, by, bz, bw = b
+    return np.array([aw * bx + ax * bw + ay * bz - az * by, aw * by - ax * bz + ay * bw + az * bx,
+                     aw * bz + ax * by - ay * bx + az * bw, aw * bw - ax * bx - ay * by - az * bz])
+
+
+def _rand_quat(rng):
+    q = rng.normal(size=4)
+    return q / np.linalg.norm(q)
+
+
+def _bundled(seed=5, n=3):
+    desc, _ = scenes.muscle_scene(num_muscles=n, seed=seed, target_pills=None, mesh_vertices=0, bundling=True)
+    return desc
+
+
+def _mat2quat(M):
+    """Unit quaternion (x y z w) of a rotation matrix (Shepperd's method)."""
+    t = np.trace(M)
+    if t > 0:
+        w = np.sqrt(1 + t) / 2
+        return np.array([(M[2, 1] - M[1, 2]) / (4 * w), (M[0, 2] - M[2, 0]) / (4 * w), (M[1, 0] - M[0, 1]) / (4 * w), w])
+    i = int(np.argmax(np.diag(M)))
+    j, k = (i + 1) % 3, (i + 2) % 3
+    r = np.sqrt(1 + M[i, i] - M[j, j] - M[k, k])
+    q = np.zeros(4)
+    q[i] = r / 2
+    q[j] = (M[j, i] + M[i, j]) / (2 * r)
+    q[k] = (M[k, i] + M[i, k]) / (2 * r)
+    q[3] = (M[k, j] - M[j, k]) / (2 * r)
+    return q
+
+
+def test_rotation_extraction_is_the_polar_factor():
+    """Mueller's iteration targets argmin |R - A|_F over SO(3), the polar factor
+    U diag(1,1,det) V^T of the SVD A = U S V^T (numpy): the polar factor is a fixed point
+    of the iteration, and from a start within 20 degrees (its use: warm-started from the
+    previous substep) it converges to the 1e-9 rad stopping rule for near-rotations, and
+    to 1e-4 within the 20-step budget for strongly distorted matrices (linear rate)."""
+    rng = np.random.default_rng(3)
+    for trial in range(60):
+        amp, tol = (0.05, 5e-9) if trial % 2 == 0 else (0.3, 1e-4)
+        R0 = _qmat(_rand_quat(rng))
+        A = R0 @ (np.eye(3) + amp * rng.normal(size=(3, 3))) * rng.uniform(0.5, 2.0)
+        U, _, Vt = np.linalg.svd(A)
+        P = U @ np.diag([1, 1, np.sign(np.linalg.det(U @ Vt))]) @ Vt
+        qp = _mat2quat(P)
+        assert np.abs(_qmat(oracle.extract_rotation(A, qp)) - P).max() < 1e-12
+        ax = rng.normal(size=3)
+        ax /= np.linalg.norm(ax)
+        ang = np.radians(rng.uniform(0.0, 20.0))
+        q0 = _qmul(np.array([*(np.sin(ang / 2) * ax), np.cos(ang / 2)]), qp)
+        err = np.abs(_qmat(oracle.extract_rotation(A, q0)) - P).max()
+        assert err < tol, (trial, err)
+
+
+def _set_similarity(o, desc, rest, R0, s0, t0, q0):
+    """State where every pill's transform is T0 Tbar_i (T0 = [s0 R0 | t0])."""
+    P = desc.num_pills
+    x = s0 * desc.rest_pos @ R0.T + t0
+    q = np.array([_qmul(q0, rest["qrest"][p]) for p in range(P)])
+    o.set_state(x=x, s=np.full(P, s0), q=q)
+
+
+def test_bundling_recovers_an_exact_similarity_and_is_then_a_fixed_point():
+    desc = _bundled()
+    rng = np.random.default_rng(7)
+    o = oracle.OracleScene(desc, "f64")
+    rest = o.rest()
+    q0 = _rand_quat(rng)
+    R0, s0, t0 = _qmat(q0), 0.9, np.array([0.02, -0.01, 0.03])
+    _set_similarity(o, desc, rest, R0, s0, t0, q0)
+    # rotations of ~2 rad need the start near the answer: the extraction is warm-started in use
+    for k in range(len(desc.section_offsets) - 1):
+        R, s, c, _ = o.section_fit(k)
+        # the extraction stops once its update falls below 1e-9 rad
+        assert abs(s - s0) < 1e-12 and np.abs(R - R0).max() < 1e-8 and np.abs(c - t0).max() < 1e-9 or \
+            np.trace(R.T @ R0) < 1.0     # (a start more than 90 degrees away may stop at a saddle)
+    o2 = oracle.OracleScene(desc, "f64")
+    q0 = _qmul(np.array([0.05, -0.03, 0.02, 1.0]) / np.linalg.norm([0.05, -0.03, 0.02, 1.0]), np.array([0, 0, 0, 1.0]))
+    R0 = _qmat(q0)
+    _set_similarity(o2, desc, rest, R0, s0, t0, q0)
+    before = o2.get_state()
+    for k in range(len(desc.section_offsets) - 1):
+        R, s, c, _ = o2.section_fit(k)
+        assert abs(s - s0) < 1e-12 and np.abs(R - R0).max() < 1e-8 and np.abs(c - t0).max() < 1e-9
+    o2.bundle()
+    after = o2.get_state()
+    for key in ("x", "s"):
+        assert np.abs(after[key] - before[key]).max() < 1e-9, key
+    qa, qb = after["q"], before["q"]
+    assert np.minimum(np.abs(qa - qb).max(axis=1), np.abs(qa + qb).max(axis=1)).max() < 1e-9
+
+
+def _shape_energy(desc, rest, st, k, R, s, c):
+    """E_shape of section k for the similarity [s R | c] (the paper's energy, 3x4 blocks)."""
+    off = np.asarray(desc.rod_offsets)
+    last = set((off[1:] - 1).tolist())
+    E = 0.0
+    for p in desc.section_pills[desc.section_offsets[k]:desc.section_offsets[k + 1]]:
+        e = p - 1 if p in last else p
+        Ti = np.hstack([st["s"][p] * _qmat(st["q"][e]), st["x"][p][:, None]])
+        Tb = np.hstack([1.0 * _qmat(rest["qrest"][e]), desc.rest_pos[p][:, None]])
+        TT = np.hstack([s * R @ Tb[:, :3], (s * R @ Tb[:, 3] + c)[:, None]])
+        E += ((TT - Ti) ** 2).sum()
+    return E
+
+
+def test_bundling_fit_minimises_the_shape_energy():
+    """From a perturbed state, every perturbation of the fitted T* (rotation, scale,
+    translation) raises E_shape: a dropped term, a transposed A or a wrong mean fails."""
+    desc = _bundled(seed=8)
+    rng = np.random.default_rng(2)
+    o = oracle.OracleScene(desc, "f64")
+    rest = o.rest()
+    o.step(1 / 60, 10, 4, collide=False)
+    P = desc.num_pills
+    st = o.get_state()
+    st["x"] = st["x"] + rng.normal(0, 2e-3, (P, 3))
+    st["s"] = st["s"] * rng.uniform(0.9, 1.1, P)
+    st["q"] = np.array([_qmul(np.array([*rng.normal(0, 0.05, 3), 1.0]) / np.linalg.norm([*rng.normal(0, 0.05, 3), 1.0]), q)
+                        for q in st["q"]])
+    st["q"] /= np.linalg.norm(st["q"], axis=1, keepdims=True)
+    o.set_state(x=st["x"], s=st["s"], q=st["q"])
+    st = o.get_state()
+    for k in rng.choice(len(desc.section_offsets) - 1, 6, replace=False):
+        R, s, c, _ = o.section_fit(k)
+        E0 = _shape_energy(desc, rest, st, k, R, s, c)
+        for _ in range(12):
+            dq = np.array([*rng.normal(0, 1e-3, 3), 1.0]); dq /= np.linalg.norm(dq)
+            E1 = _shape_energy(desc, rest, st, k, _qmat(dq) @ R, s * (1 + rng.normal(0, 1e-3)),
+                               c + rng.normal(0, 1e-4, 3))
+            assert E1 > E0
+        # translation: stationary at c* (central difference of E along each axis ~ 0)
+        for ax in range(3):
+            d = np.zeros(3); d[ax] = 1e-6
+            g = (_shape_energy(desc, rest, st, k, R, s, c + d) - _shape_energy(desc, rest, st, k, R, s, c - d)) / 2e-6
+            assert abs(g) < 1e-6 * max(1.0, E0)
+
+
+def test_bundling_sets_every_pill_to_the_fitted_transform():
+    desc = _bundled(seed=9)
+    o = oracle.OracleScene(desc, "f64")
+    rest = o.rest()
+    o.step(1 / 60, 10, 4, collide=False)
+    rng = np.random.default_rng(4)
+    st = o.get_state()
+    o.set_state(x=st["x"] + rng.normal(0, 1e-3, st["x"].shape), s=st["s"] * rng.uniform(0.95, 1.05, desc.num_pills))
+    before = o.get_state()
+    fits = [o.section_fit(k) for k in range(len(desc.section_offsets) - 1)]
+    o.bundle()
+    after = o.get_state()
+    off = np.asarray(desc.rod_offsets)
+    last = set((off[1:] - 1).tolist())
+    for k, (R, s, c, q) in enumerate(fits):
+        for p in desc.section_pills[desc.section_offsets[k]:desc.section_offsets[k + 1]]:
+            assert abs(after["s"][p] - s) < 1e-14
+            want = before["x"][p] if desc.pinned[p] else s * R @ desc.rest_pos[p] + c
+            assert np.abs(after["x"][p] - want).max() < 1e-13
+            if p not in last:
+                qq = _qmul(q, rest["qrest"][p])
+                assert np.minimum(np.abs(after["q"][p] - qq).max(), np.abs(after["q"][p] + qq).max()) < 1e-13
