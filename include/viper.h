@@ -69,6 +69,18 @@ typedef struct {
   int32_t precision;            /* viper_precision: storage and arithmetic type on the device */
   int32_t collisions;           /* nonzero = pill-pill contacts on */
   int32_t contact_capacity_per_capsule; /* candidate pairs per capsule reserved (<= 0: 16) */
+  /* Bundling (Sec. 7.3, scale-invariant shape matching of muscle cross-sections): section k
+   * is the pills section_pills[section_offsets[k] .. section_offsets[k+1]) (host arrays, read
+   * during create only; section_offsets[0] = 0, every section non-empty, no pill in two
+   * sections).  Once per substep, after the constraint iterations, each section is fitted
+   * with one similarity transform of its rest frames (current and rest frames [s R | x] of
+   * its pills; a rod's last pill takes the rotation of its incoming edge) and every pill is
+   * set to that transform of its rest frame; pinned pills keep their position.
+   * num_sections = 0 turns bundling off.  A scene with sections steps in
+   * VIPER_MODE_ITERATION or VIPER_MODE_GRAPH; the pool and the adjoint reject it. */
+  int32_t num_sections;
+  const int32_t* section_offsets;
+  const int32_t* section_pills;
 } viper_scene_desc;
 
 /* Bytes of device workspace the scene needs (host-only computation; validates the

@@ -567,6 +567,21 @@ __global__ void __launch_bounds__(256) contact_pair_kernel(const Dev<T>* __restr
   }
 }
 
+// Apply the last pass's averaged corrections now (before a bundling projection, which
+// reads and overwrites the state of its section pills); the velocity update then finds
+// nothing left to apply.
+template <class T>
+__global__ void __launch_bounds__(256) contact_flush_kernel(const Dev<T>* __restrict__ D, const ContactDev* __restrict__ CD,
+                                                            const Blk* __restrict__ tab) {
+  BLOCK_SCENE(tab, D, CD)
+  const int p = blk_.base + (int)threadIdx.x;
+  if (p >= c.P) return;
+  T x0 = d.px[p], x1 = d.py[p], x2 = d.pz[p], s = d.s[p];
+  if (contact_apply(c, p, x0, x1, x2, s)) {
+    d.px[p] = x0; d.py[p] = x1; d.pz[p] = x2; d.s[p] = s;
+  }
+}
+
 }  // namespace
 
 // ----------------------------------------------------------------------------- host side
@@ -714,6 +729,14 @@ hipError_t launch_contact_project(const BatchDev& b, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <class T>
+hipError_t launch_contact_flush(const BatchDev& b, hipStream_t st) {
+  if (b.nscenes == 0 || b.nblk[TB_DET] == 0) return hipSuccess;
+  hipLaunchKernelGGL(contact_flush_kernel<T>, dim3(b.nblk[TB_DET]), dim3(256), 0, st, (const Dev<T>*)b.dev, b.cd,
+                     b.tab[TB_DET]);
+  return hipGetLastError();
+}
+
 hipError_t contact_copy_det(const ContactDev& c, bool x, void* dst, int P, size_t ts, hipStream_t st) {
   return hipMemcpyAsync(dst, x ? (void*)c.xdet : c.sdet, (x ? 3 * 8 : ts) * (size_t)P, hipMemcpyDefault, st);
 }
@@ -737,5 +760,7 @@ template hipError_t launch_contact_detect<float>(const BatchDev&, hipStream_t);
 template hipError_t launch_contact_detect<double>(const BatchDev&, hipStream_t);
 template hipError_t launch_contact_project<float>(const BatchDev&, hipStream_t);
 template hipError_t launch_contact_project<double>(const BatchDev&, hipStream_t);
+template hipError_t launch_contact_flush<float>(const BatchDev&, hipStream_t);
+template hipError_t launch_contact_flush<double>(const BatchDev&, hipStream_t);
 
 }  // namespace viper

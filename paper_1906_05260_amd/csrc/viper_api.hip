@@ -59,6 +59,7 @@ struct Offsets {
   size_t edge_rest[18];    // ilb il0 cbt inert dbx dby dbz css cvol csg cbtc qrx qry qrz qrw mrx mry mrz
   size_t scratch[10];      // xpx xpy xpz spv qpx qpy qpz qpw i1 lam(8P)
   size_t flags, wave_start, status, stage, xform, anchor, rod_of, header;
+  size_t sec_off = 0, sec_pill = 0, sec_of = 0, sec_xr = 0, sec_q = 0, sec_fit = 0;   // bundling
   ContactOffsets contact;
   size_t total;
 };
@@ -72,6 +73,9 @@ struct Host {
   std::vector<double> x, rbar, winv, wsinv, anchor, xloc;
   std::vector<int32_t> rod_of;
   std::vector<double> ilb, il0, cbt, inert, db[3], cs[4], qr[4], mr[3];
+  // bundling sections: offsets, pills, section of each entry, world rest position of each entry
+  std::vector<int32_t> sec_off, sec_pill, sec_of;
+  std::vector<double> sec_xr;
 };
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0; }
@@ -111,6 +115,23 @@ viper_status validate(const viper_scene_desc* d) {
              dz = d->rest_pos[3 * p + 5] - d->rest_pos[3 * p + 2];
       if (!(dx * dx + dy * dy + dz * dz > 0)) return fail(VIPER_ERR_INVALID, "consecutive rest pills coincide");
     }
+  if (d->num_sections < 0) return fail(VIPER_ERR_INVALID, "num_sections < 0");
+  if (d->num_sections > 0) {
+    if (!d->section_offsets || !d->section_pills)
+      return fail(VIPER_ERR_INVALID, "section_offsets and section_pills are required");
+    if (d->section_offsets[0] != 0) return fail(VIPER_ERR_INVALID, "section_offsets[0] must be 0");
+    std::vector<uint8_t> used(P, 0);
+    for (int k = 0; k < d->num_sections; ++k) {
+      if (d->section_offsets[k + 1] <= d->section_offsets[k])
+        return fail(VIPER_ERR_INVALID, "section " + std::to_string(k) + " is empty");
+      for (int i = d->section_offsets[k]; i < d->section_offsets[k + 1]; ++i) {
+        const int p = d->section_pills[i];
+        if (p < 0 || p >= P) return fail(VIPER_ERR_INVALID, "section pill out of range");
+        if (used[p]) return fail(VIPER_ERR_INVALID, "pill " + std::to_string(p) + " is in two sections");
+        used[p] = 1;
+      }
+    }
+  }
   return VIPER_OK;
 }
 
@@ -135,11 +156,11 @@ int pack_waves(const viper_scene_desc* d, std::vector<int32_t>& ws) {
 
 // Per-scene item counts of every stage.
 struct Counts {
-  int W = 0, P = 0, E = 0, T = 0, cap = 0;
+  int W = 0, P = 0, E = 0, T = 0, cap = 0, S = 0, N = 0;   // ... bundling sections and entries
   bool contacts = false;
 };
 
-const int kStageItems[TB_COUNT] = {4, 256, 28, 256, 1024, 1024, 256};
+const int kStageItems[TB_COUNT] = {4, 256, 28, 256, 1024, 1024, 256, 4, 256};
 
 int stage_items(const Counts& c, int stage) {
   switch (stage) {
@@ -150,6 +171,8 @@ int stage_items(const Counts& c, int stage) {
     case TB_SCAN_E: return c.contacts ? 9 * c.E : 0;
     case TB_SCAN_T: return c.contacts ? c.T : 0;
     case TB_DET: return c.contacts ? std::max(c.P, std::max(c.T, c.E)) : 0;
+    case TB_SECT: return c.S;
+    case TB_SECP: return c.N;
     default: return 0;
   }
 }
@@ -207,8 +230,18 @@ Offsets make_layout(const viper_scene_desc* d, int P, int W, int E, int cap) {
   o.xform = L.take(4 * 12 * (size_t)P);      // skinning transforms
   o.anchor = L.take(8 * 3 * (size_t)std::max(d->num_rods, 1));
   o.rod_of = L.take(4 * (size_t)P);
+  const int NS = d->num_sections > 0 ? d->num_sections : 0, NP = NS ? d->section_offsets[NS] : 0;
+  if (NS) {
+    o.sec_off = L.take(4 * (size_t)(NS + 1));
+    o.sec_pill = L.take(4 * (size_t)NP);
+    o.sec_of = L.take(4 * (size_t)NP);
+    o.sec_xr = L.take(8 * 3 * (size_t)NP);
+    o.sec_q = L.take(8 * 4 * (size_t)NS);
+    o.sec_fit = L.take(8 * (size_t)kSecFit * NS);
+  }
   Counts c;
   c.W = W; c.P = P; c.E = E; c.T = contact_table_size(E); c.cap = cap * E; c.contacts = d->collisions != 0;
+  c.S = NS; c.N = NP;
   o.header = L.take(header_bytes(std::vector<Counts>{c}, d->precision == VIPER_F64 ? sizeof(Dev<double>) : sizeof(Dev<float>)));
   o.contact = contact_layout(L.off, d->collisions != 0, P, E, cap, d->precision == VIPER_F64);
   L.off = o.contact.end;
@@ -248,6 +281,18 @@ void build_host(const viper_scene_desc* d, Host& H) {
   for (int k = 0; k < H.R; ++k) H.group[k] = d->group ? d->group[k] : k;
   H.W = pack_waves(d, H.wave_start);
   H.x.assign(d->rest_pos, d->rest_pos + 3 * (size_t)P);
+  if (d->num_sections > 0) {
+    const int NS = d->num_sections, NP = d->section_offsets[NS];
+    H.sec_off.assign(d->section_offsets, d->section_offsets + NS + 1);
+    H.sec_pill.assign(d->section_pills, d->section_pills + NP);
+    H.sec_of.resize(NP);
+    H.sec_xr.resize(3 * (size_t)NP);
+    for (int k = 0; k < NS; ++k)
+      for (int i = H.sec_off[k]; i < H.sec_off[k + 1]; ++i) {
+        H.sec_of[i] = k;
+        for (int t = 0; t < 3; ++t) H.sec_xr[3 * (size_t)i + t] = H.x[3 * (size_t)H.sec_pill[i] + t];
+      }
+  }
   H.anchor.assign(3 * (size_t)H.R, 0.0);
   H.xloc.assign(3 * (size_t)P, 0.0);
   H.rod_of.assign(P, 0);
@@ -354,6 +399,7 @@ struct Skin {
 struct viper_scene_s {
   int precision = 0;
   int collisions = 0;
+  int nsec = 0, nsecp = 0;    // bundling sections and their entries
   int cap = 16;
   int R = 0, P = 0, W = 0, E = 0;
   int64_t proj_per_iter = 0;
@@ -402,6 +448,14 @@ void fill_dev(viper_scene_s* S, Dev<T>& d) {
   d.status = (int32_t*)(b + S->o.status);
   d.anchor = (const double*)(b + S->o.anchor);
   d.rod_of = (const int32_t*)(b + S->o.rod_of);
+  d.nsec = S->nsec;
+  d.nsecp = S->nsecp;
+  d.sec_off = S->nsec ? (const int32_t*)(b + S->o.sec_off) : nullptr;
+  d.sec_pill = S->nsec ? (const int32_t*)(b + S->o.sec_pill) : nullptr;
+  d.sec_of = S->nsec ? (const int32_t*)(b + S->o.sec_of) : nullptr;
+  d.sec_xr = S->nsec ? (const double*)(b + S->o.sec_xr) : nullptr;
+  d.sec_q = S->nsec ? (double*)(b + S->o.sec_q) : nullptr;
+  d.sec_fit = S->nsec ? (double*)(b + S->o.sec_fit) : nullptr;
 }
 
 template <class T>
@@ -440,6 +494,16 @@ viper_status upload(viper_scene_s* S, const Host& H, hipStream_t st) {
   HIP_TRY(hipMemcpyAsync(b + S->o.rod_of, H.rod_of.data(), 4 * (size_t)P, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(b + S->o.wave_start, H.wave_start.data(), 4 * H.wave_start.size(), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemsetAsync(b + S->o.status, 0, 4 * ST_WORDS, st));
+  if (S->nsec) {
+    std::vector<double> q0(4 * (size_t)S->nsec, 0.0);
+    for (int k = 0; k < S->nsec; ++k) q0[4 * (size_t)k + 3] = 1.0;     // first extraction starts at the identity
+    HIP_TRY(hipMemcpyAsync(b + S->o.sec_off, H.sec_off.data(), 4 * H.sec_off.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(b + S->o.sec_pill, H.sec_pill.data(), 4 * H.sec_pill.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(b + S->o.sec_of, H.sec_of.data(), 4 * H.sec_of.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(b + S->o.sec_xr, H.sec_xr.data(), 8 * H.sec_xr.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(b + S->o.sec_q, q0.data(), 8 * q0.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  }
   HIP_TRY(hipStreamSynchronize(st));   // the host staging vectors die with this frame
   return VIPER_OK;
 }
@@ -452,9 +516,10 @@ template <> Dev<double>& dev<double>(viper_scene_s* S) { return S->dd; }
 template <class T>
 viper_status batch_step(const BatchDev& b, bool collisions, double dt, int sub, int iters, int mode, hipStream_t st) {
   const double h = dt / sub;
-  if (mode == VIPER_MODE_AUTO) mode = collisions ? VIPER_MODE_ITERATION : VIPER_MODE_FRAME;
-  if (collisions && mode != VIPER_MODE_ITERATION)
-    return fail(VIPER_ERR_INVALID, "scenes with collisions step in VIPER_MODE_ITERATION");
+  const bool bundled = b.nblk[TB_SECT] > 0;
+  if (mode == VIPER_MODE_AUTO) mode = (collisions || bundled) ? VIPER_MODE_ITERATION : VIPER_MODE_FRAME;
+  if ((collisions || bundled) && mode != VIPER_MODE_ITERATION)
+    return fail(VIPER_ERR_INVALID, "scenes with collisions or bundling sections step in VIPER_MODE_ITERATION");
   if (mode == VIPER_MODE_FRAME) {
     HIP_TRY(launch_rod_frame<T>(b, sub, h, iters, st));
   } else if (mode == VIPER_MODE_SUBSTEP) {
@@ -467,6 +532,10 @@ viper_status batch_step(const BatchDev& b, bool collisions, double dt, int sub, 
       for (int it = 0; it < iters; ++it) {
         HIP_TRY(launch_rod_iteration<T>(b, h, cd, st));
         if (collisions) HIP_TRY(launch_contact_project<T>(b, st));
+      }
+      if (bundled) {      // shape matching of the cross-sections (Sec. 7.3) after the iterations
+        if (collisions) HIP_TRY(launch_contact_flush<T>(b, st));
+        HIP_TRY(launch_bundle<T>(b, st));
       }
       HIP_TRY(launch_velocity<T>(b, h, cd, st));
     }
@@ -508,7 +577,7 @@ viper_status capture_frame(viper_scene_s* S, double dt, int sub, int iters) {
 
 template <class T>
 viper_status step_t(viper_scene_s* S, double dt, int sub, int iters, int mode, hipStream_t st) {
-  if (mode == VIPER_MODE_AUTO && S->collisions) mode = VIPER_MODE_GRAPH;
+  if (mode == VIPER_MODE_AUTO && (S->collisions || S->nsec)) mode = VIPER_MODE_GRAPH;
   if (mode != VIPER_MODE_GRAPH) return batch_step<T>(S->batch, S->collisions != 0, dt, sub, iters, mode, st);
   if (!S->graph || S->graph_h != dt / sub || S->graph_sub != sub || S->graph_iters != iters) {
     viper_status r = capture_frame<T>(S, dt, sub, iters);
@@ -523,6 +592,7 @@ Counts scene_counts(const viper_scene_s* S) {
   c.W = S->W; c.P = S->P; c.E = S->E; c.T = S->collisions ? S->cd.T : contact_table_size(S->E);
   c.cap = S->collisions ? S->cd.cap : S->cap * S->E;
   c.contacts = S->collisions != 0;
+  c.S = S->nsec; c.N = S->nsecp;
   return c;
 }
 
@@ -563,6 +633,8 @@ viper_status viper_create_scene(const viper_scene_desc* desc, void* workspace, s
   viper_scene_s* S = new viper_scene_s();
   S->precision = desc->precision;
   S->collisions = desc->collisions != 0;
+  S->nsec = desc->num_sections > 0 ? desc->num_sections : 0;
+  S->nsecp = S->nsec ? desc->section_offsets[S->nsec] : 0;
   S->cap = cap;
   S->R = H.R; S->P = H.P; S->W = H.W; S->E = H.E;
   S->proj_per_iter = H.proj_per_iter;
@@ -734,6 +806,7 @@ namespace {
 viper_status adjoint_check(viper_scene S, int32_t frames, int32_t substeps, int32_t iterations) {
   if (!S) return fail(VIPER_ERR_INVALID, "scene is NULL");
   if (S->collisions) return fail(VIPER_ERR_INVALID, "the adjoint covers collision-free scenes");
+  if (S->nsec) return fail(VIPER_ERR_INVALID, "the adjoint does not cover bundling sections");
   if (frames < 1 || substeps < 1 || iterations < 0)
     return fail(VIPER_ERR_INVALID, "frames >= 1, substeps >= 1 and iterations >= 0 required");
   return VIPER_OK;
@@ -948,6 +1021,7 @@ viper_status viper_pool_create(void* workspace, size_t bytes, int32_t max_scenes
 viper_status viper_pool_admit(viper_pool P, const viper_scene_desc* desc, void* stream, int32_t* slot) {
   if (!P || !desc || !slot) return fail(VIPER_ERR_INVALID, "pool, desc and slot are required");
   if (desc->precision != P->precision) return fail(VIPER_ERR_INVALID, "scene precision differs from the pool's");
+  if (desc->num_sections > 0) return fail(VIPER_ERR_INVALID, "scenes with bundling sections are stepped with viper_step");
   size_t fp = 0;
   viper_status r = viper_scene_footprint(desc, &fp);
   if (r != VIPER_OK) return r;

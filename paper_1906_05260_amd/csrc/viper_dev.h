@@ -51,7 +51,14 @@ struct Dev {
   const double* anchor;      // [3*R]
   const int32_t* rod_of;     // [P]
   T gx, gy, gz;
+  // bundling cross-sections (Sec. 7.3): nsec sections over nsecp entries
+  int nsec, nsecp;
+  const int32_t *sec_off, *sec_pill, *sec_of;  // [nsec+1], [nsecp] pill, [nsecp] section of the entry
+  const double* sec_xr;      // [3*nsecp] world rest position of each entry
+  double* sec_q;             // [4*nsec] rotation of the last fit (start of the next extraction)
+  double* sec_fit;           // [kSecFit*nsec] R* (row-major), s*, c*, q*
 };
+constexpr int kSecFit = 20;
 
 // Contact buffers of one scene (device pointers into its workspace).
 struct ContactDev {
@@ -113,6 +120,8 @@ enum Stage {
   TB_SCAN_E,      // 1024 (capsule, neighbour column) counts per block (scans)
   TB_SCAN_T,      // 1024 cells per block
   TB_DET,         // 256 of max(pills, cells, capsules) per block: start of contact detection
+  TB_SECT,        // 4 bundling sections per block (one wavefront each)
+  TB_SECP,        // 256 bundling section entries per block
   TB_COUNT
 };
 
@@ -133,6 +142,10 @@ template <class T> hipError_t launch_rod_iteration(const BatchDev& b, double h, 
 template <class T> hipError_t launch_velocity(const BatchDev& b, double h, const ContactDev* cd, hipStream_t st);
 template <class T> hipError_t launch_contact_detect(const BatchDev& b, hipStream_t st);
 template <class T> hipError_t launch_contact_project(const BatchDev& b, hipStream_t st);
+// Apply the last contact pass's averaged corrections now (before a bundling projection).
+template <class T> hipError_t launch_contact_flush(const BatchDev& b, hipStream_t st);
+// Bundling projection of every section (fit, then apply).
+template <class T> hipError_t launch_bundle(const BatchDev& b, hipStream_t st);
 template <class T> hipError_t launch_gather_field(const Dev<T>& d, int which, T* out, hipStream_t st);
 template <class T> hipError_t launch_scatter_field(const Dev<T>& d, int which, const T* in, hipStream_t st);
 // Adjoint of the collision-free frame (single scene): checkpoint layout [substep][15][P].

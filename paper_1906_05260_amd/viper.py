@@ -57,6 +57,9 @@ class SceneDescC(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("collisions", ctypes.c_int32),
         ("contact_capacity_per_capsule", ctypes.c_int32),
+        ("num_sections", ctypes.c_int32),
+        ("section_offsets", ctypes.c_void_p),
+        ("section_pills", ctypes.c_void_p),
     ]
 
 
@@ -136,6 +139,12 @@ class _DescHolder:
         c.precision = F64 if precision in ("f64", F64) else F32
         c.collisions = int(bool(desc.collisions if collisions is None else collisions))
         c.contact_capacity_per_capsule = int(capacity)
+        if getattr(desc, "section_offsets", None) is not None:
+            a["soff"] = np.ascontiguousarray(desc.section_offsets, np.int32)
+            a["spill"] = np.ascontiguousarray(desc.section_pills, np.int32)
+            c.num_sections = int(a["soff"].shape[0] - 1)
+            c.section_offsets = a["soff"].ctypes.data
+            c.section_pills = a["spill"].ctypes.data
         self.c = c
 
 

@@ -1,6 +1,7 @@
 """Host-only checks of the C ABI: the library loads, exports every declared symbol, and
 validates descriptions / computes footprints without touching a GPU."""
 import ctypes
+import dataclasses
 import os
 import re
 
@@ -92,3 +93,18 @@ def test_step_rejects_bad_arguments_without_gpu():
     L = viper.lib()
     assert L.viper_step(None, 1 / 60, 1, 1, None) == viper.ERR_INVALID
     assert L.viper_sync(None, None) == viper.ERR_INVALID
+
+
+def test_bundling_sections_footprint_and_validation():
+    """Bundling sections (Sec. 7.3) add their buffers to the footprint; empty sections,
+    out-of-range pills and a pill in two sections are rejected on the host."""
+    d, _ = scenes.muscle_scene(num_muscles=2, seed=5, target_pills=None, mesh_vertices=0)
+    base = viper.footprint(d)
+    b, _ = scenes.muscle_scene(num_muscles=2, seed=5, target_pills=None, mesh_vertices=0, bundling=True)
+    assert viper.footprint(b) > base
+    for offs, pills, msg in (([0, 0, 2], [0, 1], "empty"), ([0, 2], [0, b.num_pills], "range"),
+                             ([0, 2, 4], [0, 1, 1, 2], "two sections"), ([1, 2], [0, 1], "section_offsets[0]")):
+        bad = dataclasses.replace(b, section_offsets=np.asarray(offs, np.int32), section_pills=np.asarray(pills, np.int32))
+        with pytest.raises(viper.ViperError) as ei:
+            viper.footprint(bad)
+        assert ei.value.status == viper.ERR_INVALID and msg in str(ei.value), str(ei.value)
