@@ -286,6 +286,35 @@ def paper_shaped_timing(torch, viper, scenes, dev, frames=10):
     return res
 
 
+def bundling_timing(torch, viper, scenes, dev, frames=10):
+    """The 64-muscle scene (FP32, contacts, 20 substeps x 8 iterations) with one bundling
+    cross-section per pill index of each muscle (Sec. 7.3 shape matching after the
+    iterations of every substep): ms per frame beside the same scene without sections.
+    The difference is mostly not the two bundling kernels (~35 us per substep): the hard
+    projection leaves this synthetic muscle faster-moving and more crowded, and the
+    neighbour search walks more."""
+    res = {}
+    for bundling in (False, True):
+        desc, _ = scenes.muscle_scene(64, seed=2, mesh_vertices=0, bundling=bundling)
+        sc = viper.Scene(desc, "f32", device=dev, collisions=True)
+        for _ in range(2):
+            sc.step(1.0 / 60.0, 20, 8)
+        st = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(frames):
+            sc.step(1.0 / 60.0, 20, 8)
+        e1.record(st)
+        torch.cuda.synchronize()
+        sc.sync()
+        res["frame_ms_bundled" if bundling else "frame_ms_plain"] = e0.elapsed_time(e1) / frames
+        if bundling:
+            res.update(workload="muscle64_%dpills_bundled" % desc.num_pills,
+                       sections=int(len(desc.section_offsets) - 1), section_entries=int(desc.section_offsets[-1]))
+    res["bundling_ms_per_substep"] = (res["frame_ms_bundled"] - res["frame_ms_plain"]) / 20
+    return res
+
+
 def serving_run(torch, scenes, serve, seconds):
     """Poisson arrivals (200/s) of helix and muscle scenes of 1k-200k pills (log-uniform),
     60 frames each; continuous batching vs the plain per-scene path on the same requests."""
@@ -411,6 +440,8 @@ def main():
         out["contacts_skinning"] = contact_skin_timing(torch, viper, scenes, dev)
         out["paper_shaped"] = paper_shaped_timing(torch, viper, scenes, dev)
         log("contacts and skinning done")
+        out["bundling"] = bundling_timing(torch, viper, scenes, dev)
+        log("bundling done")
     if not args.no_adjoint:
         out["adjoint"] = adjoint_timing(torch, viper, scenes, dev)
         log("adjoint done")
