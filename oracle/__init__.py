@@ -68,6 +68,8 @@ def lib():
         L.orc_set_masses.argtypes = [P, P, P, P]
         L.orc_contact_pass.argtypes = [P, I, D]
         L.orc_set_sections.argtypes = [P, I, P, P]
+        L.orc_set_floor.argtypes = [P, P, D]
+        L.orc_floor_pass.argtypes = [P]
         L.orc_section_fit.argtypes = [P, I, P]
         L.orc_bundle.argtypes = [P]
         L.orc_extract_rotation.argtypes = [P, P, P]
@@ -121,6 +123,13 @@ class OracleScene:
             self._sec = (np.ascontiguousarray(desc.section_offsets, dtype=np.int32),
                          np.ascontiguousarray(desc.section_pills, dtype=np.int32))
             L.orc_set_sections(self.h, int(self._sec[0].shape[0] - 1), _p(self._sec[0]), _p(self._sec[1]))
+        if getattr(desc, "floor", None) is not None:
+            n = np.ascontiguousarray(desc.floor[:3], dtype=np.float64)
+            L.orc_set_floor(self.h, _p(n), float(desc.floor[3]))
+
+    def floor_pass(self):
+        """One projection of every pill against the half-plane floor (Sec. 7)."""
+        lib().orc_floor_pass(self.h)
 
     def section_fit(self, k):
         """Bundling fit of section k at the current state (Sec. 7.3): (R*, s*, c*, q*)."""

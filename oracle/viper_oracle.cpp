@@ -253,6 +253,10 @@ template <class R> struct Scene {
   // previous substep (the start of the next rotation extraction)
   std::vector<int> sec_off, sec_pill;
   std::vector<Q4<double>> sec_q;
+  // kinematic half-plane floor (Sec. 7): pills stay in n . x >= d
+  bool floor_on = false;
+  V3<double> floor_n;
+  double floor_d = 0.0;
   std::vector<int32_t> pairs;  // sorted (a, b), a < b, capsule id = first pill of the edge
   std::vector<int> active_count; // number of active contacts in the last contact pass
   int64_t projections = 0;     // count of rod + active contact projections performed
@@ -693,6 +697,29 @@ template <class R> void velocity_rods(Scene<R>& S, R h, int r0, int r1) {
 }
 
 // ---------------------------------------------------------------------------
+// Half-plane floor (Sec. 7: the floor is a kinematic half-plane collision proxy).  For every
+// pill the hard constraint C = n . x - d - s rbar >= 0 (its sphere above the plane) is
+// projected on the position only: x += -C n (S = w |n|^2, dl = -C / S, dx = w n dl).
+// Readings: the paper couples radii and positions for pill-pill contacts but calls the floor a
+// simple half-plane constraint; with the scale DOF in the update its very small mass would
+// take nearly the whole correction and shrink penetrating pills (to negative radii) instead of
+// lifting them.  A pill's sphere suffices (the distance of a capsule to a plane minus its
+// radius is linear along it, so its minimum is at a pill); pinned pills are not moved; the
+// projection runs at the start of every iteration, after the previous contact pass.
+// ---------------------------------------------------------------------------
+template <class R> int64_t project_floor(Scene<R>& S) {
+  int64_t n = 0;
+  const R nx = R(S.floor_n.x), ny = R(S.floor_n.y), nz = R(S.floor_n.z), d = R(S.floor_d);
+  for (int p = 0; p < S.P; ++p) {
+    const R C = (nx * S.x[p].x + ny * S.x[p].y + nz * S.x[p].z) - d - S.s[p] * S.rbar[p];
+    if (!(C < R(0.0)) || !(S.winv[p] > R(0.0))) continue;
+    S.x[p] = S.x[p] + (-C) * v3<R>(nx, ny, nz);
+    ++n;
+  }
+  return n;
+}
+
+// ---------------------------------------------------------------------------
 // Scale-invariant shape matching of a muscle cross-section ("bundling", Sec. 7.3).
 // Each pill i of a section carries a similarity transform T_i = [s_i R_i | x_i]; the
 // section is fitted with one global similarity T* of its rest transforms (Umeyama),
@@ -810,7 +837,7 @@ template <class R> void bundle(Scene<R>& S) {
 
 template <class R> void substep(Scene<R>& S, R h, int iters, bool collide, int search_iters, double delta, int threads) {
   R ih2 = R(1.0) / (h * h);
-  if (!collide && threads > 1 && S.nrods > 1 && S.sec_off.size() < 2) {
+  if (!collide && threads > 1 && S.nrods > 1 && S.sec_off.size() < 2 && !S.floor_on) {
     int nt = std::min(threads, S.nrods);
     std::vector<std::thread> pool;
     std::vector<int64_t> proj(nt, 0);
@@ -830,6 +857,7 @@ template <class R> void substep(Scene<R>& S, R h, int iters, bool collide, int s
   if (collide) detect(S);
   else S.pairs.clear();
   for (int it = 0; it < iters; ++it) {
+    if (S.floor_on) S.projections += project_floor(S);
     S.projections += solve_colours(S, ih2, 0, S.nrods);
     if (collide) project_contacts(S, search_iters, delta);
   }
@@ -932,6 +960,13 @@ template <class R> static void set_sections_t(Scene<R>& S, int nsec, const int32
   S.sec_q.assign(nsec, q4<double>(0, 0, 0, 1));
 }
 
+template <class R> static void set_floor_t(Scene<R>& S, const double* n, double d) {
+  const double l = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+  S.floor_on = true;
+  S.floor_n = v3<double>(n[0] / l, n[1] / l, n[2] / l);
+  S.floor_d = d / l;
+}
+
 static Desc make_desc(int num_rods, const int32_t* off, const double* rest_pos, const double* rest_radius, const uint8_t* pinned,
                       const double* activation, const double* compliance, const int32_t* group, double density, const double* gravity) {
   Desc d;
@@ -989,6 +1024,15 @@ void orc_section_fit(void* hp, int k, double* out) {
     for (int c = 0; c < 3; ++c) out[3 * r + c] = F.R.m[r][c];
   out[9] = F.s; out[10] = F.c.x; out[11] = F.c.y; out[12] = F.c.z;
   out[13] = F.q.x; out[14] = F.q.y; out[15] = F.q.z; out[16] = F.q.w;
+}
+// Half-plane floor n . x >= d (n normalised here); one projection pass at the current state.
+void orc_set_floor(void* hp, const double* n, double d) {
+  Handle* h = (Handle*)hp;
+  if (h->d) set_floor_t(*h->d, n, d); else set_floor_t(*h->f, n, d);
+}
+void orc_floor_pass(void* hp) {
+  Handle* h = (Handle*)hp;
+  if (h->d) project_floor(*h->d); else project_floor(*h->f);
 }
 // One bundling projection of every section at the current state.
 void orc_bundle(void* hp) {

@@ -38,6 +38,8 @@ class SceneDesc:
     # bundling cross-sections (Sec. 7.3): section k = pills section_pills[section_offsets[k]:section_offsets[k+1]]
     section_offsets: np.ndarray = None  # int32 [S+1]
     section_pills: np.ndarray = None    # int32
+    # half-plane floor (Sec. 7): (nx, ny, nz, d), pills stay in n . x >= d; None = no floor
+    floor: tuple = None
 
     @property
     def num_rods(self) -> int:

@@ -736,3 +736,60 @@ def test_bundling_sets_every_pill_to_the_fitted_transform():
             if p not in last:
                 qq = _qmul(q, rest["qrest"][p])
                 assert np.minimum(np.abs(after["q"][p] - qq).max(), np.abs(after["q"][p] + qq).max()) < 1e-13
+
+
+# ----------------------------------------------------------------------------- half-plane floor (Sec. 7)
+
+def _flat_rods(n_rods=4, n_pills=8, height=0.05, floor=(0.0, 1.0, 0.0, 0.0)):
+    """Straight horizontal rods above a floor (1 cm pills, r = 4 mm, compliance 1e-6)."""
+    pos, off = [], [0]
+    for k in range(n_rods):
+        p = np.zeros((n_pills, 3))
+        p[:, 0] = 0.01 * np.arange(n_pills)
+        p[:, 1] = height + 0.01 * k
+        p[:, 2] = 0.03 * k
+        pos.append(p)
+        off.append(off[-1] + n_pills)
+    P = off[-1]
+    desc = scenes.SceneDesc(np.asarray(off, np.int32), np.concatenate(pos), np.full(P, 0.004), np.zeros(P, np.uint8),
+                            np.ones(n_rods), np.full((n_rods, 4), 1e-6), np.arange(n_rods, dtype=np.int32),
+                            name="flat", floor=floor)
+    return desc
+
+
+def test_floor_projection_is_the_classic_ground_projection():
+    """A pill whose sphere reaches below the plane moves along n exactly onto
+    n.x = d + s rbar (tangential coordinates and scale unchanged); pills above the plane
+    and pinned pills are untouched.  Tilted plane, offset d != 0."""
+    n_raw, d_raw = np.array([0.2, 1.0, -0.1]), 0.01
+    desc = _flat_rods(floor=(*n_raw, d_raw))
+    desc.pinned[::5] = 1
+    n, d = n_raw / np.linalg.norm(n_raw), d_raw / np.linalg.norm(n_raw)
+    o = oracle.OracleScene(desc, "f64")
+    rng = np.random.default_rng(1)
+    x = rng.normal(0.0, 0.02, (desc.num_pills, 3))
+    s = rng.uniform(0.8, 1.2, desc.num_pills)
+    o.set_state(x=x, s=s)
+    o.floor_pass()
+    st = o.get_state()
+    r = desc.rest_radius
+    C0 = x @ n - d - s * r
+    moved = (C0 < 0) & (desc.pinned == 0)
+    assert moved.any() and (~moved).any()
+    assert np.array_equal(st["x"][~moved], x[~moved])
+    assert np.abs(st["x"][moved] @ n - d - s[moved] * r[moved]).max() < 1e-15
+    dx = st["x"][moved] - x[moved]
+    assert np.abs(dx - np.outer(dx @ n, n)).max() < 1e-16
+    assert np.array_equal(st["s"], s)
+
+
+def test_rods_dropped_on_the_floor_come_to_rest_on_it():
+    desc = _flat_rods()
+    o = oracle.OracleScene(desc, "f64")
+    for _ in range(90):
+        o.step(1 / 60, 10, 4)
+    st = o.get_state()
+    C = st["x"][:, 1] - st["s"] * desc.rest_radius
+    assert C.min() > -1e-3                      # penetration bounded by the last iterations' drift
+    assert st["x"][:, 1].max() < 0.02           # they fell ...
+    assert np.abs(st["v"]).max() < 0.05         # ... and are at rest
