@@ -81,6 +81,14 @@ typedef struct {
   int32_t num_sections;
   const int32_t* section_offsets;
   const int32_t* section_pills;
+  /* Kinematic half-plane floor (Sec. 7): nonzero floor_on keeps every pill's sphere in
+   * floor_normal . x >= floor_offset + s rbar (normal need not be unit; it is normalised).
+   * Projected on positions only, at the start of every constraint iteration; pinned pills
+   * are not moved.  A scene with a floor steps in VIPER_MODE_ITERATION or VIPER_MODE_GRAPH;
+   * the pool and the adjoint reject it. */
+  int32_t floor_on;
+  double floor_normal[3];
+  double floor_offset;
 } viper_scene_desc;
 
 /* Bytes of device workspace the scene needs (host-only computation; validates the

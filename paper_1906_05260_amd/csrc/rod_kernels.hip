@@ -122,6 +122,10 @@ __global__ void __launch_bounds__(256) rod_iteration_kernel(const Dev<T>* __rest
     if (P.A.f & F_VALID) contact_apply(c, pA, P.A.x0, P.A.x1, P.A.x2, P.A.s);
     if (P.B.f & F_VALID) contact_apply(c, pB, P.B.x0, P.B.x1, P.B.x2, P.B.s);
   }
+  if (d.floor_on) {   // then the half-plane floor, at the start of the iteration
+    if (P.A.f & F_VALID) floor_apply(d, pA, P.A.x0, P.A.x1, P.A.x2, P.A.s);
+    if (P.B.f & F_VALID) floor_apply(d, pB, P.B.x0, P.B.x1, P.B.x2, P.B.s);
+  }
   load_lane_consts(d, P, pA, pB, rcp(h * h));
   P.I1N = dn(P.A.I1);
   iteration_lane(P);

@@ -115,6 +115,12 @@ viper_status validate(const viper_scene_desc* d) {
              dz = d->rest_pos[3 * p + 5] - d->rest_pos[3 * p + 2];
       if (!(dx * dx + dy * dy + dz * dz > 0)) return fail(VIPER_ERR_INVALID, "consecutive rest pills coincide");
     }
+  if (d->floor_on) {
+    const double* n = d->floor_normal;
+    if (!std::isfinite(n[0]) || !std::isfinite(n[1]) || !std::isfinite(n[2]) || !std::isfinite(d->floor_offset) ||
+        !(n[0] * n[0] + n[1] * n[1] + n[2] * n[2] > 0))
+      return fail(VIPER_ERR_INVALID, "floor_normal must be finite and nonzero, floor_offset finite");
+  }
   if (d->num_sections < 0) return fail(VIPER_ERR_INVALID, "num_sections < 0");
   if (d->num_sections > 0) {
     if (!d->section_offsets || !d->section_pills)
@@ -400,6 +406,8 @@ struct viper_scene_s {
   int precision = 0;
   int collisions = 0;
   int nsec = 0, nsecp = 0;    // bundling sections and their entries
+  int floor_on = 0;           // half-plane floor (unit normal, offset)
+  double floor_n[3] = {0.0, 0.0, 0.0}, floor_d = 0.0;
   int cap = 16;
   int R = 0, P = 0, W = 0, E = 0;
   int64_t proj_per_iter = 0;
@@ -456,6 +464,8 @@ void fill_dev(viper_scene_s* S, Dev<T>& d) {
   d.sec_xr = S->nsec ? (const double*)(b + S->o.sec_xr) : nullptr;
   d.sec_q = S->nsec ? (double*)(b + S->o.sec_q) : nullptr;
   d.sec_fit = S->nsec ? (double*)(b + S->o.sec_fit) : nullptr;
+  d.floor_on = S->floor_on;
+  d.fnx = S->floor_n[0]; d.fny = S->floor_n[1]; d.fnz = S->floor_n[2]; d.fd = S->floor_d;
 }
 
 template <class T>
@@ -514,12 +524,16 @@ template <> Dev<double>& dev<double>(viper_scene_s* S) { return S->dd; }
 
 // One frame of a batch (all scenes share precision, dt, substeps and iterations).
 template <class T>
-viper_status batch_step(const BatchDev& b, bool collisions, double dt, int sub, int iters, int mode, hipStream_t st) {
+// `iteration_only`: the batch has collisions, bundling sections or a floor, whose projections
+// need a grid-wide step between iterations (the single-launch modes cannot run them).
+viper_status batch_step(const BatchDev& b, bool collisions, bool iteration_only, double dt, int sub, int iters, int mode,
+                        hipStream_t st) {
   const double h = dt / sub;
   const bool bundled = b.nblk[TB_SECT] > 0;
-  if (mode == VIPER_MODE_AUTO) mode = (collisions || bundled) ? VIPER_MODE_ITERATION : VIPER_MODE_FRAME;
-  if ((collisions || bundled) && mode != VIPER_MODE_ITERATION)
-    return fail(VIPER_ERR_INVALID, "scenes with collisions or bundling sections step in VIPER_MODE_ITERATION");
+  iteration_only = iteration_only || collisions || bundled;
+  if (mode == VIPER_MODE_AUTO) mode = iteration_only ? VIPER_MODE_ITERATION : VIPER_MODE_FRAME;
+  if (iteration_only && mode != VIPER_MODE_ITERATION)
+    return fail(VIPER_ERR_INVALID, "scenes with collisions, bundling sections or a floor step in VIPER_MODE_ITERATION");
   if (mode == VIPER_MODE_FRAME) {
     HIP_TRY(launch_rod_frame<T>(b, sub, h, iters, st));
   } else if (mode == VIPER_MODE_SUBSTEP) {
@@ -555,7 +569,8 @@ viper_status capture_frame(viper_scene_s* S, double dt, int sub, int iters) {
   }
   if (!S->capture) HIP_TRY(hipStreamCreateWithFlags(&S->capture, hipStreamNonBlocking));
   HIP_TRY(hipStreamBeginCapture(S->capture, hipStreamCaptureModeThreadLocal));
-  viper_status r = batch_step<T>(S->batch, S->collisions != 0, dt, sub, iters, VIPER_MODE_ITERATION, S->capture);
+  viper_status r = batch_step<T>(S->batch, S->collisions != 0, S->floor_on != 0, dt, sub, iters, VIPER_MODE_ITERATION,
+                                 S->capture);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(S->capture, &g);
   if (r != VIPER_OK) {
@@ -577,8 +592,9 @@ viper_status capture_frame(viper_scene_s* S, double dt, int sub, int iters) {
 
 template <class T>
 viper_status step_t(viper_scene_s* S, double dt, int sub, int iters, int mode, hipStream_t st) {
-  if (mode == VIPER_MODE_AUTO && (S->collisions || S->nsec)) mode = VIPER_MODE_GRAPH;
-  if (mode != VIPER_MODE_GRAPH) return batch_step<T>(S->batch, S->collisions != 0, dt, sub, iters, mode, st);
+  if (mode == VIPER_MODE_AUTO && (S->collisions || S->nsec || S->floor_on)) mode = VIPER_MODE_GRAPH;
+  if (mode != VIPER_MODE_GRAPH)
+    return batch_step<T>(S->batch, S->collisions != 0, S->floor_on != 0, dt, sub, iters, mode, st);
   if (!S->graph || S->graph_h != dt / sub || S->graph_sub != sub || S->graph_iters != iters) {
     viper_status r = capture_frame<T>(S, dt, sub, iters);
     if (r != VIPER_OK) return r;
@@ -635,6 +651,13 @@ viper_status viper_create_scene(const viper_scene_desc* desc, void* workspace, s
   S->collisions = desc->collisions != 0;
   S->nsec = desc->num_sections > 0 ? desc->num_sections : 0;
   S->nsecp = S->nsec ? desc->section_offsets[S->nsec] : 0;
+  if (desc->floor_on) {
+    const double* n = desc->floor_normal;
+    const double l = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    S->floor_on = 1;
+    for (int i = 0; i < 3; ++i) S->floor_n[i] = n[i] / l;
+    S->floor_d = desc->floor_offset / l;
+  }
   S->cap = cap;
   S->R = H.R; S->P = H.P; S->W = H.W; S->E = H.E;
   S->proj_per_iter = H.proj_per_iter;
@@ -807,6 +830,7 @@ viper_status adjoint_check(viper_scene S, int32_t frames, int32_t substeps, int3
   if (!S) return fail(VIPER_ERR_INVALID, "scene is NULL");
   if (S->collisions) return fail(VIPER_ERR_INVALID, "the adjoint covers collision-free scenes");
   if (S->nsec) return fail(VIPER_ERR_INVALID, "the adjoint does not cover bundling sections");
+  if (S->floor_on) return fail(VIPER_ERR_INVALID, "the adjoint does not cover the floor");
   if (frames < 1 || substeps < 1 || iterations < 0)
     return fail(VIPER_ERR_INVALID, "frames >= 1, substeps >= 1 and iterations >= 0 required");
   return VIPER_OK;
@@ -967,7 +991,7 @@ viper_status pool_step_class(viper_pool_s* P, bool contact, double dt, int sub, 
   }
   const BatchDev& b = contact ? P->cb : P->fb;
   if (b.nscenes == 0) return VIPER_OK;
-  return batch_step<T>(b, contact, dt, sub, iters, contact ? VIPER_MODE_ITERATION : VIPER_MODE_FRAME, st);
+  return batch_step<T>(b, contact, false, dt, sub, iters, contact ? VIPER_MODE_ITERATION : VIPER_MODE_FRAME, st);
 }
 
 // Both classes: collision-free on `st`, contacts on the pool's second stream, joined.
@@ -1021,7 +1045,8 @@ viper_status viper_pool_create(void* workspace, size_t bytes, int32_t max_scenes
 viper_status viper_pool_admit(viper_pool P, const viper_scene_desc* desc, void* stream, int32_t* slot) {
   if (!P || !desc || !slot) return fail(VIPER_ERR_INVALID, "pool, desc and slot are required");
   if (desc->precision != P->precision) return fail(VIPER_ERR_INVALID, "scene precision differs from the pool's");
-  if (desc->num_sections > 0) return fail(VIPER_ERR_INVALID, "scenes with bundling sections are stepped with viper_step");
+  if (desc->num_sections > 0 || desc->floor_on)
+    return fail(VIPER_ERR_INVALID, "scenes with bundling sections or a floor are stepped with viper_step");
   size_t fp = 0;
   viper_status r = viper_scene_footprint(desc, &fp);
   if (r != VIPER_OK) return r;

@@ -57,6 +57,9 @@ struct Dev {
   const double* sec_xr;      // [3*nsecp] world rest position of each entry
   double* sec_q;             // [4*nsec] rotation of the last fit (start of the next extraction)
   double* sec_fit;           // [kSecFit*nsec] R* (row-major), s*, c*, q*
+  // half-plane floor (Sec. 7): n . x >= fd + s rbar, unit n
+  int floor_on;
+  double fnx, fny, fnz, fd;
 };
 constexpr int kSecFit = 20;
 
@@ -103,6 +106,20 @@ __device__ __forceinline__ bool contact_apply(const ContactDev& c, int p, T& x0,
   a[0] = 0ull; a[1] = 0ull; a[2] = 0ull; a[3] = 0ull;
   c.acnt[p] = 0;
   return true;
+}
+
+// Half-plane floor, for pill p at (x0, x1, x2) with scale s: lift the pill along the normal
+// until its sphere touches the plane (positions only; pinned pills stay).
+template <class T>
+__device__ __forceinline__ void floor_apply(const Dev<T>& d, int p, T& x0, T& x1, T& x2, T s) {
+  if (!(d.winv[p] > T(0))) return;
+  const double* an = d.anchor + 3 * (size_t)d.rod_of[p];
+  const double C = (d.fnx * (an[0] + (double)x0) + d.fny * (an[1] + (double)x1) + d.fnz * (an[2] + (double)x2)) -
+                   d.fd - (double)s * (double)d.rbar[p];
+  if (!(C < 0.0)) return;
+  x0 = (T)((double)x0 - C * d.fnx);
+  x1 = (T)((double)x1 - C * d.fny);
+  x2 = (T)((double)x2 - C * d.fnz);
 }
 
 // A batch of scenes advanced by the same launches.  Each launch's grid is described by a

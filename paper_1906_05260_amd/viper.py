@@ -60,6 +60,9 @@ class SceneDescC(ctypes.Structure):
         ("num_sections", ctypes.c_int32),
         ("section_offsets", ctypes.c_void_p),
         ("section_pills", ctypes.c_void_p),
+        ("floor_on", ctypes.c_int32),
+        ("floor_normal", ctypes.c_double * 3),
+        ("floor_offset", ctypes.c_double),
     ]
 
 
@@ -145,6 +148,11 @@ class _DescHolder:
             c.num_sections = int(a["soff"].shape[0] - 1)
             c.section_offsets = a["soff"].ctypes.data
             c.section_pills = a["spill"].ctypes.data
+        if getattr(desc, "floor", None) is not None:
+            c.floor_on = 1
+            for i in range(3):
+                c.floor_normal[i] = float(desc.floor[i])
+            c.floor_offset = float(desc.floor[3])
         self.c = c
 
 

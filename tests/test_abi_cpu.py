@@ -108,3 +108,13 @@ def test_bundling_sections_footprint_and_validation():
         with pytest.raises(viper.ViperError) as ei:
             viper.footprint(bad)
         assert ei.value.status == viper.ERR_INVALID and msg in str(ei.value), str(ei.value)
+
+
+def test_floor_validation():
+    """The half-plane floor (Sec. 7) needs a finite nonzero normal and a finite offset."""
+    d = scenes.helix_rods(2, 8, seed=1)
+    viper.footprint(dataclasses.replace(d, floor=(0.0, 2.0, 0.0, -0.1)))
+    for fl in ((0.0, 0.0, 0.0, 0.0), (np.nan, 1.0, 0.0, 0.0), (0.0, 1.0, 0.0, np.inf)):
+        with pytest.raises(viper.ViperError) as ei:
+            viper.footprint(dataclasses.replace(d, floor=fl))
+        assert ei.value.status == viper.ERR_INVALID and "floor" in str(ei.value)

@@ -1,0 +1,113 @@
+"""Half-plane floor (Sec. 7, kinematic half-plane collision proxy) on the GPU against the
+FP64 oracle.
+
+Workload: 4 straight rods of 8 pills (r = 4 mm) dropped from 5-8 cm onto a tilted plane
+(normal (0.05, 1, 0.02), offset -0.002).  Checks:
+- FP64: 30 frames of 10 substeps x 4 iterations (the fall, the impact, the rods coming to
+  rest) equal the oracle's to 1e-9 of the rod length;
+- FP32: the first 15 frames (through the impact) within the 1e-4 bound of the other tests;
+- after 90 frames on a level floor the rods rest on it: no sphere below it by more than 1 mm
+  (on the tilted plane, frictionless, they keep sliding);
+- the captured-graph frame equals the eager launches bit for bit;
+- the single-kernel modes, the pool and the adjoint reject a scene with a floor.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from paper_1906_05260_amd import scenes, viper  # noqa: E402
+
+sys.path.insert(0, __file__.rsplit("/", 1)[0])
+from test_gpu_rods import errors  # noqa: E402
+
+FLOOR = (0.05, 1.0, 0.02, -0.002)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def flat_rods(floor=FLOOR):
+    pos, off = [], [0]
+    for k in range(4):
+        p = np.zeros((8, 3))
+        p[:, 0] = 0.01 * np.arange(8)
+        p[:, 1] = 0.05 + 0.01 * k
+        p[:, 2] = 0.03 * k
+        pos.append(p)
+        off.append(off[-1] + 8)
+    return scenes.SceneDesc(np.asarray(off, np.int32), np.concatenate(pos), np.full(32, 0.004), np.zeros(32, np.uint8),
+                            np.ones(4), np.full((4, 4), 1e-6), np.arange(4, dtype=np.int32), name="flat", floor=floor)
+
+
+def run(desc, prec, frames, mode=viper.MODE_ITERATION):
+    sc = viper.Scene(desc, prec)
+    for _ in range(frames):
+        sc.step(1 / 60, 10, 4, mode=mode)
+    sc.sync()
+    return sc.state()
+
+
+def oracle_run(desc, frames):
+    o = oracle.OracleScene(desc, "f64")
+    for _ in range(frames):
+        o.step(1 / 60, 10, 4)
+    return o.get_state()
+
+
+def test_fp64_matches_oracle_through_impact_and_rest():
+    desc = flat_rods()
+    say("case: floor fp64", desc.num_pills)
+    g, r = run(desc, "f64", 30), oracle_run(desc, 30)
+    ex, es, eq = errors(desc, g, r)
+    say("fp64 floor errors", ex, es, eq)
+    assert ex < 1e-9 and es < 1e-9 and eq < 1e-9
+
+
+def test_fp32_through_impact():
+    desc = flat_rods()
+    g, r = run(desc, "f32", 15), oracle_run(desc, 15)
+    ex, es, eq = errors(desc, g, r)
+    say("fp32 floor errors", ex, es, eq)
+    assert ex < 1e-4 and es < 1e-4 and eq < 1e-4
+
+
+def test_rods_rest_on_the_floor():
+    level = (0.0, 1.0, 0.0, -0.002)
+    desc = flat_rods(level)
+    g = run(desc, "f32", 90, mode=viper.MODE_AUTO)
+    n = np.asarray(level[:3])
+    d = level[3]
+    C = g["x"] @ n - d - g["s"] * desc.rest_radius
+    say("floor gap min", C.min(), "speed max", np.abs(g["v"]).max())
+    assert C.min() > -1e-3 and np.abs(g["v"]).max() < 0.05
+
+
+def test_graph_equals_eager():
+    desc = flat_rods()
+    a = run(desc, "f32", 5, mode=viper.MODE_AUTO)       # captured graph
+    b = run(desc, "f32", 5, mode=viper.MODE_ITERATION)
+    for k in ("x", "v", "s", "q"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_rejections():
+    desc = flat_rods()
+    sc = viper.Scene(desc, "f32")
+    for mode in (viper.MODE_FRAME, viper.MODE_SUBSTEP):
+        with pytest.raises(viper.ViperError) as ei:
+            sc.step(1 / 60, 4, 4, mode=mode)
+        assert ei.value.status == viper.ERR_INVALID
+    with pytest.raises(viper.ViperError) as ei:
+        sc.step_checkpointed(1 / 60, 1, 4, 4)
+    assert ei.value.status == viper.ERR_INVALID
+    pool = viper.Pool(16 << 20, precision="f32")
+    with pytest.raises(viper.ViperError) as ei:
+        pool.admit(desc)
+    assert ei.value.status == viper.ERR_INVALID
