@@ -89,7 +89,17 @@ viper_status validate(const viper_scene_desc* d) {
   if (!finite_pos(d->density)) return fail(VIPER_ERR_INVALID, "density must be finite and > 0");
   for (int i = 0; i < 3; ++i)
     if (!std::isfinite(d->gravity[i])) return fail(VIPER_ERR_INVALID, "gravity must be finite");
-  if (d->num_rods == 0) return VIPER_OK;
+  if (d->floor_on) {
+    const double* n = d->floor_normal;
+    if (!std::isfinite(n[0]) || !std::isfinite(n[1]) || !std::isfinite(n[2]) || !std::isfinite(d->floor_offset) ||
+        !(n[0] * n[0] + n[1] * n[1] + n[2] * n[2] > 0))
+      return fail(VIPER_ERR_INVALID, "floor_normal must be finite and nonzero, floor_offset finite");
+  }
+  if (d->num_sections < 0) return fail(VIPER_ERR_INVALID, "num_sections < 0");
+  if (d->num_rods == 0) {
+    if (d->num_sections > 0) return fail(VIPER_ERR_INVALID, "bundling sections need pills");
+    return VIPER_OK;
+  }
   if (d->rod_offsets[0] != 0) return fail(VIPER_ERR_INVALID, "rod_offsets[0] must be 0");
   for (int k = 0; k < d->num_rods; ++k) {
     int n = d->rod_offsets[k + 1] - d->rod_offsets[k];
@@ -115,13 +125,6 @@ viper_status validate(const viper_scene_desc* d) {
              dz = d->rest_pos[3 * p + 5] - d->rest_pos[3 * p + 2];
       if (!(dx * dx + dy * dy + dz * dz > 0)) return fail(VIPER_ERR_INVALID, "consecutive rest pills coincide");
     }
-  if (d->floor_on) {
-    const double* n = d->floor_normal;
-    if (!std::isfinite(n[0]) || !std::isfinite(n[1]) || !std::isfinite(n[2]) || !std::isfinite(d->floor_offset) ||
-        !(n[0] * n[0] + n[1] * n[1] + n[2] * n[2] > 0))
-      return fail(VIPER_ERR_INVALID, "floor_normal must be finite and nonzero, floor_offset finite");
-  }
-  if (d->num_sections < 0) return fail(VIPER_ERR_INVALID, "num_sections < 0");
   if (d->num_sections > 0) {
     if (!d->section_offsets || !d->section_pills)
       return fail(VIPER_ERR_INVALID, "section_offsets and section_pills are required");
@@ -512,7 +515,7 @@ viper_status upload(viper_scene_s* S, const Host& H, hipStream_t st) {
     HIP_TRY(hipMemcpyAsync(b + S->o.sec_of, H.sec_of.data(), 4 * H.sec_of.size(), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(b + S->o.sec_xr, H.sec_xr.data(), 8 * H.sec_xr.size(), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(b + S->o.sec_q, q0.data(), 8 * q0.size(), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(hipStreamSynchronize(st));   // q0 dies with this block
   }
   HIP_TRY(hipStreamSynchronize(st));   // the host staging vectors die with this frame
   return VIPER_OK;
