@@ -70,6 +70,9 @@ def lib():
         L.orc_set_sections.argtypes = [P, I, P, P]
         L.orc_set_floor.argtypes = [P, P, D]
         L.orc_floor_pass.argtypes = [P]
+        L.orc_set_solver.argtypes = [P, I]
+        L.orc_rod_iteration.restype = ctypes.c_int64
+        L.orc_rod_iteration.argtypes = [P, D, I]
         L.orc_section_fit.argtypes = [P, I, P]
         L.orc_bundle.argtypes = [P]
         L.orc_extract_rotation.argtypes = [P, P, P]
@@ -123,9 +126,16 @@ class OracleScene:
             self._sec = (np.ascontiguousarray(desc.section_offsets, dtype=np.int32),
                          np.ascontiguousarray(desc.section_pills, dtype=np.int32))
             L.orc_set_sections(self.h, int(self._sec[0].shape[0] - 1), _p(self._sec[0]), _p(self._sec[1]))
+        if getattr(desc, "solver", "gauss_seidel") == "jacobi":
+            L.orc_set_solver(self.h, 1)
         if getattr(desc, "floor", None) is not None:
             n = np.ascontiguousarray(desc.floor[:3], dtype=np.float64)
             L.orc_set_floor(self.h, _p(n), float(desc.floor[3]))
+
+    def rod_iterations(self, h, iters=1):
+        """`iters` iterations of the rod constraints at the current state (substep h), from
+        zero multipliers (as project_one)."""
+        return int(lib().orc_rod_iteration(self.h, float(h), int(iters)))
 
     def floor_pass(self):
         """One projection of every pill against the half-plane floor (Sec. 7)."""

@@ -253,6 +253,9 @@ template <class R> struct Scene {
   // previous substep (the start of the next rotation extraction)
   std::vector<int> sec_off, sec_pill;
   std::vector<Q4<double>> sec_q;
+  // solver for the rod constraints: false = coloured Gauss-Seidel, true = Jacobi with
+  // averaging (the paper's engine, Sec. 7)
+  bool jacobi = false;
   // kinematic half-plane floor (Sec. 7): pills stay in n . x >= d
   bool floor_on = false;
   V3<double> floor_n;
@@ -682,6 +685,67 @@ template <class R> int64_t solve_colours(Scene<R>& S, R ih2, int r0, int r1) {
   return n;
 }
 
+// One all-Jacobi iteration with averaging (Sec. 7: constraints computed in parallel, their
+// displacements averaged by a reduction).  Every rod constraint is projected from the state
+// at the start of the iteration; each degree of freedom then moves by the mean of the
+// corrections of the active constraints acting on it.  Readings: the count is the number of
+// active constraints on the DOF; a rotation moves by the mean quaternion increment,
+// q <- normalize(q + mean(q_c - q)); each constraint keeps its own multiplier update.
+template <class R> int64_t solve_jacobi(Scene<R>& S, R ih2) {
+  const int P = S.P;
+  std::vector<V3<R>> dx(P, v3<R>(R(0.0), R(0.0), R(0.0)));
+  std::vector<R> ds(P, R(0.0));
+  std::vector<Q4<R>> dq(P, q4<R>(R(0.0), R(0.0), R(0.0), R(0.0)));
+  std::vector<int> nx(P, 0), ns(P, 0), nq(P, 0);
+  int64_t n = 0;
+  // project constraint `kind` at p in place, record what it moved, restore the state
+  auto eval = [&](int kind, int p) {
+    const int q1 = p + 1;
+    const V3<R> x0 = S.x[p], x1 = S.x[q1];
+    const R s0 = S.s[p], s1 = S.s[q1];
+    const Q4<R> r0 = S.q[p], r1 = S.q[q1];
+    int a = 0;
+    if (kind == SS) a = project_ss(S, p, ih2);
+    else if (kind == VOL) a = project_vol(S, p, ih2);
+    else if (kind == SG) a = project_sg(S, p, ih2);
+    else a = project_bt(S, p, ih2);
+    if (!a) return;
+    n += a;
+    if (kind == SS || kind == VOL) {
+      dx[p] = dx[p] + (S.x[p] - x0); dx[q1] = dx[q1] + (S.x[q1] - x1); ++nx[p]; ++nx[q1];
+    }
+    if (kind == VOL || kind == SG) {
+      ds[p] = ds[p] + (S.s[p] - s0); ds[q1] = ds[q1] + (S.s[q1] - s1); ++ns[p]; ++ns[q1];
+    }
+    if (kind == BT) { ds[q1] = ds[q1] + (S.s[q1] - s1); ++ns[q1]; }
+    auto addq = [&](int i, const Q4<R>& before) {
+      dq[i] = q4<R>(dq[i].x + (S.q[i].x - before.x), dq[i].y + (S.q[i].y - before.y), dq[i].z + (S.q[i].z - before.z),
+                    dq[i].w + (S.q[i].w - before.w));
+      ++nq[i];
+    };
+    if (kind == SS) addq(p, r0);
+    if (kind == BT) { addq(p, r0); addq(q1, r1); }
+    S.x[p] = x0; S.x[q1] = x1; S.s[p] = s0; S.s[q1] = s1; S.q[p] = r0; S.q[q1] = r1;
+  };
+  for (int k = 0; k < S.nrods; ++k)
+    for (int p = S.off[k]; p + 1 < S.off[k + 1]; ++p) {
+      eval(SS, p);
+      eval(VOL, p);
+      eval(SG, p);
+      if (p + 2 < S.off[k + 1]) eval(BT, p);
+    }
+  for (int p = 0; p < P; ++p) {
+    if (nx[p]) S.x[p] = S.x[p] + (R(1.0) / R(double(nx[p]))) * dx[p];
+    if (ns[p]) S.s[p] = S.s[p] + ds[p] / R(double(ns[p]));
+    if (nq[p]) {
+      const R f = R(1.0) / R(double(nq[p]));
+      S.q[p] = qnormalize(q4<R>(S.q[p].x + f * dq[p].x, S.q[p].y + f * dq[p].y, S.q[p].z + f * dq[p].z,
+                                S.q[p].w + f * dq[p].w));
+    }
+  }
+  return n;
+}
+
 // Velocity update (reading: first-order finite difference over the substep).
 template <class R> void velocity_rods(Scene<R>& S, R h, int r0, int r1) {
   for (int k = r0; k < r1; ++k)
@@ -837,7 +901,7 @@ template <class R> void bundle(Scene<R>& S) {
 
 template <class R> void substep(Scene<R>& S, R h, int iters, bool collide, int search_iters, double delta, int threads) {
   R ih2 = R(1.0) / (h * h);
-  if (!collide && threads > 1 && S.nrods > 1 && S.sec_off.size() < 2 && !S.floor_on) {
+  if (!collide && threads > 1 && S.nrods > 1 && S.sec_off.size() < 2 && !S.floor_on && !S.jacobi) {
     int nt = std::min(threads, S.nrods);
     std::vector<std::thread> pool;
     std::vector<int64_t> proj(nt, 0);
@@ -845,7 +909,7 @@ template <class R> void substep(Scene<R>& S, R h, int iters, bool collide, int s
       int r0 = int(int64_t(S.nrods) * t / nt), r1 = int(int64_t(S.nrods) * (t + 1) / nt);
       pool.emplace_back([&, r0, r1, t]() {
         predict_rods(S, h, r0, r1);
-        for (int it = 0; it < iters; ++it) proj[t] += solve_colours(S, ih2, r0, r1);
+        for (int it = 0; it < iters; ++it) proj[t] += solve_colours(S, ih2, r0, r1);   // (Gauss-Seidel only)
         velocity_rods(S, h, r0, r1);
       });
     }
@@ -858,7 +922,7 @@ template <class R> void substep(Scene<R>& S, R h, int iters, bool collide, int s
   else S.pairs.clear();
   for (int it = 0; it < iters; ++it) {
     if (S.floor_on) S.projections += project_floor(S);
-    S.projections += solve_colours(S, ih2, 0, S.nrods);
+    S.projections += S.jacobi ? solve_jacobi(S, ih2) : solve_colours(S, ih2, 0, S.nrods);
     if (collide) project_contacts(S, search_iters, delta);
   }
   if constexpr (std::is_floating_point<R>::value) bundle(S);
@@ -967,6 +1031,22 @@ template <class R> static void set_floor_t(Scene<R>& S, const double* n, double 
   S.floor_d = d / l;
 }
 
+// `iters` rod-constraint iterations (no prediction, no contacts) at the current state, from
+// zero multipliers and the inertias of the current scales (as orc_project_one).
+template <class R> static int64_t rod_iterations_t(Scene<R>& S, double h_sub, int iters) {
+  for (int i = 0; i < S.P; ++i) {
+    if (S.has_edge(i)) {
+      R sm = R(0.5) * (S.s[i] + S.s[i + 1]);
+      R I = S.inert_base[i] * sm * sm;
+      S.I1inv[i] = R(4.0) / I; S.I3inv[i] = R(2.0) / I;
+    }
+    for (int t = 0; t < 8; ++t) S.lam[size_t(i) * 8 + t] = R(0.0);
+  }
+  const R ih2 = R(1.0 / (h_sub * h_sub));
+  int64_t n = 0;
+  for (int it = 0; it < iters; ++it) n += S.jacobi ? solve_jacobi(S, ih2) : solve_colours(S, ih2, 0, S.nrods);
+  return n;
+}
 static Desc make_desc(int num_rods, const int32_t* off, const double* rest_pos, const double* rest_radius, const uint8_t* pinned,
                       const double* activation, const double* compliance, const int32_t* group, double density, const double* gravity) {
   Desc d;
@@ -1029,6 +1109,15 @@ void orc_section_fit(void* hp, int k, double* out) {
 void orc_set_floor(void* hp, const double* n, double d) {
   Handle* h = (Handle*)hp;
   if (h->d) set_floor_t(*h->d, n, d); else set_floor_t(*h->f, n, d);
+}
+// Solver of the rod constraints: 0 = coloured Gauss-Seidel, 1 = Jacobi with averaging.
+void orc_set_solver(void* hp, int jacobi) {
+  Handle* h = (Handle*)hp;
+  if (h->d) h->d->jacobi = jacobi != 0; else h->f->jacobi = jacobi != 0;
+}
+int64_t orc_rod_iteration(void* hp, double h_sub, int iters) {
+  Handle* h = (Handle*)hp;
+  return h->d ? rod_iterations_t(*h->d, h_sub, iters) : rod_iterations_t(*h->f, h_sub, iters);
 }
 void orc_floor_pass(void* hp) {
   Handle* h = (Handle*)hp;
@@ -1125,7 +1214,7 @@ void orc_substep_residuals(void* hp, double h, int iters, double* out) {
   double ih2 = 1.0 / (h * h);
   predict_rods(S, h, 0, S.nrods);
   for (int it = 0; it < iters; ++it) {
-    solve_colours(S, ih2, 0, S.nrods);
+    if (S.jacobi) solve_jacobi(S, ih2); else solve_colours(S, ih2, 0, S.nrods);
     out[it] = rod_residual(S, ih2);
   }
   velocity_rods(S, h, 0, S.nrods);

@@ -40,6 +40,8 @@ class SceneDesc:
     section_pills: np.ndarray = None    # int32
     # half-plane floor (Sec. 7): (nx, ny, nz, d), pills stay in n . x >= d; None = no floor
     floor: tuple = None
+    # rod-constraint solver: "gauss_seidel" (coloured) or "jacobi" (with averaging, Sec. 7)
+    solver: str = "gauss_seidel"
 
     @property
     def num_rods(self) -> int:
