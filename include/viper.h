@@ -89,6 +89,12 @@ typedef struct {
   int32_t floor_on;
   double floor_normal[3];
   double floor_offset;
+  /* Rod-constraint solver: 0 = coloured Gauss-Seidel (default), 1 = Jacobi with averaging
+   * (Sec. 7: every constraint projected from the state at the start of the iteration, each
+   * degree of freedom moved by the mean correction of the constraints acting on it).  A
+   * Jacobi scene steps in VIPER_MODE_ITERATION or VIPER_MODE_GRAPH; the pool and the adjoint
+   * reject it. */
+  int32_t solver;
 } viper_scene_desc;
 
 /* Bytes of device workspace the scene needs (host-only computation; validates the

@@ -107,6 +107,97 @@ __device__ __forceinline__ void store_iter(const Dev<T>& d, const Slot<T>& L, in
   for (int i = 0; i < 8; ++i) d.lam[(size_t)i * d.P + p] = L.l[i];
 }
 
+// ITERATION mode, Jacobi variant of stage 2 (Sec. 7: constraints computed in parallel, their
+// displacements averaged by a reduction).  Every rod constraint of the lane's slots is
+// projected on register copies of the state at the start of the iteration (one constraint
+// type at a time, through the same closed forms as the Gauss-Seidel passes); each slot then
+// moves by the mean of the corrections of the active constraints acting on it (positions and
+// scales; rotations by the mean quaternion increment, renormalised).  Each constraint keeps
+// its own multiplier update.  Corrections of the next lane's slot A (from this lane's B-edge
+// and B-vertex bend-twist) travel back by one lane shift.
+template <class T>
+struct JacobiAcc {
+  T dx0 = T(0), dx1 = T(0), dx2 = T(0), ds = T(0), dq0 = T(0), dq1 = T(0), dq2 = T(0), dq3 = T(0);
+  T nx = T(0), ns = T(0), nq = T(0);
+};
+
+template <class T>
+__device__ __forceinline__ void jacobi_edge(Slot<T>& L, const Slot<T>& L0, T b0, T b1, T b2, T sb, T wb, T wsb,
+                                            JacobiAcc<T>& aL, JacobiAcc<T>& aR) {
+  const uint32_t types[3] = {F_SS, F_VOL, F_SG};
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    if (!(L0.f & types[t])) continue;
+    Slot<T> a = L0;
+    a.f = (L0.f & ~(F_SS | F_VOL | F_SG)) | types[t];
+    T c0 = b0, c1 = b1, c2 = b2, cs = sb;
+    edge_update(a, c0, c1, c2, cs, wb, wsb);
+    if (t == 0) {
+      L.l[0] = a.l[0]; L.l[1] = a.l[1]; L.l[2] = a.l[2];
+      aL.dq0 += a.q0 - L0.q0; aL.dq1 += a.q1 - L0.q1; aL.dq2 += a.q2 - L0.q2; aL.dq3 += a.q3 - L0.q3; aL.nq += T(1);
+    } else {
+      L.l[2 + t] = a.l[2 + t];
+      aL.ds += a.s - L0.s; aR.ds += cs - sb; aL.ns += T(1); aR.ns += T(1);
+    }
+    if (t < 2) {
+      aL.dx0 += a.x0 - L0.x0; aL.dx1 += a.x1 - L0.x1; aL.dx2 += a.x2 - L0.x2; aL.nx += T(1);
+      aR.dx0 += c0 - b0; aR.dx1 += c1 - b1; aR.dx2 += c2 - b2; aR.nx += T(1);
+    }
+  }
+}
+
+template <class T>
+__device__ __forceinline__ void jacobi_bt(Slot<T>& L, const Slot<T>& L0, T b0, T b1, T b2, T b3, T sb, T Ib, T wsb,
+                                          JacobiAcc<T>& aL, JacobiAcc<T>& aR) {
+  Slot<T> a = L0;
+  T c0 = b0, c1 = b1, c2 = b2, c3 = b3, cs = sb;
+  bt_update(a, c0, c1, c2, c3, cs, Ib, wsb);
+  L.l[5] = a.l[5]; L.l[6] = a.l[6]; L.l[7] = a.l[7];
+  aL.dq0 += a.q0 - L0.q0; aL.dq1 += a.q1 - L0.q1; aL.dq2 += a.q2 - L0.q2; aL.dq3 += a.q3 - L0.q3; aL.nq += T(1);
+  aR.dq0 += c0 - b0; aR.dq1 += c1 - b1; aR.dq2 += c2 - b2; aR.dq3 += c3 - b3; aR.nq += T(1);
+  aR.ds += cs - sb; aR.ns += T(1);
+}
+
+template <class T>
+__device__ __forceinline__ void jacobi_apply(Slot<T>& L, const JacobiAcc<T>& a) {
+  if (a.nx > T(0)) {
+    const T f = T(1) / a.nx;
+    L.x0 += f * a.dx0; L.x1 += f * a.dx1; L.x2 += f * a.dx2;
+  }
+  if (a.ns > T(0)) L.s += a.ds / a.ns;
+  if (a.nq > T(0)) {
+    const T f = T(1) / a.nq;
+    const T q0 = L.q0 + f * a.dq0, q1 = L.q1 + f * a.dq1, q2 = L.q2 + f * a.dq2, q3 = L.q3 + f * a.dq3;
+    const T in = T(1) / sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+    L.q0 = q0 * in; L.q1 = q1 * in; L.q2 = q2 * in; L.q3 = q3 * in;
+  }
+}
+
+template <class T>
+__device__ __forceinline__ void jacobi_lane(Lane2<T>& P) {
+  const Slot<T> A0 = P.A, B0 = P.B;
+  // the next lane's slot A as it stands at the start of the iteration
+  const T n0 = dn(A0.x0), n1 = dn(A0.x1), n2 = dn(A0.x2), ns = dn(A0.s);
+  const T nq0 = dn(A0.q0), nq1 = dn(A0.q1), nq2 = dn(A0.q2), nq3 = dn(A0.q3);
+  JacobiAcc<T> aA, aB, aN;
+  if (A0.f & F_EDGE) jacobi_edge(P.A, A0, B0.x0, B0.x1, B0.x2, B0.s, B0.w, B0.ws, aA, aB);
+  if (B0.f & F_EDGE) jacobi_edge(P.B, B0, n0, n1, n2, ns, P.wN, P.wsN, aB, aN);
+  if ((A0.f & F_BT) && (A0.f & F_BTEN)) jacobi_bt(P.A, A0, B0.q0, B0.q1, B0.q2, B0.q3, B0.s, B0.I1, B0.ws, aA, aB);
+  if ((B0.f & F_BT) && (B0.f & F_BTEN)) jacobi_bt(P.B, B0, nq0, nq1, nq2, nq3, ns, P.I1N, P.wsN, aB, aN);
+  // this lane's contributions to the next lane's A arrive there; add the previous lane's here
+  JacobiAcc<T> r;
+  r.dx0 = up(aN.dx0); r.dx1 = up(aN.dx1); r.dx2 = up(aN.dx2); r.ds = up(aN.ds);
+  r.dq0 = up(aN.dq0); r.dq1 = up(aN.dq1); r.dq2 = up(aN.dq2); r.dq3 = up(aN.dq3);
+  r.nx = up(aN.nx); r.ns = up(aN.ns); r.nq = up(aN.nq);
+  if ((A0.f & F_VALID) && !(A0.f & F_FIRST)) {
+    aA.dx0 += r.dx0; aA.dx1 += r.dx1; aA.dx2 += r.dx2; aA.ds += r.ds;
+    aA.dq0 += r.dq0; aA.dq1 += r.dq1; aA.dq2 += r.dq2; aA.dq3 += r.dq3;
+    aA.nx += r.nx; aA.ns += r.ns; aA.nq += r.nq;
+  }
+  jacobi_apply(P.A, aA);
+  jacobi_apply(P.B, aB);
+}
+
 template <class T>
 __global__ void __launch_bounds__(256) rod_iteration_kernel(const Dev<T>* __restrict__ D, const Blk* __restrict__ tab,
                                                             T h, const ContactDev* __restrict__ CD) {
@@ -128,7 +219,8 @@ __global__ void __launch_bounds__(256) rod_iteration_kernel(const Dev<T>* __rest
   }
   load_lane_consts(d, P, pA, pB, rcp(h * h));
   P.I1N = dn(P.A.I1);
-  iteration_lane(P);
+  if (d.jacobi) jacobi_lane(P);       // wave-uniform: one scene per block
+  else iteration_lane(P);
   store_iter(d, P.A, pA);
   store_iter(d, P.B, pB);
 }

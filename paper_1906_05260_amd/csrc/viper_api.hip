@@ -95,6 +95,7 @@ viper_status validate(const viper_scene_desc* d) {
         !(n[0] * n[0] + n[1] * n[1] + n[2] * n[2] > 0))
       return fail(VIPER_ERR_INVALID, "floor_normal must be finite and nonzero, floor_offset finite");
   }
+  if (d->solver != 0 && d->solver != 1) return fail(VIPER_ERR_INVALID, "solver must be 0 (Gauss-Seidel) or 1 (Jacobi)");
   if (d->num_sections < 0) return fail(VIPER_ERR_INVALID, "num_sections < 0");
   if (d->num_rods == 0) {
     if (d->num_sections > 0) return fail(VIPER_ERR_INVALID, "bundling sections need pills");
@@ -410,6 +411,7 @@ struct viper_scene_s {
   int collisions = 0;
   int nsec = 0, nsecp = 0;    // bundling sections and their entries
   int floor_on = 0;           // half-plane floor (unit normal, offset)
+  int jacobi = 0;             // rod constraints by Jacobi with averaging
   double floor_n[3] = {0.0, 0.0, 0.0}, floor_d = 0.0;
   int cap = 16;
   int R = 0, P = 0, W = 0, E = 0;
@@ -469,6 +471,7 @@ void fill_dev(viper_scene_s* S, Dev<T>& d) {
   d.sec_fit = S->nsec ? (double*)(b + S->o.sec_fit) : nullptr;
   d.floor_on = S->floor_on;
   d.fnx = S->floor_n[0]; d.fny = S->floor_n[1]; d.fnz = S->floor_n[2]; d.fd = S->floor_d;
+  d.jacobi = S->jacobi;
 }
 
 template <class T>
@@ -536,7 +539,8 @@ viper_status batch_step(const BatchDev& b, bool collisions, bool iteration_only,
   iteration_only = iteration_only || collisions || bundled;
   if (mode == VIPER_MODE_AUTO) mode = iteration_only ? VIPER_MODE_ITERATION : VIPER_MODE_FRAME;
   if (iteration_only && mode != VIPER_MODE_ITERATION)
-    return fail(VIPER_ERR_INVALID, "scenes with collisions, bundling sections or a floor step in VIPER_MODE_ITERATION");
+    return fail(VIPER_ERR_INVALID,
+                "scenes with collisions, bundling sections, a floor or the Jacobi solver step in VIPER_MODE_ITERATION");
   if (mode == VIPER_MODE_FRAME) {
     HIP_TRY(launch_rod_frame<T>(b, sub, h, iters, st));
   } else if (mode == VIPER_MODE_SUBSTEP) {
@@ -572,8 +576,8 @@ viper_status capture_frame(viper_scene_s* S, double dt, int sub, int iters) {
   }
   if (!S->capture) HIP_TRY(hipStreamCreateWithFlags(&S->capture, hipStreamNonBlocking));
   HIP_TRY(hipStreamBeginCapture(S->capture, hipStreamCaptureModeThreadLocal));
-  viper_status r = batch_step<T>(S->batch, S->collisions != 0, S->floor_on != 0, dt, sub, iters, VIPER_MODE_ITERATION,
-                                 S->capture);
+  viper_status r = batch_step<T>(S->batch, S->collisions != 0, S->floor_on || S->jacobi, dt, sub, iters,
+                                 VIPER_MODE_ITERATION, S->capture);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(S->capture, &g);
   if (r != VIPER_OK) {
@@ -595,9 +599,9 @@ viper_status capture_frame(viper_scene_s* S, double dt, int sub, int iters) {
 
 template <class T>
 viper_status step_t(viper_scene_s* S, double dt, int sub, int iters, int mode, hipStream_t st) {
-  if (mode == VIPER_MODE_AUTO && (S->collisions || S->nsec || S->floor_on)) mode = VIPER_MODE_GRAPH;
+  if (mode == VIPER_MODE_AUTO && (S->collisions || S->nsec || S->floor_on || S->jacobi)) mode = VIPER_MODE_GRAPH;
   if (mode != VIPER_MODE_GRAPH)
-    return batch_step<T>(S->batch, S->collisions != 0, S->floor_on != 0, dt, sub, iters, mode, st);
+    return batch_step<T>(S->batch, S->collisions != 0, S->floor_on || S->jacobi, dt, sub, iters, mode, st);
   if (!S->graph || S->graph_h != dt / sub || S->graph_sub != sub || S->graph_iters != iters) {
     viper_status r = capture_frame<T>(S, dt, sub, iters);
     if (r != VIPER_OK) return r;
@@ -654,6 +658,7 @@ viper_status viper_create_scene(const viper_scene_desc* desc, void* workspace, s
   S->collisions = desc->collisions != 0;
   S->nsec = desc->num_sections > 0 ? desc->num_sections : 0;
   S->nsecp = S->nsec ? desc->section_offsets[S->nsec] : 0;
+  S->jacobi = desc->solver == 1;
   if (desc->floor_on) {
     const double* n = desc->floor_normal;
     const double l = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
@@ -834,6 +839,7 @@ viper_status adjoint_check(viper_scene S, int32_t frames, int32_t substeps, int3
   if (S->collisions) return fail(VIPER_ERR_INVALID, "the adjoint covers collision-free scenes");
   if (S->nsec) return fail(VIPER_ERR_INVALID, "the adjoint does not cover bundling sections");
   if (S->floor_on) return fail(VIPER_ERR_INVALID, "the adjoint does not cover the floor");
+  if (S->jacobi) return fail(VIPER_ERR_INVALID, "the adjoint covers the Gauss-Seidel solver");
   if (frames < 1 || substeps < 1 || iterations < 0)
     return fail(VIPER_ERR_INVALID, "frames >= 1, substeps >= 1 and iterations >= 0 required");
   return VIPER_OK;
@@ -1048,8 +1054,8 @@ viper_status viper_pool_create(void* workspace, size_t bytes, int32_t max_scenes
 viper_status viper_pool_admit(viper_pool P, const viper_scene_desc* desc, void* stream, int32_t* slot) {
   if (!P || !desc || !slot) return fail(VIPER_ERR_INVALID, "pool, desc and slot are required");
   if (desc->precision != P->precision) return fail(VIPER_ERR_INVALID, "scene precision differs from the pool's");
-  if (desc->num_sections > 0 || desc->floor_on)
-    return fail(VIPER_ERR_INVALID, "scenes with bundling sections or a floor are stepped with viper_step");
+  if (desc->num_sections > 0 || desc->floor_on || desc->solver == 1)
+    return fail(VIPER_ERR_INVALID, "scenes with bundling sections, a floor or the Jacobi solver are stepped with viper_step");
   size_t fp = 0;
   viper_status r = viper_scene_footprint(desc, &fp);
   if (r != VIPER_OK) return r;

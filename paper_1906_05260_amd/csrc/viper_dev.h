@@ -60,6 +60,8 @@ struct Dev {
   // half-plane floor (Sec. 7): n . x >= fd + s rbar, unit n
   int floor_on;
   double fnx, fny, fnz, fd;
+  // rod-constraint solver in ITERATION mode: 0 = coloured Gauss-Seidel, 1 = Jacobi with averaging
+  int jacobi;
 };
 constexpr int kSecFit = 20;
 

@@ -63,6 +63,7 @@ class SceneDescC(ctypes.Structure):
         ("floor_on", ctypes.c_int32),
         ("floor_normal", ctypes.c_double * 3),
         ("floor_offset", ctypes.c_double),
+        ("solver", ctypes.c_int32),
     ]
 
 
@@ -153,6 +154,7 @@ class _DescHolder:
             for i in range(3):
                 c.floor_normal[i] = float(desc.floor[i])
             c.floor_offset = float(desc.floor[3])
+        c.solver = 1 if getattr(desc, "solver", "gauss_seidel") == "jacobi" else 0
         self.c = c
 
 
