@@ -315,6 +315,28 @@ def bundling_timing(torch, viper, scenes, dev, frames=10):
     return res
 
 
+def solver_timing(torch, viper, scenes, dev, frames=5):
+    """The helix workload (4096 x 64, FP32, 20 substeps x 8 iterations) in ITERATION mode
+    (one launch per constraint iteration), coloured Gauss-Seidel beside Jacobi with averaging
+    (Sec. 7): ms per frame, HIP events on the launch stream."""
+    import dataclasses
+    base = scenes.helix_rods(4096, 64, seed=1)
+    res = {"workload": "helix4096x64_iteration_mode"}
+    for solver in ("gauss_seidel", "jacobi"):
+        sc = viper.Scene(dataclasses.replace(base, solver=solver), "f32", device=dev)
+        sc.step(1.0 / 60.0, 20, 8, mode=viper.MODE_ITERATION)
+        st = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(frames):
+            sc.step(1.0 / 60.0, 20, 8, mode=viper.MODE_ITERATION)
+        e1.record(st)
+        torch.cuda.synchronize()
+        sc.sync()
+        res["frame_ms_" + solver] = e0.elapsed_time(e1) / frames
+    return res
+
+
 def serving_run(torch, scenes, serve, seconds):
     """Poisson arrivals (200/s) of helix and muscle scenes of 1k-200k pills (log-uniform),
     60 frames each; continuous batching vs the plain per-scene path on the same requests."""
@@ -442,6 +464,8 @@ def main():
         log("contacts and skinning done")
         out["bundling"] = bundling_timing(torch, viper, scenes, dev)
         log("bundling done")
+    out["solvers"] = solver_timing(torch, viper, scenes, dev)
+    log("solvers done")
     if not args.no_adjoint:
         out["adjoint"] = adjoint_timing(torch, viper, scenes, dev)
         log("adjoint done")
