@@ -111,7 +111,8 @@ viper_status viper_create_scene(const viper_scene_desc* desc, void* workspace, s
 
 /* Execution strategy for viper_step_ex. */
 typedef enum {
-  VIPER_MODE_AUTO = 0,      /* FRAME without collisions, GRAPH with */
+  VIPER_MODE_AUTO = 0,      /* FRAME for plain rod scenes; GRAPH with collisions, bundling sections,
+                               a floor or the Jacobi solver (these need the ITERATION launches) */
   VIPER_MODE_FRAME = 1,     /* one launch per call: all substeps with the rod state in registers */
   VIPER_MODE_SUBSTEP = 2,   /* one launch per substep: state streamed through HBM every substep */
   VIPER_MODE_ITERATION = 3, /* separate launches per stage and iteration (the contact path) */
@@ -123,7 +124,11 @@ typedef enum {
 /* Advance one frame of length dt (s) in `substeps` substeps of h = dt/substeps, each with
  * `iterations` constraint iterations (Sec. 6: prediction, then per-constraint dual
  * updates with lambda reset to 0 each substep, relaxation 1).  dt > 0, substeps >= 1,
- * iterations >= 0. */
+ * iterations >= 0.  Per substep: prediction; contact detection (collisions); per iteration
+ * the floor projection, the rod constraints (coloured Gauss-Seidel or Jacobi) and the
+ * contact pass; after the iterations the bundling projection; the velocity update.
+ * viper_step = viper_step_ex with VIPER_MODE_AUTO.  A mode the scene cannot run in (FRAME or
+ * SUBSTEP with collisions, sections, a floor or the Jacobi solver) is VIPER_ERR_INVALID. */
 viper_status viper_step(viper_scene scene, double dt, int32_t substeps, int32_t iterations, void* stream);
 viper_status viper_step_ex(viper_scene scene, double dt, int32_t substeps, int32_t iterations, int32_t mode,
                            void* stream);
