@@ -71,6 +71,7 @@ def lib():
         L.orc_set_floor.argtypes = [P, P, D]
         L.orc_floor_pass.argtypes = [P]
         L.orc_set_solver.argtypes = [P, I]
+        L.orc_skin_weights.argtypes = [P, I, P, P, P]
         L.orc_rod_iteration.restype = ctypes.c_int64
         L.orc_rod_iteration.argtypes = [P, D, I]
         L.orc_section_fit.argtypes = [P, I, P]
@@ -131,6 +132,14 @@ class OracleScene:
         if getattr(desc, "floor", None) is not None:
             n = np.ascontiguousarray(desc.floor[:3], dtype=np.float64)
             L.orc_set_floor(self.h, _p(n), float(desc.floor[3]))
+
+    def skin_weights(self, rest_v):
+        """Initial skinning weights (Sec. 7.4) of rest vertices: (capsule ids [V,4], weights [V,4])."""
+        v = np.ascontiguousarray(rest_v, dtype=np.float64).reshape(-1, 3)
+        caps = np.zeros((v.shape[0], 4), np.int32)
+        w = np.zeros((v.shape[0], 4))
+        lib().orc_skin_weights(self.h, int(v.shape[0]), _p(v), _p(caps), _p(w))
+        return caps, w
 
     def rod_iterations(self, h, iters=1):
         """`iters` iterations of the rod constraints at the current state (substep h), from

@@ -1242,6 +1242,48 @@ int orc_brute_pairs(int num_rods, const int32_t* off, const int32_t* group, cons
   return n;
 }
 
+// Skinning weights (Sec. 7.4): each vertex's initial weights are proportional to the inverse
+// square distance from the vertex to the surface of each capsule (rest pose).  Readings: the
+// distance is |v - c(t)| - r(t) at the capsule's closest sphere t (App. D projection), clamped
+// below at 1e-9 m (a vertex inside a capsule); the four largest weights are kept and
+// normalised to sum 1 (4-influence LBS); the paper's fairing over the mesh is not applied
+// (it needs the mesh connectivity).  Ties keep the lower capsule id.  Outputs the capsule
+// ids (first pill of each capsule) and weights, 4 per vertex, strongest first.
+void orc_skin_weights(void* hp, int V, const double* v, int32_t* caps, double* w) {
+  Handle* h = (Handle*)hp;
+  Scene<double>& S = *h->d;
+  std::vector<int> cap;
+  for (int k = 0; k < S.nrods; ++k)
+    for (int p = S.off[k]; p + 1 < S.off[k + 1]; ++p) cap.push_back(p);
+  for (int i = 0; i < V; ++i) {
+    const V3<double> x = v3(v[3 * i], v[3 * i + 1], v[3 * i + 2]);
+    int best[4] = {-1, -1, -1, -1};
+    double bw[4] = {-1.0, -1.0, -1.0, -1.0};
+    for (int e : cap) {
+      const V3<double> c1 = S.xrest[e], c2 = S.xrest[e + 1];
+      const double r1 = S.rbar[e], r2 = S.rbar[e + 1];
+      const double t = pill_project(x, c1, r1, c2, r2);
+      const V3<double> c = c1 + t * (c2 - c1);
+      const double r = r1 + t * (r2 - r1);
+      const double d = std::max(norm(x - c) - r, 1e-9);
+      const double wt = 1.0 / (d * d);
+      // insert into the strongest four (strictly greater moves ahead: ties keep the lower id)
+      for (int k = 0; k < 4; ++k)
+        if (wt > bw[k]) {
+          for (int m = 3; m > k; --m) { bw[m] = bw[m - 1]; best[m] = best[m - 1]; }
+          bw[k] = wt; best[k] = e;
+          break;
+        }
+    }
+    double sum = 0.0;
+    for (int k = 0; k < 4; ++k) if (best[k] >= 0) sum += bw[k];
+    for (int k = 0; k < 4; ++k) {
+      caps[4 * i + k] = best[k] >= 0 ? best[k] : best[0];
+      w[4 * i + k] = best[k] >= 0 ? bw[k] / sum : 0.0;
+    }
+  }
+}
+
 double orc_pill_project(const double* x, const double* c1, double r1, const double* c2, double r2) {
   return pill_project(v3(x[0], x[1], x[2]), v3(c1[0], c1[1], c1[2]), r1, v3(c2[0], c2[1], c2[2]), r2);
 }

@@ -869,3 +869,43 @@ def test_jacobi_converges_linearly_on_the_stretched_rod():
     assert rj[-1] < 1e-3 * rj[:10].max() and rg[-1] < 1e-3 * rg[:10].max()
     assert -1.3 < slope(rj) < -0.7
     assert slope(rg) < slope(rj)
+
+
+# ----------------------------------------------------------------------------- skinning weights (Sec. 7.4)
+
+def _capsule_dist_sampled(x, c1, r1, c2, r2, n=200001):
+    """Distance from x to the surface of a tapered capsule by dense sampling of its spheres."""
+    t = np.linspace(0.0, 1.0, n)[:, None]
+    c = c1 + t * (c2 - c1)
+    r = r1 + t[:, 0] * (r2 - r1)
+    return (np.linalg.norm(x - c, axis=1) - r).min()
+
+
+def test_skin_weights_match_sampled_distances():
+    desc = scenes.helix_rods(3, 6, seed=4)
+    o = oracle.OracleScene(desc, "f64")
+    rng = np.random.default_rng(8)
+    V = desc.rest_pos[rng.integers(0, desc.num_pills, 12)] + rng.normal(0.0, 0.01, (12, 3))
+    caps, w = o.skin_weights(V)
+    off = np.asarray(desc.rod_offsets)
+    cap_ids = np.concatenate([np.arange(off[k], off[k + 1] - 1) for k in range(desc.num_rods)])
+    for i in range(len(V)):
+        d = np.array([max(_capsule_dist_sampled(V[i], desc.rest_pos[e], desc.rest_radius[e], desc.rest_pos[e + 1],
+                                                desc.rest_radius[e + 1]), 1e-9) for e in cap_ids])
+        order = np.argsort(-1.0 / d ** 2, kind="stable")[:4]
+        ww = 1.0 / d[order] ** 2
+        assert np.array_equal(caps[i], cap_ids[order])
+        assert np.allclose(w[i], ww / ww.sum(), rtol=1e-6, atol=0)
+
+
+def test_skin_weights_nearest_and_equal_distance_limits():
+    """On one capsule's surface the vertex is fully attached to it (the paper's starting
+    assignment); equidistant from two mirror-image capsules it takes half of each (the
+    case the inverse-square assignment is for)."""
+    pos = np.array([[0.0, 0.0, 0.0], [0.02, 0.0, 0.0], [0.0, 0.05, 0.0], [0.02, 0.05, 0.0]])
+    desc = scenes.SceneDesc(np.asarray([0, 2, 4], np.int32), pos, np.full(4, 0.005), np.zeros(4, np.uint8),
+                            np.ones(2), np.full((2, 4), 1e-6), np.arange(2, dtype=np.int32), name="pair")
+    o = oracle.OracleScene(desc, "f64")
+    caps, w = o.skin_weights(np.array([[0.01, 0.005, 0.0], [0.01, 0.025, 0.0]]))
+    assert caps[0, 0] == 0 and w[0, 0] > 1 - 1e-9
+    assert set(caps[1, :2].tolist()) == {0, 2} and abs(w[1, 0] - 0.5) < 1e-12 and abs(w[1, 1] - 0.5) < 1e-12
