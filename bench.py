@@ -222,6 +222,17 @@ def contact_skin_timing(torch, viper, scenes, dev, frames=10):
     eager_ms = e2.elapsed_time(e3) / frames
     V = int(mesh.rest_v.shape[0])
     skin_bytes = 56 * V + 48 * sc.capsules     # rest vertex 12 + 4 ids 16 + 4 weights 16 + out 12; transforms
+    # initial skinning weights of the same mesh (Sec. 7.4; brute force over every capsule), on a
+    # fresh scene at the rest pose
+    rest_sc = viper.Scene(desc, "f32", device=dev, collisions=True)
+    e7, e8 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    rest_sc.skin_weights(mesh.rest_v[:1024])
+    e7.record(st)
+    rest_sc.skin_weights(mesh.rest_v)
+    e8.record(st)
+    torch.cuda.synchronize()
+    weights_ms = e7.elapsed_time(e8)
+    del rest_sc
     # the same skinning with a mesh far beyond the caches: the 200k-vertex mesh tiled to
     # ~16.8M vertices (0.94 GB of vertex data); every tile references the same capsules
     reps = (16 << 20) // V
@@ -249,7 +260,7 @@ def contact_skin_timing(torch, viper, scenes, dev, frames=10):
             "frame_ms_eager_launches": eager_ms, "frame_ms_wall_graph": wall_graph,
             "pill_substeps_per_s": desc.num_pills * sub / (frame_ms * 1e-3),
             "launches_per_frame": sub * (2 + 11 + 2 * iters),
-            "skin_vertices": V, "skin_ms": skin_ms,
+            "skin_vertices": V, "skin_ms": skin_ms, "skin_weights_ms": weights_ms,
             "skin_algorithmic_GB_per_s": skin_bytes / (skin_ms * 1e-3) / 1e9,
             "skin_large": {"vertices": VL, "ms": skin_l_ms, "algorithmic_bytes": skin_l_bytes,
                            "GB_per_s": skin_l_bytes / (skin_l_ms * 1e-3) / 1e9,

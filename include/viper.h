@@ -165,6 +165,15 @@ viper_status viper_create_skin(viper_scene scene, int32_t V, const float* rest_v
 /* out [V*3] float (device): v = sum_k w_k [s R(q) R(q_rest)^T | m - s R(q) R(q_rest)^T m_rest] [v_rest; 1]
  * per capsule (similarity transform of eq. shapematch, blended as in Sec. 7.4). */
 viper_status viper_skin(viper_scene scene, int32_t skin_id, float* out_dev, void* stream);
+/* Initial skinning weights (Sec. 7.4): for each of V vertices rest_v_dev [V*3] float (device),
+ * weights proportional to the inverse square distance from the vertex to the surface of each
+ * capsule at the scene's current pose (call it right after creation for the rest pose),
+ * the four strongest kept and normalised: caps_dev [V*4] int32 capsule ids (first pill of the
+ * capsule), w_dev [V*4] float, strongest first (device; caller-owned).  The paper's fairing of
+ * these weights over the mesh is not applied (it needs the mesh connectivity).  Brute force
+ * over all capsules: O(V * capsules). */
+viper_status viper_skin_weights(viper_scene scene, int32_t V, const float* rest_v_dev, int32_t* caps_dev, float* w_dev,
+                                void* stream);
 
 /* Wait for `stream` and report device-side conditions raised since the last sync:
  * VIPER_ERR_NAN, VIPER_ERR_CAPACITY, or VIPER_ERR_DEVICE. Clears them. */

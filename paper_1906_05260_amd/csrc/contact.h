@@ -27,5 +27,8 @@ viper_status contact_init(ContactDev& c, char* ws, const ContactOffsets& o, cons
                           hipStream_t st);
 hipError_t contact_copy_det(const ContactDev& c, bool x, void* dst, int P, size_t ts, hipStream_t st);
 viper_status contact_get_pairs(const ContactDev& c, int32_t* pairs, int32_t cap, int32_t* n, hipStream_t st);
+// Initial skinning weights of V rest vertices at the scene's current pose (Sec. 7.4).
+template <class T>
+hipError_t launch_skin_weights(const Dev<T>& d, int V, const float* rest_v, int32_t* caps, float* w, hipStream_t st);
 
 }  // namespace viper

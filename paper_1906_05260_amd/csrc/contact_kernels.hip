@@ -567,6 +567,48 @@ __global__ void __launch_bounds__(256) contact_pair_kernel(const Dev<T>* __restr
   }
 }
 
+// Initial skinning weights (Sec. 7.4): a vertex's weight for each capsule is proportional to
+// the inverse square distance from the vertex to the capsule's surface, |v - c(t)| - r(t) at the
+// capsule's closest sphere t (App. D projection, FP64), clamped below at 1e-9 m; the four
+// strongest are kept (ties keep the lower capsule id) and normalised.  One thread per vertex
+// over every capsule of the scene, at the scene's current pose.
+template <class T>
+__global__ void __launch_bounds__(256) skin_weights_kernel(const Dev<T> d, int V, const float* __restrict__ rest_v,
+                                                           int32_t* __restrict__ caps, float* __restrict__ w) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i >= V) return;
+  const D3 x = d3((double)rest_v[3 * (size_t)i], (double)rest_v[3 * (size_t)i + 1], (double)rest_v[3 * (size_t)i + 2]);
+  int best[4] = {-1, -1, -1, -1};
+  double bw[4] = {-1.0, -1.0, -1.0, -1.0};
+  for (int p = 0; p + 1 < d.P; ++p) {
+    if (!(d.flags[p] & F_EDGE)) continue;
+    const double* an = d.anchor + 3 * (size_t)d.rod_of[p];
+    const D3 c1 = d3(an[0] + (double)d.px[p], an[1] + (double)d.py[p], an[2] + (double)d.pz[p]);
+    const D3 c2 = d3(an[0] + (double)d.px[p + 1], an[1] + (double)d.py[p + 1], an[2] + (double)d.pz[p + 1]);
+    const double r1 = (double)d.s[p] * (double)d.rbar[p], r2 = (double)d.s[p + 1] * (double)d.rbar[p + 1];
+    const double t = pill_param(x, c1, r1, c2, r2);
+    const D3 rel = sub(x, lerp(c1, c2, t));
+    const double dist = fmax(sqrt(dotp(rel, rel)) - (r1 + t * (r2 - r1)), 1e-9);
+    const double wt = 1.0 / (dist * dist);
+    if (wt > bw[3]) {
+      int k = 3;
+      while (k > 0 && wt > bw[k - 1]) {
+        bw[k] = bw[k - 1]; best[k] = best[k - 1];
+        --k;
+      }
+      bw[k] = wt; best[k] = p;
+    }
+  }
+  double sum = 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) if (best[k] >= 0) sum += bw[k];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    caps[4 * (size_t)i + k] = best[k] >= 0 ? best[k] : best[0];
+    w[4 * (size_t)i + k] = best[k] >= 0 ? (float)(bw[k] / sum) : 0.0f;
+  }
+}
+
 // Apply the last pass's averaged corrections now (before a bundling projection, which
 // reads and overwrites the state of its section pills); the velocity update then finds
 // nothing left to apply.
@@ -736,6 +778,15 @@ hipError_t launch_contact_flush(const BatchDev& b, hipStream_t st) {
                      b.tab[TB_DET]);
   return hipGetLastError();
 }
+
+template <class T>
+hipError_t launch_skin_weights(const Dev<T>& d, int V, const float* rest_v, int32_t* caps, float* w, hipStream_t st) {
+  if (V <= 0) return hipSuccess;
+  hipLaunchKernelGGL(skin_weights_kernel<T>, dim3((V + 255) / 256), dim3(256), 0, st, d, V, rest_v, caps, w);
+  return hipGetLastError();
+}
+template hipError_t launch_skin_weights<float>(const Dev<float>&, int, const float*, int32_t*, float*, hipStream_t);
+template hipError_t launch_skin_weights<double>(const Dev<double>&, int, const float*, int32_t*, float*, hipStream_t);
 
 hipError_t contact_copy_det(const ContactDev& c, bool x, void* dst, int P, size_t ts, hipStream_t st) {
   return hipMemcpyAsync(dst, x ? (void*)c.xdet : c.sdet, (x ? 3 * 8 : ts) * (size_t)P, hipMemcpyDefault, st);

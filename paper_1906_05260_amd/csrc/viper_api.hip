@@ -797,6 +797,16 @@ viper_status viper_skin(viper_scene S, int32_t skin_id, float* out, void* stream
   return VIPER_OK;
 }
 
+viper_status viper_skin_weights(viper_scene S, int32_t V, const float* rest_v, int32_t* caps, float* w, void* stream) {
+  if (!S || V < 0) return fail(VIPER_ERR_INVALID, "scene and V >= 0 are required");
+  if (V > 0 && (!rest_v || !caps || !w)) return fail(VIPER_ERR_INVALID, "rest_v, caps and w are required");
+  if (S->E == 0 && V > 0) return fail(VIPER_ERR_INVALID, "the scene has no capsules");
+  hipStream_t st = (hipStream_t)stream;
+  if (S->precision == VIPER_F64) HIP_TRY(launch_skin_weights<double>(S->dd, V, rest_v, caps, w, st));
+  else HIP_TRY(launch_skin_weights<float>(S->df, V, rest_v, caps, w, st));
+  return VIPER_OK;
+}
+
 viper_status viper_sync(viper_scene S, void* stream) {
   if (!S) return fail(VIPER_ERR_INVALID, "scene is NULL");
   hipStream_t st = (hipStream_t)stream;

@@ -33,6 +33,7 @@ ABI_SYMBOLS = [
     "viper_pool_create", "viper_pool_admit", "viper_pool_step", "viper_pool_retire", "viper_pool_scene",
     "viper_pool_info", "viper_pool_destroy",
     "viper_adjoint_sizes", "viper_step_checkpointed", "viper_step_backward", "viper_pool_step_ex",
+    "viper_skin_weights",
 ]
 
 
@@ -292,6 +293,19 @@ class Scene:
             out = torch.empty((V, 3), dtype=torch.float32, device=self.device)
         check(lib().viper_skin(self.handle, int(skin_id), ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
         return out
+
+    def skin_weights(self, rest_v, stream=None):
+        """Initial skinning weights (include/viper.h, viper_skin_weights) of rest vertices at the
+        scene's current pose: (capsule ids [V,4] int32, weights [V,4] float32) device tensors."""
+        import torch
+        rv = torch.as_tensor(rest_v, dtype=torch.float32).to(self.device).contiguous()
+        V = int(rv.shape[0])
+        caps = torch.empty((V, 4), dtype=torch.int32, device=self.device)
+        w = torch.empty((V, 4), dtype=torch.float32, device=self.device)
+        check(lib().viper_skin_weights(self.handle, V, ctypes.c_void_p(rv.data_ptr()), ctypes.c_void_p(caps.data_ptr()),
+                                       ctypes.c_void_p(w.data_ptr()), _stream_ptr(stream)))
+        self._keep_alive = rv
+        return caps, w
 
     def sync(self, stream=None):
         check(lib().viper_sync(self.handle, _stream_ptr(stream)))

@@ -198,3 +198,26 @@ def test_graph_replay_equals_eager_launches():
             for k in ("x", "v", "s", "sd", "q", "om"):
                 assert np.array_equal(sa[k], sb[k]), (prec, frame, k)
             assert np.array_equal(a.contacts(), b.contacts())
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_skin_weights_match_oracle(prec):
+    """Initial skinning weights (Sec. 7.4) of a 4000-vertex muscle mesh at the rest pose: in
+    FP64 the strongest four capsules equal the oracle's for every vertex and the weights agree
+    to float rounding; in FP32 (positions rounded) the same where the ranking is not a near tie."""
+    desc, mesh = small_muscles(seed=6)
+    say("case: skin weights", prec, desc.num_pills, mesh.rest_v.shape[0])
+    sc = viper.Scene(desc, prec)
+    caps, w = sc.skin_weights(mesh.rest_v)
+    caps, w = caps.cpu().numpy(), w.cpu().numpy()
+    o = oracle.OracleScene(desc, "f64")
+    rc, rw = o.skin_weights(mesh.rest_v.astype(np.float64))
+    np.testing.assert_allclose(w.sum(1), 1.0, rtol=0, atol=1e-6)
+    if prec == "f64":
+        assert np.array_equal(caps, rc)
+        assert np.abs(w - rw).max() < 1e-6
+    else:
+        same = np.all(caps == rc, axis=1)
+        say("fp32 weight rankings equal on", same.mean())
+        assert same.mean() > 0.99
+        assert np.abs(w[same] - rw[same]).max() < 1e-3
