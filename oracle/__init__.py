@@ -71,6 +71,7 @@ def lib():
         L.orc_set_floor.argtypes = [P, P, D]
         L.orc_floor_pass.argtypes = [P]
         L.orc_set_solver.argtypes = [P, I]
+        L.orc_set_cross_stretch.argtypes = [P, P]
         L.orc_skin_weights.argtypes = [P, I, P, P, P]
         L.orc_rod_iteration.restype = ctypes.c_int64
         L.orc_rod_iteration.argtypes = [P, D, I]
@@ -132,6 +133,9 @@ class OracleScene:
         if getattr(desc, "floor", None) is not None:
             n = np.ascontiguousarray(desc.floor[:3], dtype=np.float64)
             L.orc_set_floor(self.h, _p(n), float(desc.floor[3]))
+        if getattr(desc, "cross_compliance", None) is not None:
+            self._sr = _f64(desc.cross_compliance).reshape(-1)
+            L.orc_set_cross_stretch(self.h, _p(self._sr))
 
     def skin_weights(self, rest_v):
         """Initial skinning weights (Sec. 7.4) of rest vertices: (capsule ids [V,4], weights [V,4])."""

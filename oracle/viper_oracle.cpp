@@ -218,7 +218,7 @@ struct Desc {
   double gravity[3];
 };
 
-enum { SS = 0, VOL = 1, SG = 2, BT = 3 };
+enum { SS = 0, VOL = 1, SG = 2, BT = 3, SR = 4 };
 
 template <class R> struct Scene {
   int nrods = 0, P = 0;
@@ -238,6 +238,10 @@ template <class R> struct Scene {
   std::vector<R> inert_base;      // rho pi rbar_{j+1/2}^4 l0_j per edge (times s^2 diag(1/4,1/4,1/2))
   std::vector<R> comp[4];         // per-constraint compliance alpha_type / (G * length), per slot
   std::vector<uint8_t> enabled;   // [nrods*4]
+  // cross-section stretch (eq. stretch_xy), optional, off by default: per-rod enable,
+  // per-slot compliance alpha / (pi r^2 l) and multiplier
+  std::vector<uint8_t> sr_on;
+  std::vector<R> comp_sr, lam_sr;
   // state
   std::vector<V3<R>> x, v;
   std::vector<R> s, sd;
@@ -353,6 +357,9 @@ template <class R> void build(Scene<R>& S, const Desc& d, const R* rbar, const R
   S.xprev.resize(P); S.sprev.resize(P); S.qprev.resize(P);
   S.I1inv.assign(P, R(0.0)); S.I3inv.assign(P, R(0.0));
   S.lam.assign(size_t(P) * 8, R(0.0));
+  S.sr_on.assign(S.nrods, 0);
+  S.comp_sr.assign(P, R(0.0));
+  S.lam_sr.assign(P, R(0.0));
   S.active_count.assign(P, 0);
 }
 
@@ -444,6 +451,21 @@ template <class R> int project_sg(Scene<R>& S, int p, R ih2) {
   B[0].ndof = 1; B[0].J[0][0] = R(-1.0) / l0; B[0].W[0][0] = S.wsinv[p];
   B[1].ndof = 1; B[1].J[0][0] = R(1.0) / l0; B[1].W[0][0] = S.wsinv[p + 1];
   xpbd_update(1, C, alpha, &S.lam[size_t(p) * 8 + 4], B, 2);
+  S.s[p] += B[0].out[0];
+  S.s[p + 1] += B[1].out[0];
+  return 1;
+}
+
+// Cross-section stretch at edge p (eq. stretch_xy): the midpoint scale is pulled back to its
+// rest value one, C = (s_p + s_{p+1}) / 2 - 1, with the energy weight pi r^2 of SS and VOL.
+template <class R> int project_sr(Scene<R>& S, int p, R ih2) {
+  if (!S.sr_on[S.rod_of[p]]) return 0;
+  R C[1] = {R(0.5) * (S.s[p] + S.s[p + 1]) - R(1.0)};
+  R alpha[1] = {S.comp_sr[p] * ih2};
+  Block<R> B[2];
+  B[0].ndof = 1; B[0].J[0][0] = R(0.5); B[0].W[0][0] = S.wsinv[p];
+  B[1].ndof = 1; B[1].J[0][0] = R(0.5); B[1].W[0][0] = S.wsinv[p + 1];
+  xpbd_update(1, C, alpha, &S.lam_sr[p], B, 2);
   S.s[p] += B[0].out[0];
   S.s[p + 1] += B[1].out[0];
   return 1;
@@ -657,6 +679,7 @@ template <class R> void predict_rods(Scene<R>& S, R h, int r0, int r1) {
         S.q[p] = qrotate(S.q[p], h * S.om[p]);
       }
       for (int t = 0; t < 8; ++t) S.lam[size_t(p) * 8 + t] = R(0.0);
+      S.lam_sr[p] = R(0.0);
     }
   for (int k = r0; k < r1; ++k)
     for (int p = S.off[k]; p + 1 < S.off[k + 1]; ++p) {
@@ -678,6 +701,7 @@ template <class R> int64_t solve_colours(Scene<R>& S, R ih2, int r0, int r1) {
         n += project_ss(S, p, ih2);
         n += project_vol(S, p, ih2);
         n += project_sg(S, p, ih2);
+        n += project_sr(S, p, ih2);
       }
   for (int colour = 0; colour < 2; ++colour)
     for (int k = r0; k < r1; ++k)
@@ -708,13 +732,14 @@ template <class R> int64_t solve_jacobi(Scene<R>& S, R ih2) {
     if (kind == SS) a = project_ss(S, p, ih2);
     else if (kind == VOL) a = project_vol(S, p, ih2);
     else if (kind == SG) a = project_sg(S, p, ih2);
+    else if (kind == SR) a = project_sr(S, p, ih2);
     else a = project_bt(S, p, ih2);
     if (!a) return;
     n += a;
     if (kind == SS || kind == VOL) {
       dx[p] = dx[p] + (S.x[p] - x0); dx[q1] = dx[q1] + (S.x[q1] - x1); ++nx[p]; ++nx[q1];
     }
-    if (kind == VOL || kind == SG) {
+    if (kind == VOL || kind == SG || kind == SR) {
       ds[p] = ds[p] + (S.s[p] - s0); ds[q1] = ds[q1] + (S.s[q1] - s1); ++ns[p]; ++ns[q1];
     }
     if (kind == BT) { ds[q1] = ds[q1] + (S.s[q1] - s1); ++ns[q1]; }
@@ -732,6 +757,7 @@ template <class R> int64_t solve_jacobi(Scene<R>& S, R ih2) {
       eval(SS, p);
       eval(VOL, p);
       eval(SG, p);
+      eval(SR, p);
       if (p + 2 < S.off[k + 1]) eval(BT, p);
     }
   for (int p = 0; p < P; ++p) {
@@ -952,6 +978,10 @@ template <class R> double rod_residual(const Scene<R>& S0, R ih2) {
         R C = (S.s[p + 1] - S.s[p]) / S.l0[p] + S.comp[SG][p] * ih2 * L[4];
         acc += val(C * C);
       }
+      if (S.sr_on[k]) {
+        R C = R(0.5) * (S.s[p] + S.s[p + 1]) - R(1.0) + S.comp_sr[p] * ih2 * S.lam_sr[p];
+        acc += val(C * C);
+      }
       if (p + 2 < S.off[k + 1] && S.enabled[4 * k + BT]) {
         Q4<R> r = qmul(qconj(S.q[p]), S.q[p + 1]);
         if (r.w < R(0.0)) r = q4<R>(-r.x, -r.y, -r.z, -r.w);
@@ -1024,6 +1054,19 @@ template <class R> static void set_sections_t(Scene<R>& S, int nsec, const int32
   S.sec_q.assign(nsec, q4<double>(0, 0, 0, 1));
 }
 
+// Cross-section stretch compliance per rod (+inf: off); G = pi r^2 over the edge length, with
+// r the edge's mean rest radius, as for SS and VOL.
+template <class R> static void set_cross_stretch_t(Scene<R>& S, const double* comp) {
+  const double pi = 3.14159265358979323846;
+  for (int k = 0; k < S.nrods; ++k) {
+    S.sr_on[k] = std::isfinite(comp[k]) ? 1 : 0;
+    for (int p = S.off[k]; p + 1 < S.off[k + 1]; ++p) {
+      const R rm = R(0.5) * (S.rbar[p] + S.rbar[p + 1]);
+      S.comp_sr[p] = S.sr_on[k] ? R(comp[k]) / (R(pi) * rm * rm * S.l0[p]) : R(0.0);
+    }
+  }
+}
+
 template <class R> static void set_floor_t(Scene<R>& S, const double* n, double d) {
   const double l = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
   S.floor_on = true;
@@ -1041,6 +1084,7 @@ template <class R> static int64_t rod_iterations_t(Scene<R>& S, double h_sub, in
       S.I1inv[i] = R(4.0) / I; S.I3inv[i] = R(2.0) / I;
     }
     for (int t = 0; t < 8; ++t) S.lam[size_t(i) * 8 + t] = R(0.0);
+    S.lam_sr[i] = R(0.0);
   }
   const R ih2 = R(1.0 / (h_sub * h_sub));
   int64_t n = 0;
@@ -1110,6 +1154,11 @@ void orc_set_floor(void* hp, const double* n, double d) {
   Handle* h = (Handle*)hp;
   if (h->d) set_floor_t(*h->d, n, d); else set_floor_t(*h->f, n, d);
 }
+// Cross-section stretch (eq. stretch_xy) compliance per rod, [nrods]; +inf leaves it off.
+void orc_set_cross_stretch(void* hp, const double* comp) {
+  Handle* h = (Handle*)hp;
+  if (h->d) set_cross_stretch_t(*h->d, comp); else set_cross_stretch_t(*h->f, comp);
+}
 // Solver of the rod constraints: 0 = coloured Gauss-Seidel, 1 = Jacobi with averaging.
 void orc_set_solver(void* hp, int jacobi) {
   Handle* h = (Handle*)hp;
@@ -1168,7 +1217,7 @@ void orc_get_rest(void* hp, double* l0, double* lbar, double* qrest, double* dar
 }
 
 // Single-constraint primitives for closed-form pins (double scene only).
-// kind: 0 SS, 1 VOL, 2 SG, 3 BT at slot p, with the substep inertia computed from
+// kind: 0 SS, 1 VOL, 2 SG, 3 BT, 4 SR at slot p, with the substep inertia computed from
 // the current scale.  lambda is zeroed first.
 void orc_project_one(void* hp, int kind, int p, double h) {
   Handle* hd = (Handle*)hp;
@@ -1180,10 +1229,12 @@ void orc_project_one(void* hp, int kind, int p, double h) {
       S.I1inv[i] = 4.0 / I; S.I3inv[i] = 2.0 / I;
     }
     for (int t = 0; t < 8; ++t) S.lam[size_t(i) * 8 + t] = 0.0;
+    S.lam_sr[i] = 0.0;
   }
   double ih2 = 1.0 / (h * h);
   if (kind == 0) project_ss(S, p, ih2);
   if (kind == 1) project_vol(S, p, ih2);
+  if (kind == 4) project_sr(S, p, ih2);
   if (kind == 2) project_sg(S, p, ih2);
   if (kind == 3) project_bt(S, p, ih2);
 }

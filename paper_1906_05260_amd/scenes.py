@@ -42,6 +42,8 @@ class SceneDesc:
     floor: tuple = None
     # rod-constraint solver: "gauss_seidel" (coloured) or "jacobi" (with averaging, Sec. 7)
     solver: str = "gauss_seidel"
+    # cross-section stretch (eq. stretch_xy) compliance per rod [num_rods]; None or +inf = off
+    cross_compliance: np.ndarray = None
 
     @property
     def num_rods(self) -> int:

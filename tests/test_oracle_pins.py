@@ -909,3 +909,77 @@ def test_skin_weights_nearest_and_equal_distance_limits():
     caps, w = o.skin_weights(np.array([[0.01, 0.005, 0.0], [0.01, 0.025, 0.0]]))
     assert caps[0, 0] == 0 and w[0, 0] > 1 - 1e-9
     assert set(caps[1, :2].tolist()) == {0, 2} and abs(w[1, 0] - 0.5) < 1e-12 and abs(w[1, 1] - 0.5) < 1e-12
+
+
+# ---------------------------------------------------------------- cross-section stretch
+
+def _sr_scene(comp_sr, n=3):
+    d = small_scene([line(n)], radius=np.linspace(0.005, 0.003, n), comp=(INF, INF, INF, INF))
+    d.cross_compliance = np.array([comp_sr])
+    return d
+
+
+def test_cross_stretch_rigid_projection_is_the_mass_weighted_projection():
+    """Cross-section stretch (eq. stretch_xy) with zero compliance at edge 0 of a 3-pill rod
+    (pill 1 carries two edges' scale inertia, pill 0 one): the projection equals the solution
+    of the KKT system  min 1/2 ds^T M ds  s.t. the midpoint scale (s0 + s1)/2 returns to one,
+    solved here as a plain linear system; positions, rotations and pill 2 are untouched."""
+    o = OracleScene(_sr_scene(0.0))
+    s0 = np.array([1.3, 1.1, 0.9])
+    o.set_state(s=s0)
+    before = o.get_state()
+    o.project_one(4, 0, 1e-3)
+    st = o.get_state()
+    M = np.diag(1.0 / o.rest()["wsinv"][:2])
+    a = np.array([0.5, 0.5])
+    K = np.block([[M, a[:, None]], [a[None, :], np.zeros((1, 1))]])
+    sol = np.linalg.solve(K, np.array([0.0, 0.0, -(a @ s0[:2] - 1.0)]))
+    assert abs(M[0, 0] - M[1, 1]) > 0.3 * M[0, 0]          # unequal masses: the split is tested
+    assert np.abs(st["s"][:2] - (s0[:2] + sol[:2])).max() < 1e-14
+    assert abs(0.5 * (st["s"][0] + st["s"][1]) - 1.0) < 1e-15
+    assert st["s"][2] == s0[2]
+    assert np.array_equal(st["x"], before["x"]) and np.array_equal(st["q"], before["q"])
+
+
+def test_cross_stretch_compliant_projection_minimises_the_implicit_potential():
+    """With compliance alpha, one projection from zero multiplier is the minimiser of the
+    implicit-Euler potential 1/2 ds^T M ds + (C(s0) + a.ds)^2 / (2 alpha~), alpha~ = alpha /
+    (pi r^2 l h^2) (energy weight pi r^2 of eq. stretch_xy over the edge length, r the edge's
+    mean rest radius), solved as the normal equations of that quadratic."""
+    alpha, h = 2e-4, 1e-3
+    o = OracleScene(_sr_scene(alpha))
+    s0 = np.array([0.8, 1.25, 1.0])
+    o.set_state(s=s0)
+    o.project_one(4, 0, h)
+    st = o.get_state()
+    rm = 0.5 * (0.005 + 0.004)
+    at = alpha / (math.pi * rm * rm * 0.01) / h ** 2
+    M = np.diag(1.0 / o.rest()["wsinv"][:2])
+    a = np.array([0.5, 0.5])
+    C0 = a @ s0[:2] - 1.0
+    ds = np.linalg.solve(M + np.outer(a, a) / at, -a * C0 / at)
+    assert abs(C0 + a @ ds) > 1e-3 * abs(C0)                 # compliant: not fully restored
+    assert np.abs(st["s"][:2] - (s0[:2] + ds)).max() < 1e-13
+
+
+def test_cross_stretch_with_scale_gradient_drives_every_scale_to_rest():
+    """Rigid cross-section stretch plus rigid scale gradient on a 10-pill rod: the only
+    configuration satisfying both is s = 1 on every pill; Gauss-Seidel reaches it from random
+    scales, and stays put when started there.  Off (+inf) leaves the scales to the other
+    constraints: with only the scale gradient on, the mean scale does not return to one."""
+    rng = np.random.default_rng(3)
+    s0 = rng.uniform(0.7, 1.3, 10)
+    d = small_scene([line(10)], comp=(INF, INF, 0.0, INF))
+    d.cross_compliance = np.array([0.0])
+    o = OracleScene(d)
+    o.set_state(s=s0)
+    o.rod_iterations(1 / 600, 400)
+    assert np.abs(o.get_state()["s"] - 1.0).max() < 1e-9
+    o.set_state(s=np.ones(10))
+    o.rod_iterations(1 / 600, 5)
+    assert np.abs(o.get_state()["s"] - 1.0).max() < 1e-15
+    d.cross_compliance = np.array([INF])
+    off = OracleScene(d)
+    off.set_state(s=s0)
+    off.rod_iterations(1 / 600, 400)
+    assert abs(off.get_state()["s"].mean() - 1.0) > 1e-3
