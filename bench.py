@@ -345,6 +345,20 @@ def solver_timing(torch, viper, scenes, dev, frames=5):
         torch.cuda.synchronize()
         sc.sync()
         res["frame_ms_" + solver] = e0.elapsed_time(e1) / frames
+    # the fused frame kernel (one launch per frame) with the optional cross-section stretch
+    # (eq. stretch_xy) on every rod, beside the same kernel without it
+    for name, c in (("frame_ms_fused", None), ("frame_ms_fused_cross_stretch", np.full(base.num_rods, 1e-7))):
+        sc = viper.Scene(dataclasses.replace(base, cross_compliance=c), "f32", device=dev)
+        sc.step(1.0 / 60.0, 20, 8, mode=viper.MODE_FRAME)
+        st = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(frames):
+            sc.step(1.0 / 60.0, 20, 8, mode=viper.MODE_FRAME)
+        e1.record(st)
+        torch.cuda.synchronize()
+        sc.sync()
+        res[name] = e0.elapsed_time(e1) / frames
     return res
 
 

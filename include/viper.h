@@ -95,6 +95,12 @@ typedef struct {
    * Jacobi scene steps in VIPER_MODE_ITERATION or VIPER_MODE_GRAPH; the pool and the adjoint
    * reject it. */
   int32_t solver;
+  /* Cross-section stretch (eq. stretch_xy), optional: compliance per rod [num_rods] of the
+   * constraint C = (s_j + s_{j+1}) / 2 - 1 on every edge (the midpoint scale pulled back to
+   * its rest value), scaled by 1 / (pi r^2 l) as stretch-shear and volume; >= 0, +inf = off
+   * for that rod; NULL = off everywhere.  Solved after the scale gradient in the same edge
+   * pass (both solvers); the pool and the adjoint reject a scene that turns it on. */
+  const double* cross_compliance;
 } viper_scene_desc;
 
 /* Bytes of device workspace the scene needs (host-only computation; validates the

@@ -51,11 +51,11 @@ struct Slot {
   T x0, x1, x2, v0, v1, v2, s, sd;
   T q0, q1, q2, q3, o0, o1, o2;
   T xp0, xp1, xp2, sp, qp0, qp1, qp2, qp3;
-  T l[8];                      // multipliers of the constraints owned by this slot
+  T l[9];                      // multipliers of the slot's constraints: ss(3) vol sg bt(3) sr
   T w, ws;                     // inverse position / scale mass
   T ilb, il0, cbt, inert;      // edge constants
   T db0, db1, db2;             // rest Darboux vector
-  T ass, avol, asg, abt;       // compliance / (G l h^2)
+  T ass, avol, asg, abt, asr;  // compliance / (G l h^2)
   T I1;                        // inverse bending inertia of the slot's edge (this substep)
   uint32_t f;
 };
@@ -81,7 +81,7 @@ __device__ __forceinline__ void predict_slot(Slot<T>& L, T h, T gx, T gy, T gz) 
   L.qp0 = L.q0; L.qp1 = L.q1; L.qp2 = L.q2; L.qp3 = L.q3;
   if (L.f & F_EDGE) qrot_world(L.q0, L.q1, L.q2, L.q3, h * L.o0, h * L.o1, h * L.o2);
 #pragma unroll
-  for (int i = 0; i < 8; ++i) L.l[i] = T(0);
+  for (int i = 0; i < 9; ++i) L.l[i] = T(0);
 }
 
 // Inverse bending inertia 4 / (rho pi r^4 l s_m^2) of an edge from the substep-start
@@ -185,6 +185,15 @@ __device__ __forceinline__ void edge_update(Slot<T>& L, T& b0, T& b1, T& b2, T& 
     L.l[4] += dl;
     sa -= L.ws * il0 * dl;
     sb += wsb * il0 * dl;
+  }
+  if (L.f & F_SR) {   // cross-section stretch: midpoint scale back to one, dC/ds = 1/2 each
+    const T at = L.asr;
+    const T C = T(0.5) * (sa + sb) - T(1);
+    const T S = T(0.25) * (L.ws + wsb) + at;
+    const T dl = (-C - at * L.l[8]) * rcp(S);
+    L.l[8] += dl;
+    sa += T(0.5) * L.ws * dl;
+    sb += T(0.5) * wsb * dl;
   }
   L.x0 = a0; L.x1 = a1; L.x2 = a2; L.s = sa;
 }
@@ -354,6 +363,7 @@ __device__ __forceinline__ void load_consts(const Dev<T>& d, Slot<T>& L, int p, 
   L.ilb = d.ilb[p]; L.il0 = d.il0[p]; L.cbt = d.cbt[p]; L.inert = d.inert[p];
   L.db0 = d.dbx[p]; L.db1 = d.dby[p]; L.db2 = d.dbz[p];
   L.ass = d.css[p] * ih2; L.avol = d.cvol[p] * ih2; L.asg = d.csg[p] * ih2; L.abt = d.cbtc[p] * ih2;
+  L.asr = (L.f & F_SR) ? d.csr[p] * ih2 : T(0);
 }
 
 template <class T>

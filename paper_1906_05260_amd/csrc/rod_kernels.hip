@@ -66,7 +66,7 @@ __device__ __forceinline__ void store_predicted(const Dev<T>& d, const Slot<T>& 
   d.qpx[p] = L.qp0; d.qpy[p] = L.qp1; d.qpz[p] = L.qp2; d.qpw[p] = L.qp3;
   d.i1[p] = L.I1;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) d.lam[(size_t)i * d.P + p] = T(0);
+  for (int i = 0; i < 9; ++i) d.lam[(size_t)i * d.P + p] = T(0);
 }
 
 template <class T>
@@ -94,7 +94,7 @@ __device__ __forceinline__ void load_iter(const Dev<T>& d, Slot<T>& L, int p) {
   L.x0 = d.px[p]; L.x1 = d.py[p]; L.x2 = d.pz[p]; L.s = d.s[p];
   L.q0 = d.qx[p]; L.q1 = d.qy[p]; L.q2 = d.qz[p]; L.q3 = d.qw[p];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) L.l[i] = d.lam[(size_t)i * d.P + p];
+  for (int i = 0; i < 9; ++i) L.l[i] = d.lam[(size_t)i * d.P + p];
   L.I1 = d.i1[p];
 }
 
@@ -104,7 +104,7 @@ __device__ __forceinline__ void store_iter(const Dev<T>& d, const Slot<T>& L, in
   d.px[p] = L.x0; d.py[p] = L.x1; d.pz[p] = L.x2; d.s[p] = L.s;
   d.qx[p] = L.q0; d.qy[p] = L.q1; d.qz[p] = L.q2; d.qw[p] = L.q3;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) d.lam[(size_t)i * d.P + p] = L.l[i];
+  for (int i = 0; i < 9; ++i) d.lam[(size_t)i * d.P + p] = L.l[i];
 }
 
 // ITERATION mode, Jacobi variant of stage 2 (Sec. 7: constraints computed in parallel, their
@@ -124,19 +124,20 @@ struct JacobiAcc {
 template <class T>
 __device__ __forceinline__ void jacobi_edge(Slot<T>& L, const Slot<T>& L0, T b0, T b1, T b2, T sb, T wb, T wsb,
                                             JacobiAcc<T>& aL, JacobiAcc<T>& aR) {
-  const uint32_t types[3] = {F_SS, F_VOL, F_SG};
+  const uint32_t types[4] = {F_SS, F_VOL, F_SG, F_SR};
 #pragma unroll
-  for (int t = 0; t < 3; ++t) {
+  for (int t = 0; t < 4; ++t) {
     if (!(L0.f & types[t])) continue;
     Slot<T> a = L0;
-    a.f = (L0.f & ~(F_SS | F_VOL | F_SG)) | types[t];
+    a.f = (L0.f & ~(F_SS | F_VOL | F_SG | F_SR)) | types[t];
     T c0 = b0, c1 = b1, c2 = b2, cs = sb;
     edge_update(a, c0, c1, c2, cs, wb, wsb);
     if (t == 0) {
       L.l[0] = a.l[0]; L.l[1] = a.l[1]; L.l[2] = a.l[2];
       aL.dq0 += a.q0 - L0.q0; aL.dq1 += a.q1 - L0.q1; aL.dq2 += a.q2 - L0.q2; aL.dq3 += a.q3 - L0.q3; aL.nq += T(1);
     } else {
-      L.l[2 + t] = a.l[2 + t];
+      const int li = (t == 3) ? 8 : 2 + t;
+      L.l[li] = a.l[li];
       aL.ds += a.s - L0.s; aR.ds += cs - sb; aL.ns += T(1); aR.ns += T(1);
     }
     if (t < 2) {

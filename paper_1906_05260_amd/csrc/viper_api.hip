@@ -56,8 +56,8 @@ struct Layout {
 struct Offsets {
   size_t state[15];        // px py pz vx vy vz s sd qx qy qz qw ox oy oz
   size_t pill_rest[3];     // winv wsinv rbar
-  size_t edge_rest[18];    // ilb il0 cbt inert dbx dby dbz css cvol csg cbtc qrx qry qrz qrw mrx mry mrz
-  size_t scratch[10];      // xpx xpy xpz spv qpx qpy qpz qpw i1 lam(8P)
+  size_t edge_rest[19];    // ilb il0 cbt inert dbx dby dbz css cvol csg cbtc qrx qry qrz qrw mrx mry mrz csr
+  size_t scratch[10];      // xpx xpy xpz spv qpx qpy qpz qpw i1 lam(9P)
   size_t flags, wave_start, status, stage, xform, anchor, rod_of, header;
   size_t sec_off = 0, sec_pill = 0, sec_of = 0, sec_xr = 0, sec_q = 0, sec_fit = 0;   // bundling
   ContactOffsets contact;
@@ -72,7 +72,8 @@ struct Host {
   // rest data (FP64)
   std::vector<double> x, rbar, winv, wsinv, anchor, xloc;
   std::vector<int32_t> rod_of;
-  std::vector<double> ilb, il0, cbt, inert, db[3], cs[4], qr[4], mr[3];
+  std::vector<double> ilb, il0, cbt, inert, db[3], cs[5], qr[4], mr[3];
+  bool any_sr = false;
   // bundling sections: offsets, pills, section of each entry, world rest position of each entry
   std::vector<int32_t> sec_off, sec_pill, sec_of;
   std::vector<double> sec_xr;
@@ -112,6 +113,8 @@ viper_status validate(const viper_scene_desc* d) {
       double c = d->compliance[4 * k + t];
       if (std::isnan(c) || c < 0) return fail(VIPER_ERR_INVALID, "compliance must be >= 0 or +inf");
     }
+    if (d->cross_compliance && (std::isnan(d->cross_compliance[k]) || d->cross_compliance[k] < 0))
+      return fail(VIPER_ERR_INVALID, "cross_compliance must be >= 0 or +inf");
   }
   const int P = d->rod_offsets[d->num_rods];
   if (P > (1 << 27)) return fail(VIPER_ERR_INVALID, "too many pills");
@@ -232,7 +235,7 @@ Offsets make_layout(const viper_scene_desc* d, int P, int W, int E, int cap) {
   for (auto& v : o.pill_rest) v = L.take(ts * P);
   for (auto& v : o.edge_rest) v = L.take(ts * P);
   for (int i = 0; i < 9; ++i) o.scratch[i] = L.take(ts * P);
-  o.scratch[9] = L.take(ts * 8 * (size_t)P);
+  o.scratch[9] = L.take(ts * 9 * (size_t)P);
   o.flags = L.take(4 * (size_t)P);
   o.wave_start = L.take(4 * (size_t)(W + 1));
   o.status = L.take(4 * ST_WORDS);
@@ -320,6 +323,8 @@ void build_host(const viper_scene_desc* d, Host& H) {
   H.ilb.assign(P, 0); H.il0.assign(P, 0); H.cbt.assign(P, 0); H.inert.assign(P, 0);
   for (int i = 0; i < 3; ++i) { H.db[i].assign(P, 0); H.mr[i].assign(P, 0); }
   for (int i = 0; i < 4; ++i) { H.cs[i].assign(P, 0); H.qr[i].assign(P, 0); }
+  H.cs[4].assign(P, 0);
+  H.any_sr = false;
   for (int p = 0; p < P; ++p) H.qr[3][p] = 1.0;
   const double rho = d->density;
   H.E = 0;
@@ -330,7 +335,10 @@ void build_host(const viper_scene_desc* d, Host& H) {
     const double act = d->activation ? d->activation[k] : 1.0;
     bool en[4];
     for (int t = 0; t < 4; ++t) en[t] = std::isfinite(d->compliance[4 * k + t]);
-    uint32_t ef = (en[0] ? F_SS : 0u) | (en[1] ? F_VOL : 0u) | (en[2] ? F_SG : 0u) | (en[3] ? F_BTEN : 0u);
+    const bool sr = d->cross_compliance && std::isfinite(d->cross_compliance[k]);
+    H.any_sr = H.any_sr || sr;
+    uint32_t ef = (en[0] ? F_SS : 0u) | (en[1] ? F_VOL : 0u) | (en[2] ? F_SG : 0u) | (en[3] ? F_BTEN : 0u) |
+                  (sr ? F_SR : 0u);
     double tprev[3] = {0, 0, 1}, qcur[4] = {0, 0, 0, 1};
     for (int p = a; p < b; ++p) {
       uint32_t f = F_VALID | ef;
@@ -362,8 +370,9 @@ void build_host(const viper_scene_desc* d, Host& H) {
       if (en[0]) H.cs[0][p] = d->compliance[4 * k + 0] / (kPi * r2 * len);
       if (en[1]) H.cs[1][p] = d->compliance[4 * k + 1] / (kPi * r2 * len);
       if (en[2]) H.cs[2][p] = d->compliance[4 * k + 2] / (kPi * r4 / 2.0 * len);
+      if (sr) H.cs[4][p] = d->cross_compliance[k] / (kPi * r2 * len);
       H.E += 1;
-      H.proj_per_iter += (int64_t)en[0] + en[1] + en[2];
+      H.proj_per_iter += (int64_t)en[0] + en[1] + en[2] + sr;
     }
     for (int p = a; p + 2 < b; ++p) {
       const double rv = H.rbar[p + 1], r4 = rv * rv * rv * rv;
@@ -412,6 +421,7 @@ struct viper_scene_s {
   int nsec = 0, nsecp = 0;    // bundling sections and their entries
   int floor_on = 0;           // half-plane floor (unit normal, offset)
   int jacobi = 0;             // rod constraints by Jacobi with averaging
+  int cross_stretch = 0;      // some rod has the cross-section stretch constraint
   double floor_n[3] = {0.0, 0.0, 0.0}, floor_d = 0.0;
   int cap = 16;
   int R = 0, P = 0, W = 0, E = 0;
@@ -452,9 +462,9 @@ void fill_dev(viper_scene_s* S, Dev<T>& d) {
   for (int i = 0; i < 15; ++i) *st[i] = P_(S->o.state[i]);
   const T** pr[3] = {&d.winv, &d.wsinv, &d.rbar};
   for (int i = 0; i < 3; ++i) *pr[i] = P_(S->o.pill_rest[i]);
-  const T** er[18] = {&d.ilb, &d.il0, &d.cbt, &d.inert, &d.dbx, &d.dby, &d.dbz, &d.css, &d.cvol,
-                      &d.csg, &d.cbtc, &d.qrx, &d.qry, &d.qrz, &d.qrw, &d.mrx, &d.mry, &d.mrz};
-  for (int i = 0; i < 18; ++i) *er[i] = P_(S->o.edge_rest[i]);
+  const T** er[19] = {&d.ilb, &d.il0, &d.cbt, &d.inert, &d.dbx, &d.dby, &d.dbz, &d.css, &d.cvol,
+                      &d.csg, &d.cbtc, &d.qrx, &d.qry, &d.qrz, &d.qrw, &d.mrx, &d.mry, &d.mrz, &d.csr};
+  for (int i = 0; i < 19; ++i) *er[i] = P_(S->o.edge_rest[i]);
   T** sc[9] = {&d.xpx, &d.xpy, &d.xpz, &d.spv, &d.qpx, &d.qpy, &d.qpz, &d.qpw, &d.i1};
   for (int i = 0; i < 9; ++i) *sc[i] = P_(S->o.scratch[i]);
   d.lam = P_(S->o.scratch[9]);
@@ -501,10 +511,10 @@ viper_status upload(viper_scene_s* S, const Host& H, hipStream_t st) {
   HIP_TRY(put(S->o.pill_rest[0], H.winv));
   HIP_TRY(put(S->o.pill_rest[1], H.wsinv));
   HIP_TRY(put(S->o.pill_rest[2], H.rbar));
-  const std::vector<double>* er[18] = {&H.ilb, &H.il0, &H.cbt, &H.inert, &H.db[0], &H.db[1], &H.db[2], &H.cs[0],
+  const std::vector<double>* er[19] = {&H.ilb, &H.il0, &H.cbt, &H.inert, &H.db[0], &H.db[1], &H.db[2], &H.cs[0],
                                        &H.cs[1], &H.cs[2], &H.cs[3], &H.qr[0], &H.qr[1], &H.qr[2], &H.qr[3],
-                                       &H.mr[0], &H.mr[1], &H.mr[2]};
-  for (int i = 0; i < 18; ++i) HIP_TRY(put(S->o.edge_rest[i], *er[i]));
+                                       &H.mr[0], &H.mr[1], &H.mr[2], &H.cs[4]};
+  for (int i = 0; i < 19; ++i) HIP_TRY(put(S->o.edge_rest[i], *er[i]));
   HIP_TRY(hipMemcpyAsync(b + S->o.flags, H.flags.data(), 4 * (size_t)P, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(b + S->o.anchor, H.anchor.data(), 8 * H.anchor.size(), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(b + S->o.rod_of, H.rod_of.data(), 4 * (size_t)P, hipMemcpyHostToDevice, st));
@@ -659,6 +669,7 @@ viper_status viper_create_scene(const viper_scene_desc* desc, void* workspace, s
   S->nsec = desc->num_sections > 0 ? desc->num_sections : 0;
   S->nsecp = S->nsec ? desc->section_offsets[S->nsec] : 0;
   S->jacobi = desc->solver == 1;
+  S->cross_stretch = H.any_sr ? 1 : 0;
   if (desc->floor_on) {
     const double* n = desc->floor_normal;
     const double l = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
@@ -850,6 +861,7 @@ viper_status adjoint_check(viper_scene S, int32_t frames, int32_t substeps, int3
   if (S->nsec) return fail(VIPER_ERR_INVALID, "the adjoint does not cover bundling sections");
   if (S->floor_on) return fail(VIPER_ERR_INVALID, "the adjoint does not cover the floor");
   if (S->jacobi) return fail(VIPER_ERR_INVALID, "the adjoint covers the Gauss-Seidel solver");
+  if (S->cross_stretch) return fail(VIPER_ERR_INVALID, "the adjoint does not cover the cross-section stretch");
   if (frames < 1 || substeps < 1 || iterations < 0)
     return fail(VIPER_ERR_INVALID, "frames >= 1, substeps >= 1 and iterations >= 0 required");
   return VIPER_OK;
@@ -1066,6 +1078,10 @@ viper_status viper_pool_admit(viper_pool P, const viper_scene_desc* desc, void* 
   if (desc->precision != P->precision) return fail(VIPER_ERR_INVALID, "scene precision differs from the pool's");
   if (desc->num_sections > 0 || desc->floor_on || desc->solver == 1)
     return fail(VIPER_ERR_INVALID, "scenes with bundling sections, a floor or the Jacobi solver are stepped with viper_step");
+  if (desc->cross_compliance)
+    for (int k = 0; k < desc->num_rods; ++k)
+      if (std::isfinite(desc->cross_compliance[k]))
+        return fail(VIPER_ERR_INVALID, "scenes with the cross-section stretch are stepped with viper_step");
   size_t fp = 0;
   viper_status r = viper_scene_footprint(desc, &fp);
   if (r != VIPER_OK) return r;

@@ -65,6 +65,7 @@ class SceneDescC(ctypes.Structure):
         ("floor_normal", ctypes.c_double * 3),
         ("floor_offset", ctypes.c_double),
         ("solver", ctypes.c_int32),
+        ("cross_compliance", ctypes.c_void_p),
     ]
 
 
@@ -156,6 +157,11 @@ class _DescHolder:
                 c.floor_normal[i] = float(desc.floor[i])
             c.floor_offset = float(desc.floor[3])
         c.solver = 1 if getattr(desc, "solver", "gauss_seidel") == "jacobi" else 0
+        if getattr(desc, "cross_compliance", None) is not None:
+            a["sr"] = np.ascontiguousarray(desc.cross_compliance, np.float64).reshape(-1)
+            if a["sr"].shape[0] != c.num_rods:
+                raise ValueError("cross_compliance needs one value per rod")
+            c.cross_compliance = a["sr"].ctypes.data
         self.c = c
 
 

@@ -118,3 +118,18 @@ def test_floor_validation():
         with pytest.raises(viper.ViperError) as ei:
             viper.footprint(dataclasses.replace(d, floor=fl))
         assert ei.value.status == viper.ERR_INVALID and "floor" in str(ei.value)
+
+
+def test_cross_stretch_validation():
+    """Cross-section stretch compliances (eq. stretch_xy): one per rod, >= 0 or +inf; the
+    footprint grows by one per-edge rest array and one multiplier array when it is off or on
+    alike (the layout does not depend on it)."""
+    d = scenes.helix_rods(2, 8, seed=1)
+    base = viper.footprint(d)
+    assert viper.footprint(dataclasses.replace(d, cross_compliance=np.array([1e-6, np.inf]))) == base
+    for bad in (np.array([-1.0, 0.0]), np.array([np.nan, 0.0])):
+        with pytest.raises(viper.ViperError) as ei:
+            viper.footprint(dataclasses.replace(d, cross_compliance=bad))
+        assert ei.value.status == viper.ERR_INVALID and "cross_compliance" in str(ei.value)
+    with pytest.raises(ValueError):
+        viper.footprint(dataclasses.replace(d, cross_compliance=np.zeros(3)))
