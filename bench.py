@@ -397,6 +397,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-contacts", action="store_true")
+    ap.add_argument("--no-solvers", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=0.15,
                     help="arrival window of the serving workload (Poisson, 200 requests/s)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -489,8 +490,9 @@ def main():
         log("contacts and skinning done")
         out["bundling"] = bundling_timing(torch, viper, scenes, dev)
         log("bundling done")
-    out["solvers"] = solver_timing(torch, viper, scenes, dev)
-    log("solvers done")
+    if not args.no_solvers:
+        out["solvers"] = solver_timing(torch, viper, scenes, dev)
+        log("solvers done")
     if not args.no_adjoint:
         out["adjoint"] = adjoint_timing(torch, viper, scenes, dev)
         log("adjoint done")
