@@ -72,6 +72,8 @@ def lib():
         L.orc_floor_pass.argtypes = [P]
         L.orc_set_solver.argtypes = [P, I]
         L.orc_set_cross_stretch.argtypes = [P, P]
+        L.orc_set_bones.argtypes = [P, I, P, P, P]
+        L.orc_bone_frame.argtypes = [P, P]
         L.orc_skin_weights.argtypes = [P, I, P, P, P]
         L.orc_rod_iteration.restype = ctypes.c_int64
         L.orc_rod_iteration.argtypes = [P, D, I]
@@ -133,6 +135,10 @@ class OracleScene:
         if getattr(desc, "floor", None) is not None:
             n = np.ascontiguousarray(desc.floor[:3], dtype=np.float64)
             L.orc_set_floor(self.h, _p(n), float(desc.floor[3]))
+        if getattr(desc, "bone_rest", None) is not None:
+            self._bones = (_f64(desc.bone_rest).reshape(-1), np.ascontiguousarray(desc.pill_bones, np.int32).reshape(-1),
+                           _f64(desc.pill_bone_weights).reshape(-1))
+            L.orc_set_bones(self.h, int(self._bones[0].shape[0] // 12), *[_p(a) for a in self._bones])
         if getattr(desc, "cross_compliance", None) is not None:
             self._sr = _f64(desc.cross_compliance).reshape(-1)
             L.orc_set_cross_stretch(self.h, _p(self._sr))
@@ -149,6 +155,11 @@ class OracleScene:
         """`iters` iterations of the rod constraints at the current state (substep h), from
         zero multipliers (as project_one)."""
         return int(lib().orc_rod_iteration(self.h, float(h), int(iters)))
+
+    def set_bones(self, transforms):
+        """The bones' transforms of a new frame ([nb, 3, 4]): warm start of the pills (Sec. 8.2)."""
+        t = _f64(transforms).reshape(-1)
+        lib().orc_bone_frame(self.h, _p(t))
 
     def floor_pass(self):
         """One projection of every pill against the half-plane floor (Sec. 7)."""

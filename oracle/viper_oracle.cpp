@@ -264,6 +264,12 @@ template <class R> struct Scene {
   bool floor_on = false;
   V3<double> floor_n;
   double floor_d = 0.0;
+  // kinematic bones (Sec. 8.2): each bone's transform of the last frame, [A | b] row-major
+  // 3x4 per bone, and two (bone, weight) influences per pill
+  int nbones = 0;
+  std::vector<double> bone_prev;
+  std::vector<int32_t> pill_bone;
+  std::vector<double> pill_bone_w;
   std::vector<int32_t> pairs;  // sorted (a, b), a < b, capsule id = first pill of the edge
   std::vector<int> active_count; // number of active contacts in the last contact pass
   int64_t projections = 0;     // count of rod + active contact projections performed
@@ -1054,6 +1060,53 @@ template <class R> static void set_sections_t(Scene<R>& S, int nsec, const int32
   S.sec_q.assign(nsec, q4<double>(0, 0, 0, 1));
 }
 
+// x -> A x + b for a bone transform T = [A | b] (3x4, row-major).
+inline V3<double> affine_apply(const double* T, const V3<double>& x) {
+  return v3<double>(T[0] * x.x + T[1] * x.y + T[2] * x.z + T[3], T[4] * x.x + T[5] * x.y + T[6] * x.z + T[7],
+                    T[8] * x.x + T[9] * x.y + T[10] * x.z + T[11]);
+}
+
+// Inverse of T = [A | b]: [A^-1 | -A^-1 b], A^-1 by the adjugate over the determinant.
+inline void affine_inverse(const double* T, double* out) {
+  const double a = T[0], b = T[1], c = T[2], d = T[4], e = T[5], f = T[6], g = T[8], h = T[9], i = T[10];
+  const double det = a * (e * i - f * h) - b * (d * i - f * g) + c * (d * h - e * g);
+  const double adj[9] = {e * i - f * h, c * h - b * i, b * f - c * e,
+                         f * g - d * i, a * i - c * g, c * d - a * f,
+                         d * h - e * g, b * g - a * h, a * e - b * d};
+  for (int r = 0; r < 3; ++r) {
+    for (int k = 0; k < 3; ++k) out[4 * r + k] = adj[3 * r + k] / det;
+    out[4 * r + 3] = -(out[4 * r] * T[3] + out[4 * r + 1] * T[7] + out[4 * r + 2] * T[11]);
+  }
+}
+
+// Bone-driven warm start (Sec. 8.2): the bones moved from their last transforms T_prev to
+// T_cur; every pill with influences moves to the weighted blend of its bones' motions,
+//     x <- sum_k w_k T_cur,k T_prev,k^-1 x / sum_k w_k      (linear blend skinning)
+// (pinned pills too: that is their kinematic attachment); pills without weight stay.
+// Velocities, scales and rotations are not changed.  T_prev <- T_cur afterwards.
+template <class R> void bone_warm_start(Scene<R>& S, const double* cur) {
+  std::vector<double> inv(12 * (size_t)S.nbones);
+  for (int b = 0; b < S.nbones; ++b) affine_inverse(&S.bone_prev[12 * (size_t)b], &inv[12 * (size_t)b]);
+  for (int p = 0; p < S.P; ++p) {
+    const V3<double> x = v3<double>(val(S.x[p].x), val(S.x[p].y), val(S.x[p].z));
+    V3<double> acc = v3<double>(0, 0, 0);
+    double wsum = 0.0;
+    for (int k = 0; k < 2; ++k) {
+      const double w = S.pill_bone_w[2 * (size_t)p + k];
+      if (w <= 0.0) continue;
+      const int b = S.pill_bone[2 * (size_t)p + k];
+      const V3<double> y = affine_apply(&cur[12 * (size_t)b], affine_apply(&inv[12 * (size_t)b], x));
+      acc = acc + w * y;
+      wsum += w;
+    }
+    if (wsum > 0.0) {
+      const V3<double> y = (1.0 / wsum) * acc;
+      S.x[p] = v3<R>(R(y.x), R(y.y), R(y.z));
+    }
+  }
+  S.bone_prev.assign(cur, cur + 12 * (size_t)S.nbones);
+}
+
 // Cross-section stretch compliance per rod (+inf: off); G = pi r^2 over the edge length, with
 // r the edge's mean rest radius, as for SS and VOL.
 template <class R> static void set_cross_stretch_t(Scene<R>& S, const double* comp) {
@@ -1153,6 +1206,23 @@ void orc_section_fit(void* hp, int k, double* out) {
 void orc_set_floor(void* hp, const double* n, double d) {
   Handle* h = (Handle*)hp;
   if (h->d) set_floor_t(*h->d, n, d); else set_floor_t(*h->f, n, d);
+}
+// Bones (Sec. 8.2): nb rest transforms [nb*12] (3x4 row-major, the bones' pose at the rest
+// positions) and two (bone, weight) influences per pill, [P*2] each.
+void orc_set_bones(void* hp, int nb, const double* rest, const int32_t* pb, const double* pw) {
+  Handle* h = (Handle*)hp;
+  auto set = [&](auto& S) {
+    S.nbones = nb;
+    S.bone_prev.assign(rest, rest + 12 * (size_t)nb);
+    S.pill_bone.assign(pb, pb + 2 * (size_t)S.P);
+    S.pill_bone_w.assign(pw, pw + 2 * (size_t)S.P);
+  };
+  if (h->d) set(*h->d); else set(*h->f);
+}
+// The bones' transforms of the new frame, [nb*12]: warm start of every influenced pill.
+void orc_bone_frame(void* hp, const double* cur) {
+  Handle* h = (Handle*)hp;
+  if (h->d) bone_warm_start(*h->d, cur); else bone_warm_start(*h->f, cur);
 }
 // Cross-section stretch (eq. stretch_xy) compliance per rod, [nrods]; +inf leaves it off.
 void orc_set_cross_stretch(void* hp, const double* comp) {

@@ -983,3 +983,118 @@ def test_cross_stretch_with_scale_gradient_drives_every_scale_to_rest():
     off.set_state(s=s0)
     off.rod_iterations(1 / 600, 400)
     assert abs(off.get_state()["s"].mean() - 1.0) > 1e-3
+
+
+# ---------------------------------------------------------------- bones (warm start)
+
+def _rot(axis, ang):
+    a = np.asarray(axis, float) / np.linalg.norm(axis)
+    K = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+    return np.eye(3) + math.sin(ang) * K + (1 - math.cos(ang)) * K @ K
+
+
+def _affine(R, t):
+    return np.hstack([R, np.asarray(t, float)[:, None]])
+
+
+def _compose(M, T):
+    """M after T for 3x4 affine transforms."""
+    return np.hstack([M[:, :3] @ T[:, :3], (M[:, :3] @ T[:, 3] + M[:, 3])[:, None]])
+
+
+def _bone_scene(n_rods=3, n=10, pin_ends=True):
+    """Straight rods along x, each pill blended between bone 0 (u=0 end) and bone 1 (u=1 end)
+    with weights (1-u, u); rod ends pinned; bone rest poses rotated and offset."""
+    rods = [line(n, origin=(0, 0.02 * k, 0)) for k in range(n_rods)]
+    d = small_scene(rods, comp=(1e-6, 1e-6, 1e-6, 1e-5))
+    P = d.num_pills
+    u = np.tile(np.linspace(0.0, 1.0, n), n_rods)
+    d.pill_bones = np.tile(np.array([[0, 1]], np.int32), (P, 1))
+    d.pill_bone_weights = np.stack([1.0 - u, u], 1)
+    d.bone_rest = np.stack([_affine(_rot((1, 2, 3), 0.4), (0.1, -0.2, 0.05)),
+                            _affine(_rot((0, 1, 0), -0.7), (0.3, 0.0, 0.2))])
+    if pin_ends:
+        for k in range(n_rods):
+            d.pinned[k * n] = 1
+            d.pinned[k * n + n - 1] = 1
+    return d
+
+
+def test_bones_common_rigid_motion_moves_every_pill_rigidly():
+    """Both bones take the same extra rigid motion M (T_cur = M T_rest): every influenced pill
+    goes to M x, whatever its weights (the blend of equal motions is that motion)."""
+    d = _bone_scene()
+    o = OracleScene(d)
+    x0 = o.get_state()["x"]
+    M = _affine(_rot((0.3, -1.0, 0.2), 1.1), (0.05, 0.4, -0.3))
+    o.set_bones(np.stack([_compose(M, T) for T in d.bone_rest]))
+    x1 = o.get_state()["x"]
+    ref = x0 @ M[:, :3].T + M[:, 3]
+    assert np.abs(x1 - ref).max() < 1e-14
+
+
+def test_bones_translations_blend_linearly():
+    """Bones translated by t0 and t1: a pill with weights (w0, w1) moves by
+    (w0 t0 + w1 t1) / (w0 + w1) (weights given unnormalised here, scaled by 2.5)."""
+    d = _bone_scene()
+    d.pill_bone_weights = 2.5 * d.pill_bone_weights
+    o = OracleScene(d)
+    x0 = o.get_state()["x"]
+    t = np.array([[0.1, -0.05, 0.2], [-0.3, 0.1, 0.0]])
+    cur = d.bone_rest.copy()
+    cur[:, :, 3] += t
+    o.set_bones(cur)
+    w = d.pill_bone_weights / d.pill_bone_weights.sum(1, keepdims=True)
+    assert np.abs(o.get_state()["x"] - (x0 + w @ t)).max() < 1e-14
+
+
+def test_bones_frames_compose_for_single_bone_pills_and_identity_is_still():
+    """Pills with one bone: two frames T1, T2 equal the single frame T2 (T2 T1^-1 T1 T0^-1 =
+    T2 T0^-1); pills without weight never move; a frame that repeats the last transforms
+    moves nothing."""
+    d = _bone_scene(pin_ends=False)
+    P = d.num_pills
+    w = d.pill_bone_weights.copy()
+    w[::3] = (1.0, 0.0)
+    w[1::3] = (0.0, 1.0)
+    w[2::3] = (0.0, 0.0)
+    d.pill_bone_weights = w
+    T1 = np.stack([_compose(_affine(_rot((1, 0, 0), 0.3), (0.1, 0, 0)), T) for T in d.bone_rest])
+    T2 = np.stack([_compose(_affine(_rot((0, 0, 1), -0.8), (0, 0.2, 0.1)), T) for T in d.bone_rest])
+    a, b = OracleScene(d), OracleScene(d)
+    x0 = a.get_state()["x"]
+    a.set_bones(T1)
+    a.set_bones(T2)
+    b.set_bones(T2)
+    xa, xb = a.get_state()["x"], b.get_state()["x"]
+    single = np.zeros(P, bool)
+    single[::3] = single[1::3] = True
+    assert np.abs(xa[single] - xb[single]).max() < 1e-14
+    assert np.array_equal(xa[2::3], x0[2::3])
+    a.set_bones(T2)
+    assert np.abs(a.get_state()["x"] - xa).max() < 1e-15
+
+
+def test_bones_pinned_ends_follow_their_bone_through_a_frame():
+    """A pinned rod end with all its weight on one bone sits at T_cur T_rest^-1 x_rest after
+    the warm start and after the frame's substeps (the kinematic attachment); the free pills
+    are pulled along (they move)."""
+    d = _bone_scene()
+    n = 10
+    w = d.pill_bone_weights.copy()
+    w[0::n] = (1.0, 0.0)
+    w[n - 1::n] = (0.0, 1.0)
+    d.pill_bone_weights = w
+    o = OracleScene(d)
+    x0 = o.get_state()["x"]
+    M0 = _affine(_rot((0, 0, 1), 0.2), (0.0, 0.05, 0.0))
+    M1 = _affine(_rot((0, 1, 0), -0.3), (0.02, 0.0, 0.04))
+    cur = np.stack([_compose(M0, d.bone_rest[0]), _compose(M1, d.bone_rest[1])])
+    o.set_bones(cur)
+    o.step(1 / 60, 10, 4)
+    x1 = o.get_state()["x"]
+    e0, e1 = np.arange(0, d.num_pills, n), np.arange(n - 1, d.num_pills, n)
+    assert np.abs(x1[e0] - (x0[e0] @ M0[:, :3].T + M0[:, 3])).max() < 1e-14
+    assert np.abs(x1[e1] - (x0[e1] @ M1[:, :3].T + M1[:, 3])).max() < 1e-14
+    mid = np.arange(d.num_pills)[d.pinned == 0]
+    assert np.abs(x1[mid] - x0[mid]).max() > 1e-3
