@@ -362,6 +362,40 @@ def solver_timing(torch, viper, scenes, dev, frames=5):
     return res
 
 
+def bones_timing(torch, viper, scenes, dev, calls=50):
+    """The bone warm start (Sec. 8.2) on the helix workload (4096 x 64, FP32): two bones, every
+    pill blended between them by its position along its rod; us per set_bones call (HIP events
+    on the launch stream) and algorithmic GB/s (per pill: two weights 16 B, two ids 8 B, the
+    position read and written 24 B, its rod index 4 B)."""
+    import dataclasses
+    d = scenes.helix_rods(4096, 64, seed=1)
+    u = np.tile(np.linspace(0.0, 1.0, 64), 4096)
+    rest = np.tile(np.hstack([np.eye(3), np.zeros((3, 1))])[None], (2, 1, 1))
+    d = dataclasses.replace(d, bone_rest=rest, pill_bones=np.tile(np.array([[0, 1]], np.int32), (d.num_pills, 1)),
+                            pill_bone_weights=np.stack([1.0 - u, u], 1))
+    sc = viper.Scene(d, "f32", device=dev)
+    c, sn = np.cos(1e-4), np.sin(1e-4)
+    frames = []
+    for f in range(calls + 1):
+        T = rest.copy()
+        T[0, :2, :2] = [[c, -sn], [sn, c]]        # small turns either way keep the scene in place
+        T[0, 0, 3] = 1e-5 * (f % 2)
+        T[1, 1, 3] = -1e-5 * (f % 2)
+        frames.append(T)
+    sc.set_bones(frames[0])
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for f in range(1, calls + 1):
+        sc.set_bones(frames[f])
+    e1.record(st)
+    torch.cuda.synchronize()
+    sc.sync()
+    us = e0.elapsed_time(e1) * 1e3 / calls
+    return {"workload": "helix4096x64_two_bones", "pills": d.num_pills, "us_per_call": us,
+            "algorithmic_GB_per_s": 52.0 * d.num_pills / (us * 1e-6) / 1e9}
+
+
 def serving_run(torch, scenes, serve, seconds):
     """Poisson arrivals (200/s) of helix and muscle scenes of 1k-200k pills (log-uniform),
     60 frames each; continuous batching vs the plain per-scene path on the same requests."""
@@ -493,6 +527,8 @@ def main():
     if not args.no_solvers:
         out["solvers"] = solver_timing(torch, viper, scenes, dev)
         log("solvers done")
+    out["bones"] = bones_timing(torch, viper, scenes, dev)
+    log("bones done")
     if not args.no_adjoint:
         out["adjoint"] = adjoint_timing(torch, viper, scenes, dev)
         log("adjoint done")

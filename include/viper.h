@@ -101,6 +101,16 @@ typedef struct {
    * for that rod; NULL = off everywhere.  Solved after the scale gradient in the same edge
    * pass (both solvers); the pool and the adjoint reject a scene that turns it on. */
   const double* cross_compliance;
+  /* Kinematic bones (Sec. 8.2), optional: num_bones rest transforms bone_rest [num_bones*12]
+   * (each [A | b], 3x4 row-major: the bone's pose when the pills are at rest_pos; A
+   * invertible), and two influences per pill, pill_bones [P*2] bone ids and
+   * pill_bone_weights [P*2] weights >= 0 (an id is read only where its weight is > 0; a pill
+   * whose weights are both 0 has no bone).  viper_set_bones then moves the pills with the
+   * bones.  num_bones = 0 turns them off; the pool and the adjoint reject a scene with bones. */
+  int32_t num_bones;
+  const double* bone_rest;
+  const int32_t* pill_bones;
+  const double* pill_bone_weights;
 } viper_scene_desc;
 
 /* Bytes of device workspace the scene needs (host-only computation; validates the
@@ -180,6 +190,16 @@ viper_status viper_skin(viper_scene scene, int32_t skin_id, float* out_dev, void
  * over all capsules: O(V * capsules). */
 viper_status viper_skin_weights(viper_scene scene, int32_t V, const float* rest_v_dev, int32_t* caps_dev, float* w_dev,
                                 void* stream);
+
+/* Kinematic bones (Sec. 8.2): the bones' transforms of a new frame, transforms [num_bones*12]
+ * host memory (read before the call returns), each [A | b] 3x4 row-major with A invertible.
+ * Every pill with bone weight moves by the blend of its bones' motions since the previous
+ * call (or since the rest transforms), x <- sum_k w_k T_k T_prev,k^-1 x / sum_k w_k, in world
+ * coordinates; pinned pills too (that is their kinematic attachment); velocities, scales and
+ * rotations are kept.  Call it at the start of a frame, before viper_step; ordered on
+ * `stream`.  VIPER_ERR_INVALID for a scene without bones or a non-finite or singular
+ * transform (nothing moved). */
+viper_status viper_set_bones(viper_scene scene, const double* transforms, void* stream);
 
 /* Wait for `stream` and report device-side conditions raised since the last sync:
  * VIPER_ERR_NAN, VIPER_ERR_CAPACITY, or VIPER_ERR_DEVICE. Clears them. */

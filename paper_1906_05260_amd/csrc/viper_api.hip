@@ -18,6 +18,7 @@
 
 #include "../../include/viper.h"
 #include "viper_dev.h"
+#include "bones.h"
 #include "contact.h"
 
 using namespace viper;
@@ -60,6 +61,7 @@ struct Offsets {
   size_t scratch[10];      // xpx xpy xpz spv qpx qpy qpz qpw i1 lam(9P)
   size_t flags, wave_start, status, stage, xform, anchor, rod_of, header;
   size_t sec_off = 0, sec_pill = 0, sec_of = 0, sec_xr = 0, sec_q = 0, sec_fit = 0;   // bundling
+  size_t bone_prev = 0, bone_delta = 0, pill_bone = 0, pill_bone_w = 0;  // bones
   ContactOffsets contact;
   size_t total;
 };
@@ -74,12 +76,26 @@ struct Host {
   std::vector<int32_t> rod_of;
   std::vector<double> ilb, il0, cbt, inert, db[3], cs[5], qr[4], mr[3];
   bool any_sr = false;
+  std::vector<double> bone_rest, pill_bone_w;   // bones: rest transforms, two weights per pill
+  std::vector<int32_t> pill_bone;
   // bundling sections: offsets, pills, section of each entry, world rest position of each entry
   std::vector<int32_t> sec_off, sec_pill, sec_of;
   std::vector<double> sec_xr;
 };
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0; }
+
+// A bone transform [A | b] (3x4 row-major): finite, and A far from singular.
+bool affine_ok(const double* T) {
+  double m = 0.0;
+  for (int i = 0; i < 12; ++i) {
+    if (!std::isfinite(T[i])) return false;
+    if (i % 4 != 3) m = std::max(m, std::fabs(T[i]));
+  }
+  const double det = T[0] * (T[5] * T[10] - T[6] * T[9]) - T[1] * (T[4] * T[10] - T[6] * T[8]) +
+                     T[2] * (T[4] * T[9] - T[5] * T[8]);
+  return m > 0 && std::fabs(det) > 1e-12 * m * m * m;
+}
 
 viper_status validate(const viper_scene_desc* d) {
   if (!d) return fail(VIPER_ERR_INVALID, "desc is NULL");
@@ -97,6 +113,14 @@ viper_status validate(const viper_scene_desc* d) {
       return fail(VIPER_ERR_INVALID, "floor_normal must be finite and nonzero, floor_offset finite");
   }
   if (d->solver != 0 && d->solver != 1) return fail(VIPER_ERR_INVALID, "solver must be 0 (Gauss-Seidel) or 1 (Jacobi)");
+  if (d->num_bones < 0) return fail(VIPER_ERR_INVALID, "num_bones < 0");
+  if (d->num_bones > 0) {
+    if (!d->bone_rest || !d->pill_bones || !d->pill_bone_weights)
+      return fail(VIPER_ERR_INVALID, "bone_rest, pill_bones and pill_bone_weights are required");
+    for (int b = 0; b < d->num_bones; ++b)
+      if (!affine_ok(d->bone_rest + 12 * (size_t)b))
+        return fail(VIPER_ERR_INVALID, "bone_rest must be finite with an invertible linear part");
+  }
   if (d->num_sections < 0) return fail(VIPER_ERR_INVALID, "num_sections < 0");
   if (d->num_rods == 0) {
     if (d->num_sections > 0) return fail(VIPER_ERR_INVALID, "bundling sections need pills");
@@ -129,6 +153,14 @@ viper_status validate(const viper_scene_desc* d) {
              dz = d->rest_pos[3 * p + 5] - d->rest_pos[3 * p + 2];
       if (!(dx * dx + dy * dy + dz * dz > 0)) return fail(VIPER_ERR_INVALID, "consecutive rest pills coincide");
     }
+  if (d->num_bones > 0)
+    for (int p = 0; p < P; ++p)
+      for (int k = 0; k < 2; ++k) {
+        const double w = d->pill_bone_weights[2 * (size_t)p + k];
+        if (!std::isfinite(w) || w < 0) return fail(VIPER_ERR_INVALID, "pill_bone_weights must be finite and >= 0");
+        const int b = d->pill_bones[2 * (size_t)p + k];
+        if (w > 0 && (b < 0 || b >= d->num_bones)) return fail(VIPER_ERR_INVALID, "pill_bones out of range");
+      }
   if (d->num_sections > 0) {
     if (!d->section_offsets || !d->section_pills)
       return fail(VIPER_ERR_INVALID, "section_offsets and section_pills are required");
@@ -252,6 +284,12 @@ Offsets make_layout(const viper_scene_desc* d, int P, int W, int E, int cap) {
     o.sec_q = L.take(8 * 4 * (size_t)NS);
     o.sec_fit = L.take(8 * (size_t)kSecFit * NS);
   }
+  if (d->num_bones > 0) {
+    o.bone_prev = L.take(8 * 12 * (size_t)d->num_bones);
+    o.bone_delta = L.take(8 * 12 * (size_t)d->num_bones);
+    o.pill_bone = L.take(4 * 2 * (size_t)P);
+    o.pill_bone_w = L.take(8 * 2 * (size_t)P);
+  }
   Counts c;
   c.W = W; c.P = P; c.E = E; c.T = contact_table_size(E); c.cap = cap * E; c.contacts = d->collisions != 0;
   c.S = NS; c.N = NP;
@@ -290,6 +328,11 @@ void build_host(const viper_scene_desc* d, Host& H) {
   H.off.assign(d->rod_offsets, d->rod_offsets + H.R + 1);
   H.P = H.off[H.R];
   const int P = H.P;
+  if (d->num_bones > 0) {
+    H.bone_rest.assign(d->bone_rest, d->bone_rest + 12 * (size_t)d->num_bones);
+    H.pill_bone.assign(d->pill_bones, d->pill_bones + 2 * (size_t)P);
+    H.pill_bone_w.assign(d->pill_bone_weights, d->pill_bone_weights + 2 * (size_t)P);
+  }
   H.group.resize(H.R);
   for (int k = 0; k < H.R; ++k) H.group[k] = d->group ? d->group[k] : k;
   H.W = pack_waves(d, H.wave_start);
@@ -422,6 +465,7 @@ struct viper_scene_s {
   int floor_on = 0;           // half-plane floor (unit normal, offset)
   int jacobi = 0;             // rod constraints by Jacobi with averaging
   int cross_stretch = 0;      // some rod has the cross-section stretch constraint
+  int nbones = 0;             // kinematic bones
   double floor_n[3] = {0.0, 0.0, 0.0}, floor_d = 0.0;
   int cap = 16;
   int R = 0, P = 0, W = 0, E = 0;
@@ -529,6 +573,11 @@ viper_status upload(viper_scene_s* S, const Host& H, hipStream_t st) {
     HIP_TRY(hipMemcpyAsync(b + S->o.sec_xr, H.sec_xr.data(), 8 * H.sec_xr.size(), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(b + S->o.sec_q, q0.data(), 8 * q0.size(), hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));   // q0 dies with this block
+  }
+  if (S->nbones) {
+    HIP_TRY(hipMemcpyAsync(b + S->o.bone_prev, H.bone_rest.data(), 8 * H.bone_rest.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(b + S->o.pill_bone, H.pill_bone.data(), 4 * H.pill_bone.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(b + S->o.pill_bone_w, H.pill_bone_w.data(), 8 * H.pill_bone_w.size(), hipMemcpyHostToDevice, st));
   }
   HIP_TRY(hipStreamSynchronize(st));   // the host staging vectors die with this frame
   return VIPER_OK;
@@ -670,6 +719,7 @@ viper_status viper_create_scene(const viper_scene_desc* desc, void* workspace, s
   S->nsecp = S->nsec ? desc->section_offsets[S->nsec] : 0;
   S->jacobi = desc->solver == 1;
   S->cross_stretch = H.any_sr ? 1 : 0;
+  S->nbones = desc->num_bones > 0 ? desc->num_bones : 0;
   if (desc->floor_on) {
     const double* n = desc->floor_normal;
     const double l = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
@@ -818,6 +868,23 @@ viper_status viper_skin_weights(viper_scene S, int32_t V, const float* rest_v, i
   return VIPER_OK;
 }
 
+viper_status viper_set_bones(viper_scene S, const double* transforms, void* stream) {
+  if (!S || !transforms) return fail(VIPER_ERR_INVALID, "scene and transforms are required");
+  if (S->nbones == 0) return fail(VIPER_ERR_INVALID, "the scene has no bones");
+  for (int b = 0; b < S->nbones; ++b)
+    if (!affine_ok(transforms + 12 * (size_t)b))
+      return fail(VIPER_ERR_INVALID, "bone transforms must be finite with an invertible linear part");
+  hipStream_t st = (hipStream_t)stream;
+  char* w = S->ws;
+  double* prev = (double*)(w + S->o.bone_prev);
+  double* delta = (double*)(w + S->o.bone_delta);
+  const int32_t* pb = (const int32_t*)(w + S->o.pill_bone);
+  const double* pw = (const double*)(w + S->o.pill_bone_w);
+  if (S->precision == VIPER_F64) HIP_TRY(launch_bone_warm<double>(S->dd, S->nbones, transforms, prev, delta, pb, pw, st));
+  else HIP_TRY(launch_bone_warm<float>(S->df, S->nbones, transforms, prev, delta, pb, pw, st));
+  return VIPER_OK;
+}
+
 viper_status viper_sync(viper_scene S, void* stream) {
   if (!S) return fail(VIPER_ERR_INVALID, "scene is NULL");
   hipStream_t st = (hipStream_t)stream;
@@ -862,6 +929,7 @@ viper_status adjoint_check(viper_scene S, int32_t frames, int32_t substeps, int3
   if (S->floor_on) return fail(VIPER_ERR_INVALID, "the adjoint does not cover the floor");
   if (S->jacobi) return fail(VIPER_ERR_INVALID, "the adjoint covers the Gauss-Seidel solver");
   if (S->cross_stretch) return fail(VIPER_ERR_INVALID, "the adjoint does not cover the cross-section stretch");
+  if (S->nbones) return fail(VIPER_ERR_INVALID, "the adjoint does not cover bones");
   if (frames < 1 || substeps < 1 || iterations < 0)
     return fail(VIPER_ERR_INVALID, "frames >= 1, substeps >= 1 and iterations >= 0 required");
   return VIPER_OK;
@@ -1082,6 +1150,7 @@ viper_status viper_pool_admit(viper_pool P, const viper_scene_desc* desc, void* 
     for (int k = 0; k < desc->num_rods; ++k)
       if (std::isfinite(desc->cross_compliance[k]))
         return fail(VIPER_ERR_INVALID, "scenes with the cross-section stretch are stepped with viper_step");
+  if (desc->num_bones > 0) return fail(VIPER_ERR_INVALID, "scenes with bones are stepped with viper_step");
   size_t fp = 0;
   viper_status r = viper_scene_footprint(desc, &fp);
   if (r != VIPER_OK) return r;

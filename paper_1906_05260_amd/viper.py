@@ -33,7 +33,7 @@ ABI_SYMBOLS = [
     "viper_pool_create", "viper_pool_admit", "viper_pool_step", "viper_pool_retire", "viper_pool_scene",
     "viper_pool_info", "viper_pool_destroy",
     "viper_adjoint_sizes", "viper_step_checkpointed", "viper_step_backward", "viper_pool_step_ex",
-    "viper_skin_weights",
+    "viper_skin_weights", "viper_set_bones",
 ]
 
 
@@ -66,6 +66,10 @@ class SceneDescC(ctypes.Structure):
         ("floor_offset", ctypes.c_double),
         ("solver", ctypes.c_int32),
         ("cross_compliance", ctypes.c_void_p),
+        ("num_bones", ctypes.c_int32),
+        ("bone_rest", ctypes.c_void_p),
+        ("pill_bones", ctypes.c_void_p),
+        ("pill_bone_weights", ctypes.c_void_p),
     ]
 
 
@@ -162,6 +166,17 @@ class _DescHolder:
             if a["sr"].shape[0] != c.num_rods:
                 raise ValueError("cross_compliance needs one value per rod")
             c.cross_compliance = a["sr"].ctypes.data
+        if getattr(desc, "bone_rest", None) is not None:
+            a["brest"] = np.ascontiguousarray(desc.bone_rest, np.float64).reshape(-1)
+            a["pbone"] = np.ascontiguousarray(desc.pill_bones, np.int32).reshape(-1)
+            a["pbw"] = np.ascontiguousarray(desc.pill_bone_weights, np.float64).reshape(-1)
+            if a["brest"].shape[0] % 12 or a["pbone"].shape[0] != 2 * desc.num_pills or \
+                    a["pbw"].shape[0] != 2 * desc.num_pills:
+                raise ValueError("bone_rest needs [nb, 3, 4]; pill_bones and pill_bone_weights [P, 2]")
+            c.num_bones = a["brest"].shape[0] // 12
+            c.bone_rest = a["brest"].ctypes.data
+            c.pill_bones = a["pbone"].ctypes.data
+            c.pill_bone_weights = a["pbw"].ctypes.data
         self.c = c
 
 
@@ -312,6 +327,12 @@ class Scene:
                                        ctypes.c_void_p(w.data_ptr()), _stream_ptr(stream)))
         self._keep_alive = rv
         return caps, w
+
+    def set_bones(self, transforms, stream=None):
+        """The bones' transforms of a new frame, [nb, 3, 4] (include/viper.h, viper_set_bones):
+        every pill with bone weight moves by the blend of its bones' motions (Sec. 8.2)."""
+        t = np.ascontiguousarray(transforms, np.float64).reshape(-1)
+        check(lib().viper_set_bones(self.handle, ctypes.c_void_p(t.ctypes.data), _stream_ptr(stream)))
 
     def sync(self, stream=None):
         check(lib().viper_sync(self.handle, _stream_ptr(stream)))

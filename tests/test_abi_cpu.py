@@ -133,3 +133,41 @@ def test_cross_stretch_validation():
         assert ei.value.status == viper.ERR_INVALID and "cross_compliance" in str(ei.value)
     with pytest.raises(ValueError):
         viper.footprint(dataclasses.replace(d, cross_compliance=np.zeros(3)))
+
+
+def _with_bones(d, nb=2):
+    P = d.num_pills
+    rest = np.tile(np.hstack([np.eye(3), np.zeros((3, 1))])[None], (nb, 1, 1))
+    pb = np.tile(np.array([[0, nb - 1]], np.int32), (P, 1))
+    pw = np.tile(np.array([[0.25, 0.75]]), (P, 1))
+    return dataclasses.replace(d, bone_rest=rest, pill_bones=pb, pill_bone_weights=pw)
+
+
+def test_bone_validation():
+    """Bones (Sec. 8.2): rest transforms finite with an invertible linear part, weights finite
+    and >= 0, a bone id in range wherever its weight is positive (ignored where it is zero);
+    the workspace grows by the bone and influence arrays."""
+    d = scenes.helix_rods(2, 8, seed=1)
+    base = viper.footprint(d)
+    assert viper.footprint(_with_bones(d)) > base
+    ok = _with_bones(d)
+    ok.pill_bones[3] = (-1, 1)
+    ok.pill_bone_weights[3] = (0.0, 1.0)
+    viper.footprint(ok)
+    bad = []
+    b = _with_bones(d)
+    b.bone_rest[1, :, :3] = 0.0
+    bad.append((b, "bone_rest"))
+    b = _with_bones(d)
+    b.bone_rest[0, 1, 3] = np.nan
+    bad.append((b, "bone_rest"))
+    b = _with_bones(d)
+    b.pill_bone_weights[5, 0] = -0.1
+    bad.append((b, "pill_bone_weights"))
+    b = _with_bones(d)
+    b.pill_bones[2, 1] = 2
+    bad.append((b, "pill_bones"))
+    for b, msg in bad:
+        with pytest.raises(viper.ViperError) as ei:
+            viper.footprint(b)
+        assert ei.value.status == viper.ERR_INVALID and msg in str(ei.value), str(ei.value)
