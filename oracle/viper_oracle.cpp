@@ -218,7 +218,7 @@ struct Desc {
   double gravity[3];
 };
 
-enum { SS = 0, VOL = 1, SG = 2, BT = 3, SR = 4 };
+enum { SS = 0, VOL = 1, SG = 2, BT = 3, SR = 4, SB = 5 };
 
 template <class R> struct Scene {
   int nrods = 0, P = 0;
@@ -242,6 +242,11 @@ template <class R> struct Scene {
   // per-slot compliance alpha / (pi r^2 l) and multiplier
   std::vector<uint8_t> sr_on;
   std::vector<R> comp_sr, lam_sr;
+  // surface bending (second variation of the scale along the rod), optional, off by default:
+  // per-rod enable, per-slot compliance alpha / (pi r^4 / 4 l_v) and multiplier (slot p: the
+  // vertex between edges p and p+1)
+  std::vector<uint8_t> sb_on;
+  std::vector<R> comp_sb, lam_sb;
   // state
   std::vector<V3<R>> x, v;
   std::vector<R> s, sd;
@@ -366,6 +371,9 @@ template <class R> void build(Scene<R>& S, const Desc& d, const R* rbar, const R
   S.sr_on.assign(S.nrods, 0);
   S.comp_sr.assign(P, R(0.0));
   S.lam_sr.assign(P, R(0.0));
+  S.sb_on.assign(S.nrods, 0);
+  S.comp_sb.assign(P, R(0.0));
+  S.lam_sb.assign(P, R(0.0));
   S.active_count.assign(P, 0);
 }
 
@@ -474,6 +482,27 @@ template <class R> int project_sr(Scene<R>& S, int p, R ih2) {
   xpbd_update(1, C, alpha, &S.lam_sr[p], B, 2);
   S.s[p] += B[0].out[0];
   S.s[p + 1] += B[1].out[0];
+  return 1;
+}
+
+// Surface bending at vertex p+1 (the energy of the Laplacian of the scale, Sec. 5): along the
+// rod the Laplacian is the second difference of the pill scales over the vertex's Voronoi
+// length l_v = (l0_p + l0_{p+1}) / 2; the rest scale is one everywhere, so its Laplacian is 0:
+//   C = [(s_{p+2} - s_{p+1}) / l0_{p+1} - (s_{p+1} - s_p) / l0_p] / l_v
+template <class R> int project_sb(Scene<R>& S, int p, R ih2) {
+  if (!S.sb_on[S.rod_of[p]]) return 0;
+  const R la = S.l0[p], lb = S.l0[p + 1], lv = R(0.5) * (la + lb);
+  R C[1] = {((S.s[p + 2] - S.s[p + 1]) / lb - (S.s[p + 1] - S.s[p]) / la) / lv};
+  R alpha[1] = {S.comp_sb[p] * ih2};
+  Block<R> B[3];
+  const R g0 = R(1.0) / (la * lv), g2 = R(1.0) / (lb * lv);
+  B[0].ndof = 1; B[0].J[0][0] = g0; B[0].W[0][0] = S.wsinv[p];
+  B[1].ndof = 1; B[1].J[0][0] = -(g0 + g2); B[1].W[0][0] = S.wsinv[p + 1];
+  B[2].ndof = 1; B[2].J[0][0] = g2; B[2].W[0][0] = S.wsinv[p + 2];
+  xpbd_update(1, C, alpha, &S.lam_sb[p], B, 3);
+  S.s[p] += B[0].out[0];
+  S.s[p + 1] += B[1].out[0];
+  S.s[p + 2] += B[2].out[0];
   return 1;
 }
 
@@ -686,6 +715,7 @@ template <class R> void predict_rods(Scene<R>& S, R h, int r0, int r1) {
       }
       for (int t = 0; t < 8; ++t) S.lam[size_t(p) * 8 + t] = R(0.0);
       S.lam_sr[p] = R(0.0);
+      S.lam_sb[p] = R(0.0);
     }
   for (int k = r0; k < r1; ++k)
     for (int p = S.off[k]; p + 1 < S.off[k + 1]; ++p) {
@@ -712,6 +742,10 @@ template <class R> int64_t solve_colours(Scene<R>& S, R ih2, int r0, int r1) {
   for (int colour = 0; colour < 2; ++colour)
     for (int k = r0; k < r1; ++k)
       for (int p = S.off[k] + colour; p + 2 < S.off[k + 1]; p += 2) n += project_bt(S, p, ih2);
+  // surface bending touches three consecutive scales: three colours
+  for (int colour = 0; colour < 3; ++colour)
+    for (int k = r0; k < r1; ++k)
+      for (int p = S.off[k] + colour; p + 2 < S.off[k + 1]; p += 3) n += project_sb(S, p, ih2);
   return n;
 }
 
@@ -733,12 +767,14 @@ template <class R> int64_t solve_jacobi(Scene<R>& S, R ih2) {
     const int q1 = p + 1;
     const V3<R> x0 = S.x[p], x1 = S.x[q1];
     const R s0 = S.s[p], s1 = S.s[q1];
+    const R s2 = (kind == SB) ? S.s[p + 2] : R(0.0);
     const Q4<R> r0 = S.q[p], r1 = S.q[q1];
     int a = 0;
     if (kind == SS) a = project_ss(S, p, ih2);
     else if (kind == VOL) a = project_vol(S, p, ih2);
     else if (kind == SG) a = project_sg(S, p, ih2);
     else if (kind == SR) a = project_sr(S, p, ih2);
+    else if (kind == SB) a = project_sb(S, p, ih2);
     else a = project_bt(S, p, ih2);
     if (!a) return;
     n += a;
@@ -749,6 +785,11 @@ template <class R> int64_t solve_jacobi(Scene<R>& S, R ih2) {
       ds[p] = ds[p] + (S.s[p] - s0); ds[q1] = ds[q1] + (S.s[q1] - s1); ++ns[p]; ++ns[q1];
     }
     if (kind == BT) { ds[q1] = ds[q1] + (S.s[q1] - s1); ++ns[q1]; }
+    if (kind == SB) {
+      ds[p] = ds[p] + (S.s[p] - s0); ds[q1] = ds[q1] + (S.s[q1] - s1); ds[p + 2] = ds[p + 2] + (S.s[p + 2] - s2);
+      ++ns[p]; ++ns[q1]; ++ns[p + 2];
+      S.s[p + 2] = s2;
+    }
     auto addq = [&](int i, const Q4<R>& before) {
       dq[i] = q4<R>(dq[i].x + (S.q[i].x - before.x), dq[i].y + (S.q[i].y - before.y), dq[i].z + (S.q[i].z - before.z),
                     dq[i].w + (S.q[i].w - before.w));
@@ -765,6 +806,7 @@ template <class R> int64_t solve_jacobi(Scene<R>& S, R ih2) {
       eval(SG, p);
       eval(SR, p);
       if (p + 2 < S.off[k + 1]) eval(BT, p);
+      if (p + 2 < S.off[k + 1]) eval(SB, p);
     }
   for (int p = 0; p < P; ++p) {
     if (nx[p]) S.x[p] = S.x[p] + (R(1.0) / R(double(nx[p]))) * dx[p];
@@ -988,6 +1030,11 @@ template <class R> double rod_residual(const Scene<R>& S0, R ih2) {
         R C = R(0.5) * (S.s[p] + S.s[p + 1]) - R(1.0) + S.comp_sr[p] * ih2 * S.lam_sr[p];
         acc += val(C * C);
       }
+      if (p + 2 < S.off[k + 1] && S.sb_on[k]) {
+        const R la = S.l0[p], lb = S.l0[p + 1], lv = R(0.5) * (la + lb);
+        R C = ((S.s[p + 2] - S.s[p + 1]) / lb - (S.s[p + 1] - S.s[p]) / la) / lv + S.comp_sb[p] * ih2 * S.lam_sb[p];
+        acc += val(C * C);
+      }
       if (p + 2 < S.off[k + 1] && S.enabled[4 * k + BT]) {
         Q4<R> r = qmul(qconj(S.q[p]), S.q[p + 1]);
         if (r.w < R(0.0)) r = q4<R>(-r.x, -r.y, -r.z, -r.w);
@@ -1120,6 +1167,19 @@ template <class R> static void set_cross_stretch_t(Scene<R>& S, const double* co
   }
 }
 
+// Surface-bending compliance per rod (+inf: off); G = pi r^4 / 4 over the Voronoi length,
+// r the vertex's rest radius, as for bend-twist.
+template <class R> static void set_surface_bending_t(Scene<R>& S, const double* comp) {
+  const double pi = 3.14159265358979323846;
+  for (int k = 0; k < S.nrods; ++k) {
+    S.sb_on[k] = std::isfinite(comp[k]) ? 1 : 0;
+    for (int p = S.off[k]; p + 2 < S.off[k + 1]; ++p) {
+      const R rv = S.rbar[p + 1], lv = R(0.5) * (S.l0[p] + S.l0[p + 1]);
+      S.comp_sb[p] = S.sb_on[k] ? R(comp[k]) / (R(pi) * rv * rv * rv * rv / R(4.0) * lv) : R(0.0);
+    }
+  }
+}
+
 template <class R> static void set_floor_t(Scene<R>& S, const double* n, double d) {
   const double l = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
   S.floor_on = true;
@@ -1138,6 +1198,7 @@ template <class R> static int64_t rod_iterations_t(Scene<R>& S, double h_sub, in
     }
     for (int t = 0; t < 8; ++t) S.lam[size_t(i) * 8 + t] = R(0.0);
     S.lam_sr[i] = R(0.0);
+    S.lam_sb[i] = R(0.0);
   }
   const R ih2 = R(1.0 / (h_sub * h_sub));
   int64_t n = 0;
@@ -1229,6 +1290,11 @@ void orc_set_cross_stretch(void* hp, const double* comp) {
   Handle* h = (Handle*)hp;
   if (h->d) set_cross_stretch_t(*h->d, comp); else set_cross_stretch_t(*h->f, comp);
 }
+// Surface-bending compliance per rod, [nrods]; +inf leaves it off.
+void orc_set_surface_bending(void* hp, const double* comp) {
+  Handle* h = (Handle*)hp;
+  if (h->d) set_surface_bending_t(*h->d, comp); else set_surface_bending_t(*h->f, comp);
+}
 // Solver of the rod constraints: 0 = coloured Gauss-Seidel, 1 = Jacobi with averaging.
 void orc_set_solver(void* hp, int jacobi) {
   Handle* h = (Handle*)hp;
@@ -1287,7 +1353,7 @@ void orc_get_rest(void* hp, double* l0, double* lbar, double* qrest, double* dar
 }
 
 // Single-constraint primitives for closed-form pins (double scene only).
-// kind: 0 SS, 1 VOL, 2 SG, 3 BT, 4 SR at slot p, with the substep inertia computed from
+// kind: 0 SS, 1 VOL, 2 SG, 3 BT, 4 SR, 5 SB at slot p, with the substep inertia computed from
 // the current scale.  lambda is zeroed first.
 void orc_project_one(void* hp, int kind, int p, double h) {
   Handle* hd = (Handle*)hp;
@@ -1300,11 +1366,13 @@ void orc_project_one(void* hp, int kind, int p, double h) {
     }
     for (int t = 0; t < 8; ++t) S.lam[size_t(i) * 8 + t] = 0.0;
     S.lam_sr[i] = 0.0;
+    S.lam_sb[i] = 0.0;
   }
   double ih2 = 1.0 / (h * h);
   if (kind == 0) project_ss(S, p, ih2);
   if (kind == 1) project_vol(S, p, ih2);
   if (kind == 4) project_sr(S, p, ih2);
+  if (kind == 5) project_sb(S, p, ih2);
   if (kind == 2) project_sg(S, p, ih2);
   if (kind == 3) project_bt(S, p, ih2);
 }

@@ -44,6 +44,9 @@ class SceneDesc:
     solver: str = "gauss_seidel"
     # cross-section stretch (eq. stretch_xy) compliance per rod [num_rods]; None or +inf = off
     cross_compliance: np.ndarray = None
+    # surface bending (Laplacian of the scale along the rod, Sec. 5) compliance per rod
+    # [num_rods]; None or +inf = off
+    bending_compliance: np.ndarray = None
     # kinematic bones (Sec. 8.2): rest transforms [nb, 3, 4] (the bones' pose at rest_pos) and
     # two (bone, weight) influences per pill, [P, 2] int32 and [P, 2] float64; None = no bones
     bone_rest: np.ndarray = None

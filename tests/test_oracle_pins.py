@@ -1098,3 +1098,68 @@ def test_bones_pinned_ends_follow_their_bone_through_a_frame():
     assert np.abs(x1[e1] - (x0[e1] @ M1[:, :3].T + M1[:, 3])).max() < 1e-14
     mid = np.arange(d.num_pills)[d.pinned == 0]
     assert np.abs(x1[mid] - x0[mid]).max() > 1e-3
+
+
+# ---------------------------------------------------------------- surface bending
+
+def _sb_scene(comp_sb, z, radius=0.005):
+    pos = np.zeros((len(z), 3))
+    pos[:, 0] = z
+    d = small_scene([pos], radius=radius, comp=(INF, INF, INF, INF))
+    d.bending_compliance = np.array([comp_sb])
+    return d
+
+
+def test_surface_bending_leaves_linear_scale_profiles_alone():
+    """The Laplacian of a scale profile linear in arclength vanishes, on unevenly spaced pills
+    too (a length taken from the wrong edge would not vanish here): every projection of a
+    rigid surface bending leaves such a profile exactly as it is (to rounding)."""
+    z = np.cumsum([0.0, 0.010, 0.017, 0.008, 0.013, 0.021, 0.009])
+    o = OracleScene(_sb_scene(0.0, z))
+    s = 0.9 + 3.0 * z
+    o.set_state(s=s)
+    o.rod_iterations(1 / 600, 3)
+    assert np.abs(o.get_state()["s"] - s).max() < 1e-14
+
+
+def test_surface_bending_rigid_projection_is_the_mass_weighted_projection():
+    """On three unevenly spaced pills with unequal scale masses and a quadratic scale profile
+    (second derivative 2 everywhere), one rigid projection equals the KKT solution of
+    min 1/2 ds^T M ds  s.t. the three-point second difference of s + ds (the second
+    derivative of the parabola through the three pills) is 0."""
+    z = np.array([0.0, 0.012, 0.031])
+    d = _sb_scene(0.0, z, radius=np.array([0.005, 0.004, 0.003]))
+    o = OracleScene(d)
+    s0 = 1.0 + 40.0 * z ** 2
+    o.set_state(s=s0)
+    o.project_one(5, 0, 1e-3)
+    s1 = o.get_state()["s"]
+    M = np.diag(1.0 / o.rest()["wsinv"])
+    # second derivative of the interpolating parabola = 2 * divided difference [z0, z1, z2]
+    a = 2.0 * np.array([1 / ((z[0] - z[1]) * (z[0] - z[2])), 1 / ((z[1] - z[0]) * (z[1] - z[2])),
+                        1 / ((z[2] - z[0]) * (z[2] - z[1]))])
+    assert abs(a @ s0 - 80.0) < 1e-9
+    K = np.block([[M, a[:, None]], [a[None, :], np.zeros((1, 1))]])
+    sol = np.linalg.solve(K, np.concatenate([np.zeros(3), [-(a @ s0)]]))
+    assert np.abs(s1 - (s0 + sol[:3])).max() < 1e-13
+    assert abs(a @ s1) < 1e-9
+
+
+def test_surface_bending_with_cross_stretch_drives_every_scale_to_rest():
+    """Rigid surface bending and rigid cross-section stretch on 11 pills: surface bending alone
+    keeps linear profiles, cross-section stretch alone keeps the alternating one (1 +- e);
+    together only s = 1 remains, and Gauss-Seidel reaches it from random scales."""
+    z = 0.01 * np.arange(11)
+    d = _sb_scene(0.0, z)
+    d.cross_compliance = np.array([0.0])
+    o = OracleScene(d)
+    rng = np.random.default_rng(4)
+    o.set_state(s=rng.uniform(0.7, 1.3, 11))
+    o.rod_iterations(1 / 600, 3000)
+    assert np.abs(o.get_state()["s"] - 1.0).max() < 1e-8
+    alt = 1.0 + 0.05 * (-1.0) ** np.arange(11)
+    d.bending_compliance = np.array([INF])
+    a = OracleScene(d)
+    a.set_state(s=alt)
+    a.rod_iterations(1 / 600, 5)
+    assert np.abs(a.get_state()["s"] - alt).max() < 1e-14
