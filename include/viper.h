@@ -111,6 +111,14 @@ typedef struct {
   const double* bone_rest;
   const int32_t* pill_bones;
   const double* pill_bone_weights;
+  /* Surface bending (Sec. 5: the energy of the Laplacian of the scale), optional: compliance
+   * per rod [num_rods] of the constraint at every interior vertex j (between edges j-1, j)
+   * C = [(s_{j+1} - s_j) / l_j - (s_j - s_{j-1}) / l_{j-1}] / l_v, l_v = (l_{j-1} + l_j) / 2
+   * (the rest scale is one, its Laplacian zero), scaled by 1 / (pi r^4 / 4 l_v) as bend-twist;
+   * >= 0, +inf = off for that rod; NULL = off everywhere.  Solved in three colour passes after
+   * bend-twist (Gauss-Seidel only: a Jacobi scene that turns it on is VIPER_ERR_INVALID); the
+   * pool and the adjoint reject a scene that turns it on. */
+  const double* bending_compliance;
 } viper_scene_desc;
 
 /* Bytes of device workspace the scene needs (host-only computation; validates the

@@ -51,11 +51,12 @@ struct Slot {
   T x0, x1, x2, v0, v1, v2, s, sd;
   T q0, q1, q2, q3, o0, o1, o2;
   T xp0, xp1, xp2, sp, qp0, qp1, qp2, qp3;
-  T l[9];                      // multipliers of the slot's constraints: ss(3) vol sg bt(3) sr
+  T l[10];                     // multipliers of the slot's constraints: ss(3) vol sg bt(3) sr sb
   T w, ws;                     // inverse position / scale mass
   T ilb, il0, cbt, inert;      // edge constants
   T db0, db1, db2;             // rest Darboux vector
   T ass, avol, asg, abt, asr;  // compliance / (G l h^2)
+  T asb, sg0, sg2;             // surface bending: compliance / (G l_v h^2), dC/ds of the first and third pill
   T I1;                        // inverse bending inertia of the slot's edge (this substep)
   uint32_t f;
 };
@@ -64,6 +65,7 @@ template <class T>
 struct Lane2 {
   Slot<T> A, B;
   T wN, wsN, I1N;              // next lane's slot A: inverse masses, inverse bending inertia
+  bool sb;                     // some rod of the wavefront has surface bending
 };
 
 // ---------------------------------------------------------------- per-slot stages
@@ -81,7 +83,7 @@ __device__ __forceinline__ void predict_slot(Slot<T>& L, T h, T gx, T gy, T gz) 
   L.qp0 = L.q0; L.qp1 = L.q1; L.qp2 = L.q2; L.qp3 = L.q3;
   if (L.f & F_EDGE) qrot_world(L.q0, L.q1, L.q2, L.q3, h * L.o0, h * L.o1, h * L.o2);
 #pragma unroll
-  for (int i = 0; i < 9; ++i) L.l[i] = T(0);
+  for (int i = 0; i < 10; ++i) L.l[i] = T(0);
 }
 
 // Inverse bending inertia 4 / (rho pi r^4 l s_m^2) of an edge from the substep-start
@@ -318,12 +320,60 @@ __device__ __forceinline__ void pass_bt(Lane2<T>& P, int colour) {
   }
 }
 
+// Surface bending at the vertex after slot L's edge: scales s0 (the slot's), s1, s2 (the next
+// two pills) with inverse scale masses w0..w2,
+//   C = g0 s0 - (g0 + g2) s1 + g2 s2,  g0 = 1 / (l_a l_v), g2 = 1 / (l_b l_v).
+template <class T>
+__device__ __forceinline__ void sb_update(Slot<T>& L, T& s0, T& s1, T& s2, T w0, T w1, T w2) {
+  const T g0 = L.sg0, g2 = L.sg2, g1 = -(g0 + g2), at = L.asb;
+  const T C = g0 * s0 + g1 * s1 + g2 * s2;
+  const T S = w0 * g0 * g0 + w1 * g1 * g1 + w2 * g2 * g2 + at;
+  const T dl = (-C - at * L.l[9]) * rcp(S);
+  L.l[9] += dl;
+  s0 += w0 * g0 * dl;
+  s1 += w1 * g1 * dl;
+  s2 += w2 * g2 * dl;
+}
+
+__device__ __forceinline__ bool mod3_is(uint32_t f, int colour) {
+  return (int)((f & F_M3A) ? 1 : (f & F_M3B) ? 2 : 0) == colour;
+}
+
+// Surface bending at every vertex whose first pill has local index `colour` mod 3.  Three
+// consecutive scales: an owner in slot A reaches the next lane's A, an owner in slot B the
+// next lane's A and B; the changed values travel back up one lane.
+template <class T>
+__device__ __forceinline__ void pass_sb(Lane2<T>& P, int colour) {
+  T nA = dn(P.A.s), nB = dn(P.B.s);
+  const T wsNB = dn(P.B.ws);
+  T sent = T(0);   // 1: the next lane's A changed, 2: its A and B
+  if ((P.A.f & F_BT) && (P.A.f & F_SB) && mod3_is(P.A.f, colour)) {
+    sb_update(P.A, P.A.s, P.B.s, nA, P.A.ws, P.B.ws, P.wsN);
+    sent = T(1);
+  } else if ((P.B.f & F_BT) && (P.B.f & F_SB) && mod3_is(P.B.f, colour)) {
+    sb_update(P.B, P.B.s, nA, nB, P.B.ws, P.wsN, wsNB);
+    sent = T(2);
+  }
+  nA = up(nA); nB = up(nB); sent = up(sent);
+  // a rod's first pill is never reached from the previous lane (this also covers lane 0,
+  // whose shifted values are its own)
+  if ((P.A.f & F_VALID) && !(P.A.f & F_FIRST) && sent > T(0)) {
+    P.A.s = nA;
+    if (sent > T(1.5) && (P.B.f & F_VALID)) P.B.s = nB;
+  }
+}
+
 template <class T>
 __device__ __forceinline__ void iteration_lane(Lane2<T>& P) {
   pass_edges(P, 0);
   pass_edges(P, 1);
   pass_bt(P, 0);
   pass_bt(P, 1);
+  if (P.sb) {   // the same on every lane of the wavefront
+    pass_sb(P, 0);
+    pass_sb(P, 1);
+    pass_sb(P, 2);
+  }
 }
 
 // ---------------------------------------------------------------- load / store
@@ -345,6 +395,7 @@ __device__ __forceinline__ const Dev<T>* lane_setup(const Dev<T>* D, const Blk* 
   pB = p0 + (vB ? 2 * lane + 1 : 0);
   P.A.f = vA ? d->flags[pA] : 0u;
   P.B.f = vB ? d->flags[pB] : 0u;
+  P.sb = __any(((P.A.f | P.B.f) & F_SB) != 0u) != 0;
   return d;
 }
 
@@ -364,6 +415,10 @@ __device__ __forceinline__ void load_consts(const Dev<T>& d, Slot<T>& L, int p, 
   L.db0 = d.dbx[p]; L.db1 = d.dby[p]; L.db2 = d.dbz[p];
   L.ass = d.css[p] * ih2; L.avol = d.cvol[p] * ih2; L.asg = d.csg[p] * ih2; L.abt = d.cbtc[p] * ih2;
   L.asr = (L.f & F_SR) ? d.csr[p] * ih2 : T(0);
+  const bool sb = (L.f & F_SB) && (L.f & F_BT);
+  L.asb = sb ? d.csb[p] * ih2 : T(0);
+  L.sg0 = sb ? d.sbg0[p] : T(0);
+  L.sg2 = sb ? d.sbg2[p] : T(0);
 }
 
 template <class T>

@@ -66,7 +66,7 @@ __device__ __forceinline__ void store_predicted(const Dev<T>& d, const Slot<T>& 
   d.qpx[p] = L.qp0; d.qpy[p] = L.qp1; d.qpz[p] = L.qp2; d.qpw[p] = L.qp3;
   d.i1[p] = L.I1;
 #pragma unroll
-  for (int i = 0; i < 9; ++i) d.lam[(size_t)i * d.P + p] = T(0);
+  for (int i = 0; i < 10; ++i) d.lam[(size_t)i * d.P + p] = T(0);
 }
 
 template <class T>
@@ -94,7 +94,7 @@ __device__ __forceinline__ void load_iter(const Dev<T>& d, Slot<T>& L, int p) {
   L.x0 = d.px[p]; L.x1 = d.py[p]; L.x2 = d.pz[p]; L.s = d.s[p];
   L.q0 = d.qx[p]; L.q1 = d.qy[p]; L.q2 = d.qz[p]; L.q3 = d.qw[p];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) L.l[i] = d.lam[(size_t)i * d.P + p];
+  for (int i = 0; i < 10; ++i) L.l[i] = d.lam[(size_t)i * d.P + p];
   L.I1 = d.i1[p];
 }
 
@@ -104,7 +104,7 @@ __device__ __forceinline__ void store_iter(const Dev<T>& d, const Slot<T>& L, in
   d.px[p] = L.x0; d.py[p] = L.x1; d.pz[p] = L.x2; d.s[p] = L.s;
   d.qx[p] = L.q0; d.qy[p] = L.q1; d.qz[p] = L.q2; d.qw[p] = L.q3;
 #pragma unroll
-  for (int i = 0; i < 9; ++i) d.lam[(size_t)i * d.P + p] = L.l[i];
+  for (int i = 0; i < 10; ++i) d.lam[(size_t)i * d.P + p] = L.l[i];
 }
 
 // ITERATION mode, Jacobi variant of stage 2 (Sec. 7: constraints computed in parallel, their

@@ -57,8 +57,9 @@ struct Layout {
 struct Offsets {
   size_t state[15];        // px py pz vx vy vz s sd qx qy qz qw ox oy oz
   size_t pill_rest[3];     // winv wsinv rbar
-  size_t edge_rest[19];    // ilb il0 cbt inert dbx dby dbz css cvol csg cbtc qrx qry qrz qrw mrx mry mrz csr
-  size_t scratch[10];      // xpx xpy xpz spv qpx qpy qpz qpw i1 lam(9P)
+  size_t edge_rest[22];    // ilb il0 cbt inert dbx dby dbz css cvol csg cbtc qrx qry qrz qrw mrx mry mrz csr
+                           // csb sbg0 sbg2
+  size_t scratch[10];      // xpx xpy xpz spv qpx qpy qpz qpw i1 lam(10P)
   size_t flags, wave_start, status, stage, xform, anchor, rod_of, header;
   size_t sec_off = 0, sec_pill = 0, sec_of = 0, sec_xr = 0, sec_q = 0, sec_fit = 0;   // bundling
   size_t bone_prev = 0, bone_delta = 0, pill_bone = 0, pill_bone_w = 0;  // bones
@@ -75,7 +76,8 @@ struct Host {
   std::vector<double> x, rbar, winv, wsinv, anchor, xloc;
   std::vector<int32_t> rod_of;
   std::vector<double> ilb, il0, cbt, inert, db[3], cs[5], qr[4], mr[3];
-  bool any_sr = false;
+  std::vector<double> sbc, sbg0, sbg2;   // surface bending: compliance scaling, dC/ds_j-1, dC/ds_j+1
+  bool any_sr = false, any_sb = false;
   std::vector<double> bone_rest, pill_bone_w;   // bones: rest transforms, two weights per pill
   std::vector<int32_t> pill_bone;
   // bundling sections: offsets, pills, section of each entry, world rest position of each entry
@@ -139,6 +141,12 @@ viper_status validate(const viper_scene_desc* d) {
     }
     if (d->cross_compliance && (std::isnan(d->cross_compliance[k]) || d->cross_compliance[k] < 0))
       return fail(VIPER_ERR_INVALID, "cross_compliance must be >= 0 or +inf");
+    if (d->bending_compliance) {
+      const double c = d->bending_compliance[k];
+      if (std::isnan(c) || c < 0) return fail(VIPER_ERR_INVALID, "bending_compliance must be >= 0 or +inf");
+      if (d->solver == 1 && std::isfinite(c))
+        return fail(VIPER_ERR_INVALID, "surface bending (bending_compliance) needs the Gauss-Seidel solver");
+    }
   }
   const int P = d->rod_offsets[d->num_rods];
   if (P > (1 << 27)) return fail(VIPER_ERR_INVALID, "too many pills");
@@ -267,7 +275,7 @@ Offsets make_layout(const viper_scene_desc* d, int P, int W, int E, int cap) {
   for (auto& v : o.pill_rest) v = L.take(ts * P);
   for (auto& v : o.edge_rest) v = L.take(ts * P);
   for (int i = 0; i < 9; ++i) o.scratch[i] = L.take(ts * P);
-  o.scratch[9] = L.take(ts * 9 * (size_t)P);
+  o.scratch[9] = L.take(ts * 10 * (size_t)P);
   o.flags = L.take(4 * (size_t)P);
   o.wave_start = L.take(4 * (size_t)(W + 1));
   o.status = L.take(4 * ST_WORDS);
@@ -367,7 +375,9 @@ void build_host(const viper_scene_desc* d, Host& H) {
   for (int i = 0; i < 3; ++i) { H.db[i].assign(P, 0); H.mr[i].assign(P, 0); }
   for (int i = 0; i < 4; ++i) { H.cs[i].assign(P, 0); H.qr[i].assign(P, 0); }
   H.cs[4].assign(P, 0);
+  H.sbc.assign(P, 0); H.sbg0.assign(P, 0); H.sbg2.assign(P, 0);
   H.any_sr = false;
+  H.any_sb = false;
   for (int p = 0; p < P; ++p) H.qr[3][p] = 1.0;
   const double rho = d->density;
   H.E = 0;
@@ -379,14 +389,18 @@ void build_host(const viper_scene_desc* d, Host& H) {
     bool en[4];
     for (int t = 0; t < 4; ++t) en[t] = std::isfinite(d->compliance[4 * k + t]);
     const bool sr = d->cross_compliance && std::isfinite(d->cross_compliance[k]);
+    const bool sb = d->bending_compliance && std::isfinite(d->bending_compliance[k]);
     H.any_sr = H.any_sr || sr;
+    H.any_sb = H.any_sb || sb;
     uint32_t ef = (en[0] ? F_SS : 0u) | (en[1] ? F_VOL : 0u) | (en[2] ? F_SG : 0u) | (en[3] ? F_BTEN : 0u) |
-                  (sr ? F_SR : 0u);
+                  (sr ? F_SR : 0u) | (sb ? F_SB : 0u);
     double tprev[3] = {0, 0, 1}, qcur[4] = {0, 0, 0, 1};
     for (int p = a; p < b; ++p) {
       uint32_t f = F_VALID | ef;
       if (p == a) f |= F_FIRST;
       if ((p - a) & 1) f |= F_ODD;
+      if ((p - a) % 3 == 1) f |= F_M3A;
+      if ((p - a) % 3 == 2) f |= F_M3B;
       if (p + 1 < b) f |= F_EDGE;
       if (p + 2 < b) f |= F_BT;
       H.flags[p] = f;
@@ -421,6 +435,12 @@ void build_host(const viper_scene_desc* d, Host& H) {
       const double rv = H.rbar[p + 1], r4 = rv * rv * rv * rv;
       const double lv = 0.5 * (l0[p] + l0[p + 1]);
       if (en[3]) H.cs[3][p] = d->compliance[4 * k + 3] / (kPi * r4 / 4.0 * lv);
+      if (sb) {
+        H.sbc[p] = d->bending_compliance[k] / (kPi * r4 / 4.0 * lv);
+        H.sbg0[p] = 1.0 / (l0[p] * lv);
+        H.sbg2[p] = 1.0 / (l0[p + 1] * lv);
+        H.proj_per_iter += 1;
+      }
       const double c = 4.0 / (l0[p] + l0[p + 1]);
       H.cbt[p] = c;
       const double qa[4] = {-H.qr[0][p], -H.qr[1][p], -H.qr[2][p], H.qr[3][p]};
@@ -466,6 +486,7 @@ struct viper_scene_s {
   int jacobi = 0;             // rod constraints by Jacobi with averaging
   int cross_stretch = 0;      // some rod has the cross-section stretch constraint
   int nbones = 0;             // kinematic bones
+  int surface_bending = 0;    // some rod has the surface-bending constraint
   double floor_n[3] = {0.0, 0.0, 0.0}, floor_d = 0.0;
   int cap = 16;
   int R = 0, P = 0, W = 0, E = 0;
@@ -506,9 +527,10 @@ void fill_dev(viper_scene_s* S, Dev<T>& d) {
   for (int i = 0; i < 15; ++i) *st[i] = P_(S->o.state[i]);
   const T** pr[3] = {&d.winv, &d.wsinv, &d.rbar};
   for (int i = 0; i < 3; ++i) *pr[i] = P_(S->o.pill_rest[i]);
-  const T** er[19] = {&d.ilb, &d.il0, &d.cbt, &d.inert, &d.dbx, &d.dby, &d.dbz, &d.css, &d.cvol,
-                      &d.csg, &d.cbtc, &d.qrx, &d.qry, &d.qrz, &d.qrw, &d.mrx, &d.mry, &d.mrz, &d.csr};
-  for (int i = 0; i < 19; ++i) *er[i] = P_(S->o.edge_rest[i]);
+  const T** er[22] = {&d.ilb, &d.il0, &d.cbt, &d.inert, &d.dbx, &d.dby, &d.dbz, &d.css, &d.cvol,
+                      &d.csg, &d.cbtc, &d.qrx, &d.qry, &d.qrz, &d.qrw, &d.mrx, &d.mry, &d.mrz, &d.csr,
+                      &d.csb, &d.sbg0, &d.sbg2};
+  for (int i = 0; i < 22; ++i) *er[i] = P_(S->o.edge_rest[i]);
   T** sc[9] = {&d.xpx, &d.xpy, &d.xpz, &d.spv, &d.qpx, &d.qpy, &d.qpz, &d.qpw, &d.i1};
   for (int i = 0; i < 9; ++i) *sc[i] = P_(S->o.scratch[i]);
   d.lam = P_(S->o.scratch[9]);
@@ -555,10 +577,10 @@ viper_status upload(viper_scene_s* S, const Host& H, hipStream_t st) {
   HIP_TRY(put(S->o.pill_rest[0], H.winv));
   HIP_TRY(put(S->o.pill_rest[1], H.wsinv));
   HIP_TRY(put(S->o.pill_rest[2], H.rbar));
-  const std::vector<double>* er[19] = {&H.ilb, &H.il0, &H.cbt, &H.inert, &H.db[0], &H.db[1], &H.db[2], &H.cs[0],
+  const std::vector<double>* er[22] = {&H.ilb, &H.il0, &H.cbt, &H.inert, &H.db[0], &H.db[1], &H.db[2], &H.cs[0],
                                        &H.cs[1], &H.cs[2], &H.cs[3], &H.qr[0], &H.qr[1], &H.qr[2], &H.qr[3],
-                                       &H.mr[0], &H.mr[1], &H.mr[2], &H.cs[4]};
-  for (int i = 0; i < 19; ++i) HIP_TRY(put(S->o.edge_rest[i], *er[i]));
+                                       &H.mr[0], &H.mr[1], &H.mr[2], &H.cs[4], &H.sbc, &H.sbg0, &H.sbg2};
+  for (int i = 0; i < 22; ++i) HIP_TRY(put(S->o.edge_rest[i], *er[i]));
   HIP_TRY(hipMemcpyAsync(b + S->o.flags, H.flags.data(), 4 * (size_t)P, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(b + S->o.anchor, H.anchor.data(), 8 * H.anchor.size(), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(b + S->o.rod_of, H.rod_of.data(), 4 * (size_t)P, hipMemcpyHostToDevice, st));
@@ -719,6 +741,7 @@ viper_status viper_create_scene(const viper_scene_desc* desc, void* workspace, s
   S->nsecp = S->nsec ? desc->section_offsets[S->nsec] : 0;
   S->jacobi = desc->solver == 1;
   S->cross_stretch = H.any_sr ? 1 : 0;
+  S->surface_bending = H.any_sb ? 1 : 0;
   S->nbones = desc->num_bones > 0 ? desc->num_bones : 0;
   if (desc->floor_on) {
     const double* n = desc->floor_normal;
@@ -930,6 +953,7 @@ viper_status adjoint_check(viper_scene S, int32_t frames, int32_t substeps, int3
   if (S->jacobi) return fail(VIPER_ERR_INVALID, "the adjoint covers the Gauss-Seidel solver");
   if (S->cross_stretch) return fail(VIPER_ERR_INVALID, "the adjoint does not cover the cross-section stretch");
   if (S->nbones) return fail(VIPER_ERR_INVALID, "the adjoint does not cover bones");
+  if (S->surface_bending) return fail(VIPER_ERR_INVALID, "the adjoint does not cover surface bending");
   if (frames < 1 || substeps < 1 || iterations < 0)
     return fail(VIPER_ERR_INVALID, "frames >= 1, substeps >= 1 and iterations >= 0 required");
   return VIPER_OK;
@@ -1151,6 +1175,10 @@ viper_status viper_pool_admit(viper_pool P, const viper_scene_desc* desc, void* 
       if (std::isfinite(desc->cross_compliance[k]))
         return fail(VIPER_ERR_INVALID, "scenes with the cross-section stretch are stepped with viper_step");
   if (desc->num_bones > 0) return fail(VIPER_ERR_INVALID, "scenes with bones are stepped with viper_step");
+  if (desc->bending_compliance)
+    for (int k = 0; k < desc->num_rods; ++k)
+      if (std::isfinite(desc->bending_compliance[k]))
+        return fail(VIPER_ERR_INVALID, "scenes with surface bending are stepped with viper_step");
   size_t fp = 0;
   viper_status r = viper_scene_footprint(desc, &fp);
   if (r != VIPER_OK) return r;

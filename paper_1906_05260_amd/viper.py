@@ -70,6 +70,7 @@ class SceneDescC(ctypes.Structure):
         ("bone_rest", ctypes.c_void_p),
         ("pill_bones", ctypes.c_void_p),
         ("pill_bone_weights", ctypes.c_void_p),
+        ("bending_compliance", ctypes.c_void_p),
     ]
 
 
@@ -177,6 +178,11 @@ class _DescHolder:
             c.bone_rest = a["brest"].ctypes.data
             c.pill_bones = a["pbone"].ctypes.data
             c.pill_bone_weights = a["pbw"].ctypes.data
+        if getattr(desc, "bending_compliance", None) is not None:
+            a["sb"] = np.ascontiguousarray(desc.bending_compliance, np.float64).reshape(-1)
+            if a["sb"].shape[0] != c.num_rods:
+                raise ValueError("bending_compliance needs one value per rod")
+            c.bending_compliance = a["sb"].ctypes.data
         self.c = c
 
 

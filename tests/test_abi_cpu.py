@@ -171,3 +171,20 @@ def test_bone_validation():
         with pytest.raises(viper.ViperError) as ei:
             viper.footprint(b)
         assert ei.value.status == viper.ERR_INVALID and msg in str(ei.value), str(ei.value)
+
+
+def test_surface_bending_validation():
+    """Surface bending compliances: one per rod, >= 0 or +inf, and only with the Gauss-Seidel
+    solver (the Jacobi path does not carry it)."""
+    d = scenes.helix_rods(2, 8, seed=1)
+    viper.footprint(dataclasses.replace(d, bending_compliance=np.array([1e-6, np.inf])))
+    for bad in (np.array([-1.0, 0.0]), np.array([np.nan, 0.0])):
+        with pytest.raises(viper.ViperError) as ei:
+            viper.footprint(dataclasses.replace(d, bending_compliance=bad))
+        assert ei.value.status == viper.ERR_INVALID and "bending_compliance" in str(ei.value)
+    with pytest.raises(viper.ViperError) as ei:
+        viper.footprint(dataclasses.replace(d, bending_compliance=np.array([1e-6, np.inf]), solver="jacobi"))
+    assert ei.value.status == viper.ERR_INVALID and "Gauss-Seidel" in str(ei.value)
+    viper.footprint(dataclasses.replace(d, bending_compliance=np.array([np.inf, np.inf]), solver="jacobi"))
+    with pytest.raises(ValueError):
+        viper.footprint(dataclasses.replace(d, bending_compliance=np.zeros(3)))
