@@ -73,6 +73,7 @@ def lib():
         L.orc_set_solver.argtypes = [P, I]
         L.orc_set_cross_stretch.argtypes = [P, P]
         L.orc_set_surface_bending.argtypes = [P, P]
+        L.orc_set_volume_bending.argtypes = [P, I]
         L.orc_set_bones.argtypes = [P, I, P, P, P]
         L.orc_bone_frame.argtypes = [P, P]
         L.orc_skin_weights.argtypes = [P, I, P, P, P]
@@ -143,6 +144,8 @@ class OracleScene:
         if getattr(desc, "cross_compliance", None) is not None:
             self._sr = _f64(desc.cross_compliance).reshape(-1)
             L.orc_set_cross_stretch(self.h, _p(self._sr))
+        if getattr(desc, "volume_bending", False):
+            L.orc_set_volume_bending(self.h, 1)
         if getattr(desc, "bending_compliance", None) is not None:
             self._sb = _f64(desc.bending_compliance).reshape(-1)
             L.orc_set_surface_bending(self.h, _p(self._sb))

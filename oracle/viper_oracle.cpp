@@ -156,11 +156,21 @@ template <class R> struct Block {
   R out[3];        // resulting correction W J^T dl
 };
 
-// Solve the m x m system S y = b by Cramer's rule (m = 1 or 3).  The system is
+// Solve the m x m system S y = b by Cramer's rule (m = 1, 2 or 3).  The system is
 // first divided by its largest entry (same solution) so that the cubic
 // determinants stay inside the float range when R = float.
 template <class R> void solve_small(int m, const R S0[3][3], const R b0[3], R y[3]) {
   if (m == 1) { y[0] = b0[0] / S0[0][0]; return; }
+  if (m == 2) {
+    R big(0.0);
+    for (int i = 0; i < 2; ++i) for (int j = 0; j < 2; ++j) { R a = S0[i][j] < R(0.0) ? -S0[i][j] : S0[i][j]; big = rmax(big, a); }
+    const R a = S0[0][0] / big, b = S0[0][1] / big, c = S0[1][0] / big, d = S0[1][1] / big;
+    const R e = b0[0] / big, f = b0[1] / big;
+    const R det = a * d - b * c;
+    y[0] = (e * d - b * f) / det;
+    y[1] = (a * f - e * c) / det;
+    return;
+  }
   R big(0.0);
   for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) { R a = S0[i][j] < R(0.0) ? -S0[i][j] : S0[i][j]; big = rmax(big, a); }
   R S[3][3], b[3];
@@ -218,7 +228,7 @@ struct Desc {
   double gravity[3];
 };
 
-enum { SS = 0, VOL = 1, SG = 2, BT = 3, SR = 4, SB = 5 };
+enum { SS = 0, VOL = 1, SG = 2, BT = 3, SR = 4, SB = 5, VB = 6 };
 
 template <class R> struct Scene {
   int nrods = 0, P = 0;
@@ -247,6 +257,12 @@ template <class R> struct Scene {
   // vertex between edges p and p+1)
   std::vector<uint8_t> sb_on;
   std::vector<R> comp_sb, lam_sb;
+  // volume-bending coupling (the s^3 Omega^{u,v} terms of the volume energy), optional, off by
+  // default, on rods whose volume constraint is on: compliance alpha_vol / (pi r^4 / 2 l_v)
+  // per slot (vertex after edge p) and two multipliers
+  bool vb_on = false;
+  std::vector<double> alpha_vol;   // [nrods] the volume compliance as given
+  std::vector<R> comp_vb, lam_vb;
   // state
   std::vector<V3<R>> x, v;
   std::vector<R> s, sd;
@@ -309,10 +325,12 @@ template <class R> void build(Scene<R>& S, const Desc& d, const R* rbar, const R
   S.inert_base.assign(P, R(0.0));
   for (int t = 0; t < 4; ++t) S.comp[t].assign(P, R(0.0));
   S.enabled.assign(S.nrods * 4, 1);
+  S.alpha_vol.assign(S.nrods, 0.0);
   std::vector<R> M(P, R(0.0)), Ms(P, R(0.0));
   R rho(d.density), PI(pi);
   for (int k = 0; k < S.nrods; ++k) {
     for (int t = 0; t < 4; ++t) S.enabled[4 * k + t] = std::isfinite(d.compliance[4 * k + t]) ? 1 : 0;
+    S.alpha_vol[k] = d.compliance[4 * k + VOL];
     const int a = S.off[k], b = S.off[k + 1];
     // rest frames by parallel transport (reading: zero rest twist; q0 takes e_z onto t0)
     std::vector<Q4<double>> qd(b - a);
@@ -374,6 +392,8 @@ template <class R> void build(Scene<R>& S, const Desc& d, const R* rbar, const R
   S.sb_on.assign(S.nrods, 0);
   S.comp_sb.assign(P, R(0.0));
   S.lam_sb.assign(P, R(0.0));
+  S.comp_vb.assign(P, R(0.0));
+  S.lam_vb.assign(2 * size_t(P), R(0.0));
   S.active_count.assign(P, 0);
 }
 
@@ -540,6 +560,47 @@ template <class R> int project_bt(Scene<R>& S, int p, R ih2) {
   B[2].J[0][0] = c * im.x; B[2].J[1][0] = c * im.y; B[2].J[2][0] = c * im.z;
   B[2].W[0][0] = S.wsinv[p + 1];
   xpbd_update(3, C, alpha, &S.lam[size_t(p) * 8 + 5], B, 3);
+  S.q[p] = qrotate(S.q[p], v3<R>(B[0].out[0], B[0].out[1], B[0].out[2]));
+  S.q[p + 1] = qrotate(S.q[p + 1], v3<R>(B[1].out[0], B[1].out[1], B[1].out[2]));
+  S.s[p + 1] += B[2].out[0];
+  return 1;
+}
+
+// Volume-bending coupling at vertex p+1 (the s^3 Omega^u, s^3 Omega^v terms of the volume
+// energy, Sec. 5): the bending components of the bend-twist Darboux vector with the vertex scale
+// cubed, against their rest values (rest scale one),
+//   C = s_{p+1}^3 c Im(r)_{u,v} - Omega_rest_{u,v},   r, c as in bend-twist,
+// with the volume stiffness k_v and the weight pi r^4 / 2 of the energy.
+template <class R> int project_vb(Scene<R>& S, int p, R ih2) {
+  const int k = S.rod_of[p];
+  if (!S.vb_on || !S.enabled[4 * k + VOL]) return 0;
+  Q4<R> r = qmul(qconj(S.q[p]), S.q[p + 1]);
+  if (r.w < R(0.0)) r = q4<R>(-r.x, -r.y, -r.z, -r.w);
+  const R c = R(4.0) / (S.l0[p] + S.l0[p + 1]);
+  const R sv = S.s[p + 1], s3 = sv * sv * sv;
+  const V3<R> im = qim(r);
+  R C[2] = {s3 * c * im.x - S.darb_rest[p].x, s3 * c * im.y - S.darb_rest[p].y};
+  const R a = S.comp_vb[p] * ih2;
+  R alpha[2] = {a, a};
+  // d Im(r) / d theta_{p+1} = 1/2 (r_w I - [r_v]_x) R_p^T ; d/d theta_p = minus that
+  M3<R> Bm = mzero<R>();
+  Bm.m[0][0] = Bm.m[1][1] = Bm.m[2][2] = r.w;
+  M3<R> sk = skew(im);
+  for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) Bm.m[i][j] -= sk.m[i][j];
+  const M3<R> Jp1 = mmul(Bm, mtrans(qmat(S.q[p])));
+  const R fac = R(0.5) * s3 * c;
+  Block<R> B[3];
+  const M3<R> W0 = inv_inertia_world(S, p), W1 = inv_inertia_world(S, p + 1);
+  B[0].ndof = 3; B[1].ndof = 3;
+  for (int i = 0; i < 2; ++i) for (int j = 0; j < 3; ++j) {
+    B[0].J[i][j] = -fac * Jp1.m[i][j];
+    B[1].J[i][j] = fac * Jp1.m[i][j];
+  }
+  for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) { B[0].W[i][j] = W0.m[i][j]; B[1].W[i][j] = W1.m[i][j]; }
+  B[2].ndof = 1;
+  B[2].J[0][0] = R(3.0) * sv * sv * c * im.x; B[2].J[1][0] = R(3.0) * sv * sv * c * im.y;
+  B[2].W[0][0] = S.wsinv[p + 1];
+  xpbd_update(2, C, alpha, &S.lam_vb[2 * size_t(p)], B, 3);
   S.q[p] = qrotate(S.q[p], v3<R>(B[0].out[0], B[0].out[1], B[0].out[2]));
   S.q[p + 1] = qrotate(S.q[p + 1], v3<R>(B[1].out[0], B[1].out[1], B[1].out[2]));
   S.s[p + 1] += B[2].out[0];
@@ -716,6 +777,7 @@ template <class R> void predict_rods(Scene<R>& S, R h, int r0, int r1) {
       for (int t = 0; t < 8; ++t) S.lam[size_t(p) * 8 + t] = R(0.0);
       S.lam_sr[p] = R(0.0);
       S.lam_sb[p] = R(0.0);
+      S.lam_vb[2 * size_t(p)] = S.lam_vb[2 * size_t(p) + 1] = R(0.0);
     }
   for (int k = r0; k < r1; ++k)
     for (int p = S.off[k]; p + 1 < S.off[k + 1]; ++p) {
@@ -741,7 +803,10 @@ template <class R> int64_t solve_colours(Scene<R>& S, R ih2, int r0, int r1) {
       }
   for (int colour = 0; colour < 2; ++colour)
     for (int k = r0; k < r1; ++k)
-      for (int p = S.off[k] + colour; p + 2 < S.off[k + 1]; p += 2) n += project_bt(S, p, ih2);
+      for (int p = S.off[k] + colour; p + 2 < S.off[k + 1]; p += 2) {
+        n += project_bt(S, p, ih2);
+        n += project_vb(S, p, ih2);
+      }
   // surface bending touches three consecutive scales: three colours
   for (int colour = 0; colour < 3; ++colour)
     for (int k = r0; k < r1; ++k)
@@ -775,6 +840,7 @@ template <class R> int64_t solve_jacobi(Scene<R>& S, R ih2) {
     else if (kind == SG) a = project_sg(S, p, ih2);
     else if (kind == SR) a = project_sr(S, p, ih2);
     else if (kind == SB) a = project_sb(S, p, ih2);
+    else if (kind == VB) a = project_vb(S, p, ih2);
     else a = project_bt(S, p, ih2);
     if (!a) return;
     n += a;
@@ -784,7 +850,7 @@ template <class R> int64_t solve_jacobi(Scene<R>& S, R ih2) {
     if (kind == VOL || kind == SG || kind == SR) {
       ds[p] = ds[p] + (S.s[p] - s0); ds[q1] = ds[q1] + (S.s[q1] - s1); ++ns[p]; ++ns[q1];
     }
-    if (kind == BT) { ds[q1] = ds[q1] + (S.s[q1] - s1); ++ns[q1]; }
+    if (kind == BT || kind == VB) { ds[q1] = ds[q1] + (S.s[q1] - s1); ++ns[q1]; }
     if (kind == SB) {
       ds[p] = ds[p] + (S.s[p] - s0); ds[q1] = ds[q1] + (S.s[q1] - s1); ds[p + 2] = ds[p + 2] + (S.s[p + 2] - s2);
       ++ns[p]; ++ns[q1]; ++ns[p + 2];
@@ -796,7 +862,7 @@ template <class R> int64_t solve_jacobi(Scene<R>& S, R ih2) {
       ++nq[i];
     };
     if (kind == SS) addq(p, r0);
-    if (kind == BT) { addq(p, r0); addq(q1, r1); }
+    if (kind == BT || kind == VB) { addq(p, r0); addq(q1, r1); }
     S.x[p] = x0; S.x[q1] = x1; S.s[p] = s0; S.s[q1] = s1; S.q[p] = r0; S.q[q1] = r1;
   };
   for (int k = 0; k < S.nrods; ++k)
@@ -807,6 +873,7 @@ template <class R> int64_t solve_jacobi(Scene<R>& S, R ih2) {
       eval(SR, p);
       if (p + 2 < S.off[k + 1]) eval(BT, p);
       if (p + 2 < S.off[k + 1]) eval(SB, p);
+      if (p + 2 < S.off[k + 1]) eval(VB, p);
     }
   for (int p = 0; p < P; ++p) {
     if (nx[p]) S.x[p] = S.x[p] + (R(1.0) / R(double(nx[p]))) * dx[p];
@@ -1030,6 +1097,15 @@ template <class R> double rod_residual(const Scene<R>& S0, R ih2) {
         R C = R(0.5) * (S.s[p] + S.s[p + 1]) - R(1.0) + S.comp_sr[p] * ih2 * S.lam_sr[p];
         acc += val(C * C);
       }
+      if (p + 2 < S.off[k + 1] && S.vb_on && S.enabled[4 * k + VOL]) {
+        Q4<R> r = qmul(qconj(S.q[p]), S.q[p + 1]);
+        if (r.w < R(0.0)) r = q4<R>(-r.x, -r.y, -r.z, -r.w);
+        const R c = R(4.0) / (S.l0[p] + S.l0[p + 1]), s3 = S.s[p + 1] * S.s[p + 1] * S.s[p + 1];
+        const R a = S.comp_vb[p] * ih2;
+        R c0 = s3 * c * r.x - S.darb_rest[p].x + a * S.lam_vb[2 * size_t(p)];
+        R c1 = s3 * c * r.y - S.darb_rest[p].y + a * S.lam_vb[2 * size_t(p) + 1];
+        acc += val(c0 * c0 + c1 * c1);
+      }
       if (p + 2 < S.off[k + 1] && S.sb_on[k]) {
         const R la = S.l0[p], lb = S.l0[p + 1], lv = R(0.5) * (la + lb);
         R C = ((S.s[p + 2] - S.s[p + 1]) / lb - (S.s[p + 1] - S.s[p]) / la) / lv + S.comp_sb[p] * ih2 * S.lam_sb[p];
@@ -1180,6 +1256,18 @@ template <class R> static void set_surface_bending_t(Scene<R>& S, const double* 
   }
 }
 
+// Volume-bending coupling on (on rods with the volume constraint): compliance = the rod's volume
+// compliance over G l_v with G = pi r^4 / 2 and r the vertex's rest radius.
+template <class R> static void set_volume_bending_t(Scene<R>& S, int on) {
+  const double pi = 3.14159265358979323846;
+  S.vb_on = on != 0;
+  for (int k = 0; k < S.nrods; ++k)
+    for (int p = S.off[k]; p + 2 < S.off[k + 1]; ++p) {
+      const R rv = S.rbar[p + 1], lv = R(0.5) * (S.l0[p] + S.l0[p + 1]);
+      S.comp_vb[p] = S.enabled[4 * k + VOL] ? R(S.alpha_vol[k]) / (R(pi) * rv * rv * rv * rv / R(2.0) * lv) : R(0.0);
+    }
+}
+
 template <class R> static void set_floor_t(Scene<R>& S, const double* n, double d) {
   const double l = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
   S.floor_on = true;
@@ -1199,6 +1287,7 @@ template <class R> static int64_t rod_iterations_t(Scene<R>& S, double h_sub, in
     for (int t = 0; t < 8; ++t) S.lam[size_t(i) * 8 + t] = R(0.0);
     S.lam_sr[i] = R(0.0);
     S.lam_sb[i] = R(0.0);
+    S.lam_vb[2 * size_t(i)] = S.lam_vb[2 * size_t(i) + 1] = R(0.0);
   }
   const R ih2 = R(1.0 / (h_sub * h_sub));
   int64_t n = 0;
@@ -1295,6 +1384,11 @@ void orc_set_surface_bending(void* hp, const double* comp) {
   Handle* h = (Handle*)hp;
   if (h->d) set_surface_bending_t(*h->d, comp); else set_surface_bending_t(*h->f, comp);
 }
+// Volume-bending coupling: nonzero turns it on for every rod with the volume constraint.
+void orc_set_volume_bending(void* hp, int on) {
+  Handle* h = (Handle*)hp;
+  if (h->d) set_volume_bending_t(*h->d, on); else set_volume_bending_t(*h->f, on);
+}
 // Solver of the rod constraints: 0 = coloured Gauss-Seidel, 1 = Jacobi with averaging.
 void orc_set_solver(void* hp, int jacobi) {
   Handle* h = (Handle*)hp;
@@ -1353,7 +1447,7 @@ void orc_get_rest(void* hp, double* l0, double* lbar, double* qrest, double* dar
 }
 
 // Single-constraint primitives for closed-form pins (double scene only).
-// kind: 0 SS, 1 VOL, 2 SG, 3 BT, 4 SR, 5 SB at slot p, with the substep inertia computed from
+// kind: 0 SS, 1 VOL, 2 SG, 3 BT, 4 SR, 5 SB, 6 VB at slot p, with the substep inertia computed from
 // the current scale.  lambda is zeroed first.
 void orc_project_one(void* hp, int kind, int p, double h) {
   Handle* hd = (Handle*)hp;
@@ -1367,12 +1461,14 @@ void orc_project_one(void* hp, int kind, int p, double h) {
     for (int t = 0; t < 8; ++t) S.lam[size_t(i) * 8 + t] = 0.0;
     S.lam_sr[i] = 0.0;
     S.lam_sb[i] = 0.0;
+    S.lam_vb[2 * size_t(i)] = S.lam_vb[2 * size_t(i) + 1] = 0.0;
   }
   double ih2 = 1.0 / (h * h);
   if (kind == 0) project_ss(S, p, ih2);
   if (kind == 1) project_vol(S, p, ih2);
   if (kind == 4) project_sr(S, p, ih2);
   if (kind == 5) project_sb(S, p, ih2);
+  if (kind == 6) project_vb(S, p, ih2);
   if (kind == 2) project_sg(S, p, ih2);
   if (kind == 3) project_bt(S, p, ih2);
 }

@@ -47,6 +47,9 @@ class SceneDesc:
     # surface bending (Laplacian of the scale along the rod, Sec. 5) compliance per rod
     # [num_rods]; None or +inf = off
     bending_compliance: np.ndarray = None
+    # volume-bending coupling (the s^3 Omega^{u,v} terms of the volume energy, Sec. 5) on rods
+    # with the volume constraint, at the volume compliance
+    volume_bending: bool = False
     # kinematic bones (Sec. 8.2): rest transforms [nb, 3, 4] (the bones' pose at rest_pos) and
     # two (bone, weight) influences per pill, [P, 2] int32 and [P, 2] float64; None = no bones
     bone_rest: np.ndarray = None

@@ -1163,3 +1163,82 @@ def test_surface_bending_with_cross_stretch_drives_every_scale_to_rest():
     a.set_state(s=alt)
     a.rod_iterations(1 / 600, 5)
     assert np.abs(a.get_state()["s"] - alt).max() < 1e-14
+
+
+# ---------------------------------------------------------------- volume-bending coupling
+
+def _vb_scene():
+    d = small_scene([line(3)], comp=(INF, 0.0, INF, INF))
+    d.volume_bending = True
+    return d
+
+
+def test_volume_bending_is_a_newton_step():
+    """Zero compliance: one projection of the coupling s^3 c Im(r)_{u,v} (rest Darboux zero on
+    a straight rod) leaves a violation quadratic in the one before (a wrong Jacobian sign,
+    power of s or frame would leave a linear residual)."""
+    ratios = []
+    for eps in (1e-3, 1e-4):
+        o = OracleScene(_vb_scene())
+        st0 = o.get_state()
+        rng = np.random.default_rng(6)
+        q = st0["q"].copy()
+        q[0] = qmul(qaxis(rng.normal(size=3), eps), q[0])
+        q[1] = qmul(qaxis(rng.normal(size=3), eps), q[1])
+        s = 1 + eps * rng.normal(size=3)
+        o.set_state(q=q, s=s)
+
+        def viol():
+            st = o.get_state()
+            r = qmul(st["q"][0] * np.array([-1, -1, -1, 1]), st["q"][1])
+            r = r if r[3] >= 0 else -r
+            return np.linalg.norm(st["s"][1] ** 3 * 4 / 0.02 * r[:2])
+        c0 = viol()
+        o.project_one(6, 0, 1e-3)
+        c1 = viol()
+        ratios.append(c1 / c0 ** 2)
+        assert c1 < 1e-2 * c0
+    assert ratios[1] < 10 * ratios[0] + 1.0
+
+
+@pytest.mark.parametrize("axis", [[1, 0, 0], [0.6, -0.8, 0]])
+def test_volume_bending_removes_a_pure_bend_and_ignores_twist(axis):
+    """Edge 0 and the scale frozen, zero compliance: a bend by psi about an axis normal to the
+    tangent is removed in one projection exactly (the two rows are the bend-twist bending rows
+    times s^3 = 1); a pure twist about the tangent has no bending component and is kept."""
+    d = _vb_scene()
+    o = OracleScene(d)
+    o.set_masses(wsinv=np.zeros(3), inert=np.array([1e300, 1.0, 1.0]))
+    q = o.get_state()["q"].copy()
+    q[1] = qmul(q[0], qaxis(axis, 0.5))
+    o.set_state(q=q)
+    o.project_one(6, 0, 1e-3)
+    st = o.get_state()
+    r = qmul(st["q"][0] * np.array([-1, -1, -1, 1]), st["q"][1])
+    assert np.abs(r[:3]).max() < 1e-14
+    t = OracleScene(d)
+    t.set_masses(wsinv=np.zeros(3), inert=np.array([1e300, 1.0, 1.0]))
+    qt = t.get_state()["q"].copy()
+    qt[1] = qmul(qt[0], qaxis([0, 0, 1], 0.5))
+    t.set_state(q=qt)
+    t.project_one(6, 0, 1e-3)
+    assert np.abs(t.get_state()["q"] - qt).max() < 1e-15
+
+
+def test_volume_bending_scale_step_is_newton_on_the_cube():
+    """Rotations all but frozen (inertia 1e200), a fixed bend about the material x axis, rest
+    Darboux zero: the coupling's one active row is C = k s^3 in the vertex scale alone (the
+    y row is zero), and one rigid projection is Newton's step on it,
+    s -> s - k s^3 / (3 k s^2) = 2 s / 3 (a wrong power or factor of the scale gradient lands
+    elsewhere)."""
+    d = _vb_scene()
+    o = OracleScene(d)
+    o.set_masses(inert=np.array([1e200, 1e200, 1e200]))
+    q = o.get_state()["q"].copy()
+    q[1] = qmul(q[0], qaxis([1, 0, 0], 0.3))
+    s0 = np.array([1.0, 1.2, 1.0])
+    o.set_state(q=q, s=s0)
+    o.project_one(6, 0, 1e-3)
+    st = o.get_state()
+    assert abs(st["s"][1] - 2.0 / 3.0 * 1.2) < 1e-12
+    assert st["s"][0] == 1.0 and st["s"][2] == 1.0
