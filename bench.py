@@ -46,7 +46,7 @@ def kernel_source_hash():
     with open(os.path.join(csrc, "rod_kernels.hip")) as fh:
         src = fh.read()
     i = src.index(" rod_frame_kernel(")
-    h.update(src[src.rfind("template <class T>", 0, i):src.index("\n}\n", i) + 3].encode())
+    h.update(src[src.rfind("template <", 0, i):src.index("\n}\n", i) + 3].encode())
     for f in (os.path.join(csrc, "rod_device.h"), os.path.join(csrc, "viper_dev.h"),
               os.path.join(ROOT, "paper_1906_05260_amd", "build.py")):
         with open(f, "rb") as fh:

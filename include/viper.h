@@ -119,6 +119,14 @@ typedef struct {
    * bend-twist (Gauss-Seidel only: a Jacobi scene that turns it on is VIPER_ERR_INVALID); the
    * pool and the adjoint reject a scene that turns it on. */
   const double* bending_compliance;
+  /* Volume-bending coupling (Sec. 5: the s^3 Omega^u, s^3 Omega^v terms of the volume
+   * energy), optional: nonzero turns it on for every rod whose volume constraint is on, at
+   * every interior vertex, C = s^3 c Im(r)_{u,v} - Omega_rest_{u,v} (r, c as bend-twist, s the
+   * vertex scale; rest scale one), with the rod's volume compliance scaled by
+   * 1 / (pi r^4 / 2 l_v).  Solved right after bend-twist at the same vertex (Gauss-Seidel only:
+   * a Jacobi scene that turns it on is VIPER_ERR_INVALID); the pool and the adjoint reject a
+   * scene that turns it on. */
+  int32_t volume_bending;
 } viper_scene_desc;
 
 /* Bytes of device workspace the scene needs (host-only computation; validates the

@@ -803,10 +803,11 @@ template <class R> int64_t solve_colours(Scene<R>& S, R ih2, int r0, int r1) {
       }
   for (int colour = 0; colour < 2; ++colour)
     for (int k = r0; k < r1; ++k)
-      for (int p = S.off[k] + colour; p + 2 < S.off[k + 1]; p += 2) {
-        n += project_bt(S, p, ih2);
-        n += project_vb(S, p, ih2);
-      }
+      for (int p = S.off[k] + colour; p + 2 < S.off[k + 1]; p += 2) n += project_bt(S, p, ih2);
+  // the volume-bending coupling at the same vertices, after every bend-twist projection
+  for (int colour = 0; colour < 2; ++colour)
+    for (int k = r0; k < r1; ++k)
+      for (int p = S.off[k] + colour; p + 2 < S.off[k + 1]; p += 2) n += project_vb(S, p, ih2);
   // surface bending touches three consecutive scales: three colours
   for (int colour = 0; colour < 3; ++colour)
     for (int k = r0; k < r1; ++k)

@@ -51,12 +51,13 @@ struct Slot {
   T x0, x1, x2, v0, v1, v2, s, sd;
   T q0, q1, q2, q3, o0, o1, o2;
   T xp0, xp1, xp2, sp, qp0, qp1, qp2, qp3;
-  T l[10];                     // multipliers of the slot's constraints: ss(3) vol sg bt(3) sr sb
+  T l[12];                     // multipliers of the slot's constraints: ss(3) vol sg bt(3) sr sb vb(2)
   T w, ws;                     // inverse position / scale mass
   T ilb, il0, cbt, inert;      // edge constants
   T db0, db1, db2;             // rest Darboux vector
   T ass, avol, asg, abt, asr;  // compliance / (G l h^2)
   T asb, sg0, sg2;             // surface bending: compliance / (G l_v h^2), dC/ds of the first and third pill
+  T avb;                       // volume-bending coupling: compliance / (G l_v h^2)
   T I1;                        // inverse bending inertia of the slot's edge (this substep)
   uint32_t f;
 };
@@ -66,6 +67,7 @@ struct Lane2 {
   Slot<T> A, B;
   T wN, wsN, I1N;              // next lane's slot A: inverse masses, inverse bending inertia
   bool sb;                     // some rod of the wavefront has surface bending
+  bool vb;                     // some rod of the wavefront has the volume-bending coupling
 };
 
 // ---------------------------------------------------------------- per-slot stages
@@ -83,7 +85,7 @@ __device__ __forceinline__ void predict_slot(Slot<T>& L, T h, T gx, T gy, T gz) 
   L.qp0 = L.q0; L.qp1 = L.q1; L.qp2 = L.q2; L.qp3 = L.q3;
   if (L.f & F_EDGE) qrot_world(L.q0, L.q1, L.q2, L.q3, h * L.o0, h * L.o1, h * L.o2);
 #pragma unroll
-  for (int i = 0; i < 10; ++i) L.l[i] = T(0);
+  for (int i = 0; i < 12; ++i) L.l[i] = T(0);
 }
 
 // Inverse bending inertia 4 / (rho pi r^4 l s_m^2) of an edge from the substep-start
@@ -129,8 +131,10 @@ __device__ __forceinline__ void velocity_slot(Slot<T>& L, T ih) {
 // ---------------------------------------------------------------- constraints
 
 // Stretch-shear, volume and scale gradient of the edge from slot L to the right pill
-// (b, sb) with inverse masses (wb, wsb).  Updates L and (b, sb) in place.
-template <class T>
+// (b, sb) with inverse masses (wb, wsb).  Updates L and (b, sb) in place.  X: the optional
+// terms (cross-section stretch here) are compiled in; without them the code is the plain
+// constraint set.
+template <class T, bool X = false>
 __device__ __forceinline__ void edge_update(Slot<T>& L, T& b0, T& b1, T& b2, T& sb, T wb, T wsb) {
   T a0 = L.x0, a1 = L.x1, a2 = L.x2, sa = L.s;
   const T wa = L.w;
@@ -188,7 +192,7 @@ __device__ __forceinline__ void edge_update(Slot<T>& L, T& b0, T& b1, T& b2, T& 
     sa -= L.ws * il0 * dl;
     sb += wsb * il0 * dl;
   }
-  if (L.f & F_SR) {   // cross-section stretch: midpoint scale back to one, dC/ds = 1/2 each
+  if (X && (L.f & F_SR)) {   // cross-section stretch: midpoint scale back to one, dC/ds = 1/2 each
     const T at = L.asr;
     const T C = T(0.5) * (sa + sb) - T(1);
     const T S = T(0.25) * (L.ws + wsb) + at;
@@ -287,16 +291,91 @@ __device__ __forceinline__ void bt_update(Slot<T>& L, T& b0, T& b1, T& b2, T& b3
   sb += wsb * c * (v0 * g0 + v1 * g1 + v2 * g2);
 }
 
+// Volume-bending coupling at the same vertex: the two bending rows of the bend-twist Darboux
+// vector with the vertex scale cubed, C = s^3 c v_{u,v} - Omega_rest_{u,v}.  The bend-twist
+// system restricted to those rows, with K = (s^3 c)^2 / 4 and the scale column 3 s^2 c v:
+//   S = K[(Ia+Ib)(I - v v^T) - Ia/2 u u^T - Ib/2 y y^T] + wsb (3 s^2 c)^2 v v^T + a I   (2 x 2)
+// and the rotations of bend-twist driven by B^T (g0, g1, 0).
+template <class T>
+__device__ __forceinline__ void vb_update(Slot<T>& L, T& b0, T& b1, T& b2, T& b3, T& sb, T Ib, T wsb) {
+  const T a0 = L.q0, a1 = L.q1, a2 = L.q2, a3 = L.q3;
+  const T rx = a3 * b0 - a0 * b3 - a1 * b2 + a2 * b1;
+  const T ry = a3 * b1 + a0 * b2 - a1 * b3 - a2 * b0;
+  const T rz = a3 * b2 - a0 * b1 + a1 * b0 - a2 * b3;
+  const T rw = a3 * b3 + a0 * b0 + a1 * b1 + a2 * b2;
+  const T sg = (rw < T(0)) ? T(-1) : T(1);
+  const T v0 = sg * rx, v1 = sg * ry, v2 = sg * rz, w = sg * rw;
+  const T c = L.cbt;
+  const T s2 = sb * sb;
+  const T sc = s2 * sb * c, gs = T(3) * s2 * c;
+  const T C0 = sc * v0 - L.db0, C1 = sc * v1 - L.db1;
+  const T t0 = T(2) * (v0 * v2 + w * v1);
+  const T t1 = T(2) * (v1 * v2 - w * v0);
+  const T t2 = T(1) - T(2) * (v0 * v0 + v1 * v1);
+  const T u0 = -v1, u1 = v0;
+  const T y0 = w * t0 - (v1 * t2 - v2 * t1);
+  const T y1 = w * t1 - (v2 * t0 - v0 * t2);
+  const T Ia = L.I1;
+  const T K = T(0.25) * sc * sc;
+  const T m = K * (Ia + Ib);
+  const T ha = T(0.5) * K * Ia, hb = T(0.5) * K * Ib;
+  const T qv = wsb * gs * gs - m;
+  const T at = L.avb;
+  const T S00 = m + qv * v0 * v0 - ha * u0 * u0 - hb * y0 * y0 + at;
+  const T S11 = m + qv * v1 * v1 - ha * u1 * u1 - hb * y1 * y1 + at;
+  const T S01 = qv * v0 * v1 - ha * u0 * u1 - hb * y0 * y1;
+  const T r0 = -C0 - at * L.l[10], r1 = -C1 - at * L.l[11];
+  // equilibrate by the trace (FP32 range), then 2 x 2 inverse
+  const T sgm = rcp(S00 + S11);
+  const T s00 = S00 * sgm, s11 = S11 * sgm, s01 = S01 * sgm;
+  const T idet = sgm * rcp(s00 * s11 - s01 * s01);
+  const T g0 = (s11 * r0 - s01 * r1) * idet;
+  const T g1 = (s00 * r1 - s01 * r0) * idet;
+  L.l[10] += g0; L.l[11] += g1;
+  const T e0 = w * g0 - v2 * g1;
+  const T e1 = w * g1 + v2 * g0;
+  const T e2 = v0 * g1 - v1 * g0;
+  const T hs = T(0.5) * sc;
+  const T ka = -hs * Ia;
+  const T da0 = ka * e0, da1 = ka * e1, da2 = T(0.5) * ka * e2;
+  const T te = T(0.5) * (t0 * e0 + t1 * e1 + t2 * e2);
+  const T kb = hs * Ib;
+  const T dB0 = kb * (e0 - te * t0), dB1 = kb * (e1 - te * t1), dB2 = kb * (e2 - te * t2);
+  {
+    const T h0 = T(0.5) * da0, h1 = T(0.5) * da1, h2 = T(0.5) * da2;
+    const T nx = a0 + (a3 * h0 + (a1 * h2 - a2 * h1));
+    const T ny = a1 + (a3 * h1 + (a2 * h0 - a0 * h2));
+    const T nz = a2 + (a3 * h2 + (a0 * h1 - a1 * h0));
+    const T nw = a3 - (a0 * h0 + a1 * h1 + a2 * h2);
+    const T in = rsq(nx * nx + ny * ny + nz * nz + nw * nw);
+    L.q0 = nx * in; L.q1 = ny * in; L.q2 = nz * in; L.q3 = nw * in;
+  }
+  {
+    const T h0 = T(0.5) * sg * dB0, h1 = T(0.5) * sg * dB1, h2 = T(0.5) * sg * dB2;
+    const T p0 = w * h0 + (h1 * v2 - h2 * v1);
+    const T p1 = w * h1 + (h2 * v0 - h0 * v2);
+    const T p2 = w * h2 + (h0 * v1 - h1 * v0);
+    const T p3 = -(h0 * v0 + h1 * v1 + h2 * v2);
+    const T nx = b0 + (a3 * p0 + a0 * p3 + a1 * p2 - a2 * p1);
+    const T ny = b1 + (a3 * p1 - a0 * p2 + a1 * p3 + a2 * p0);
+    const T nz = b2 + (a3 * p2 + a0 * p1 - a1 * p0 + a2 * p3);
+    const T nw = b3 + (a3 * p3 - a0 * p0 - a1 * p1 - a2 * p2);
+    const T in = rsq(nx * nx + ny * ny + nz * nz + nw * nw);
+    b0 = nx * in; b1 = ny * in; b2 = nz * in; b3 = nw * in;
+  }
+  sb += wsb * gs * (v0 * g0 + v1 * g1);
+}
+
 __device__ __forceinline__ bool colour_is(uint32_t f, int colour) { return ((f & F_ODD) != 0) == (colour != 0); }
 
 // Stretch-shear, volume and scale gradient of every edge of parity `colour`.
-template <class T>
+template <class T, bool X = false>
 __device__ __forceinline__ void pass_edges(Lane2<T>& P, int colour) {
   T n0 = dn(P.A.x0), n1 = dn(P.A.x1), n2 = dn(P.A.x2), ns = dn(P.A.s);
   if ((P.A.f & F_EDGE) && colour_is(P.A.f, colour)) {
-    edge_update(P.A, P.B.x0, P.B.x1, P.B.x2, P.B.s, P.B.w, P.B.ws);
+    edge_update<T, X>(P.A, P.B.x0, P.B.x1, P.B.x2, P.B.s, P.B.w, P.B.ws);
   } else if ((P.B.f & F_EDGE) && colour_is(P.B.f, colour)) {
-    edge_update(P.B, n0, n1, n2, ns, P.wN, P.wsN);
+    edge_update<T, X>(P.B, n0, n1, n2, ns, P.wN, P.wsN);
   }
   // the right end of a B-edge belongs to the next lane's slot A
   n0 = up(n0); n1 = up(n1); n2 = up(n2); ns = up(ns);
@@ -316,6 +395,22 @@ __device__ __forceinline__ void pass_bt(Lane2<T>& P, int colour) {
   }
   n0 = up(n0); n1 = up(n1); n2 = up(n2); n3 = up(n3); ns = up(ns);
   if ((P.A.f & F_EDGE) && !(P.A.f & F_FIRST) && (P.A.f & F_BTEN) && !colour_is(P.A.f, colour)) {
+    P.A.q0 = n0; P.A.q1 = n1; P.A.q2 = n2; P.A.q3 = n3; P.A.s = ns;
+  }
+}
+
+// Volume-bending coupling at every vertex of parity `colour` (after all bend-twist passes;
+// the same lane exchange as bend-twist).
+template <class T>
+__device__ __forceinline__ void pass_vb(Lane2<T>& P, int colour) {
+  T n0 = dn(P.A.q0), n1 = dn(P.A.q1), n2 = dn(P.A.q2), n3 = dn(P.A.q3), ns = dn(P.A.s);
+  if ((P.A.f & F_BT) && (P.A.f & F_VB) && colour_is(P.A.f, colour)) {
+    vb_update(P.A, P.B.q0, P.B.q1, P.B.q2, P.B.q3, P.B.s, P.B.I1, P.B.ws);
+  } else if ((P.B.f & F_BT) && (P.B.f & F_VB) && colour_is(P.B.f, colour)) {
+    vb_update(P.B, n0, n1, n2, n3, ns, P.I1N, P.wsN);
+  }
+  n0 = up(n0); n1 = up(n1); n2 = up(n2); n3 = up(n3); ns = up(ns);
+  if ((P.A.f & F_EDGE) && !(P.A.f & F_FIRST) && (P.A.f & F_VB) && !colour_is(P.A.f, colour)) {
     P.A.q0 = n0; P.A.q1 = n1; P.A.q2 = n2; P.A.q3 = n3; P.A.s = ns;
   }
 }
@@ -363,16 +458,24 @@ __device__ __forceinline__ void pass_sb(Lane2<T>& P, int colour) {
   }
 }
 
-template <class T>
+// One Gauss-Seidel iteration.  X: the optional terms (cross-section stretch, volume-bending
+// coupling, surface bending) are compiled in; the plain instantiation runs scenes without them.
+template <class T, bool X = false>
 __device__ __forceinline__ void iteration_lane(Lane2<T>& P) {
-  pass_edges(P, 0);
-  pass_edges(P, 1);
+  pass_edges<T, X>(P, 0);
+  pass_edges<T, X>(P, 1);
   pass_bt(P, 0);
   pass_bt(P, 1);
-  if (P.sb) {   // the same on every lane of the wavefront
-    pass_sb(P, 0);
-    pass_sb(P, 1);
-    pass_sb(P, 2);
+  if constexpr (X) {
+    if (P.vb) {   // the same on every lane of the wavefront
+      pass_vb(P, 0);
+      pass_vb(P, 1);
+    }
+    if (P.sb) {   // the same on every lane of the wavefront
+      pass_sb(P, 0);
+      pass_sb(P, 1);
+      pass_sb(P, 2);
+    }
   }
 }
 
@@ -396,6 +499,7 @@ __device__ __forceinline__ const Dev<T>* lane_setup(const Dev<T>* D, const Blk* 
   P.A.f = vA ? d->flags[pA] : 0u;
   P.B.f = vB ? d->flags[pB] : 0u;
   P.sb = __any(((P.A.f | P.B.f) & F_SB) != 0u) != 0;
+  P.vb = __any(((P.A.f | P.B.f) & F_VB) != 0u) != 0;
   return d;
 }
 
@@ -408,23 +512,26 @@ __device__ __forceinline__ void load_state(const Dev<T>& d, Slot<T>& L, int p) {
   L.o0 = d.ox[p]; L.o1 = d.oy[p]; L.o2 = d.oz[p];
 }
 
-template <class T>
+template <class T, bool X = false>
 __device__ __forceinline__ void load_consts(const Dev<T>& d, Slot<T>& L, int p, T ih2) {
   L.w = d.winv[p]; L.ws = d.wsinv[p];
   L.ilb = d.ilb[p]; L.il0 = d.il0[p]; L.cbt = d.cbt[p]; L.inert = d.inert[p];
   L.db0 = d.dbx[p]; L.db1 = d.dby[p]; L.db2 = d.dbz[p];
   L.ass = d.css[p] * ih2; L.avol = d.cvol[p] * ih2; L.asg = d.csg[p] * ih2; L.abt = d.cbtc[p] * ih2;
-  L.asr = (L.f & F_SR) ? d.csr[p] * ih2 : T(0);
-  const bool sb = (L.f & F_SB) && (L.f & F_BT);
-  L.asb = sb ? d.csb[p] * ih2 : T(0);
-  L.sg0 = sb ? d.sbg0[p] : T(0);
-  L.sg2 = sb ? d.sbg2[p] : T(0);
+  if constexpr (X) {
+    L.asr = (L.f & F_SR) ? d.csr[p] * ih2 : T(0);
+    const bool sb = (L.f & F_SB) && (L.f & F_BT);
+    L.asb = sb ? d.csb[p] * ih2 : T(0);
+    L.sg0 = sb ? d.sbg0[p] : T(0);
+    L.sg2 = sb ? d.sbg2[p] : T(0);
+    L.avb = (L.f & F_VB) ? d.cvb[p] * ih2 : T(0);
+  }
 }
 
-template <class T>
+template <class T, bool X = false>
 __device__ __forceinline__ void load_lane_consts(const Dev<T>& d, Lane2<T>& P, int pA, int pB, T ih2) {
-  load_consts(d, P.A, pA, ih2);
-  load_consts(d, P.B, pB, ih2);
+  load_consts<T, X>(d, P.A, pA, ih2);
+  load_consts<T, X>(d, P.B, pB, ih2);
   P.wN = dn(P.A.w);
   P.wsN = dn(P.A.ws);
 }

@@ -28,8 +28,9 @@ namespace viper {
 
 // ---------------------------------------------------------------- kernels
 
-// FRAME / SUBSTEP mode: nsub substeps with the rod state in registers.
-template <class T>
+// FRAME / SUBSTEP mode: nsub substeps with the rod state in registers.  X: the optional
+// constraint terms are compiled in (chosen per batch on the host).
+template <class T, bool X>
 __global__ void __launch_bounds__(256) rod_frame_kernel(const Dev<T>* __restrict__ D, const Blk* __restrict__ tab,
                                                         int nsub, T h, int iters) {
   Lane2<T> P;
@@ -39,13 +40,13 @@ __global__ void __launch_bounds__(256) rod_frame_kernel(const Dev<T>* __restrict
   const Dev<T>& d = *dp;
   load_state(d, P.A, pA);
   load_state(d, P.B, pB);
-  load_lane_consts(d, P, pA, pB, rcp(h * h));
+  load_lane_consts<T, X>(d, P, pA, pB, rcp(h * h));
   const T ih = T(1) / h;
   for (int sub = 0; sub < nsub; ++sub) {
     predict_slot(P.A, h, d.gx, d.gy, d.gz);
     predict_slot(P.B, h, d.gx, d.gy, d.gz);
     inertia_lane(P);
-    for (int it = 0; it < iters; ++it) iteration_lane(P);
+    for (int it = 0; it < iters; ++it) iteration_lane<T, X>(P);
     velocity_slot(P.A, ih);
     velocity_slot(P.B, ih);
   }
@@ -66,7 +67,7 @@ __device__ __forceinline__ void store_predicted(const Dev<T>& d, const Slot<T>& 
   d.qpx[p] = L.qp0; d.qpy[p] = L.qp1; d.qpz[p] = L.qp2; d.qpw[p] = L.qp3;
   d.i1[p] = L.I1;
 #pragma unroll
-  for (int i = 0; i < 10; ++i) d.lam[(size_t)i * d.P + p] = T(0);
+  for (int i = 0; i < 12; ++i) d.lam[(size_t)i * d.P + p] = T(0);
 }
 
 template <class T>
@@ -89,22 +90,26 @@ __global__ void __launch_bounds__(256) predict_kernel(const Dev<T>* __restrict__
 
 // ITERATION mode, stage 2: one constraint iteration (four colour passes) with the
 // state and multipliers streamed from and back to memory.
-template <class T>
+// Multipliers streamed per iteration: the plain constraint set's 8, or all 12 with the
+// optional terms (cross-section stretch, surface bending, volume-bending coupling).
+template <bool X> constexpr int kLam = X ? 12 : 8;
+
+template <class T, bool X>
 __device__ __forceinline__ void load_iter(const Dev<T>& d, Slot<T>& L, int p) {
   L.x0 = d.px[p]; L.x1 = d.py[p]; L.x2 = d.pz[p]; L.s = d.s[p];
   L.q0 = d.qx[p]; L.q1 = d.qy[p]; L.q2 = d.qz[p]; L.q3 = d.qw[p];
 #pragma unroll
-  for (int i = 0; i < 10; ++i) L.l[i] = d.lam[(size_t)i * d.P + p];
+  for (int i = 0; i < kLam<X>; ++i) L.l[i] = d.lam[(size_t)i * d.P + p];
   L.I1 = d.i1[p];
 }
 
-template <class T>
+template <class T, bool X>
 __device__ __forceinline__ void store_iter(const Dev<T>& d, const Slot<T>& L, int p) {
   if (!(L.f & F_VALID)) return;
   d.px[p] = L.x0; d.py[p] = L.x1; d.pz[p] = L.x2; d.s[p] = L.s;
   d.qx[p] = L.q0; d.qy[p] = L.q1; d.qz[p] = L.q2; d.qw[p] = L.q3;
 #pragma unroll
-  for (int i = 0; i < 10; ++i) d.lam[(size_t)i * d.P + p] = L.l[i];
+  for (int i = 0; i < kLam<X>; ++i) d.lam[(size_t)i * d.P + p] = L.l[i];
 }
 
 // ITERATION mode, Jacobi variant of stage 2 (Sec. 7: constraints computed in parallel, their
@@ -121,17 +126,17 @@ struct JacobiAcc {
   T nx = T(0), ns = T(0), nq = T(0);
 };
 
-template <class T>
+template <class T, bool X>
 __device__ __forceinline__ void jacobi_edge(Slot<T>& L, const Slot<T>& L0, T b0, T b1, T b2, T sb, T wb, T wsb,
                                             JacobiAcc<T>& aL, JacobiAcc<T>& aR) {
   const uint32_t types[4] = {F_SS, F_VOL, F_SG, F_SR};
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
+  for (int t = 0; t < (X ? 4 : 3); ++t) {
     if (!(L0.f & types[t])) continue;
     Slot<T> a = L0;
     a.f = (L0.f & ~(F_SS | F_VOL | F_SG | F_SR)) | types[t];
     T c0 = b0, c1 = b1, c2 = b2, cs = sb;
-    edge_update(a, c0, c1, c2, cs, wb, wsb);
+    edge_update<T, X>(a, c0, c1, c2, cs, wb, wsb);
     if (t == 0) {
       L.l[0] = a.l[0]; L.l[1] = a.l[1]; L.l[2] = a.l[2];
       aL.dq0 += a.q0 - L0.q0; aL.dq1 += a.q1 - L0.q1; aL.dq2 += a.q2 - L0.q2; aL.dq3 += a.q3 - L0.q3; aL.nq += T(1);
@@ -174,15 +179,15 @@ __device__ __forceinline__ void jacobi_apply(Slot<T>& L, const JacobiAcc<T>& a) 
   }
 }
 
-template <class T>
+template <class T, bool X>
 __device__ __forceinline__ void jacobi_lane(Lane2<T>& P) {
   const Slot<T> A0 = P.A, B0 = P.B;
   // the next lane's slot A as it stands at the start of the iteration
   const T n0 = dn(A0.x0), n1 = dn(A0.x1), n2 = dn(A0.x2), ns = dn(A0.s);
   const T nq0 = dn(A0.q0), nq1 = dn(A0.q1), nq2 = dn(A0.q2), nq3 = dn(A0.q3);
   JacobiAcc<T> aA, aB, aN;
-  if (A0.f & F_EDGE) jacobi_edge(P.A, A0, B0.x0, B0.x1, B0.x2, B0.s, B0.w, B0.ws, aA, aB);
-  if (B0.f & F_EDGE) jacobi_edge(P.B, B0, n0, n1, n2, ns, P.wN, P.wsN, aB, aN);
+  if (A0.f & F_EDGE) jacobi_edge<T, X>(P.A, A0, B0.x0, B0.x1, B0.x2, B0.s, B0.w, B0.ws, aA, aB);
+  if (B0.f & F_EDGE) jacobi_edge<T, X>(P.B, B0, n0, n1, n2, ns, P.wN, P.wsN, aB, aN);
   if ((A0.f & F_BT) && (A0.f & F_BTEN)) jacobi_bt(P.A, A0, B0.q0, B0.q1, B0.q2, B0.q3, B0.s, B0.I1, B0.ws, aA, aB);
   if ((B0.f & F_BT) && (B0.f & F_BTEN)) jacobi_bt(P.B, B0, nq0, nq1, nq2, nq3, ns, P.I1N, P.wsN, aB, aN);
   // this lane's contributions to the next lane's A arrive there; add the previous lane's here
@@ -199,7 +204,7 @@ __device__ __forceinline__ void jacobi_lane(Lane2<T>& P) {
   jacobi_apply(P.B, aB);
 }
 
-template <class T>
+template <class T, bool X>
 __global__ void __launch_bounds__(256) rod_iteration_kernel(const Dev<T>* __restrict__ D, const Blk* __restrict__ tab,
                                                             T h, const ContactDev* __restrict__ CD) {
   Lane2<T> P;
@@ -207,8 +212,8 @@ __global__ void __launch_bounds__(256) rod_iteration_kernel(const Dev<T>* __rest
   const Dev<T>* dp = lane_setup(D, tab, P, pA, pB);
   if (!dp) return;
   const Dev<T>& d = *dp;
-  load_iter(d, P.A, pA);
-  load_iter(d, P.B, pB);
+  load_iter<T, X>(d, P.A, pA);
+  load_iter<T, X>(d, P.B, pB);
   if (CD) {   // the previous contact pass's corrections come first
     const ContactDev& c = CD[dp - D];
     if (P.A.f & F_VALID) contact_apply(c, pA, P.A.x0, P.A.x1, P.A.x2, P.A.s);
@@ -218,12 +223,12 @@ __global__ void __launch_bounds__(256) rod_iteration_kernel(const Dev<T>* __rest
     if (P.A.f & F_VALID) floor_apply(d, pA, P.A.x0, P.A.x1, P.A.x2, P.A.s);
     if (P.B.f & F_VALID) floor_apply(d, pB, P.B.x0, P.B.x1, P.B.x2, P.B.s);
   }
-  load_lane_consts(d, P, pA, pB, rcp(h * h));
+  load_lane_consts<T, X>(d, P, pA, pB, rcp(h * h));
   P.I1N = dn(P.A.I1);
-  if (d.jacobi) jacobi_lane(P);       // wave-uniform: one scene per block
-  else iteration_lane(P);
-  store_iter(d, P.A, pA);
-  store_iter(d, P.B, pB);
+  if (d.jacobi) jacobi_lane<T, X>(P);       // wave-uniform: one scene per block
+  else iteration_lane<T, X>(P);
+  store_iter<T, X>(d, P.A, pA);
+  store_iter<T, X>(d, P.B, pB);
 }
 
 // ITERATION mode, stage 3: velocity update.
@@ -379,8 +384,12 @@ __global__ void __launch_bounds__(256) lbs_kernel(int V, const float* __restrict
 
 template <class T> hipError_t launch_rod_frame(const BatchDev& b, int nsub, double h, int iters, hipStream_t st) {
   if (b.nblk[TB_WAVES] == 0) return hipSuccess;
-  hipLaunchKernelGGL(rod_frame_kernel<T>, dim3(b.nblk[TB_WAVES]), dim3(256), 0, st, (const Dev<T>*)b.dev,
-                     b.tab[TB_WAVES], nsub, (T)h, iters);
+  if (b.extras)
+    hipLaunchKernelGGL((rod_frame_kernel<T, true>), dim3(b.nblk[TB_WAVES]), dim3(256), 0, st, (const Dev<T>*)b.dev,
+                       b.tab[TB_WAVES], nsub, (T)h, iters);
+  else
+    hipLaunchKernelGGL((rod_frame_kernel<T, false>), dim3(b.nblk[TB_WAVES]), dim3(256), 0, st, (const Dev<T>*)b.dev,
+                       b.tab[TB_WAVES], nsub, (T)h, iters);
   return hipGetLastError();
 }
 template <class T> hipError_t launch_predict(const BatchDev& b, double h, hipStream_t st) {
@@ -391,8 +400,12 @@ template <class T> hipError_t launch_predict(const BatchDev& b, double h, hipStr
 }
 template <class T> hipError_t launch_rod_iteration(const BatchDev& b, double h, const ContactDev* cd, hipStream_t st) {
   if (b.nblk[TB_WAVES] == 0) return hipSuccess;
-  hipLaunchKernelGGL(rod_iteration_kernel<T>, dim3(b.nblk[TB_WAVES]), dim3(256), 0, st, (const Dev<T>*)b.dev,
-                     b.tab[TB_WAVES], (T)h, cd);
+  if (b.extras)
+    hipLaunchKernelGGL((rod_iteration_kernel<T, true>), dim3(b.nblk[TB_WAVES]), dim3(256), 0, st, (const Dev<T>*)b.dev,
+                       b.tab[TB_WAVES], (T)h, cd);
+  else
+    hipLaunchKernelGGL((rod_iteration_kernel<T, false>), dim3(b.nblk[TB_WAVES]), dim3(256), 0, st, (const Dev<T>*)b.dev,
+                       b.tab[TB_WAVES], (T)h, cd);
   return hipGetLastError();
 }
 template <class T> hipError_t launch_velocity(const BatchDev& b, double h, const ContactDev* cd, hipStream_t st) {

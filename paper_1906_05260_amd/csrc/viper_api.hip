@@ -57,9 +57,9 @@ struct Layout {
 struct Offsets {
   size_t state[15];        // px py pz vx vy vz s sd qx qy qz qw ox oy oz
   size_t pill_rest[3];     // winv wsinv rbar
-  size_t edge_rest[22];    // ilb il0 cbt inert dbx dby dbz css cvol csg cbtc qrx qry qrz qrw mrx mry mrz csr
-                           // csb sbg0 sbg2
-  size_t scratch[10];      // xpx xpy xpz spv qpx qpy qpz qpw i1 lam(10P)
+  size_t edge_rest[23];    // ilb il0 cbt inert dbx dby dbz css cvol csg cbtc qrx qry qrz qrw mrx mry mrz csr
+                           // csb sbg0 sbg2 cvb
+  size_t scratch[10];      // xpx xpy xpz spv qpx qpy qpz qpw i1 lam(12P)
   size_t flags, wave_start, status, stage, xform, anchor, rod_of, header;
   size_t sec_off = 0, sec_pill = 0, sec_of = 0, sec_xr = 0, sec_q = 0, sec_fit = 0;   // bundling
   size_t bone_prev = 0, bone_delta = 0, pill_bone = 0, pill_bone_w = 0;  // bones
@@ -77,6 +77,7 @@ struct Host {
   std::vector<int32_t> rod_of;
   std::vector<double> ilb, il0, cbt, inert, db[3], cs[5], qr[4], mr[3];
   std::vector<double> sbc, sbg0, sbg2;   // surface bending: compliance scaling, dC/ds_j-1, dC/ds_j+1
+  std::vector<double> vbc;               // volume-bending coupling: compliance scaling
   bool any_sr = false, any_sb = false;
   std::vector<double> bone_rest, pill_bone_w;   // bones: rest transforms, two weights per pill
   std::vector<int32_t> pill_bone;
@@ -115,6 +116,8 @@ viper_status validate(const viper_scene_desc* d) {
       return fail(VIPER_ERR_INVALID, "floor_normal must be finite and nonzero, floor_offset finite");
   }
   if (d->solver != 0 && d->solver != 1) return fail(VIPER_ERR_INVALID, "solver must be 0 (Gauss-Seidel) or 1 (Jacobi)");
+  if (d->volume_bending && d->solver == 1)
+    return fail(VIPER_ERR_INVALID, "the volume-bending coupling (volume_bending) needs the Gauss-Seidel solver");
   if (d->num_bones < 0) return fail(VIPER_ERR_INVALID, "num_bones < 0");
   if (d->num_bones > 0) {
     if (!d->bone_rest || !d->pill_bones || !d->pill_bone_weights)
@@ -275,7 +278,7 @@ Offsets make_layout(const viper_scene_desc* d, int P, int W, int E, int cap) {
   for (auto& v : o.pill_rest) v = L.take(ts * P);
   for (auto& v : o.edge_rest) v = L.take(ts * P);
   for (int i = 0; i < 9; ++i) o.scratch[i] = L.take(ts * P);
-  o.scratch[9] = L.take(ts * 10 * (size_t)P);
+  o.scratch[9] = L.take(ts * 12 * (size_t)P);
   o.flags = L.take(4 * (size_t)P);
   o.wave_start = L.take(4 * (size_t)(W + 1));
   o.status = L.take(4 * ST_WORDS);
@@ -376,6 +379,7 @@ void build_host(const viper_scene_desc* d, Host& H) {
   for (int i = 0; i < 4; ++i) { H.cs[i].assign(P, 0); H.qr[i].assign(P, 0); }
   H.cs[4].assign(P, 0);
   H.sbc.assign(P, 0); H.sbg0.assign(P, 0); H.sbg2.assign(P, 0);
+  H.vbc.assign(P, 0);
   H.any_sr = false;
   H.any_sb = false;
   for (int p = 0; p < P; ++p) H.qr[3][p] = 1.0;
@@ -392,8 +396,9 @@ void build_host(const viper_scene_desc* d, Host& H) {
     const bool sb = d->bending_compliance && std::isfinite(d->bending_compliance[k]);
     H.any_sr = H.any_sr || sr;
     H.any_sb = H.any_sb || sb;
+    const bool vb = d->volume_bending != 0 && en[1];
     uint32_t ef = (en[0] ? F_SS : 0u) | (en[1] ? F_VOL : 0u) | (en[2] ? F_SG : 0u) | (en[3] ? F_BTEN : 0u) |
-                  (sr ? F_SR : 0u) | (sb ? F_SB : 0u);
+                  (sr ? F_SR : 0u) | (sb ? F_SB : 0u) | (vb ? F_VB : 0u);
     double tprev[3] = {0, 0, 1}, qcur[4] = {0, 0, 0, 1};
     for (int p = a; p < b; ++p) {
       uint32_t f = F_VALID | ef;
@@ -435,6 +440,10 @@ void build_host(const viper_scene_desc* d, Host& H) {
       const double rv = H.rbar[p + 1], r4 = rv * rv * rv * rv;
       const double lv = 0.5 * (l0[p] + l0[p + 1]);
       if (en[3]) H.cs[3][p] = d->compliance[4 * k + 3] / (kPi * r4 / 4.0 * lv);
+      if (vb) {
+        H.vbc[p] = d->compliance[4 * k + 1] / (kPi * r4 / 2.0 * lv);
+        H.proj_per_iter += 1;
+      }
       if (sb) {
         H.sbc[p] = d->bending_compliance[k] / (kPi * r4 / 4.0 * lv);
         H.sbg0[p] = 1.0 / (l0[p] * lv);
@@ -487,6 +496,7 @@ struct viper_scene_s {
   int cross_stretch = 0;      // some rod has the cross-section stretch constraint
   int nbones = 0;             // kinematic bones
   int surface_bending = 0;    // some rod has the surface-bending constraint
+  int volume_bending = 0;     // the volume-bending coupling is on
   double floor_n[3] = {0.0, 0.0, 0.0}, floor_d = 0.0;
   int cap = 16;
   int R = 0, P = 0, W = 0, E = 0;
@@ -527,10 +537,10 @@ void fill_dev(viper_scene_s* S, Dev<T>& d) {
   for (int i = 0; i < 15; ++i) *st[i] = P_(S->o.state[i]);
   const T** pr[3] = {&d.winv, &d.wsinv, &d.rbar};
   for (int i = 0; i < 3; ++i) *pr[i] = P_(S->o.pill_rest[i]);
-  const T** er[22] = {&d.ilb, &d.il0, &d.cbt, &d.inert, &d.dbx, &d.dby, &d.dbz, &d.css, &d.cvol,
+  const T** er[23] = {&d.ilb, &d.il0, &d.cbt, &d.inert, &d.dbx, &d.dby, &d.dbz, &d.css, &d.cvol,
                       &d.csg, &d.cbtc, &d.qrx, &d.qry, &d.qrz, &d.qrw, &d.mrx, &d.mry, &d.mrz, &d.csr,
-                      &d.csb, &d.sbg0, &d.sbg2};
-  for (int i = 0; i < 22; ++i) *er[i] = P_(S->o.edge_rest[i]);
+                      &d.csb, &d.sbg0, &d.sbg2, &d.cvb};
+  for (int i = 0; i < 23; ++i) *er[i] = P_(S->o.edge_rest[i]);
   T** sc[9] = {&d.xpx, &d.xpy, &d.xpz, &d.spv, &d.qpx, &d.qpy, &d.qpz, &d.qpw, &d.i1};
   for (int i = 0; i < 9; ++i) *sc[i] = P_(S->o.scratch[i]);
   d.lam = P_(S->o.scratch[9]);
@@ -577,10 +587,10 @@ viper_status upload(viper_scene_s* S, const Host& H, hipStream_t st) {
   HIP_TRY(put(S->o.pill_rest[0], H.winv));
   HIP_TRY(put(S->o.pill_rest[1], H.wsinv));
   HIP_TRY(put(S->o.pill_rest[2], H.rbar));
-  const std::vector<double>* er[22] = {&H.ilb, &H.il0, &H.cbt, &H.inert, &H.db[0], &H.db[1], &H.db[2], &H.cs[0],
+  const std::vector<double>* er[23] = {&H.ilb, &H.il0, &H.cbt, &H.inert, &H.db[0], &H.db[1], &H.db[2], &H.cs[0],
                                        &H.cs[1], &H.cs[2], &H.cs[3], &H.qr[0], &H.qr[1], &H.qr[2], &H.qr[3],
-                                       &H.mr[0], &H.mr[1], &H.mr[2], &H.cs[4], &H.sbc, &H.sbg0, &H.sbg2};
-  for (int i = 0; i < 22; ++i) HIP_TRY(put(S->o.edge_rest[i], *er[i]));
+                                       &H.mr[0], &H.mr[1], &H.mr[2], &H.cs[4], &H.sbc, &H.sbg0, &H.sbg2, &H.vbc};
+  for (int i = 0; i < 23; ++i) HIP_TRY(put(S->o.edge_rest[i], *er[i]));
   HIP_TRY(hipMemcpyAsync(b + S->o.flags, H.flags.data(), 4 * (size_t)P, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(b + S->o.anchor, H.anchor.data(), 8 * H.anchor.size(), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(b + S->o.rod_of, H.rod_of.data(), 4 * (size_t)P, hipMemcpyHostToDevice, st));
@@ -742,6 +752,7 @@ viper_status viper_create_scene(const viper_scene_desc* desc, void* workspace, s
   S->jacobi = desc->solver == 1;
   S->cross_stretch = H.any_sr ? 1 : 0;
   S->surface_bending = H.any_sb ? 1 : 0;
+  S->volume_bending = desc->volume_bending != 0;
   S->nbones = desc->num_bones > 0 ? desc->num_bones : 0;
   if (desc->floor_on) {
     const double* n = desc->floor_normal;
@@ -775,6 +786,7 @@ viper_status viper_create_scene(const viper_scene_desc* desc, void* workspace, s
     const size_t dsz = S->precision == VIPER_F64 ? sizeof(Dev<double>) : sizeof(Dev<float>);
     build_header(S->header, std::vector<const void*>{dv}, dsz, std::vector<ContactDev>{S->cd},
                  std::vector<Counts>{scene_counts(S)}, S->ws + o.header, S->batch);
+    S->batch.extras = S->cross_stretch || S->surface_bending || S->volume_bending;
     if (hipMemcpyAsync(S->ws + o.header, S->header.data(), S->header.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
       r = fail(VIPER_ERR_DEVICE, "header upload failed");
@@ -954,6 +966,7 @@ viper_status adjoint_check(viper_scene S, int32_t frames, int32_t substeps, int3
   if (S->cross_stretch) return fail(VIPER_ERR_INVALID, "the adjoint does not cover the cross-section stretch");
   if (S->nbones) return fail(VIPER_ERR_INVALID, "the adjoint does not cover bones");
   if (S->surface_bending) return fail(VIPER_ERR_INVALID, "the adjoint does not cover surface bending");
+  if (S->volume_bending) return fail(VIPER_ERR_INVALID, "the adjoint does not cover the volume-bending coupling");
   if (frames < 1 || substeps < 1 || iterations < 0)
     return fail(VIPER_ERR_INVALID, "frames >= 1, substeps >= 1 and iterations >= 0 required");
   return VIPER_OK;
@@ -1175,6 +1188,8 @@ viper_status viper_pool_admit(viper_pool P, const viper_scene_desc* desc, void* 
       if (std::isfinite(desc->cross_compliance[k]))
         return fail(VIPER_ERR_INVALID, "scenes with the cross-section stretch are stepped with viper_step");
   if (desc->num_bones > 0) return fail(VIPER_ERR_INVALID, "scenes with bones are stepped with viper_step");
+  if (desc->volume_bending)
+    return fail(VIPER_ERR_INVALID, "scenes with the volume-bending coupling are stepped with viper_step");
   if (desc->bending_compliance)
     for (int k = 0; k < desc->num_rods; ++k)
       if (std::isfinite(desc->bending_compliance[k]))

@@ -21,7 +21,8 @@ enum : uint32_t {
   F_SS = 32u, F_VOL = 64u, F_SG = 128u, F_BTEN = 256u,  // constraint types enabled for the rod
   F_SR = 512u,    // cross-section stretch enabled for the rod (optional, eq. stretch_xy)
   F_SB = 1024u,   // surface bending enabled for the rod (optional, Laplacian of the scale)
-  F_M3A = 2048u, F_M3B = 4096u  // local pill index mod 3 is 1 / is 2 (surface-bending colour)
+  F_M3A = 2048u, F_M3B = 4096u,  // local pill index mod 3 is 1 / is 2 (surface-bending colour)
+  F_VB = 8192u    // volume-bending coupling at the vertex after the slot's edge (optional)
 };
 
 enum { ST_NAN = 0, ST_OVERFLOW = 1, ST_WORDS = 4 };
@@ -41,12 +42,13 @@ struct Dev {
   const T *ilb, *il0, *cbt, *inert;             // 1/lbar, 1/l0, 4/(l0_j + l0_{j+1}), rho pi r^4 l0
   const T *dbx, *dby, *dbz;                     // rest Darboux vector of the bend-twist at this slot
   const T *css, *cvol, *csg, *cbtc, *csr;
-  const T *csb, *sbg0, *sbg2;                   // surface bending at the vertex after the slot's edge             // compliance / (G * length)
+  const T *csb, *sbg0, *sbg2;                   // surface bending at the vertex after the slot's edge
+  const T *cvb;                                 // volume-bending coupling, compliance / (G l_v)             // compliance / (G * length)
   const T *qrx, *qry, *qrz, *qrw;               // rest quaternion
   const T *mrx, *mry, *mrz;                     // rest capsule midpoint
   // substep scratch (ITERATION mode)
   T *xpx, *xpy, *xpz, *spv, *qpx, *qpy, *qpz, *qpw;  // state at substep start
-  T *lam;                    // [10*P] accumulated multipliers: ss(3) vol sg bt(3) sr sb
+  T *lam;                    // [12*P] accumulated multipliers: ss(3) vol sg bt(3) sr sb vb(2)
   T *i1;                     // [P] inverse bending inertia of the edge for this substep
   int32_t* status;           // [ST_WORDS]
   // Positions are stored relative to a per-rod anchor (the rest position of the rod's
@@ -154,6 +156,8 @@ struct BatchDev {
   const ContactDev* cd = nullptr;     // ContactDev[nscenes] in device memory (contact batches)
   const Blk* tab[TB_COUNT] = {};
   int nblk[TB_COUNT] = {};
+  bool extras = false;                // some scene uses an optional constraint term (the rod
+                                      // kernels' instantiation with them compiled in)
 };
 
 // Launchers over a batch (enqueue on `stream`, return hipError_t of the launches).

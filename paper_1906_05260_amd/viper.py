@@ -71,6 +71,7 @@ class SceneDescC(ctypes.Structure):
         ("pill_bones", ctypes.c_void_p),
         ("pill_bone_weights", ctypes.c_void_p),
         ("bending_compliance", ctypes.c_void_p),
+        ("volume_bending", ctypes.c_int32),
     ]
 
 
@@ -183,6 +184,7 @@ class _DescHolder:
             if a["sb"].shape[0] != c.num_rods:
                 raise ValueError("bending_compliance needs one value per rod")
             c.bending_compliance = a["sb"].ctypes.data
+        c.volume_bending = 1 if getattr(desc, "volume_bending", False) else 0
         self.c = c
 
 

@@ -188,3 +188,13 @@ def test_surface_bending_validation():
     viper.footprint(dataclasses.replace(d, bending_compliance=np.array([np.inf, np.inf]), solver="jacobi"))
     with pytest.raises(ValueError):
         viper.footprint(dataclasses.replace(d, bending_compliance=np.zeros(3)))
+
+
+def test_volume_bending_validation():
+    """The volume-bending coupling is a Gauss-Seidel-only option: a Jacobi scene that turns it
+    on is rejected; the footprint does not depend on it."""
+    d = scenes.helix_rods(2, 8, seed=1)
+    assert viper.footprint(dataclasses.replace(d, volume_bending=True)) == viper.footprint(d)
+    with pytest.raises(viper.ViperError) as ei:
+        viper.footprint(dataclasses.replace(d, volume_bending=True, solver="jacobi"))
+    assert ei.value.status == viper.ERR_INVALID and "volume_bending" in str(ei.value)
