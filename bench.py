@@ -111,8 +111,10 @@ def copy_reference(torch, dev, mib, steps):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
-    print(json.dumps({"kernel": "neg (elementwise copy)", "bytes_read": 4 * n, "bytes_written": 4 * n,
-                      "ms_per_launch": ms, "GB_per_s": 8 * n / (ms * 1e-3) / 1e9}), flush=True)
+    rec = {"kernel": "neg (elementwise copy)", "bytes_read": 4 * n, "bytes_written": 4 * n,
+           "ms_per_launch": ms, "GB_per_s": 8 * n / (ms * 1e-3) / 1e9}
+    del a, b
+    return rec
 
 
 def adjoint_timing(torch, viper, scenes, dev, reps=5):
@@ -449,7 +451,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.copy_mib:
-        copy_reference(torch, dev, args.copy_mib, args.steps)
+        print(json.dumps(copy_reference(torch, dev, args.copy_mib, args.steps)), flush=True)
         return
     dt, sub, iters = 1.0 / 60.0, args.substeps, args.iters
     desc = scenes.helix_rods(args.rods, args.pills, seed=1)
@@ -485,6 +487,15 @@ def main():
     bts = P - 2 * desc.num_rods
     proj_per_frame = sc.projections_per_iteration * iters * sub
     value = proj_per_frame * K / elapsed
+    # the same rate split by constraint type (a type counts on the rods whose compliance for it
+    # is finite: edges for stretch-shear, volume and scale gradient, interior vertices for
+    # bend-twist)
+    comp = np.asarray(desc.compliance, float).reshape(-1, 4)
+    n_rod = np.diff(np.asarray(desc.rod_offsets))
+    per_iter = {t: int(np.sum(np.where(np.isfinite(comp[:, i]), n_rod - (2 if t == "bt" else 1), 0)))
+                for i, t in enumerate(("ss", "vol", "sg", "bt"))}
+    assert sum(per_iter.values()) == sc.projections_per_iteration
+    by_type = {t: v * iters * sub * K / elapsed for t, v in per_iter.items()}
     flop_sub = iters * (edges * (FLOP["ss"] + FLOP["vol"] + FLOP["sg"]) + bts * FLOP["bt"]) + \
         P * (FLOP["predict"] + FLOP["velocity"])
     flop_launch = flop_sub * (sub if mode == viper.MODE_FRAME else 1)
@@ -513,7 +524,7 @@ def main():
         "data": "synthetic (seeded random helices)",
         "config": {"workload": workload, "rods": args.rods, "pills_per_rod": args.pills, "substeps": sub,
                    "iterations": iters, "frames_timed": K, "collisions": False, "launch": args.mode,
-                   "pill_substeps_per_s": P * sub * K / elapsed},
+                   "pill_substeps_per_s": P * sub * K / elapsed, "projections_per_s_by_type": by_type},
         "roofline": roof,
     }
     log("headline: %.3f ms/frame, rod kernel %.3f ms" % (elapsed * 1e3 / K, kern_ms))
@@ -532,6 +543,9 @@ def main():
     if not args.no_adjoint:
         out["adjoint"] = adjoint_timing(torch, viper, scenes, dev)
         log("adjoint done")
+    # the measured copy ceiling beside the 8 TB/s specification (1 GiB read + 1 GiB written)
+    out["copy_ceiling"] = copy_reference(torch, dev, 1024, 20)
+    log("copy ceiling done")
     if not args.no_serve:
         from paper_1906_05260_amd import serve
         out["serving"] = serving_run(torch, scenes, serve, args.serve_seconds)
