@@ -207,6 +207,14 @@ viper_status viper_skin(viper_scene scene, int32_t skin_id, float* out_dev, void
 viper_status viper_skin_weights(viper_scene scene, int32_t V, const float* rest_v_dev, int32_t* caps_dev, float* w_dev,
                                 void* stream);
 
+/* Kinematic half-plane (Sec. 7 collision proxies): move the floor of a scene created with
+ * floor_on to floor_normal . x >= floor_offset + s rbar (host values; the normal need not be
+ * unit, it is normalised).  Ordered on `stream`: frames enqueued after it (captured graph
+ * replays included) project onto the new plane; frames already enqueued keep the old one.
+ * VIPER_ERR_INVALID for a scene without a floor or a non-finite or zero normal (nothing
+ * changed). */
+viper_status viper_set_floor(viper_scene scene, const double* floor_normal, double floor_offset, void* stream);
+
 /* Kinematic bones (Sec. 8.2): the bones' transforms of a new frame, transforms [num_bones*12]
  * host memory (read before the call returns), each [A | b] 3x4 row-major with A invertible.
  * Every pill with bone weight moves by the blend of its bones' motions since the previous

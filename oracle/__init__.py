@@ -163,6 +163,11 @@ class OracleScene:
         zero multipliers (as project_one)."""
         return int(lib().orc_rod_iteration(self.h, float(h), int(iters)))
 
+    def set_floor(self, plane):
+        """Move the half-plane floor to plane = (nx, ny, nz, d) (Sec. 7, kinematic proxy)."""
+        n = np.ascontiguousarray(plane[:3], dtype=np.float64)
+        lib().orc_set_floor(self.h, _p(n), float(plane[3]))
+
     def set_bones(self, transforms):
         """The bones' transforms of a new frame ([nb, 3, 4]): warm start of the pills (Sec. 8.2)."""
         t = _f64(transforms).reshape(-1)

@@ -903,6 +903,30 @@ viper_status viper_skin_weights(viper_scene S, int32_t V, const float* rest_v, i
   return VIPER_OK;
 }
 
+viper_status viper_set_floor(viper_scene S, const double* normal, double offset, void* stream) {
+  if (!S || !normal) return fail(VIPER_ERR_INVALID, "scene and normal are required");
+  if (!S->floor_on) return fail(VIPER_ERR_INVALID, "the scene was created without a floor");
+  if (!std::isfinite(normal[0]) || !std::isfinite(normal[1]) || !std::isfinite(normal[2]) || !std::isfinite(offset) ||
+      !(normal[0] * normal[0] + normal[1] * normal[1] + normal[2] * normal[2] > 0))
+    return fail(VIPER_ERR_INVALID, "floor normal must be finite and nonzero, offset finite");
+  const double l = std::sqrt(normal[0] * normal[0] + normal[1] * normal[1] + normal[2] * normal[2]);
+  for (int i = 0; i < 3; ++i) S->floor_n[i] = normal[i] / l;
+  S->floor_d = offset / l;
+  // the scene record lives at the start of the device header: update it there, in stream order
+  size_t dsz;
+  if (S->precision == VIPER_F64) {
+    S->dd.fnx = S->floor_n[0]; S->dd.fny = S->floor_n[1]; S->dd.fnz = S->floor_n[2]; S->dd.fd = S->floor_d;
+    dsz = sizeof(Dev<double>);
+    std::memcpy(S->header.data(), &S->dd, dsz);
+  } else {
+    S->df.fnx = S->floor_n[0]; S->df.fny = S->floor_n[1]; S->df.fnz = S->floor_n[2]; S->df.fd = S->floor_d;
+    dsz = sizeof(Dev<float>);
+    std::memcpy(S->header.data(), &S->df, dsz);
+  }
+  HIP_TRY(hipMemcpyAsync(S->ws + S->o.header, S->header.data(), dsz, hipMemcpyHostToDevice, (hipStream_t)stream));
+  return VIPER_OK;
+}
+
 viper_status viper_set_bones(viper_scene S, const double* transforms, void* stream) {
   if (!S || !transforms) return fail(VIPER_ERR_INVALID, "scene and transforms are required");
   if (S->nbones == 0) return fail(VIPER_ERR_INVALID, "the scene has no bones");

@@ -33,7 +33,7 @@ ABI_SYMBOLS = [
     "viper_pool_create", "viper_pool_admit", "viper_pool_step", "viper_pool_retire", "viper_pool_scene",
     "viper_pool_info", "viper_pool_destroy",
     "viper_adjoint_sizes", "viper_step_checkpointed", "viper_step_backward", "viper_pool_step_ex",
-    "viper_skin_weights", "viper_set_bones",
+    "viper_skin_weights", "viper_set_bones", "viper_set_floor",
 ]
 
 
@@ -335,6 +335,12 @@ class Scene:
                                        ctypes.c_void_p(w.data_ptr()), _stream_ptr(stream)))
         self._keep_alive = rv
         return caps, w
+
+    def set_floor(self, plane, stream=None):
+        """Move the floor (include/viper.h, viper_set_floor) to plane = (nx, ny, nz, d)."""
+        n = np.ascontiguousarray(plane[:3], np.float64)
+        check(lib().viper_set_floor(self.handle, ctypes.c_void_p(n.ctypes.data), ctypes.c_double(float(plane[3])),
+                                    _stream_ptr(stream)))
 
     def set_bones(self, transforms, stream=None):
         """The bones' transforms of a new frame, [nb, 3, 4] (include/viper.h, viper_set_bones):

@@ -111,3 +111,48 @@ def test_rejections():
     with pytest.raises(viper.ViperError) as ei:
         pool.admit(desc)
     assert ei.value.status == viper.ERR_INVALID
+
+
+def moving_plane(f):
+    """A floor that rises 1 mm and tilts a little more each frame."""
+    return (0.05 + 0.004 * f, 1.0, 0.02 - 0.002 * f, -0.002 + 0.001 * f)
+
+
+def test_moving_floor_fp64_and_graph():
+    """Kinematic half-plane: the floor moves before every frame (viper_set_floor).  FP64: 20
+    frames equal the oracle moving its floor the same way; FP32: the captured-graph frames
+    (which read the plane from the scene record) equal eager launches bit for bit; a scene
+    without a floor and a zero normal are rejected."""
+    desc = flat_rods()
+    say("case: moving floor fp64")
+    sc = viper.Scene(desc, "f64")
+    o = oracle.OracleScene(desc, "f64")
+    for f in range(1, 21):
+        sc.set_floor(moving_plane(f))
+        o.set_floor(moving_plane(f))
+        sc.step(1 / 60, 10, 4)
+        o.step(1 / 60, 10, 4)
+    sc.sync()
+    ex, es, eq = errors(desc, sc.state(), o.get_state())
+    say("moving floor fp64 errors", ex, es, eq)
+    assert ex < 1e-9 and es < 1e-9 and eq < 1e-9
+    n = np.asarray(moving_plane(20)[:3])
+    x = sc.state()["x"]
+    assert (x @ n / np.linalg.norm(n) - moving_plane(20)[3] / np.linalg.norm(n)).min() > 0.0
+    a, b = viper.Scene(desc, "f32"), viper.Scene(desc, "f32")
+    for f in range(1, 11):
+        for s in (a, b):
+            s.set_floor(moving_plane(f))
+        a.step(1 / 60, 10, 4)
+        b.step(1 / 60, 10, 4, mode=viper.MODE_ITERATION)
+    a.sync()
+    b.sync()
+    for k in ("x", "v", "s", "q"):
+        assert np.array_equal(a.state()[k], b.state()[k]), k
+    with pytest.raises(viper.ViperError) as ei:
+        a.set_floor((0.0, 0.0, 0.0, 0.0))
+    assert ei.value.status == viper.ERR_INVALID
+    plain = viper.Scene(scenes.helix_rods(2, 8, seed=1), "f32")
+    with pytest.raises(viper.ViperError) as ei:
+        plain.set_floor((0.0, 1.0, 0.0, 0.0))
+    assert ei.value.status == viper.ERR_INVALID
