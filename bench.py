@@ -364,6 +364,33 @@ def solver_timing(torch, viper, scenes, dev, frames=5):
     return res
 
 
+def large_timing(torch, viper, scenes, dev, rods=65536, frames=5):
+    """The helix workload at 16x the rods (65,536 x 64 = 4.2M pills, FP32, 20 x 8): its state
+    (~1.4 GB of workspace) no longer fits the 256 MB MALL, so each frame launch streams it from
+    HBM.  ms per frame launch (HIP events on the launch stream) and the same VALU roofline as
+    the headline."""
+    desc = scenes.helix_rods(rods, 64, seed=1)
+    sc = viper.Scene(desc, "f32", device=dev)
+    sc.step(1.0 / 60.0, 20, 8, mode=viper.MODE_FRAME)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(frames):
+        sc.step(1.0 / 60.0, 20, 8, mode=viper.MODE_FRAME)
+    e1.record(st)
+    torch.cuda.synchronize()
+    sc.sync()
+    ms = e0.elapsed_time(e1) / frames
+    P = desc.num_pills
+    edges, bts = P - desc.num_rods, P - 2 * desc.num_rods
+    flop = 20 * (8 * (edges * (FLOP["ss"] + FLOP["vol"] + FLOP["sg"]) + bts * FLOP["bt"]) +
+                 P * (FLOP["predict"] + FLOP["velocity"]))
+    return {"workload": "helix%dx64" % rods, "pills": P, "ms_per_frame": ms,
+            "projections_per_s": sc.projections_per_iteration * 8 * 20 / (ms * 1e-3),
+            "tflops": flop / (ms * 1e-3) / 1e12, "frac": flop / (ms * 1e-3) / PEAK_FP32_VALU,
+            "algorithmic_GB_per_s": BYTES_PER_PILL_LAUNCH * P / (ms * 1e-3) / 1e9}
+
+
 def bones_timing(torch, viper, scenes, dev, calls=50):
     """The bone warm start (Sec. 8.2) on the helix workload (4096 x 64, FP32): two bones, every
     pill blended between them by its position along its rod; us per set_bones call (HIP events
@@ -540,6 +567,9 @@ def main():
         log("solvers done")
     out["bones"] = bones_timing(torch, viper, scenes, dev)
     log("bones done")
+    if not args.no_solvers:
+        out["helix_16x"] = large_timing(torch, viper, scenes, dev)
+        log("16x helix done")
     if not args.no_adjoint:
         out["adjoint"] = adjoint_timing(torch, viper, scenes, dev)
         log("adjoint done")
