@@ -365,10 +365,10 @@ def solver_timing(torch, viper, scenes, dev, frames=5):
 
 
 def large_timing(torch, viper, scenes, dev, rods=65536, frames=5):
-    """The helix workload at 16x the rods (65,536 x 64 = 4.2M pills, FP32, 20 x 8): its state
-    (~1.4 GB of workspace) no longer fits the 256 MB MALL, so each frame launch streams it from
-    HBM.  ms per frame launch (HIP events on the launch stream) and the same VALU roofline as
-    the headline."""
+    """The helix workload at 16x the rods (65,536 x 64 = 4.2M pills, FP32, 20 x 8): its workspace
+    (~1.4 GB) no longer fits the 256 MB MALL; a frame launch still reads and writes the state
+    once, so the kernel stays VALU-bound.  ms per frame launch (HIP events on the launch
+    stream) and the same VALU roofline as the headline."""
     desc = scenes.helix_rods(rods, 64, seed=1)
     sc = viper.Scene(desc, "f32", device=dev)
     sc.step(1.0 / 60.0, 20, 8, mode=viper.MODE_FRAME)
