@@ -571,34 +571,61 @@ __global__ void __launch_bounds__(256) contact_pair_kernel(const Dev<T>* __restr
 // the inverse square distance from the vertex to the capsule's surface, |v - c(t)| - r(t) at the
 // capsule's closest sphere t (App. D projection, FP64), clamped below at 1e-9 m; the four
 // strongest are kept (ties keep the lower capsule id) and normalised.  One thread per vertex
-// over every capsule of the scene, at the scene's current pose.
+// over every capsule of the scene, at the scene's current pose; the block stages the capsules
+// in tiles of kSkinTile (world endpoints and radii in FP64, 17 KB of LDS) and every thread
+// scans the tile in capsule order.
+constexpr int kSkinTile = 256;
+
 template <class T>
-__global__ void __launch_bounds__(256) skin_weights_kernel(const Dev<T> d, int V, const float* __restrict__ rest_v,
-                                                           int32_t* __restrict__ caps, float* __restrict__ w) {
+__global__ void __launch_bounds__(kSkinTile) skin_weights_kernel(const Dev<T> d, int V, const float* __restrict__ rest_v,
+                                                                 int32_t* __restrict__ caps, float* __restrict__ w) {
+  __shared__ double s_geo[kSkinTile][8];   // c1 (3), c2 (3), r1, r2
+  __shared__ int s_id[kSkinTile];          // capsule id, -1 for a slot without an edge
   const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-  if (i >= V) return;
-  const D3 x = d3((double)rest_v[3 * (size_t)i], (double)rest_v[3 * (size_t)i + 1], (double)rest_v[3 * (size_t)i + 2]);
+  const bool live = i < V;                 // every thread takes part in the staging
+  const D3 x = live ? d3((double)rest_v[3 * (size_t)i], (double)rest_v[3 * (size_t)i + 1], (double)rest_v[3 * (size_t)i + 2])
+                    : d3(0.0, 0.0, 0.0);
   int best[4] = {-1, -1, -1, -1};
   double bw[4] = {-1.0, -1.0, -1.0, -1.0};
-  for (int p = 0; p + 1 < d.P; ++p) {
-    if (!(d.flags[p] & F_EDGE)) continue;
-    const double* an = d.anchor + 3 * (size_t)d.rod_of[p];
-    const D3 c1 = d3(an[0] + (double)d.px[p], an[1] + (double)d.py[p], an[2] + (double)d.pz[p]);
-    const D3 c2 = d3(an[0] + (double)d.px[p + 1], an[1] + (double)d.py[p + 1], an[2] + (double)d.pz[p + 1]);
-    const double r1 = (double)d.s[p] * (double)d.rbar[p], r2 = (double)d.s[p + 1] * (double)d.rbar[p + 1];
-    const double t = pill_param(x, c1, r1, c2, r2);
-    const D3 rel = sub(x, lerp(c1, c2, t));
-    const double dist = fmax(sqrt(dotp(rel, rel)) - (r1 + t * (r2 - r1)), 1e-9);
-    const double wt = 1.0 / (dist * dist);
-    if (wt > bw[3]) {
-      int k = 3;
-      while (k > 0 && wt > bw[k - 1]) {
-        bw[k] = bw[k - 1]; best[k] = best[k - 1];
-        --k;
-      }
-      bw[k] = wt; best[k] = p;
+  for (int base = 0; base + 1 < d.P; base += kSkinTile) {
+    const int p = base + (int)threadIdx.x;
+    int id = -1;
+    if (p + 1 < d.P && (d.flags[p] & F_EDGE)) {
+      const double* an = d.anchor + 3 * (size_t)d.rod_of[p];
+      double* g = s_geo[threadIdx.x];
+      g[0] = an[0] + (double)d.px[p]; g[1] = an[1] + (double)d.py[p]; g[2] = an[2] + (double)d.pz[p];
+      g[3] = an[0] + (double)d.px[p + 1]; g[4] = an[1] + (double)d.py[p + 1]; g[5] = an[2] + (double)d.pz[p + 1];
+      g[6] = (double)d.s[p] * (double)d.rbar[p];
+      g[7] = (double)d.s[p + 1] * (double)d.rbar[p + 1];
+      id = p;
     }
+    s_id[threadIdx.x] = id;
+    __syncthreads();
+    if (live) {
+      const int n = min(kSkinTile, d.P - 1 - base);
+      for (int j = 0; j < n; ++j) {
+        const int pid = s_id[j];
+        if (pid < 0) continue;
+        const double* g = s_geo[j];
+        const D3 c1 = d3(g[0], g[1], g[2]), c2 = d3(g[3], g[4], g[5]);
+        const double r1 = g[6], r2 = g[7];
+        const double t = pill_param(x, c1, r1, c2, r2);
+        const D3 rel = sub(x, lerp(c1, c2, t));
+        const double dist = fmax(sqrt(dotp(rel, rel)) - (r1 + t * (r2 - r1)), 1e-9);
+        const double wt = 1.0 / (dist * dist);
+        if (wt > bw[3]) {
+          int k = 3;
+          while (k > 0 && wt > bw[k - 1]) {
+            bw[k] = bw[k - 1]; best[k] = best[k - 1];
+            --k;
+          }
+          bw[k] = wt; best[k] = pid;
+        }
+      }
+    }
+    __syncthreads();                       // the tile is overwritten next
   }
+  if (!live) return;
   double sum = 0.0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) if (best[k] >= 0) sum += bw[k];
@@ -782,7 +809,8 @@ hipError_t launch_contact_flush(const BatchDev& b, hipStream_t st) {
 template <class T>
 hipError_t launch_skin_weights(const Dev<T>& d, int V, const float* rest_v, int32_t* caps, float* w, hipStream_t st) {
   if (V <= 0) return hipSuccess;
-  hipLaunchKernelGGL(skin_weights_kernel<T>, dim3((V + 255) / 256), dim3(256), 0, st, d, V, rest_v, caps, w);
+  hipLaunchKernelGGL(skin_weights_kernel<T>, dim3((V + kSkinTile - 1) / kSkinTile), dim3(kSkinTile), 0, st, d, V, rest_v,
+                     caps, w);
   return hipGetLastError();
 }
 template hipError_t launch_skin_weights<float>(const Dev<float>&, int, const float*, int32_t*, float*, hipStream_t);
