@@ -1242,3 +1242,26 @@ def test_volume_bending_scale_step_is_newton_on_the_cube():
     st = o.get_state()
     assert abs(st["s"][1] - 2.0 / 3.0 * 1.2) < 1e-12
     assert st["s"][0] == 1.0 and st["s"][2] == 1.0
+
+
+@pytest.mark.parametrize("term", ["cross_stretch", "surface_bending"])
+def test_jacobi_with_one_optional_constraint_is_gauss_seidel(term):
+    """One cross-section stretch (2 pills) or one surface bending (3 pills) constraint and
+    nothing else: a Jacobi iteration with averaging moves each scale by that constraint's own
+    correction, which is the Gauss-Seidel result."""
+    n = 2 if term == "cross_stretch" else 3
+    d = small_scene([line(n)], comp=(INF, INF, INF, INF))
+    if term == "cross_stretch":
+        d.cross_compliance = np.array([1e-7])
+    else:
+        d.bending_compliance = np.array([1e-7])
+    s0 = np.array([1.2, 0.9, 1.1])[:n]
+    gs = OracleScene(d)
+    d.solver = "jacobi"
+    jc = OracleScene(d)
+    for o in (gs, jc):
+        o.set_state(s=s0)
+        o.rod_iterations(1 / 600, 1)
+    a, b = gs.get_state()["s"], jc.get_state()["s"]
+    assert np.abs(a - s0).max() > 1e-6
+    assert np.abs(a - b).max() < 1e-15
