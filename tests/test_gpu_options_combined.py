@@ -100,3 +100,25 @@ def test_fp32_graph_equals_eager():
     sa, sb = a.state(), b.state()
     for k in ("x", "v", "s", "q"):
         assert np.array_equal(sa[k], sb[k]), k
+
+
+def test_fp32_frames_within_the_fp32_rounding_floor():
+    """FP32 GPU over the same four frames against the FP64 oracle, bounded by 4x the distance of
+    the oracle's own FP32 run from FP64 (its rounding floor on this scene: ~5e-5 in scale by the
+    fourth frame), with the same candidate-pair counts."""
+    d = combined()
+    sc = viper.Scene(d, "f32")
+    o64, o32 = oracle.OracleScene(d, "f64"), oracle.OracleScene(d, "f32")
+    for f in (1, 2, 3, 4):
+        sc.set_bones(bones_at(f))
+        for o in (o64, o32):
+            o.set_bones(bones_at(f))
+            o.step(1 / 60, 4, 4, collide=True)
+        sc.step(1 / 60, 4, 4)
+    sc.sync()
+    g, r, r32 = sc.state(), o64.get_state(), o32.get_state()
+    fx, fs, fq = errors(d, r32, r)
+    ex, es, eq = errors(d, g, r)
+    say("fp32 floor", fx, fs, fq, "gpu", ex, es, eq, "contacts", len(sc.contacts()), len(o64.pairs()))
+    assert len(sc.contacts()) == len(o64.pairs())
+    assert ex <= 4 * fx + 1e-7 and es <= 4 * fs + 1e-7 and eq <= 4 * fq + 1e-7
