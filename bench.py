@@ -10,7 +10,13 @@ synchronisations.
 
 Prints one JSON line with the throughput, a roofline object for the dominant kernel
 (timed per launch with HIP events on the launch stream) and the oracle timed on the
-host cores on a bounded sample of the same workload.
+host cores on a bounded sample of the same workload.  Further entries of the same line:
+the rate split by constraint type (`config.projections_per_s_by_type`), the 32-pill FP64
+rod (`single_rod`), the contact, skinning, skinning-weight, octopus-shaped and bundling
+scenes, the two solvers and the optional energy terms (`solvers`), the bone warm start
+(`bones`), the helix scene at 16x the rods (`helix_16x`), the measured copy ceiling
+(`copy_ceiling`), the adjoint and the serving loop (`serving`, whose p50/p99 frame
+latencies are repeated at the top level).
 """
 from __future__ import annotations
 
