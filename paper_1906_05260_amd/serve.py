@@ -70,6 +70,7 @@ def serve_batched(requests, pool_bytes, dt=1.0 / 60.0, substeps=20, iterations=8
     steps = 0
     host = {"admit_s": 0.0, "step_enqueue_s": 0.0, "gpu_wait_s": 0.0, "retire_s": 0.0}
     t0 = time.perf_counter()
+    last_report = [t0]
 
     def admit_ready():
         nonlocal peak_bytes
@@ -101,9 +102,12 @@ def serve_batched(requests, pool_bytes, dt=1.0 / 60.0, substeps=20, iterations=8
         host["step_enqueue_s"] += time.perf_counter() - ts
         lane["event"], lane["members"] = ev, members
         steps += 1
-        if progress is not None and steps % 100 == 0:
-            progress("batched: %d class steps, %d resident, %d waiting, %d pending, t=%.2fs" %
-                     (steps, len(resident), len(waiting), len(pending), time.perf_counter() - t0))
+        now = time.perf_counter()
+        # every 100 class steps, and at least every 5 s while steps are slow
+        if progress is not None and (steps % 100 == 0 or now - last_report[0] > 5.0):
+            last_report[0] = now
+            progress("batched: %d class steps (class %d, %d scenes in it), %d resident, %d waiting, %d pending, "
+                     "t=%.2fs" % (steps, cls, len(members), len(resident), len(waiting), len(pending), now - t0))
 
     def complete(cls):
         nonlocal pill_frames
