@@ -1265,3 +1265,25 @@ def test_jacobi_with_one_optional_constraint_is_gauss_seidel(term):
     a, b = gs.get_state()["s"], jc.get_state()["s"]
     assert np.abs(a - s0).max() > 1e-6
     assert np.abs(a - b).max() < 1e-15
+
+
+def test_moved_floor_is_the_plane_projected_onto():
+    """Kinematic floor: after the plane moves (set_floor, unnormalised normal), one floor pass
+    puts every penetrating free pill exactly on the new plane n.x = d + s rbar and leaves the
+    pills above it, and the old plane no longer acts."""
+    desc = _flat_rods(floor=(0.0, 1.0, 0.0, 0.0))
+    o = oracle.OracleScene(desc, "f64")
+    rng = np.random.default_rng(2)
+    x = rng.normal(0.0, 0.02, (desc.num_pills, 3))
+    o.set_state(x=x)
+    n_raw, d_raw = np.array([0.3, 2.0, 0.1]), 0.012
+    o.set_floor((*n_raw, d_raw))
+    o.floor_pass()
+    n, d = n_raw / np.linalg.norm(n_raw), d_raw / np.linalg.norm(n_raw)
+    st = o.get_state()
+    r = desc.rest_radius
+    C0 = x @ n - d - r
+    moved = C0 < 0
+    assert moved.any() and (~moved).any()
+    assert np.abs(st["x"][moved] @ n - d - r[moved]).max() < 1e-15
+    assert np.array_equal(st["x"][~moved], x[~moved])
