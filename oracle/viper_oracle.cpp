@@ -759,6 +759,20 @@ template <class R> void project_contacts(Scene<R>& S, int search_iters, double d
 
 // ------------------------------ substep -------------------------------------
 
+// Rotational inertia of every edge for one substep (App. B, the m s^2 I term of the frame
+// update): the body-frame tensor of edge p is  rho pi rbar^4 l0 * s^2 * diag(1/4, 1/4, 1/2),
+// with s the midpoint scale at the START of the substep (held fixed through the substep).
+// inert_base = rho pi rbar^4 l0; only the inverses are stored.
+template <class R> void substep_inertia(Scene<R>& S, int r0, int r1) {
+  for (int k = r0; k < r1; ++k)
+    for (int p = S.off[k]; p + 1 < S.off[k + 1]; ++p) {
+      R sm = R(0.5) * (S.sprev[p] + S.sprev[p + 1]);
+      R I = S.inert_base[p] * sm * sm;
+      S.I1inv[p] = R(4.0) / I;   // I1 = I/4
+      S.I3inv[p] = R(2.0) / I;   // I3 = I/2
+    }
+}
+
 // Prediction (Sec. 6 prediction step, App. B): under gravity the external
 // torque and the scale counterpart vanish, so
 //   c^ = c + h v + h^2 g,  s^ = s + h sdot,  theta^ = theta + h omega.
@@ -779,13 +793,7 @@ template <class R> void predict_rods(Scene<R>& S, R h, int r0, int r1) {
       S.lam_sb[p] = R(0.0);
       S.lam_vb[2 * size_t(p)] = S.lam_vb[2 * size_t(p) + 1] = R(0.0);
     }
-  for (int k = r0; k < r1; ++k)
-    for (int p = S.off[k]; p + 1 < S.off[k + 1]; ++p) {
-      R sm = R(0.5) * (S.sprev[p] + S.sprev[p + 1]);
-      R I = S.inert_base[p] * sm * sm;
-      S.I1inv[p] = R(4.0) / I;   // I1 = I/4
-      S.I3inv[p] = R(2.0) / I;   // I3 = I/2
-    }
+  substep_inertia(S, r0, r1);
 }
 
 // One iteration of the four colour passes (reading: colours 0/1 = even/odd edges
@@ -1279,12 +1287,9 @@ template <class R> static void set_floor_t(Scene<R>& S, const double* n, double 
 // `iters` rod-constraint iterations (no prediction, no contacts) at the current state, from
 // zero multipliers and the inertias of the current scales (as orc_project_one).
 template <class R> static int64_t rod_iterations_t(Scene<R>& S, double h_sub, int iters) {
+  for (int i = 0; i < S.P; ++i) S.sprev[i] = S.s[i];
+  substep_inertia(S, 0, S.nrods);
   for (int i = 0; i < S.P; ++i) {
-    if (S.has_edge(i)) {
-      R sm = R(0.5) * (S.s[i] + S.s[i + 1]);
-      R I = S.inert_base[i] * sm * sm;
-      S.I1inv[i] = R(4.0) / I; S.I3inv[i] = R(2.0) / I;
-    }
     for (int t = 0; t < 8; ++t) S.lam[size_t(i) * 8 + t] = R(0.0);
     S.lam_sr[i] = R(0.0);
     S.lam_sb[i] = R(0.0);
@@ -1453,12 +1458,9 @@ void orc_get_rest(void* hp, double* l0, double* lbar, double* qrest, double* dar
 void orc_project_one(void* hp, int kind, int p, double h) {
   Handle* hd = (Handle*)hp;
   Scene<double>& S = *hd->d;
+  for (int i = 0; i < S.P; ++i) S.sprev[i] = S.s[i];
+  substep_inertia(S, 0, S.nrods);     // the routine every substep's prediction uses
   for (int i = 0; i < S.P; ++i) {
-    if (S.has_edge(i)) {
-      double sm = 0.5 * (S.s[i] + S.s[i + 1]);
-      double I = S.inert_base[i] * sm * sm;
-      S.I1inv[i] = 4.0 / I; S.I3inv[i] = 2.0 / I;
-    }
     for (int t = 0; t < 8; ++t) S.lam[size_t(i) * 8 + t] = 0.0;
     S.lam_sr[i] = 0.0;
     S.lam_sb[i] = 0.0;

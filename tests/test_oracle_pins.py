@@ -522,6 +522,211 @@ def test_skin_identity_at_rest_and_rigid_motion():
     assert np.abs(out - (rest_v @ Rm.T + t)).max() < 1e-14
 
 
+def _similar_capsule_state(d, Q, sigma, t):
+    """Current state of a one-capsule scene that is the exact similarity image of its rest
+    capsule: scaled by sigma about the rest midpoint, rotated by Q, moved by t."""
+    xr = d.rest_pos
+    mr = 0.5 * (xr[0] + xr[1])
+    x = (mr + t)[None, :] + sigma * (xr - mr[None, :]) @ qmat(Q).T
+    return x, mr + t
+
+
+def test_skin_follows_a_scaled_rotated_capsule():
+    """Sec. 7.4 / eq. shapematch: a capsule that is the similarity image (scale sigma, rotation
+    Q, translation) of its rest capsule carries the mesh with it.  Its rest end points map to
+    its current end points, and a rest surface point (an end centre plus rbar along a rest
+    normal) maps to the current surface point (the end centre plus the scaled radius
+    sigma rbar along the rotated normal).  A dropped or misplaced scale moves the points
+    off the pill."""
+    d = small_scene([line(2, spacing=0.02, origin=(0.1, -0.05, 0.2), direction=(1, 2, -1))], radius=0.004)
+    o = OracleScene(d)
+    q0 = o.get_state()["q"]
+    Q = qaxis([0.3, -1.0, 0.5], 1.1)
+    sigma = 1.3
+    t = np.array([0.05, 0.02, -0.07])
+    x, _ = _similar_capsule_state(d, Q, sigma, t)
+    o.set_state(x=x, s=np.full(2, sigma), q=np.array([qmul(Q, q0[0]), qmul(Q, q0[1])]))
+    tang = d.rest_pos[1] - d.rest_pos[0]
+    nrm = np.cross(tang, [0.0, 0.0, 1.0])
+    nrm /= np.linalg.norm(nrm)
+    rest_v = np.array([d.rest_pos[0], d.rest_pos[1], d.rest_pos[0] + 0.004 * nrm, d.rest_pos[1] - 0.004 * nrm])
+    caps = np.zeros((4, 4), np.int32)
+    w = np.zeros((4, 4))
+    w[:, 0] = 1.0
+    out = o.skin(rest_v, caps, w)
+    Rq = qmat(Q)
+    expect = np.array([x[0], x[1], x[0] + sigma * 0.004 * Rq @ nrm, x[1] - sigma * 0.004 * Rq @ nrm])
+    assert np.abs(out - expect).max() < 1e-15
+    # the current end radii sigma rbar are the distances from the end centres
+    assert abs(np.linalg.norm(out[2] - x[0]) - sigma * 0.004) < 1e-16
+
+
+def test_skin_scale_is_the_midpoint_scale():
+    """The capsule's scale in the transform is the midpoint average of its two pill scales
+    (s_{j+1/2}, Sec. 4): unequal end scales skin exactly like both ends at their mean, and
+    the mean is pinned by the similarity test above."""
+    d = small_scene([line(2, spacing=0.02)], radius=0.004)
+    o = OracleScene(d)
+    q0 = o.get_state()["q"]
+    Q = qaxis([1.0, 0.2, -0.3], 0.6)
+    x, _ = _similar_capsule_state(d, Q, 1.3, np.array([0.01, 0.0, 0.03]))
+    qs = np.array([qmul(Q, q0[0]), qmul(Q, q0[1])])
+    rng = np.random.default_rng(21)
+    rest_v = d.rest_pos[0] + rng.normal(size=(20, 3)) * 0.01
+    caps = np.zeros((20, 4), np.int32)
+    w = np.zeros((20, 4))
+    w[:, 0] = 1.0
+    o.set_state(x=x, q=qs, s=np.array([1.2, 1.4]))
+    a = o.skin(rest_v, caps, w)
+    o.set_state(s=np.array([1.3, 1.3]))
+    b = o.skin(rest_v, caps, w)
+    assert np.abs(a - b).max() < 1e-15
+    o.set_state(s=np.array([1.2, 1.2]))
+    c = o.skin(rest_v, caps, w)
+    assert np.abs(a - c).max() > 1e-4
+
+
+def test_skin_blend_is_linear_in_the_four_weights():
+    """Linear blend skinning (Sec. 7.4): a vertex with four influences lands at the
+    weighted sum of where each capsule alone would carry it, for weights that differ per
+    slot (0.1, 0.2, 0.3, 0.4 over four capsules with four different transforms)."""
+    d = small_scene([line(3, spacing=0.015), line(3, spacing=0.015, origin=(0, 0.03, 0))], radius=0.004)
+    o = OracleScene(d)
+    st = o.get_state()
+    rng = np.random.default_rng(22)
+    # every pill gets its own displacement, scale and rotation: four distinct capsule transforms
+    qs = np.array([qmul(qaxis(rng.normal(size=3), rng.uniform(0.2, 1.0)), q) for q in st["q"]])
+    o.set_state(x=st["x"] + rng.normal(size=st["x"].shape) * 0.01, q=qs, s=rng.uniform(0.8, 1.3, d.num_pills))
+    caps4 = np.array([0, 1, 3, 4], np.int32)
+    V = 16
+    rest_v = rng.normal(size=(V, 3)) * 0.02
+    wts = np.array([0.1, 0.2, 0.3, 0.4])
+    out = o.skin(rest_v, np.tile(caps4, (V, 1)), np.tile(wts, (V, 1)))
+    single = []
+    for c in caps4:
+        w1 = np.zeros((V, 4))
+        w1[:, 0] = 1.0
+        single.append(o.skin(rest_v, np.full((V, 4), c, np.int32), w1))
+    expect = sum(wt * sg for wt, sg in zip(wts, single))
+    assert np.abs(out - expect).max() < 1e-15
+    # and the four transforms really differ
+    assert min(np.abs(single[i] - single[j]).max() for i in range(4) for j in range(i + 1, 4)) > 1e-3
+
+
+# ----------------------------------------------------------------------------- pins of the substep's inertia, volume scale step and contact averaging
+
+@pytest.mark.parametrize("axis,which", [([0, 0, 1], "twist"), ([1, 0, 0], "bend")])
+def test_substep_inertia_uses_substep_start_scale(axis, which):
+    """App. B: over a substep the edge's rotational inertia is m s^2 I with
+    I = diag(pi r^4/4, pi r^4/4, pi r^4/2) and s the midpoint scale at the START of the
+    substep.  One full substep (prediction, one iteration, velocity update) of a 3-pill rod
+    with only bend-twist on, edge 0 frozen, scales that differ from one and grow during
+    the prediction (sdot != 0), and a compliant relative rotation psi about the body axis:
+    the block of that axis decouples, so
+        dl = -s1 c sin(psi/2) / ((s1 c cos(psi/2)/2)^2 / I_axis + alpha~_axis),
+        psi' = psi + 2 atan(s1 c cos(psi/2) dl / (4 I_axis)),
+    with s1 the predicted scale of pill 1, I_axis = rho l0 s_m^2 J_axis (J from disc
+    quadrature) and s_m the substep-start midpoint scale of edge 1."""
+    alpha = 3e-5
+    d = small_scene([line(3)], comp=(INF, INF, INF, alpha), gravity=(0, 0, 0))
+    o = OracleScene(d)
+    rest = o.rest()
+    o.set_masses(wsinv=np.zeros(3), inert=np.array([1e300, rest["inert"][1], 1.0]))
+    q = o.get_state()["q"].copy()
+    psi = 0.3
+    q[1] = qmul(q[0], qaxis(axis, psi))
+    s0 = np.array([1.1, 1.2, 1.3])
+    sd = np.array([0.0, 25.0, 25.0])
+    h = 2e-3
+    o.set_state(q=q, s=s0, sd=sd)
+    o.step(h, 1, 1)
+    st = o.get_state()
+    r = qmul(st["q"][0] * np.array([-1, -1, -1, 1]), st["q"][1])
+    r = r if r[3] >= 0 else -r
+    k = 2 if which == "twist" else 0
+    psi_after = 2 * math.atan2(r[k], r[3])
+    A, Ixx, Izz = disc_moments(0.005)
+    J_axis = Izz if which == "twist" else Ixx
+    c = 4 / 0.02
+    s1 = s0[1] + h * sd[1]
+    sm = 0.5 * (s0[1] + s0[2])
+    I_axis = RHO * 0.01 * sm * sm * J_axis
+    at = alpha / (J_axis * 0.01 * h * h)
+    dl = -s1 * c * math.sin(psi / 2) / ((s1 * c * math.cos(psi / 2) / 2) ** 2 / I_axis + at)
+    expect = psi + 2 * math.atan(s1 * c * math.cos(psi / 2) * dl / (4 * I_axis))
+    # the projection moves a sizeable part of psi, so every factor of the inertia shows
+    assert 0.2 * psi < psi - expect < 0.8 * psi
+    assert abs(psi_after - expect) < 1e-10 * psi
+    # the other two components of the relative rotation stay zero
+    assert np.abs(np.delete(r[:3], k)).max() < 1e-15
+
+
+def test_volume_scale_projection_is_newton_on_the_midpoint_scale():
+    """Eq. vol with positions frozen (w = 0) and zero compliance: the constraint
+    f(m) = m^2 l / l0 - 1 depends on the scales only through the midpoint m = (s0+s1)/2, so
+    one projection is a Newton step m' = m - f(m)/f'(m), with f'(m) = 2 m l / l0, split
+    between the two scales in the ratio of their inverse scale masses."""
+    d = small_scene([line(2)], comp=(INF, 0.0, INF, INF))
+    o = OracleScene(d)
+    ws = np.array([2.0, 5.0])
+    o.set_masses(winv=np.zeros(2), wsinv=ws)
+    xs = np.array([[0.0, 0.0, 0.0], [0.0121, 0.0013, -0.0007]])
+    s = np.array([1.05, 0.93])
+    o.set_state(x=xs, s=s)
+    o.project_one(1, 0, 1e-3)
+    st = o.get_state()
+    ell = np.linalg.norm(xs[1] - xs[0]) / 0.01
+    m = 0.5 * s.sum()
+    m_new = m - (m * m * ell - 1) / (2 * m * ell)
+    ds = st["s"] - s
+    assert abs(0.5 * (st["s"][0] + st["s"][1]) - m_new) < 1e-15
+    assert abs(ds[0] * ws[1] - ds[1] * ws[0]) < 1e-15
+    assert np.all(st["x"] == xs)
+
+
+def test_contacts_move_a_shared_pill_by_the_mean_correction():
+    """Sec. 7: contacts are solved in parallel (Jacobi) and the displacements acting on one
+    degree of freedom are averaged.  Capsule A is crossed by B from above and by C from
+    below; in the three-capsule scene A's pills move by the mean of the corrections each
+    contact gives alone (two-capsule scenes A+B and A+C), and B and C move as alone."""
+    A = line(2, spacing=0.01)
+    B = np.array([[0.004, 0.007, -0.005], [0.004, 0.007, 0.005]])
+    C = np.array([[0.0065, -0.008, -0.006], [0.0065, -0.008, 0.004]])
+
+    def run(rods):
+        dd = small_scene(rods, radius=0.005, gravity=(0, 0, 0))
+        oo = OracleScene(dd)
+        x0 = oo.get_state()["x"].copy()
+        oo.contact_pass()
+        st = oo.get_state()
+        return st["x"] - x0, st["s"] - 1.0, oo.active_count()
+
+    dx_ab, ds_ab, n_ab = run([A, B])
+    dx_ac, ds_ac, n_ac = run([A, C])
+    dx, ds, n = run([A, B, C])
+    assert np.all(n_ab == 1) and np.all(n_ac == 1)
+    assert list(n) == [2, 2, 1, 1, 1, 1]
+    # both contacts are real and push A in opposite directions, by different amounts
+    assert dx_ab[0, 1] < 0 < dx_ac[0, 1] and abs(dx_ab[0, 1] + dx_ac[0, 1]) > 1e-5
+    assert np.abs(dx[:2] - 0.5 * (dx_ab[:2] + dx_ac[:2])).max() < 1e-17
+    assert np.abs(ds[:2] - 0.5 * (ds_ab[:2] + ds_ac[:2])).max() < 1e-15
+    assert np.abs(dx[2:4] - dx_ab[2:4]).max() == 0 and np.abs(dx[4:6] - dx_ac[2:4]).max() == 0
+    assert np.abs(ds[2:4] - ds_ab[2:4]).max() == 0 and np.abs(ds[4:6] - ds_ac[2:4]).max() == 0
+
+
+def test_dichotomous_tie_keeps_the_upper_part():
+    """Reading of the search on a flat objective (coincident segments of zero radius: the
+    gap is exactly 0 at every alpha): every comparison ties and the tie moves the lower
+    end up, lo_k = (lo_{k-1} + 1)/2 - delta, whose closed form is
+    lo_k = (1 - 2 delta)(1 - 2^-k); the result is (lo_10 + 1)/2."""
+    a1, a2 = [0.0, 0.0, 0.0], [0.015625, 0.0, 0.0]
+    assert oracle.coll_gap(a1, 0.0, a2, 0.0, a1, 0.0, a2, 0.0, 0.3) == 0.0
+    delta = 1e-4
+    al = oracle.dichotomous(a1, 0.0, a2, 0.0, a1, 0.0, a2, 0.0, 10, delta)
+    lo = (1 - 2 * delta) * (1 - 2.0 ** -10)
+    assert abs(al - 0.5 * (lo + 1)) < 1e-15
+
+
 # ----------------------------------------------------------------------------- gradients
 
 @pytest.mark.slow
