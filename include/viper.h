@@ -189,6 +189,28 @@ viper_status viper_set_state(viper_scene scene, int32_t which, const void* src, 
  * (synchronises `stream`).  VIPER_ERR_NO_CAPACITY if n > cap (nothing written). */
 viper_status viper_get_contacts(viper_scene scene, int32_t* pairs, int32_t cap, int32_t* n, void* stream);
 
+/* Record of the last contact detection of a scene (Sec. 7.1 uniform grid).  The grid's cell
+ * width is twice the cell radius: the top of the histogram bin (4 bins per octave) that
+ * holds the 33rd-largest capsule bounding radius, so that at most 32 larger capsules exist;
+ * those are kept in a list that every capsule searches besides its 27 neighbour cells.
+ * Capsules whose bounding sphere is not finite are left out (and raise VIPER_ERR_NAN at
+ * viper_sync).  If the cell radius would exceed 8 times the largest bounding radius of the
+ * rest pose, the scene has diverged: its detection is skipped (no candidates that substep)
+ * and viper_sync reports VIPER_ERR_NAN.  So the candidate search examines at most the
+ * entries of 27 cells of width <= 16 rest radii plus 32 list entries per capsule. */
+typedef struct {
+  int64_t walk_entries;       /* bucket and list entries the candidate count pass examined */
+  int32_t oversized;          /* capsules in the oversized list */
+  int32_t nonfinite;          /* capsules left out: bounding sphere not finite */
+  int32_t skipped;            /* 1 if the detection was skipped (diverged scene) */
+  int32_t cell_bin;           /* histogram bin of the cell radius */
+  double cell_width;          /* m; 0 when skipped */
+  double cell_radius_limit;   /* m: 8 x the largest bounding radius at rest */
+} viper_contact_info;
+/* Fills *info for a scene with collisions (synchronises `stream`); VIPER_ERR_INVALID
+ * otherwise. */
+viper_status viper_contact_stats(viper_scene scene, viper_contact_info* info, void* stream);
+
 /* Linear-blend skinning (Sec. 7.4): register a mesh of V rest vertices, each with 4
  * (capsule id, weight) influences.  Device arrays, owned by the caller, read at every
  * viper_skin call: rest_v [V*3] float, caps [V*4] int32, w [V*4] float. */
@@ -226,7 +248,8 @@ viper_status viper_set_floor(viper_scene scene, const double* floor_normal, doub
 viper_status viper_set_bones(viper_scene scene, const double* transforms, void* stream);
 
 /* Wait for `stream` and report device-side conditions raised since the last sync:
- * VIPER_ERR_NAN, VIPER_ERR_CAPACITY, or VIPER_ERR_DEVICE. Clears them. */
+ * VIPER_ERR_NAN (a non-finite state, or a contact detection skipped because the scene
+ * diverged), VIPER_ERR_CAPACITY, or VIPER_ERR_DEVICE. Clears them. */
 viper_status viper_sync(viper_scene scene, void* stream);
 
 /* Release the host handle (the workspace stays the caller's). */
@@ -275,7 +298,8 @@ viper_status viper_step_backward(viper_scene scene, double dt, int32_t frames, i
  * free range or slot fits, nothing changed), stay resident on the device, and every
  * viper_pool_step advances every resident scene by one frame: all collision-free scenes
  * in one launch over a shared block table, all scenes with contacts through one shared
- * sequence of launches on a second stream that overlaps the first.  A scene admitted
+ * sequence of launches on a second stream that overlaps the first (both start after the
+ * work already on `stream`; `stream` then waits for both).  A scene admitted
  * while a step runs joins at the next step; uploads of new scenes do not touch resident
  * state.  All scenes of a pool share `precision`.  The scene handles of a pool
  * (viper_pool_scene) serve viper_get_state / viper_set_state / viper_get_contacts /
@@ -294,7 +318,17 @@ viper_status viper_pool_step(viper_pool pool, double dt, int32_t substeps, int32
  * class's last step has completed. */
 viper_status viper_pool_step_ex(viper_pool pool, double dt, int32_t substeps, int32_t iterations, int32_t classes,
                                 void* stream);
+/* Free a scene's slot and range.  Waits for the last step of the scene's class (on
+ * whichever stream it ran) before the range can be reused; `stream` is not used. */
 viper_status viper_pool_retire(viper_pool pool, int32_t slot, void* stream);
+/* Device-side condition of a resident scene as of the last step of its class: every class
+ * step ends by copying its scenes' status words to pinned host memory in stream order, so
+ * once the caller has seen that step complete (an event recorded after it, or a stream
+ * synchronisation) *scene_status holds VIPER_OK, VIPER_ERR_NAN (non-finite state or a
+ * diverged contact detection) or VIPER_ERR_CAPACITY (contact buffer overflow) for it,
+ * without a further synchronisation.  Before the scene's first completed step the value
+ * is meaningless.  The conditions stay set (viper_sync on the scene clears them). */
+viper_status viper_pool_status(viper_pool pool, int32_t slot, int32_t* scene_status);
 viper_status viper_pool_scene(viper_pool pool, int32_t slot, viper_scene* scene);
 viper_status viper_pool_info(viper_pool pool, size_t* free_bytes, size_t* largest_free, int32_t* resident,
                              int64_t* resident_pills);

@@ -13,7 +13,7 @@ namespace viper {
 // Offsets of the contact buffers inside a scene workspace.
 struct ContactOffsets {
   bool on = false;
-  size_t cap_ids, cap_rod, cap_grp, sph, maxr, key, cell, cell_cnt, cell_start, cell_cur, sorted, cgmin, cgmax;
+  size_t cap_ids, cap_rod, cap_grp, sph, hist, dcnt, walk, cw, key, cell, cell_cnt, cell_start, cell_cur, sorted, cgmin, cgmax;
   size_t pcount, poff, stage, pairs, npairs, ssph, skey, srg, acc, acnt;
   size_t xdet, sdet, bsum;
   size_t end;
@@ -27,6 +27,8 @@ viper_status contact_init(ContactDev& c, char* ws, const ContactOffsets& o, cons
                           hipStream_t st);
 hipError_t contact_copy_det(const ContactDev& c, bool x, void* dst, int P, size_t ts, hipStream_t st);
 viper_status contact_get_pairs(const ContactDev& c, int32_t* pairs, int32_t cap, int32_t* n, hipStream_t st);
+// Record of the last detection (walk length, oversized and non-finite capsules, cell width).
+viper_status contact_get_info(const ContactDev& c, viper_contact_info* out, hipStream_t st);
 // Initial skinning weights of V rest vertices at the scene's current pose (Sec. 7.4).
 template <class T>
 hipError_t launch_skin_weights(const Dev<T>& d, int V, const float* rest_v, int32_t* caps, float* w, hipStream_t st);

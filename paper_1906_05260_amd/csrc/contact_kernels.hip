@@ -3,6 +3,14 @@
 // Detection (Sec. 7.1, after Green 2010): each capsule (tapered pill primitive)
 // gets a bounding sphere; a uniform grid with cell width equal to the largest
 // sphere diameter guarantees that overlapping spheres sit in neighbouring cells.
+// The cell radius is not the single largest bounding radius: a histogram of the radii
+// sets it to the top of the bin that holds the (kOversized+1)-th largest, and the at most
+// kOversized larger capsules are kept in a short list that every capsule walks besides its
+// neighbour cells (one stretched capsule would otherwise widen every cell of its scene and
+// make the walk quadratic).  A capsule whose bounding sphere is not finite is left out and
+// raises the scene's non-finite status; a scene whose cell radius would exceed kRadLimit
+// times its largest bounding radius at rest has diverged: its detection is skipped (no
+// candidates) and its status says so.
 // Cells are hashed into a table and filled by a counting sort; every capsule then
 // counts its candidates in the 27 neighbouring cells, an exclusive scan turns the
 // counts into offsets, and a second pass emits the candidate list in parallel
@@ -22,7 +30,9 @@
 
 #include "contact.h"
 
+#include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <string>
 
 namespace viper {
@@ -195,15 +205,32 @@ __global__ void __launch_bounds__(256) scan_add_kernel(const ContactDev* __restr
 
 // ---- detection
 
+// Histogram bin of a bounding radius R (finite, m): 4 bins per octave, bin 96 starts at 1 m,
+// clamped to [0, kRadBins - 1]; bin b holds [2^((b-96)/4), 2^((b-95)/4)).
+__device__ __forceinline__ int radius_bin(double R) {
+  if (!(R > 0x1p-24)) return 0;
+  const double f = floor(4.0 * log2(R)) + 96.0;
+  return f < 0.0 ? 0 : (f > kRadBins - 1 ? kRadBins - 1 : (int)f);
+}
+
+// Upper edge of bin b (the top bin is unbounded).
+__device__ __forceinline__ double bin_top(int b) { return b >= kRadBins - 1 ? INFINITY : exp2(0.25 * (b - 95)); }
+
 // Start of detection, one launch over max(pills, cells, capsules) items of each scene:
-// copy the detection state, reset the hash buckets, and form every capsule's bounding
-// sphere with a max-reduction of the radii (the cell width of Sec. 7.1's grid).
+// copy the detection state, reset the hash buckets, form every capsule's bounding sphere
+// and histogram the radii (per block in LDS, then one global add per non-empty bin).
 template <class T>
 __global__ void __launch_bounds__(256) det_kernel(const Dev<T>* __restrict__ D, const ContactDev* __restrict__ CD,
                                                   const Blk* __restrict__ tab) {
-  __shared__ double sh[256];
+  __shared__ int sh[kRadBins + 1];
   BLOCK_SCENE(tab, D, CD)
   const int i = blk_.base + (int)threadIdx.x;
+  if (blk_.base == 0 && threadIdx.x == 0) {   // counters of this detection (last read by the previous one)
+    c.dcnt[0] = 0;
+    c.walk[0] = 0ull;
+  }
+  for (int k = (int)threadIdx.x; k <= kRadBins; k += 256) sh[k] = 0;
+  __syncthreads();
   if (i < d.P) {                       // detection state: FP64 world positions, scales
     world_pos(d, i, c.xdet + 3 * (size_t)i);
     ((T*)c.sdet)[i] = d.s[i];
@@ -214,7 +241,6 @@ __global__ void __launch_bounds__(256) det_kernel(const Dev<T>* __restrict__ D, 
     c.cgmin[i] = 0x7fffffff;
     c.cgmax[i] = -0x7fffffff - 1;
   }
-  double R = 0.0;
   if (i < c.E) {                       // bounding sphere of each capsule
     double sp[4];
     capsule_sphere(d, c.cap_ids[i], sp);
@@ -222,29 +248,65 @@ __global__ void __launch_bounds__(256) det_kernel(const Dev<T>* __restrict__ D, 
     c.sph[4 * (size_t)i + 1] = sp[1];
     c.sph[4 * (size_t)i + 2] = sp[2];
     c.sph[4 * (size_t)i + 3] = sp[3];
-    R = sp[3];
+    int bin = kRadBins;                // not finite: left out of this detection
+    if (isfinite(sp[0]) && isfinite(sp[1]) && isfinite(sp[2]) && isfinite(sp[3])) bin = radius_bin(sp[3]);
+    else c.status[ST_NAN] = 1;
+    c.key[i] = bin;
+    atomicAdd(&sh[bin], 1);
   }
-  sh[threadIdx.x] = R;
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
-    __syncthreads();
-  }
-  // maxr is zero here: set at scene set-up, cleared again by the end of every detection
-  if (threadIdx.x == 0) atomicMax(c.maxr, (unsigned long long)__double_as_longlong(sh[0]));
+  for (int k = (int)threadIdx.x; k <= kRadBins; k += 256)
+    if (sh[k]) atomicAdd(&c.hist[k], sh[k]);
 }
 
-__device__ __forceinline__ double cell_width(const ContactDev& c) {
-  const double R = __longlong_as_double((long long)c.maxr[0]);
-  return (R > 0.0) ? 2.0 * R * (1.0 + 1e-6) : 1.0;
+// Cell radius from the histogram: the top of the bin holding the (kOversized+1)-th largest
+// radius (bins above it hold at most kOversized capsules).  Returns that bin.
+__device__ int cell_bin(const int* h) {
+  int above = 0, b = kRadBins - 1;
+  while (b > 0 && above + h[b] <= kOversized) above += h[b--];
+  return b;
 }
 
+// Cell keys: a capsule in a bin up to the cell bin goes to its grid cell, a larger one to the
+// oversized list, a non-finite one (or every capsule of a skipped scene) nowhere; the
+// candidate counts of capsules that are not placed are cleared here, since no search
+// thread visits them.
 __global__ void __launch_bounds__(256) key_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
+  __shared__ int sh[kRadBins + 1];
+  __shared__ int s_bin;
   const Blk b = tab[blockIdx.x];
   const ContactDev& c = CD[b.scene];
+  for (int k = (int)threadIdx.x; k <= kRadBins; k += 256) sh[k] = c.hist[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int cb = cell_bin(sh);
+    s_bin = cb;
+    if (b.base == 0) {                 // the detection's record, read back by viper_contact_stats
+      const bool skip = !(bin_top(cb) <= c.rlim);
+      c.dcnt[1] = skip;
+      c.dcnt[2] = sh[kRadBins];
+      c.dcnt[3] = cb;
+      c.cw[0] = skip ? 0.0 : 2.0 * bin_top(cb) * (1.0 + 1e-6);
+      if (skip) c.status[ST_DIVERGED] = 1;
+    }
+  }
+  __syncthreads();
   const int i = b.base + (int)threadIdx.x;
   if (i >= c.E) return;
-  const double cw = cell_width(c);
+  const int cb = s_bin;
+  const double rc = bin_top(cb);
+  const int bin = c.key[i];
+  if (!(rc <= c.rlim) || bin == kRadBins) {
+    c.key[i] = -1;
+#pragma unroll
+    for (int k = 0; k < kSearchSub; ++k) c.pcount[kSearchSub * (size_t)i + k] = 0;
+    return;
+  }
+  if (bin > cb) {                      // oversized: position in the list after the grid's entries
+    c.key[i] = -2 - atomicAdd(&c.dcnt[0], 1);
+    return;
+  }
+  const double cw = 2.0 * rc * (1.0 + 1e-6);
   const int cx = cell_of(c.sph[4 * (size_t)i], cw), cy = cell_of(c.sph[4 * (size_t)i + 1], cw),
             cz = cell_of(c.sph[4 * (size_t)i + 2], cw);
   c.cell[3 * (size_t)i] = cx; c.cell[3 * (size_t)i + 1] = cy; c.cell[3 * (size_t)i + 2] = cz;
@@ -268,12 +330,15 @@ __global__ void __launch_bounds__(256) bucket_scatter_kernel(const ContactDev* _
   const int i = b.base + (int)threadIdx.x;
   if (i >= c.E) return;
   const int h = c.key[i];
-  const int pos = c.cell_start[h] + atomicAdd(&c.cell_cur[h], 1);
-  // the capsule's search data goes straight to its bucket slot: sphere, exact cell, rod, group
+  if (h == -1) return;                 // not placed in this detection
+  // grid capsules go to their bucket, oversized ones after every bucket (cell_start[T] is the
+  // number of grid capsules)
+  const int pos = h >= 0 ? c.cell_start[h] + atomicAdd(&c.cell_cur[h], 1) : c.cell_start[c.T] + (-2 - h);
+  // the capsule's search data goes straight to its slot: sphere, exact cell, rod, group
   c.sorted[pos] = i;
 #pragma unroll
   for (int k = 0; k < 4; ++k) c.ssph[4 * (size_t)pos + k] = c.sph[4 * (size_t)i + k];
-  c.skey[pos] = pack_cell(c.cell[3 * (size_t)i], c.cell[3 * (size_t)i + 1], c.cell[3 * (size_t)i + 2]);
+  c.skey[pos] = h >= 0 ? pack_cell(c.cell[3 * (size_t)i], c.cell[3 * (size_t)i + 1], c.cell[3 * (size_t)i + 2]) : -1ll;
   c.srg[2 * (size_t)pos] = c.cap_rod[i];
   c.srg[2 * (size_t)pos + 1] = c.cap_grp[i];
 }
@@ -286,17 +351,22 @@ __global__ void __launch_bounds__(256) bucket_scatter_kernel(const ContactDev* _
 // gives every thread its output offset.  The count pass keeps a column's first 4
 // candidates, so the emit pass re-walks only the columns that had more.  After the emit
 // pass the capsule's first thread sorts the capsule's segment by b and stores capsule ids.  A bucket whose entries all
-// share the capsule's collision group (the interior of a muscle) is skipped unread.
+// share the capsule's collision group (the interior of a muscle) is skipped unread.  The
+// centre column also walks the oversized list: a grid capsule takes every oversized
+// candidate (whichever index is lower: the oversized capsule walks no cells), an oversized
+// capsule the oversized candidates above it; a pair is stored as (lower, higher) capsule id.
 template <bool EMIT>
 __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
   const Blk blk = tab[blockIdx.x];
   const ContactDev& c = CD[blk.scene];
-  if (EMIT && blk.base == 0 && threadIdx.x == 0) {
-    // the scene's pair count and overflow flag; the largest radius has had its last reader
-    const int total = c.poff[kSearchSub * (size_t)c.E];
-    c.npairs[0] = min(total, c.cap);
-    if (total > c.cap) c.status[ST_OVERFLOW] = 1;
-    c.maxr[0] = 0ull;
+  if (EMIT && blk.base == 0) {
+    // the scene's pair count and overflow flag; the radius histogram has had its last reader
+    if (threadIdx.x == 0) {
+      const int total = c.poff[kSearchSub * (size_t)c.E];
+      c.npairs[0] = min(total, c.cap);
+      if (total > c.cap) c.status[ST_OVERFLOW] = 1;
+    }
+    for (int k = (int)threadIdx.x; k <= kRadBins; k += 256) c.hist[k] = 0;
   }
   // Each wavefront holds 7 whole capsules x 9 columns (lane 63 idles): a capsule's columns
   // and the balanced walk below stay inside one wavefront.  Wavefront w of the scene takes
@@ -306,7 +376,9 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
   const int q = wv * kCapsPerWave + lane / kSearchSub, sub = lane % kSearchSub;
   const int nwave = kWaves * ((c.E + kSearchCaps - 1) / kSearchCaps);
   const int jh = blk.base / kCapsPerWave + wv + nwave * (lane / kSearchSub);   // home capsule's bucket position
-  const bool live = lane < kCapsPerWave * kSearchSub && jh < c.E;
+  const int ngrid = c.cell_start[c.T];                 // grid capsules; the oversized list follows
+  const int nplaced = ngrid + c.dcnt[0];
+  const bool live = lane < kCapsPerWave * kSearchSub && jh < nplaced;
   int a = 0, have = 0;
   if (live) {
     a = c.sorted[jh];
@@ -325,36 +397,42 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
   // share the capsule's group is left out) ...
   __shared__ int s_off[kWaves][65];
   __shared__ int s_cnt[kWaves][64];
-  __shared__ int s_col[kWaves][64][12];   // js0 js1 js2, cum1 cum2, cx ny nz, a ra ga, out
+  __shared__ int s_col[kWaves][64][15];   // js0..js3, cum1 cum2 cum3, cx ny nz, a ra ga, out, oversized home
   __shared__ double s_sph[kWaves][64][4];
   int w = 0;
   {
-    int js[3] = {0, 0, 0}, ln[3] = {0, 0, 0}, cx = 0, ny = 0, nz = 0, ra = 0, ga = 0;
+    int js[4] = {0, 0, 0, 0}, ln[4] = {0, 0, 0, 0}, cx = 0, ny = 0, nz = 0, ra = 0, ga = 0;
+    const bool over = jh >= ngrid;
     double sa[4] = {0.0, 0.0, 0.0, 0.0};
     if (live && (!EMIT || have > kStage)) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) sa[k] = c.ssph[4 * (size_t)jh + k];
       ra = c.srg[2 * (size_t)jh]; ga = c.srg[2 * (size_t)jh + 1];
-      cx = c.cell[3 * (size_t)a];
-      ny = c.cell[3 * (size_t)a + 1] + sub % 3 - 1;
-      nz = c.cell[3 * (size_t)a + 2] + sub / 3 - 1;
-      uint32_t hc[3];
-      int gmn[3], gmx[3], je[3];
+      if (!over) {
+        cx = c.cell[3 * (size_t)a];
+        ny = c.cell[3 * (size_t)a + 1] + sub % 3 - 1;
+        nz = c.cell[3 * (size_t)a + 2] + sub / 3 - 1;
+        uint32_t hc[3];
+        int gmn[3], gmx[3], je[3];
 #pragma unroll
-      for (int d = 0; d < 3; ++d) hc[d] = cell_hash(cx + d - 1, ny, nz, c.T);
+        for (int d = 0; d < 3; ++d) hc[d] = cell_hash(cx + d - 1, ny, nz, c.T);
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        gmn[d] = c.cgmin[hc[d]]; gmx[d] = c.cgmax[hc[d]];
-        js[d] = c.cell_start[hc[d]]; je[d] = c.cell_start[hc[d] + 1];
+        for (int d = 0; d < 3; ++d) {
+          gmn[d] = c.cgmin[hc[d]]; gmx[d] = c.cgmax[hc[d]];
+          js[d] = c.cell_start[hc[d]]; je[d] = c.cell_start[hc[d] + 1];
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) ln[d] = (gmn[d] == ga && gmx[d] == ga) ? 0 : je[d] - js[d];
       }
-#pragma unroll
-      for (int d = 0; d < 3; ++d) ln[d] = (gmn[d] == ga && gmx[d] == ga) ? 0 : je[d] - js[d];
+      if (sub == kSearchSub / 2) { js[3] = ngrid; ln[3] = nplaced - ngrid; }
     }
-    w = ln[0] + ln[1] + ln[2];
+    w = ln[0] + ln[1] + ln[2] + ln[3];
     int* sc = s_col[wv][lane];
-    sc[0] = js[0]; sc[1] = js[1]; sc[2] = js[2]; sc[3] = ln[0]; sc[4] = ln[0] + ln[1];
-    sc[5] = cx; sc[6] = ny; sc[7] = nz; sc[8] = a; sc[9] = ra; sc[10] = ga;
-    sc[11] = EMIT ? (live ? c.poff[col] : 0) : col;
+    sc[0] = js[0]; sc[1] = js[1]; sc[2] = js[2]; sc[3] = js[3];
+    sc[4] = ln[0]; sc[5] = ln[0] + ln[1]; sc[6] = ln[0] + ln[1] + ln[2];
+    sc[7] = cx; sc[8] = ny; sc[9] = nz; sc[10] = a; sc[11] = ra; sc[12] = ga;
+    sc[13] = EMIT ? (live ? c.poff[col] : 0) : col;
+    sc[14] = over;
 #pragma unroll
     for (int k = 0; k < 4; ++k) s_sph[wv][lane][k] = sa[k];
     s_cnt[wv][lane] = 0;
@@ -372,6 +450,7 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
   if (lane == 63) s_off[wv][64] = incl;
   __syncthreads();
   const int W = s_off[wv][64];
+  if (!EMIT && lane == 0 && W > 0) atomicAdd(c.walk, (unsigned long long)W);
   for (int g0 = 0; g0 < W; g0 += 64 * kWalkItems) {
     int own[kWalkItems], jj[kWalkItems], dd[kWalkItems], bb[kWalkItems], rr[kWalkItems], gg[kWalkItems];
     long long kk[kWalkItems];
@@ -387,8 +466,8 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
       const int* sc = s_col[wv][lo];
       const int k = g - s_off[wv][lo];
       own[u] = g < W ? lo : -1;
-      dd[u] = k < sc[3] ? 0 : (k < sc[4] ? 1 : 2);
-      jj[u] = dd[u] == 0 ? sc[0] + k : (dd[u] == 1 ? sc[1] + k - sc[3] : sc[2] + k - sc[4]);
+      dd[u] = k < sc[4] ? 0 : (k < sc[5] ? 1 : (k < sc[6] ? 2 : 3));
+      jj[u] = sc[dd[u]] + k - (dd[u] == 0 ? 0 : sc[3 + dd[u]]);
       if (g >= W) jj[u] = 0;          // past the end: a harmless in-bounds read, masked below
     }
 #pragma unroll
@@ -407,17 +486,21 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
       if (o < 0) continue;
       const int* sc = s_col[wv][o];
       const int b = bb[u];
-      if (b <= sc[8]) continue;
-      if (kk[u] != pack_cell(sc[5] + dd[u] - 1, sc[6], sc[7])) continue;   // another cell (hash collision)
-      if (rr[u] == sc[9] || gg[u] == sc[10]) continue;
+      if (dd[u] < 3) {
+        if (b <= sc[10]) continue;
+        if (kk[u] != pack_cell(sc[7] + dd[u] - 1, sc[8], sc[9])) continue;   // another cell (hash collision)
+      } else if (b == sc[10] || (sc[14] && b < sc[10])) {
+        continue;                                          // oversized list: see above
+      }
+      if (rr[u] == sc[11] || gg[u] == sc[12]) continue;
       const double sb[4] = {s01[u].x, s01[u].y, s23[u].x, s23[u].y};
       if (!spheres_overlap(s_sph[wv][o], sb)) continue;
       const int pos = atomicAdd(&s_cnt[wv][o], 1);
       if (EMIT) {
-        const int idx = sc[11] + pos;
+        const int idx = sc[13] + pos;
         if (idx < c.cap) c.pairs[2 * (size_t)idx + 1] = b;   // capsule index for now
       } else if (pos < kStage) {
-        c.stage[(size_t)kStage * sc[11] + pos] = b;
+        c.stage[(size_t)kStage * sc[13] + pos] = b;
       }
     }
   }
@@ -446,8 +529,9 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
       const int v = seg[q][i];
       int r = 0;
       for (int k = 0; k < n; ++k) r += seg[q][k] < v;
-      c.pairs[2 * (size_t)(s0 + r)] = ida;
-      c.pairs[2 * (size_t)(s0 + r) + 1] = c.cap_ids[v];
+      const int idb = c.cap_ids[v];
+      c.pairs[2 * (size_t)(s0 + r)] = min(ida, idb);
+      c.pairs[2 * (size_t)(s0 + r) + 1] = max(ida, idb);
     }
     return;
   }
@@ -464,8 +548,9 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
     c.pairs[2 * (size_t)(j + 1) + 1] = v;
   }
   for (int i = s0; i < s1; ++i) {
-    c.pairs[2 * (size_t)i] = ida;
-    c.pairs[2 * (size_t)i + 1] = c.cap_ids[c.pairs[2 * (size_t)i + 1]];
+    const int idb = c.cap_ids[c.pairs[2 * (size_t)i + 1]];
+    c.pairs[2 * (size_t)i] = min(ida, idb);
+    c.pairs[2 * (size_t)i + 1] = max(ida, idb);
   }
 }
 
@@ -676,7 +761,10 @@ ContactOffsets contact_layout(size_t start, bool on, int P, int E, int cpc, bool
   o.cap_rod = take(4 * (size_t)E);
   o.cap_grp = take(4 * (size_t)E);
   o.sph = take(8 * 4 * (size_t)E);
-  o.maxr = take(8);
+  o.hist = take(4 * (size_t)(kRadBins + 1));
+  o.dcnt = take(4 * 4);
+  o.walk = take(8);
+  o.cw = take(8);
   o.key = take(4 * (size_t)E);
   o.cell = take(12 * (size_t)E);
   o.cell_cnt = take(4 * (size_t)T);
@@ -716,8 +804,16 @@ viper_status contact_init(ContactDev& c, char* ws, const ContactOffsets& o, cons
   const int R = (int)off.size() - 1;
   c.P = off[R];
   std::vector<int32_t> ids, rod, grp;
+  double rmax = 0.0;                   // largest bounding radius at rest
   for (int k = 0; k < R; ++k)
-    for (int p = off[k]; p + 1 < off[k + 1]; ++p) { ids.push_back(p); rod.push_back(k); grp.push_back(group[k]); }
+    for (int p = off[k]; p + 1 < off[k + 1]; ++p) {
+      ids.push_back(p); rod.push_back(k); grp.push_back(group[k]);
+      const double* x0 = d->rest_pos + 3 * (size_t)p;
+      const double dx = x0[3] - x0[0], dy = x0[4] - x0[1], dz = x0[5] - x0[2];
+      const double R0 = 0.5 * std::sqrt(dx * dx + dy * dy + dz * dz) + std::max(d->rest_radius[p], d->rest_radius[p + 1]);
+      rmax = std::max(rmax, R0);
+    }
+  c.rlim = kRadLimit * rmax;
   c.E = (int)ids.size();
   c.T = contact_table_size(c.E);
   const int cpc = d->contact_capacity_per_capsule > 0 ? d->contact_capacity_per_capsule : 16;
@@ -726,7 +822,10 @@ viper_status contact_init(ContactDev& c, char* ws, const ContactOffsets& o, cons
   c.cap_rod = (int32_t*)(ws + o.cap_rod);
   c.cap_grp = (int32_t*)(ws + o.cap_grp);
   c.sph = (double*)(ws + o.sph);
-  c.maxr = (unsigned long long*)(ws + o.maxr);
+  c.hist = (int32_t*)(ws + o.hist);
+  c.dcnt = (int32_t*)(ws + o.dcnt);
+  c.walk = (unsigned long long*)(ws + o.walk);
+  c.cw = (double*)(ws + o.cw);
   c.key = (int32_t*)(ws + o.key);
   c.cell = (int32_t*)(ws + o.cell);
   c.cell_cnt = (int32_t*)(ws + o.cell_cnt);
@@ -752,7 +851,10 @@ viper_status contact_init(ContactDev& c, char* ws, const ContactOffsets& o, cons
   if (hipMemcpyAsync(c.cap_ids, ids.data(), 4 * ids.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(c.cap_rod, rod.data(), 4 * rod.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(c.cap_grp, grp.data(), 4 * grp.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
-      hipMemsetAsync(c.npairs, 0, 4, st) != hipSuccess || hipMemsetAsync(c.maxr, 0, 8, st) != hipSuccess ||
+      hipMemsetAsync(c.npairs, 0, 4, st) != hipSuccess ||
+      hipMemsetAsync(c.hist, 0, 4 * (size_t)(kRadBins + 1), st) != hipSuccess ||
+      hipMemsetAsync(c.dcnt, 0, 16, st) != hipSuccess || hipMemsetAsync(c.walk, 0, 8, st) != hipSuccess ||
+      hipMemsetAsync(c.cw, 0, 8, st) != hipSuccess ||
       hipMemsetAsync(c.acc, 0, 8 * 4 * (size_t)c.P, st) != hipSuccess ||
       hipMemsetAsync(c.acnt, 0, 4 * (size_t)c.P, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
     return VIPER_ERR_DEVICE;
@@ -828,10 +930,38 @@ viper_status contact_get_pairs(const ContactDev& c, int32_t* pairs, int32_t cap,
   if (h > cap) return VIPER_ERR_NO_CAPACITY;
   if (h > 0) {
     if (!pairs) return VIPER_ERR_INVALID;
-    if (hipMemcpyAsync(pairs, c.pairs, 8 * (size_t)h, hipMemcpyDefault, st) != hipSuccess ||
+    // the device list is ordered by the emitting capsule; a pair with an oversized capsule sits
+    // in its grid partner's segment, so the canonical (a, b) order is restored here
+    std::vector<int64_t> v((size_t)h);
+    if (hipMemcpyAsync(v.data(), c.pairs, 8 * (size_t)h, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return VIPER_ERR_DEVICE;
+    std::vector<std::pair<int32_t, int32_t>> pr((size_t)h);
+    std::memcpy(pr.data(), v.data(), 8 * (size_t)h);
+    std::sort(pr.begin(), pr.end());
+    std::memcpy(v.data(), pr.data(), 8 * (size_t)h);
+    if (hipMemcpyAsync(pairs, v.data(), 8 * (size_t)h, hipMemcpyDefault, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
       return VIPER_ERR_DEVICE;
   }
+  return VIPER_OK;
+}
+
+viper_status contact_get_info(const ContactDev& c, viper_contact_info* out, hipStream_t st) {
+  int32_t cnt[4];
+  unsigned long long walk = 0;
+  double cw = 0.0;
+  if (hipMemcpyAsync(cnt, c.dcnt, 16, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(&walk, c.walk, 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(&cw, c.cw, 8, hipMemcpyDeviceToHost, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
+    return VIPER_ERR_DEVICE;
+  out->walk_entries = (int64_t)walk;
+  out->oversized = cnt[0];
+  out->skipped = cnt[1];
+  out->nonfinite = cnt[2];
+  out->cell_bin = cnt[3];
+  out->cell_width = cw;
+  out->cell_radius_limit = c.rlim;
   return VIPER_OK;
 }
 

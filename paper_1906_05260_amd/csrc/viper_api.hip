@@ -951,12 +951,23 @@ viper_status viper_sync(viper_scene S, void* stream) {
   HIP_TRY(hipMemcpyAsync(h, S->ws + S->o.status, sizeof(h), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   HIP_TRY(hipGetLastError());
-  if (h[ST_NAN] || h[ST_OVERFLOW]) {
+  if (h[ST_NAN] || h[ST_OVERFLOW] || h[ST_DIVERGED]) {
     HIP_TRY(hipMemsetAsync(S->ws + S->o.status, 0, sizeof(h), st));
     HIP_TRY(hipStreamSynchronize(st));
     if (h[ST_NAN]) return fail(VIPER_ERR_NAN, "non-finite state detected");
+    if (h[ST_DIVERGED])
+      return fail(VIPER_ERR_NAN, "the scene diverged: capsules outgrew 8x their rest bounding radius "
+                                 "(contact detection skipped)");
     return fail(VIPER_ERR_CAPACITY, "contact buffer overflow: raise contact_capacity_per_capsule");
   }
+  return VIPER_OK;
+}
+
+viper_status viper_contact_stats(viper_scene S, viper_contact_info* info, void* stream) {
+  if (!S || !info) return fail(VIPER_ERR_INVALID, "scene and info are required");
+  if (!S->collisions) return fail(VIPER_ERR_INVALID, "the scene has no contacts");
+  viper_status r = contact_get_info(S->cd, info, (hipStream_t)stream);
+  if (r != VIPER_OK) return fail(r, "could not read the detection record");
   return VIPER_OK;
 }
 
@@ -1093,6 +1104,13 @@ struct viper_pool_s {
   std::vector<char> hf, hc;              // host images of the headers
   hipStream_t aux = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t done[2] = {nullptr, nullptr};   // end of the last step of each class (any stream)
+  bool stepped[2] = {false, false};
+  // status words of each class's last step: device [2][max_scenes] (after the headers), the
+  // slot of every batch member [2][max_scenes], and the pinned host copy [2][max_scenes]
+  int32_t* dstat = nullptr;
+  int32_t* dslot = nullptr;
+  int32_t* hstat = nullptr;
 };
 
 namespace {
@@ -1118,17 +1136,25 @@ void pool_free_range(viper_pool_s* P, size_t off, size_t size) {
 // first, so that no step still reads the header being replaced.
 template <class T>
 viper_status pool_rebuild(viper_pool_s* P, bool contact, hipStream_t st) {
+  const int cls = contact ? 1 : 0;
+  if (P->stepped[cls]) HIP_TRY(hipEventSynchronize(P->done[cls]));   // its last step, on any stream
   HIP_TRY(hipStreamSynchronize(st));
   std::vector<const void*> dv;
   std::vector<ContactDev> cc;
   std::vector<Counts> vc;
-  for (const PoolSlot& sl : P->slots) {
+  std::vector<int32_t> slot_of;
+  for (int i = 0; i < (int)P->slots.size(); ++i) {
+    const PoolSlot& sl = P->slots[i];
     if (!sl.scene || (sl.scene->collisions != 0) != contact) continue;
     viper_scene_s* S = sl.scene;
     dv.push_back((const void*)&dev<T>(S));
     if (contact) cc.push_back(S->cd);
     vc.push_back(scene_counts(S));
+    slot_of.push_back(i);
   }
+  if (!slot_of.empty())
+    HIP_TRY(hipMemcpyAsync(P->dslot + (size_t)cls * P->max_scenes, slot_of.data(), 4 * slot_of.size(),
+                           hipMemcpyHostToDevice, st));
   const size_t half = P->header_cap / 2;
   if (header_bytes(vc, sizeof(Dev<T>)) > half)
     return fail(VIPER_ERR_NO_CAPACITY, "pool header region too small for the resident set");
@@ -1143,6 +1169,16 @@ viper_status pool_rebuild(viper_pool_s* P, bool contact, hipStream_t st) {
   return VIPER_OK;
 }
 
+// Status words of every scene of a batch into the class's status array, by slot.
+template <class T>
+__global__ void __launch_bounds__(256) pool_status_kernel(const Dev<T>* __restrict__ D, int n, const int32_t* __restrict__ slot,
+                                                          int32_t* __restrict__ out) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i >= n) return;
+  const int32_t* w = D[i].status;
+  out[slot[i]] = w[ST_NAN] || w[ST_DIVERGED] ? VIPER_ERR_NAN : (w[ST_OVERFLOW] ? VIPER_ERR_CAPACITY : VIPER_OK);
+}
+
 template <class T>
 viper_status pool_step_class(viper_pool_s* P, bool contact, double dt, int sub, int iters, hipStream_t st) {
   if (contact ? P->dirty_c : P->dirty_f) {
@@ -1151,18 +1187,35 @@ viper_status pool_step_class(viper_pool_s* P, bool contact, double dt, int sub, 
   }
   const BatchDev& b = contact ? P->cb : P->fb;
   if (b.nscenes == 0) return VIPER_OK;
-  return batch_step<T>(b, contact, false, dt, sub, iters, contact ? VIPER_MODE_ITERATION : VIPER_MODE_FRAME, st);
+  viper_status r =
+      batch_step<T>(b, contact, false, dt, sub, iters, contact ? VIPER_MODE_ITERATION : VIPER_MODE_FRAME, st);
+  if (r != VIPER_OK) return r;
+  // the members' conditions, to pinned host memory in stream order (read by viper_pool_status
+  // once the caller has seen this step complete)
+  const int cls = contact ? 1 : 0;
+  int32_t* ds = P->dstat + (size_t)cls * P->max_scenes;
+  hipLaunchKernelGGL(pool_status_kernel<T>, dim3((b.nscenes + 255) / 256), dim3(256), 0, st, (const Dev<T>*)b.dev,
+                     b.nscenes, P->dslot + (size_t)cls * P->max_scenes, ds);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(P->hstat + (size_t)cls * P->max_scenes, ds, 4 * (size_t)P->max_scenes, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipEventRecord(P->done[cls], st));
+  P->stepped[cls] = true;
+  return VIPER_OK;
 }
 
-// Both classes: collision-free on `st`, contacts on the pool's second stream, joined.
+// Both classes: collision-free on `st`, contacts on the pool's second stream; both start
+// after the work already on `st`, and `st` waits for both.
 template <class T>
 viper_status pool_step_t(viper_pool_s* P, double dt, int sub, int iters, hipStream_t st) {
-  viper_status r = pool_step_class<T>(P, false, dt, sub, iters, st);
-  if (r != VIPER_OK) return r;
-  if (P->dirty_c || P->cb.nscenes > 0) {
+  const bool contacts = P->dirty_c || P->cb.nscenes > 0;
+  if (contacts) {
     if (!P->aux) HIP_TRY(hipStreamCreateWithFlags(&P->aux, hipStreamNonBlocking));
     HIP_TRY(hipEventRecord(P->ev0, st));
     HIP_TRY(hipStreamWaitEvent(P->aux, P->ev0, 0));
+  }
+  viper_status r = pool_step_class<T>(P, false, dt, sub, iters, st);
+  if (r != VIPER_OK) return r;
+  if (contacts) {
     r = pool_step_class<T>(P, true, dt, sub, iters, P->aux);
     if (r != VIPER_OK) return r;
     HIP_TRY(hipEventRecord(P->ev1, P->aux));
@@ -1182,22 +1235,29 @@ viper_status viper_pool_create(void* workspace, size_t bytes, int32_t max_scenes
   if (((uintptr_t)workspace) & 255) return fail(VIPER_ERR_INVALID, "workspace must be 256-byte aligned");
   if (precision != VIPER_F32 && precision != VIPER_F64) return fail(VIPER_ERR_INVALID, "unknown precision");
   const size_t header = align256(std::max<size_t>(bytes / 64, 1u << 20) + (size_t)max_scenes * 8192);
-  if (bytes < 2 * header) return fail(VIPER_ERR_NO_CAPACITY, "pool workspace too small");
+  const size_t stat = align256(4 * 4 * (size_t)max_scenes);   // status words and member slots of both classes
+  if (bytes < 2 * (header + stat)) return fail(VIPER_ERR_NO_CAPACITY, "pool workspace too small");
   viper_pool_s* P = new viper_pool_s();
   P->ws = (char*)workspace;
   P->bytes = bytes;
   P->precision = precision;
   P->max_scenes = max_scenes;
   P->header_cap = header;
-  P->free_[header] = bytes - header;
+  P->dstat = (int32_t*)(P->ws + header);
+  P->dslot = P->dstat + 2 * (size_t)max_scenes;
+  P->free_[header + stat] = bytes - header - stat;
   P->slots.resize(max_scenes);
   // the second stream of the joint step is created at its first use (callers that step the
   // classes on their own streams never need it, and every stream takes a hardware queue)
   if (hipEventCreateWithFlags(&P->ev0, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&P->ev1, hipEventDisableTiming) != hipSuccess) {
-    delete P;
-    return fail(VIPER_ERR_DEVICE, "could not create the pool's events");
+      hipEventCreateWithFlags(&P->ev1, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&P->done[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&P->done[1], hipEventDisableTiming) != hipSuccess ||
+      hipHostMalloc((void**)&P->hstat, 4 * 2 * (size_t)max_scenes, hipHostMallocDefault) != hipSuccess) {
+    viper_pool_destroy(P);
+    return fail(VIPER_ERR_DEVICE, "could not create the pool's events and status buffer");
   }
+  std::memset(P->hstat, 0, 4 * 2 * (size_t)max_scenes);
   *out = P;
   return VIPER_OK;
 }
@@ -1270,15 +1330,25 @@ viper_status viper_pool_step_ex(viper_pool P, double dt, int32_t substeps, int32
 }
 
 viper_status viper_pool_retire(viper_pool P, int32_t slot, void* stream) {
+  (void)stream;
   if (!P || slot < 0 || slot >= P->max_scenes || !P->slots[slot].scene) return fail(VIPER_ERR_INVALID, "bad slot");
-  // the range may be reused by the next admission: let the device finish with it first
-  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
-  if (P->aux) HIP_TRY(hipStreamSynchronize(P->aux));
+  // the range may be reused by the next admission: let the device finish with it first (the
+  // scene's class's last step, on whichever stream it ran)
+  const int cls = P->slots[slot].scene->collisions ? 1 : 0;
+  if (P->stepped[cls]) HIP_TRY(hipEventSynchronize(P->done[cls]));
   PoolSlot& sl = P->slots[slot];
   (sl.scene->collisions ? P->dirty_c : P->dirty_f) = true;
   delete sl.scene;
   pool_free_range(P, sl.off, sl.size);
   sl = PoolSlot();
+  return VIPER_OK;
+}
+
+viper_status viper_pool_status(viper_pool P, int32_t slot, int32_t* scene_status) {
+  if (!P || !scene_status || slot < 0 || slot >= P->max_scenes || !P->slots[slot].scene)
+    return fail(VIPER_ERR_INVALID, "bad slot");
+  const int cls = P->slots[slot].scene->collisions ? 1 : 0;
+  *scene_status = ((volatile int32_t*)P->hstat)[(size_t)cls * P->max_scenes + slot];
   return VIPER_OK;
 }
 
@@ -1307,7 +1377,13 @@ viper_status viper_pool_info(viper_pool P, size_t* free_bytes, size_t* largest_f
 viper_status viper_pool_destroy(viper_pool P) {
   if (!P) return VIPER_OK;
   if (P->aux) (void)hipStreamSynchronize(P->aux);
+  for (int c = 0; c < 2; ++c)     // the classes' last steps (and their status copies) first
+    if (P->done[c]) {
+      if (P->stepped[c]) (void)hipEventSynchronize(P->done[c]);
+      (void)hipEventDestroy(P->done[c]);
+    }
   for (auto& sl : P->slots) delete sl.scene;
+  if (P->hstat) (void)hipHostFree(P->hstat);
   if (P->ev0) (void)hipEventDestroy(P->ev0);
   if (P->ev1) (void)hipEventDestroy(P->ev1);
   if (P->aux) (void)hipStreamDestroy(P->aux);

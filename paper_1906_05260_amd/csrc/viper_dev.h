@@ -25,7 +25,10 @@ enum : uint32_t {
   F_VB = 8192u    // volume-bending coupling at the vertex after the slot's edge (optional)
 };
 
-enum { ST_NAN = 0, ST_OVERFLOW = 1, ST_WORDS = 4 };
+// Status words of a scene, set by kernels and read by viper_sync: a non-finite state, a full
+// contact-pair buffer, and a contact detection skipped because the scene's capsules outgrew
+// the grid's limit (a diverged scene).
+enum { ST_NAN = 0, ST_OVERFLOW = 1, ST_DIVERGED = 2, ST_WORDS = 4 };
 
 template <class T>
 struct Dev {
@@ -71,6 +74,10 @@ struct Dev {
 };
 constexpr int kSecFit = 20;
 
+constexpr int kRadBins = 128;     // bounding-radius histogram: 4 bins per octave, bin 96 starts at 1 m
+constexpr int kOversized = 32;    // at most this many capsules are larger than the cell radius
+constexpr double kRadLimit = 8.0; // cell radius limit, in units of the largest bounding radius at rest
+
 // Contact buffers of one scene (device pointers into its workspace).
 struct ContactDev {
   int P = 0, E = 0, T = 0, cap = 0;   // pills, capsules, hash-table size, pair capacity
@@ -78,8 +85,15 @@ struct ContactDev {
   double delta = 1e-4;
   int32_t *cap_ids = nullptr, *cap_rod = nullptr, *cap_grp = nullptr;
   double* sph = nullptr;              // [E*4] mx my mz R
-  unsigned long long* maxr = nullptr; // bits of the largest sphere radius
-  int32_t *key = nullptr, *cell = nullptr;  // [E] hash keys, [3E] integer cell coordinates
+  // Grid sizing: a histogram of the bounding radii (kRadBins log-spaced bins, then one count of
+  // capsules whose sphere is not finite) sets the cell radius to the top of the bin holding
+  // the (kOversized+1)-th largest radius; larger capsules are walked from a list instead.
+  int32_t* hist = nullptr;            // [kRadBins + 1]
+  int32_t* dcnt = nullptr;            // [4] oversized, skipped, non-finite, cell-radius bin (last detection)
+  unsigned long long* walk = nullptr; // bucket entries examined by the last candidate count pass
+  double* cw = nullptr;               // cell width of the last detection (0 when skipped)
+  double rlim = 0.0;                  // largest admitted cell radius (8x the largest at rest)
+  int32_t *key = nullptr, *cell = nullptr;  // [E] radius bin, then hash key; [3E] integer cell coordinates
   int32_t *cell_cnt = nullptr, *cell_start = nullptr, *cell_cur = nullptr, *sorted = nullptr;
   int32_t *cgmin = nullptr, *cgmax = nullptr;  // [T] smallest / largest group id in each bucket
   int32_t *pcount = nullptr, *poff = nullptr;  // [9E], [9E+1] candidates per (capsule, column)

@@ -368,19 +368,54 @@ def scene_of_size(n_pills: int, kind: str, seed: int):
     return desc, mesh
 
 
+def capsule_mesh(desc: SceneDesc, per_pill=4, seed=0, offset=0.004) -> SkinMesh:
+    """A skinning mesh of ``per_pill`` vertices per pill, built without a nearest-capsule
+    search (the serving workload's meshes): the vertices of a pill sit ``offset`` outside the
+    surface of its capsule (a rod's last pill uses its incoming capsule), at a uniform point
+    along it and a uniform angle around it; the influences are that capsule and its
+    neighbours along the rod (the capsule itself again past a rod end), with
+    Dirichlet(1,1,1,1) weights."""
+    rng = np.random.default_rng(seed)
+    offs = np.asarray(desc.rod_offsets)
+    P = desc.num_pills
+    rod = np.repeat(np.arange(desc.num_rods), np.diff(offs))
+    first, last = offs[rod], offs[rod + 1] - 1
+    cap = np.where(np.arange(P) < last, np.arange(P), np.arange(P) - 1)      # capsule of each pill
+    prev_c = np.where(cap > first, cap - 1, cap)
+    next_c = np.where(cap + 1 < last, cap + 1, cap)
+    c = np.repeat(cap, per_pill)
+    infl = np.stack([c, np.repeat(prev_c, per_pill), np.repeat(next_c, per_pill), c], axis=1)
+    a, b = desc.rest_pos[c], desc.rest_pos[c + 1]
+    ra, rb = desc.rest_radius[c], desc.rest_radius[c + 1]
+    V = c.shape[0]
+    t = rng.uniform(0.0, 1.0, V)
+    th = rng.uniform(0.0, 2 * np.pi, V)
+    axis = b - a
+    axis /= np.linalg.norm(axis, axis=1, keepdims=True)
+    helper = np.where(np.abs(axis[:, 1:2]) < 0.9, [[0.0, 1.0, 0.0]], [[1.0, 0.0, 0.0]])
+    e1 = np.cross(axis, helper)
+    e1 /= np.linalg.norm(e1, axis=1, keepdims=True)
+    e2 = np.cross(axis, e1)
+    r = (1 - t) * ra + t * rb + offset
+    p = a + t[:, None] * (b - a) + r[:, None] * (np.cos(th)[:, None] * e1 + np.sin(th)[:, None] * e2)
+    return SkinMesh(p.astype(np.float32), infl.astype(np.int32), rng.dirichlet(np.ones(4), V).astype(np.float32))
+
+
 @dataclass
 class Request:
     arrival: float          # seconds after the start of the run
     desc: SceneDesc
     frames: int
     kind: str
+    mesh: Optional[SkinMesh] = None   # skinned after every frame (muscle requests)
 
 
 def serving_requests(rate=200.0, duration=2.0, seed=3, min_pills=1000, max_pills=200000, frames=60,
-                     kinds=("helix", "muscle")):
+                     kinds=("helix", "muscle"), skin_per_pill=4):
     """Poisson arrivals (exponential gaps of mean 1/rate) over `duration` seconds of scenes
     with log-uniform sizes in [min_pills, max_pills], kind drawn uniformly from `kinds`
-    (64-pill helix rods, or muscle bundles with contacts and no skin mesh)."""
+    (64-pill helix rods, or muscle bundles with contacts and a skinning mesh of
+    `skin_per_pill` vertices per pill, `capsule_mesh`; 0 = no mesh)."""
     rng = np.random.default_rng(seed)
     t = 0.0
     out = []
@@ -391,11 +426,14 @@ def serving_requests(rate=200.0, duration=2.0, seed=3, min_pills=1000, max_pills
             break
         n = int(np.exp(rng.uniform(np.log(min_pills), np.log(max_pills))))
         kind = kinds[int(rng.integers(len(kinds)))]
+        mesh = None
         if kind == "helix":
             desc = helix_rods(max(1, int(round(n / 64))), 64, seed=seed * 100003 + k)
         else:
             desc, _ = muscle_scene(num_muscles=max(1, int(round(n / 512))), seed=seed * 100003 + k,
                                    target_pills=None, mesh_vertices=0)
-        out.append(Request(t, desc, frames, kind))
+            if skin_per_pill:
+                mesh = capsule_mesh(desc, skin_per_pill, seed=seed * 100003 + k)
+        out.append(Request(t, desc, frames, kind, mesh))
         k += 1
     return out

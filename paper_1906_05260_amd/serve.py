@@ -9,9 +9,14 @@ footprint; their uploads run on a copy stream and they join their class's next s
 range.  The plain path serves the same requests first-come first-served, one scene at a
 time with its own launches, as a baseline.
 
+Muscle requests carry a skinning mesh; both paths skin it after every frame (Sec. 7.4),
+on the stream that stepped the scene.  Every finished class step is followed by a check of
+its scenes' device-side conditions (non-finite state, diverged contact detection, contact
+overflow): a failing scene is retired at once and reported, and its frame is not counted.
+
 Reported per run: frame latency p50/p99 (latency of frame k = completion of frame k minus
 the moment it became ready: the arrival for frame 0, the previous frame's completion
-after), time to first frame p50/p99, pill-frames/s, peak resident bytes.
+after), time to first frame p50/p99, pill-frames/s, peak resident bytes, failed requests.
 """
 from __future__ import annotations
 
@@ -52,7 +57,8 @@ def serve_batched(requests, pool_bytes, dt=1.0 / 60.0, substeps=20, iterations=8
     on a copy stream) and join their class's next step; a finished scene is retired as soon
     as its class's step completes.  `on_finish(request, scene)` (optional) is called with
     each finished scene before it is retired; `progress(msg)` (optional) receives a line
-    every 100 class steps."""
+    every 100 class steps and while a step has run for more than 5 s.  A request whose
+    footprint exceeds the whole empty pool raises RuntimeError."""
     import torch
     pool = viper.Pool(pool_bytes, max_scenes=max_scenes, precision=precision, device=device)
     copy_stream = torch.cuda.Stream(device=device)
@@ -63,7 +69,8 @@ def serve_batched(requests, pool_bytes, dt=1.0 / 60.0, substeps=20, iterations=8
     lat_cls = {1: [], 2: []}
     pending = deque(sorted(requests, key=lambda r: r.arrival))
     waiting = deque()
-    resident = {}                     # slot -> [request, frames done, t_ready, class]
+    resident = {}                     # slot -> [request, frames done, t_ready, class, skin]
+    failed = []
     lat, ttff = [], []
     pill_frames = 0
     peak_bytes = 0
@@ -82,9 +89,17 @@ def serve_batched(requests, pool_bytes, dt=1.0 / 60.0, substeps=20, iterations=8
             r = waiting[0]
             slot = pool.admit(r.desc, stream=copy_stream)
             if slot is None:
+                if not resident and all(lanes[c]["event"] is None for c in (1, 2)):
+                    raise RuntimeError("request of %d pills does not fit the empty pool (%d bytes)" %
+                                       (r.desc.num_pills, pool_bytes))
                 break
             waiting.popleft()
-            resident[slot] = [r, 0, r.arrival, 2 if r.desc.collisions else 1]
+            skin = None
+            if getattr(r, "mesh", None) is not None:
+                sc = pool.scene(slot)
+                sid = sc.create_skin(r.mesh.rest_v, r.mesh.caps, r.mesh.w, stream=copy_stream)
+                skin = (sc, sid, torch.empty((r.mesh.rest_v.shape[0], 3), dtype=torch.float32, device=device))
+            resident[slot] = [r, 0, r.arrival, 2 if r.desc.collisions else 1, skin]
         info = pool.info()
         peak_bytes = max(peak_bytes, pool_bytes - info["free_bytes"])
         host["admit_s"] += time.perf_counter() - ta
@@ -97,10 +112,15 @@ def serve_batched(requests, pool_bytes, dt=1.0 / 60.0, substeps=20, iterations=8
             return
         ts = time.perf_counter()
         pool.step(dt, substeps, iterations, stream=lane["stream"], classes=cls)
+        for k in members:                               # skinning of each stepped mesh (Sec. 7.4)
+            sk = resident[k][4]
+            if sk is not None:
+                sk[0].skin(sk[1], out=sk[2], stream=lane["stream"])
         ev = torch.cuda.Event()
         ev.record(lane["stream"])
         host["step_enqueue_s"] += time.perf_counter() - ts
         lane["event"], lane["members"] = ev, members
+        lane["t0"] = time.perf_counter()
         steps += 1
         now = time.perf_counter()
         # every 100 class steps, and at least every 5 s while steps are slow
@@ -116,6 +136,16 @@ def serve_batched(requests, pool_bytes, dt=1.0 / 60.0, substeps=20, iterations=8
         for slot in lane["members"]:
             st = resident[slot]
             r = st[0]
+            code = pool.status(slot)      # this step has completed: its status copy has landed
+            if code != viper.OK:
+                failed.append({"arrival": r.arrival, "kind": r.kind, "pills": r.desc.num_pills,
+                               "frames_done": st[1], "status": code})
+                if progress is not None:
+                    progress("batched: %s request of %d pills failed at frame %d (status %d)" %
+                             (r.kind, r.desc.num_pills, st[1], code))
+                pool.retire(slot, stream=lane["stream"])
+                del resident[slot]
+                continue
             lat.append(t_done - st[2])
             lat_cls[cls].append(t_done - st[2])
             if st[1] == 0:
@@ -147,6 +177,12 @@ def serve_batched(requests, pool_bytes, dt=1.0 / 60.0, substeps=20, iterations=8
             tw = time.perf_counter()
             time.sleep(20e-6)
             host["gpu_wait_s"] += time.perf_counter() - tw
+            if progress is not None and tw - last_report[0] > 5.0:
+                last_report[0] = tw
+                progress("batched: waiting on %s, in flight for %.1f s; %d resident, %d waiting, %d pending, "
+                         "t=%.2fs" % (", ".join("class %d (%d scenes)" % (c, len(lanes[c]["members"])) for c in busy),
+                                      max(tw - lanes[c]["t0"] for c in busy), len(resident), len(waiting),
+                                      len(pending), tw - t0))
             continue
         for c in done:
             complete(c)
@@ -160,31 +196,52 @@ def serve_batched(requests, pool_bytes, dt=1.0 / 60.0, substeps=20, iterations=8
                            "latency_ms_p99": float(np.percentile(v, 99)) if v.size else None}
     return _summary(lat, ttff, pill_frames, t_first, t_last,
                     {"path": "batched", "steps": steps, "peak_resident_bytes": int(peak_bytes),
-                     "per_class": per_class, "host_s": {k: round(v, 4) for k, v in host.items()}})
+                     "per_class": per_class, "host_s": {k: round(v, 4) for k, v in host.items()},
+                     "failed": failed})
 
 
 def serve_plain(requests, dt=1.0 / 60.0, substeps=20, iterations=8, precision="f32", device="cuda:0",
-                on_finish=None, progress=None):
-    """First-come first-served, one scene at a time, one viper_step per frame."""
+                on_finish=None, progress=None, time_limit=None):
+    """First-come first-served, one scene at a time: one viper_step per frame, then the skinning
+    of its mesh, then viper_sync (which waits for the frame and reads its status; a failing
+    scene is dropped and reported).  With `time_limit` (s of wall time) no further request is
+    started after that point; those left are reported as not served."""
     import torch
     lat, ttff = [], []
+    failed = []
     pill_frames = 0
+    reqs = sorted(requests, key=lambda r: r.arrival)
+    served = 0
     t0 = time.perf_counter()
-    for r in sorted(requests, key=lambda r: r.arrival):
+    for r in reqs:
         now = time.perf_counter() - t0
+        if time_limit is not None and now > time_limit:
+            break
         if now < r.arrival:
             time.sleep(r.arrival - now)
         sc = viper.Scene(r.desc, precision, device=device)
+        skin = None
+        if getattr(r, "mesh", None) is not None:
+            sid = sc.create_skin(r.mesh.rest_v, r.mesh.caps, r.mesh.w)
+            skin = (sid, torch.empty((r.mesh.rest_v.shape[0], 3), dtype=torch.float32, device=device))
         t_ready = r.arrival
         for k in range(r.frames):
             sc.step(dt, substeps, iterations)
-            torch.cuda.synchronize(device)
+            if skin is not None:
+                sc.skin(skin[0], out=skin[1])
+            try:
+                sc.sync()
+            except viper.ViperError as e:
+                failed.append({"arrival": r.arrival, "kind": r.kind, "pills": r.desc.num_pills, "frames_done": k,
+                               "status": e.status})
+                break
             t_done = time.perf_counter() - t0
             lat.append(t_done - t_ready)
             if k == 0:
                 ttff.append(t_done - r.arrival)
             t_ready = t_done
             pill_frames += r.desc.num_pills
+        served += 1
         if on_finish is not None:
             on_finish(r, sc)
         del sc
@@ -192,4 +249,6 @@ def serve_plain(requests, dt=1.0 / 60.0, substeps=20, iterations=8, precision="f
             progress("plain: request done (%d pills), t=%.2fs" % (r.desc.num_pills, time.perf_counter() - t0))
     t_last = time.perf_counter() - t0
     t_first = min(r.arrival for r in requests) if requests else 0.0
-    return _summary(lat, ttff, pill_frames, t_first, t_last, {"path": "plain"})
+    return _summary(lat, ttff, pill_frames, t_first, t_last,
+                    {"path": "plain", "failed": failed, "requests_served": served,
+                     "requests_not_served": len(reqs) - served})

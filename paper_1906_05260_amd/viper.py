@@ -33,7 +33,7 @@ ABI_SYMBOLS = [
     "viper_pool_create", "viper_pool_admit", "viper_pool_step", "viper_pool_retire", "viper_pool_scene",
     "viper_pool_info", "viper_pool_destroy",
     "viper_adjoint_sizes", "viper_step_checkpointed", "viper_step_backward", "viper_pool_step_ex",
-    "viper_skin_weights", "viper_set_bones", "viper_set_floor",
+    "viper_skin_weights", "viper_set_bones", "viper_set_floor", "viper_contact_stats", "viper_pool_status",
 ]
 
 
@@ -75,6 +75,19 @@ class SceneDescC(ctypes.Structure):
     ]
 
 
+class ContactInfoC(ctypes.Structure):
+    """Mirror of viper_contact_info."""
+    _fields_ = [
+        ("walk_entries", ctypes.c_int64),
+        ("oversized", ctypes.c_int32),
+        ("nonfinite", ctypes.c_int32),
+        ("skipped", ctypes.c_int32),
+        ("cell_bin", ctypes.c_int32),
+        ("cell_width", ctypes.c_double),
+        ("cell_radius_limit", ctypes.c_double),
+    ]
+
+
 _lib = None
 
 
@@ -113,6 +126,8 @@ def lib():
         L.viper_adjoint_sizes.argtypes = [P, I32, I32, I32, ctypes.POINTER(SZ), ctypes.POINTER(SZ)]
         L.viper_step_checkpointed.argtypes = [P, D, I32, I32, I32, P, SZ, P]
         L.viper_step_backward.argtypes = [P, D, I32, I32, I32, P, P, P, SZ, P, P, P]
+        L.viper_contact_stats.argtypes = [P, ctypes.POINTER(ContactInfoC), P]
+        L.viper_pool_status.argtypes = [P, I32, ctypes.POINTER(I32)]
         _lib = L
     return _lib
 
@@ -303,6 +318,13 @@ class Scene:
                                        ctypes.byref(n), _stream_ptr(stream)))
         return out[: int(n.value)].copy()
 
+    def contact_stats(self, stream=None):
+        """Record of the last contact detection (include/viper.h, viper_contact_info) as a dict
+        (synchronises)."""
+        c = ContactInfoC()
+        check(lib().viper_contact_stats(self.handle, ctypes.byref(c), _stream_ptr(stream)))
+        return {name: getattr(c, name) for name, _ in ContactInfoC._fields_}
+
     def create_skin(self, rest_v, caps, w, stream=None):
         import torch
         rv = torch.as_tensor(rest_v, dtype=torch.float32).to(self.device).contiguous()
@@ -436,6 +458,13 @@ class Pool:
     def retire(self, slot, stream=None):
         check(lib().viper_pool_retire(self.handle, int(slot), _stream_ptr(stream)))
         self.descs.pop(int(slot), None)
+
+    def status(self, slot):
+        """Condition of a resident scene as of its class's last completed step (include/viper.h,
+        viper_pool_status): OK, ERR_NAN or ERR_CAPACITY; no synchronisation."""
+        v = ctypes.c_int32(-1)
+        check(lib().viper_pool_status(self.handle, int(slot), ctypes.byref(v)))
+        return int(v.value)
 
     def scene(self, slot):
         h = ctypes.c_void_p()

@@ -200,24 +200,27 @@ def test_volume_bending_validation():
     assert ei.value.status == viper.ERR_INVALID and "volume_bending" in str(ei.value)
 
 
-def test_desc_layout_matches_header(tmp_path):
-    """The binding's mirror of viper_scene_desc has the header's size and every field at the
-    header's offset (a C program compiled here prints sizeof and offsetof)."""
+@pytest.mark.parametrize("cname,mirror", [("viper_scene_desc", "SceneDescC"), ("viper_contact_info", "ContactInfoC")])
+def test_desc_layout_matches_header(tmp_path, cname, mirror):
+    """The binding's mirrors of viper_scene_desc and viper_contact_info have the header's size
+    and every field at the header's offset (a C program compiled here prints sizeof and
+    offsetof)."""
     import shutil
     import subprocess
     if shutil.which("gcc") is None:
         pytest.skip("gcc not available")
-    fields = [f[0] for f in viper.SceneDescC._fields_]
+    M = getattr(viper, mirror)
+    fields = [f[0] for f in M._fields_]
     root = __file__.rsplit("/", 2)[0]
     src = ["#include <stdio.h>", "#include <stddef.h>", '#include "include/viper.h"', "int main(void) {",
-           '  printf("%zu\\n", sizeof(viper_scene_desc));']
-    src += ['  printf("%%zu\\n", offsetof(viper_scene_desc, %s));' % f for f in fields]
+           '  printf("%%zu\\n", sizeof(%s));' % cname]
+    src += ['  printf("%%zu\\n", offsetof(%s, %s));' % (cname, f) for f in fields]
     src += ["  return 0;", "}"]
     c = tmp_path / "layout.c"
     c.write_text("\n".join(src) + "\n")
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-I", root, str(c), "-o", str(exe)])
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
-    assert got[0] == ctypes.sizeof(viper.SceneDescC)
+    assert got[0] == ctypes.sizeof(M)
     for name, off in zip(fields, got[1:]):
-        assert getattr(viper.SceneDescC, name).offset == off, name
+        assert getattr(M, name).offset == off, name

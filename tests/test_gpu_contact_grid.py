@@ -1,0 +1,166 @@
+"""The contact grid under outliers (Sec. 7.1 detection), through the C ABI on the GPU.
+
+The grid's cell radius ignores the 32 largest capsule bounding radii (those capsules are
+searched from a list), capsules whose bounding sphere is not finite are left out, and a
+scene whose cells would exceed 8x its largest rest bounding radius is reported as diverged
+with its detection skipped.  Checked here:
+- one stretched capsule (a pill moved 1 m away): the cell width stays that of the intact
+  scene, the candidate count pass examines at most 1.5x the intact scene's entries plus one
+  list entry per capsule and oversized capsule, and the candidate set still equals the
+  oracle's brute force;
+- a non-finite pill: its capsules are left out with the same walk bound, the candidate set
+  equals the brute force (which admits no pair with a non-finite sphere), and viper_sync
+  reports VIPER_ERR_NAN; a scene that is non-finite everywhere examines nothing;
+- more than 32 stretched capsules: the detection is skipped (no candidates, nothing walked)
+  and viper_sync reports VIPER_ERR_NAN with the divergence named;
+- the serving pool's per-scene status: a failing scene is named by viper_pool_status after
+  its class step, its neighbours in the same launches are not.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from paper_1906_05260_amd import scenes, viper  # noqa: E402
+
+DT = 1 / 60
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def muscles():
+    desc, _ = scenes.muscle_scene(num_muscles=8, seed=5, target_pills=None, mesh_vertices=0)
+    return desc
+
+
+def oracle_pairs(desc, sc):
+    xd = sc.get("xdet").double().cpu().numpy()
+    sd = sc.get("sdet").double().cpu().numpy()
+    rb = desc.rest_radius.astype(np.float32).astype(np.float64) if sc.precision == viper.F32 else desc.rest_radius
+    return oracle.brute_pairs(desc, xd, sd, rb)
+
+
+def free_interior_pills(desc, n):
+    """n free pills, each the middle pill of a different rod (two capsules each)."""
+    off = np.asarray(desc.rod_offsets)
+    mid = (off[:-1] + off[1:]) // 2
+    mid = mid[~desc.pinned[mid].astype(bool)]
+    assert len(mid) >= n
+    return mid[:n]
+
+
+def warm(prec):
+    desc = muscles()
+    sc = viper.Scene(desc, prec)
+    for _ in range(2):
+        sc.step(DT, 20, 8)
+    sc.sync()
+    base = sc.contact_stats()
+    say("intact scene:", desc.num_pills, "pills", sc.capsules, "capsules", base)
+    assert base["oversized"] <= 32 and base["nonfinite"] == 0 and base["skipped"] == 0
+    assert base["walk_entries"] > 0
+    return desc, sc, base
+
+
+def substep_on(sc, x):
+    """Set the positions and run one substep without constraint iterations: the detection
+    runs on these positions advanced by one prediction."""
+    sc.set("x", torch.as_tensor(x))
+    sc.step(DT / 20, 1, 0)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_one_stretched_capsule(prec):
+    desc, sc, base = warm(prec)
+    x = sc.state()["x"]
+    p = int(free_interior_pills(desc, 1)[0])
+    x[p] += np.array([0.0, 1.0, 0.0])                 # its two capsules become ~1 m long
+    substep_on(sc, x)
+    st = sc.contact_stats()
+    say(prec, "one stretched capsule:", st)
+    assert st["skipped"] == 0 and st["nonfinite"] == 0
+    assert 2 <= st["oversized"] <= 32
+    assert st["cell_width"] <= 1.2 * base["cell_width"]
+    assert st["walk_entries"] <= 1.5 * base["walk_entries"] + st["oversized"] * sc.capsules
+    got = sc.contacts()
+    ref = oracle_pairs(desc, sc)
+    involved = int(np.isin(ref, [p - 1, p]).any(1).sum())
+    say("pairs", len(got), len(ref), "with the stretched capsules", involved)
+    assert involved > 0
+    assert np.array_equal(got, ref)
+    sc.sync()
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_nonfinite_pill_left_out(prec):
+    desc, sc, base = warm(prec)
+    x = sc.state()["x"]
+    p = int(free_interior_pills(desc, 1)[0])
+    x[p] = np.nan
+    substep_on(sc, x)
+    st = sc.contact_stats()
+    say(prec, "one non-finite pill:", st)
+    assert st["nonfinite"] == 2 and st["skipped"] == 0
+    assert st["walk_entries"] <= 1.5 * base["walk_entries"]
+    got = sc.contacts()
+    ref = oracle_pairs(desc, sc)
+    assert np.array_equal(got, ref)
+    with pytest.raises(viper.ViperError) as ei:
+        sc.sync()
+    assert ei.value.status == viper.ERR_NAN
+    # the whole scene non-finite: nothing placed, nothing walked, no candidates
+    substep_on(sc, np.full_like(x, np.nan))
+    st = sc.contact_stats()
+    say(prec, "all non-finite:", st)
+    assert st["nonfinite"] == sc.capsules and st["walk_entries"] == 0
+    assert len(sc.contacts()) == 0
+    with pytest.raises(viper.ViperError):
+        sc.sync()
+
+
+def test_diverged_scene_skips_detection():
+    desc, sc, base = warm("f32")
+    x = sc.state()["x"]
+    for p in free_interior_pills(desc, 40):           # 80 capsules of ~0.5 m bounding radius
+        x[p] += np.array([1.0, 0.0, 0.0])
+    substep_on(sc, x)
+    st = sc.contact_stats()
+    say("diverged:", st)
+    assert st["skipped"] == 1 and st["walk_entries"] == 0 and st["cell_width"] == 0.0
+    assert len(sc.contacts()) == 0
+    with pytest.raises(viper.ViperError) as ei:
+        sc.sync()
+    assert ei.value.status == viper.ERR_NAN and "diverged" in str(ei.value)
+
+
+def test_pool_status_names_the_failing_scene():
+    A = scenes.helix_rods(8, 64, seed=41)
+    B = muscles()
+    C, _ = scenes.muscle_scene(num_muscles=4, seed=42, target_pills=None, mesh_vertices=0)
+    pool = viper.Pool(256 << 20, max_scenes=4)
+    sa, sb, sc_ = pool.admit(A), pool.admit(B), pool.admit(C)
+    pool.step(DT, 20, 8)
+    torch.cuda.synchronize()
+    assert [pool.status(s) for s in (sa, sb, sc_)] == [viper.OK] * 3
+    scene_b = pool.scene(sb)
+    x = scene_b.state()["x"]
+    x[int(free_interior_pills(B, 1)[0])] = np.nan
+    scene_b.set("x", torch.as_tensor(x))
+    ev = torch.cuda.Event()
+    pool.step(DT, 20, 8)
+    ev.record()
+    ev.synchronize()
+    codes = [pool.status(s) for s in (sa, sb, sc_)]
+    say("pool statuses after a non-finite pill in the second scene:", codes)
+    assert codes == [viper.OK, viper.ERR_NAN, viper.OK]
+    pool.retire(sb)
+    pool.step(DT, 20, 8)
+    torch.cuda.synchronize()
+    assert [pool.status(s) for s in (sa, sc_)] == [viper.OK] * 2
