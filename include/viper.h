@@ -193,19 +193,21 @@ viper_status viper_get_contacts(viper_scene scene, int32_t* pairs, int32_t cap, 
  * width is twice the cell radius: the top of the histogram bin (4 bins per octave) that
  * holds the 33rd-largest capsule bounding radius, so that at most 32 larger capsules exist;
  * those are kept in a list that every capsule searches besides its 27 neighbour cells.
- * Capsules whose bounding sphere is not finite are left out (and raise VIPER_ERR_NAN at
- * viper_sync).  If the cell radius would exceed 8 times the largest bounding radius of the
- * rest pose, the scene has diverged: its detection is skipped (no candidates that substep)
- * and viper_sync reports VIPER_ERR_NAN.  So the candidate search examines at most the
- * entries of 27 cells of width <= 16 rest radii plus 32 list entries per capsule. */
+ * Capsules whose bounding sphere is not finite are left out and raise VIPER_ERR_NAN at
+ * viper_sync; capsules with an end radius s r <= 0 (no surface while a scale passes through
+ * zero) are left out too (no contact).  If the cell radius would exceed 4 times the largest
+ * bounding radius of the rest pose, the scene has diverged: its detection is skipped (no
+ * candidates that substep) and viper_sync reports VIPER_ERR_NAN.  So the candidate search
+ * examines at most the entries of 27 cells of width <= 8 rest radii plus 32 list entries
+ * per capsule. */
 typedef struct {
   int64_t walk_entries;       /* bucket and list entries the candidate count pass examined */
   int32_t oversized;          /* capsules in the oversized list */
-  int32_t nonfinite;          /* capsules left out: bounding sphere not finite */
+  int32_t excluded;           /* capsules left out: sphere not finite or an end radius <= 0 */
   int32_t skipped;            /* 1 if the detection was skipped (diverged scene) */
   int32_t cell_bin;           /* histogram bin of the cell radius */
   double cell_width;          /* m; 0 when skipped */
-  double cell_radius_limit;   /* m: 8 x the largest bounding radius at rest */
+  double cell_radius_limit;   /* m: 4 x the largest bounding radius at rest */
 } viper_contact_info;
 /* Fills *info for a scene with collisions (synchronises `stream`); VIPER_ERR_INVALID
  * otherwise. */

@@ -682,6 +682,8 @@ inline bool spheres_overlap(const Sphere& a, const Sphere& b) {
 }
 
 // Brute-force O(E^2) candidate set, sorted by (a, b), a < b; excludes same rod and same group.
+// Reading: a capsule is the swept sphere of radius s r (Sec. 7); one whose end radius is not
+// positive (a scale driven through zero) has no surface and takes no contact.
 inline void brute_pairs(int nrods, const int* off, const int* group, const double* x, const double* s, const double* rbar, std::vector<int32_t>& out) {
   out.clear();
   int P = off[nrods];
@@ -689,7 +691,11 @@ inline void brute_pairs(int nrods, const int* off, const int* group, const doubl
   for (int k = 0; k < nrods; ++k) for (int p = off[k]; p < off[k + 1]; ++p) rod_of[p] = k;
   std::vector<int> caps;
   std::vector<Sphere> sph;
-  for (int p = 0; p < P; ++p) if (p + 1 < off[rod_of[p] + 1]) { caps.push_back(p); sph.push_back(capsule_sphere(x, s, rbar, p)); }
+  for (int p = 0; p < P; ++p)
+    if (p + 1 < off[rod_of[p] + 1] && s[p] > 0.0 && s[p + 1] > 0.0) {
+      caps.push_back(p);
+      sph.push_back(capsule_sphere(x, s, rbar, p));
+    }
   for (size_t i = 0; i < caps.size(); ++i)
     for (size_t j = i + 1; j < caps.size(); ++j) {
       int a = caps[i], b = caps[j];

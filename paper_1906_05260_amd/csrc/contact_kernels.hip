@@ -8,9 +8,10 @@
 // kOversized larger capsules are kept in a short list that every capsule walks besides its
 // neighbour cells (one stretched capsule would otherwise widen every cell of its scene and
 // make the walk quadratic).  A capsule whose bounding sphere is not finite is left out and
-// raises the scene's non-finite status; a scene whose cell radius would exceed kRadLimit
-// times its largest bounding radius at rest has diverged: its detection is skipped (no
-// candidates) and its status says so.
+// raises the scene's non-finite status; one with an end radius s r <= 0 (no surface) is left
+// out too; a scene whose cell radius would exceed kRadLimit times its largest bounding
+// radius at rest has diverged: its detection is skipped (no candidates) and its status says
+// so.
 // Cells are hashed into a table and filled by a counting sort; every capsule then
 // counts its candidates in the 27 neighbouring cells, an exclusive scan turns the
 // counts into offsets, and a second pass emits the candidate list in parallel
@@ -248,9 +249,13 @@ __global__ void __launch_bounds__(256) det_kernel(const Dev<T>* __restrict__ D, 
     c.sph[4 * (size_t)i + 1] = sp[1];
     c.sph[4 * (size_t)i + 2] = sp[2];
     c.sph[4 * (size_t)i + 3] = sp[3];
-    int bin = kRadBins;                // not finite: left out of this detection
-    if (isfinite(sp[0]) && isfinite(sp[1]) && isfinite(sp[2]) && isfinite(sp[3])) bin = radius_bin(sp[3]);
-    else c.status[ST_NAN] = 1;
+    // left out of this detection: a sphere that is not finite (non-finite state, reported),
+    // or an end radius s r that is not positive (a capsule without surface while a scale
+    // passes through zero: no contact, as in the oracle's candidate set)
+    int bin = kRadBins;
+    const int p = c.cap_ids[i];
+    if (!(isfinite(sp[0]) && isfinite(sp[1]) && isfinite(sp[2]) && isfinite(sp[3]))) c.status[ST_NAN] = 1;
+    else if (d.s[p] > T(0) && d.s[p + 1] > T(0)) bin = radius_bin(sp[3]);
     c.key[i] = bin;
     atomicAdd(&sh[bin], 1);
   }
@@ -958,7 +963,7 @@ viper_status contact_get_info(const ContactDev& c, viper_contact_info* out, hipS
   out->walk_entries = (int64_t)walk;
   out->oversized = cnt[0];
   out->skipped = cnt[1];
-  out->nonfinite = cnt[2];
+  out->excluded = cnt[2];
   out->cell_bin = cnt[3];
   out->cell_width = cw;
   out->cell_radius_limit = c.rlim;

@@ -956,7 +956,7 @@ viper_status viper_sync(viper_scene S, void* stream) {
     HIP_TRY(hipStreamSynchronize(st));
     if (h[ST_NAN]) return fail(VIPER_ERR_NAN, "non-finite state detected");
     if (h[ST_DIVERGED])
-      return fail(VIPER_ERR_NAN, "the scene diverged: capsules outgrew 8x their rest bounding radius "
+      return fail(VIPER_ERR_NAN, "the scene diverged: capsules outgrew 4x their rest bounding radius "
                                  "(contact detection skipped)");
     return fail(VIPER_ERR_CAPACITY, "contact buffer overflow: raise contact_capacity_per_capsule");
   }

@@ -76,7 +76,7 @@ constexpr int kSecFit = 20;
 
 constexpr int kRadBins = 128;     // bounding-radius histogram: 4 bins per octave, bin 96 starts at 1 m
 constexpr int kOversized = 32;    // at most this many capsules are larger than the cell radius
-constexpr double kRadLimit = 8.0; // cell radius limit, in units of the largest bounding radius at rest
+constexpr double kRadLimit = 4.0; // cell radius limit, in units of the largest bounding radius at rest
 
 // Contact buffers of one scene (device pointers into its workspace).
 struct ContactDev {
@@ -92,7 +92,7 @@ struct ContactDev {
   int32_t* dcnt = nullptr;            // [4] oversized, skipped, non-finite, cell-radius bin (last detection)
   unsigned long long* walk = nullptr; // bucket entries examined by the last candidate count pass
   double* cw = nullptr;               // cell width of the last detection (0 when skipped)
-  double rlim = 0.0;                  // largest admitted cell radius (8x the largest at rest)
+  double rlim = 0.0;                  // largest admitted cell radius (4x the largest at rest)
   int32_t *key = nullptr, *cell = nullptr;  // [E] radius bin, then hash key; [3E] integer cell coordinates
   int32_t *cell_cnt = nullptr, *cell_start = nullptr, *cell_cur = nullptr, *sorted = nullptr;
   int32_t *cgmin = nullptr, *cgmax = nullptr;  // [T] smallest / largest group id in each bucket

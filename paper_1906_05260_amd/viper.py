@@ -80,7 +80,7 @@ class ContactInfoC(ctypes.Structure):
     _fields_ = [
         ("walk_entries", ctypes.c_int64),
         ("oversized", ctypes.c_int32),
-        ("nonfinite", ctypes.c_int32),
+        ("excluded", ctypes.c_int32),
         ("skipped", ctypes.c_int32),
         ("cell_bin", ctypes.c_int32),
         ("cell_width", ctypes.c_double),

@@ -473,6 +473,24 @@ def test_candidate_predicate_threshold():
     assert len(oracle.brute_pairs(d, d.rest_pos, np.ones(4), d.rest_radius)) == 0
 
 
+def test_capsule_without_positive_radius_takes_no_contact():
+    """Reading of Sec. 7: a capsule is the swept sphere of radius s r; one whose end scale is
+    driven to zero or below has no surface and is no candidate, even where its bounding
+    sphere (half length + larger end radius) still overlaps a neighbour's."""
+    base = line(2, spacing=0.01)
+    d = small_scene([base, base + np.array([0, 0.004, 0])], radius=0.003)
+    ones = np.ones(4)
+    assert len(oracle.brute_pairs(d, d.rest_pos, ones, d.rest_radius)) == 1
+    for k in range(4):
+        for v in (0.0, -0.2):
+            s = ones.copy()
+            s[k] = v
+            assert len(oracle.brute_pairs(d, d.rest_pos, s, d.rest_radius)) == 0, (k, v)
+    s = ones.copy()
+    s[1] = 1e-6                        # tiny but positive: still a candidate
+    assert len(oracle.brute_pairs(d, d.rest_pos, s, d.rest_radius)) == 1
+
+
 def test_parallel_contact_resolved_in_one_pass():
     """Two parallel capsules overlapping by a margin: with the contact parameters held
     fixed the gap is linear along the normal and in the scales, so one hard projection
