@@ -173,7 +173,11 @@ def _loss_gpu64(desc, targets):
     return float(((x[last] - targets) ** 2).sum())
 
 
-def test_adjoint_vs_finite_differences(work):
+@pytest.mark.parametrize("rel", [1e-4, 1e-3])
+def test_adjoint_vs_finite_differences(work, rel):
+    """Central differences of the loss: rel = 1e-3 is the differentiation workload's step
+    (relative for a rest radius, r (1 +- 1e-3); absolute for an activation, a +- 1e-3),
+    rel = 1e-4 a finer one (relative for both)."""
     desc, targets = work
     rods = np.arange(5, 1024, 128)
     sub = desc.subset(rods)
@@ -182,7 +186,6 @@ def test_adjoint_vs_finite_differences(work):
     _, drb32, dac32 = gpu_grad(sub, tg, "f32")
     checks = [("r", 31), ("r", 7), ("r", 32 + 20), ("r", 3 * 32 + 31), ("a", 0), ("a", 5)]
     for kind, i in checks:
-        rel = 1e-4
         dp, dm = dataclasses.replace(sub), dataclasses.replace(sub)
         if kind == "r":
             h = rel * sub.rest_radius[i]
@@ -190,7 +193,7 @@ def test_adjoint_vs_finite_differences(work):
             dm.rest_radius = sub.rest_radius.copy(); dm.rest_radius[i] -= h
             g64, g32 = drb64[i], drb32[i]
         else:
-            h = rel * sub.activation[i]
+            h = rel if rel == 1e-3 else rel * sub.activation[i]
             dp.activation = sub.activation.copy(); dp.activation[i] += h
             dm.activation = sub.activation.copy(); dm.activation[i] -= h
             g64, g32 = dac64[i], dac32[i]

@@ -133,6 +133,35 @@ def test_crowded_cell_pair_set(prec):
     assert np.array_equal(got, ref)
 
 
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-9), ("f32", 1e-4)])
+def test_full_muscle_scene_substep_parity(prec, tol):
+    """The ~45k-pill muscle workload (64 muscles, its fixed compliances) after two frames of
+    20 x 8: one h = 1/1200 substep of 8 iterations from the identical state on the GPU and in
+    the FP64 oracle; the candidate pair sets equal and every pill within tolerance (FP32:
+    the FP32 oracle's own distance from FP64 is printed beside it)."""
+    desc, _ = scenes.muscle_scene(mesh_vertices=0)
+    say("case: full muscle scene substep", prec, desc.num_pills)
+    sc = viper.Scene(desc, prec)
+    for _ in range(2):
+        sc.step(1 / 60, 20, 8)
+    st0 = sc.state()
+    sc.step(1 / 1200, 1, 8)
+    sc.sync()
+    got = sc.contacts()
+    o = oracle.OracleScene(desc, "f64")
+    o.set_state(**st0)
+    o.step(1 / 1200, 1, 8, collide=True)
+    r = o.get_state()
+    assert np.array_equal(got, o.pairs())
+    assert (o.active_count() > 0).any()
+    e = errors(desc, sc.state(), r)
+    f32 = oracle.OracleScene(desc, "f32")
+    f32.set_state(**st0)
+    f32.step(1 / 1200, 1, 8, collide=True)
+    say(prec, "errors", e, "FP32 oracle floor", errors(desc, f32.get_state(), r), "pairs", len(got))
+    assert max(e) < tol
+
+
 def test_full_muscle_scene_pair_set_and_overflow_flag():
     """The ~50k-pill muscle scene: exact candidate set after a frame; a tiny capacity
     raises the overflow status instead of writing out of bounds."""

@@ -190,6 +190,26 @@ def test_helix_4096x64_full_horizon():
     assert n_checked["f64"] >= 40 and n_checked["f32"] >= 10
 
 
+def test_helix_4096x64_every_pill_first_frame():
+    """Every one of the 262,144 pills of the 4096 x 64 helix workload after its first frame
+    (20 x 8, the benchmark's frame kernel): FP32 within 1e-4 and FP64 within 1e-9 of the FP64
+    oracle, per rod (each rod in its own anchored frame, as the GPU stores it)."""
+    import os
+    desc = scenes.helix_rods(4096, 64, seed=1)
+    sub = local_subset(desc, range(desc.num_rods))
+    o = oracle.OracleScene(sub, "f64")
+    o.step(1 / 60, 20, 8, threads=max(1, min(16, os.cpu_count() or 1)))
+    r = o.get_state()
+    for prec, tol in (("f32", TOL), ("f64", 1e-9)):
+        say("case: helix 4096x64 every pill, frame 1", prec)
+        sc = viper.Scene(desc, prec)
+        sc.step(1 / 60, 20, 8, mode=viper.MODE_FRAME)
+        sc.sync()
+        e = rod_errors(sub, sc.state(local=True), r)
+        say(prec, "largest per-rod error %.3g (rod %d), median %.3g" % (e.max(), int(np.argmax(e)), np.median(e)))
+        assert np.all(np.isfinite(e)) and e.max() < tol
+
+
 def test_helix_one_frame_parity_late_in_horizon():
     """From the GPU's own FP32 state after 50 and 99 frames (rods swinging at several
     m/s), one more frame on the GPU and on the FP64 oracle, per rod against the FP32 floor
