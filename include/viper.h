@@ -294,6 +294,18 @@ viper_status viper_step_backward(viper_scene scene, double dt, int32_t frames, i
                                  const void* ckpt, const void* dl_dx, void* work, size_t work_bytes,
                                  double* dl_drbar, double* dl_dact, void* stream);
 
+/* viper_step_backward without a work buffer, for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops, harnesses that forbid allocation): the
+ * scratch is a library-owned static device array of 80 MiB per GPU (held from the library's
+ * load until the process ends), so the call allocates nothing.  Same arguments, semantics
+ * and results as viper_step_backward otherwise.  VIPER_ERR_NO_CAPACITY (nothing enqueued)
+ * when the work bytes of viper_adjoint_sizes exceed 80 MiB (the 1024 x 32 FP32 workload at
+ * 8 iterations needs 67 MiB).  Every call on a GPU shares that GPU's array: calls that
+ * overlap on one GPU (other streams or threads) race and must be serialised by the caller. */
+viper_status viper_step_backward_static(viper_scene scene, double dt, int32_t frames, int32_t substeps,
+                                        int32_t iterations, const void* ckpt, const void* dl_dx, double* dl_drbar,
+                                        double* dl_dact, void* stream);
+
 /* ---- Serving pool: continuous batching of many scenes in one workspace ----------------
  * The pool owns no device memory either: the caller hands in one workspace.  Scenes are
  * admitted by footprint (first-fit inside the workspace; VIPER_ERR_NO_CAPACITY when no

@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1017,6 +1018,38 @@ void adjoint_bytes(viper_scene S, int32_t frames, int32_t substeps, int32_t iter
   *padj = align256(8 * P * ts);
 }
 
+viper_status backward_launch(viper_scene S, double dt, int32_t frames, int32_t substeps, int32_t iterations,
+                             const void* ckpt, const void* dl_dx, char* w, double* dl_drbar, double* dl_dact,
+                             void* stream);
+
+// Scratch of viper_step_backward_static, for callers that cannot allocate device memory: one
+// copy per GPU (each device holds it from the library's load until the process ends), shared
+// by every call on that GPU.  Host code never uses the array's name as an address: its device
+// address is looked up once per device (static_scratch) and kept.
+constexpr size_t kStaticScratchBytes = size_t(80) << 20;
+__device__ __align__(256) static char scratch[kStaticScratchBytes];
+
+std::mutex g_scratch_mu;
+std::vector<char*> g_scratch_ptr;      // device address of `scratch`, per device id
+
+// Device address of the current device's `scratch` (looked up at the first call on a device,
+// with that device current).
+viper_status static_scratch(char** out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(VIPER_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = (char*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return VIPER_OK;
+}
+
 template <class T>
 viper_status ckpt_t(viper_scene S, double h, int32_t frames, int32_t sub, int32_t iters, T* ckpt,
                            hipStream_t st) {
@@ -1064,10 +1097,40 @@ viper_status viper_step_backward(viper_scene S, double dt, int32_t frames, int32
   size_t c, sn, a, pa;
   adjoint_bytes(S, frames, substeps, iterations, &c, &sn, &a, &pa);
   if (!work || work_bytes < sn + a + pa) return fail(VIPER_ERR_INVALID, "work buffer missing or too small");
+  return backward_launch(S, dt, frames, substeps, iterations, ckpt, dl_dx, (char*)work, dl_drbar, dl_dact, stream);
+}
+
+viper_status viper_step_backward_static(viper_scene S, double dt, int32_t frames, int32_t substeps, int32_t iterations,
+                                        const void* ckpt, const void* dl_dx, double* dl_drbar, double* dl_dact,
+                                        void* stream) {
+  viper_status r = adjoint_check(S, frames, substeps, iterations);
+  if (r != VIPER_OK) return r;
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(VIPER_ERR_INVALID, "dt must be finite and > 0");
+  if (!ckpt || !dl_dx || !dl_drbar || !dl_dact) return fail(VIPER_ERR_INVALID, "ckpt, dl_dx and outputs are required");
+  size_t c, sn, a, pa;
+  adjoint_bytes(S, frames, substeps, iterations, &c, &sn, &a, &pa);
+  if (sn + a + pa > kStaticScratchBytes)
+    return fail(VIPER_ERR_NO_CAPACITY, "the backward needs " + std::to_string(sn + a + pa) +
+                                           " bytes of scratch, more than the static " +
+                                           std::to_string(kStaticScratchBytes) + "; use viper_step_backward");
+  char* w = nullptr;
+  r = static_scratch(&w);
+  if (r != VIPER_OK) return r;
+  return backward_launch(S, dt, frames, substeps, iterations, ckpt, dl_dx, w, dl_drbar, dl_dact, stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+viper_status backward_launch(viper_scene S, double dt, int32_t frames, int32_t substeps, int32_t iterations,
+                             const void* ckpt, const void* dl_dx, char* w, double* dl_drbar, double* dl_dact,
+                             void* stream) {
+  size_t c, sn, a, pa;
+  adjoint_bytes(S, frames, substeps, iterations, &c, &sn, &a, &pa);
   const double h = dt / substeps;
   const int nsub = frames * substeps;
   hipStream_t st = (hipStream_t)stream;
-  char* w = (char*)work;
   if (S->precision == VIPER_F64) {
     HIP_TRY(launch_backward<double>(S->batch, S->P, nsub, h, iterations, (const double*)ckpt, (const double*)dl_dx,
                                     (double*)w, (double*)(w + sn), (double*)(w + sn + a), S->density, dl_drbar,
@@ -1080,7 +1143,7 @@ viper_status viper_step_backward(viper_scene S, double dt, int32_t frames, int32
   return VIPER_OK;
 }
 
-}  // extern "C"
+}  // namespace
 
 // ============================================================================= serving pool
 

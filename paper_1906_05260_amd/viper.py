@@ -33,7 +33,7 @@ ABI_SYMBOLS = [
     "viper_pool_create", "viper_pool_admit", "viper_pool_step", "viper_pool_retire", "viper_pool_scene",
     "viper_pool_info", "viper_pool_destroy",
     "viper_adjoint_sizes", "viper_step_checkpointed", "viper_step_backward", "viper_pool_step_ex",
-    "viper_skin_weights", "viper_set_bones", "viper_set_floor", "viper_contact_stats", "viper_pool_status",
+    "viper_skin_weights", "viper_set_bones", "viper_set_floor", "viper_contact_stats", "viper_pool_status", "viper_step_backward_static",
 ]
 
 
@@ -127,6 +127,7 @@ def lib():
         L.viper_step_checkpointed.argtypes = [P, D, I32, I32, I32, P, SZ, P]
         L.viper_step_backward.argtypes = [P, D, I32, I32, I32, P, P, P, SZ, P, P, P]
         L.viper_contact_stats.argtypes = [P, ctypes.POINTER(ContactInfoC), P]
+        L.viper_step_backward_static.argtypes = [P, D, I32, I32, I32, P, P, P, P, P]
         L.viper_pool_status.argtypes = [P, I32, ctypes.POINTER(I32)]
         _lib = L
     return _lib
@@ -409,6 +410,22 @@ class Scene:
                                         _stream_ptr(stream)))
         self._keep_alive = (g, work)
         return drbar, dact
+
+
+def backward_static(scene, dt, frames, substeps, iterations, ckpt, dl_dx, stream=None):
+    """viper_step_backward_static (no work buffer; the library's static scratch): (dL/d rest
+    radius [P], dL/d activation [R]) as float64 device tensors."""
+    import torch
+    g = torch.as_tensor(dl_dx).to(device=scene.device, dtype=scene.dtype).contiguous()
+    assert g.numel() == 3 * scene.P
+    drbar = torch.empty(scene.P, dtype=torch.float64, device=scene.device)
+    dact = torch.empty(scene.num_rods, dtype=torch.float64, device=scene.device)
+    check(lib().viper_step_backward_static(scene.handle, float(dt), int(frames), int(substeps), int(iterations),
+                                           ctypes.c_void_p(ckpt.data_ptr()), ctypes.c_void_p(g.data_ptr()),
+                                           ctypes.c_void_p(drbar.data_ptr()), ctypes.c_void_p(dact.data_ptr()),
+                                           _stream_ptr(stream)))
+    scene._keep_alive = g
+    return drbar, dact
 
 
 class Pool:

@@ -1,0 +1,57 @@
+"""The allocation-free adjoint entry point (viper_step_backward_static) against
+viper_step_backward with a caller work buffer, through the C ABI: the same kernels on the
+same inputs, so the gradients must agree bit for bit.  Two calls in a row, the second on a
+smaller scene (the static scratch keeps the first call's contents); a scene whose scratch
+exceeds the static size is refused with VIPER_ERR_NO_CAPACITY."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1906_05260_amd import scenes, viper  # noqa: E402
+
+DT, SUB, IT = 1 / 60, 20, 8
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def grads_both(desc, targets, prec):
+    sc = viper.Scene(desc, prec)
+    ckpt = sc.step_checkpointed(DT, 1, SUB, IT)
+    x = sc.get("x")
+    last = torch.as_tensor(np.asarray(desc.rod_offsets[1:]) - 1, device=x.device, dtype=torch.long)
+    g = torch.zeros_like(x)
+    g[last] = 2.0 * (x[last] - torch.as_tensor(targets, device=x.device, dtype=x.dtype))
+    ref = sc.backward(DT, 1, SUB, IT, ckpt, g)
+    got = viper.backward_static(sc, DT, 1, SUB, IT, ckpt, g)
+    torch.cuda.synchronize()
+    sc.sync()
+    return [t.cpu().numpy() for t in ref], [t.cpu().numpy() for t in got]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_static_scratch_backward_equals_work_buffer(prec):
+    for rods in (512, 96):                       # the second call on a smaller scene
+        desc, targets = scenes.straight_rods(rods, 32, seed=4)
+        say("case: static-scratch backward", prec, rods, "rods")
+        (rb, ra), (gb, ga) = grads_both(desc, targets, prec)
+        assert np.all(np.isfinite(rb)) and np.abs(rb).max() > 0
+        assert np.array_equal(rb, gb) and np.array_equal(ra, ga)
+
+
+def test_static_scratch_refuses_large_scenes():
+    desc, _ = scenes.straight_rods(2048, 32, seed=4)
+    sc = viper.Scene(desc, "f32")
+    nc, nw = sc.adjoint_sizes(1, SUB, IT)
+    assert nw > 80 << 20
+    ckpt = sc.step_checkpointed(DT, 1, SUB, IT)
+    g = torch.zeros((desc.num_pills, 3), dtype=torch.float32, device="cuda:0")
+    with pytest.raises(viper.ViperError) as ei:
+        viper.backward_static(sc, DT, 1, SUB, IT, ckpt, g)
+    assert ei.value.status == viper.ERR_NO_CAPACITY
