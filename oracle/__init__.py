@@ -77,6 +77,7 @@ def lib():
         L.orc_set_bones.argtypes = [P, I, P, P, P]
         L.orc_bone_frame.argtypes = [P, P]
         L.orc_skin_weights.argtypes = [P, I, P, P, P]
+        L.orc_skin_weights_faired.argtypes = [P, I, P, I, P, I, D, P, P]
         L.orc_rod_iteration.restype = ctypes.c_int64
         L.orc_rod_iteration.argtypes = [P, D, I]
         L.orc_section_fit.argtypes = [P, I, P]
@@ -156,6 +157,17 @@ class OracleScene:
         caps = np.zeros((v.shape[0], 4), np.int32)
         w = np.zeros((v.shape[0], 4))
         lib().orc_skin_weights(self.h, int(v.shape[0]), _p(v), _p(caps), _p(w))
+        return caps, w
+
+    def skin_weights_faired(self, rest_v, tris, iterations, lam=0.5):
+        """Initial skinning weights faired over the mesh (Sec. 7.4; readings in the source):
+        (capsule ids [V,4], weights [V,4])."""
+        v = np.ascontiguousarray(rest_v, dtype=np.float64).reshape(-1, 3)
+        t = np.ascontiguousarray(tris, dtype=np.int32).reshape(-1, 3)
+        caps = np.zeros((v.shape[0], 4), np.int32)
+        w = np.zeros((v.shape[0], 4))
+        lib().orc_skin_weights_faired(self.h, int(v.shape[0]), _p(v), int(t.shape[0]), _p(t), int(iterations),
+                                      float(lam), _p(caps), _p(w))
         return caps, w
 
     def rod_iterations(self, h, iters=1):

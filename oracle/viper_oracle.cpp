@@ -1578,6 +1578,109 @@ void orc_skin_weights(void* hp, int V, const double* v, int32_t* caps, double* w
   }
 }
 
+// Fairing of the initial skinning weights over the mesh (Sec. 7.4: the weights start from the
+// inverse-square assignment and are then faired over the surface, following the
+// Sphere-Meshes skinning the paper builds on; the paper gives no steps).  Readings:
+//  - every vertex keeps a list of at most kFairK = 8 (capsule, weight) entries: initially its
+//    8 strongest inverse-square weights (as above, ties keep the lower id), normalised to sum 1;
+//  - the mesh graph: the undirected edges of the triangles, each vertex's neighbours in
+//    ascending index, no repeats;
+//  - one fairing iteration (Jacobi, every vertex from the previous lists) is the Laplacian
+//    smoothing step w <- (1 - lambda) w(v) + lambda * mean over neighbours u of w(u), on the
+//    sparse lists: a vertex's own entries (scaled by 1 - lambda) in list order, then each
+//    neighbour's entries (scaled by lambda / degree) in neighbour order, each added into the
+//    entry of its capsule (a new capsule is appended); the 8 largest are kept (ties keep the
+//    lower id), ordered largest first, and divided by their sum (summed in that order);
+//  - after the iterations the 4 largest are kept and normalised the same way (fewer than 4
+//    capsules: the remaining slots repeat the first capsule with weight 0).
+// With at most 8 capsules in reach nothing is truncated and this is exactly linear Laplacian
+// smoothing of the weight field.
+constexpr int kFairK = 8;
+struct FairList {
+  int n = 0;
+  int id[kFairK];
+  double w[kFairK];
+};
+
+// Keep the `keep` largest of (id, w) (ties: lower id first), ordered, normalised in that order.
+inline void fair_select(const std::vector<std::pair<int, double>>& acc, int keep, FairList& out) {
+  std::vector<std::pair<int, double>> e(acc);
+  std::sort(e.begin(), e.end(), [](const std::pair<int, double>& a, const std::pair<int, double>& b) {
+    return a.second > b.second || (a.second == b.second && a.first < b.first);
+  });
+  out.n = std::min<int>(keep, int(e.size()));
+  double sum = 0.0;
+  for (int k = 0; k < out.n; ++k) sum += e[k].second;
+  for (int k = 0; k < out.n; ++k) { out.id[k] = e[k].first; out.w[k] = e[k].second / sum; }
+}
+
+void orc_skin_weights_faired(void* hp, int V, const double* v, int nf, const int32_t* tris, int iters, double lam,
+                             int32_t* caps, double* w) {
+  Handle* h = (Handle*)hp;
+  Scene<double>& S = *h->d;
+  std::vector<int> cap;
+  for (int k = 0; k < S.nrods; ++k)
+    for (int p = S.off[k]; p + 1 < S.off[k + 1]; ++p) cap.push_back(p);
+  // initial lists: inverse-square distance to each capsule surface (as orc_skin_weights)
+  std::vector<FairList> cur(V), nxt(V);
+  for (int i = 0; i < V; ++i) {
+    const V3<double> x = v3(v[3 * i], v[3 * i + 1], v[3 * i + 2]);
+    std::vector<std::pair<int, double>> all;
+    for (int e : cap) {
+      const V3<double> c1 = S.xrest[e], c2 = S.xrest[e + 1];
+      const double r1 = S.rbar[e], r2 = S.rbar[e + 1];
+      const double t = pill_project(x, c1, r1, c2, r2);
+      const V3<double> c = c1 + t * (c2 - c1);
+      const double r = r1 + t * (r2 - r1);
+      const double d = std::max(norm(x - c) - r, 1e-9);
+      all.push_back({e, 1.0 / (d * d)});
+    }
+    fair_select(all, kFairK, cur[i]);
+  }
+  // mesh graph
+  std::vector<std::vector<int>> nb(V);
+  for (int f = 0; f < nf; ++f)
+    for (int a = 0; a < 3; ++a) {
+      const int p = tris[3 * f + a], q = tris[3 * f + (a + 1) % 3];
+      if (p == q) continue;
+      nb[p].push_back(q);
+      nb[q].push_back(p);
+    }
+  for (auto& n : nb) {
+    std::sort(n.begin(), n.end());
+    n.erase(std::unique(n.begin(), n.end()), n.end());
+  }
+  for (int it = 0; it < iters; ++it) {
+    for (int i = 0; i < V; ++i) {
+      std::vector<std::pair<int, double>> acc;
+      auto add = [&](int id, double x) {
+        for (auto& a : acc)
+          if (a.first == id) { a.second += x; return; }
+        acc.push_back({id, x});
+      };
+      const double self = 1.0 - lam;
+      for (int k = 0; k < cur[i].n; ++k) add(cur[i].id[k], self * cur[i].w[k]);
+      if (!nb[i].empty()) {
+        const double c = lam / double(nb[i].size());
+        for (int u : nb[i])
+          for (int k = 0; k < cur[u].n; ++k) add(cur[u].id[k], c * cur[u].w[k]);
+      }
+      fair_select(acc, kFairK, nxt[i]);
+    }
+    std::swap(cur, nxt);
+  }
+  for (int i = 0; i < V; ++i) {
+    std::vector<std::pair<int, double>> acc;
+    for (int k = 0; k < cur[i].n; ++k) acc.push_back({cur[i].id[k], cur[i].w[k]});
+    FairList out;
+    fair_select(acc, 4, out);
+    for (int k = 0; k < 4; ++k) {
+      caps[4 * i + k] = k < out.n ? out.id[k] : out.id[0];
+      w[4 * i + k] = k < out.n ? out.w[k] : 0.0;
+    }
+  }
+}
+
 double orc_pill_project(const double* x, const double* c1, double r1, const double* c2, double r2) {
   return pill_project(v3(x[0], x[1], x[2]), v3(c1[0], c1[1], c1[2]), r1, v3(c2[0], c2[1], c2[2]), r2);
 }

@@ -1510,3 +1510,165 @@ def test_moved_floor_is_the_plane_projected_onto():
     assert moved.any() and (~moved).any()
     assert np.abs(st["x"][moved] @ n - d - r[moved]).max() < 1e-15
     assert np.array_equal(st["x"][~moved], x[~moved])
+
+
+# ---------------------------------------------------------------- fairing of the skinning weights
+
+
+def _tube(centre_line, radius, around, seed, jitter=0.1):
+    """Jittered triangle tube around a polyline (rings at its points), open ends."""
+    rng = np.random.default_rng(seed)
+    pts = []
+    for c in centre_line:
+        th = 2 * np.pi * np.arange(around) / around + rng.uniform(-0.2, 0.2, around)
+        r = radius * (1 + jitter * rng.uniform(-1, 1, around))
+        pts.append(np.stack([np.full(around, c[0]), c[1] + r * np.cos(th), c[2] + r * np.sin(th)], 1))
+    v = np.concatenate(pts)
+    tris = []
+    for i in range(len(centre_line) - 1):
+        for j in range(around):
+            a, b = i * around + j, i * around + (j + 1) % around
+            tris += [(a, b, a + around), (b, b + around, a + around)]
+    return v, np.asarray(tris, np.int32)
+
+
+def _inverse_square(desc, v):
+    """Dense inverse-square weights to every capsule surface [V, caps] (App. D projection)."""
+    caps = [p for k in range(desc.num_rods) for p in range(desc.rod_offsets[k], desc.rod_offsets[k + 1] - 1)]
+    W = np.zeros((len(v), len(caps)))
+    for i, x in enumerate(v):
+        for j, e in enumerate(caps):
+            c1, c2 = desc.rest_pos[e], desc.rest_pos[e + 1]
+            r1, r2 = desc.rest_radius[e], desc.rest_radius[e + 1]
+            t = oracle.pill_project(x, c1, r1, c2, r2)
+            d = max(np.linalg.norm(x - (c1 + t * (c2 - c1))) - (r1 + t * (r2 - r1)), 1e-9)
+            W[i, j] = 1.0 / d ** 2
+    return np.asarray(caps), W
+
+
+def _smooth(W, tris, lam, iters, keep=None):
+    """Dense Jacobi Laplacian smoothing of the weight field on the triangle graph; with `keep`,
+    every row is cut to its `keep` largest entries and renormalised after each step."""
+    V = W.shape[0]
+    A = np.zeros((V, V))
+    for t in tris:
+        for a in range(3):
+            p, q = t[a], t[(a + 1) % 3]
+            A[p, q] = A[q, p] = 1.0
+    deg = A.sum(1)
+
+    def cut(M):
+        if keep is None:
+            return M / M.sum(1, keepdims=True)
+        out = np.zeros_like(M)
+        for i in range(V):
+            idx = np.lexsort((np.arange(M.shape[1]), -M[i]))[:keep]
+            out[i, idx] = M[i, idx] / M[i, idx].sum()
+        return out
+
+    W = cut(W)
+    for _ in range(iters):
+        nbr = np.where(deg[:, None] > 0, (A @ W) / np.maximum(deg, 1)[:, None], 0.0)
+        W = cut(np.where(deg[:, None] > 0, (1 - lam) * W + lam * nbr, W))
+    return W
+
+
+def _top4(caps, W):
+    ids = np.zeros((W.shape[0], 4), np.int64)
+    w = np.zeros((W.shape[0], 4))
+    for i in range(W.shape[0]):
+        idx = np.lexsort((np.arange(W.shape[1]), -W[i]))[:4]
+        ids[i] = caps[idx]
+        w[i] = W[i, idx] / W[i, idx].sum()
+    return ids, w
+
+
+def test_fairing_without_iterations_is_the_initial_assignment():
+    d = small_scene([line(6, spacing=0.01), line(5, spacing=0.012) + np.array([0, 0.03, 0])])
+    rng = np.random.default_rng(3)
+    v = rng.uniform([-0.01, -0.02, -0.02], [0.07, 0.05, 0.02], (40, 3))
+    o = OracleScene(d)
+    c0, w0 = o.skin_weights(v)
+    c1, w1 = o.skin_weights_faired(v, np.zeros((0, 3), np.int32), 0)
+    assert np.array_equal(c0, c1)
+    assert np.abs(w0 - w1).max() < 1e-15
+
+
+def test_fairing_is_laplacian_smoothing():
+    """At most 8 capsules in reach: nothing is truncated, so the fairing is exactly dense
+    linear Laplacian smoothing of the inverse-square weight field (a partition of unity)."""
+    rod = line(9, spacing=0.01)                       # 8 capsules
+    d = small_scene([rod], radius=0.004)
+    v, tris = _tube(rod[::2] + np.array([0.002, 0, 0]), 0.009, 7, seed=5)
+    caps, W0 = _inverse_square(d, v)
+    o = OracleScene(d)
+    for lam, iters in ((0.5, 3), (0.25, 7)):
+        ids, w = o.skin_weights_faired(v, tris, iters, lam)
+        rid, rw = _top4(caps, _smooth(W0, tris, lam, iters))
+        assert np.array_equal(ids, rid), (lam, iters)
+        assert np.abs(w - rw).max() < 1e-12
+        assert np.abs(w.sum(1) - 1).max() < 1e-14 and (w >= 0).all()
+
+
+def test_fairing_truncation_against_dense_brute_force():
+    """More capsules than a list holds: each step keeps the 8 largest and renormalises."""
+    rods = [line(7, spacing=0.01) + np.array([0, dy, dz]) for dy, dz in ((0, 0), (0.012, 0.003), (-0.004, 0.011))]
+    d = small_scene(rods, radius=0.003)
+    v, tris = _tube(line(7, spacing=0.01) + np.array([0, 0.003, 0.004]), 0.016, 9, seed=8)
+    caps, W0 = _inverse_square(d, v)
+    assert len(caps) == 18
+    ids, w = OracleScene(d).skin_weights_faired(v, tris, 4, 0.5)
+    rid, rw = _top4(caps, _smooth(W0, tris, 0.5, 4, keep=8))
+    assert np.array_equal(ids, rid)
+    assert np.abs(w - rw).max() < 1e-12
+    # the truncation matters here: without it the result differs
+    _, rw_lin = _top4(caps, _smooth(W0, tris, 0.5, 4))
+    assert np.abs(w - rw_lin).max() > 1e-6
+
+
+def test_fairing_fixed_point_and_symmetry():
+    """Two equal capsules mirrored in the plane y = 0.  A mesh in that plane is equidistant
+    from both: every vertex has (1/2, 1/2), a fixed point of the fairing.  A mesh symmetric
+    under y -> -y keeps the symmetry: a vertex's weight on one capsule is its mirror
+    vertex's weight on the other."""
+    a = line(2, spacing=0.02) + np.array([0, 0.015, 0])
+    b = line(2, spacing=0.02) + np.array([0, -0.015, 0])
+    d = small_scene([a, b], radius=0.004)
+    o = OracleScene(d)
+    gx, gz = np.meshgrid(np.linspace(-0.01, 0.03, 6), np.linspace(-0.02, 0.02, 5), indexing="ij")
+    v = np.stack([gx.ravel(), np.zeros(gx.size), gz.ravel()], 1)
+    tris = []
+    for i in range(5):
+        for j in range(4):
+            p = i * 5 + j
+            tris += [(p, p + 5, p + 1), (p + 1, p + 5, p + 6)]
+    tris = np.asarray(tris, np.int32)
+    ids, w = o.skin_weights_faired(v, tris, 6, 0.5)
+    assert np.all(np.sort(ids[:, :2], 1) == [0, 2]) and np.abs(w[:, :2] - 0.5).max() < 1e-15
+    assert np.all(w[:, 2:] == 0)
+    # a symmetric mesh off the plane: rows y = +-k dy
+    gx, gy = np.meshgrid(np.linspace(-0.01, 0.03, 5), np.linspace(-0.02, 0.02, 5), indexing="ij")
+    v = np.stack([gx.ravel(), gy.ravel(), np.full(gx.size, 0.006)], 1)
+    tris = []
+    for i in range(4):
+        for j in range(4):
+            p = i * 5 + j
+            # split each cell along the diagonal that the mirror j -> 4 - j maps onto itself
+            if j < 2:
+                tris += [(p, p + 5, p + 1), (p + 1, p + 5, p + 6)]
+            else:
+                tris += [(p, p + 5, p + 6), (p, p + 6, p + 1)]
+    tris = np.asarray(tris, np.int32)
+    ids, w = o.skin_weights_faired(v, tris, 5, 0.5)
+    mirror = (np.arange(25) // 5) * 5 + 4 - np.arange(25) % 5
+    def per_capsule(i):       # padded slots repeat the first id with weight 0: sum per id
+        out = {0: 0.0, 2: 0.0}
+        for c, x in zip(ids[i], w[i]):
+            out[int(c)] += x
+        return out
+    asym = 0
+    for i in range(25):
+        wi, wm = per_capsule(i), per_capsule(mirror[i])
+        assert abs(wi[0] - wm[2]) < 1e-14 and abs(wi[2] - wm[0]) < 1e-14
+        asym += abs(wi[0] - wi[2]) > 1e-3
+    assert asym >= 10             # most vertices are not on the mirror plane
