@@ -225,11 +225,31 @@ viper_status viper_skin(viper_scene scene, int32_t skin_id, float* out_dev, void
  * weights proportional to the inverse square distance from the vertex to the surface of each
  * capsule at the scene's current pose (call it right after creation for the rest pose),
  * the four strongest kept and normalised: caps_dev [V*4] int32 capsule ids (first pill of the
- * capsule), w_dev [V*4] float, strongest first (device; caller-owned).  The paper's fairing of
- * these weights over the mesh is not applied (it needs the mesh connectivity).  Brute force
- * over all capsules: O(V * capsules). */
+ * capsule), w_dev [V*4] float, strongest first (device; caller-owned).  Without fairing (see
+ * viper_skin_weights_faired, which needs the mesh connectivity).  Brute force over all
+ * capsules: O(V * capsules). */
 viper_status viper_skin_weights(viper_scene scene, int32_t V, const float* rest_v_dev, int32_t* caps_dev, float* w_dev,
                                 void* stream);
+
+/* Skinning weights faired over the mesh (Sec. 7.4: the paper starts from the inverse-square
+ * assignment above and fairs it over the surface, after the Sphere-Meshes skinning it cites;
+ * the steps are this library's reading).  Every vertex keeps its 8 strongest initial weights
+ * (ties: lower capsule id), normalised; then `iterations` Jacobi Laplacian-smoothing steps on
+ * the mesh graph (the undirected edges of the nf triangles tris_host [nf*3], host memory):
+ * w(v) <- (1 - lambda) w(v) + lambda * mean of w over v's neighbours, summed per capsule in a
+ * fixed order (own entries, then neighbours in ascending index) in FP64, the 8 largest kept
+ * and renormalised after each step; finally the 4 largest, renormalised, are written to
+ * caps_dev [V*4] / w_dev [V*4] (device; as viper_skin_weights).  With at most 8 capsules in
+ * reach this is exactly linear Laplacian smoothing, which keeps a partition of unity.
+ * work: device scratch of viper_skin_fair_work_bytes (the mesh graph and two sets of
+ * per-vertex lists).  Synchronises `stream`.  VIPER_ERR_INVALID for 0 < lambda <= 1 violated,
+ * iterations < 0, a triangle index outside [0, V) or a short work buffer; VIPER_ERR_CAPACITY
+ * if a fairing step gathers more than 256 distinct capsules around one vertex (the result is
+ * then incomplete). */
+viper_status viper_skin_fair_work_bytes(int32_t V, int32_t nf, const int32_t* tris_host, size_t* work_bytes);
+viper_status viper_skin_weights_faired(viper_scene scene, int32_t V, const float* rest_v_dev, int32_t nf,
+                                       const int32_t* tris_host, int32_t iterations, double lambda, void* work,
+                                       size_t work_bytes, int32_t* caps_dev, float* w_dev, void* stream);
 
 /* Kinematic half-plane (Sec. 7 collision proxies): move the floor of a scene created with
  * floor_on to floor_normal . x >= floor_offset + s rbar (host values; the normal need not be

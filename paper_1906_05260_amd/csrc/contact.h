@@ -32,5 +32,15 @@ viper_status contact_get_info(const ContactDev& c, viper_contact_info* out, hipS
 // Initial skinning weights of V rest vertices at the scene's current pose (Sec. 7.4).
 template <class T>
 hipError_t launch_skin_weights(const Dev<T>& d, int V, const float* rest_v, int32_t* caps, float* w, hipStream_t st);
+// Scratch of the faired weights: the mesh graph (CSR offsets [V+1], neighbours) at the start,
+// then two sets of per-vertex candidate lists.
+size_t skin_fair_work_bytes(int V, int64_t nbr_entries);
+// Initial weights faired over the mesh graph (off, nbr: CSR inside `work`, already uploaded),
+// `iters` Jacobi Laplacian-smoothing iterations with weight `lam`; the four largest written to
+// caps / w.  *overflow (device) is set if a vertex gathers more capsules than a step holds.
+template <class T>
+hipError_t launch_skin_weights_faired(const Dev<T>& d, int V, const float* rest_v, const int32_t* off,
+                                      const int32_t* nbr, int64_t nbr_entries, int iters, double lam, char* work,
+                                      int32_t* overflow, int32_t* caps, float* w, hipStream_t st);
 
 }  // namespace viper

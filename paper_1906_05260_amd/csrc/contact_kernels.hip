@@ -659,24 +659,36 @@ __global__ void __launch_bounds__(256) contact_pair_kernel(const Dev<T>* __restr
 
 // Initial skinning weights (Sec. 7.4): a vertex's weight for each capsule is proportional to
 // the inverse square distance from the vertex to the capsule's surface, |v - c(t)| - r(t) at the
-// capsule's closest sphere t (App. D projection, FP64), clamped below at 1e-9 m; the four
+// capsule's closest sphere t (App. D projection, FP64), clamped below at 1e-9 m; the K
 // strongest are kept (ties keep the lower capsule id) and normalised.  One thread per vertex
 // over every capsule of the scene, at the scene's current pose; the block stages the capsules
 // in tiles of kSkinTile (world endpoints and radii in FP64, 17 KB of LDS) and every thread
-// scans the tile in capsule order.
+// scans the tile in capsule order.  K = 4: the final influences (float weights); K = kFairK:
+// the start of the fairing (FP64 lists, largest first).
 constexpr int kSkinTile = 256;
+constexpr int kFairK = 8;       // entries kept per vertex while fairing
+constexpr int kFairAcc = 256;   // distinct capsules a fairing step can gather around one vertex
 
-template <class T>
+struct FairLists {
+  int32_t* id;    // [V*kFairK]
+  double* w;      // [V*kFairK]
+  int32_t* n;     // [V] entries in use
+};
+
+template <class T, int K>
 __global__ void __launch_bounds__(kSkinTile) skin_weights_kernel(const Dev<T> d, int V, const float* __restrict__ rest_v,
-                                                                 int32_t* __restrict__ caps, float* __restrict__ w) {
+                                                                 int32_t* __restrict__ caps, float* __restrict__ w,
+                                                                 FairLists fl) {
   __shared__ double s_geo[kSkinTile][8];   // c1 (3), c2 (3), r1, r2
   __shared__ int s_id[kSkinTile];          // capsule id, -1 for a slot without an edge
   const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
   const bool live = i < V;                 // every thread takes part in the staging
   const D3 x = live ? d3((double)rest_v[3 * (size_t)i], (double)rest_v[3 * (size_t)i + 1], (double)rest_v[3 * (size_t)i + 2])
                     : d3(0.0, 0.0, 0.0);
-  int best[4] = {-1, -1, -1, -1};
-  double bw[4] = {-1.0, -1.0, -1.0, -1.0};
+  int best[K];
+  double bw[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) { best[k] = -1; bw[k] = -1.0; }
   for (int base = 0; base + 1 < d.P; base += kSkinTile) {
     const int p = base + (int)threadIdx.x;
     int id = -1;
@@ -703,8 +715,8 @@ __global__ void __launch_bounds__(kSkinTile) skin_weights_kernel(const Dev<T> d,
         const D3 rel = sub(x, lerp(c1, c2, t));
         const double dist = fmax(sqrt(dotp(rel, rel)) - (r1 + t * (r2 - r1)), 1e-9);
         const double wt = 1.0 / (dist * dist);
-        if (wt > bw[3]) {
-          int k = 3;
+        if (wt > bw[K - 1]) {
+          int k = K - 1;
           while (k > 0 && wt > bw[k - 1]) {
             bw[k] = bw[k - 1]; best[k] = best[k - 1];
             --k;
@@ -718,11 +730,97 @@ __global__ void __launch_bounds__(kSkinTile) skin_weights_kernel(const Dev<T> d,
   if (!live) return;
   double sum = 0.0;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) if (best[k] >= 0) sum += bw[k];
+  for (int k = 0; k < K; ++k) if (best[k] >= 0) sum += bw[k];
+  if constexpr (K == 4) {
 #pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      caps[4 * (size_t)i + k] = best[k] >= 0 ? best[k] : best[0];
+      w[4 * (size_t)i + k] = best[k] >= 0 ? (float)(bw[k] / sum) : 0.0f;
+    }
+  } else {
+    int n = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (best[k] >= 0) n = k + 1;
+      fl.id[(size_t)K * i + k] = best[k];
+      fl.w[(size_t)K * i + k] = best[k] >= 0 ? bw[k] / sum : 0.0;
+    }
+    fl.n[i] = n;
+  }
+}
+
+// One fairing iteration (Jacobi; the readings are those of the oracle's fairing): vertex i's
+// new list is (1 - lambda) times its own entries, then lambda / degree times each neighbour's
+// entries (neighbours in ascending index, each list largest first), summed per capsule in
+// that order (FP64, no contraction); the kFairK largest are kept (ties: lower id first), in
+// that order, divided by their sum (summed in that order).  More than kFairAcc distinct
+// capsules around a vertex set *overflow.
+__global__ void __launch_bounds__(256) skin_fair_step_kernel(int V, const int32_t* __restrict__ off,
+                                                             const int32_t* __restrict__ nbr, FairLists in,
+                                                             FairLists out, double lam, int32_t* __restrict__ overflow) {
+#pragma clang fp contract(off)
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i >= V) return;
+  int aid[kFairAcc];
+  double aw[kFairAcc];
+  int na = 0;
+  bool full = false;
+  auto add = [&](int id, double x) {
+    for (int a = 0; a < na; ++a)
+      if (aid[a] == id) { aw[a] += x; return; }
+    if (na == kFairAcc) { full = true; return; }
+    aid[na] = id; aw[na] = x; ++na;
+  };
+  const double self = 1.0 - lam;
+  const int n0 = in.n[i];
+  for (int k = 0; k < n0; ++k) add(in.id[(size_t)kFairK * i + k], self * in.w[(size_t)kFairK * i + k]);
+  const int b = off[i], e = off[i + 1];
+  if (e > b) {
+    const double c = lam / (double)(e - b);
+    for (int j = b; j < e; ++j) {
+      const int u = nbr[j];
+      const int nu = in.n[u];
+      for (int k = 0; k < nu; ++k) add(in.id[(size_t)kFairK * u + k], c * in.w[(size_t)kFairK * u + k]);
+    }
+  }
+  if (full) atomicExch(overflow, 1);
+  // the kFairK largest, largest first (ties: lower id)
+  int sid[kFairK];
+  double sw[kFairK];
+  const int n = min(kFairK, na);
+  for (int k = 0; k < n; ++k) {
+    int bi = -1;
+    for (int a = 0; a < na; ++a) {
+      if (aid[a] < 0) continue;
+      if (bi < 0 || aw[a] > aw[bi] || (aw[a] == aw[bi] && aid[a] < aid[bi])) bi = a;
+    }
+    sid[k] = aid[bi];
+    sw[k] = aw[bi];
+    aid[bi] = -1;                        // taken
+  }
+  double sum = 0.0;
+  for (int k = 0; k < n; ++k) sum += sw[k];
+  for (int k = 0; k < kFairK; ++k) {
+    out.id[(size_t)kFairK * i + k] = k < n ? sid[k] : -1;
+    out.w[(size_t)kFairK * i + k] = k < n ? sw[k] / sum : 0.0;
+  }
+  out.n[i] = n;
+}
+
+// The four largest entries of each faired list (the lists are ordered largest first),
+// normalised (summed in that order); fewer than four: the first capsule repeated, weight 0.
+__global__ void __launch_bounds__(256) skin_fair_final_kernel(int V, FairLists in, int32_t* __restrict__ caps,
+                                                              float* __restrict__ w) {
+#pragma clang fp contract(off)
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i >= V) return;
+  const int n = min(4, in.n[i]);
+  double sum = 0.0;
+  for (int k = 0; k < n; ++k) sum += in.w[(size_t)kFairK * i + k];
+  const int first = in.id[(size_t)kFairK * i];
   for (int k = 0; k < 4; ++k) {
-    caps[4 * (size_t)i + k] = best[k] >= 0 ? best[k] : best[0];
-    w[4 * (size_t)i + k] = best[k] >= 0 ? (float)(bw[k] / sum) : 0.0f;
+    caps[4 * (size_t)i + k] = k < n ? in.id[(size_t)kFairK * i + k] : first;
+    w[4 * (size_t)i + k] = k < n ? (float)(in.w[(size_t)kFairK * i + k] / sum) : 0.0f;
   }
 }
 
@@ -916,12 +1014,45 @@ hipError_t launch_contact_flush(const BatchDev& b, hipStream_t st) {
 template <class T>
 hipError_t launch_skin_weights(const Dev<T>& d, int V, const float* rest_v, int32_t* caps, float* w, hipStream_t st) {
   if (V <= 0) return hipSuccess;
-  hipLaunchKernelGGL(skin_weights_kernel<T>, dim3((V + kSkinTile - 1) / kSkinTile), dim3(kSkinTile), 0, st, d, V, rest_v,
-                     caps, w);
+  hipLaunchKernelGGL((skin_weights_kernel<T, 4>), dim3((V + kSkinTile - 1) / kSkinTile), dim3(kSkinTile), 0, st, d, V,
+                     rest_v, caps, w, FairLists{nullptr, nullptr, nullptr});
   return hipGetLastError();
 }
 template hipError_t launch_skin_weights<float>(const Dev<float>&, int, const float*, int32_t*, float*, hipStream_t);
 template hipError_t launch_skin_weights<double>(const Dev<double>&, int, const float*, int32_t*, float*, hipStream_t);
+
+size_t skin_fair_work_bytes(int V, int64_t nbr_entries) {
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t lists = al(4 * (size_t)kFairK * V) + al(8 * (size_t)kFairK * V) + al(4 * (size_t)V);
+  return al(4 * ((size_t)V + 1)) + al(4 * (size_t)nbr_entries) + 2 * lists + 256;
+}
+
+template <class T>
+hipError_t launch_skin_weights_faired(const Dev<T>& d, int V, const float* rest_v, const int32_t* off,
+                                      const int32_t* nbr, int64_t nbr_entries, int iters, double lam, char* work,
+                                      int32_t* overflow, int32_t* caps, float* w, hipStream_t st) {
+  if (V <= 0) return hipSuccess;
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  char* at = work + al(4 * ((size_t)V + 1)) + al(4 * (size_t)nbr_entries);
+  FairLists L[2];
+  for (int b = 0; b < 2; ++b) {
+    L[b].id = (int32_t*)at; at += al(4 * (size_t)kFairK * V);
+    L[b].w = (double*)at; at += al(8 * (size_t)kFairK * V);
+    L[b].n = (int32_t*)at; at += al(4 * (size_t)V);
+  }
+  hipLaunchKernelGGL((skin_weights_kernel<T, kFairK>), dim3((V + kSkinTile - 1) / kSkinTile), dim3(kSkinTile), 0, st, d,
+                     V, rest_v, (int32_t*)nullptr, (float*)nullptr, L[0]);
+  const dim3 g((V + 255) / 256), blk(256);
+  for (int it = 0; it < iters; ++it)
+    hipLaunchKernelGGL(skin_fair_step_kernel, g, blk, 0, st, V, off, nbr, L[it & 1], L[(it + 1) & 1], lam, overflow);
+  hipLaunchKernelGGL(skin_fair_final_kernel, g, blk, 0, st, V, L[iters & 1], caps, w);
+  return hipGetLastError();
+}
+template hipError_t launch_skin_weights_faired<float>(const Dev<float>&, int, const float*, const int32_t*, const int32_t*,
+                                                      int64_t, int, double, char*, int32_t*, int32_t*, float*, hipStream_t);
+template hipError_t launch_skin_weights_faired<double>(const Dev<double>&, int, const float*, const int32_t*,
+                                                       const int32_t*, int64_t, int, double, char*, int32_t*, int32_t*,
+                                                       float*, hipStream_t);
 
 hipError_t contact_copy_det(const ContactDev& c, bool x, void* dst, int P, size_t ts, hipStream_t st) {
   return hipMemcpyAsync(dst, x ? (void*)c.xdet : c.sdet, (x ? 3 * 8 : ts) * (size_t)P, hipMemcpyDefault, st);

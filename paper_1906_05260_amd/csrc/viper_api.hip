@@ -904,6 +904,84 @@ viper_status viper_skin_weights(viper_scene S, int32_t V, const float* rest_v, i
   return VIPER_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Undirected edges of the triangles as a CSR graph: neighbours of each vertex ascending, no
+// repeats, no self loops.  False if a vertex index is out of range.
+bool mesh_graph(int V, int nf, const int32_t* tris, std::vector<int32_t>& off, std::vector<int32_t>& nbr) {
+  std::vector<std::pair<int32_t, int32_t>> e;
+  e.reserve(6 * (size_t)nf);
+  for (int f = 0; f < nf; ++f)
+    for (int a = 0; a < 3; ++a) {
+      const int32_t p = tris[3 * (size_t)f + a], q = tris[3 * (size_t)f + (a + 1) % 3];
+      if (p < 0 || p >= V || q < 0 || q >= V) return false;
+      if (p == q) continue;
+      e.push_back({p, q});
+      e.push_back({q, p});
+    }
+  std::sort(e.begin(), e.end());
+  e.erase(std::unique(e.begin(), e.end()), e.end());
+  off.assign((size_t)V + 1, 0);
+  nbr.resize(e.size());
+  for (size_t k = 0; k < e.size(); ++k) {
+    ++off[(size_t)e[k].first + 1];
+    nbr[k] = e[k].second;
+  }
+  for (int i = 0; i < V; ++i) off[i + 1] += off[i];
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+viper_status viper_skin_fair_work_bytes(int32_t V, int32_t nf, const int32_t* tris, size_t* bytes) {
+  if (V < 0 || nf < 0 || !bytes || (nf > 0 && !tris)) return fail(VIPER_ERR_INVALID, "V, nf >= 0, tris and bytes required");
+  std::vector<int32_t> off, nbr;
+  if (!mesh_graph(V, nf, tris, off, nbr)) return fail(VIPER_ERR_INVALID, "a triangle references a vertex outside [0, V)");
+  *bytes = skin_fair_work_bytes(V, (int64_t)nbr.size());
+  return VIPER_OK;
+}
+
+viper_status viper_skin_weights_faired(viper_scene S, int32_t V, const float* rest_v, int32_t nf, const int32_t* tris,
+                                       int32_t iterations, double lambda, void* work, size_t work_bytes, int32_t* caps,
+                                       float* w, void* stream) {
+  if (!S || V < 0 || nf < 0) return fail(VIPER_ERR_INVALID, "scene, V >= 0 and nf >= 0 are required");
+  if (V > 0 && (!rest_v || !caps || !w || !work)) return fail(VIPER_ERR_INVALID, "rest_v, caps, w and work are required");
+  if (nf > 0 && !tris) return fail(VIPER_ERR_INVALID, "tris is NULL");
+  if (S->E == 0 && V > 0) return fail(VIPER_ERR_INVALID, "the scene has no capsules");
+  if (iterations < 0 || !(lambda > 0.0 && lambda <= 1.0))
+    return fail(VIPER_ERR_INVALID, "iterations >= 0 and 0 < lambda <= 1 required");
+  if (V == 0) return VIPER_OK;
+  std::vector<int32_t> off, nbr;
+  if (!mesh_graph(V, nf, tris, off, nbr)) return fail(VIPER_ERR_INVALID, "a triangle references a vertex outside [0, V)");
+  const size_t need = skin_fair_work_bytes(V, (int64_t)nbr.size());
+  if (work_bytes < need) return fail(VIPER_ERR_INVALID, "work buffer too small: need " + std::to_string(need) + " bytes");
+  hipStream_t st = (hipStream_t)stream;
+  char* wk = (char*)work;
+  const size_t noff = align256(4 * off.size());
+  int32_t* overflow = (int32_t*)(wk + need - 256);
+  const int32_t zero = 0;
+  HIP_TRY(hipMemcpyAsync(wk, off.data(), 4 * off.size(), hipMemcpyHostToDevice, st));
+  if (!nbr.empty()) HIP_TRY(hipMemcpyAsync(wk + noff, nbr.data(), 4 * nbr.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(overflow, &zero, 4, hipMemcpyHostToDevice, st));
+  const int32_t* doff = (const int32_t*)wk;
+  const int32_t* dnbr = (const int32_t*)(wk + noff);
+  if (S->precision == VIPER_F64)
+    HIP_TRY(launch_skin_weights_faired<double>(S->dd, V, rest_v, doff, dnbr, (int64_t)nbr.size(), iterations, lambda, wk,
+                                               overflow, caps, w, st));
+  else
+    HIP_TRY(launch_skin_weights_faired<float>(S->df, V, rest_v, doff, dnbr, (int64_t)nbr.size(), iterations, lambda, wk,
+                                              overflow, caps, w, st));
+  int32_t flag = 0;
+  HIP_TRY(hipMemcpyAsync(&flag, overflow, 4, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));   // the host graph and flag die with this frame
+  if (flag) return fail(VIPER_ERR_CAPACITY, "a vertex gathered more than 256 distinct capsules in one fairing step");
+  return VIPER_OK;
+}
+
 viper_status viper_set_floor(viper_scene S, const double* normal, double offset, void* stream) {
   if (!S || !normal) return fail(VIPER_ERR_INVALID, "scene and normal are required");
   if (!S->floor_on) return fail(VIPER_ERR_INVALID, "the scene was created without a floor");

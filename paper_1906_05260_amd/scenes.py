@@ -88,6 +88,7 @@ class SkinMesh:
     rest_v: np.ndarray     # float32 [V,3]
     caps: np.ndarray       # int32 [V,4]  capsule id = global index of the capsule's first pill
     w: np.ndarray          # float32 [V,4], rows sum to 1
+    tris: Optional[np.ndarray] = None   # int32 [F,3] triangles (meshes with connectivity)
 
 
 def _log_uniform(rng, lo, hi, size):
@@ -279,6 +280,53 @@ def muscle_mesh(desc: SceneDesc, muscle_info, V, rng) -> SkinMesh:
         ww.append(rng.dirichlet(np.ones(4), nv))
     return SkinMesh(np.concatenate(rv).astype(np.float32), np.concatenate(cp).astype(np.int32),
                     np.concatenate(ww).astype(np.float32))
+
+
+def tube_mesh(desc: SceneDesc, vertices=200000, seed=0, offset=0.004, jitter=0.0) -> SkinMesh:
+    """A closed-surface triangle mesh on each muscle's envelope (a muscle scene's
+    ``extra["muscles"]``): a tube of rings around the muscle axis, ring count and ring size
+    chosen so that the muscle's share of ``vertices`` is proportional to its pills, capped by
+    a fan at each end; ``offset`` m outside the bundle radius, optional radial ``jitter``
+    (fraction of the radius, seeded).  Influences and weights are left empty (caps -1, w 0):
+    they come from the skinning-weight computation."""
+    rng = np.random.default_rng(seed)
+    offs = desc.rod_offsets
+    mus = desc.extra["muscles"]
+    pills = np.array([sum(int(offs[k + 1] - offs[k]) for k in mi["rods"]) for mi in mus], dtype=np.float64)
+    share = vertices * pills / pills.sum()
+    pos, tri, base = [], [], 0
+    for m, mi in enumerate(mus):
+        n = max(int(share[m]), 10)
+        # rings of `ar` vertices, `al` rings, aspect about the tube's length / circumference
+        rr = mi["radius"] + offset
+        circ, L = 2 * np.pi * rr, max(mi["L"], 1e-3)
+        ar = max(3, int(round(np.sqrt(n * circ / L))))
+        al = max(2, (n - 2) // ar)
+        u = np.linspace(0.0, 1.0, al)
+        th = 2 * np.pi * np.arange(ar) / ar
+        xx = mi["x0"] + u[:, None] * L + 0 * th[None, :]
+        r = rr * (1.0 + jitter * rng.uniform(-1.0, 1.0, (al, ar)))
+        cy = mi["centre"][0] + mi["tilt"][0] * xx + r * np.cos(th)[None, :]
+        cz = mi["centre"][1] + mi["tilt"][1] * xx + r * np.sin(th)[None, :]
+        ring = np.stack([xx, cy, cz], -1).reshape(-1, 3)
+        ends = np.array([[mi["x0"], mi["centre"][0] + mi["tilt"][0] * mi["x0"], mi["centre"][1] + mi["tilt"][1] * mi["x0"]],
+                         [mi["x0"] + L, mi["centre"][0] + mi["tilt"][0] * (mi["x0"] + L),
+                          mi["centre"][1] + mi["tilt"][1] * (mi["x0"] + L)]])
+        pos.append(np.vstack([ring, ends]))
+        i = np.arange(al - 1)[:, None] * ar
+        j = np.arange(ar)[None, :]
+        a, b = i + j, i + (j + 1) % ar
+        c, d = a + ar, b + ar
+        t = np.concatenate([np.stack([a, b, c], -1).reshape(-1, 3), np.stack([b, d, c], -1).reshape(-1, 3)])
+        c0, c1 = al * ar, al * ar + 1
+        f0 = np.stack([np.full(ar, c0), (np.arange(ar) + 1) % ar, np.arange(ar)], -1)
+        f1 = np.stack([np.full(ar, c1), (al - 1) * ar + np.arange(ar), (al - 1) * ar + (np.arange(ar) + 1) % ar], -1)
+        tri.append(np.concatenate([t, f0, f1]) + base)
+        base += al * ar + 2
+    v = np.concatenate(pos).astype(np.float32)
+    V = v.shape[0]
+    return SkinMesh(v, np.full((V, 4), -1, np.int32), np.zeros((V, 4), np.float32),
+                    np.concatenate(tri).astype(np.int32))
 
 
 def octopus_scene(num_models=100, seed=5, mesh_vertices_per_model=6500, spacing=0.2):

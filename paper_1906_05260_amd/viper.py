@@ -34,6 +34,7 @@ ABI_SYMBOLS = [
     "viper_pool_info", "viper_pool_destroy",
     "viper_adjoint_sizes", "viper_step_checkpointed", "viper_step_backward", "viper_pool_step_ex",
     "viper_skin_weights", "viper_set_bones", "viper_set_floor", "viper_contact_stats", "viper_pool_status", "viper_step_backward_static",
+    "viper_skin_fair_work_bytes", "viper_skin_weights_faired",
 ]
 
 
@@ -128,6 +129,8 @@ def lib():
         L.viper_step_backward.argtypes = [P, D, I32, I32, I32, P, P, P, SZ, P, P, P]
         L.viper_contact_stats.argtypes = [P, ctypes.POINTER(ContactInfoC), P]
         L.viper_step_backward_static.argtypes = [P, D, I32, I32, I32, P, P, P, P, P]
+        L.viper_skin_fair_work_bytes.argtypes = [I32, I32, P, ctypes.POINTER(ctypes.c_size_t)]
+        L.viper_skin_weights_faired.argtypes = [P, I32, P, I32, P, I32, D, P, ctypes.c_size_t, P, P, P]
         L.viper_pool_status.argtypes = [P, I32, ctypes.POINTER(I32)]
         _lib = L
     return _lib
@@ -357,6 +360,25 @@ class Scene:
         check(lib().viper_skin_weights(self.handle, V, ctypes.c_void_p(rv.data_ptr()), ctypes.c_void_p(caps.data_ptr()),
                                        ctypes.c_void_p(w.data_ptr()), _stream_ptr(stream)))
         self._keep_alive = rv
+        return caps, w
+
+    def skin_weights_faired(self, rest_v, tris, iterations, lam=0.5, stream=None):
+        """Skinning weights faired over the mesh (include/viper.h, viper_skin_weights_faired):
+        (capsule ids [V,4] int32, weights [V,4] float32) device tensors (synchronises)."""
+        import torch
+        rv = torch.as_tensor(rest_v, dtype=torch.float32).to(self.device).contiguous()
+        V = int(rv.shape[0])
+        t = np.ascontiguousarray(tris, np.int32).reshape(-1, 3)
+        nb = ctypes.c_size_t(0)
+        check(lib().viper_skin_fair_work_bytes(V, int(t.shape[0]), ctypes.c_void_p(t.ctypes.data), ctypes.byref(nb)))
+        work = torch.empty(max(int(nb.value), 256), dtype=torch.uint8, device=self.device)
+        caps = torch.empty((V, 4), dtype=torch.int32, device=self.device)
+        w = torch.empty((V, 4), dtype=torch.float32, device=self.device)
+        check(lib().viper_skin_weights_faired(self.handle, V, ctypes.c_void_p(rv.data_ptr()), int(t.shape[0]),
+                                              ctypes.c_void_p(t.ctypes.data), int(iterations), float(lam),
+                                              ctypes.c_void_p(work.data_ptr()), ctypes.c_size_t(work.numel()),
+                                              ctypes.c_void_p(caps.data_ptr()), ctypes.c_void_p(w.data_ptr()),
+                                              _stream_ptr(stream)))
         return caps, w
 
     def set_floor(self, plane, stream=None):
