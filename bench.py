@@ -94,8 +94,9 @@ def cpu_baseline(desc, dt, sub, iters, rods, threads):
     n = o.step(dt, sub, iters, threads=threads)
     el = time.perf_counter() - t0
     return {"value": n / el, "unit": "projections/s", "cores": threads, "kind": "oracle",
-            "sample": "%d of %d rods, 1 frame (%d substeps x %d iterations), FP64, %d threads on %s" %
-                      (rods, desc.num_rods, sub, iters, threads, cpu_model()),
+            "host_cores": os.cpu_count(),
+            "sample": "%d of %d rods, 1 frame (%d substeps x %d iterations), FP64, %d threads on %s (%d cores "
+                      "visible)" % (rods, desc.num_rods, sub, iters, threads, cpu_model(), os.cpu_count() or 0),
             "seconds": el, "pill_substeps_per_s": sample.num_pills * sub / el}
 
 
