@@ -12,10 +12,11 @@ Prints one JSON line with the throughput, a roofline object for the dominant ker
 (timed per launch with HIP events on the launch stream) and the oracle timed on the
 host cores on a bounded sample of the same workload.  Further entries of the same line:
 the rate split by constraint type (`config.projections_per_s_by_type`), the 32-pill FP64
-rod (`single_rod`), the contact, skinning, skinning-weight, octopus-shaped and bundling
-scenes, the two solvers and the optional energy terms (`solvers`), the bone warm start
-(`bones`), the helix scene at 16x the rods (`helix_16x`), the measured copy ceiling
-(`copy_ceiling`), the adjoint and the serving loop (`serving`, whose p50/p99 frame
+rod (`single_rod`), the contact, skinning, skinning-weight (initial and faired),
+octopus-shaped and bundling scenes, the two solvers and the optional energy terms
+(`solvers`), the bone warm start (`bones`), the one-substep-per-launch kernel
+(`substep_kernel`), the helix scene at 16x the rods (`helix_16x`), the measured copy
+ceiling (`copy_ceiling`), the adjoint and the serving loop (`serving`, whose p50/p99 frame
 latencies are repeated at the top level).
 """
 from __future__ import annotations
@@ -40,6 +41,7 @@ FLOP = {"ss": 122, "vol": 53, "sg": 16, "bt": 337, "predict": 59, "velocity": 42
 # 13 rest words and one flag word read.
 BYTES_PER_PILL_LAUNCH = 4 * (15 + 15 + 13 + 1)
 PEAK_FP32_VALU = 78.6e12     # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz, packed FP32 disabled
+SURVEY_FLOP_PER_PILL_SUBSTEP = 2750.0   # the survey's estimate of the same work (2.5-3 kFLOP)
 PEAK_HBM = 8.0e12
 
 
@@ -243,27 +245,45 @@ def contact_skin_timing(torch, viper, scenes, dev, frames=10):
     weights_ms = e7.elapsed_time(e8)
     del rest_sc
     # the same skinning with a mesh far beyond the caches: the 200k-vertex mesh tiled to
-    # ~16.8M vertices (0.94 GB of vertex data); every tile references the same capsules
+    # ~16.6M vertices (0.93 GB of vertex data); every tile references the same capsules.  The
+    # mesh numbers its vertices by first capsule; the same mesh numbered along each muscle's
+    # axis (random around it) is timed beside it
     reps = (16 << 20) // V
     VL = reps * V
-    big_caps = np.tile(mesh.caps, (reps, 1))
-    big_w = np.tile(mesh.w, (reps, 1))
-    big_v = np.tile(mesh.rest_v, (reps, 1))
-    sid_l = sc.create_skin(big_v, big_caps, big_w)
-    del big_caps, big_w, big_v
-    out_l = torch.empty((VL, 3), dtype=torch.float32, device=dev)
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < 0.3:       # the host-side set-up left the GPU idle: clocks up first
-        sc.skin(sid_l, out=out_l)
+
+    def large_pass(m):
+        big_caps = np.tile(m.caps, (reps, 1))
+        big_w = np.tile(m.w, (reps, 1))
+        big_v = np.tile(m.rest_v, (reps, 1))
+        sid_l = sc.create_skin(big_v, big_caps, big_w)
+        del big_caps, big_w, big_v
+        out_l = torch.empty((VL, 3), dtype=torch.float32, device=dev)
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < 0.3:       # the host-side set-up left the GPU idle: clocks up first
+            sc.skin(sid_l, out=out_l)
+            torch.cuda.synchronize()
+        e5, e6 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e5.record(st)
+        for _ in range(frames):
+            sc.skin(sid_l, out=out_l)
+        e6.record(st)
         torch.cuda.synchronize()
-    e5, e6 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e5.record(st)
-    for _ in range(frames):
-        sc.skin(sid_l, out=out_l)
-    e6.record(st)
-    torch.cuda.synchronize()
-    skin_l_ms = e5.elapsed_time(e6) / frames
+        sc._skins[sid_l] = None                     # free the device copies
+        return e5.elapsed_time(e6) / frames
+
+    skin_l_ms = large_pass(mesh)
+    _, mesh_axis = scenes.muscle_scene(64, seed=2, capsule_order=False)
+    skin_axis_ms = large_pass(mesh_axis)
     skin_l_bytes = 56 * VL + 48 * sc.capsules
+    # skinning weights faired over a closed 200k-vertex tube mesh on the muscles' envelopes
+    # (4 Jacobi iterations), on a fresh scene at the rest pose
+    tube = scenes.tube_mesh(desc, V, seed=2, jitter=0.05)
+    rest_sc = viper.Scene(desc, "f32", device=dev, collisions=True)
+    rest_sc.skin_weights_faired(tube.rest_v[:1024], tube.tris[:0], 1)
+    t0 = time.perf_counter()
+    rest_sc.skin_weights_faired(tube.rest_v, tube.tris, 4, 0.5)
+    faired_s = time.perf_counter() - t0
+    del rest_sc
     return {"workload": "muscle64_%dpills" % desc.num_pills, "pills": desc.num_pills, "capsules": sc.capsules,
             "contact_pairs_last_substep": int(len(sc.contacts())), "frame_ms": frame_ms,
             "frame_ms_eager_launches": eager_ms, "frame_ms_wall_graph": wall_graph,
@@ -273,7 +293,12 @@ def contact_skin_timing(torch, viper, scenes, dev, frames=10):
             "skin_algorithmic_GB_per_s": skin_bytes / (skin_ms * 1e-3) / 1e9,
             "skin_large": {"vertices": VL, "ms": skin_l_ms, "algorithmic_bytes": skin_l_bytes,
                            "GB_per_s": skin_l_bytes / (skin_l_ms * 1e-3) / 1e9,
-                           "hbm_frac": skin_l_bytes / (skin_l_ms * 1e-3) / PEAK_HBM}}
+                           "hbm_frac": skin_l_bytes / (skin_l_ms * 1e-3) / PEAK_HBM,
+                           "vertex_order": "by first capsule",
+                           "axis_order_ms": skin_axis_ms,
+                           "axis_order_GB_per_s": skin_l_bytes / (skin_axis_ms * 1e-3) / 1e9},
+            "skin_weights_faired": {"vertices": int(tube.rest_v.shape[0]), "triangles": int(tube.tris.shape[0]),
+                                    "iterations": 4, "wall_s_with_host_graph": faired_s}}
 
 
 def paper_shaped_timing(torch, viper, scenes, dev, frames=10):
@@ -398,6 +423,34 @@ def large_timing(torch, viper, scenes, dev, rods=65536, frames=5):
             "algorithmic_GB_per_s": BYTES_PER_PILL_LAUNCH * P / (ms * 1e-3) / 1e9}
 
 
+def substep_kernel_timing(torch, viper, scenes, dev, frames=3):
+    """The helix workload (4096 x 64, FP32, 8 iterations) with one launch per substep
+    (VIPER_MODE_SUBSTEP: the state streamed through HBM every substep), each launch timed with
+    HIP events on the launch stream: us per launch, algorithmic GB/s against 8 TB/s, and the
+    HBM bytes per launch from the committed counter summary (when taken on this source)."""
+    desc = scenes.helix_rods(4096, 64, seed=1)
+    sc = viper.Scene(desc, "f32", device=dev)
+    h = 1.0 / 60.0 / 20
+    sc.step(h, 1, 8, mode=viper.MODE_SUBSTEP)
+    st = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(20 * frames)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record(st)
+        sc.step(h, 1, 8, mode=viper.MODE_SUBSTEP)
+        b.record(st)
+    torch.cuda.synchronize()
+    sc.sync()
+    us = sum(a.elapsed_time(b) for a, b in ev) / len(ev) * 1e3
+    P = desc.num_pills
+    nbytes = BYTES_PER_PILL_LAUNCH * P
+    traffic = measured_traffic("rod_frame_kernel_substep", "helix4096x64")
+    return {"workload": "helix4096x64", "kernel": "rod_frame_kernel (one substep per launch)", "us_per_launch": us,
+            "algorithmic_bytes_per_launch": nbytes, "algorithmic_GB_per_s": nbytes / (us * 1e-6) / 1e9,
+            "hbm_frac": nbytes / (us * 1e-6) / PEAK_HBM, "traffic": traffic,
+            "counter_GB_per_s": traffic / (us * 1e-6) / 1e9 if traffic else None}
+
+
 def bones_timing(torch, viper, scenes, dev, calls=50):
     """The bone warm start (Sec. 8.2) on the helix workload (4096 x 64, FP32): two bones, every
     pill blended between them by its position along its rod; us per set_bones call (HIP events
@@ -432,19 +485,29 @@ def bones_timing(torch, viper, scenes, dev, calls=50):
             "algorithmic_GB_per_s": 52.0 * d.num_pills / (us * 1e-6) / 1e9}
 
 
-def serving_run(torch, scenes, serve, seconds):
-    """Poisson arrivals (200/s) of helix and muscle scenes of 1k-200k pills (log-uniform),
-    60 frames each; continuous batching vs the plain per-scene path on the same requests."""
+def serving_run(torch, scenes, serve, seconds, plain_limit):
+    """Poisson arrivals (200/s) of helix and muscle scenes of 1k-200k pills (log-uniform; muscle
+    scenes skinned, 4 mesh vertices per pill), 60 frames each; continuous batching vs the plain
+    per-scene path on the same requests (the plain path starts no request after `plain_limit`
+    s of wall time).  A scene that diverges is dropped by both paths at the same frame."""
+    t0 = time.perf_counter()
     reqs = scenes.serving_requests(rate=200, duration=seconds, seed=3)
-    b = serve.serve_batched(reqs, pool_bytes=32 << 30, progress=log)
+    gen_s = time.perf_counter() - t0
+    log("serving: %d requests built in %.1f s" % (len(reqs), gen_s))
+    b = serve.serve_batched(reqs, pool_bytes=64 << 30, progress=log)
     torch.cuda.synchronize()
-    p = serve.serve_plain(reqs, progress=log)
+    p = serve.serve_plain(reqs, progress=None, time_limit=plain_limit)
     keep = ("frames", "latency_ms_p50", "latency_ms_p99", "ttff_ms_p50", "ttff_ms_p99", "pill_frames_per_s", "wall_s")
+    fail = lambda r: {"requests": len(r["failed"]), "kinds": sorted({f["kind"] for f in r["failed"]}),
+                      "pills": int(sum(f["pills"] for f in r["failed"]))}
     return {"workload": "poisson200x%.2fs_1k-200k_60frames" % seconds, "requests": len(reqs),
             "pills": int(sum(r.desc.num_pills for r in reqs)),
             "contact_requests": int(sum(r.kind == "muscle" for r in reqs)),
-            "batched": {k: b[k] for k in keep + ("steps", "peak_resident_bytes", "per_class", "host_s")},
-            "plain": {k: p[k] for k in keep}}
+            "skinned_vertices": int(sum(r.mesh.rest_v.shape[0] for r in reqs if r.mesh is not None)),
+            "batched": dict({k: b[k] for k in keep + ("steps", "peak_resident_bytes", "per_class", "host_s")},
+                            failed=fail(b)),
+            "plain": dict({k: p[k] for k in keep + ("requests_served", "requests_not_served")}, failed=fail(p),
+                          time_limit_s=plain_limit)}
 
 
 def log(msg):
@@ -468,8 +531,12 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-contacts", action="store_true")
     ap.add_argument("--no-solvers", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=0.15,
+    ap.add_argument("--serve-seconds", type=float, default=1.0,
                     help="arrival window of the serving workload (Poisson, 200 requests/s)")
+    ap.add_argument("--plain-limit", type=float, default=30.0,
+                    help="wall seconds after which the plain serving path starts no further request")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="only the serving comparison (prints its JSON object)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="instead of the solver, time a plain device copy of this many MiB (the "
                          "reference kernel for scaling HBM byte counters)")
@@ -486,6 +553,10 @@ def main():
     torch.cuda.set_device(dev)
     if args.copy_mib:
         print(json.dumps(copy_reference(torch, dev, args.copy_mib, args.steps)), flush=True)
+        return
+    if args.serve_only:
+        from paper_1906_05260_amd import serve
+        print(json.dumps(serving_run(torch, scenes, serve, args.serve_seconds, args.plain_limit)), flush=True)
         return
     dt, sub, iters = 1.0 / 60.0, args.substeps, args.iters
     desc = scenes.helix_rods(args.rods, args.pills, seed=1)
@@ -537,10 +608,15 @@ def main():
     achieved = flop_launch / (kern_ms * 1e-3)
     workload = "helix%dx%d" % (args.rods, args.pills)
     kname = "rod_frame_kernel"
+    # the survey's estimate of the work, 2.5-3 kFLOP per pill-substep (midpoint), beside the
+    # count from the closed forms above
+    flop_survey = SURVEY_FLOP_PER_PILL_SUBSTEP * P * (sub if mode == viper.MODE_FRAME else 1)
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_VALU, "traffic": measured_traffic(kname + ("" if mode == viper.MODE_FRAME
                                                                                  else "_substep"), workload),
             "kernel": kname, "kernel_ms": kern_ms, "flop_per_launch": flop_launch,
+            "frac_at_survey_flop_count": flop_survey / (kern_ms * 1e-3) / PEAK_FP32_VALU,
+            "frac_of_packed_fp32_peak": achieved / 157.3e12,
             "algorithmic_bytes_per_launch": bytes_launch,
             "algorithmic_hbm_frac": bytes_launch / (kern_ms * 1e-3) / PEAK_HBM}
     out = {
@@ -574,6 +650,8 @@ def main():
         log("solvers done")
     out["bones"] = bones_timing(torch, viper, scenes, dev)
     log("bones done")
+    out["substep_kernel"] = substep_kernel_timing(torch, viper, scenes, dev)
+    log("substep kernel done")
     if not args.no_solvers:
         out["helix_16x"] = large_timing(torch, viper, scenes, dev)
         log("16x helix done")
@@ -585,7 +663,7 @@ def main():
     log("copy ceiling done")
     if not args.no_serve:
         from paper_1906_05260_amd import serve
-        out["serving"] = serving_run(torch, scenes, serve, args.serve_seconds)
+        out["serving"] = serving_run(torch, scenes, serve, args.serve_seconds, args.plain_limit)
         log("serving done")
         out["latency_ms_p50"] = out["serving"]["batched"]["latency_ms_p50"]
         out["latency_ms_p99"] = out["serving"]["batched"]["latency_ms_p99"]

@@ -190,9 +190,10 @@ viper_status viper_set_state(viper_scene scene, int32_t which, const void* src, 
 viper_status viper_get_contacts(viper_scene scene, int32_t* pairs, int32_t cap, int32_t* n, void* stream);
 
 /* Record of the last contact detection of a scene (Sec. 7.1 uniform grid).  The grid's cell
- * width is twice the cell radius: the top of the histogram bin (4 bins per octave) that
- * holds the 33rd-largest capsule bounding radius, so that at most 32 larger capsules exist;
- * those are kept in a list that every capsule searches besides its 27 neighbour cells.
+ * width is twice the cell radius: the largest capsule bounding radius of the histogram bin
+ * (4 bins per octave) that holds the 33rd-largest radius, so that at most 32 larger capsules
+ * exist (with no outliers, the largest radius of all); those are kept in a list that every
+ * capsule searches besides its 27 neighbour cells.
  * Capsules whose bounding sphere is not finite are left out and raise VIPER_ERR_NAN at
  * viper_sync; capsules with an end radius s r <= 0 (no surface while a scale passes through
  * zero) are left out too (no contact).  If the cell radius would exceed 4 times the largest

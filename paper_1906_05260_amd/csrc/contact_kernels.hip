@@ -3,9 +3,10 @@
 // Detection (Sec. 7.1, after Green 2010): each capsule (tapered pill primitive)
 // gets a bounding sphere; a uniform grid with cell width equal to the largest
 // sphere diameter guarantees that overlapping spheres sit in neighbouring cells.
-// The cell radius is not the single largest bounding radius: a histogram of the radii
-// sets it to the top of the bin that holds the (kOversized+1)-th largest, and the at most
-// kOversized larger capsules are kept in a short list that every capsule walks besides its
+// The cell radius is not the single largest bounding radius: a histogram of the radii finds
+// the bin that holds the (kOversized+1)-th largest, the cell radius is the largest radius of
+// that bin, and the at most kOversized larger capsules are kept in a short list that every
+// capsule walks besides its
 // neighbour cells (one stretched capsule would otherwise widen every cell of its scene and
 // make the walk quadratic).  A capsule whose bounding sphere is not finite is left out and
 // raises the scene's non-finite status; one with an end radius s r <= 0 (no surface) is left
@@ -214,8 +215,9 @@ __device__ __forceinline__ int radius_bin(double R) {
   return f < 0.0 ? 0 : (f > kRadBins - 1 ? kRadBins - 1 : (int)f);
 }
 
-// Upper edge of bin b (the top bin is unbounded).
-__device__ __forceinline__ double bin_top(int b) { return b >= kRadBins - 1 ? INFINITY : exp2(0.25 * (b - 95)); }
+// Cell width for cell radius rc (> every grid capsule's bounding radius; a zero radius, an
+// empty scene, gets a unit cell).
+__device__ __forceinline__ double cell_width_of(double rc) { return rc > 0.0 ? 2.0 * rc * (1.0 + 1e-6) : 1.0; }
 
 // Start of detection, one launch over max(pills, cells, capsules) items of each scene:
 // copy the detection state, reset the hash buckets, form every capsule's bounding sphere
@@ -224,13 +226,17 @@ template <class T>
 __global__ void __launch_bounds__(256) det_kernel(const Dev<T>* __restrict__ D, const ContactDev* __restrict__ CD,
                                                   const Blk* __restrict__ tab) {
   __shared__ int sh[kRadBins + 1];
+  __shared__ unsigned long long shm[kRadBins];
   BLOCK_SCENE(tab, D, CD)
   const int i = blk_.base + (int)threadIdx.x;
-  if (blk_.base == 0 && threadIdx.x == 0) {   // counters of this detection (last read by the previous one)
-    c.dcnt[0] = 0;
-    c.walk[0] = 0ull;
+  if (blk_.base == 0 && threadIdx.x < kWalkCounters) {   // counters of this detection (last read by the previous one)
+    if (threadIdx.x == 0) c.dcnt[0] = 0;
+    c.walk[threadIdx.x] = 0ull;
   }
-  for (int k = (int)threadIdx.x; k <= kRadBins; k += 256) sh[k] = 0;
+  for (int k = (int)threadIdx.x; k <= kRadBins; k += 256) {
+    sh[k] = 0;
+    if (k < kRadBins) shm[k] = 0ull;
+  }
   __syncthreads();
   if (i < d.P) {                       // detection state: FP64 world positions, scales
     world_pos(d, i, c.xdet + 3 * (size_t)i);
@@ -258,18 +264,33 @@ __global__ void __launch_bounds__(256) det_kernel(const Dev<T>* __restrict__ D, 
     else if (d.s[p] > T(0) && d.s[p + 1] > T(0)) bin = radius_bin(sp[3]);
     c.key[i] = bin;
     atomicAdd(&sh[bin], 1);
+    // largest radius of the bin (a positive double orders as its bit pattern)
+    if (bin < kRadBins) atomicMax(&shm[bin], (unsigned long long)__double_as_longlong(fmax(sp[3], 0.0)));
   }
   __syncthreads();
   for (int k = (int)threadIdx.x; k <= kRadBins; k += 256)
-    if (sh[k]) atomicAdd(&c.hist[k], sh[k]);
+    if (sh[k]) {
+      atomicAdd(&c.hist[k], sh[k]);
+      if (k < kRadBins) atomicMax(&c.binmax[k], shm[k]);
+    }
 }
 
-// Cell radius from the histogram: the top of the bin holding the (kOversized+1)-th largest
-// radius (bins above it hold at most kOversized capsules).  Returns that bin.
-__device__ int cell_bin(const int* h) {
-  int above = 0, b = kRadBins - 1;
-  while (b > 0 && above + h[b] <= kOversized) above += h[b--];
-  return b;
+// Cell bin from the histogram, by the first wavefront (64 lanes, two bins each): the bin
+// holding the (kOversized+1)-th largest radius, i.e. the highest bin b whose suffix count
+// (capsules in bins >= b) exceeds kOversized, or bin 0; bins above it hold at most
+// kOversized capsules.  The count of bins with such a suffix is a ballot.
+__device__ int cell_bin_wave(const int* h, int lane) {
+  static_assert(kRadBins == 128, "two bins per lane");
+  const int h0 = h[2 * lane], h1 = h[2 * lane + 1];
+  int t = h0 + h1;                      // suffix sum over lanes >= this one
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u = __shfl_down(t, o);
+    if (lane + o < 64) t += u;
+  }
+  const int s0 = t, s1 = t - h0;        // capsules in bins >= 2 lane, >= 2 lane + 1
+  const int n = __popcll(__ballot(s0 > kOversized)) + __popcll(__ballot(s1 > kOversized));
+  return n > 0 ? n - 1 : 0;
 }
 
 // Cell keys: a capsule in a bin up to the cell bin goes to its grid cell, a larger one to the
@@ -277,29 +298,36 @@ __device__ int cell_bin(const int* h) {
 // candidate counts of capsules that are not placed are cleared here, since no search
 // thread visits them.
 __global__ void __launch_bounds__(256) key_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
-  __shared__ int sh[kRadBins + 1];
+  __shared__ int sh[kRadBins];
   __shared__ int s_bin;
+  __shared__ double s_rc;
   const Blk b = tab[blockIdx.x];
   const ContactDev& c = CD[b.scene];
-  for (int k = (int)threadIdx.x; k <= kRadBins; k += 256) sh[k] = c.hist[k];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int cb = cell_bin(sh);
-    s_bin = cb;
-    if (b.base == 0) {                 // the detection's record, read back by viper_contact_stats
-      const bool skip = !(bin_top(cb) <= c.rlim);
-      c.dcnt[1] = skip;
-      c.dcnt[2] = sh[kRadBins];
-      c.dcnt[3] = cb;
-      c.cw[0] = skip ? 0.0 : 2.0 * bin_top(cb) * (1.0 + 1e-6);
-      if (skip) c.status[ST_DIVERGED] = 1;
+  if (threadIdx.x < 64) {
+    const int lane = (int)threadIdx.x;
+    sh[2 * lane] = c.hist[2 * lane];
+    sh[2 * lane + 1] = c.hist[2 * lane + 1];
+    const int cb = cell_bin_wave(sh, lane);
+    if (lane == 0) {
+      // the cell radius: the largest radius of the cell bin, i.e. of every capsule in the grid
+      const double rc = __longlong_as_double((long long)c.binmax[cb]);
+      s_bin = cb;
+      s_rc = rc;
+      if (b.base == 0) {               // the detection's record, read back by viper_contact_stats
+        const bool skip = !(rc <= c.rlim);
+        c.dcnt[1] = skip;
+        c.dcnt[2] = c.hist[kRadBins];
+        c.dcnt[3] = cb;
+        c.cw[0] = skip ? 0.0 : cell_width_of(rc);
+        if (skip) c.status[ST_DIVERGED] = 1;
+      }
     }
   }
   __syncthreads();
   const int i = b.base + (int)threadIdx.x;
   if (i >= c.E) return;
   const int cb = s_bin;
-  const double rc = bin_top(cb);
+  const double rc = s_rc;
   const int bin = c.key[i];
   if (!(rc <= c.rlim) || bin == kRadBins) {
     c.key[i] = -1;
@@ -311,7 +339,7 @@ __global__ void __launch_bounds__(256) key_kernel(const ContactDev* __restrict__
     c.key[i] = -2 - atomicAdd(&c.dcnt[0], 1);
     return;
   }
-  const double cw = 2.0 * rc * (1.0 + 1e-6);
+  const double cw = cell_width_of(rc);
   const int cx = cell_of(c.sph[4 * (size_t)i], cw), cy = cell_of(c.sph[4 * (size_t)i + 1], cw),
             cz = cell_of(c.sph[4 * (size_t)i + 2], cw);
   c.cell[3 * (size_t)i] = cx; c.cell[3 * (size_t)i + 1] = cy; c.cell[3 * (size_t)i + 2] = cz;
@@ -371,7 +399,10 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
       c.npairs[0] = min(total, c.cap);
       if (total > c.cap) c.status[ST_OVERFLOW] = 1;
     }
-    for (int k = (int)threadIdx.x; k <= kRadBins; k += 256) c.hist[k] = 0;
+    for (int k = (int)threadIdx.x; k <= kRadBins; k += 256) {
+      c.hist[k] = 0;
+      if (k < kRadBins) c.binmax[k] = 0ull;
+    }
   }
   // Each wavefront holds 7 whole capsules x 9 columns (lane 63 idles): a capsule's columns
   // and the balanced walk below stay inside one wavefront.  Wavefront w of the scene takes
@@ -455,7 +486,9 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
   if (lane == 63) s_off[wv][64] = incl;
   __syncthreads();
   const int W = s_off[wv][64];
-  if (!EMIT && lane == 0 && W > 0) atomicAdd(c.walk, (unsigned long long)W);
+  // walk length for the detection record: one add per wavefront, spread over kWalkCounters
+  // addresses so that the adds of a scene's wavefronts do not queue on one
+  if (!EMIT && lane == 0 && W > 0) atomicAdd(c.walk + ((blockIdx.x * kWaves + wv) & (kWalkCounters - 1)), (unsigned long long)W);
   for (int g0 = 0; g0 < W; g0 += 64 * kWalkItems) {
     int own[kWalkItems], jj[kWalkItems], dd[kWalkItems], bb[kWalkItems], rr[kWalkItems], gg[kWalkItems];
     long long kk[kWalkItems];
@@ -865,8 +898,9 @@ ContactOffsets contact_layout(size_t start, bool on, int P, int E, int cpc, bool
   o.cap_grp = take(4 * (size_t)E);
   o.sph = take(8 * 4 * (size_t)E);
   o.hist = take(4 * (size_t)(kRadBins + 1));
+  o.binmax = take(8 * (size_t)kRadBins);
   o.dcnt = take(4 * 4);
-  o.walk = take(8);
+  o.walk = take(8 * kWalkCounters);
   o.cw = take(8);
   o.key = take(4 * (size_t)E);
   o.cell = take(12 * (size_t)E);
@@ -926,6 +960,7 @@ viper_status contact_init(ContactDev& c, char* ws, const ContactOffsets& o, cons
   c.cap_grp = (int32_t*)(ws + o.cap_grp);
   c.sph = (double*)(ws + o.sph);
   c.hist = (int32_t*)(ws + o.hist);
+  c.binmax = (unsigned long long*)(ws + o.binmax);
   c.dcnt = (int32_t*)(ws + o.dcnt);
   c.walk = (unsigned long long*)(ws + o.walk);
   c.cw = (double*)(ws + o.cw);
@@ -956,7 +991,8 @@ viper_status contact_init(ContactDev& c, char* ws, const ContactOffsets& o, cons
       hipMemcpyAsync(c.cap_grp, grp.data(), 4 * grp.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemsetAsync(c.npairs, 0, 4, st) != hipSuccess ||
       hipMemsetAsync(c.hist, 0, 4 * (size_t)(kRadBins + 1), st) != hipSuccess ||
-      hipMemsetAsync(c.dcnt, 0, 16, st) != hipSuccess || hipMemsetAsync(c.walk, 0, 8, st) != hipSuccess ||
+      hipMemsetAsync(c.binmax, 0, 8 * (size_t)kRadBins, st) != hipSuccess ||
+      hipMemsetAsync(c.dcnt, 0, 16, st) != hipSuccess || hipMemsetAsync(c.walk, 0, 8 * kWalkCounters, st) != hipSuccess ||
       hipMemsetAsync(c.cw, 0, 8, st) != hipSuccess ||
       hipMemsetAsync(c.acc, 0, 8 * 4 * (size_t)c.P, st) != hipSuccess ||
       hipMemsetAsync(c.acnt, 0, 4 * (size_t)c.P, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
@@ -1085,13 +1121,15 @@ viper_status contact_get_pairs(const ContactDev& c, int32_t* pairs, int32_t cap,
 
 viper_status contact_get_info(const ContactDev& c, viper_contact_info* out, hipStream_t st) {
   int32_t cnt[4];
-  unsigned long long walk = 0;
+  unsigned long long walk[kWalkCounters];
   double cw = 0.0;
   if (hipMemcpyAsync(cnt, c.dcnt, 16, hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipMemcpyAsync(&walk, c.walk, 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(walk, c.walk, sizeof(walk), hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipMemcpyAsync(&cw, c.cw, 8, hipMemcpyDeviceToHost, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
     return VIPER_ERR_DEVICE;
-  out->walk_entries = (int64_t)walk;
+  unsigned long long total = 0;
+  for (int k = 0; k < kWalkCounters; ++k) total += walk[k];
+  out->walk_entries = (int64_t)total;
   out->oversized = cnt[0];
   out->skipped = cnt[1];
   out->excluded = cnt[2];

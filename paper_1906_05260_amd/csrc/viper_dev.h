@@ -76,6 +76,7 @@ constexpr int kSecFit = 20;
 
 constexpr int kRadBins = 128;     // bounding-radius histogram: 4 bins per octave, bin 96 starts at 1 m
 constexpr int kOversized = 32;    // at most this many capsules are larger than the cell radius
+constexpr int kWalkCounters = 64; // partial sums of the candidate walk length (a power of two)
 constexpr double kRadLimit = 4.0; // cell radius limit, in units of the largest bounding radius at rest
 
 // Contact buffers of one scene (device pointers into its workspace).
@@ -86,11 +87,12 @@ struct ContactDev {
   int32_t *cap_ids = nullptr, *cap_rod = nullptr, *cap_grp = nullptr;
   double* sph = nullptr;              // [E*4] mx my mz R
   // Grid sizing: a histogram of the bounding radii (kRadBins log-spaced bins, then one count of
-  // capsules whose sphere is not finite) sets the cell radius to the top of the bin holding
-  // the (kOversized+1)-th largest radius; larger capsules are walked from a list instead.
+  // capsules left out) finds the bin holding the (kOversized+1)-th largest radius; the cell
+  // radius is that bin's largest radius; larger capsules are walked from a list instead.
   int32_t* hist = nullptr;            // [kRadBins + 1]
+  unsigned long long* binmax = nullptr;  // [kRadBins] bits of the largest radius in each bin
   int32_t* dcnt = nullptr;            // [4] oversized, skipped, non-finite, cell-radius bin (last detection)
-  unsigned long long* walk = nullptr; // bucket entries examined by the last candidate count pass
+  unsigned long long* walk = nullptr; // [kWalkCounters] partial sums of the entries the last count pass examined
   double* cw = nullptr;               // cell width of the last detection (0 when skipped)
   double rlim = 0.0;                  // largest admitted cell radius (4x the largest at rest)
   int32_t *key = nullptr, *cell = nullptr;  // [E] radius bin, then hash key; [3E] integer cell coordinates

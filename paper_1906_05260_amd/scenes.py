@@ -168,7 +168,7 @@ MUSCLE_COMPLIANCE = (1e-7, 1e-8, 1e-8, 1e-5)     # stretch-shear, volume, scale 
 
 
 def muscle_scene(num_muscles=64, seed=2, target_pills=(45000, 55000), rods_range=(16, 48), pills_range=(8, 24),
-                 mesh_vertices=200000, spacing=0.01, compliance=MUSCLE_COMPLIANCE, bundling=False):
+                 mesh_vertices=200000, spacing=0.01, compliance=MUSCLE_COMPLIANCE, bundling=False, capsule_order=True):
     """Bundles of parallel rods ("muscles") packed side by side so that neighbours touch.
 
     Each muscle has U{16..48} rods of U{8..24} pills (all rods of a muscle share the
@@ -180,7 +180,8 @@ def muscle_scene(num_muscles=64, seed=2, target_pills=(45000, 55000), rods_range
     its volume, and with volume or scale-gradient compliances near 1e-4 the activation
     step drives some scales through zero (negative radii) within the first frames;
     ``compliance="loguniform"`` draws them log-uniform 1e-8..1e-4 per type and rod as
-    in the helix scene.  With ``bundling`` every muscle gets one cross-section per pill
+    in the helix scene.  ``capsule_order``: mesh vertices numbered by first capsule (see
+    ``muscle_mesh``).  With ``bundling`` every muscle gets one cross-section per pill
     index (that pill of each of its rods) for the shape matching of Sec. 7.3.  Returns (desc, mesh) with a skinning mesh of ``mesh_vertices`` vertices
     on the muscles' envelopes, 4 nearest capsules each, Dirichlet(1,1,1,1) weights.
     """
@@ -235,7 +236,7 @@ def muscle_scene(num_muscles=64, seed=2, target_pills=(45000, 55000), rods_range
     desc = SceneDesc(np.asarray(offs, np.int32), np.concatenate(xs), np.concatenate(rbs), np.concatenate(pins),
                      np.asarray(acts), np.asarray(comps), np.asarray(groups, np.int32), collisions=True,
                      name="muscles_%d" % num_muscles)
-    mesh = muscle_mesh(desc, muscle_info, mesh_vertices, rng) if mesh_vertices else None
+    mesh = muscle_mesh(desc, muscle_info, mesh_vertices, rng, capsule_order) if mesh_vertices else None
     desc.extra["muscles"] = muscle_info
     if bundling:
         # one cross-section per pill index of each muscle: pill k of every rod of the muscle
@@ -250,10 +251,11 @@ def muscle_scene(num_muscles=64, seed=2, target_pills=(45000, 55000), rods_range
     return desc, mesh
 
 
-def muscle_mesh(desc: SceneDesc, muscle_info, V, rng) -> SkinMesh:
-    """Vertices on each muscle's envelope cylinder (count proportional to its pills), in
-    order along the muscle's axis; influences = the 4 nearest capsules of that muscle at
-    rest, Dirichlet(1,1,1,1) weights."""
+def muscle_mesh(desc: SceneDesc, muscle_info, V, rng, capsule_order=True) -> SkinMesh:
+    """Vertices on each muscle's envelope cylinder (count proportional to its pills);
+    influences = the 4 nearest capsules of that muscle at rest, Dirichlet(1,1,1,1) weights.
+    Each muscle's vertices are numbered in the order of their first capsule (capsule_order;
+    otherwise along the muscle's axis, random around it)."""
     offs = desc.rod_offsets
     pills = np.array([sum(int(offs[k + 1] - offs[k]) for k in mi["rods"]) for mi in muscle_info], dtype=np.float64)
     counts = np.floor(V * pills / pills.sum()).astype(np.int64)
@@ -271,13 +273,20 @@ def muscle_mesh(desc: SceneDesc, muscle_info, V, rng) -> SkinMesh:
         rr = mi["radius"] + 0.004
         p = np.stack([xx, mi["centre"][0] + mi["tilt"][0] * xx + rr * np.cos(th),
                       mi["centre"][1] + mi["tilt"][1] * xx + rr * np.sin(th)], axis=1)
+        mc = []
         for c0 in range(0, nv, 4096):
             pc = p[c0:c0 + 4096]
             d2 = ((pc[:, None, :] - mids[None, :, :]) ** 2).sum(-1)
             nn = np.argsort(d2, axis=1, kind="stable")[:, :4]
-            cp.append(caps[nn])
-        rv.append(p)
-        ww.append(rng.dirichlet(np.ones(4), nv))
+            mc.append(caps[nn])
+        mc = np.concatenate(mc)
+        wm = rng.dirichlet(np.ones(4), nv)
+        # vertices renumbered in the order of their first capsule (stable), as a mesh pipeline
+        # orders vertices for the skinning pass: neighbouring vertices then share transforms
+        o = np.argsort(mc[:, 0], kind="stable") if capsule_order else np.arange(nv)
+        rv.append(p[o])
+        cp.append(mc[o])
+        ww.append(wm[o])
     return SkinMesh(np.concatenate(rv).astype(np.float32), np.concatenate(cp).astype(np.int32),
                     np.concatenate(ww).astype(np.float32))
 
