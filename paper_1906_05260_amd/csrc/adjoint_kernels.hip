@@ -371,8 +371,9 @@ __device__ __forceinline__ void ckpt_io(T* base, size_t P, int p, Slot<T>& L, bo
 }
 
 // The frame kernel with the state at the start of every substep written to ckpt
-// ([substep][field][pill]).
-template <class T>
+// ([substep][field][pill]).  EVEN as in the frame kernel (the same instantiation of the
+// passes, so that both give the same bits).
+template <class T, bool EVEN>
 __global__ void __launch_bounds__(256) rod_frame_ckpt_kernel(const Dev<T>* __restrict__ D, const Blk* __restrict__ tab,
                                                              int nsub, T h, int iters, T* __restrict__ ckpt) {
   Lane2<T> P;
@@ -391,7 +392,7 @@ __global__ void __launch_bounds__(256) rod_frame_ckpt_kernel(const Dev<T>* __res
     predict_slot(P.A, h, d.gx, d.gy, d.gz);
     predict_slot(P.B, h, d.gx, d.gy, d.gz);
     inertia_lane(P);
-    for (int it = 0; it < iters; ++it) iteration_lane(P);
+    for (int it = 0; it < iters; ++it) iteration_lane<T, false, EVEN>(P);
     velocity_slot(P.A, ih);
     velocity_slot(P.B, ih);
   }
@@ -426,7 +427,7 @@ __device__ __forceinline__ const Dev<T>* lane_setup_rep(const Dev<T>* D, const B
   return d;
 }
 
-template <class T>
+template <class T, bool EVEN>
 __global__ void __launch_bounds__(64 * kReps) rod_backward_kernel(const Dev<T>* __restrict__ D, const Blk* __restrict__ tab,
                                                            T h, int iters, const T* __restrict__ ckpt, T* __restrict__ snap,
                                                            T* __restrict__ adj, T* __restrict__ padj) {
@@ -454,7 +455,7 @@ __global__ void __launch_bounds__(64 * kReps) rod_backward_kernel(const Dev<T>* 
   for (int it = 0; it < iters; ++it) {
     for (int k = 0; k < 4; ++k) {
       if (writer) snap_io(snap + ((size_t)(it * 4 + k) * 32) * NL + lg, NL, P.A, P.B, true);
-      if (k < 2) pass_edges(P, k); else pass_bt(P, k - 2);
+      if (k < 2) pass_edges<T, false, EVEN>(P, k); else pass_bt<T, EVEN>(P, k - 2);
     }
   }
   velocity_slot(P.A, ih);
@@ -596,8 +597,12 @@ __global__ void adjoint_chain_kernel(const Dev<T>* __restrict__ D, const T* __re
 template <class T>
 hipError_t launch_frame_ckpt(const BatchDev& b, int nsub, double h, int iters, T* ckpt, hipStream_t st) {
   if (b.nblk[TB_WAVES] == 0) return hipSuccess;
-  hipLaunchKernelGGL(rod_frame_ckpt_kernel<T>, dim3(b.nblk[TB_WAVES]), dim3(256), 0, st, (const Dev<T>*)b.dev,
-                     b.tab[TB_WAVES], nsub, (T)h, iters, ckpt);
+  if (b.even)
+    hipLaunchKernelGGL((rod_frame_ckpt_kernel<T, true>), dim3(b.nblk[TB_WAVES]), dim3(256), 0, st, (const Dev<T>*)b.dev,
+                       b.tab[TB_WAVES], nsub, (T)h, iters, ckpt);
+  else
+    hipLaunchKernelGGL((rod_frame_ckpt_kernel<T, false>), dim3(b.nblk[TB_WAVES]), dim3(256), 0, st, (const Dev<T>*)b.dev,
+                       b.tab[TB_WAVES], nsub, (T)h, iters, ckpt);
   return hipGetLastError();
 }
 
@@ -606,9 +611,15 @@ hipError_t launch_backward(const BatchDev& b, int P, int nsub, double h, int ite
                            T* snap, T* adj, T* padj, double rho, double* drbar, double* dact, hipStream_t st) {
   if (P == 0) return hipSuccess;
   hipLaunchKernelGGL(adjoint_seed_kernel<T>, dim3((P + 255) / 256), dim3(256), 0, st, P, dldx, adj, padj);
-  for (int sub = nsub - 1; sub >= 0; --sub)
-    hipLaunchKernelGGL(rod_backward_kernel<T>, dim3(4 * b.nblk[TB_WAVES]), dim3(64 * kReps), 0, st, (const Dev<T>*)b.dev,
-                       b.tab[TB_WAVES], (T)h, iters, ckpt + (size_t)sub * kCkptFields * P, snap, adj, padj);
+  for (int sub = nsub - 1; sub >= 0; --sub) {
+    const T* ck = ckpt + (size_t)sub * kCkptFields * P;
+    if (b.even)
+      hipLaunchKernelGGL((rod_backward_kernel<T, true>), dim3(4 * b.nblk[TB_WAVES]), dim3(64 * kReps), 0, st,
+                         (const Dev<T>*)b.dev, b.tab[TB_WAVES], (T)h, iters, ck, snap, adj, padj);
+    else
+      hipLaunchKernelGGL((rod_backward_kernel<T, false>), dim3(4 * b.nblk[TB_WAVES]), dim3(64 * kReps), 0, st,
+                         (const Dev<T>*)b.dev, b.tab[TB_WAVES], (T)h, iters, ck, snap, adj, padj);
+  }
   hipLaunchKernelGGL(adjoint_chain_kernel<T>, dim3((P + 255) / 256), dim3(256), 0, st, (const Dev<T>*)b.dev,
                      (const T*)padj, rho, drbar, dact);
   return hipGetLastError();

@@ -33,6 +33,18 @@ template <> __device__ __forceinline__ double up<double>(double v) {
   return __hiloint2double(dpp_up(__double2hiint(v)), dpp_up(__double2loint(v)));
 }
 
+// q <- normalize(q + [a, 0] (x) q): rotate by the world-frame vector 2a (a = half the
+// rotation vector).
+template <class T>
+__device__ __forceinline__ void qrot_world_half(T& x, T& y, T& z, T& w, T a0, T a1, T a2) {
+  const T nx = x + (w * a0 + (a1 * z - a2 * y));
+  const T ny = y + (w * a1 + (a2 * x - a0 * z));
+  const T nz = z + (w * a2 + (a0 * y - a1 * x));
+  const T nw = w - (a0 * x + a1 * y + a2 * z);
+  const T in = rsq(nx * nx + ny * ny + nz * nz + nw * nw);
+  x = nx * in; y = ny * in; z = nz * in; w = nw * in;
+}
+
 // q <- normalize(q + 1/2 [t, 0] (x) q): rotate by the world-frame vector t.
 template <class T>
 __device__ __forceinline__ void qrot_world(T& x, T& y, T& z, T& w, T t0, T t1, T t2) {
@@ -161,8 +173,9 @@ __device__ __forceinline__ void edge_update(Slot<T>& L, T& b0, T& b1, T& b2, T& 
     const T fa = wa * ilb, fb = wb * ilb;
     a0 -= fa * g0; a1 -= fa * g1; a2 -= fa * g2;
     b0 += fb * g0; b1 += fb * g1; b2 += fb * g2;
-    const T nI = -L.I1;   // dtheta = -(d3 x dl) / I_bend
-    qrot_world(L.q0, L.q1, L.q2, L.q3, nI * (d1 * g2 - d2 * g1), nI * (d2 * g0 - d0 * g2), nI * (d0 * g1 - d1 * g0));
+    const T nI = T(-0.5) * L.I1;   // dtheta = -(d3 x dl) / I_bend, halved for the quaternion update
+    qrot_world_half(L.q0, L.q1, L.q2, L.q3, nI * (d1 * g2 - d2 * g1), nI * (d2 * g0 - d0 * g2),
+                    nI * (d0 * g1 - d1 * g0));
   }
   if (L.f & F_VOL) {
     const T e0 = b0 - a0, e1 = b1 - a1, e2 = b2 - a2;
@@ -223,28 +236,32 @@ __device__ __forceinline__ void bt_update(Slot<T>& L, T& b0, T& b1, T& b2, T& b3
   const T t0 = T(2) * (v0 * v2 + w * v1);
   const T t1 = T(2) * (v1 * v2 - w * v0);
   const T t2 = T(1) - T(2) * (v0 * v0 + v1 * v1);
-  const T u0 = -v1, u1 = v0, u2 = w;
   const T y0 = w * t0 - (v1 * t2 - v2 * t1);
   const T y1 = w * t1 - (v2 * t0 - v0 * t2);
   const T y2 = w * t2 - (v0 * t1 - v1 * t0);
-  // S = K[(Ia+Ib)(I - v v^T) - Ia/2 u u^T - Ib/2 y y^T] + wsb c^2 v v^T + diag(a, a, a/2)
+  // S = K[(Ia+Ib)(I - v v^T) - Ia/2 u u^T - Ib/2 y y^T] + wsb c^2 v v^T + diag(a, a, a/2),
+  // assembled directly as s = S / (m + a), m = K (Ia + Ib): the entries reach ~1e14 for thin
+  // rods and the cubic determinant would leave the FP32 range; scaled they are O(1) (each
+  // term of S is at most of the order of m or a).  S^-1 = adj(s) / (det(s) (m + a)).
+  //   s = I - diag(0, 0, a/2) sgm + qs v v^T - has u u^T - hbs y y^T,  u = (-v1, v0, w)
   const T Ia = L.I1;
   const T K = T(0.25) * sc * sc;
   const T m = K * (Ia + Ib);
-  const T ha = T(0.5) * K * Ia, hb = T(0.5) * K * Ib;
-  const T qv = wsb * c * c - m;
   const T at = L.abt;
-  const T S00 = m + qv * v0 * v0 - ha * u0 * u0 - hb * y0 * y0 + at;
-  const T S11 = m + qv * v1 * v1 - ha * u1 * u1 - hb * y1 * y1 + at;
-  const T S22 = m + qv * v2 * v2 - ha * u2 * u2 - hb * y2 * y2 + T(0.5) * at;
-  const T S01 = qv * v0 * v1 - ha * u0 * u1 - hb * y0 * y1;
-  const T S02 = qv * v0 * v2 - ha * u0 * u2 - hb * y0 * y2;
-  const T S12 = qv * v1 * v2 - ha * u1 * u2 - hb * y1 * y2;
+  const T sgm = rcp(m + at);
+  const T qs = (wsb * c * c - m) * sgm;
+  const T kh = T(0.5) * K * sgm;
+  const T has = kh * Ia, hbs = kh * Ib;
+  const T pv0 = qs * v0, pv1 = qs * v1, pv2 = qs * v2;
+  const T hv0 = has * v0, hv1 = has * v1, hw = has * w;
+  const T py0 = hbs * y0, py1 = hbs * y1, py2 = hbs * y2;
+  const T s00 = T(1) + pv0 * v0 - hv1 * v1 - py0 * y0;
+  const T s11 = T(1) + pv1 * v1 - hv0 * v0 - py1 * y1;
+  const T s22 = (T(1) - T(0.5) * at * sgm) + pv2 * v2 - hw * w - py2 * y2;
+  const T s01 = pv0 * v1 + hv1 * v0 - py0 * y1;
+  const T s02 = pv0 * v2 + hv1 * w - py0 * y2;
+  const T s12 = pv1 * v2 - hv0 * w - py1 * y2;
   const T r0 = -C0 - at * L.l[5], r1 = -C1 - at * L.l[6], r2 = -C2 - T(0.5) * at * L.l[7];
-  // The entries reach ~1e14 for thin rods; equilibrate by the trace so that the
-  // cubic determinant stays inside the FP32 range.  S^-1 = adj(sS) s / det(sS).
-  const T sgm = rcp(S00 + S11 + S22);
-  const T s00 = S00 * sgm, s11 = S11 * sgm, s22 = S22 * sgm, s01 = S01 * sgm, s02 = S02 * sgm, s12 = S12 * sgm;
   const T A00 = s11 * s22 - s12 * s12, A01 = s02 * s12 - s01 * s22, A02 = s01 * s12 - s02 * s11;
   const T A11 = s00 * s22 - s02 * s02, A12 = s01 * s02 - s00 * s12, A22 = s00 * s11 - s01 * s01;
   const T idet = sgm * rcp(s00 * A00 + s01 * A01 + s02 * A02);
@@ -257,16 +274,14 @@ __device__ __forceinline__ void bt_update(Slot<T>& L, T& b0, T& b1, T& b2, T& b3
   const T e1 = w * g1 + (v2 * g0 - v0 * g2);
   const T e2 = w * g2 + (v0 * g1 - v1 * g0);
   const T hs = T(0.5) * sc;
-  // body-frame (a) rotation of edge a: -hs Ia (e - e_z e_z/2)
-  const T ka = -hs * Ia;
-  const T da0 = ka * e0, da1 = ka * e1, da2 = T(0.5) * ka * e2;
-  // frame-a rotation of edge b: hs Ib (e - (t.e) t / 2)
+  // body-frame (a) rotation of edge a: da = -hs Ia (e - e_z e_z/2); h = da / 2
+  const T ka = T(-0.5) * hs * Ia;
+  // frame-a rotation of edge b: dB = hs Ib (e - (t.e) t / 2); h = sg dB / 2
   const T te = T(0.5) * (t0 * e0 + t1 * e1 + t2 * e2);
-  const T kb = hs * Ib;
-  const T dB0 = kb * (e0 - te * t0), dB1 = kb * (e1 - te * t1), dB2 = kb * (e2 - te * t2);
+  const T kb = T(0.5) * sg * hs * Ib;
   // q_a <- normalize(q_a + 1/2 q_a (x) [da, 0])
   {
-    const T h0 = T(0.5) * da0, h1 = T(0.5) * da1, h2 = T(0.5) * da2;
+    const T h0 = ka * e0, h1 = ka * e1, h2 = T(0.5) * ka * e2;
     const T nx = a0 + (a3 * h0 + (a1 * h2 - a2 * h1));
     const T ny = a1 + (a3 * h1 + (a2 * h0 - a0 * h2));
     const T nz = a2 + (a3 * h2 + (a0 * h1 - a1 * h0));
@@ -276,7 +291,7 @@ __device__ __forceinline__ void bt_update(Slot<T>& L, T& b0, T& b1, T& b2, T& b3
   }
   // q_b <- normalize(q_b + 1/2 q_a (x) [dB, 0] (x) r_true),  r_true = sg (v, w)
   {
-    const T h0 = T(0.5) * sg * dB0, h1 = T(0.5) * sg * dB1, h2 = T(0.5) * sg * dB2;
+    const T h0 = kb * (e0 - te * t0), h1 = kb * (e1 - te * t1), h2 = kb * (e2 - te * t2);
     const T p0 = w * h0 + (h1 * v2 - h2 * v1);
     const T p1 = w * h1 + (h2 * v0 - h0 * v2);
     const T p2 = w * h2 + (h0 * v1 - h1 * v0);
@@ -368,9 +383,24 @@ __device__ __forceinline__ void vb_update(Slot<T>& L, T& b0, T& b1, T& b2, T& b3
 
 __device__ __forceinline__ bool colour_is(uint32_t f, int colour) { return ((f & F_ODD) != 0) == (colour != 0); }
 
-// Stretch-shear, volume and scale gradient of every edge of parity `colour`.
-template <class T, bool X = false>
+// Stretch-shear, volume and scale gradient of every edge of parity `colour`.  EVEN: every rod
+// of the batch starts on an even slot of its wavefront, so slot A holds the even pills: the
+// even edges are lane-local (A to B) and the odd ones all join slot B to the next lane's A.
+template <class T, bool X = false, bool EVEN = false>
 __device__ __forceinline__ void pass_edges(Lane2<T>& P, int colour) {
+  if constexpr (EVEN) {
+    if (colour == 0) {
+      if (P.A.f & F_EDGE) edge_update<T, X>(P.A, P.B.x0, P.B.x1, P.B.x2, P.B.s, P.B.w, P.B.ws);
+      return;
+    }
+    T n0 = dn(P.A.x0), n1 = dn(P.A.x1), n2 = dn(P.A.x2), ns = dn(P.A.s);
+    if (P.B.f & F_EDGE) edge_update<T, X>(P.B, n0, n1, n2, ns, P.wN, P.wsN);
+    n0 = up(n0); n1 = up(n1); n2 = up(n2); ns = up(ns);
+    if ((P.A.f & F_VALID) && !(P.A.f & F_FIRST)) {
+      P.A.x0 = n0; P.A.x1 = n1; P.A.x2 = n2; P.A.s = ns;
+    }
+    return;
+  }
   T n0 = dn(P.A.x0), n1 = dn(P.A.x1), n2 = dn(P.A.x2), ns = dn(P.A.s);
   if ((P.A.f & F_EDGE) && colour_is(P.A.f, colour)) {
     edge_update<T, X>(P.A, P.B.x0, P.B.x1, P.B.x2, P.B.s, P.B.w, P.B.ws);
@@ -385,8 +415,22 @@ __device__ __forceinline__ void pass_edges(Lane2<T>& P, int colour) {
 }
 
 // Bend-twist at every vertex of parity `colour` (between the slot's edge and the next).
-template <class T>
+// EVEN: as for pass_edges.
+template <class T, bool EVEN = false>
 __device__ __forceinline__ void pass_bt(Lane2<T>& P, int colour) {
+  if constexpr (EVEN) {
+    if (colour == 0) {
+      if ((P.A.f & F_BT) && (P.A.f & F_BTEN)) bt_update(P.A, P.B.q0, P.B.q1, P.B.q2, P.B.q3, P.B.s, P.B.I1, P.B.ws);
+      return;
+    }
+    T n0 = dn(P.A.q0), n1 = dn(P.A.q1), n2 = dn(P.A.q2), n3 = dn(P.A.q3), ns = dn(P.A.s);
+    if ((P.B.f & F_BT) && (P.B.f & F_BTEN)) bt_update(P.B, n0, n1, n2, n3, ns, P.I1N, P.wsN);
+    n0 = up(n0); n1 = up(n1); n2 = up(n2); n3 = up(n3); ns = up(ns);
+    if ((P.A.f & F_EDGE) && !(P.A.f & F_FIRST) && (P.A.f & F_BTEN)) {
+      P.A.q0 = n0; P.A.q1 = n1; P.A.q2 = n2; P.A.q3 = n3; P.A.s = ns;
+    }
+    return;
+  }
   T n0 = dn(P.A.q0), n1 = dn(P.A.q1), n2 = dn(P.A.q2), n3 = dn(P.A.q3), ns = dn(P.A.s);
   if ((P.A.f & F_BT) && (P.A.f & F_BTEN) && colour_is(P.A.f, colour)) {
     bt_update(P.A, P.B.q0, P.B.q1, P.B.q2, P.B.q3, P.B.s, P.B.I1, P.B.ws);
@@ -460,12 +504,12 @@ __device__ __forceinline__ void pass_sb(Lane2<T>& P, int colour) {
 
 // One Gauss-Seidel iteration.  X: the optional terms (cross-section stretch, volume-bending
 // coupling, surface bending) are compiled in; the plain instantiation runs scenes without them.
-template <class T, bool X = false>
+template <class T, bool X = false, bool EVEN = false>
 __device__ __forceinline__ void iteration_lane(Lane2<T>& P) {
-  pass_edges<T, X>(P, 0);
-  pass_edges<T, X>(P, 1);
-  pass_bt(P, 0);
-  pass_bt(P, 1);
+  pass_edges<T, X, EVEN>(P, 0);
+  pass_edges<T, X, EVEN>(P, 1);
+  pass_bt<T, EVEN>(P, 0);
+  pass_bt<T, EVEN>(P, 1);
   if constexpr (X) {
     if (P.vb) {   // the same on every lane of the wavefront
       pass_vb(P, 0);

@@ -29,8 +29,9 @@ namespace viper {
 // ---------------------------------------------------------------- kernels
 
 // FRAME / SUBSTEP mode: nsub substeps with the rod state in registers.  X: the optional
-// constraint terms are compiled in (chosen per batch on the host).
-template <class T, bool X>
+// constraint terms are compiled in; EVEN: every rod starts on an even slot of its wavefront
+// (both chosen per batch on the host).
+template <class T, bool X, bool EVEN>
 __global__ void __launch_bounds__(256) rod_frame_kernel(const Dev<T>* __restrict__ D, const Blk* __restrict__ tab,
                                                         int nsub, T h, int iters) {
   Lane2<T> P;
@@ -46,7 +47,7 @@ __global__ void __launch_bounds__(256) rod_frame_kernel(const Dev<T>* __restrict
     predict_slot(P.A, h, d.gx, d.gy, d.gz);
     predict_slot(P.B, h, d.gx, d.gy, d.gz);
     inertia_lane(P);
-    for (int it = 0; it < iters; ++it) iteration_lane<T, X>(P);
+    for (int it = 0; it < iters; ++it) iteration_lane<T, X, EVEN>(P);
     velocity_slot(P.A, ih);
     velocity_slot(P.B, ih);
   }
@@ -204,7 +205,7 @@ __device__ __forceinline__ void jacobi_lane(Lane2<T>& P) {
   jacobi_apply(P.B, aB);
 }
 
-template <class T, bool X>
+template <class T, bool X, bool EVEN>
 __global__ void __launch_bounds__(256) rod_iteration_kernel(const Dev<T>* __restrict__ D, const Blk* __restrict__ tab,
                                                             T h, const ContactDev* __restrict__ CD) {
   Lane2<T> P;
@@ -226,7 +227,7 @@ __global__ void __launch_bounds__(256) rod_iteration_kernel(const Dev<T>* __rest
   load_lane_consts<T, X>(d, P, pA, pB, rcp(h * h));
   P.I1N = dn(P.A.I1);
   if (d.jacobi) jacobi_lane<T, X>(P);       // wave-uniform: one scene per block
-  else iteration_lane<T, X>(P);
+  else iteration_lane<T, X, EVEN>(P);
   store_iter<T, X>(d, P.A, pA);
   store_iter<T, X>(d, P.B, pB);
 }
@@ -382,14 +383,20 @@ __global__ void __launch_bounds__(256) lbs_kernel(int V, const float* __restrict
 
 // ---------------------------------------------------------------- launchers
 
+template <class T, bool X, bool EVEN>
+void launch_rod_frame_as(const BatchDev& b, int nsub, double h, int iters, hipStream_t st) {
+  hipLaunchKernelGGL((rod_frame_kernel<T, X, EVEN>), dim3(b.nblk[TB_WAVES]), dim3(256), 0, st, (const Dev<T>*)b.dev,
+                     b.tab[TB_WAVES], nsub, (T)h, iters);
+}
 template <class T> hipError_t launch_rod_frame(const BatchDev& b, int nsub, double h, int iters, hipStream_t st) {
   if (b.nblk[TB_WAVES] == 0) return hipSuccess;
-  if (b.extras)
-    hipLaunchKernelGGL((rod_frame_kernel<T, true>), dim3(b.nblk[TB_WAVES]), dim3(256), 0, st, (const Dev<T>*)b.dev,
-                       b.tab[TB_WAVES], nsub, (T)h, iters);
-  else
-    hipLaunchKernelGGL((rod_frame_kernel<T, false>), dim3(b.nblk[TB_WAVES]), dim3(256), 0, st, (const Dev<T>*)b.dev,
-                       b.tab[TB_WAVES], nsub, (T)h, iters);
+  if (b.extras) {
+    if (b.even) launch_rod_frame_as<T, true, true>(b, nsub, h, iters, st);
+    else launch_rod_frame_as<T, true, false>(b, nsub, h, iters, st);
+  } else {
+    if (b.even) launch_rod_frame_as<T, false, true>(b, nsub, h, iters, st);
+    else launch_rod_frame_as<T, false, false>(b, nsub, h, iters, st);
+  }
   return hipGetLastError();
 }
 template <class T> hipError_t launch_predict(const BatchDev& b, double h, hipStream_t st) {
@@ -398,14 +405,20 @@ template <class T> hipError_t launch_predict(const BatchDev& b, double h, hipStr
                      b.tab[TB_WAVES], (T)h);
   return hipGetLastError();
 }
+template <class T, bool X, bool EVEN>
+void launch_rod_iteration_as(const BatchDev& b, double h, const ContactDev* cd, hipStream_t st) {
+  hipLaunchKernelGGL((rod_iteration_kernel<T, X, EVEN>), dim3(b.nblk[TB_WAVES]), dim3(256), 0, st, (const Dev<T>*)b.dev,
+                     b.tab[TB_WAVES], (T)h, cd);
+}
 template <class T> hipError_t launch_rod_iteration(const BatchDev& b, double h, const ContactDev* cd, hipStream_t st) {
   if (b.nblk[TB_WAVES] == 0) return hipSuccess;
-  if (b.extras)
-    hipLaunchKernelGGL((rod_iteration_kernel<T, true>), dim3(b.nblk[TB_WAVES]), dim3(256), 0, st, (const Dev<T>*)b.dev,
-                       b.tab[TB_WAVES], (T)h, cd);
-  else
-    hipLaunchKernelGGL((rod_iteration_kernel<T, false>), dim3(b.nblk[TB_WAVES]), dim3(256), 0, st, (const Dev<T>*)b.dev,
-                       b.tab[TB_WAVES], (T)h, cd);
+  if (b.extras) {
+    if (b.even) launch_rod_iteration_as<T, true, true>(b, h, cd, st);
+    else launch_rod_iteration_as<T, true, false>(b, h, cd, st);
+  } else {
+    if (b.even) launch_rod_iteration_as<T, false, true>(b, h, cd, st);
+    else launch_rod_iteration_as<T, false, false>(b, h, cd, st);
+  }
   return hipGetLastError();
 }
 template <class T> hipError_t launch_velocity(const BatchDev& b, double h, const ContactDev* cd, hipStream_t st) {

@@ -80,6 +80,7 @@ struct Host {
   std::vector<double> sbc, sbg0, sbg2;   // surface bending: compliance scaling, dC/ds_j-1, dC/ds_j+1
   std::vector<double> vbc;               // volume-bending coupling: compliance scaling
   bool any_sr = false, any_sb = false;
+  bool even = true;                      // every rod starts on an even slot of its wavefront
   std::vector<double> bone_rest, pill_bone_w;   // bones: rest transforms, two weights per pill
   std::vector<int32_t> pill_bone;
   // bundling sections: offsets, pills, section of each entry, world rest position of each entry
@@ -192,8 +193,9 @@ viper_status validate(const viper_scene_desc* d) {
   return VIPER_OK;
 }
 
-int pack_waves(const viper_scene_desc* d, std::vector<int32_t>& ws) {
+int pack_waves(const viper_scene_desc* d, std::vector<int32_t>& ws, bool& even) {
   ws.clear();
+  even = true;
   int start = 0, n = 0;
   for (int k = 0; k < d->num_rods; ++k) {
     int len = d->rod_offsets[k + 1] - d->rod_offsets[k];
@@ -202,6 +204,7 @@ int pack_waves(const viper_scene_desc* d, std::vector<int32_t>& ws) {
       start = d->rod_offsets[k];
       n = 0;
     }
+    if (n & 1) even = false;   // this rod starts on an odd slot of its wavefront
     n += len;
   }
   if (d->num_rods > 0) ws.push_back(start);
@@ -347,7 +350,7 @@ void build_host(const viper_scene_desc* d, Host& H) {
   }
   H.group.resize(H.R);
   for (int k = 0; k < H.R; ++k) H.group[k] = d->group ? d->group[k] : k;
-  H.W = pack_waves(d, H.wave_start);
+  H.W = pack_waves(d, H.wave_start, H.even);
   H.x.assign(d->rest_pos, d->rest_pos + 3 * (size_t)P);
   if (d->num_sections > 0) {
     const int NS = d->num_sections, NP = d->section_offsets[NS];
@@ -498,6 +501,7 @@ struct viper_scene_s {
   int nbones = 0;             // kinematic bones
   int surface_bending = 0;    // some rod has the surface-bending constraint
   int volume_bending = 0;     // the volume-bending coupling is on
+  int even = 0;               // every rod starts on an even slot of its wavefront
   double floor_n[3] = {0.0, 0.0, 0.0}, floor_d = 0.0;
   int cap = 16;
   int R = 0, P = 0, W = 0, E = 0;
@@ -702,6 +706,9 @@ viper_status step_t(viper_scene_s* S, double dt, int sub, int iters, int mode, h
   return VIPER_OK;
 }
 
+// Some optional constraint term is on (the rod kernels' instantiation with them compiled in).
+bool scene_extras(const viper_scene_s* S) { return S->cross_stretch || S->surface_bending || S->volume_bending; }
+
 Counts scene_counts(const viper_scene_s* S) {
   Counts c;
   c.W = S->W; c.P = S->P; c.E = S->E; c.T = S->collisions ? S->cd.T : contact_table_size(S->E);
@@ -724,7 +731,8 @@ viper_status viper_scene_footprint(const viper_scene_desc* desc, size_t* bytes) 
   if (s != VIPER_OK) return s;
   if (!bytes) return fail(VIPER_ERR_INVALID, "bytes is NULL");
   std::vector<int32_t> ws;
-  int W = pack_waves(desc, ws);
+  bool even;
+  int W = pack_waves(desc, ws, even);
   int P = desc->num_rods ? desc->rod_offsets[desc->num_rods] : 0;
   int E = P - desc->num_rods;
   int cap = desc->contact_capacity_per_capsule > 0 ? desc->contact_capacity_per_capsule : 16;
@@ -754,6 +762,7 @@ viper_status viper_create_scene(const viper_scene_desc* desc, void* workspace, s
   S->cross_stretch = H.any_sr ? 1 : 0;
   S->surface_bending = H.any_sb ? 1 : 0;
   S->volume_bending = desc->volume_bending != 0;
+  S->even = H.even ? 1 : 0;
   S->nbones = desc->num_bones > 0 ? desc->num_bones : 0;
   if (desc->floor_on) {
     const double* n = desc->floor_normal;
@@ -787,7 +796,8 @@ viper_status viper_create_scene(const viper_scene_desc* desc, void* workspace, s
     const size_t dsz = S->precision == VIPER_F64 ? sizeof(Dev<double>) : sizeof(Dev<float>);
     build_header(S->header, std::vector<const void*>{dv}, dsz, std::vector<ContactDev>{S->cd},
                  std::vector<Counts>{scene_counts(S)}, S->ws + o.header, S->batch);
-    S->batch.extras = S->cross_stretch || S->surface_bending || S->volume_bending;
+    S->batch.extras = scene_extras(S);
+    S->batch.even = S->even != 0;
     if (hipMemcpyAsync(S->ws + o.header, S->header.data(), S->header.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
       r = fail(VIPER_ERR_DEVICE, "header upload failed");
@@ -1284,10 +1294,13 @@ viper_status pool_rebuild(viper_pool_s* P, bool contact, hipStream_t st) {
   std::vector<ContactDev> cc;
   std::vector<Counts> vc;
   std::vector<int32_t> slot_of;
+  bool extras = false, even = true;
   for (int i = 0; i < (int)P->slots.size(); ++i) {
     const PoolSlot& sl = P->slots[i];
     if (!sl.scene || (sl.scene->collisions != 0) != contact) continue;
     viper_scene_s* S = sl.scene;
+    extras = extras || scene_extras(S);
+    even = even && S->even != 0;
     dv.push_back((const void*)&dev<T>(S));
     if (contact) cc.push_back(S->cd);
     vc.push_back(scene_counts(S));
@@ -1301,7 +1314,10 @@ viper_status pool_rebuild(viper_pool_s* P, bool contact, hipStream_t st) {
     return fail(VIPER_ERR_NO_CAPACITY, "pool header region too small for the resident set");
   std::vector<char>& img = contact ? P->hc : P->hf;
   char* at = P->ws + (contact ? half : 0);
-  build_header(img, dv, sizeof(Dev<T>), cc, vc, at, contact ? P->cb : P->fb);
+  BatchDev& b = contact ? P->cb : P->fb;
+  build_header(img, dv, sizeof(Dev<T>), cc, vc, at, b);
+  b.extras = extras;
+  b.even = even;
   if (!img.empty()) {
     HIP_TRY(hipMemcpyAsync(at, img.data(), img.size(), hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));   // the host image may change before the next rebuild

@@ -174,6 +174,8 @@ struct BatchDev {
   int nblk[TB_COUNT] = {};
   bool extras = false;                // some scene uses an optional constraint term (the rod
                                       // kernels' instantiation with them compiled in)
+  bool even = false;                  // every rod of every scene starts on an even slot of its
+                                      // wavefront (the rod kernels' lane-local colour passes)
 };
 
 // Launchers over a batch (enqueue on `stream`, return hipError_t of the launches).

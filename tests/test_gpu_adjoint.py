@@ -130,9 +130,12 @@ def compare(name, got, ref, rel_tol, cos_tol=None):
         assert cos >= cos_tol
 
 
-def test_checkpointed_forward_is_the_frame_step(work):
+@pytest.mark.parametrize("layout", ["even", "ragged"])
+def test_checkpointed_forward_is_the_frame_step(work, layout):
+    """Bit-identical: the same passes in the same instantiation (rods all on even wavefront
+    slots, or the ragged scene's general layout)."""
     desc, _ = work
-    sub = desc.subset(np.arange(0, 1024, 8))
+    sub = desc.subset(np.arange(0, 1024, 8)) if layout == "even" else ragged_scene()[0]
     for prec in ("f32", "f64"):
         a = viper.Scene(sub, prec)
         a.step(DT, SUB, IT, mode=viper.MODE_FRAME)

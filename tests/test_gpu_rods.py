@@ -105,6 +105,41 @@ def test_mixed_lengths_ragged_fp32_and_fp64():
         assert ex < tol and es < tol and eq < tol
 
 
+def test_even_and_general_wave_layouts_agree():
+    """Rods that all start on an even slot of their wavefront take the frame kernel's
+    lane-local colour passes; one 3-pill rod in front shifts every later rod to an odd slot
+    (the general passes).  The shared rods' frames agree to rounding (FP64 1e-12 after one
+    frame, FP32 within the parity bound), and both equal the oracle."""
+    base = scenes.helix_rods(65, 64, seed=23)
+    even = base.subset(range(1, 65))
+    lead = base.subset([0])
+    n = 3
+    shifted = scenes.SceneDesc(
+        np.concatenate([[0], n + np.asarray(even.rod_offsets)]).astype(np.int32),
+        np.concatenate([lead.rest_pos[:n], even.rest_pos]), np.concatenate([lead.rest_radius[:n], even.rest_radius]),
+        np.concatenate([lead.pinned[:n], even.pinned]), np.concatenate([lead.activation, even.activation]),
+        np.concatenate([lead.compliance, even.compliance]), np.arange(65, dtype=np.int32))
+    for prec, tol in (("f64", 1e-12), ("f32", TOL)):
+        say("case: even vs general layout", prec)
+        a = viper.Scene(even, prec)
+        b = viper.Scene(shifted, prec)
+        a.step(1 / 60, 20, 8, mode=viper.MODE_FRAME)
+        b.step(1 / 60, 20, 8, mode=viper.MODE_FRAME)
+        a.sync()
+        b.sync()
+        sa, sb = a.state(), b.state()
+        tail = {k: v[n:] for k, v in sb.items()}
+        e = errors(even, sa, tail)
+        say(prec, "even vs general", e)
+        assert max(e) < tol
+        if prec == "f64":
+            o = oracle.OracleScene(even, "f64")
+            o.step(1 / 60, 20, 8)
+            e = errors(even, sa, o.get_state())
+            say("even layout vs oracle", e)
+            assert max(e) < 1e-9
+
+
 def local_subset(desc, rods):
     """The given rods, each translated so that its first pill sits at the origin (the GPU
     stores positions relative to that anchor; the physics is translation invariant)."""
