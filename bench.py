@@ -75,6 +75,72 @@ def measured_traffic(kernel, workload):
     return rec.get("hbm_bytes_per_launch")
 
 
+def _dispatch_values(db, counter, name_like):
+    """Per-dispatch values of one counter (summed over its hardware instances) for the kernels
+    whose name matches, in dispatch order, from a rocprofv3 results database."""
+    import sqlite3
+    con = sqlite3.connect(db)
+    rows = con.execute("SELECT dispatch_id, kernel_name, value FROM counters_collection WHERE counter_name = ? AND "
+                       "kernel_name LIKE ? ORDER BY dispatch_id", (counter, name_like)).fetchall()
+    con.close()
+    return rows
+
+
+def write_counter_summaries(fetch_db, write_db, copy_fetch_db, copy_write_db, frames, copy_mib):
+    """HBM bytes per launch of the FP32 frame kernel on the helix 4096 x 64 workload, from two
+    rocprofv3 --pmc runs of this bench (FETCH_SIZE, then WRITE_SIZE; the first `frames` float
+    frame-kernel dispatches are the headline's whole-frame launches, the rest the per-substep
+    leg's) and two of its --copy-mib run, which scale each counter to known bytes.  Writes
+    profiles/rod_frame_kernel{,_substep}_helix4096x64_counters.json with the source hash."""
+    like = "%rod_frame_kernel<float%"
+    known = copy_mib * (1 << 20)
+    scale = {}
+    for key, db, counter in (("fetch", copy_fetch_db, "FETCH_SIZE"), ("write", copy_write_db, "WRITE_SIZE")):
+        v = [r[2] for r in _dispatch_values(db, counter, "%neg%")]
+        if not v:
+            raise SystemExit("no copy-reference dispatches in %s" % db)
+        scale[key] = known / (float(np.median(v)) * 1024.0)
+    fetch = _dispatch_values(fetch_db, "FETCH_SIZE", like)
+    write = _dispatch_values(write_db, "WRITE_SIZE", like)
+    if len(fetch) <= frames or len(write) <= frames:
+        raise SystemExit("expected more than %d frame-kernel dispatches" % frames)
+    for suffix, sel in (("", slice(0, frames)), ("_substep", slice(frames + 1, None))):
+        f = float(np.mean([r[2] for r in fetch[sel]]))
+        w = float(np.mean([r[2] for r in write[sel]]))
+        rd, wr = f * 1024.0 * scale["fetch"], w * 1024.0 * scale["write"]
+        rec = {"kernel": fetch[0][1].split("(")[0].replace("void viper::", ""), "workload": "helix4096x64",
+               "launch": "one frame (20 substeps)" if not suffix else "one substep",
+               "source_hash": kernel_source_hash(), "dispatches": len(fetch[sel]),
+               "fetch_kib_per_dispatch": f, "write_kib_per_dispatch": w,
+               "fetch_scale": scale["fetch"], "write_scale": scale["write"],
+               "hbm_bytes_per_launch": rd + wr, "hbm_read_bytes_per_launch": rd, "hbm_write_bytes_per_launch": wr,
+               "copy_reference": "torch neg over %d MiB (bench.py --copy-mib %d)" % (copy_mib, copy_mib),
+               "source_files": ["paper_1906_05260_amd/csrc/rod_kernels.hip (rod_frame_kernel)",
+                                "paper_1906_05260_amd/csrc/rod_device.h", "paper_1906_05260_amd/csrc/viper_dev.h",
+                                "paper_1906_05260_amd/build.py"]}
+        path = os.path.join(ROOT, "profiles", "rod_frame_kernel%s_helix4096x64_counters.json" % suffix)
+        with open(path, "w") as fh:
+            json.dump(rec, fh, indent=1)
+            fh.write("\n")
+        print(path, json.dumps(rec), flush=True)
+
+
+def sync_diverged(viper, sc, desc):
+    """viper_sync; on the NaN status, the number of rods with a non-finite state instead of an
+    error.  Some soft helices of the random-compliance workload go unstable (scales through
+    zero) within the first frames, in the FP64 oracle too, and such a rod can overflow in FP32
+    after tens of frames; rods are independent, so the rest of the scene is unaffected."""
+    try:
+        sc.sync()
+        return 0
+    except viper.ViperError as e:
+        if e.status != viper.ERR_NAN:
+            raise
+    st = sc.state()
+    bad = ~(np.isfinite(st["x"]).all(1) & np.isfinite(st["s"]) & np.isfinite(st["q"]).all(1))
+    return len(set((np.searchsorted(desc.rod_offsets, np.nonzero(bad)[0], side="right") - 1).tolist()))
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -540,7 +606,15 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="instead of the solver, time a plain device copy of this many MiB (the "
                          "reference kernel for scaling HBM byte counters)")
+    ap.add_argument("--counter-summaries", nargs=4, metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB"),
+                    help="write the frame kernel's HBM counter summaries under profiles/ from four rocprofv3 "
+                         "--pmc result databases (no GPU needed); --counter-frames and --copy-mib as in those runs")
+    ap.add_argument("--counter-frames", type=int, default=4,
+                    help="whole-frame launches (warmup + steps) of the counted bench run")
     args = ap.parse_args()
+    if args.counter_summaries:
+        write_counter_summaries(*args.counter_summaries, frames=args.counter_frames, copy_mib=args.copy_mib or 1024)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the solver runs on a single MI355X "
               "(rods and scenes are independent; see the sharding note in the design document)", file=sys.stderr)
@@ -564,7 +638,7 @@ def main():
     mode = viper.MODE_FRAME if args.mode == "frame" else viper.MODE_SUBSTEP
     for _ in range(args.warmup):
         sc.step(dt, sub, iters, mode=mode)
-    sc.sync()
+    sync_diverged(viper, sc, desc)
     stream = torch.cuda.current_stream()
     K = args.steps
     launches = K if mode == viper.MODE_FRAME else K * sub
@@ -584,7 +658,7 @@ def main():
                 e[1].record(stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    sc.sync()
+    diverged = sync_diverged(viper, sc, desc)
     kern_ms = sum(a.elapsed_time(b) for a, b in ev) / launches
 
     P = desc.num_pills
@@ -634,7 +708,8 @@ def main():
         "data": "synthetic (seeded random helices)",
         "config": {"workload": workload, "rods": args.rods, "pills_per_rod": args.pills, "substeps": sub,
                    "iterations": iters, "frames_timed": K, "collisions": False, "launch": args.mode,
-                   "pill_substeps_per_s": P * sub * K / elapsed, "projections_per_s_by_type": by_type},
+                   "pill_substeps_per_s": P * sub * K / elapsed, "projections_per_s_by_type": by_type,
+                   "rods_nonfinite_at_end": diverged},
         "roofline": roof,
     }
     log("headline: %.3f ms/frame, rod kernel %.3f ms" % (elapsed * 1e3 / K, kern_ms))

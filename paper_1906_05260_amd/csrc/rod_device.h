@@ -18,10 +18,11 @@ template <> __device__ __forceinline__ double rcp<double>(double a) { return 1.0
 
 // Neighbour exchange by DPP wave shifts (a VALU move, no LDS round trip):
 // wave_shl:1 delivers lane l+1's value to lane l, wave_shr:1 lane l-1's.  The lane
-// without a source keeps its own value; the rod layout never reads it (rods do not
-// cross wavefronts).
-__device__ __forceinline__ int dpp_dn(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xF, 0xF, false); }
-__device__ __forceinline__ int dpp_up(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xF, 0xF, false); }
+// without a source (63, resp. 0) reads zero (bound_ctrl), so the move needs no copy of the
+// source to preserve; the rod layout never reads that value (rods do not cross wavefronts:
+// lane 63 holds no edge that continues into a next lane, lane 0's slot A starts a rod).
+__device__ __forceinline__ int dpp_dn(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, true); }
+__device__ __forceinline__ int dpp_up(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, true); }
 template <class T> __device__ __forceinline__ T dn(T v);
 template <class T> __device__ __forceinline__ T up(T v);
 template <> __device__ __forceinline__ float dn<float>(float v) { return __int_as_float(dpp_dn(__float_as_int(v))); }
@@ -157,10 +158,10 @@ __device__ __forceinline__ void edge_update(Slot<T>& L, T& b0, T& b1, T& b2, T& 
     // bias that a stiff stretch-shear constraint enforces, and gradients of stiff FP32 rods
     // amplify it by orders of magnitude.
     const T na = q0 * q0 + q1 * q1, nb = q2 * q2 + q3 * q3;
-    const T tw = T(2) * rcp(na + nb);
+    const T in = rcp(na + nb), tw = in + in;
     const T d0 = (q0 * q2 + q3 * q1) * tw;
     const T d1 = (q1 * q2 - q3 * q0) * tw;
-    const T d2 = (nb - na) * (T(0.5) * tw);
+    const T d2 = (nb - na) * in;
     const T ilb = L.ilb, at = L.ass;
     const T c0 = (b0 - a0) * ilb - d0, c1 = (b1 - a1) * ilb - d1, c2 = (b2 - a2) * ilb - d2;
     const T k1 = (wa + wb) * ilb * ilb + at;
@@ -182,10 +183,9 @@ __device__ __forceinline__ void edge_update(Slot<T>& L, T& b0, T& b1, T& b2, T& 
     const T len2 = e0 * e0 + e1 * e1 + e2 * e2;
     const T ilen = rsq(len2);
     const T len = len2 * ilen;
-    const T sm = T(0.5) * (sa + sb);
-    const T sm2 = sm * sm;
-    const T C = sm2 * len * L.il0 - T(1);
-    const T gx = sm2 * L.il0, gs = sm * len * L.il0;
+    const T ss = sa + sb;   // twice the midpoint scale sm
+    const T gx = (ss * ss) * (T(0.25) * L.il0), gs = (ss * len) * (T(0.5) * L.il0);   // sm^2 / l0, sm l / l0
+    const T C = gx * len - T(1);
     const T at = L.avol;
     const T S = (wa + wb) * gx * gx + (L.ws + wsb) * gs * gs + at;
     const T dl = (-C - at * L.l[3]) * rcp(S);
@@ -232,35 +232,34 @@ __device__ __forceinline__ void bt_update(Slot<T>& L, T& b0, T& b1, T& b2, T& b3
   const T c = L.cbt;
   const T sc = sb * c;
   const T C0 = sc * v0 - L.db0, C1 = sc * v1 - L.db1, C2 = sc * v2 - L.db2;
-  // tangent of edge b in frame a: t = R(r) e_z;  u = B e_z, y = B t with B = w I - [v]x
-  const T t0 = T(2) * (v0 * v2 + w * v1);
-  const T t1 = T(2) * (v1 * v2 - w * v0);
-  const T t2 = T(1) - T(2) * (v0 * v0 + v1 * v1);
-  const T y0 = w * t0 - (v1 * t2 - v2 * t1);
-  const T y1 = w * t1 - (v2 * t0 - v0 * t2);
-  const T y2 = w * t2 - (v0 * t1 - v1 * t0);
+  // tangent of edge b in frame a: t = R(r) e_z;  u = B e_z, y = B t with B = w I - [v]x.
+  // For a unit r, B t = Im(conj(r) (x) r (x) e_z (x) conj(r)) = Im(e_z (x) conj(r)), so
+  // y = (v1, -v0, w) and u = (-v1, v0, w): y y^T is u u^T with its (0,2), (1,2) entries negated.
+  const T v0s = v0 * v0, v1s = v1 * v1;
+  const T th0 = v0 * v2 + w * v1, th1 = v1 * v2 - w * v0, th2 = T(0.5) - (v0s + v1s);   // t / 2
   // S = K[(Ia+Ib)(I - v v^T) - Ia/2 u u^T - Ib/2 y y^T] + wsb c^2 v v^T + diag(a, a, a/2),
   // assembled directly as s = S / (m + a), m = K (Ia + Ib): the entries reach ~1e14 for thin
   // rods and the cubic determinant would leave the FP32 range; scaled they are O(1) (each
   // term of S is at most of the order of m or a).  S^-1 = adj(s) / (det(s) (m + a)).
-  //   s = I - diag(0, 0, a/2) sgm + qs v v^T - has u u^T - hbs y y^T,  u = (-v1, v0, w)
+  //   s = I - diag(0, 0, a/2) sgm + qs v v^T - has u u^T - hbs y y^T
+  //     = I - diag(0, 0, a/2) sgm + qs v v^T - hp (u0^2, u1^2, u2^2, u0 u1 off the last
+  //       column) - hm (u0 u2, u1 u2),  hp = has + hbs, hm = has - hbs
+  //   (K = sc^2 / 4: m = sc^2 (Ia+Ib)/4, hp = sc^2 sgm (Ia+Ib)/8, hm = sc^2 sgm (Ia-Ib)/8)
   const T Ia = L.I1;
-  const T K = T(0.25) * sc * sc;
-  const T m = K * (Ia + Ib);
+  const T sc2 = sc * sc;
+  const T m = sc2 * (T(0.25) * (Ia + Ib));
   const T at = L.abt;
   const T sgm = rcp(m + at);
   const T qs = (wsb * c * c - m) * sgm;
-  const T kh = T(0.5) * K * sgm;
-  const T has = kh * Ia, hbs = kh * Ib;
+  const T ks = sc2 * sgm;
+  const T hp = ks * (T(0.125) * (Ia + Ib)), hm = ks * (T(0.125) * (Ia - Ib));
   const T pv0 = qs * v0, pv1 = qs * v1, pv2 = qs * v2;
-  const T hv0 = has * v0, hv1 = has * v1, hw = has * w;
-  const T py0 = hbs * y0, py1 = hbs * y1, py2 = hbs * y2;
-  const T s00 = T(1) + pv0 * v0 - hv1 * v1 - py0 * y0;
-  const T s11 = T(1) + pv1 * v1 - hv0 * v0 - py1 * y1;
-  const T s22 = (T(1) - T(0.5) * at * sgm) + pv2 * v2 - hw * w - py2 * y2;
-  const T s01 = pv0 * v1 + hv1 * v0 - py0 * y1;
-  const T s02 = pv0 * v2 + hv1 * w - py0 * y2;
-  const T s12 = pv1 * v2 - hv0 * w - py1 * y2;
+  const T s00 = T(1) + pv0 * v0 - hp * v1s;
+  const T s11 = T(1) + pv1 * v1 - hp * v0s;
+  const T s22 = (T(1) - T(0.5) * at * sgm) + pv2 * v2 - hp * (w * w);
+  const T s01 = (qs + hp) * (v0 * v1);
+  const T s02 = pv0 * v2 + hm * (v1 * w);
+  const T s12 = pv1 * v2 - hm * (v0 * w);
   const T r0 = -C0 - at * L.l[5], r1 = -C1 - at * L.l[6], r2 = -C2 - T(0.5) * at * L.l[7];
   const T A00 = s11 * s22 - s12 * s12, A01 = s02 * s12 - s01 * s22, A02 = s01 * s12 - s02 * s11;
   const T A11 = s00 * s22 - s02 * s02, A12 = s01 * s02 - s00 * s12, A22 = s00 * s11 - s01 * s01;
@@ -273,15 +272,15 @@ __device__ __forceinline__ void bt_update(Slot<T>& L, T& b0, T& b1, T& b2, T& b3
   const T e0 = w * g0 + (v1 * g2 - v2 * g1);
   const T e1 = w * g1 + (v2 * g0 - v0 * g2);
   const T e2 = w * g2 + (v0 * g1 - v1 * g0);
-  const T hs = T(0.5) * sc;
-  // body-frame (a) rotation of edge a: da = -hs Ia (e - e_z e_z/2); h = da / 2
-  const T ka = T(-0.5) * hs * Ia;
+  // body-frame (a) rotation of edge a: da = -hs Ia (e - e_z e_z/2), hs = sc/2; h = da / 2
+  const T ka = sc * (T(-0.25) * Ia), ka2 = sc * (T(-0.125) * Ia);
   // frame-a rotation of edge b: dB = hs Ib (e - (t.e) t / 2); h = sg dB / 2
-  const T te = T(0.5) * (t0 * e0 + t1 * e1 + t2 * e2);
-  const T kb = T(0.5) * sg * hs * Ib;
+  const T te = th0 * e0 + th1 * e1 + th2 * e2;   // (t.e) / 2
+  const T te2 = te + te;
+  const T kb = (sg * sc) * (T(0.25) * Ib);
   // q_a <- normalize(q_a + 1/2 q_a (x) [da, 0])
   {
-    const T h0 = ka * e0, h1 = ka * e1, h2 = T(0.5) * ka * e2;
+    const T h0 = ka * e0, h1 = ka * e1, h2 = ka2 * e2;
     const T nx = a0 + (a3 * h0 + (a1 * h2 - a2 * h1));
     const T ny = a1 + (a3 * h1 + (a2 * h0 - a0 * h2));
     const T nz = a2 + (a3 * h2 + (a0 * h1 - a1 * h0));
@@ -291,7 +290,7 @@ __device__ __forceinline__ void bt_update(Slot<T>& L, T& b0, T& b1, T& b2, T& b3
   }
   // q_b <- normalize(q_b + 1/2 q_a (x) [dB, 0] (x) r_true),  r_true = sg (v, w)
   {
-    const T h0 = kb * (e0 - te * t0), h1 = kb * (e1 - te * t1), h2 = kb * (e2 - te * t2);
+    const T h0 = kb * (e0 - te2 * th0), h1 = kb * (e1 - te2 * th1), h2 = kb * (e2 - te2 * th2);
     const T p0 = w * h0 + (h1 * v2 - h2 * v1);
     const T p1 = w * h1 + (h2 * v0 - h0 * v2);
     const T p2 = w * h2 + (h0 * v1 - h1 * v0);
