@@ -5,219 +5,410 @@
 // Each launch reloads its checkpoint, recomputes the substep exactly as the forward does
 // (same device code) while storing the state before every colour pass, then sweeps back:
 // velocity update, the 4 x iterations passes in reverse, the substep-start inertia, and
-// the prediction.  The vector-Jacobian product of each projection is formed from forward
-// derivatives of that projection taken with dual numbers over the same templated update
-// (four input directions per evaluation), so the adjoint differentiates exactly the
-// arithmetic the forward performs.  Adjoints of the per-slot parameters (inverse masses,
-// inverse stretch rest length, inertia base, compliance scalings) are accumulated per
-// slot and chained to rest radii and activations on the host.
-
-#include <type_traits>
+// the prediction.  The vector-Jacobian product of each projection is written out in closed
+// form: the projection's intermediates are recomputed from its pre-pass inputs, then their
+// adjoints are propagated back through the same formulas in reverse order (the derivative
+// of the arithmetic the forward performs, with the hardware reciprocal and reciprocal
+// square root taken as exact).  Adjoints of the per-slot parameters (inverse masses,
+// inverse stretch rest length, inertia base, compliance scalings) are accumulated per slot
+// and chained to rest radii and activations on the host.
 
 #include "rod_device.h"
 
 namespace viper {
 
-// ---------------------------------------------------------------- dual numbers
+// ---------------------------------------------------------------- quaternion helpers
 
-template <class S, int K>
-struct Dual {
-  S v;
-  S d[K];
-  __device__ __forceinline__ Dual() : v(S(0)) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) d[k] = S(0);
-  }
-  template <class U, class = typename std::enable_if<std::is_arithmetic<U>::value>::type>
-  __device__ __forceinline__ Dual(U a) : v(S(a)) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) d[k] = S(0);
-  }
+template <class T>
+struct Q4 {
+  T x, y, z, w;
 };
 
-template <class S, int K> __device__ __forceinline__ Dual<S, K> operator+(const Dual<S, K>& a, const Dual<S, K>& b) {
-  Dual<S, K> r; r.v = a.v + b.v;
-#pragma unroll
-  for (int k = 0; k < K; ++k) r.d[k] = a.d[k] + b.d[k];
-  return r;
+// a (x) b
+template <class T>
+__device__ __forceinline__ Q4<T> qmul(const Q4<T>& a, const Q4<T>& b) {
+  return {a.w * b.x + b.w * a.x + (a.y * b.z - a.z * b.y), a.w * b.y + b.w * a.y + (a.z * b.x - a.x * b.z),
+          a.w * b.z + b.w * a.z + (a.x * b.y - a.y * b.x), a.w * b.w - (a.x * b.x + a.y * b.y + a.z * b.z)};
 }
-template <class S, int K> __device__ __forceinline__ Dual<S, K> operator-(const Dual<S, K>& a, const Dual<S, K>& b) {
-  Dual<S, K> r; r.v = a.v - b.v;
-#pragma unroll
-  for (int k = 0; k < K; ++k) r.d[k] = a.d[k] - b.d[k];
-  return r;
-}
-template <class S, int K> __device__ __forceinline__ Dual<S, K> operator-(const Dual<S, K>& a) {
-  Dual<S, K> r; r.v = -a.v;
-#pragma unroll
-  for (int k = 0; k < K; ++k) r.d[k] = -a.d[k];
-  return r;
-}
-template <class S, int K> __device__ __forceinline__ Dual<S, K> operator*(const Dual<S, K>& a, const Dual<S, K>& b) {
-  Dual<S, K> r; r.v = a.v * b.v;
-#pragma unroll
-  for (int k = 0; k < K; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
-  return r;
-}
-template <class S, int K> __device__ __forceinline__ Dual<S, K>& operator+=(Dual<S, K>& a, const Dual<S, K>& b) { a = a + b; return a; }
-template <class S, int K> __device__ __forceinline__ Dual<S, K>& operator-=(Dual<S, K>& a, const Dual<S, K>& b) { a = a - b; return a; }
-template <class S, int K> __device__ __forceinline__ bool operator<(const Dual<S, K>& a, const Dual<S, K>& b) { return a.v < b.v; }
-template <class S, int K> __device__ __forceinline__ bool operator>(const Dual<S, K>& a, const Dual<S, K>& b) { return a.v > b.v; }
-// the same hardware reciprocal / rsqrt as the forward, with their exact derivatives
-template <class S, int K> __device__ __forceinline__ Dual<S, K> rcp(const Dual<S, K>& a) {
-  Dual<S, K> r; r.v = rcp(a.v);
-  const S g = -r.v * r.v;
-#pragma unroll
-  for (int k = 0; k < K; ++k) r.d[k] = g * a.d[k];
-  return r;
-}
-template <class S, int K> __device__ __forceinline__ Dual<S, K> rsq(const Dual<S, K>& a) {
-  Dual<S, K> r; r.v = rsq(a.v);
-  const S g = S(-0.5) * r.v * r.v * r.v;
-#pragma unroll
-  for (int k = 0; k < K; ++k) r.d[k] = g * a.d[k];
-  return r;
-}
+template <class T>
+__device__ __forceinline__ Q4<T> qconj(const Q4<T>& a) { return {-a.x, -a.y, -a.z, a.w}; }
 
-// Input directions per dual evaluation: four in FP32, two in FP64 (register budget).
-template <class T> struct KDim { static constexpr int v = 4; };
-template <> struct KDim<double> { static constexpr int v = 2; };
-template <class T> using DT = Dual<T, KDim<T>::v>;
-
-// Seed in[i] with unit derivative in direction i - c0 when i lies in [c0, c0 + KD).
-template <class T, int N>
-__device__ __forceinline__ void seed(DT<T> (&in)[N], const T (&v)[N], int c0) {
-  constexpr int KD = KDim<T>::v;
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    in[i] = DT<T>(v[i]);
-#pragma unroll
-    for (int k = 0; k < KD; ++k) in[i].d[k] = (i == c0 + k) ? T(1) : T(0);
-  }
-}
-
-// xb[c0 + k] = sum_o yb[o] d out[o] / d in[c0 + k]
-template <class T, int N, int M>
-__device__ __forceinline__ void gather_vjp(const DT<T> (&out)[M], const T (&yb)[M], int c0, T (&xb)[N]) {
-  constexpr int KD = KDim<T>::v;
-  T acc[KD];
-#pragma unroll
-  for (int k = 0; k < KD; ++k) {
-    acc[k] = T(0);
-#pragma unroll
-    for (int o = 0; o < M; ++o) acc[k] += yb[o] * out[o].d[k];
-  }
-#pragma unroll
-  for (int i = 0; i < N; ++i)
-#pragma unroll
-    for (int k = 0; k < KD; ++k)
-      if (i == c0 + k) xb[i] = acc[k];
+// Adjoint of n through u = n / |n| (u computed with inv = rsq(n.n)): inv u_bar - inv^3 (n.u_bar) n.
+template <class T>
+__device__ __forceinline__ Q4<T> normalize_vjp(const Q4<T>& n, T inv, const Q4<T>& ub) {
+  const T k = inv * inv * inv * (n.x * ub.x + n.y * ub.y + n.z * ub.z + n.w * ub.w);
+  return {inv * ub.x - k * n.x, inv * ub.y - k * n.y, inv * ub.z - k * n.z, inv * ub.w - k * n.w};
 }
 
 // ---------------------------------------------------------------- local VJPs
 
-// The backward kernel runs every logical lane in kReps replica waves of one block: all
-// replicas recompute the same state, and the input-direction chunks of each local VJP are
-// split between them (chunk c on replica c % kReps); share_chunks then gives every replica
-// the full result through LDS.  Called by all threads of the block (it has barriers).
-constexpr int kReps = 4;
-
-template <class T, int N>
-__device__ __forceinline__ void share_chunks(T (&xb)[N], int rep, T* X, int lane) {
-  constexpr int KD = KDim<T>::v;
-#pragma unroll
-  for (int i = 0; i < N; ++i)
-    if ((i / KD) % kReps == rep) X[i * 64 + lane] = xb[i];
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < N; ++i) xb[i] = X[i * 64 + lane];
-  __syncthreads();
-}
-
-// Stretch-shear + volume + scale gradient of slot L's edge (edge_update).
-// Inputs (26): x0 x1 x2 s q0 q1 q2 q3 l0..l4 | b0 b1 b2 sb | w ws ilb ass avol asg I1 | wb wsb
-// Outputs (17): x0 x1 x2 s q0..q3 l0..l4 | b0 b1 b2 sb
+// Stretch-shear + volume + scale gradient of slot L's edge (edge_update, the plain
+// constraint set).  Inputs (26): x0 x1 x2 s q0 q1 q2 q3 l0..l4 | b0 b1 b2 sb |
+// w ws ilb ass avol asg I1 | wb wsb.  Outputs (17): x0 x1 x2 s q0..q3 l0..l4 | b0 b1 b2 sb.
+// xb = J^T yb.
 template <class T>
-__device__ void edge_vjp(const Slot<T>& L, T b0, T b1, T b2, T sb, T wb, T wsb, const T (&yb)[17], T (&xb)[26],
-                         int rep, T* X, int lane) {
-  constexpr int KD = KDim<T>::v;
-  const T v[26] = {L.x0, L.x1, L.x2, L.s, L.q0, L.q1, L.q2, L.q3, L.l[0], L.l[1], L.l[2], L.l[3], L.l[4],
-                   b0, b1, b2, sb, L.w, L.ws, L.ilb, L.ass, L.avol, L.asg, L.I1, wb, wsb};
-#pragma unroll
-  for (int i = 0; i < 26; ++i) xb[i] = T(0);
-  for (int c0 = rep * KD; c0 < 26; c0 += kReps * KD) {
-    DT<T> in[26];
-    seed(in, v, c0);
-    Slot<DT<T>> S;
-    S.f = L.f;
-    S.x0 = in[0]; S.x1 = in[1]; S.x2 = in[2]; S.s = in[3];
-    S.q0 = in[4]; S.q1 = in[5]; S.q2 = in[6]; S.q3 = in[7];
-    S.l[0] = in[8]; S.l[1] = in[9]; S.l[2] = in[10]; S.l[3] = in[11]; S.l[4] = in[12];
-    DT<T> c0_ = in[13], c1_ = in[14], c2_ = in[15], cs_ = in[16];
-    S.w = in[17]; S.ws = in[18]; S.ilb = in[19]; S.ass = in[20]; S.avol = in[21]; S.asg = in[22]; S.I1 = in[23];
-    S.il0 = DT<T>(L.il0);
-    edge_update(S, c0_, c1_, c2_, cs_, in[24], in[25]);
-    const DT<T> out[17] = {S.x0, S.x1, S.x2, S.s, S.q0, S.q1, S.q2, S.q3, S.l[0], S.l[1], S.l[2], S.l[3], S.l[4],
-                           c0_, c1_, c2_, cs_};
-    gather_vjp(out, yb, c0, xb);
+__device__ void edge_vjp(const Slot<T>& L, T b0, T b1, T b2, T sb, T wb, T wsb, const T (&yb)[17], T (&xb)[26]) {
+  const uint32_t f = L.f;
+  const bool ss = (f & F_SS) != 0, vol = (f & F_VOL) != 0, sgr = (f & F_SG) != 0;
+  const T wa = L.w, wsa = L.ws, ilb = L.ilb, il0 = L.il0, I1 = L.I1;
+  const T ass = L.ass, avol = L.avol, asg = L.asg;
+  const Q4<T> q = {L.q0, L.q1, L.q2, L.q3};
+  // ---- forward recompute
+  // stretch-shear
+  T a0 = L.x0, a1 = L.x1, a2 = L.x2, c0 = b0, c1 = b1, c2 = b2;   // pills after it
+  T na = 0, nb = 0, in = 0, P0 = 0, P1 = 0, d0 = 0, d1 = 0, d2 = 0, ik1 = 0, ik2 = 0;
+  T r0 = 0, r1 = 0, r2 = 0, dr = 0, ee = 0, g0 = 0, g1 = 0, g2 = 0, nI = 0, rho0 = 0, rho1 = 0, rho2 = 0, inn = 0;
+  Q4<T> n = q;
+  if (ss) {
+    na = q.x * q.x + q.y * q.y; nb = q.z * q.z + q.w * q.w;
+    in = rcp(na + nb);
+    const T tw = in + in;
+    P0 = q.x * q.z + q.w * q.y; P1 = q.y * q.z - q.w * q.x;
+    d0 = P0 * tw; d1 = P1 * tw; d2 = (nb - na) * in;
+    const T k1 = (wa + wb) * ilb * ilb + ass;
+    ik1 = rcp(k1); ik2 = rcp(k1 + I1);
+    r0 = -((b0 - a0) * ilb - d0) - ass * L.l[0];
+    r1 = -((b1 - a1) * ilb - d1) - ass * L.l[1];
+    r2 = -((b2 - a2) * ilb - d2) - ass * L.l[2];
+    dr = d0 * r0 + d1 * r1 + d2 * r2;
+    ee = dr * (ik1 - ik2);
+    g0 = r0 * ik2 + ee * d0; g1 = r1 * ik2 + ee * d1; g2 = r2 * ik2 + ee * d2;
+    const T fa = wa * ilb, fb = wb * ilb;
+    a0 -= fa * g0; a1 -= fa * g1; a2 -= fa * g2;
+    c0 += fb * g0; c1 += fb * g1; c2 += fb * g2;
+    nI = T(-0.5) * I1;
+    rho0 = nI * (d1 * g2 - d2 * g1); rho1 = nI * (d2 * g0 - d0 * g2); rho2 = nI * (d0 * g1 - d1 * g0);
+    n = {q.x + (q.w * rho0 + (rho1 * q.z - rho2 * q.y)), q.y + (q.w * rho1 + (rho2 * q.x - rho0 * q.z)),
+         q.z + (q.w * rho2 + (rho0 * q.y - rho1 * q.x)), q.w - (rho0 * q.x + rho1 * q.y + rho2 * q.z)};
+    inn = rsq(n.x * n.x + n.y * n.y + n.z * n.z + n.w * n.w);
   }
-  share_chunks(xb, rep, X, lane);
+  // volume (on the pills after stretch-shear)
+  T e0 = 0, e1 = 0, e2 = 0, len2 = 0, ilen = 0, len = 0, ssum = 0, gx = 0, gs = 0, iSv = 0, dlv = 0, kv = 0;
+  T sa1 = L.s, sb1 = sb;
+  if (vol) {
+    e0 = c0 - a0; e1 = c1 - a1; e2 = c2 - a2;
+    len2 = e0 * e0 + e1 * e1 + e2 * e2;
+    ilen = rsq(len2);
+    len = len2 * ilen;
+    ssum = L.s + sb;
+    gx = (ssum * ssum) * (T(0.25) * il0); gs = (ssum * len) * (T(0.5) * il0);
+    const T C = gx * len - T(1);
+    iSv = rcp((wa + wb) * gx * gx + (wsa + wsb) * gs * gs + avol);
+    dlv = (-C - avol * L.l[3]) * iSv;
+    kv = gx * dlv * ilen;
+    sa1 += wsa * gs * dlv; sb1 += wsb * gs * dlv;
+  }
+  // scale gradient (on the scales after volume)
+  T iSg = 0, dlg = 0;
+  if (sgr) {
+    iSg = rcp((wsa + wsb) * il0 * il0 + asg);
+    dlg = (-((sb1 - sa1) * il0) - asg * L.l[4]) * iSg;
+  }
+  // ---- reverse sweep
+  T Ax0 = yb[0], Ax1 = yb[1], Ax2 = yb[2], As = yb[3];
+  Q4<T> Aq = {yb[4], yb[5], yb[6], yb[7]};
+  T Al0 = yb[8], Al1 = yb[9], Al2 = yb[10], Al3 = yb[11], Al4 = yb[12];
+  T Ab0 = yb[13], Ab1 = yb[14], Ab2 = yb[15], Asb = yb[16];
+  T Awa = 0, Awsa = 0, Ailb = 0, Aass = 0, Aavol = 0, Aasg = 0, AI1 = 0, Awb = 0, Awsb = 0;
+  if (sgr) {
+    // sa'' = sa' - wsa il0 dl,  sb'' = sb' + wsb il0 dl,  l4' = l4 + dl
+    const T Adl = -wsa * il0 * As + wsb * il0 * Asb + Al4;
+    Awsa -= il0 * dlg * As; Awsb += il0 * dlg * Asb;
+    // dl = (-C - asg l4) / S,  C = (sb' - sa') il0,  S = (wsa + wsb) il0^2 + asg
+    const T AN = Adl * iSg, AS = -Adl * dlg * iSg;
+    Aasg += AS - L.l[4] * AN;
+    Al4 -= asg * AN;
+    Awsa += il0 * il0 * AS; Awsb += il0 * il0 * AS;
+    Asb -= il0 * AN; As += il0 * AN;
+  }
+  if (vol) {
+    // a'' = a' - wa k e,  b'' = b' + wb k e,  sa' = sa + wsa gs dl,  sb' = sb + wsb gs dl,  l3' = l3 + dl
+    const T Axe = Ax0 * e0 + Ax1 * e1 + Ax2 * e2, Abe = Ab0 * e0 + Ab1 * e1 + Ab2 * e2;
+    Awa -= kv * Axe; Awb += kv * Abe;
+    const T Ak = wb * Abe - wa * Axe;
+    T Ae0 = kv * (wb * Ab0 - wa * Ax0), Ae1 = kv * (wb * Ab1 - wa * Ax1), Ae2 = kv * (wb * Ab2 - wa * Ax2);
+    T Ags = dlv * (wsa * As + wsb * Asb);
+    T Adl = gs * (wsa * As + wsb * Asb) + Al3;
+    Awsa += gs * dlv * As; Awsb += gs * dlv * Asb;
+    // k = gx dl ilen
+    T Agx = dlv * ilen * Ak;
+    Adl += gx * ilen * Ak;
+    T Ailen = gx * dlv * Ak;
+    // dl = (-C - avol l3) / S
+    const T AN = Adl * iSv, AS = -Adl * dlv * iSv;
+    Aavol += AS - L.l[3] * AN;
+    Al3 -= avol * AN;
+    // S = (wa + wb) gx^2 + (wsa + wsb) gs^2 + avol
+    Awa += gx * gx * AS; Awb += gx * gx * AS; Awsa += gs * gs * AS; Awsb += gs * gs * AS;
+    Agx += T(2) * (wa + wb) * gx * AS;
+    Ags += T(2) * (wsa + wsb) * gs * AS;
+    // C = gx len - 1 (AC = -AN)
+    Agx -= len * AN;
+    T Alen = -gx * AN;
+    // gs = ssum len il0 / 2,  gx = ssum^2 il0 / 4,  ssum = sa + sb
+    const T Assum = (T(0.5) * il0) * (len * Ags + ssum * Agx);
+    Alen += ssum * (T(0.5) * il0) * Ags;
+    As += Assum; Asb += Assum;
+    // len = len2 ilen,  ilen = rsq(len2),  len2 = e.e,  e = b' - a'
+    Ailen += len2 * Alen;
+    const T Alen2 = ilen * Alen - T(0.5) * ilen * ilen * ilen * Ailen;
+    Ae0 += T(2) * e0 * Alen2; Ae1 += T(2) * e1 * Alen2; Ae2 += T(2) * e2 * Alen2;
+    Ab0 += Ae0; Ab1 += Ae1; Ab2 += Ae2;
+    Ax0 -= Ae0; Ax1 -= Ae1; Ax2 -= Ae2;
+  }
+  if (ss) {
+    // q' = n / |n|,  n = q + [rho, 0] (x) q
+    const Q4<T> An = normalize_vjp(n, inn, Aq);
+    Aq = {An.x - An.w * rho0 - (rho1 * An.z - rho2 * An.y), An.y - An.w * rho1 - (rho2 * An.x - rho0 * An.z),
+          An.z - An.w * rho2 - (rho0 * An.y - rho1 * An.x), An.w + (rho0 * An.x + rho1 * An.y + rho2 * An.z)};
+    const T Ar0 = q.w * An.x - q.z * An.y + q.y * An.z - q.x * An.w;
+    const T Ar1 = q.z * An.x + q.w * An.y - q.x * An.z - q.y * An.w;
+    const T Ar2 = -q.y * An.x + q.x * An.y + q.w * An.z - q.z * An.w;
+    // rho = nI (d x g),  nI = -I1 / 2
+    AI1 -= T(0.5) * ((d1 * g2 - d2 * g1) * Ar0 + (d2 * g0 - d0 * g2) * Ar1 + (d0 * g1 - d1 * g0) * Ar2);
+    T Ad0 = nI * (g1 * Ar2 - g2 * Ar1), Ad1 = nI * (g2 * Ar0 - g0 * Ar2), Ad2 = nI * (g0 * Ar1 - g1 * Ar0);
+    T Ag0 = nI * (Ar1 * d2 - Ar2 * d1), Ag1 = nI * (Ar2 * d0 - Ar0 * d2), Ag2 = nI * (Ar0 * d1 - Ar1 * d0);
+    // a' = a - wa ilb g,  b' = b + wb ilb g,  l' = l + g
+    const T Afa = -(Ax0 * g0 + Ax1 * g1 + Ax2 * g2), Afb = Ab0 * g0 + Ab1 * g1 + Ab2 * g2;
+    Awa += ilb * Afa; Awb += ilb * Afb; Ailb += wa * Afa + wb * Afb;
+    const T fa = wa * ilb, fb = wb * ilb;
+    Ag0 += fb * Ab0 - fa * Ax0 + Al0; Ag1 += fb * Ab1 - fa * Ax1 + Al1; Ag2 += fb * Ab2 - fa * Ax2 + Al2;
+    // g = r ik2 + ee d,  ee = dr (ik1 - ik2),  dr = d.r
+    T Ar_0 = ik2 * Ag0, Ar_1 = ik2 * Ag1, Ar_2 = ik2 * Ag2;
+    T Aik2 = r0 * Ag0 + r1 * Ag1 + r2 * Ag2;
+    const T Aee = d0 * Ag0 + d1 * Ag1 + d2 * Ag2;
+    Ad0 += ee * Ag0; Ad1 += ee * Ag1; Ad2 += ee * Ag2;
+    const T Adr = (ik1 - ik2) * Aee;
+    const T Aik1 = dr * Aee;
+    Aik2 -= dr * Aee;
+    Ad0 += r0 * Adr; Ad1 += r1 * Adr; Ad2 += r2 * Adr;
+    Ar_0 += d0 * Adr; Ar_1 += d1 * Adr; Ar_2 += d2 * Adr;
+    // r = -C - ass l,  C = (b - a) ilb - d  (AC = -Ar)
+    Aass -= L.l[0] * Ar_0 + L.l[1] * Ar_1 + L.l[2] * Ar_2;
+    Al0 -= ass * Ar_0; Al1 -= ass * Ar_1; Al2 -= ass * Ar_2;
+    Ab0 -= ilb * Ar_0; Ab1 -= ilb * Ar_1; Ab2 -= ilb * Ar_2;
+    Ax0 += ilb * Ar_0; Ax1 += ilb * Ar_1; Ax2 += ilb * Ar_2;
+    Ailb -= (b0 - L.x0) * Ar_0 + (b1 - L.x1) * Ar_1 + (b2 - L.x2) * Ar_2;
+    Ad0 += Ar_0; Ad1 += Ar_1; Ad2 += Ar_2;
+    // ik1 = 1 / k1,  ik2 = 1 / (k1 + I1),  k1 = (wa + wb) ilb^2 + ass
+    const T Ak1 = -ik1 * ik1 * Aik1 - ik2 * ik2 * Aik2;
+    AI1 -= ik2 * ik2 * Aik2;
+    Awa += ilb * ilb * Ak1; Awb += ilb * ilb * Ak1; Ailb += T(2) * (wa + wb) * ilb * Ak1; Aass += Ak1;
+    // d = (P0 tw, P1 tw, (nb - na) in),  tw = 2 in,  in = 1 / (na + nb)
+    const T AP0 = T(2) * in * Ad0, AP1 = T(2) * in * Ad1;
+    const T Ain = T(2) * (P0 * Ad0 + P1 * Ad1) + (nb - na) * Ad2;
+    const T t = -in * in * Ain;
+    const T Ana = t - in * Ad2, Anb = t + in * Ad2;
+    Aq.x += q.z * AP0 - q.w * AP1 + T(2) * q.x * Ana;
+    Aq.y += q.w * AP0 + q.z * AP1 + T(2) * q.y * Ana;
+    Aq.z += q.x * AP0 + q.y * AP1 + T(2) * q.z * Anb;
+    Aq.w += q.y * AP0 - q.x * AP1 + T(2) * q.w * Anb;
+  }
+  xb[0] = Ax0; xb[1] = Ax1; xb[2] = Ax2; xb[3] = As;
+  xb[4] = Aq.x; xb[5] = Aq.y; xb[6] = Aq.z; xb[7] = Aq.w;
+  xb[8] = Al0; xb[9] = Al1; xb[10] = Al2; xb[11] = Al3; xb[12] = Al4;
+  xb[13] = Ab0; xb[14] = Ab1; xb[15] = Ab2; xb[16] = Asb;
+  xb[17] = Awa; xb[18] = Awsa; xb[19] = Ailb; xb[20] = Aass; xb[21] = Aavol; xb[22] = Aasg; xb[23] = AI1;
+  xb[24] = Awb; xb[25] = Awsb;
 }
 
 // Bend-twist between slot L's edge and the next edge (bt_update).
 // Inputs (16): q0..q3 l5 l6 l7 | b0..b3 sb | Ia Ib wsb abt      Outputs (12): q0..q3 l5..l7 | b0..b3 sb
 template <class T>
-__device__ void bt_vjp(const Slot<T>& L, T b0, T b1, T b2, T b3, T sb, T Ib, T wsb, const T (&yb)[12], T (&xb)[16],
-                       int rep, T* X, int lane) {
-  constexpr int KD = KDim<T>::v;
-  const T v[16] = {L.q0, L.q1, L.q2, L.q3, L.l[5], L.l[6], L.l[7], b0, b1, b2, b3, sb, L.I1, Ib, wsb, L.abt};
-#pragma unroll
-  for (int i = 0; i < 16; ++i) xb[i] = T(0);
-  for (int c0 = rep * KD; c0 < 16; c0 += kReps * KD) {
-    DT<T> in[16];
-    seed(in, v, c0);
-    Slot<DT<T>> S;
-    S.f = L.f;
-    S.q0 = in[0]; S.q1 = in[1]; S.q2 = in[2]; S.q3 = in[3];
-    S.l[5] = in[4]; S.l[6] = in[5]; S.l[7] = in[6];
-    DT<T> e0 = in[7], e1 = in[8], e2 = in[9], e3 = in[10], es = in[11];
-    S.I1 = in[12]; S.abt = in[15];
-    S.cbt = DT<T>(L.cbt); S.db0 = DT<T>(L.db0); S.db1 = DT<T>(L.db1); S.db2 = DT<T>(L.db2);
-    bt_update(S, e0, e1, e2, e3, es, in[13], in[14]);
-    const DT<T> out[12] = {S.q0, S.q1, S.q2, S.q3, S.l[5], S.l[6], S.l[7], e0, e1, e2, e3, es};
-    gather_vjp(out, yb, c0, xb);
+__device__ void bt_vjp(const Slot<T>& L, T b0, T b1, T b2, T b3, T sb, T Ib, T wsb, const T (&yb)[12], T (&xb)[16]) {
+  const Q4<T> qa = {L.q0, L.q1, L.q2, L.q3}, qb = {b0, b1, b2, b3};
+  // ---- forward recompute
+  const Q4<T> r = qmul(qconj(qa), qb);
+  const T sg = (r.w < T(0)) ? T(-1) : T(1);
+  const T v0 = sg * r.x, v1 = sg * r.y, v2 = sg * r.z, w = sg * r.w;
+  const T c = L.cbt, sc = sb * c;
+  const T v0s = v0 * v0, v1s = v1 * v1;
+  const T th0 = v0 * v2 + w * v1, th1 = v1 * v2 - w * v0, th2 = T(0.5) - (v0s + v1s);
+  const T Ia = L.I1, at = L.abt;
+  const T sc2 = sc * sc;
+  const T m = sc2 * (T(0.25) * (Ia + Ib));
+  const T sgm = rcp(m + at);
+  const T wc2 = wsb * c * c;
+  const T qs = (wc2 - m) * sgm;
+  const T ks = sc2 * sgm;
+  const T hp = ks * (T(0.125) * (Ia + Ib)), hm = ks * (T(0.125) * (Ia - Ib));
+  const T pv0 = qs * v0, pv1 = qs * v1, pv2 = qs * v2;
+  const T s00 = T(1) + pv0 * v0 - hp * v1s;
+  const T s11 = T(1) + pv1 * v1 - hp * v0s;
+  const T s22 = (T(1) - T(0.5) * at * sgm) + pv2 * v2 - hp * (w * w);
+  const T s01 = (qs + hp) * (v0 * v1);
+  const T s02 = pv0 * v2 + hm * (v1 * w);
+  const T s12 = pv1 * v2 - hm * (v0 * w);
+  const T C0 = sc * v0 - L.db0, C1 = sc * v1 - L.db1, C2 = sc * v2 - L.db2;
+  const T r0 = -C0 - at * L.l[5], r1 = -C1 - at * L.l[6], r2 = -C2 - T(0.5) * at * L.l[7];
+  const T A00 = s11 * s22 - s12 * s12, A01 = s02 * s12 - s01 * s22, A02 = s01 * s12 - s02 * s11;
+  const T A11 = s00 * s22 - s02 * s02, A12 = s01 * s02 - s00 * s12, A22 = s00 * s11 - s01 * s01;
+  const T idt = rcp(s00 * A00 + s01 * A01 + s02 * A02);
+  const T m0 = (A00 * r0 + A01 * r1 + A02 * r2) * idt;   // s^-1 r
+  const T m1 = (A01 * r0 + A11 * r1 + A12 * r2) * idt;
+  const T m2 = (A02 * r0 + A12 * r1 + A22 * r2) * idt;
+  const T g0 = sgm * m0, g1 = sgm * m1, g2 = sgm * m2;
+  const T e0 = w * g0 + (v1 * g2 - v2 * g1);
+  const T e1 = w * g1 + (v2 * g0 - v0 * g2);
+  const T e2 = w * g2 + (v0 * g1 - v1 * g0);
+  const T ka = sc * (T(-0.25) * Ia), ka2 = sc * (T(-0.125) * Ia);
+  const T te = th0 * e0 + th1 * e1 + th2 * e2;
+  const T te2 = te + te;
+  const T kb = (sg * sc) * (T(0.25) * Ib);
+  const Q4<T> ha = {ka * e0, ka * e1, ka2 * e2, T(0)};
+  const Q4<T> qha = qmul(qa, ha);
+  const Q4<T> na = {qa.x + qha.x, qa.y + qha.y, qa.z + qha.z, qa.w + qha.w};
+  const T ina = rsq(na.x * na.x + na.y * na.y + na.z * na.z + na.w * na.w);
+  const T u0 = e0 - te2 * th0, u1 = e1 - te2 * th1, u2 = e2 - te2 * th2;
+  const Q4<T> hb = {kb * u0, kb * u1, kb * u2, T(0)};
+  const Q4<T> rt = {v0, v1, v2, w};
+  const Q4<T> p = qmul(hb, rt);
+  const Q4<T> qp = qmul(qa, p);
+  const Q4<T> nb = {qb.x + qp.x, qb.y + qp.y, qb.z + qp.z, qb.w + qp.w};
+  const T inb = rsq(nb.x * nb.x + nb.y * nb.y + nb.z * nb.z + nb.w * nb.w);
+  // ---- reverse sweep
+  Q4<T> Aqa = {0, 0, 0, 0};
+  T Al5 = yb[4], Al6 = yb[5], Al7 = yb[6];
+  T Asb = yb[11];
+  T AIa = 0, AIb = 0, Awsb = 0, Aat = 0;
+  // sb' = sb + wsb c (v.g)
+  T Av0 = wsb * c * g0 * Asb, Av1 = wsb * c * g1 * Asb, Av2 = wsb * c * g2 * Asb, Aw = 0;
+  T Ag0 = wsb * c * v0 * Asb, Ag1 = wsb * c * v1 * Asb, Ag2 = wsb * c * v2 * Asb;
+  Awsb += c * (v0 * g0 + v1 * g1 + v2 * g2) * Asb;
+  // qb' = nb / |nb|,  nb = qb + qa (x) p,  p = [hb, 0] (x) (v, w)
+  const Q4<T> Anb = normalize_vjp(nb, inb, Q4<T>{yb[7], yb[8], yb[9], yb[10]});
+  Q4<T> Aqb = Anb;
+  {
+    const Q4<T> t = qmul(Anb, qconj(p));
+    Aqa.x += t.x; Aqa.y += t.y; Aqa.z += t.z; Aqa.w += t.w;
   }
-  share_chunks(xb, rep, X, lane);
+  const Q4<T> Ap = qmul(qconj(qa), Anb);
+  const Q4<T> Ahb = qmul(Ap, qconj(rt));
+  {
+    const Q4<T> t = qmul(Q4<T>{-hb.x, -hb.y, -hb.z, T(0)}, Ap);
+    Av0 += t.x; Av1 += t.y; Av2 += t.z; Aw += t.w;
+  }
+  // hb = kb (e - te2 th)
+  const T Akb = Ahb.x * u0 + Ahb.y * u1 + Ahb.z * u2;
+  T Ae0 = kb * Ahb.x, Ae1 = kb * Ahb.y, Ae2 = kb * Ahb.z;
+  const T Ate2 = -kb * (th0 * Ahb.x + th1 * Ahb.y + th2 * Ahb.z);
+  T Ath0 = -kb * te2 * Ahb.x, Ath1 = -kb * te2 * Ahb.y, Ath2 = -kb * te2 * Ahb.z;
+  // qa' = na / |na|,  na = qa + qa (x) [ha, 0]
+  const Q4<T> Ana = normalize_vjp(na, ina, Q4<T>{yb[0], yb[1], yb[2], yb[3]});
+  {
+    const Q4<T> t = qmul(Ana, Q4<T>{-ha.x, -ha.y, -ha.z, T(0)});
+    Aqa.x += Ana.x + t.x; Aqa.y += Ana.y + t.y; Aqa.z += Ana.z + t.z; Aqa.w += Ana.w + t.w;
+  }
+  const Q4<T> Aha = qmul(qconj(qa), Ana);
+  // ha = (ka e0, ka e1, ka2 e2)
+  const T Aka = Aha.x * e0 + Aha.y * e1, Aka2 = Aha.z * e2;
+  Ae0 += ka * Aha.x; Ae1 += ka * Aha.y; Ae2 += ka2 * Aha.z;
+  // kb = sg sc Ib / 4,  ka = -sc Ia / 4,  ka2 = -sc Ia / 8
+  T Asc = sg * T(0.25) * Ib * Akb - T(0.25) * Ia * Aka - T(0.125) * Ia * Aka2;
+  AIb += sg * sc * T(0.25) * Akb;
+  AIa -= sc * (T(0.25) * Aka + T(0.125) * Aka2);
+  // te2 = 2 te,  te = th.e
+  const T Ate = T(2) * Ate2;
+  Ath0 += e0 * Ate; Ath1 += e1 * Ate; Ath2 += e2 * Ate;
+  Ae0 += th0 * Ate; Ae1 += th1 * Ate; Ae2 += th2 * Ate;
+  // e = w g + v x g
+  Aw += Ae0 * g0 + Ae1 * g1 + Ae2 * g2;
+  Ag0 += w * Ae0 + (Ae1 * v2 - Ae2 * v1);
+  Ag1 += w * Ae1 + (Ae2 * v0 - Ae0 * v2);
+  Ag2 += w * Ae2 + (Ae0 * v1 - Ae1 * v0);
+  Av0 += g1 * Ae2 - g2 * Ae1;
+  Av1 += g2 * Ae0 - g0 * Ae2;
+  Av2 += g0 * Ae1 - g1 * Ae0;
+  // l' = l + g
+  Ag0 += Al5; Ag1 += Al6; Ag2 += Al7;
+  // g = sgm s^-1 r:  r_bar = sgm s^-1 g_bar,  sgm_bar = g_bar . s^-1 r,  s_bar = -(s^-1 g_bar) g^T
+  const T z0 = (A00 * Ag0 + A01 * Ag1 + A02 * Ag2) * idt;
+  const T z1 = (A01 * Ag0 + A11 * Ag1 + A12 * Ag2) * idt;
+  const T z2 = (A02 * Ag0 + A12 * Ag1 + A22 * Ag2) * idt;
+  const T Ar0 = sgm * z0, Ar1 = sgm * z1, Ar2 = sgm * z2;
+  T Asgm = Ag0 * m0 + Ag1 * m1 + Ag2 * m2;
+  const T As00 = -z0 * g0, As11 = -z1 * g1, As22 = -z2 * g2;
+  const T As01 = -(z0 * g1 + z1 * g0), As02 = -(z0 * g2 + z2 * g0), As12 = -(z1 * g2 + z2 * g1);
+  // r = -C - at (l5, l6, l7 / 2),  C = sc v - db
+  Aat -= L.l[5] * Ar0 + L.l[6] * Ar1 + T(0.5) * L.l[7] * Ar2;
+  Al5 -= at * Ar0; Al6 -= at * Ar1; Al7 -= T(0.5) * at * Ar2;
+  Asc -= v0 * Ar0 + v1 * Ar1 + v2 * Ar2;
+  Av0 -= sc * Ar0; Av1 -= sc * Ar1; Av2 -= sc * Ar2;
+  // s assembly
+  T Aqs = v0s * As00 + v1s * As11 + v2 * v2 * As22 + v0 * v1 * As01 + v0 * v2 * As02 + v1 * v2 * As12;
+  T Ahp = -v1s * As00 - v0s * As11 - w * w * As22 + v0 * v1 * As01;
+  const T Ahm = v1 * w * As02 - v0 * w * As12;
+  Av0 += T(2) * qs * v0 * As00 - T(2) * hp * v0 * As11 + (qs + hp) * v1 * As01 + qs * v2 * As02 - hm * w * As12;
+  Av1 += T(2) * qs * v1 * As11 - T(2) * hp * v1 * As00 + (qs + hp) * v0 * As01 + hm * w * As02 + qs * v2 * As12;
+  Av2 += T(2) * qs * v2 * As22 + qs * v0 * As02 + qs * v1 * As12;
+  Aw += -T(2) * hp * w * As22 + hm * v1 * As02 - hm * v0 * As12;
+  Aat -= T(0.5) * sgm * As22;
+  Asgm -= T(0.5) * at * As22;
+  // hp = ks (Ia + Ib) / 8,  hm = ks (Ia - Ib) / 8
+  const T Aks = T(0.125) * ((Ia + Ib) * Ahp + (Ia - Ib) * Ahm);
+  AIa += T(0.125) * ks * (Ahp + Ahm);
+  AIb += T(0.125) * ks * (Ahp - Ahm);
+  // ks = sc2 sgm,  qs = (wc2 - m) sgm
+  T Asc2 = sgm * Aks;
+  Asgm += sc2 * Aks + (wc2 - m) * Aqs;
+  Awsb += c * c * sgm * Aqs;
+  T Am = -sgm * Aqs;
+  // sgm = 1 / (m + at)
+  const T tq = -sgm * sgm * Asgm;
+  Am += tq; Aat += tq;
+  // m = sc2 (Ia + Ib) / 4,  sc2 = sc^2,  sc = sb c
+  Asc2 += T(0.25) * (Ia + Ib) * Am;
+  AIa += T(0.25) * sc2 * Am; AIb += T(0.25) * sc2 * Am;
+  Asc += T(2) * sc * Asc2;
+  Asb += c * Asc;
+  // t/2 = (v0 v2 + w v1, v1 v2 - w v0, 1/2 - v0^2 - v1^2)
+  Av0 += v2 * Ath0 - w * Ath1 - T(2) * v0 * Ath2;
+  Av1 += w * Ath0 + v2 * Ath1 - T(2) * v1 * Ath2;
+  Av2 += v0 * Ath0 + v1 * Ath1;
+  Aw += v1 * Ath0 - v0 * Ath1;
+  // (v, w) = sg r,  r = conj(qa) (x) qb
+  const Q4<T> Ar = {sg * Av0, sg * Av1, sg * Av2, sg * Aw};
+  {
+    const Q4<T> t = qmul(qa, Ar);
+    Aqb.x += t.x; Aqb.y += t.y; Aqb.z += t.z; Aqb.w += t.w;
+    const Q4<T> u = qmul(qb, qconj(Ar));
+    Aqa.x += u.x; Aqa.y += u.y; Aqa.z += u.z; Aqa.w += u.w;
+  }
+  xb[0] = Aqa.x; xb[1] = Aqa.y; xb[2] = Aqa.z; xb[3] = Aqa.w;
+  xb[4] = Al5; xb[5] = Al6; xb[6] = Al7;
+  xb[7] = Aqb.x; xb[8] = Aqb.y; xb[9] = Aqb.z; xb[10] = Aqb.w; xb[11] = Asb;
+  xb[12] = AIa; xb[13] = AIb; xb[14] = Awsb; xb[15] = Aat;
 }
 
-// Angular velocity from the quaternions after / before the substep (omega_of).
+// Angular velocity from the quaternions after / before the substep (omega_of):
+// o = sgf Im(q (x) conj(p)), sgf = +-2 / h by the sign of the real part.
 // Inputs (8): q0..q3 p0..p3       Outputs (3): o0 o1 o2
 template <class T>
 __device__ void omega_vjp(const Slot<T>& L, T ih, const T (&yb)[3], T (&xb)[8]) {
-  const T v[8] = {L.q0, L.q1, L.q2, L.q3, L.qp0, L.qp1, L.qp2, L.qp3};
-  for (int c0 = 0; c0 < 8; c0 += KDim<T>::v) {
-    DT<T> in[8];
-    seed(in, v, c0);
-    DT<T> o[3];
-    omega_of(in[0], in[1], in[2], in[3], in[4], in[5], in[6], in[7], DT<T>(ih), o[0], o[1], o[2]);
-    gather_vjp(o, yb, c0, xb);
-  }
+  const Q4<T> q = {L.q0, L.q1, L.q2, L.q3}, p = {L.qp0, L.qp1, L.qp2, L.qp3};
+  const Q4<T> r = qmul(q, qconj(p));
+  const T sgf = (r.w < T(0)) ? T(-2) * ih : T(2) * ih;
+  const Q4<T> Ar = {sgf * yb[0], sgf * yb[1], sgf * yb[2], T(0)};
+  const Q4<T> Aq = qmul(Ar, p);                 // r = R(conj p) q
+  const Q4<T> Ap = qmul(qconj(Ar), q);          // r = L(q) conj(p)
+  xb[0] = Aq.x; xb[1] = Aq.y; xb[2] = Aq.z; xb[3] = Aq.w;
+  xb[4] = Ap.x; xb[5] = Ap.y; xb[6] = Ap.z; xb[7] = Ap.w;
 }
 
-// Predicted quaternion normalize(q + 1/2 [h w, 0] (x) q).
+// Predicted quaternion normalize(q + [a, 0] (x) q), a = h w / 2 (qrot_world).
 // Inputs (7): q0..q3 w0 w1 w2     Outputs (4): q0..q3
 template <class T>
 __device__ void qpredict_vjp(T q0, T q1, T q2, T q3, T w0, T w1, T w2, T h, const T (&yb)[4], T (&xb)[7]) {
-  const T v[7] = {q0, q1, q2, q3, w0, w1, w2};
-  for (int c0 = 0; c0 < 7; c0 += KDim<T>::v) {
-    DT<T> in[7];
-    seed(in, v, c0);
-    DT<T> a = in[0], b = in[1], c = in[2], e = in[3];
-    const DT<T> hh(h);
-    qrot_world(a, b, c, e, hh * in[4], hh * in[5], hh * in[6]);
-    const DT<T> out[4] = {a, b, c, e};
-    gather_vjp(out, yb, c0, xb);
-  }
+  const Q4<T> q = {q0, q1, q2, q3};
+  const Q4<T> a = {T(0.5) * (h * w0), T(0.5) * (h * w1), T(0.5) * (h * w2), T(0)};
+  const Q4<T> aq = qmul(a, q);
+  const Q4<T> n = {q.x + aq.x, q.y + aq.y, q.z + aq.z, q.w + aq.w};
+  const T inv = rsq(n.x * n.x + n.y * n.y + n.z * n.z + n.w * n.w);
+  const Q4<T> An = normalize_vjp(n, inv, Q4<T>{yb[0], yb[1], yb[2], yb[3]});
+  const Q4<T> t = qmul(Q4<T>{-a.x, -a.y, -a.z, T(0)}, An);   // n = q + L(a) q
+  const Q4<T> Aa = qmul(An, qconj(q));                      // n = q + R(q) a
+  xb[0] = An.x + t.x; xb[1] = An.y + t.y; xb[2] = An.z + t.z; xb[3] = An.w + t.w;
+  xb[4] = T(0.5) * h * Aa.x; xb[5] = T(0.5) * h * Aa.y; xb[6] = T(0.5) * h * Aa.z;
 }
 
 // ---------------------------------------------------------------- adjoint state
@@ -240,54 +431,122 @@ __device__ __forceinline__ void zero_adj(SAdj<T>& a) {
   a.w = a.ws = a.ilb = a.ass = a.avol = a.asg = a.abt = a.I1 = a.inert = T(0);
 }
 
-// Snapshot of the pre-pass state of both slots (x, s, q, lambda): 32 values per lane,
-// stored field-major over the scene's lanes for coalesced access.
+// Snapshots of the pre-pass state, stored field-major over the scene's lanes for coalesced
+// access: before an edge pass the values it reads and changes (x, s, q, the stretch-shear,
+// volume and scale-gradient multipliers) of both slots, 26 per lane; before a bend-twist
+// pass q, s and the bend-twist multipliers of both slots, 16 per lane.  One iteration's four
+// snapshots take kSnapPerIter values per lane.
+__host__ __device__ constexpr int snap_offset(int k) { return k < 2 ? k * kSnapEdge : 2 * kSnapEdge + (k - 2) * kSnapBt; }
+
 template <class T>
-__device__ __forceinline__ void snap_io(T* base, size_t NL, Slot<T>& A, Slot<T>& B, bool store) {
-#define SNAP_FIELD(i, ref) { T* p = base + (size_t)(i) * NL; if (store) *p = (ref); else (ref) = *p; }
-  SNAP_FIELD(0, A.x0) SNAP_FIELD(1, A.x1) SNAP_FIELD(2, A.x2) SNAP_FIELD(3, A.s)
-  SNAP_FIELD(4, A.q0) SNAP_FIELD(5, A.q1) SNAP_FIELD(6, A.q2) SNAP_FIELD(7, A.q3)
-  SNAP_FIELD(16, B.x0) SNAP_FIELD(17, B.x1) SNAP_FIELD(18, B.x2) SNAP_FIELD(19, B.s)
-  SNAP_FIELD(20, B.q0) SNAP_FIELD(21, B.q1) SNAP_FIELD(22, B.q2) SNAP_FIELD(23, B.q3)
+__device__ __forceinline__ void snap_edge_store(T* base, size_t NL, const Slot<T>& A, const Slot<T>& B) {
+  const T v[kSnapEdge] = {A.x0, A.x1, A.x2, A.s, A.q0, A.q1, A.q2, A.q3, A.l[0], A.l[1], A.l[2], A.l[3], A.l[4],
+                          B.x0, B.x1, B.x2, B.s, B.q0, B.q1, B.q2, B.q3, B.l[0], B.l[1], B.l[2], B.l[3], B.l[4]};
 #pragma unroll
-  for (int i = 0; i < 8; ++i) { SNAP_FIELD(8 + i, A.l[i]) SNAP_FIELD(24 + i, B.l[i]) }
-#undef SNAP_FIELD
+  for (int i = 0; i < kSnapEdge; ++i) base[(size_t)i * NL] = v[i];
+}
+template <class T>
+__device__ __forceinline__ void snap_bt_store(T* base, size_t NL, const Slot<T>& A, const Slot<T>& B) {
+  const T v[kSnapBt] = {A.q0, A.q1, A.q2, A.q3, A.s, A.l[5], A.l[6], A.l[7],
+                        B.q0, B.q1, B.q2, B.q3, B.s, B.l[5], B.l[6], B.l[7]};
+#pragma unroll
+  for (int i = 0; i < kSnapBt; ++i) base[(size_t)i * NL] = v[i];
+}
+template <class T, int N>
+__device__ __forceinline__ void snap_load(const T* base, size_t NL, T (&v)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = base[(size_t)i * NL];
+}
+template <class T>
+__device__ __forceinline__ void snap_edge_apply(const T (&v)[kSnapEdge], Slot<T>& A, Slot<T>& B) {
+  A.x0 = v[0]; A.x1 = v[1]; A.x2 = v[2]; A.s = v[3]; A.q0 = v[4]; A.q1 = v[5]; A.q2 = v[6]; A.q3 = v[7];
+  A.l[0] = v[8]; A.l[1] = v[9]; A.l[2] = v[10]; A.l[3] = v[11]; A.l[4] = v[12];
+  B.x0 = v[13]; B.x1 = v[14]; B.x2 = v[15]; B.s = v[16]; B.q0 = v[17]; B.q1 = v[18]; B.q2 = v[19]; B.q3 = v[20];
+  B.l[0] = v[21]; B.l[1] = v[22]; B.l[2] = v[23]; B.l[3] = v[24]; B.l[4] = v[25];
+}
+template <class T>
+__device__ __forceinline__ void snap_bt_apply(const T (&v)[kSnapBt], Slot<T>& A, Slot<T>& B) {
+  A.q0 = v[0]; A.q1 = v[1]; A.q2 = v[2]; A.q3 = v[3]; A.s = v[4]; A.l[5] = v[5]; A.l[6] = v[6]; A.l[7] = v[7];
+  B.q0 = v[8]; B.q1 = v[9]; B.q2 = v[10]; B.q3 = v[11]; B.s = v[12]; B.l[5] = v[13]; B.l[6] = v[14]; B.l[7] = v[15];
 }
 
 // ---------------------------------------------------------------- reverse passes
 
-// Every lane calls the local VJP once per pass (the call has block barriers): on its A edge,
-// its B edge, or on a dummy whose result it discards.
+// Each lane forms the local VJP of the projection it owns in this pass (its A edge or its B
+// edge; none when neither has the colour).  The right end of a B edge is the next lane's A:
+// its pre-pass values come down one lane, its adjoint goes back up.
+// The edge VJP of slot L with right end (b, sb; wb, wsb), result written to the adjoints a
+// (slot) and its right end (bx, bs, bw, bws).
 template <class T>
-__device__ void pass_edges_vjp(Lane2<T>& P, SAdj<T>& aA, SAdj<T>& aB, int colour, int rep, T* X, int lane) {
+__device__ __forceinline__ void edge_vjp_apply(const Slot<T>& L, SAdj<T>& a, T b0, T b1, T b2, T sb, T wb, T wsb,
+                                               T& bx0, T& bx1, T& bx2, T& bs, T& bw, T& bws) {
+  const T yb[17] = {a.x0, a.x1, a.x2, a.s, a.q0, a.q1, a.q2, a.q3, a.l[0], a.l[1], a.l[2], a.l[3], a.l[4],
+                    bx0, bx1, bx2, bs};
+  T xb[26];
+  edge_vjp(L, b0, b1, b2, sb, wb, wsb, yb, xb);
+  a.x0 = xb[0]; a.x1 = xb[1]; a.x2 = xb[2]; a.s = xb[3];
+  a.q0 = xb[4]; a.q1 = xb[5]; a.q2 = xb[6]; a.q3 = xb[7];
+  a.l[0] = xb[8]; a.l[1] = xb[9]; a.l[2] = xb[10]; a.l[3] = xb[11]; a.l[4] = xb[12];
+  a.w += xb[17]; a.ws += xb[18]; a.ilb += xb[19]; a.ass += xb[20]; a.avol += xb[21]; a.asg += xb[22];
+  a.I1 += xb[23];
+  bx0 = xb[13]; bx1 = xb[14]; bx2 = xb[15]; bs = xb[16]; bw += xb[24]; bws += xb[25];
+}
+
+// The bend-twist VJP of slot L with the next edge (qb, sb; Ib, wsb), result written to the
+// adjoints a (slot) and the next edge's (bq, bs, bI, bws).
+template <class T>
+__device__ __forceinline__ void bt_vjp_apply(const Slot<T>& L, SAdj<T>& a, T b0, T b1, T b2, T b3, T sb, T Ib, T wsb,
+                                             T& bq0, T& bq1, T& bq2, T& bq3, T& bs, T& bI, T& bws) {
+  const T yb[12] = {a.q0, a.q1, a.q2, a.q3, a.l[5], a.l[6], a.l[7], bq0, bq1, bq2, bq3, bs};
+  T xb[16];
+  bt_vjp(L, b0, b1, b2, b3, sb, Ib, wsb, yb, xb);
+  a.q0 = xb[0]; a.q1 = xb[1]; a.q2 = xb[2]; a.q3 = xb[3];
+  a.l[5] = xb[4]; a.l[6] = xb[5]; a.l[7] = xb[6];
+  a.I1 += xb[12]; a.abt += xb[15];
+  bq0 = xb[7]; bq1 = xb[8]; bq2 = xb[9]; bq3 = xb[10]; bs = xb[11]; bI += xb[13]; bws += xb[14];
+}
+
+template <class T, bool EVEN>
+__device__ void pass_edges_vjp(Lane2<T>& P, SAdj<T>& aA, SAdj<T>& aB, int colour) {
+  if constexpr (EVEN) {   // slot A holds the even pills (the forward's lane-local passes)
+    if (colour == 0) {
+      if (P.A.f & F_EDGE)
+        edge_vjp_apply(P.A, aA, P.B.x0, P.B.x1, P.B.x2, P.B.s, P.B.w, P.B.ws, aB.x0, aB.x1, aB.x2, aB.s, aB.w, aB.ws);
+      return;
+    }
+    const T n0 = dn(P.A.x0), n1 = dn(P.A.x1), n2 = dn(P.A.x2), ns = dn(P.A.s);
+    T r0 = dn(aA.x0), r1 = dn(aA.x1), r2 = dn(aA.x2), rs = dn(aA.s), rw = T(0), rws = T(0);
+    if (P.B.f & F_EDGE) edge_vjp_apply(P.B, aB, n0, n1, n2, ns, P.wN, P.wsN, r0, r1, r2, rs, rw, rws);
+    r0 = up(r0); r1 = up(r1); r2 = up(r2); rs = up(rs); rw = up(rw); rws = up(rws);
+    if ((P.A.f & F_VALID) && !(P.A.f & F_FIRST)) {
+      aA.x0 = r0; aA.x1 = r1; aA.x2 = r2; aA.s = rs; aA.w += rw; aA.ws += rws;
+    }
+    return;
+  }
   const T n0 = dn(P.A.x0), n1 = dn(P.A.x1), n2 = dn(P.A.x2), ns = dn(P.A.s);       // pre-pass next slot A
   const T g0 = dn(aA.x0), g1 = dn(aA.x1), g2 = dn(aA.x2), gs = dn(aA.s);            // adjoint of its post-pass value
   const bool useA = (P.A.f & F_EDGE) && colour_is(P.A.f, colour);
   const bool useB = !useA && (P.B.f & F_EDGE) && colour_is(P.B.f, colour);
-  const Slot<T> L = useB ? P.B : P.A;
-  const T yb[17] = {useB ? aB.x0 : aA.x0, useB ? aB.x1 : aA.x1, useB ? aB.x2 : aA.x2, useB ? aB.s : aA.s,
-                    useB ? aB.q0 : aA.q0, useB ? aB.q1 : aA.q1, useB ? aB.q2 : aA.q2, useB ? aB.q3 : aA.q3,
-                    useB ? aB.l[0] : aA.l[0], useB ? aB.l[1] : aA.l[1], useB ? aB.l[2] : aA.l[2],
-                    useB ? aB.l[3] : aA.l[3], useB ? aB.l[4] : aA.l[4],
-                    useB ? g0 : aB.x0, useB ? g1 : aB.x1, useB ? g2 : aB.x2, useB ? gs : aB.s};
-  T xb[26];
-  edge_vjp(L, useB ? n0 : P.B.x0, useB ? n1 : P.B.x1, useB ? n2 : P.B.x2, useB ? ns : P.B.s,
-           useB ? P.wN : P.B.w, useB ? P.wsN : P.B.ws, yb, xb, rep, X, lane);
   T r0 = T(0), r1 = T(0), r2 = T(0), rs = T(0), rw = T(0), rws = T(0);
-  if (useA) {
-    aA.x0 = xb[0]; aA.x1 = xb[1]; aA.x2 = xb[2]; aA.s = xb[3];
-    aA.q0 = xb[4]; aA.q1 = xb[5]; aA.q2 = xb[6]; aA.q3 = xb[7];
-    aA.l[0] = xb[8]; aA.l[1] = xb[9]; aA.l[2] = xb[10]; aA.l[3] = xb[11]; aA.l[4] = xb[12];
-    aB.x0 = xb[13]; aB.x1 = xb[14]; aB.x2 = xb[15]; aB.s = xb[16];
-    aA.w += xb[17]; aA.ws += xb[18]; aA.ilb += xb[19]; aA.ass += xb[20]; aA.avol += xb[21]; aA.asg += xb[22];
-    aA.I1 += xb[23]; aB.w += xb[24]; aB.ws += xb[25];
-  } else if (useB) {
-    aB.x0 = xb[0]; aB.x1 = xb[1]; aB.x2 = xb[2]; aB.s = xb[3];
-    aB.q0 = xb[4]; aB.q1 = xb[5]; aB.q2 = xb[6]; aB.q3 = xb[7];
-    aB.l[0] = xb[8]; aB.l[1] = xb[9]; aB.l[2] = xb[10]; aB.l[3] = xb[11]; aB.l[4] = xb[12];
-    r0 = xb[13]; r1 = xb[14]; r2 = xb[15]; rs = xb[16];
-    aB.w += xb[17]; aB.ws += xb[18]; aB.ilb += xb[19]; aB.ass += xb[20]; aB.avol += xb[21]; aB.asg += xb[22];
-    aB.I1 += xb[23]; rw = xb[24]; rws = xb[25];
+  if (useA || useB) {
+    const Slot<T>& L = useB ? P.B : P.A;
+    SAdj<T>& a = useB ? aB : aA;
+    const T yb[17] = {a.x0, a.x1, a.x2, a.s, a.q0, a.q1, a.q2, a.q3, a.l[0], a.l[1], a.l[2], a.l[3], a.l[4],
+                      useB ? g0 : aB.x0, useB ? g1 : aB.x1, useB ? g2 : aB.x2, useB ? gs : aB.s};
+    T xb[26];
+    edge_vjp(L, useB ? n0 : P.B.x0, useB ? n1 : P.B.x1, useB ? n2 : P.B.x2, useB ? ns : P.B.s,
+             useB ? P.wN : P.B.w, useB ? P.wsN : P.B.ws, yb, xb);
+    a.x0 = xb[0]; a.x1 = xb[1]; a.x2 = xb[2]; a.s = xb[3];
+    a.q0 = xb[4]; a.q1 = xb[5]; a.q2 = xb[6]; a.q3 = xb[7];
+    a.l[0] = xb[8]; a.l[1] = xb[9]; a.l[2] = xb[10]; a.l[3] = xb[11]; a.l[4] = xb[12];
+    a.w += xb[17]; a.ws += xb[18]; a.ilb += xb[19]; a.ass += xb[20]; a.avol += xb[21]; a.asg += xb[22];
+    a.I1 += xb[23];
+    if (useA) {
+      aB.x0 = xb[13]; aB.x1 = xb[14]; aB.x2 = xb[15]; aB.s = xb[16];
+      aB.w += xb[24]; aB.ws += xb[25];
+    } else {
+      r0 = xb[13]; r1 = xb[14]; r2 = xb[15]; rs = xb[16]; rw = xb[24]; rws = xb[25];
+    }
   }
   r0 = up(r0); r1 = up(r1); r2 = up(r2); rs = up(rs); rw = up(rw); rws = up(rws);
   if ((P.A.f & F_VALID) && !(P.A.f & F_FIRST) && !colour_is(P.A.f, colour)) {
@@ -295,30 +554,47 @@ __device__ void pass_edges_vjp(Lane2<T>& P, SAdj<T>& aA, SAdj<T>& aB, int colour
   }
 }
 
-template <class T>
-__device__ void pass_bt_vjp(Lane2<T>& P, SAdj<T>& aA, SAdj<T>& aB, int colour, int rep, T* X, int lane) {
+template <class T, bool EVEN>
+__device__ void pass_bt_vjp(Lane2<T>& P, SAdj<T>& aA, SAdj<T>& aB, int colour) {
+  if constexpr (EVEN) {
+    if (colour == 0) {
+      if ((P.A.f & F_BT) && (P.A.f & F_BTEN))
+        bt_vjp_apply(P.A, aA, P.B.q0, P.B.q1, P.B.q2, P.B.q3, P.B.s, P.B.I1, P.B.ws, aB.q0, aB.q1, aB.q2, aB.q3, aB.s,
+                     aB.I1, aB.ws);
+      return;
+    }
+    const T n0 = dn(P.A.q0), n1 = dn(P.A.q1), n2 = dn(P.A.q2), n3 = dn(P.A.q3), ns = dn(P.A.s);
+    T r0 = dn(aA.q0), r1 = dn(aA.q1), r2 = dn(aA.q2), r3 = dn(aA.q3), rs = dn(aA.s), rI = T(0), rws = T(0);
+    if ((P.B.f & F_BT) && (P.B.f & F_BTEN))
+      bt_vjp_apply(P.B, aB, n0, n1, n2, n3, ns, P.I1N, P.wsN, r0, r1, r2, r3, rs, rI, rws);
+    r0 = up(r0); r1 = up(r1); r2 = up(r2); r3 = up(r3); rs = up(rs); rI = up(rI); rws = up(rws);
+    if ((P.A.f & F_EDGE) && !(P.A.f & F_FIRST) && (P.A.f & F_BTEN)) {
+      aA.q0 = r0; aA.q1 = r1; aA.q2 = r2; aA.q3 = r3; aA.s = rs; aA.I1 += rI; aA.ws += rws;
+    }
+    return;
+  }
   const T n0 = dn(P.A.q0), n1 = dn(P.A.q1), n2 = dn(P.A.q2), n3 = dn(P.A.q3), ns = dn(P.A.s);
   const T g0 = dn(aA.q0), g1 = dn(aA.q1), g2 = dn(aA.q2), g3 = dn(aA.q3), gs = dn(aA.s);
   const bool useA = (P.A.f & F_BT) && (P.A.f & F_BTEN) && colour_is(P.A.f, colour);
   const bool useB = !useA && (P.B.f & F_BT) && (P.B.f & F_BTEN) && colour_is(P.B.f, colour);
-  const Slot<T> L = useB ? P.B : P.A;
-  const T yb[12] = {useB ? aB.q0 : aA.q0, useB ? aB.q1 : aA.q1, useB ? aB.q2 : aA.q2, useB ? aB.q3 : aA.q3,
-                    useB ? aB.l[5] : aA.l[5], useB ? aB.l[6] : aA.l[6], useB ? aB.l[7] : aA.l[7],
-                    useB ? g0 : aB.q0, useB ? g1 : aB.q1, useB ? g2 : aB.q2, useB ? g3 : aB.q3, useB ? gs : aB.s};
-  T xb[16];
-  bt_vjp(L, useB ? n0 : P.B.q0, useB ? n1 : P.B.q1, useB ? n2 : P.B.q2, useB ? n3 : P.B.q3, useB ? ns : P.B.s,
-         useB ? P.I1N : P.B.I1, useB ? P.wsN : P.B.ws, yb, xb, rep, X, lane);
   T r0 = T(0), r1 = T(0), r2 = T(0), r3 = T(0), rs = T(0), rI = T(0), rws = T(0);
-  if (useA) {
-    aA.q0 = xb[0]; aA.q1 = xb[1]; aA.q2 = xb[2]; aA.q3 = xb[3];
-    aA.l[5] = xb[4]; aA.l[6] = xb[5]; aA.l[7] = xb[6];
-    aB.q0 = xb[7]; aB.q1 = xb[8]; aB.q2 = xb[9]; aB.q3 = xb[10]; aB.s = xb[11];
-    aA.I1 += xb[12]; aB.I1 += xb[13]; aB.ws += xb[14]; aA.abt += xb[15];
-  } else if (useB) {
-    aB.q0 = xb[0]; aB.q1 = xb[1]; aB.q2 = xb[2]; aB.q3 = xb[3];
-    aB.l[5] = xb[4]; aB.l[6] = xb[5]; aB.l[7] = xb[6];
-    r0 = xb[7]; r1 = xb[8]; r2 = xb[9]; r3 = xb[10]; rs = xb[11];
-    aB.I1 += xb[12]; rI = xb[13]; rws = xb[14]; aB.abt += xb[15];
+  if (useA || useB) {
+    const Slot<T>& L = useB ? P.B : P.A;
+    SAdj<T>& a = useB ? aB : aA;
+    const T yb[12] = {a.q0, a.q1, a.q2, a.q3, a.l[5], a.l[6], a.l[7],
+                      useB ? g0 : aB.q0, useB ? g1 : aB.q1, useB ? g2 : aB.q2, useB ? g3 : aB.q3, useB ? gs : aB.s};
+    T xb[16];
+    bt_vjp(L, useB ? n0 : P.B.q0, useB ? n1 : P.B.q1, useB ? n2 : P.B.q2, useB ? n3 : P.B.q3, useB ? ns : P.B.s,
+           useB ? P.I1N : P.B.I1, useB ? P.wsN : P.B.ws, yb, xb);
+    a.q0 = xb[0]; a.q1 = xb[1]; a.q2 = xb[2]; a.q3 = xb[3];
+    a.l[5] = xb[4]; a.l[6] = xb[5]; a.l[7] = xb[6];
+    a.I1 += xb[12]; a.abt += xb[15];
+    if (useA) {
+      aB.q0 = xb[7]; aB.q1 = xb[8]; aB.q2 = xb[9]; aB.q3 = xb[10]; aB.s = xb[11];
+      aB.I1 += xb[13]; aB.ws += xb[14];
+    } else {
+      r0 = xb[7]; r1 = xb[8]; r2 = xb[9]; r3 = xb[10]; rs = xb[11]; rI = xb[13]; rws = xb[14];
+    }
   }
   r0 = up(r0); r1 = up(r1); r2 = up(r2); r3 = up(r3); rs = up(rs); rI = up(rI); rws = up(rws);
   if ((P.A.f & F_EDGE) && !(P.A.f & F_FIRST) && (P.A.f & F_BTEN) && !colour_is(P.A.f, colour)) {
@@ -406,40 +682,20 @@ __global__ void __launch_bounds__(256) rod_frame_ckpt_kernel(const Dev<T>* __res
 // at the end of the substep on entry and at its start on exit; padj ([8][pill]) accumulates
 // the parameter adjoints: 1/M, 1/M_s, 1/lbar, rho pi r^4 l0, and the four compliance
 // scalings; snap is this lane's pass-snapshot scratch.
-// Block b works on logical wavefront tab[b / 4].base + b % 4 (the forward's lane layout),
-// replicated in its kReps waves: replica r = wave index within the block.  A whole block is
-// inactive or active, so the early return never splits a barrier.
-template <class T>
-__device__ __forceinline__ const Dev<T>* lane_setup_rep(const Dev<T>* D, const Blk* tab, Lane2<T>& P, int& pA,
-                                                        int& pB, int& wave) {
-  const Blk b = tab[blockIdx.x >> 2];
-  const Dev<T>* d = D + b.scene;
-  wave = b.base + (int)(blockIdx.x & 3);
-  const int lane = (int)(threadIdx.x & 63);
-  if (wave >= d->W) return nullptr;
-  const int p0 = d->wave_start[wave];
-  const int n = d->wave_start[wave + 1] - p0;
-  const bool vA = 2 * lane < n, vB = 2 * lane + 1 < n;
-  pA = p0 + (vA ? 2 * lane : 0);
-  pB = p0 + (vB ? 2 * lane + 1 : 0);
-  P.A.f = vA ? d->flags[pA] : 0u;
-  P.B.f = vB ? d->flags[pB] : 0u;
-  return d;
-}
-
+// The forward's lane layout, one wavefront per block (block b runs wavefront
+// tab[b / 4].base + b % 4): a small scene's wavefronts spread over every compute unit.
 template <class T, bool EVEN>
-__global__ void __launch_bounds__(64 * kReps) rod_backward_kernel(const Dev<T>* __restrict__ D, const Blk* __restrict__ tab,
+__global__ void __launch_bounds__(64) rod_backward_kernel(const Dev<T>* __restrict__ D, const Blk* __restrict__ tab,
                                                            T h, int iters, const T* __restrict__ ckpt, T* __restrict__ snap,
                                                            T* __restrict__ adj, T* __restrict__ padj) {
-  __shared__ T X[26 * 64];                 // chunk exchange between the replicas
   Lane2<T> P;
-  int pA, pB, wave;
-  const Dev<T>* dp = lane_setup_rep(D, tab, P, pA, pB, wave);
+  int pA, pB;
+  const Blk blk = tab[blockIdx.x >> 2];
+  const int wave = blk.base + (int)(blockIdx.x & 3);
+  const Dev<T>* dp = lane_setup_wave(D, blk, wave, P, pA, pB);
   if (!dp) return;
   const Dev<T>& d = *dp;
   const int lane = (int)(threadIdx.x & 63);
-  const int rep = (int)(threadIdx.x >> 6);
-  const bool writer = rep == 0;
   const size_t NL = (size_t)d.W * 64;
   const size_t lg = (size_t)wave * 64 + lane;
   T* cbase = const_cast<T*>(ckpt);
@@ -452,15 +708,20 @@ __global__ void __launch_bounds__(64 * kReps) rod_backward_kernel(const Dev<T>* 
   predict_slot(P.A, h, d.gx, d.gy, d.gz);
   predict_slot(P.B, h, d.gx, d.gy, d.gz);
   inertia_lane(P);
+  T* const sbase = snap + lg;
   for (int it = 0; it < iters; ++it) {
-    for (int k = 0; k < 4; ++k) {
-      if (writer) snap_io(snap + ((size_t)(it * 4 + k) * 32) * NL + lg, NL, P.A, P.B, true);
-      if (k < 2) pass_edges<T, false, EVEN>(P, k); else pass_bt<T, EVEN>(P, k - 2);
-    }
+    T* const si = sbase + (size_t)it * kSnapPerIter * NL;
+    snap_edge_store(si + snap_offset(0) * NL, NL, P.A, P.B);
+    pass_edges<T, false, EVEN>(P, 0);
+    snap_edge_store(si + snap_offset(1) * NL, NL, P.A, P.B);
+    pass_edges<T, false, EVEN>(P, 1);
+    snap_bt_store(si + snap_offset(2) * NL, NL, P.A, P.B);
+    pass_bt<T, EVEN>(P, 0);
+    snap_bt_store(si + snap_offset(3) * NL, NL, P.A, P.B);
+    pass_bt<T, EVEN>(P, 1);
   }
   velocity_slot(P.A, ih);
   velocity_slot(P.B, ih);
-  __syncthreads();                         // the snapshots of replica 0 are read by all
   // adjoint of the substep-end state
   SAdj<T> aA, aB;
   zero_adj(aA);
@@ -478,11 +739,50 @@ __global__ void __launch_bounds__(64 * kReps) rod_backward_kernel(const Dev<T>* 
   }
   velocity_vjp(P.A, aA, ih);
   velocity_vjp(P.B, aB, ih);
-  // the passes in reverse order, each from its pre-pass snapshot
+  // the passes in reverse order, each from its pre-pass snapshot.  FP32: the loads of the
+  // next snapshot are issued before the current pass's VJP (FP64 has no registers to spare
+  // for that and loads it after).
+  constexpr bool kPre = sizeof(T) == 4;
+  if (iters > 0) {
+    T v[kSnapBt];
+    snap_load(sbase + ((size_t)(iters - 1) * kSnapPerIter + snap_offset(3)) * NL, NL, v);
+    snap_bt_apply(v, P.A, P.B);
+  }
   for (int it = iters - 1; it >= 0; --it) {
-    for (int k = 3; k >= 0; --k) {
-      snap_io(snap + ((size_t)(it * 4 + k) * 32) * NL + lg, NL, P.A, P.B, false);
-      if (k < 2) pass_edges_vjp(P, aA, aB, k, rep, X, lane); else pass_bt_vjp(P, aA, aB, k - 2, rep, X, lane);
+    const T* const si = sbase + (size_t)it * kSnapPerIter * NL;
+    {
+      T v[kSnapBt];
+      if (kPre) snap_load(si + snap_offset(2) * NL, NL, v);
+      pass_bt_vjp<T, EVEN>(P, aA, aB, 1);
+      if (!kPre) __builtin_amdgcn_sched_barrier(0);
+      if (!kPre) snap_load(si + snap_offset(2) * NL, NL, v);
+      snap_bt_apply(v, P.A, P.B);
+    }
+    {
+      T v[kSnapEdge];
+      if (kPre) snap_load(si + snap_offset(1) * NL, NL, v);
+      pass_bt_vjp<T, EVEN>(P, aA, aB, 0);
+      if (!kPre) __builtin_amdgcn_sched_barrier(0);
+      if (!kPre) snap_load(si + snap_offset(1) * NL, NL, v);
+      snap_edge_apply(v, P.A, P.B);
+    }
+    {
+      T v[kSnapEdge];
+      if (kPre) snap_load(si + snap_offset(0) * NL, NL, v);
+      pass_edges_vjp<T, EVEN>(P, aA, aB, 1);
+      if (!kPre) __builtin_amdgcn_sched_barrier(0);
+      if (!kPre) snap_load(si + snap_offset(0) * NL, NL, v);
+      snap_edge_apply(v, P.A, P.B);
+    }
+    if (it > 0) {
+      T v[kSnapBt];
+      if (kPre) snap_load(si - (size_t)kSnapPerIter * NL + snap_offset(3) * NL, NL, v);
+      pass_edges_vjp<T, EVEN>(P, aA, aB, 0);
+      if (!kPre) __builtin_amdgcn_sched_barrier(0);
+      if (!kPre) snap_load(si - (size_t)kSnapPerIter * NL + snap_offset(3) * NL, NL, v);
+      snap_bt_apply(v, P.A, P.B);
+    } else {
+      pass_edges_vjp<T, EVEN>(P, aA, aB, 0);
     }
   }
   // substep-start inertia of both edges (the B edge's right end is the next lane's A)
@@ -518,7 +818,6 @@ __global__ void __launch_bounds__(64 * kReps) rod_backward_kernel(const Dev<T>* 
       out.q0 = T(0); out.q1 = T(0); out.q2 = T(0); out.q3 = T(0);
       out.o0 = T(0); out.o1 = T(0); out.o2 = T(0);
     }
-    if (!writer) continue;
     ckpt_io(adj, d.P, ps[j], out, true);
     const int p = ps[j];
     padj[0 * (size_t)d.P + p] += a.w;
@@ -614,10 +913,10 @@ hipError_t launch_backward(const BatchDev& b, int P, int nsub, double h, int ite
   for (int sub = nsub - 1; sub >= 0; --sub) {
     const T* ck = ckpt + (size_t)sub * kCkptFields * P;
     if (b.even)
-      hipLaunchKernelGGL((rod_backward_kernel<T, true>), dim3(4 * b.nblk[TB_WAVES]), dim3(64 * kReps), 0, st,
+      hipLaunchKernelGGL((rod_backward_kernel<T, true>), dim3(4 * b.nblk[TB_WAVES]), dim3(64), 0, st,
                          (const Dev<T>*)b.dev, b.tab[TB_WAVES], (T)h, iters, ck, snap, adj, padj);
     else
-      hipLaunchKernelGGL((rod_backward_kernel<T, false>), dim3(4 * b.nblk[TB_WAVES]), dim3(64 * kReps), 0, st,
+      hipLaunchKernelGGL((rod_backward_kernel<T, false>), dim3(4 * b.nblk[TB_WAVES]), dim3(64), 0, st,
                          (const Dev<T>*)b.dev, b.tab[TB_WAVES], (T)h, iters, ck, snap, adj, padj);
   }
   hipLaunchKernelGGL(adjoint_chain_kernel<T>, dim3((P + 255) / 256), dim3(256), 0, st, (const Dev<T>*)b.dev,

@@ -528,10 +528,9 @@ __device__ __forceinline__ void iteration_lane(Lane2<T>& P) {
 // valid index beyond the run; such slots carry no flags and are never stored).  The block
 // table maps the block to its scene and first wavefront.
 template <class T>
-__device__ __forceinline__ const Dev<T>* lane_setup(const Dev<T>* D, const Blk* tab, Lane2<T>& P, int& pA, int& pB) {
-  const Blk b = tab[blockIdx.x];
+__device__ __forceinline__ const Dev<T>* lane_setup_wave(const Dev<T>* D, const Blk b, int wave, Lane2<T>& P, int& pA,
+                                                         int& pB) {
   const Dev<T>* d = D + b.scene;
-  const int wave = b.base + (int)(threadIdx.x >> 6);
   const int lane = (int)(threadIdx.x & 63);
   if (wave >= d->W) return nullptr;
   const int p0 = d->wave_start[wave];
@@ -544,6 +543,13 @@ __device__ __forceinline__ const Dev<T>* lane_setup(const Dev<T>* D, const Blk* 
   P.sb = __any(((P.A.f | P.B.f) & F_SB) != 0u) != 0;
   P.vb = __any(((P.A.f | P.B.f) & F_VB) != 0u) != 0;
   return d;
+}
+
+// Blocks of four wavefronts: wavefront w of the block is tab[block].base + w.
+template <class T>
+__device__ __forceinline__ const Dev<T>* lane_setup(const Dev<T>* D, const Blk* tab, Lane2<T>& P, int& pA, int& pB) {
+  const Blk b = tab[blockIdx.x];
+  return lane_setup_wave(D, b, b.base + (int)(threadIdx.x >> 6), P, pA, pB);
 }
 
 template <class T>

@@ -1101,7 +1101,7 @@ void adjoint_bytes(viper_scene S, int32_t frames, int32_t substeps, int32_t iter
   const size_t ts = S->precision == VIPER_F64 ? 8 : 4;
   const size_t P = (size_t)S->P, NL = (size_t)S->W * 64;
   *ckpt = (size_t)frames * substeps * kCkptFields * P * ts;
-  *snap = align256((size_t)iterations * 4 * 32 * NL * ts);
+  *snap = align256((size_t)iterations * kSnapPerIter * NL * ts);
   *adj = align256((size_t)kCkptFields * P * ts);
   *padj = align256(8 * P * ts);
 }

@@ -195,6 +195,10 @@ template <class T> hipError_t launch_gather_field(const Dev<T>& d, int which, T*
 template <class T> hipError_t launch_scatter_field(const Dev<T>& d, int which, const T* in, hipStream_t st);
 // Adjoint of the collision-free frame (single scene): checkpoint layout [substep][15][P].
 constexpr int kCkptFields = 15;
+// Backward scratch: per iteration, the pre-pass snapshots of the two edge passes (26 values
+// per lane) and of the two bend-twist passes (16 values per lane).
+constexpr int kSnapEdge = 26, kSnapBt = 16;
+constexpr int kSnapPerIter = 2 * kSnapEdge + 2 * kSnapBt;
 template <class T> hipError_t launch_frame_ckpt(const BatchDev& b, int nsub, double h, int iters, T* ckpt, hipStream_t st);
 template <class T> hipError_t launch_backward(const BatchDev& b, int P, int nsub, double h, int iters, const T* ckpt,
                                               const T* dldx, T* snap, T* adj, T* padj, double rho, double* drbar,
