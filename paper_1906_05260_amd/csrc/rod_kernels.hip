@@ -57,6 +57,14 @@ __global__ void __launch_bounds__(256) rod_frame_kernel(const Dev<T>* __restrict
   check_finite(d, P.B);
 }
 
+// The per-stage kernels run one wavefront per block (block b: wavefront tab[b / 4].base +
+// b % 4), so that a scene of a few hundred wavefronts spreads over every compute unit.
+template <class T>
+__device__ __forceinline__ const Dev<T>* lane_setup1(const Dev<T>* D, const Blk* tab, Lane2<T>& P, int& pA, int& pB) {
+  const Blk b = tab[blockIdx.x >> 2];
+  return lane_setup_wave(D, b, b.base + (int)(blockIdx.x & 3), P, pA, pB);
+}
+
 // ITERATION mode, stage 1: prediction of every pill and edge, saving the substep-start
 // state and resetting the multipliers.
 template <class T>
@@ -75,7 +83,7 @@ template <class T>
 __global__ void __launch_bounds__(256) predict_kernel(const Dev<T>* __restrict__ D, const Blk* __restrict__ tab, T h) {
   Lane2<T> P;
   int pA, pB;
-  const Dev<T>* dp = lane_setup(D, tab, P, pA, pB);
+  const Dev<T>* dp = lane_setup1(D, tab, P, pA, pB);
   if (!dp) return;
   const Dev<T>& d = *dp;
   load_state(d, P.A, pA);
@@ -210,7 +218,7 @@ __global__ void __launch_bounds__(256) rod_iteration_kernel(const Dev<T>* __rest
                                                             T h, const ContactDev* __restrict__ CD) {
   Lane2<T> P;
   int pA, pB;
-  const Dev<T>* dp = lane_setup(D, tab, P, pA, pB);
+  const Dev<T>* dp = lane_setup1(D, tab, P, pA, pB);
   if (!dp) return;
   const Dev<T>& d = *dp;
   load_iter<T, X>(d, P.A, pA);
@@ -255,7 +263,7 @@ __global__ void __launch_bounds__(256) velocity_kernel(const Dev<T>* __restrict_
                                                        const ContactDev* __restrict__ CD) {
   Lane2<T> P;
   int pA, pB;
-  const Dev<T>* dp = lane_setup(D, tab, P, pA, pB);
+  const Dev<T>* dp = lane_setup1(D, tab, P, pA, pB);
   if (!dp) return;
   const Dev<T>& d = *dp;
   const T ih = T(1) / h;
@@ -401,13 +409,13 @@ template <class T> hipError_t launch_rod_frame(const BatchDev& b, int nsub, doub
 }
 template <class T> hipError_t launch_predict(const BatchDev& b, double h, hipStream_t st) {
   if (b.nblk[TB_WAVES] == 0) return hipSuccess;
-  hipLaunchKernelGGL(predict_kernel<T>, dim3(b.nblk[TB_WAVES]), dim3(256), 0, st, (const Dev<T>*)b.dev,
+  hipLaunchKernelGGL(predict_kernel<T>, dim3(4 * b.nblk[TB_WAVES]), dim3(64), 0, st, (const Dev<T>*)b.dev,
                      b.tab[TB_WAVES], (T)h);
   return hipGetLastError();
 }
 template <class T, bool X, bool EVEN>
 void launch_rod_iteration_as(const BatchDev& b, double h, const ContactDev* cd, hipStream_t st) {
-  hipLaunchKernelGGL((rod_iteration_kernel<T, X, EVEN>), dim3(b.nblk[TB_WAVES]), dim3(256), 0, st, (const Dev<T>*)b.dev,
+  hipLaunchKernelGGL((rod_iteration_kernel<T, X, EVEN>), dim3(4 * b.nblk[TB_WAVES]), dim3(64), 0, st, (const Dev<T>*)b.dev,
                      b.tab[TB_WAVES], (T)h, cd);
 }
 template <class T> hipError_t launch_rod_iteration(const BatchDev& b, double h, const ContactDev* cd, hipStream_t st) {
@@ -423,7 +431,7 @@ template <class T> hipError_t launch_rod_iteration(const BatchDev& b, double h, 
 }
 template <class T> hipError_t launch_velocity(const BatchDev& b, double h, const ContactDev* cd, hipStream_t st) {
   if (b.nblk[TB_WAVES] == 0) return hipSuccess;
-  hipLaunchKernelGGL(velocity_kernel<T>, dim3(b.nblk[TB_WAVES]), dim3(256), 0, st, (const Dev<T>*)b.dev,
+  hipLaunchKernelGGL(velocity_kernel<T>, dim3(4 * b.nblk[TB_WAVES]), dim3(64), 0, st, (const Dev<T>*)b.dev,
                      b.tab[TB_WAVES], (T)h, cd);
   return hipGetLastError();
 }
