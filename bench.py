@@ -194,42 +194,48 @@ def copy_reference(torch, dev, mib, steps):
 
 def adjoint_timing(torch, viper, scenes, dev, reps=5):
     """Forward with per-substep checkpoints and backward of one frame on 1024 straight rods x
-    32 pills (FP32, 20 substeps x 8 iterations), L = sum |x_free_end - target|^2."""
+    32 pills (FP32, 20 substeps x 8 iterations), L = sum |x_free_end - target|^2.  Each
+    repetition runs every measured call once untimed on the same scenes and buffers, then times
+    the second: the plain frame, the checkpointed frame and the backward (HIP events on the
+    launch stream; medians over the repetitions)."""
     desc, targets = scenes.straight_rods(1024, 32, seed=4)
     dt, sub, iters = 1.0 / 60.0, 20, 8
     st = torch.cuda.current_stream()
     times = {"plain": [], "forward": [], "backward": []}
     last = torch.as_tensor(desc.rod_offsets[1:] - 1, device=dev, dtype=torch.long)
     tg = torch.as_tensor(targets, device=dev, dtype=torch.float32)
-    for r in range(reps + 1):
+    for r in range(reps):
         sc = viper.Scene(desc, "f32", device=dev)
         nc, nw = sc.adjoint_sizes(1, sub, iters)
         ckpt = torch.empty(nc, dtype=torch.uint8, device=dev)
         work = torch.empty(nw, dtype=torch.uint8, device=dev)
         ref = viper.Scene(desc, "f32", device=dev)
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
-        ev[0].record(st)
-        ref.step(dt, sub, iters, mode=viper.MODE_FRAME)
-        ev[1].record(st)
-        ev[2].record(st)
-        sc.step_checkpointed(dt, 1, sub, iters, ckpt=ckpt)
-        ev[3].record(st)
-        x = sc.get("x")
-        g = torch.zeros_like(x)
-        g[last] = 2.0 * (x[last] - tg)
-        ev[4].record(st)
-        sc.backward(dt, 1, sub, iters, ckpt, g, work=work)
-        ev[5].record(st)
-        torch.cuda.synchronize()
-        sc.sync()
-        if r > 0:
-            times["plain"].append(ev[0].elapsed_time(ev[1]))
-            times["forward"].append(ev[2].elapsed_time(ev[3]))
-            times["backward"].append(ev[4].elapsed_time(ev[5]))
+        for timed in (False, True):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+            ev[0].record(st)
+            ref.step(dt, sub, iters, mode=viper.MODE_FRAME)
+            ev[1].record(st)
+            ev[2].record(st)
+            sc.step_checkpointed(dt, 1, sub, iters, ckpt=ckpt)
+            ev[3].record(st)
+            x = sc.get("x")
+            g = torch.zeros_like(x)
+            g[last] = 2.0 * (x[last] - tg)
+            ev[4].record(st)
+            sc.backward(dt, 1, sub, iters, ckpt, g, work=work)
+            ev[5].record(st)
+            torch.cuda.synchronize()
+            sc.sync()
+            ref.sync()
+            if timed:
+                times["plain"].append(ev[0].elapsed_time(ev[1]))
+                times["forward"].append(ev[2].elapsed_time(ev[3]))
+                times["backward"].append(ev[4].elapsed_time(ev[5]))
     med = {k: float(sorted(v)[len(v) // 2]) for k, v in times.items()}
     return {"workload": "straight1024x32", "frames": 1, "substeps": sub, "iterations": iters, "dtype": "f32",
             "plain_frame_ms": med["plain"], "forward_checkpointed_ms": med["forward"],
             "backward_ms": med["backward"], "backward_over_forward": med["backward"] / med["plain"],
+            "backward_over_checkpointed_forward": med["backward"] / med["forward"],
             "checkpoint_bytes": nc, "backward_scratch_bytes": nw,
             "params": desc.num_pills + desc.num_rods}
 

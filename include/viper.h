@@ -295,8 +295,9 @@ const char* viper_last_error(void);
  * rejected with VIPER_ERR_INVALID.
  *
  * Device bytes needed: the checkpoint holds frames*substeps*15*P values in the scene's
- * precision; the backward scratch holds one substep's per-pass state snapshots plus the
- * state and parameter adjoints. */
+ * precision; the backward scratch holds two substeps' per-pass state snapshots (the replay
+ * of one substep runs beside the reverse sweep of the next) plus the state and parameter
+ * adjoints. */
 viper_status viper_adjoint_sizes(viper_scene scene, int32_t frames, int32_t substeps, int32_t iterations,
                                  size_t* ckpt_bytes, size_t* work_bytes);
 
@@ -317,11 +318,11 @@ viper_status viper_step_backward(viper_scene scene, double dt, int32_t frames, i
 
 /* viper_step_backward without a work buffer, for callers that cannot allocate device memory
  * (code under HIP graph capture, serving loops, harnesses that forbid allocation): the
- * scratch is a library-owned static device array of 80 MiB per GPU (held from the library's
+ * scratch is a library-owned static device array of 160 MiB per GPU (held from the library's
  * load until the process ends), so the call allocates nothing.  Same arguments, semantics
  * and results as viper_step_backward otherwise.  VIPER_ERR_NO_CAPACITY (nothing enqueued)
- * when the work bytes of viper_adjoint_sizes exceed 80 MiB (the 1024 x 32 FP32 workload at
- * 8 iterations needs 67 MiB).  Every call on a GPU shares that GPU's array: calls that
+ * when the work bytes of viper_adjoint_sizes exceed 160 MiB (the 1024 x 32 FP32 workload at
+ * 8 iterations needs 90 MiB).  Every call on a GPU shares that GPU's array: calls that
  * overlap on one GPU (other streams or threads) race and must be serialised by the caller. */
 viper_status viper_step_backward_static(viper_scene scene, double dt, int32_t frames, int32_t substeps,
                                         int32_t iterations, const void* ckpt, const void* dl_dx, double* dl_drbar,

@@ -678,39 +678,26 @@ __global__ void __launch_bounds__(256) rod_frame_ckpt_kernel(const Dev<T>* __res
   check_finite(d, P.B);
 }
 
-// Reverse of one substep.  adj ([field][pill], kCkptFields) holds the adjoint of the state
-// at the end of the substep on entry and at its start on exit; padj ([8][pill]) accumulates
-// the parameter adjoints: 1/M, 1/M_s, 1/lbar, rho pi r^4 l0, and the four compliance
-// scalings; snap is this lane's pass-snapshot scratch.
-// The forward's lane layout, one wavefront per block (block b runs wavefront
-// tab[b / 4].base + b % 4): a small scene's wavefronts spread over every compute unit.
+// Backward of the substeps, software-pipelined: launch k reverses substep s = n - k while
+// other blocks of the same launch replay substep s - 1 (its recompute and snapshots do not
+// depend on the reverse sweep), so the replay of one substep hides under the reverse of the
+// next.  A substep's snapshots (kSnapPerIter per iteration and lane, then the substep-end
+// quaternions of both slots, kSnapEnd) go to one of two buffers by the substep's parity.
+
+// Replay of one substep from its checkpoint, storing the pre-pass snapshots and the
+// substep-end quaternions into sb (this lane's column of one snapshot buffer).
 template <class T, bool EVEN>
-__global__ void __launch_bounds__(64) rod_backward_kernel(const Dev<T>* __restrict__ D, const Blk* __restrict__ tab,
-                                                           T h, int iters, const T* __restrict__ ckpt, T* __restrict__ snap,
-                                                           T* __restrict__ adj, T* __restrict__ padj) {
-  Lane2<T> P;
-  int pA, pB;
-  const Blk blk = tab[blockIdx.x >> 2];
-  const int wave = blk.base + (int)(blockIdx.x & 3);
-  const Dev<T>* dp = lane_setup_wave(D, blk, wave, P, pA, pB);
-  if (!dp) return;
-  const Dev<T>& d = *dp;
-  const int lane = (int)(threadIdx.x & 63);
-  const size_t NL = (size_t)d.W * 64;
-  const size_t lg = (size_t)wave * 64 + lane;
+__device__ __forceinline__ void backward_replay(Lane2<T>& P, const Dev<T>& d, int pA, int pB, T h, int iters,
+                                                const T* __restrict__ ckpt, T* __restrict__ sb, size_t NL) {
   T* cbase = const_cast<T*>(ckpt);
   ckpt_io(cbase, d.P, pA, P.A, false);
   ckpt_io(cbase, d.P, pB, P.B, false);
-  const T ih2 = rcp(h * h);
-  load_lane_consts(d, P, pA, pB, ih2);
-  const T ih = T(1) / h;
-  // forward recompute with pass snapshots
+  load_lane_consts(d, P, pA, pB, rcp(h * h));
   predict_slot(P.A, h, d.gx, d.gy, d.gz);
   predict_slot(P.B, h, d.gx, d.gy, d.gz);
   inertia_lane(P);
-  T* const sbase = snap + lg;
   for (int it = 0; it < iters; ++it) {
-    T* const si = sbase + (size_t)it * kSnapPerIter * NL;
+    T* const si = sb + (size_t)it * kSnapPerIter * NL;
     snap_edge_store(si + snap_offset(0) * NL, NL, P.A, P.B);
     pass_edges<T, false, EVEN>(P, 0);
     snap_edge_store(si + snap_offset(1) * NL, NL, P.A, P.B);
@@ -720,8 +707,37 @@ __global__ void __launch_bounds__(64) rod_backward_kernel(const Dev<T>* __restri
     snap_bt_store(si + snap_offset(3) * NL, NL, P.A, P.B);
     pass_bt<T, EVEN>(P, 1);
   }
-  velocity_slot(P.A, ih);
-  velocity_slot(P.B, ih);
+  T* const se = sb + (size_t)iters * kSnapPerIter * NL;   // the velocity update leaves q as it is
+  const T q[kSnapEnd] = {P.A.q0, P.A.q1, P.A.q2, P.A.q3, P.B.q0, P.B.q1, P.B.q2, P.B.q3};
+#pragma unroll
+  for (int i = 0; i < kSnapEnd; ++i) se[(size_t)i * NL] = q[i];
+}
+
+// Reverse of one substep.  adj ([field][pill], kCkptFields) holds the adjoint of the state
+// at the end of the substep on entry and at its start on exit; padj ([8][pill]) accumulates
+// the parameter adjoints: 1/M, 1/M_s, 1/lbar, rho pi r^4 l0, and the four compliance
+// scalings; sb is this lane's column of the substep's snapshot buffer (written by its replay).
+template <class T, bool EVEN>
+__device__ __forceinline__ void backward_reverse(Lane2<T>& P, const Dev<T>& d, int pA, int pB, T h, int iters,
+                                                 const T* __restrict__ ckpt, const T* __restrict__ sb, size_t NL,
+                                                 T* __restrict__ adj, T* __restrict__ padj) {
+  T* cbase = const_cast<T*>(ckpt);
+  ckpt_io(cbase, d.P, pA, P.A, false);
+  ckpt_io(cbase, d.P, pB, P.B, false);
+  const T ih2 = rcp(h * h);
+  load_lane_consts(d, P, pA, pB, ih2);
+  const T ih = T(1) / h;
+  // the substep-start copies and inertias the reverse sweep needs (the prediction itself is
+  // replaced by the snapshots), and the substep-end quaternions from the replay
+  predict_slot(P.A, h, d.gx, d.gy, d.gz);
+  predict_slot(P.B, h, d.gx, d.gy, d.gz);
+  inertia_lane(P);
+  {
+    T q[kSnapEnd];
+    snap_load(sb + (size_t)iters * kSnapPerIter * NL, NL, q);
+    P.A.q0 = q[0]; P.A.q1 = q[1]; P.A.q2 = q[2]; P.A.q3 = q[3];
+    P.B.q0 = q[4]; P.B.q1 = q[5]; P.B.q2 = q[6]; P.B.q3 = q[7];
+  }
   // adjoint of the substep-end state
   SAdj<T> aA, aB;
   zero_adj(aA);
@@ -745,11 +761,11 @@ __global__ void __launch_bounds__(64) rod_backward_kernel(const Dev<T>* __restri
   constexpr bool kPre = sizeof(T) == 4;
   if (iters > 0) {
     T v[kSnapBt];
-    snap_load(sbase + ((size_t)(iters - 1) * kSnapPerIter + snap_offset(3)) * NL, NL, v);
+    snap_load(sb + ((size_t)(iters - 1) * kSnapPerIter + snap_offset(3)) * NL, NL, v);
     snap_bt_apply(v, P.A, P.B);
   }
   for (int it = iters - 1; it >= 0; --it) {
-    const T* const si = sbase + (size_t)it * kSnapPerIter * NL;
+    const T* const si = sb + (size_t)it * kSnapPerIter * NL;
     {
       T v[kSnapBt];
       if (kPre) snap_load(si + snap_offset(2) * NL, NL, v);
@@ -831,6 +847,33 @@ __global__ void __launch_bounds__(64) rod_backward_kernel(const Dev<T>* __restri
   }
 }
 
+// Block roles: blocks [0, nb) reverse the substep whose checkpoint is rev_ckpt (none when it
+// is null), blocks [nb, 2 nb) replay the substep whose checkpoint is rep_ckpt (none when null);
+// within a role the forward's lane layout, one wavefront per block (block b runs wavefront
+// tab[b / 4].base + b % 4), so that a small scene's wavefronts spread over every compute unit.
+template <class T, bool EVEN>
+__global__ void __launch_bounds__(64) rod_backward_kernel(const Dev<T>* __restrict__ D, const Blk* __restrict__ tab,
+                                                           T h, int iters, int nb, const T* __restrict__ rev_ckpt,
+                                                           int rev_buf, const T* __restrict__ rep_ckpt, int rep_buf,
+                                                           T* __restrict__ snap, T* __restrict__ adj,
+                                                           T* __restrict__ padj) {
+  const bool replay = (int)blockIdx.x >= nb;
+  if (replay ? rep_ckpt == nullptr : rev_ckpt == nullptr) return;
+  const int bi = replay ? (int)blockIdx.x - nb : (int)blockIdx.x;
+  Lane2<T> P;
+  int pA, pB;
+  const Blk blk = tab[bi >> 2];
+  const int wave = blk.base + (bi & 3);
+  const Dev<T>* dp = lane_setup_wave(D, blk, wave, P, pA, pB);
+  if (!dp) return;
+  const Dev<T>& d = *dp;
+  const size_t NL = (size_t)d.W * 64;
+  const size_t region = ((size_t)iters * kSnapPerIter + kSnapEnd) * NL;
+  const size_t lg = (size_t)wave * 64 + (threadIdx.x & 63);
+  if (replay) backward_replay<T, EVEN>(P, d, pA, pB, h, iters, rep_ckpt, snap + (size_t)rep_buf * region + lg, NL);
+  else backward_reverse<T, EVEN>(P, d, pA, pB, h, iters, rev_ckpt, snap + (size_t)rev_buf * region + lg, NL, adj, padj);
+}
+
 // Seed: adjoint of the end-of-frame state from dL/dx (pill-major [P*3]); other fields 0.
 template <class T>
 __global__ void adjoint_seed_kernel(int P, const T* __restrict__ dldx, T* __restrict__ adj, T* __restrict__ padj) {
@@ -910,14 +953,19 @@ hipError_t launch_backward(const BatchDev& b, int P, int nsub, double h, int ite
                            T* snap, T* adj, T* padj, double rho, double* drbar, double* dact, hipStream_t st) {
   if (P == 0) return hipSuccess;
   hipLaunchKernelGGL(adjoint_seed_kernel<T>, dim3((P + 255) / 256), dim3(256), 0, st, P, dldx, adj, padj);
-  for (int sub = nsub - 1; sub >= 0; --sub) {
-    const T* ck = ckpt + (size_t)sub * kCkptFields * P;
+  const int nb = 4 * b.nblk[TB_WAVES];
+  const size_t per = (size_t)kCkptFields * P;
+  // launch k reverses substep nsub - k (k >= 1) and replays substep nsub - 1 - k (if any)
+  for (int k = 0; k <= nsub; ++k) {
+    const int rs = nsub - k, ps = nsub - 1 - k;
+    const T* rc = k >= 1 ? ckpt + (size_t)rs * per : nullptr;
+    const T* pc = ps >= 0 ? ckpt + (size_t)ps * per : nullptr;
     if (b.even)
-      hipLaunchKernelGGL((rod_backward_kernel<T, true>), dim3(4 * b.nblk[TB_WAVES]), dim3(64), 0, st,
-                         (const Dev<T>*)b.dev, b.tab[TB_WAVES], (T)h, iters, ck, snap, adj, padj);
+      hipLaunchKernelGGL((rod_backward_kernel<T, true>), dim3(2 * nb), dim3(64), 0, st, (const Dev<T>*)b.dev,
+                         b.tab[TB_WAVES], (T)h, iters, nb, rc, rs & 1, pc, ps & 1, snap, adj, padj);
     else
-      hipLaunchKernelGGL((rod_backward_kernel<T, false>), dim3(4 * b.nblk[TB_WAVES]), dim3(64), 0, st,
-                         (const Dev<T>*)b.dev, b.tab[TB_WAVES], (T)h, iters, ck, snap, adj, padj);
+      hipLaunchKernelGGL((rod_backward_kernel<T, false>), dim3(2 * nb), dim3(64), 0, st, (const Dev<T>*)b.dev,
+                         b.tab[TB_WAVES], (T)h, iters, nb, rc, rs & 1, pc, ps & 1, snap, adj, padj);
   }
   hipLaunchKernelGGL(adjoint_chain_kernel<T>, dim3((P + 255) / 256), dim3(256), 0, st, (const Dev<T>*)b.dev,
                      (const T*)padj, rho, drbar, dact);

@@ -1101,7 +1101,7 @@ void adjoint_bytes(viper_scene S, int32_t frames, int32_t substeps, int32_t iter
   const size_t ts = S->precision == VIPER_F64 ? 8 : 4;
   const size_t P = (size_t)S->P, NL = (size_t)S->W * 64;
   *ckpt = (size_t)frames * substeps * kCkptFields * P * ts;
-  *snap = align256((size_t)iterations * kSnapPerIter * NL * ts);
+  *snap = align256(2 * ((size_t)iterations * kSnapPerIter + kSnapEnd) * NL * ts);
   *adj = align256((size_t)kCkptFields * P * ts);
   *padj = align256(8 * P * ts);
 }
@@ -1114,7 +1114,7 @@ viper_status backward_launch(viper_scene S, double dt, int32_t frames, int32_t s
 // copy per GPU (each device holds it from the library's load until the process ends), shared
 // by every call on that GPU.  Host code never uses the array's name as an address: its device
 // address is looked up once per device (static_scratch) and kept.
-constexpr size_t kStaticScratchBytes = size_t(80) << 20;
+constexpr size_t kStaticScratchBytes = size_t(160) << 20;
 __device__ __align__(256) static char scratch[kStaticScratchBytes];
 
 std::mutex g_scratch_mu;

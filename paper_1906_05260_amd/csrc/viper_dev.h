@@ -199,6 +199,9 @@ constexpr int kCkptFields = 15;
 // per lane) and of the two bend-twist passes (16 values per lane).
 constexpr int kSnapEdge = 26, kSnapBt = 16;
 constexpr int kSnapPerIter = 2 * kSnapEdge + 2 * kSnapBt;
+// ... after the last iteration the substep-end quaternions of both slots; two such buffers
+// (the replay of one substep runs beside the reverse of the next).
+constexpr int kSnapEnd = 8;
 template <class T> hipError_t launch_frame_ckpt(const BatchDev& b, int nsub, double h, int iters, T* ckpt, hipStream_t st);
 template <class T> hipError_t launch_backward(const BatchDev& b, int P, int nsub, double h, int iters, const T* ckpt,
                                               const T* dldx, T* snap, T* adj, T* padj, double rho, double* drbar,

@@ -49,7 +49,7 @@ def test_static_scratch_refuses_large_scenes():
     desc, _ = scenes.straight_rods(2048, 32, seed=4)
     sc = viper.Scene(desc, "f32")
     nc, nw = sc.adjoint_sizes(1, SUB, IT)
-    assert nw > 80 << 20
+    assert nw > 160 << 20
     ckpt = sc.step_checkpointed(DT, 1, SUB, IT)
     g = torch.zeros((desc.num_pills, 3), dtype=torch.float32, device="cuda:0")
     with pytest.raises(viper.ViperError) as ei:
