@@ -56,7 +56,7 @@ typedef enum { VIPER_F32 = 0, VIPER_F64 = 1 } viper_precision;
  * collision groups (intra-muscle collisions disabled, Sec. 8). */
 typedef struct {
   int32_t num_rods;
-  const int32_t* rod_offsets;   /* [num_rods+1], increasing, 2 <= pills per rod <= 64 */
+  const int32_t* rod_offsets;   /* [num_rods+1], increasing, 2 <= pills per rod <= 128 */
   const double* rest_pos;       /* [P*3] rest vertex positions, m; consecutive pills distinct */
   const double* rest_radius;    /* [P] rest radius r, m, > 0 */
   const uint8_t* pinned;        /* [P] nonzero = position fixed (scale, rotation stay free); may be NULL */

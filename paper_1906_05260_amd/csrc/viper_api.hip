@@ -40,7 +40,7 @@ viper_status fail(viper_status s, const std::string& msg) {
   } while (0)
 
 const double kPi = 3.14159265358979323846;
-const int kMaxPills = 64;     // pills per rod
+const int kMaxPills = 128;    // pills per rod: a rod lives in one wavefront (two slots per lane)
 const int kWaveSpan = 128;    // pill slots per wavefront (two per lane)
 
 // ----------------------------------------------------------------------------- layout
@@ -138,7 +138,7 @@ viper_status validate(const viper_scene_desc* d) {
     int n = d->rod_offsets[k + 1] - d->rod_offsets[k];
     if (n < 2 || n > kMaxPills)
       return fail(VIPER_ERR_INVALID, "rod " + std::to_string(k) + " has " + std::to_string(n) +
-                                         " pills; each rod needs 2..64 pills");
+                                         " pills; each rod needs 2..128 pills");
     if (d->activation && !finite_pos(d->activation[k])) return fail(VIPER_ERR_INVALID, "activation must be > 0");
     for (int t = 0; t < 4; ++t) {
       double c = d->compliance[4 * k + t];

@@ -33,7 +33,7 @@ enum { ST_NAN = 0, ST_OVERFLOW = 1, ST_DIVERGED = 2, ST_WORDS = 4 };
 template <class T>
 struct Dev {
   int P;                     // pills
-  int W;                     // waves (each holds whole rods, <= 64 pills)
+  int W;                     // waves (each holds whole rods, <= 128 pills)
   const int32_t* wave_start; // [W+1] first pill of each wave
   const uint32_t* flags;     // [P]
   // state

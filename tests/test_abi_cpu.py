@@ -56,15 +56,16 @@ def test_invalid_descriptions_rejected(mutate, msg):
 
 
 def test_rod_length_limits():
-    ok = scenes.straight_rod(64)
-    viper.footprint(ok)
-    for n in (1, 65):
+    """A rod lives in one wavefront: 2..128 pills (two slots per lane)."""
+    for n in (2, 64, 65, 128):
+        viper.footprint(scenes.straight_rod(n))
+    for n in (1, 129):
         d = scenes.straight_rod(max(n, 2))
         if n == 1:
             d.rod_offsets = np.asarray([0, 1], np.int32)
             d.rest_pos = d.rest_pos[:1]
         else:
-            d = scenes.straight_rod(65)
+            d = scenes.straight_rod(129)
         with pytest.raises(viper.ViperError) as ei:
             viper.footprint(d)
         assert ei.value.status == viper.ERR_INVALID

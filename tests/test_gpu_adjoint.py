@@ -250,6 +250,15 @@ def test_ragged_multi_frame_fp64(frames):
     compare("ragged f64 frames=%d dact" % frames, dac, odac, 1e-7)
 
 
+def test_long_rods_fp64():
+    """Rods of 128 pills (each fills a whole wavefront): FP64 gradient vs the oracle's."""
+    desc, targets = scenes.straight_rods(6, 128, seed=9)
+    _, drb, dac = gpu_grad(desc, targets, "f64")
+    _, odrb, odac, _ = oracle_grads(desc, targets)
+    compare("long rods f64 drbar", drb, odrb, 1e-7)
+    compare("long rods f64 dact", dac, odac, 1e-7)
+
+
 def test_ragged_fp32():
     desc, targets = ragged_scene()
     _, drb, dac = gpu_grad(desc, targets, "f32")

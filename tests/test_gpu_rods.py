@@ -140,6 +140,47 @@ def test_even_and_general_wave_layouts_agree():
             assert max(e) < 1e-9
 
 
+def test_rods_up_to_a_whole_wavefront():
+    """Rods of 65..128 pills (one rod may fill a wavefront's 64 lanes x 2 slots), alone and
+    beside shorter ones, all four constraint types: FP64 three frames at 1e-9, FP32 one frame
+    within 1e-4 or, where the FP32 oracle's own distance from FP64 (its rounding floor) is
+    above 1e-5, within 20x that floor, in the frame kernel and in the split ITERATION launches."""
+    rng = np.random.default_rng(31)
+    lens = [128, 100, 65, 127, 2, 128, 33, 64, 90]
+    base = scenes.helix_rods(len(lens), 128, seed=31)
+    offs = [0]
+    pos, rad, pin = [], [], []
+    for k, n in enumerate(lens):
+        a = base.rod_offsets[k]
+        pos.append(base.rest_pos[a:a + n]); rad.append(base.rest_radius[a:a + n])
+        p = np.zeros(n, np.uint8); p[0] = 1
+        pin.append(p)
+        offs.append(offs[-1] + n)
+    desc = scenes.SceneDesc(np.asarray(offs, np.int32), np.concatenate(pos), np.concatenate(rad),
+                            np.concatenate(pin), rng.uniform(0.9, 1.1, len(lens)),
+                            base.compliance[:len(lens)].copy(), np.arange(len(lens), dtype=np.int32))
+    for prec, tol, frames in (("f64", 1e-9, 3), ("f32", TOL, 1)):
+        for mode in (viper.MODE_FRAME, viper.MODE_ITERATION):
+            say("case: long rods", prec, "mode", mode)
+            sc = viper.Scene(desc, prec)
+            o = oracle.OracleScene(desc, "f64")
+            for _ in range(frames):
+                sc.step(1 / 60, 20, 8, mode=mode)
+                o.step(1 / 60, 20, 8)
+            sc.sync()
+            e = errors(desc, sc.state(), o.get_state())
+            bound = tol
+            if prec == "f32":
+                o32 = oracle.OracleScene(desc, "f32")
+                for _ in range(frames):
+                    o32.step(1 / 60, 20, 8)
+                floor = max(errors(desc, o32.get_state(), o.get_state()))
+                bound = tol if floor < 1e-5 else 20 * floor + tol
+                say("FP32 oracle floor", floor)
+            say(prec, mode, "errors", e, "bound", bound)
+            assert max(e) < bound
+
+
 def local_subset(desc, rods):
     """The given rods, each translated so that its first pill sits at the origin (the GPU
     stores positions relative to that anchor; the physics is translation invariant)."""
