@@ -629,62 +629,83 @@ __device__ double gap_at(const D3* c, const double* r, double al) {
   return sqrt(dotp(dv, dv)) - ra - (r[2] + be * (r[3] - r[2]));
 }
 
+// Exchange of a double between the two lanes of a lane pair (2k, 2k + 1).
+__device__ __forceinline__ double pair_swap(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0xB1, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// One candidate pair per lane pair: the two gap evaluations of each step of the dichotomous
+// search run on the two lanes (the lower at m - delta, the upper at m + delta) and are
+// exchanged, so both lanes take the same decision; both then form the projection, and the
+// lower lane accumulates the corrections of the first capsule's pills, the upper lane those
+// of the second's.  A scene's blocks cover pair_span(cap) pairs per round.
 template <class T>
 __global__ void __launch_bounds__(256) contact_pair_kernel(const Dev<T>* __restrict__ D, const ContactDev* __restrict__ CD,
                                                            const Blk* __restrict__ tab) {
   BLOCK_SCENE(tab, D, CD)
-  const int i = blk_.base + (int)threadIdx.x;
-  if (i >= c.npairs[0]) return;
-  const int a = c.pairs[2 * (size_t)i], b = c.pairs[2 * (size_t)i + 1];
-  const int pid[4] = {a, a + 1, b, b + 1};
-  D3 cp[4];
-  double r[4], rb[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int p = pid[t];
-    double w[3];
-    world_pos(d, p, w);
-    cp[t] = d3(w[0], w[1], w[2]);
-    rb[t] = (double)d.rbar[p];
-    r[t] = (double)d.s[p] * rb[t];
-  }
-  // dichotomous search over the first capsule's parameter (fixed iteration count)
-  double lo = 0.0, hi = 1.0;
-  for (int k = 0; k < c.search_iters; ++k) {
-    const double m = 0.5 * (lo + hi);
-    const double x1 = m - c.delta, x2 = m + c.delta;
-    if (gap_at(cp, r, x1) < gap_at(cp, r, x2)) hi = x2; else lo = x1;
-  }
-  const double al = 0.5 * (lo + hi);
-  const D3 ca = lerp(cp[0], cp[1], al);
-  const double be = pill_param(ca, cp[2], r[2], cp[3], r[3]);
-  const D3 cb = lerp(cp[2], cp[3], be);
-  const D3 dv = sub(ca, cb);
-  const double dist = sqrt(dotp(dv, dv));
-  const double C = dist - (r[0] + al * (r[1] - r[0])) - (r[2] + be * (r[3] - r[2]));
-  if (C < 0.0 && dist > 0.0) {
-    const D3 n = d3(dv.x / dist, dv.y / dist, dv.z / dist);
-    const double wt[4] = {1.0 - al, al, -(1.0 - be), -be};   // dC/dx_t = wt n, dC/ds_t = -|wt| rbar
-    double den = 0.0;
-    double w[4], ws[4];
+  const int lane2 = blk_.base + (int)threadIdx.x;
+  const bool upper = (lane2 & 1) != 0;
+  const int span = pair_span(c.cap);
+  const int np = c.npairs[0];
+  for (int i = lane2 >> 1; i < np; i += span) {   // the same trip count on both lanes of a pair
+    const int a = c.pairs[2 * (size_t)i], b = c.pairs[2 * (size_t)i + 1];
+    const int pid[4] = {a, a + 1, b, b + 1};
+    D3 cp[4];
+    double r[4], rb[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      w[t] = (double)d.winv[pid[t]];
-      ws[t] = (double)d.wsinv[pid[t]];
-      const double gs = fabs(wt[t]) * rb[t];
-      den += w[t] * wt[t] * wt[t] + ws[t] * gs * gs;
+      const int p = pid[t];
+      double w[3];
+      world_pos(d, p, w);
+      cp[t] = d3(w[0], w[1], w[2]);
+      rb[t] = (double)d.rbar[p];
+      r[t] = (double)d.s[p] * rb[t];
     }
-    if (den > 0.0) {
-      const double dl = -C / den;
+    // dichotomous search over the first capsule's parameter (fixed iteration count)
+    double lo = 0.0, hi = 1.0;
+    for (int k = 0; k < c.search_iters; ++k) {
+      const double m = 0.5 * (lo + hi);
+      const double x1 = m - c.delta, x2 = m + c.delta;
+      const double g = gap_at(cp, r, upper ? x2 : x1);
+      const double go = pair_swap(g);
+      const double g1 = upper ? go : g, g2 = upper ? g : go;
+      if (g1 < g2) hi = x2; else lo = x1;
+    }
+    const double al = 0.5 * (lo + hi);
+    const D3 ca = lerp(cp[0], cp[1], al);
+    const double be = pill_param(ca, cp[2], r[2], cp[3], r[3]);
+    const D3 cb = lerp(cp[2], cp[3], be);
+    const D3 dv = sub(ca, cb);
+    const double dist = sqrt(dotp(dv, dv));
+    const double C = dist - (r[0] + al * (r[1] - r[0])) - (r[2] + be * (r[3] - r[2]));
+    if (C < 0.0 && dist > 0.0) {
+      const D3 n = d3(dv.x / dist, dv.y / dist, dv.z / dist);
+      const double wt[4] = {1.0 - al, al, -(1.0 - be), -be};   // dC/dx_t = wt n, dC/ds_t = -|wt| rbar
+      double den = 0.0;
+      double w[4], ws[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const double k = w[t] * wt[t] * dl;
-        unsigned long long* o = c.acc + 4 * (size_t)pid[t];
-        acc_add(o + 0, k * n.x);
-        acc_add(o + 1, k * n.y);
-        acc_add(o + 2, k * n.z);
-        acc_add(o + 3, -ws[t] * fabs(wt[t]) * rb[t] * dl);
-        atomicAdd(&c.acnt[pid[t]], 1);
+        w[t] = (double)d.winv[pid[t]];
+        ws[t] = (double)d.wsinv[pid[t]];
+        const double gs = fabs(wt[t]) * rb[t];
+        den += w[t] * wt[t] * wt[t] + ws[t] * gs * gs;
+      }
+      if (den > 0.0) {
+        const double dl = -C / den;
+        const int t0 = upper ? 2 : 0;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int t = t0 + u;
+          const double k = w[t] * wt[t] * dl;
+          unsigned long long* o = c.acc + 4 * (size_t)pid[t];
+          acc_add(o + 0, k * n.x);
+          acc_add(o + 1, k * n.y);
+          acc_add(o + 2, k * n.z);
+          acc_add(o + 3, -ws[t] * fabs(wt[t]) * rb[t] * dl);
+          atomicAdd(&c.acnt[pid[t]], 1);
+        }
       }
     }
   }

@@ -227,7 +227,7 @@ int stage_items(const Counts& c, int stage) {
     case TB_WAVES: return c.W;
     case TB_CAPS: return c.contacts ? c.E : 0;
     case TB_SEARCH: return c.contacts ? c.E : 0;
-    case TB_PAIRS: return c.contacts ? c.cap : 0;
+    case TB_PAIRS: return c.contacts ? 2 * pair_span(c.cap) : 0;
     case TB_SCAN_E: return c.contacts ? 9 * c.E : 0;
     case TB_SCAN_T: return c.contacts ? c.T : 0;
     case TB_DET: return c.contacts ? std::max(c.P, std::max(c.T, c.E)) : 0;

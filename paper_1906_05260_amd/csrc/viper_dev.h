@@ -157,7 +157,7 @@ enum Stage {
   TB_WAVES = 0,   // 4 wavefronts (<= 512 pill slots) per block: rod kernels
   TB_CAPS,        // 256 capsules per block
   TB_SEARCH,      // 28 capsules per block, 9 threads each: neighbour search
-  TB_PAIRS,       // 256 candidate-pair slots per block
+  TB_PAIRS,       // 256 lanes per block, two per candidate pair, 2 pair_span(cap) lanes per scene
   TB_SCAN_E,      // 1024 (capsule, neighbour column) counts per block (scans)
   TB_SCAN_T,      // 1024 cells per block
   TB_DET,         // 256 of max(pills, cells, capsules) per block: start of contact detection
@@ -165,6 +165,12 @@ enum Stage {
   TB_SECP,        // 256 bundling section entries per block
   TB_COUNT
 };
+
+// Candidate pairs the contact pass covers per round and scene (its blocks stride over the
+// pair list in rounds of this many pairs).
+constexpr int kPairSpan = 32768;
+__host__ __device__ inline int pair_span(int cap) { return cap < kPairSpan ? cap : kPairSpan; }
+
 
 struct BatchDev {
   int nscenes = 0;
