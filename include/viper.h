@@ -189,26 +189,33 @@ viper_status viper_set_state(viper_scene scene, int32_t which, const void* src, 
  * (synchronises `stream`).  VIPER_ERR_NO_CAPACITY if n > cap (nothing written). */
 viper_status viper_get_contacts(viper_scene scene, int32_t* pairs, int32_t cap, int32_t* n, void* stream);
 
-/* Record of the last contact detection of a scene (Sec. 7.1 uniform grid).  The grid's cell
- * width is twice the cell radius: the largest capsule bounding radius of the histogram bin
- * (4 bins per octave) that holds the 33rd-largest radius, so that at most 32 larger capsules
- * exist (with no outliers, the largest radius of all); those are kept in a list that every
- * capsule searches besides its 27 neighbour cells.
+/* Record of the last contact detection of a scene (Sec. 7.1 uniform grid, in two levels).
+ * The capsule bounding radii are histogrammed (4 bins per octave).  The cell bin holds the
+ * 33rd-largest radius: the at most 32 larger capsules are kept in a list that every capsule
+ * searches.  Below it, a fine bin splits the capsules into a fine grid (cell width twice the
+ * largest radius of the fine bin; the radii up to it) and a coarse grid (cell width twice
+ * the sum of the cell bin's and the fine bin's largest radii; the radii above it), chosen to
+ * minimise the entries examined for capsules spread uniformly; with one level the fine bin
+ * is the cell bin.  A capsule examines half of the 27 cells around its own in its level
+ * (the other half find the same pairs), a fine capsule also the 8 coarse cells nearest its
+ * centre, and the list.
  * Capsules whose bounding sphere is not finite are left out and raise VIPER_ERR_NAN at
  * viper_sync; capsules with an end radius s r <= 0 (no surface while a scale passes through
- * zero) are left out too (no contact).  If the cell radius would exceed 4 times the largest
- * bounding radius of the rest pose, the scene has diverged: its detection is skipped (no
- * candidates that substep) and viper_sync reports VIPER_ERR_NAN.  So the candidate search
- * examines at most the entries of 27 cells of width <= 8 rest radii plus 32 list entries
- * per capsule. */
+ * zero) are left out too (no contact).  If the cell bin's radius would exceed 4 times the
+ * largest bounding radius of the rest pose, the scene has diverged: its detection is skipped
+ * (no candidates that substep) and viper_sync reports VIPER_ERR_NAN.  So every cell is at
+ * most 16 rest radii wide. */
 typedef struct {
   int64_t walk_entries;       /* bucket and list entries the candidate count pass examined */
   int32_t oversized;          /* capsules in the oversized list */
   int32_t excluded;           /* capsules left out: sphere not finite or an end radius <= 0 */
   int32_t skipped;            /* 1 if the detection was skipped (diverged scene) */
-  int32_t cell_bin;           /* histogram bin of the cell radius */
-  double cell_width;          /* m; 0 when skipped */
+  int32_t cell_bin;           /* histogram bin of the fine grid's cell radius */
+  double cell_width;          /* m, fine grid; 0 when skipped */
   double cell_radius_limit;   /* m: 4 x the largest bounding radius at rest */
+  int32_t coarse_bin;         /* histogram bin of the coarse grid's largest radius; -1: one level */
+  int32_t coarse_capsules;    /* capsules in the coarse grid */
+  double coarse_width;        /* m, coarse grid; 0 with one level or when skipped */
 } viper_contact_info;
 /* Fills *info for a scene with collisions (synchronises `stream`); VIPER_ERR_INVALID
  * otherwise. */

@@ -13,7 +13,7 @@ namespace viper {
 // Offsets of the contact buffers inside a scene workspace.
 struct ContactOffsets {
   bool on = false;
-  size_t cap_ids, cap_rod, cap_grp, sph, hist, binmax, dcnt, walk, cw, key, cell, cell_cnt, cell_start, cell_cur, sorted, cgmin, cgmax;
+  size_t cap_ids, cap_rod, cap_grp, sph, hist, binmax, dcnt, walk, cw, key, pkey, cell_cnt, cell_start, cell_cur, sorted, cgmin, cgmax;
   size_t pcount, poff, stage, pairs, npairs, ssph, skey, srg, acc, acnt;
   size_t xdet, sdet, bsum;
   size_t end;

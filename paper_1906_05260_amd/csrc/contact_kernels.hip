@@ -3,22 +3,28 @@
 // Detection (Sec. 7.1, after Green 2010): each capsule (tapered pill primitive)
 // gets a bounding sphere; a uniform grid with cell width equal to the largest
 // sphere diameter guarantees that overlapping spheres sit in neighbouring cells.
-// The cell radius is not the single largest bounding radius: a histogram of the radii finds
-// the bin that holds the (kOversized+1)-th largest, the cell radius is the largest radius of
-// that bin, and the at most kOversized larger capsules are kept in a short list that every
-// capsule walks besides its
-// neighbour cells (one stretched capsule would otherwise widen every cell of its scene and
-// make the walk quadratic).  A capsule whose bounding sphere is not finite is left out and
-// raises the scene's non-finite status; one with an end radius s r <= 0 (no surface) is left
-// out too; a scene whose cell radius would exceed kRadLimit times its largest bounding
-// radius at rest has diverged: its detection is skipped (no candidates) and its status says
-// so.
+// The grid here has two levels and a list.  A histogram of the radii finds the bin that
+// holds the (kOversized+1)-th largest; the at most kOversized larger capsules are kept in a
+// short list that every capsule walks (one stretched capsule would otherwise widen every
+// cell of its scene and make the walk quadratic).  The capsules up to that bin are split at
+// a lower bin into a fine grid (cell diameter the largest fine radius) and a coarse grid of
+// the larger ones (cell diameter the sum of the largest coarse and fine radii), where that
+// split shortens the walk: a scene whose few percent of stretched capsules would otherwise
+// set the cell width of all.  A capsule walks half of the 27 cells around its own in its
+// level (the home cell for partners above it, the cells after it in (dz, dy, dx) order for
+// every partner: each pair is found once), a fine capsule also the 2 x 2 x 2 coarse cells
+// nearest its centre (the coarse capsules walk no fine cell), and the list.
+// A capsule whose bounding sphere is not
+// finite is left out and raises the scene's non-finite status; one with an end radius s r
+// <= 0 (no surface) is left out too; a scene whose cell radius would exceed kRadLimit times
+// its largest bounding radius at rest has diverged: its detection is skipped (no
+// candidates) and its status says so.
 // Cells are hashed into a table and filled by a counting sort; every capsule then
-// counts its candidates in the 27 neighbouring cells, an exclusive scan turns the
+// counts its candidates in its cells, an exclusive scan turns the
 // counts into offsets, and a second pass emits the candidate list in parallel
 // (the parallel count-then-list construction of Sec. 7.1).  Each capsule sorts its
-// own segment, so the list is ordered by (a, b) whatever order the atomics left
-// inside a bucket.  The overlap predicate runs in FP64 with no contraction, so it
+// own segment, so the list does not depend on the order the atomics left inside a
+// bucket.  The overlap predicate runs in FP64 with no contraction, so it
 // decides exactly as a serial FP64 evaluation of the same stored values.
 //
 // Handling (Sec. 7.2, App. D): per candidate pair, a 10-step dichotomous search of
@@ -52,8 +58,30 @@ constexpr int kWaves = 4;       // wavefronts per search block
 constexpr int kCapsPerWave = 7; // capsules per wavefront (7 x 9 columns = 63 lanes)
 static_assert(kWaves * kCapsPerWave == kSearchCaps, "search block layout");
 
-__device__ __forceinline__ uint32_t cell_hash(int x, int y, int z, int T) {
-  return ((uint32_t)x * 73856093u ^ (uint32_t)y * 19349663u ^ (uint32_t)z * 83492791u) & (uint32_t)(T - 1);
+// Key of a grid cell: integer cell coordinates wrapped to 21 / 21 / 20 bits and the grid
+// level (0 fine, 1 coarse) in bit 62, so every key is >= 0 (an oversized capsule's key is
+// -1).  Two cells of one level share a key only if they are >= 2^20 cells apart, too far
+// for any sphere of one to overlap a sphere of the other: the walk's key filter may admit
+// such an entry, the exact overlap test then rejects it.  Neighbour keys are formed from
+// the wrapped coordinates, so the wrap commutes with the +-1 steps.
+constexpr long long kM21 = (1ll << 21) - 1, kM20 = (1ll << 20) - 1;
+__device__ __forceinline__ long long pack_key(int x, int y, int z, int level) {
+  return ((long long)x & kM21) | (((long long)y & kM21) << 21) | (((long long)z & kM20) << 42) |
+         ((long long)level << 62);
+}
+
+// Hash-table bucket of a cell key: the two 32-bit halves multiplied by odd constants and
+// combined, then the 32-bit finalizer of MurmurHash3 (Appleby), masked to the table size T
+// (a power of two).  Neighbouring cells land in unrelated buckets, so an empty neighbour
+// rarely meets an occupied bucket.
+__device__ __forceinline__ uint32_t bucket_of(long long K, int T) {
+  uint32_t h = (uint32_t)K * 0x8DA6B343u ^ (uint32_t)((unsigned long long)K >> 32) * 0xD8163841u;
+  h ^= h >> 16;
+  h *= 0x85EBCA6Bu;
+  h ^= h >> 13;
+  h *= 0xC2B2AE35u;
+  h ^= h >> 16;
+  return h & (uint32_t)(T - 1);
 }
 
 __device__ __forceinline__ int cell_of(double m, double cw) {
@@ -275,50 +303,95 @@ __global__ void __launch_bounds__(256) det_kernel(const Dev<T>* __restrict__ D, 
     }
 }
 
-// Cell bin from the histogram, by the first wavefront (64 lanes, two bins each): the bin
-// holding the (kOversized+1)-th largest radius, i.e. the highest bin b whose suffix count
-// (capsules in bins >= b) exceeds kOversized, or bin 0; bins above it hold at most
-// kOversized capsules.  The count of bins with such a suffix is a ballot.
-__device__ int cell_bin_wave(const int* h, int lane) {
+// Grid levels from the histogram, by the first wavefront (64 lanes, two bins each).
+// The cell bin cb holds the (kOversized+1)-th largest radius: the highest bin whose suffix
+// count (capsules in bins >= it) exceeds kOversized, or bin 0; bins above it hold at most
+// kOversized capsules, searched from a list.  The fine bin bf <= cb splits the rest: bins up
+// to bf form the fine grid (cell radius rf = the largest radius of bin bf), bins in (bf, cb]
+// a coarse grid of cell radius rc + rf (rc = the largest radius of bin cb), so that a fine
+// capsule finds every coarse partner in the 2 x 2 x 2 coarse cells nearest its centre.  bf
+// is the non-empty bin that minimises the entries walked for capsules spread uniformly:
+// E_f fine capsules walk half of 27 fine cells holding E_f capsules and 8 coarse cells
+// holding E_c, the coarse ones half of 27 coarse cells (cell volumes (2 rf)^3 and
+// (2 (rc + rf))^3); bf = cb, one level, when that is cheapest or no bin qualifies.
+struct GridLevels {
+  int cb, bf, ncoarse;
+  double rc, rf;
+};
+__device__ GridLevels grid_levels_wave(const int32_t* h, const unsigned long long* bm, int lane) {
   static_assert(kRadBins == 128, "two bins per lane");
   const int h0 = h[2 * lane], h1 = h[2 * lane + 1];
+  const double m0 = __longlong_as_double((long long)bm[2 * lane]), m1 = __longlong_as_double((long long)bm[2 * lane + 1]);
   int t = h0 + h1;                      // suffix sum over lanes >= this one
+  int p = h0 + h1;                      // prefix sum over lanes <= this one
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
     const int u = __shfl_down(t, o);
     if (lane + o < 64) t += u;
+    const int v = __shfl_up(p, o);
+    if (lane >= o) p += v;
   }
   const int s0 = t, s1 = t - h0;        // capsules in bins >= 2 lane, >= 2 lane + 1
   const int n = __popcll(__ballot(s0 > kOversized)) + __popcll(__ballot(s1 > kOversized));
-  return n > 0 ? n - 1 : 0;
+  GridLevels g;
+  g.cb = n > 0 ? n - 1 : 0;
+  const int p1 = p, p0 = p - h1;        // capsules in bins <= 2 lane, <= 2 lane + 1
+  const int pc = __shfl((g.cb & 1) ? p1 : p0, g.cb >> 1);
+  const double rc = __shfl((g.cb & 1) ? m1 : m0, g.cb >> 1);
+  double best = INFINITY;
+  int bb = g.cb;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int bin = 2 * lane + k, cnt = k ? h1 : h0;
+    if (bin > g.cb || cnt == 0) continue;
+    const double ef = (double)(k ? p1 : p0), ec = (double)pc - ef;
+    const double rf = k ? m1 : m0;
+    const double vf = 8.0 * rf * rf * rf, vc = 8.0 * (rc + rf) * (rc + rf) * (rc + rf);
+    const double cost = 27.0 * ef * ef * vf + (16.0 * ef * ec + 27.0 * ec * ec) * vc;
+    if (cost <= best) { best = cost; bb = bin; }   // ties: the higher bin
+  }
+  // wave argmin (ties: the higher bin)
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ob = __shfl_xor(best, o);
+    const int obb = __shfl_xor(bb, o);
+    if (ob < best || (ob == best && obb > bb)) { best = ob; bb = obb; }
+  }
+  g.bf = bb;
+  g.ncoarse = pc - __shfl((bb & 1) ? p1 : p0, bb >> 1);
+  g.rc = rc;
+  g.rf = __shfl((bb & 1) ? m1 : m0, bb >> 1);
+  return g;
 }
 
-// Cell keys: a capsule in a bin up to the cell bin goes to its grid cell, a larger one to the
-// oversized list, a non-finite one (or every capsule of a skipped scene) nowhere; the
-// candidate counts of capsules that are not placed are cleared here, since no search
-// thread visits them.
+// Cell keys: a capsule in a bin up to the fine bin goes to its fine-grid cell, one up to the
+// cell bin to its coarse-grid cell, a larger one to the oversized list, a non-finite one (or
+// every capsule of a skipped scene) nowhere; the candidate counts of capsules that are not
+// placed are cleared here, since no search thread visits them.
 __global__ void __launch_bounds__(256) key_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
-  __shared__ int sh[kRadBins];
-  __shared__ int s_bin;
-  __shared__ double s_rc;
+  __shared__ int s_cb, s_bf;
+  __shared__ double s_rc, s_rf;
   const Blk b = tab[blockIdx.x];
   const ContactDev& c = CD[b.scene];
   if (threadIdx.x < 64) {
     const int lane = (int)threadIdx.x;
-    sh[2 * lane] = c.hist[2 * lane];
-    sh[2 * lane + 1] = c.hist[2 * lane + 1];
-    const int cb = cell_bin_wave(sh, lane);
+    const GridLevels g = grid_levels_wave(c.hist, c.binmax, lane);
     if (lane == 0) {
-      // the cell radius: the largest radius of the cell bin, i.e. of every capsule in the grid
-      const double rc = __longlong_as_double((long long)c.binmax[cb]);
-      s_bin = cb;
+      const double rc = g.rc, rf = g.rf;
+      s_cb = g.cb;
+      s_bf = g.bf;
       s_rc = rc;
+      s_rf = rf;
       if (b.base == 0) {               // the detection's record, read back by viper_contact_stats
         const bool skip = !(rc <= c.rlim);
+        const bool two = !skip && g.bf < g.cb;
         c.dcnt[1] = skip;
         c.dcnt[2] = c.hist[kRadBins];
-        c.dcnt[3] = cb;
-        c.cw[0] = skip ? 0.0 : cell_width_of(rc);
+        c.dcnt[3] = g.bf;
+        c.dcnt[4] = two ? g.cb : -1;
+        c.dcnt[5] = two ? g.ncoarse : 0;
+        c.cw[0] = skip ? 0.0 : cell_width_of(rf);
+        c.cw[1] = two ? cell_width_of(rc + rf) : 0.0;
         if (skip) c.status[ST_DIVERGED] = 1;
       }
     }
@@ -326,8 +399,8 @@ __global__ void __launch_bounds__(256) key_kernel(const ContactDev* __restrict__
   __syncthreads();
   const int i = b.base + (int)threadIdx.x;
   if (i >= c.E) return;
-  const int cb = s_bin;
-  const double rc = s_rc;
+  const int cb = s_cb, bf = s_bf;
+  const double rc = s_rc, rf = s_rf;
   const int bin = c.key[i];
   if (!(rc <= c.rlim) || bin == kRadBins) {
     c.key[i] = -1;
@@ -339,22 +412,16 @@ __global__ void __launch_bounds__(256) key_kernel(const ContactDev* __restrict__
     c.key[i] = -2 - atomicAdd(&c.dcnt[0], 1);
     return;
   }
-  const double cw = cell_width_of(rc);
-  const int cx = cell_of(c.sph[4 * (size_t)i], cw), cy = cell_of(c.sph[4 * (size_t)i + 1], cw),
-            cz = cell_of(c.sph[4 * (size_t)i + 2], cw);
-  c.cell[3 * (size_t)i] = cx; c.cell[3 * (size_t)i + 1] = cy; c.cell[3 * (size_t)i + 2] = cz;
-  const uint32_t h = cell_hash(cx, cy, cz, c.T);
+  const int level = bin > bf;
+  const double cw = level ? cell_width_of(rc + rf) : cell_width_of(rf);
+  const long long K = pack_key(cell_of(c.sph[4 * (size_t)i], cw), cell_of(c.sph[4 * (size_t)i + 1], cw),
+                               cell_of(c.sph[4 * (size_t)i + 2], cw), level);
+  c.pkey[i] = K;
+  const uint32_t h = bucket_of(K, c.T);
   c.key[i] = (int32_t)h;
   atomicAdd(&c.cell_cnt[h], 1);
   atomicMin(&c.cgmin[h], c.cap_grp[i]);
   atomicMax(&c.cgmax[h], c.cap_grp[i]);
-}
-
-// Exact cell of a capsule packed into 63 bits (21 per axis).  Two cells that alias after
-// packing are >= 2^21 cells apart, so no sphere of one overlaps a sphere of the other: the
-// filter below may admit an aliased bucket entry, the exact overlap test then rejects it.
-__device__ __forceinline__ long long pack_cell(int x, int y, int z) {
-  return (long long)(x & 0x1FFFFF) | ((long long)(y & 0x1FFFFF) << 21) | ((long long)(z & 0x1FFFFF) << 42);
 }
 
 __global__ void __launch_bounds__(256) bucket_scatter_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
@@ -367,27 +434,26 @@ __global__ void __launch_bounds__(256) bucket_scatter_kernel(const ContactDev* _
   // grid capsules go to their bucket, oversized ones after every bucket (cell_start[T] is the
   // number of grid capsules)
   const int pos = h >= 0 ? c.cell_start[h] + atomicAdd(&c.cell_cur[h], 1) : c.cell_start[c.T] + (-2 - h);
-  // the capsule's search data goes straight to its slot: sphere, exact cell, rod, group
+  // the capsule's search data goes straight to its slot: sphere, cell key, rod, group
   c.sorted[pos] = i;
 #pragma unroll
   for (int k = 0; k < 4; ++k) c.ssph[4 * (size_t)pos + k] = c.sph[4 * (size_t)i + k];
-  c.skey[pos] = h >= 0 ? pack_cell(c.cell[3 * (size_t)i], c.cell[3 * (size_t)i + 1], c.cell[3 * (size_t)i + 2]) : -1ll;
+  c.skey[pos] = h >= 0 ? c.pkey[i] : -1ll;
   c.srg[2 * (size_t)pos] = c.cap_rod[i];
   c.srg[2 * (size_t)pos + 1] = c.cap_grp[i];
 }
 
 
-// Count (EMIT = false) or emit (EMIT = true) the candidates b > a of capsule a.  Threads
-// follow bucket order, so the lanes of a wave mostly share a home cell and walk the same
-// neighbour entries (their loads coalesce); each of a capsule's 9 threads covers one
-// (dz, dy) column of 3 cells.  Counts are per (capsule, column) so that an exclusive scan
-// gives every thread its output offset.  The count pass keeps a column's first 4
-// candidates, so the emit pass re-walks only the columns that had more.  After the emit
-// pass the capsule's first thread sorts the capsule's segment by b and stores capsule ids.  A bucket whose entries all
-// share the capsule's collision group (the interior of a muscle) is skipped unread.  The
-// centre column also walks the oversized list: a grid capsule takes every oversized
-// candidate (whichever index is lower: the oversized capsule walks no cells), an oversized
-// capsule the oversized candidates above it; a pair is stored as (lower, higher) capsule id.
+// Count (EMIT = false) or emit (EMIT = true) the candidates that capsule a's walk finds
+// (see the slots below).  Threads follow bucket order, so the lanes of a wave mostly share
+// a home cell and walk the same neighbour entries (their loads coalesce); each of a
+// capsule's 9 threads covers one (dz, dy) column.  Counts are per (capsule, column) so that
+// an exclusive scan gives every thread its output offset.  The count pass keeps a column's
+// first 4 candidates, so the emit pass re-walks only the columns that had more.  After the
+// emit pass the capsule's threads sort the capsule's segment by b and store capsule ids.  A
+// bucket whose entries all share the capsule's collision group (the interior of a muscle)
+// is skipped unread.  A pair is stored as (lower, higher) capsule id in the segment of the
+// capsule whose walk found it.
 template <bool EMIT>
 __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
   const Blk blk = tab[blockIdx.x];
@@ -429,46 +495,84 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
       if (base + k < c.cap) c.pairs[2 * (size_t)(base + k) + 1] = stg[k];
   }
   // Columns to walk: all of them in the count pass, those with more than kStage candidates
-  // in the emit pass.  A lane lists its column's three cells (a bucket whose entries all
-  // share the capsule's group is left out) ...
+  // in the emit pass.  A lane lists up to 4 slots (a run of bucket entries, the key they
+  // must carry, whether b > a is required) ...
+  //  - slots 0..2, the cells dx = -1, 0, +1 of its (dz, dy) column in its capsule's own
+  //    level, half shell: a cell after the home cell in (dz, dy, dx) order gives every
+  //    partner, the home cell those above a, a cell before it none (the partner's own walk
+  //    finds that pair), so the columns with dz < 0 or (dz = 0, dy < 0) list no cell and
+  //    the centre column its home cell and dx = +1;
+  //  - slot 3 of a fine capsule's lanes 0..7: one of the 2 x 2 x 2 coarse cells nearest its
+  //    centre, every partner (a coarse capsule walks no fine cell);
+  //  - slot 3 of lane 8: the oversized list, every entry for a grid capsule, those above a
+  //    for an oversized capsule (which walks nothing else).
+  // A bucket whose entries all share the capsule's group is left out.
   __shared__ int s_off[kWaves][65];
   __shared__ int s_cnt[kWaves][64];
-  __shared__ int s_col[kWaves][64][15];   // js0..js3, cum1 cum2 cum3, cx ny nz, a ra ga, out, oversized home
+  __shared__ int s_col[kWaves][64][12];   // js0..js3, cum1 cum2 cum3, b > a mask, a ra ga, out
+  __shared__ long long s_key[kWaves][64][2];   // key of the column's dx = -1 cell, key of slot 3
   __shared__ double s_sph[kWaves][64][4];
   int w = 0;
   {
-    int js[4] = {0, 0, 0, 0}, ln[4] = {0, 0, 0, 0}, cx = 0, ny = 0, nz = 0, ra = 0, ga = 0;
+    int js[4] = {0, 0, 0, 0}, ln[4] = {0, 0, 0, 0}, ra = 0, ga = 0, gt = 0;
+    long long k0 = -1, k3 = -1;
     const bool over = jh >= ngrid;
     double sa[4] = {0.0, 0.0, 0.0, 0.0};
     if (live && (!EMIT || have > kStage)) {
+      const long long K = c.skey[jh];
 #pragma unroll
       for (int k = 0; k < 4; ++k) sa[k] = c.ssph[4 * (size_t)jh + k];
       ra = c.srg[2 * (size_t)jh]; ga = c.srg[2 * (size_t)jh + 1];
       if (!over) {
-        cx = c.cell[3 * (size_t)a];
-        ny = c.cell[3 * (size_t)a + 1] + sub % 3 - 1;
-        nz = c.cell[3 * (size_t)a + 2] + sub / 3 - 1;
-        uint32_t hc[3];
-        int gmn[3], gmx[3], je[3];
+        const int level = (int)(K >> 62);
+        const int x = (int)(K & kM21), y = (int)((K >> 21) & kM21), z = (int)((K >> 42) & kM20);
+        k0 = pack_key(x - 1, y + sub % 3 - 1, z + sub / 3 - 1, level);
+        const int dfirst = sub < kSearchSub / 2 ? 3 : (sub == kSearchSub / 2 ? 1 : 0);
+        if (sub == kSearchSub / 2) gt = 1 << 1;
+        const double cwc = c.cw[1];
+        bool coarse = false;
+        if (level == 0 && sub < 8 && cwc > 0.0) {
+          // coarse cell (bits of sub: step towards the nearer neighbour along x, y, z)
+          int kc[3];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) hc[d] = cell_hash(cx + d - 1, ny, nz, c.T);
+          for (int j = 0; j < 3; ++j) {
+            const double q = sa[j] / cwc;
+            const double f = floor(q);
+            const int side = (q - f < 0.5) ? -1 : 1;
+            kc[j] = (int)fmin(fmax(f, -1073741824.0), 1073741823.0) + (((sub >> j) & 1) ? side : 0);
+          }
+          k3 = pack_key(kc[0], kc[1], kc[2], 1);
+          coarse = true;
+        }
+        uint32_t hc[4];
+        int gmn[4], gmx[4], je[4];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
+        for (int d = 0; d < 3; ++d) hc[d] = bucket_of((k0 & ~kM21) | ((k0 + d) & kM21), c.T);
+        hc[3] = coarse ? bucket_of(k3, c.T) : 0u;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+          if (d < 3 ? d < dfirst : !coarse) continue;
           gmn[d] = c.cgmin[hc[d]]; gmx[d] = c.cgmax[hc[d]];
           js[d] = c.cell_start[hc[d]]; je[d] = c.cell_start[hc[d] + 1];
         }
 #pragma unroll
-        for (int d = 0; d < 3; ++d) ln[d] = (gmn[d] == ga && gmx[d] == ga) ? 0 : je[d] - js[d];
+        for (int d = 0; d < 4; ++d) {
+          if (d < 3 ? d < dfirst : !coarse) continue;
+          ln[d] = (gmn[d] == ga && gmx[d] == ga) ? 0 : je[d] - js[d];
+        }
+      } else if (sub == kSearchSub - 1) {
+        gt = 1 << 3;
       }
-      if (sub == kSearchSub / 2) { js[3] = ngrid; ln[3] = nplaced - ngrid; }
+      if (sub == kSearchSub - 1) { js[3] = ngrid; ln[3] = nplaced - ngrid; k3 = -1; }
     }
     w = ln[0] + ln[1] + ln[2] + ln[3];
     int* sc = s_col[wv][lane];
     sc[0] = js[0]; sc[1] = js[1]; sc[2] = js[2]; sc[3] = js[3];
     sc[4] = ln[0]; sc[5] = ln[0] + ln[1]; sc[6] = ln[0] + ln[1] + ln[2];
-    sc[7] = cx; sc[8] = ny; sc[9] = nz; sc[10] = a; sc[11] = ra; sc[12] = ga;
-    sc[13] = EMIT ? (live ? c.poff[col] : 0) : col;
-    sc[14] = over;
+    sc[7] = gt; sc[8] = a; sc[9] = ra; sc[10] = ga;
+    sc[11] = EMIT ? (live ? c.poff[col] : 0) : col;
+    s_key[wv][lane][0] = k0;
+    s_key[wv][lane][1] = k3;
 #pragma unroll
     for (int k = 0; k < 4; ++k) s_sph[wv][lane][k] = sa[k];
     s_cnt[wv][lane] = 0;
@@ -524,21 +628,20 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
       if (o < 0) continue;
       const int* sc = s_col[wv][o];
       const int b = bb[u];
-      if (dd[u] < 3) {
-        if (b <= sc[10]) continue;
-        if (kk[u] != pack_cell(sc[7] + dd[u] - 1, sc[8], sc[9])) continue;   // another cell (hash collision)
-      } else if (b == sc[10] || (sc[14] && b < sc[10])) {
-        continue;                                          // oversized list: see above
-      }
-      if (rr[u] == sc[11] || gg[u] == sc[12]) continue;
+      const int d = dd[u];
+      const long long k0 = s_key[wv][o][0];
+      const long long want = d < 3 ? ((k0 & ~kM21) | ((k0 + d) & kM21)) : s_key[wv][o][1];
+      if (kk[u] != want) continue;                         // another cell or level (hash collision)
+      if (((sc[7] >> d) & 1) && b <= sc[8]) continue;      // the home cell / an oversized capsule's list
+      if (rr[u] == sc[9] || gg[u] == sc[10]) continue;
       const double sb[4] = {s01[u].x, s01[u].y, s23[u].x, s23[u].y};
       if (!spheres_overlap(s_sph[wv][o], sb)) continue;
       const int pos = atomicAdd(&s_cnt[wv][o], 1);
       if (EMIT) {
-        const int idx = sc[13] + pos;
+        const int idx = sc[11] + pos;
         if (idx < c.cap) c.pairs[2 * (size_t)idx + 1] = b;   // capsule index for now
       } else if (pos < kStage) {
-        c.stage[(size_t)kStage * sc[13] + pos] = b;
+        c.stage[(size_t)kStage * sc[11] + pos] = b;
       }
     }
   }
@@ -920,11 +1023,11 @@ ContactOffsets contact_layout(size_t start, bool on, int P, int E, int cpc, bool
   o.sph = take(8 * 4 * (size_t)E);
   o.hist = take(4 * (size_t)(kRadBins + 1));
   o.binmax = take(8 * (size_t)kRadBins);
-  o.dcnt = take(4 * 4);
+  o.dcnt = take(4 * 8);
   o.walk = take(8 * kWalkCounters);
-  o.cw = take(8);
+  o.cw = take(8 * 2);
   o.key = take(4 * (size_t)E);
-  o.cell = take(12 * (size_t)E);
+  o.pkey = take(8 * (size_t)E);
   o.cell_cnt = take(4 * (size_t)T);
   o.cell_start = take(4 * (size_t)(T + 1));
   o.cell_cur = take(4 * (size_t)T);
@@ -986,7 +1089,7 @@ viper_status contact_init(ContactDev& c, char* ws, const ContactOffsets& o, cons
   c.walk = (unsigned long long*)(ws + o.walk);
   c.cw = (double*)(ws + o.cw);
   c.key = (int32_t*)(ws + o.key);
-  c.cell = (int32_t*)(ws + o.cell);
+  c.pkey = (long long*)(ws + o.pkey);
   c.cell_cnt = (int32_t*)(ws + o.cell_cnt);
   c.cell_start = (int32_t*)(ws + o.cell_start);
   c.cell_cur = (int32_t*)(ws + o.cell_cur);
@@ -1013,8 +1116,8 @@ viper_status contact_init(ContactDev& c, char* ws, const ContactOffsets& o, cons
       hipMemsetAsync(c.npairs, 0, 4, st) != hipSuccess ||
       hipMemsetAsync(c.hist, 0, 4 * (size_t)(kRadBins + 1), st) != hipSuccess ||
       hipMemsetAsync(c.binmax, 0, 8 * (size_t)kRadBins, st) != hipSuccess ||
-      hipMemsetAsync(c.dcnt, 0, 16, st) != hipSuccess || hipMemsetAsync(c.walk, 0, 8 * kWalkCounters, st) != hipSuccess ||
-      hipMemsetAsync(c.cw, 0, 8, st) != hipSuccess ||
+      hipMemsetAsync(c.dcnt, 0, 4 * 8, st) != hipSuccess || hipMemsetAsync(c.walk, 0, 8 * kWalkCounters, st) != hipSuccess ||
+      hipMemsetAsync(c.cw, 0, 8 * 2, st) != hipSuccess ||
       hipMemsetAsync(c.acc, 0, 8 * 4 * (size_t)c.P, st) != hipSuccess ||
       hipMemsetAsync(c.acnt, 0, 4 * (size_t)c.P, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
     return VIPER_ERR_DEVICE;
@@ -1123,8 +1226,8 @@ viper_status contact_get_pairs(const ContactDev& c, int32_t* pairs, int32_t cap,
   if (h > cap) return VIPER_ERR_NO_CAPACITY;
   if (h > 0) {
     if (!pairs) return VIPER_ERR_INVALID;
-    // the device list is ordered by the emitting capsule; a pair with an oversized capsule sits
-    // in its grid partner's segment, so the canonical (a, b) order is restored here
+    // the device list is ordered by the capsule whose walk found the pair (the lower id in a
+    // home cell, otherwise either), so the canonical (a, b) order is restored here
     std::vector<int64_t> v((size_t)h);
     if (hipMemcpyAsync(v.data(), c.pairs, 8 * (size_t)h, hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
@@ -1141,12 +1244,12 @@ viper_status contact_get_pairs(const ContactDev& c, int32_t* pairs, int32_t cap,
 }
 
 viper_status contact_get_info(const ContactDev& c, viper_contact_info* out, hipStream_t st) {
-  int32_t cnt[4];
+  int32_t cnt[8];
   unsigned long long walk[kWalkCounters];
-  double cw = 0.0;
-  if (hipMemcpyAsync(cnt, c.dcnt, 16, hipMemcpyDeviceToHost, st) != hipSuccess ||
+  double cw[2] = {0.0, 0.0};
+  if (hipMemcpyAsync(cnt, c.dcnt, sizeof(cnt), hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipMemcpyAsync(walk, c.walk, sizeof(walk), hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipMemcpyAsync(&cw, c.cw, 8, hipMemcpyDeviceToHost, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
+      hipMemcpyAsync(cw, c.cw, sizeof(cw), hipMemcpyDeviceToHost, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
     return VIPER_ERR_DEVICE;
   unsigned long long total = 0;
   for (int k = 0; k < kWalkCounters; ++k) total += walk[k];
@@ -1155,8 +1258,11 @@ viper_status contact_get_info(const ContactDev& c, viper_contact_info* out, hipS
   out->skipped = cnt[1];
   out->excluded = cnt[2];
   out->cell_bin = cnt[3];
-  out->cell_width = cw;
+  out->cell_width = cw[0];
   out->cell_radius_limit = c.rlim;
+  out->coarse_bin = cnt[4];
+  out->coarse_capsules = cnt[5];
+  out->coarse_width = cw[1];
   return VIPER_OK;
 }
 

@@ -87,22 +87,26 @@ struct ContactDev {
   int32_t *cap_ids = nullptr, *cap_rod = nullptr, *cap_grp = nullptr;
   double* sph = nullptr;              // [E*4] mx my mz R
   // Grid sizing: a histogram of the bounding radii (kRadBins log-spaced bins, then one count of
-  // capsules left out) finds the bin holding the (kOversized+1)-th largest radius; the cell
-  // radius is that bin's largest radius; larger capsules are walked from a list instead.
+  // capsules left out) finds the bin holding the (kOversized+1)-th largest radius (larger
+  // capsules are walked from a list instead) and the split between a fine and a coarse grid
+  // level below it.
   int32_t* hist = nullptr;            // [kRadBins + 1]
   unsigned long long* binmax = nullptr;  // [kRadBins] bits of the largest radius in each bin
-  int32_t* dcnt = nullptr;            // [4] oversized, skipped, non-finite, cell-radius bin (last detection)
+  // Last detection: [0] oversized, [1] skipped, [2] non-finite, [3] fine bin, [4] cell bin
+  // when a coarse level is used (else -1), [5] coarse-level capsules
+  int32_t* dcnt = nullptr;            // [8]
   unsigned long long* walk = nullptr; // [kWalkCounters] partial sums of the entries the last count pass examined
-  double* cw = nullptr;               // cell width of the last detection (0 when skipped)
+  double* cw = nullptr;               // [2] fine and coarse cell widths of the last detection (0: skipped / one level)
   double rlim = 0.0;                  // largest admitted cell radius (4x the largest at rest)
-  int32_t *key = nullptr, *cell = nullptr;  // [E] radius bin, then hash key; [3E] integer cell coordinates
+  int32_t* key = nullptr;             // [E] radius bin, then hash bucket
+  long long* pkey = nullptr;          // [E] cell key (wrapped cell coordinates and grid level)
   int32_t *cell_cnt = nullptr, *cell_start = nullptr, *cell_cur = nullptr, *sorted = nullptr;
   int32_t *cgmin = nullptr, *cgmax = nullptr;  // [T] smallest / largest group id in each bucket
   int32_t *pcount = nullptr, *poff = nullptr;  // [9E], [9E+1] candidates per (capsule, column)
   int32_t* stage = nullptr;           // [9E*4] first candidates of each (capsule, column)
   int32_t *pairs = nullptr, *npairs = nullptr;
   double* ssph = nullptr;             // [E*4] spheres in bucket (cell) order
-  long long* skey = nullptr;          // [E] packed exact cell coordinates in bucket order
+  long long* skey = nullptr;          // [E] cell keys in bucket order (-1: oversized list)
   int32_t* srg = nullptr;             // [E*2] rod, group in bucket order
   unsigned long long* acc = nullptr;  // [P*4] fixed-point sums of contact corrections (dx dy dz ds)
   int32_t* acnt = nullptr;            // [P] active contacts per pill this pass

@@ -86,6 +86,9 @@ class ContactInfoC(ctypes.Structure):
         ("cell_bin", ctypes.c_int32),
         ("cell_width", ctypes.c_double),
         ("cell_radius_limit", ctypes.c_double),
+        ("coarse_bin", ctypes.c_int32),
+        ("coarse_capsules", ctypes.c_int32),
+        ("coarse_width", ctypes.c_double),
     ]
 
 

@@ -1,9 +1,14 @@
 """The contact grid under outliers (Sec. 7.1 detection), through the C ABI on the GPU.
 
 The grid's cell radius ignores the 32 largest capsule bounding radii (those capsules are
-searched from a list), capsules whose bounding sphere is not finite are left out, and a
+searched from a list), capsules with larger radii than most go to a coarse grid level when
+that shortens the search, capsules whose bounding sphere is not finite are left out, and a
 scene whose cells would exceed 4x its largest rest bounding radius is reported as diverged
 with its detection skipped.  Checked here:
+- many moderately stretched capsules (more than the list holds): they form a coarse level,
+  the fine cell width stays that of the intact scene, the walk stays below what one grid
+  sized by the stretched capsules would examine, and the candidate set equals the oracle's
+  brute force;
 - one stretched capsule (a pill moved 1 m away): the cell width stays that of the intact
   scene, the candidate count pass examines at most 1.5x the intact scene's entries plus one
   list entry per capsule and oversized capsule, and the candidate set still equals the
@@ -94,6 +99,33 @@ def test_one_stretched_capsule(prec):
     got = sc.contacts()
     ref = oracle_pairs(desc, sc)
     involved = int(np.isin(ref, [p - 1, p]).any(1).sum())
+    say("pairs", len(got), len(ref), "with the stretched capsules", involved)
+    assert involved > 0
+    assert np.array_equal(got, ref)
+    sc.sync()
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_many_stretched_capsules_form_a_coarse_level(prec):
+    desc, sc, base = warm(prec)
+    x = sc.state()["x"]
+    rng = np.random.default_rng(7)
+    moved = free_interior_pills(desc, 60)
+    d = rng.normal(size=(len(moved), 3))
+    x[moved] += 0.03 * d / np.linalg.norm(d, axis=1, keepdims=True)   # 120 capsules ~3 cm long
+    substep_on(sc, x)
+    st = sc.contact_stats()
+    say(prec, "60 pills moved 3 cm:", st)
+    assert st["skipped"] == 0 and st["excluded"] == 0 and st["oversized"] <= 32
+    assert st["coarse_bin"] > st["cell_bin"] and st["coarse_capsules"] >= 120 - 32
+    assert st["cell_width"] <= 1.5 * base["cell_width"]
+    assert st["coarse_width"] >= 2.0 * st["cell_width"]
+    # one grid with cells as wide as the coarse level's would hold ~(coarse / fine)^3 as many
+    # capsules per cell; the two levels examine less than twice the intact scene's entries
+    assert st["walk_entries"] <= 2.0 * base["walk_entries"] + st["oversized"] * sc.capsules
+    got = sc.contacts()
+    ref = oracle_pairs(desc, sc)
+    involved = int(np.isin(ref, np.concatenate([moved - 1, moved])).any(1).sum())
     say("pairs", len(got), len(ref), "with the stretched capsules", involved)
     assert involved > 0
     assert np.array_equal(got, ref)
