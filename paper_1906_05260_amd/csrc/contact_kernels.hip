@@ -723,10 +723,53 @@ __device__ double pill_param(D3 x, D3 c1, double r1, D3 c2, double r2) {
   return fmin(fmax(t, 0.0), 1.0);
 }
 
-__device__ double gap_at(const D3* c, const double* r, double al) {
+// The terms of pill_param that depend on the capsule only (its start and unit axis, 1 / its
+// length and the slope sn / sqrt(1 - sn^2) of the nearest-sphere line), formed once for the
+// many points of a search; `fixed` >= 0 is the parameter of every point (a capsule without
+// length, or one that is its larger end sphere).
+struct PillAxis {
+  D3 c1, e;
+  double il, cot, fixed;
+};
+__device__ PillAxis pill_axis(D3 c1, double r1, D3 c2, double r2) {
+  PillAxis A;
+  A.c1 = c1;
+  A.e = d3(0.0, 0.0, 0.0);
+  A.il = 0.0;
+  A.cot = 0.0;
+  A.fixed = 0.0;
+  const D3 ax = sub(c2, c1);
+  const double l = sqrt(dotp(ax, ax));
+  if (!(l > 0.0)) return A;
+  const double sn = (r1 - r2) / l;
+  if (sn >= 1.0) return A;
+  if (sn <= -1.0) {
+    A.fixed = 1.0;
+    return A;
+  }
+  A.e = d3(ax.x / l, ax.y / l, ax.z / l);
+  A.il = 1.0 / l;
+  A.cot = sn / sqrt(1.0 - sn * sn);
+  A.fixed = -1.0;
+  return A;
+}
+
+// pill_param of point x on a capsule given by its axis terms.
+__device__ __forceinline__ double pill_param_at(const PillAxis& A, D3 x) {
+  const D3 rel = sub(x, A.c1);
+  const double u = dotp(rel, A.e);
+  const D3 perp = d3(rel.x - u * A.e.x, rel.y - u * A.e.y, rel.z - u * A.e.z);
+  const double dp = sqrt(dotp(perp, perp));
+  const double t = (u - dp * A.cot) * A.il;
+  return A.fixed >= 0.0 ? A.fixed : fmin(fmax(t, 0.0), 1.0);
+}
+
+// Signed surface gap between the first capsule's sphere at parameter al and its nearest
+// sphere on the second capsule (axis terms B).
+__device__ __forceinline__ double gap_at(const D3* c, const double* r, const PillAxis& B, double al) {
   const D3 ca = lerp(c[0], c[1], al);
   const double ra = r[0] + al * (r[1] - r[0]);
-  const double be = pill_param(ca, c[2], r[2], c[3], r[3]);
+  const double be = pill_param_at(B, ca);
   const D3 cb = lerp(c[2], c[3], be);
   const D3 dv = sub(ca, cb);
   return sqrt(dotp(dv, dv)) - ra - (r[2] + be * (r[3] - r[2]));
@@ -751,34 +794,45 @@ __global__ void __launch_bounds__(256) contact_pair_kernel(const Dev<T>* __restr
   const int lane2 = blk_.base + (int)threadIdx.x;
   const bool upper = (lane2 & 1) != 0;
   const int span = pair_span(c.cap);
+  // the first pair is read before the count is known (clamped into the list: the last
+  // block's padding lanes read the last slot), everything per pill right after it
+  int i = lane2 >> 1;
+  // the scene's pointers and scalars are requested together (an empty statement that takes
+  // them as operands), not in round trips of their own after the count
+  asm volatile("" ::"s"(d.px), "s"(d.py), "s"(d.pz), "s"(d.s), "s"(d.rbar), "s"(d.winv), "s"(d.wsinv), "s"(d.rod_of),
+               "s"(d.anchor), "s"(c.acc), "s"(c.acnt), "s"(c.search_iters), "s"(c.delta), "s"(c.pairs), "s"(c.npairs));
+  int2 ab = ((const int2*)c.pairs)[min(i, c.cap - 1)];
   const int np = c.npairs[0];
-  for (int i = lane2 >> 1; i < np; i += span) {   // the same trip count on both lanes of a pair
-    const int a = c.pairs[2 * (size_t)i], b = c.pairs[2 * (size_t)i + 1];
-    const int pid[4] = {a, a + 1, b, b + 1};
+  asm volatile("" ::"v"(ab.x), "v"(ab.y));
+  while (i < np) {   // the same trip count on both lanes of a pair
+    const int pid[4] = {ab.x, ab.x + 1, ab.y, ab.y + 1};
     D3 cp[4];
-    double r[4], rb[4];
+    double r[4], rb[4], w[4], ws[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int p = pid[t];
-      double w[3];
-      world_pos(d, p, w);
-      cp[t] = d3(w[0], w[1], w[2]);
+      double x[3];
+      world_pos(d, p, x);
+      cp[t] = d3(x[0], x[1], x[2]);
       rb[t] = (double)d.rbar[p];
       r[t] = (double)d.s[p] * rb[t];
+      w[t] = (double)d.winv[p];
+      ws[t] = (double)d.wsinv[p];
     }
     // dichotomous search over the first capsule's parameter (fixed iteration count)
+    const PillAxis B = pill_axis(cp[2], r[2], cp[3], r[3]);
     double lo = 0.0, hi = 1.0;
     for (int k = 0; k < c.search_iters; ++k) {
       const double m = 0.5 * (lo + hi);
       const double x1 = m - c.delta, x2 = m + c.delta;
-      const double g = gap_at(cp, r, upper ? x2 : x1);
+      const double g = gap_at(cp, r, B, upper ? x2 : x1);
       const double go = pair_swap(g);
       const double g1 = upper ? go : g, g2 = upper ? g : go;
       if (g1 < g2) hi = x2; else lo = x1;
     }
     const double al = 0.5 * (lo + hi);
     const D3 ca = lerp(cp[0], cp[1], al);
-    const double be = pill_param(ca, cp[2], r[2], cp[3], r[3]);
+    const double be = pill_param_at(B, ca);
     const D3 cb = lerp(cp[2], cp[3], be);
     const D3 dv = sub(ca, cb);
     const double dist = sqrt(dotp(dv, dv));
@@ -787,11 +841,8 @@ __global__ void __launch_bounds__(256) contact_pair_kernel(const Dev<T>* __restr
       const D3 n = d3(dv.x / dist, dv.y / dist, dv.z / dist);
       const double wt[4] = {1.0 - al, al, -(1.0 - be), -be};   // dC/dx_t = wt n, dC/ds_t = -|wt| rbar
       double den = 0.0;
-      double w[4], ws[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        w[t] = (double)d.winv[pid[t]];
-        ws[t] = (double)d.wsinv[pid[t]];
         const double gs = fabs(wt[t]) * rb[t];
         den += w[t] * wt[t] * wt[t] + ws[t] * gs * gs;
       }
@@ -811,6 +862,8 @@ __global__ void __launch_bounds__(256) contact_pair_kernel(const Dev<T>* __restr
         }
       }
     }
+    i += span;
+    if (i < np) ab = ((const int2*)c.pairs)[i];
   }
 }
 

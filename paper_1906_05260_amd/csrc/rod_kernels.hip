@@ -58,11 +58,67 @@ __global__ void __launch_bounds__(256) rod_frame_kernel(const Dev<T>* __restrict
 }
 
 // The per-stage kernels run one wavefront per block (block b: wavefront tab[b / 4].base +
-// b % 4), so that a scene of a few hundred wavefronts spreads over every compute unit.
+// b % 4), so that a scene of a few hundred wavefronts spreads over every compute unit.  A
+// launch of a contact substep is mostly the chain of dependent reads a wavefront waits for
+// before its work, so their start is laid out for few round trips to memory: the caller
+// copies the scene's fields into registers in one go (they sit behind the block table) and
+// names the scalars it reads later in an empty statement, so that they come with them; the
+// start has no branch (a wavefront past the scene's last reads that wave's range and gets no
+// valid slot); the slot flags are read unconditionally (an empty slot reads its wave's first
+// pill, which exists), and the per-pill reads that follow depend on the wave's range only.
 template <class T>
-__device__ __forceinline__ const Dev<T>* lane_setup1(const Dev<T>* D, const Blk* tab, Lane2<T>& P, int& pA, int& pB) {
-  const Blk b = tab[blockIdx.x >> 2];
-  return lane_setup_wave(D, b, b.base + (int)(blockIdx.x & 3), P, pA, pB);
+__device__ __forceinline__ void stage_setup(const Dev<T>& d, const Blk b, Lane2<T>& P, int& pA, int& pB) {
+  const int wave = b.base + (int)(blockIdx.x & 3);
+  const bool live = wave < d.W;        // a dead wavefront (last block of a scene) gets no valid slot
+  const int w = live ? wave : d.W - 1;
+  const int lane = (int)(threadIdx.x & 63);
+  const int p0 = d.wave_start[w];
+  const int n = live ? d.wave_start[w + 1] - p0 : 0;
+  const bool vA = 2 * lane < n, vB = 2 * lane + 1 < n;
+  pA = p0 + (vA ? 2 * lane : 0);
+  pB = p0 + (vB ? 2 * lane + 1 : 0);
+  const uint32_t fA = d.flags[pA], fB = d.flags[pB];
+  P.A.f = vA ? fA : 0u;
+  P.B.f = vB ? fB : 0u;
+  P.sb = __any(((P.A.f | P.B.f) & F_SB) != 0u) != 0;
+  P.vb = __any(((P.A.f | P.B.f) & F_VB) != 0u) != 0;
+}
+
+// The previous contact pass's averaged corrections for both slots of a lane (the
+// single-slot contact_apply, with the reads of both slots issued together and used
+// unconditionally: counts and fixed-point sums are read whether or not a slot has contacts).
+template <class T>
+__device__ __forceinline__ int contact_apply_lane(int32_t* acnt, unsigned long long* acc, Lane2<T>& P, int pA, int pB) {
+  const int n[2] = {acnt[pA], acnt[pB]};
+  const int p[2] = {pA, pB};
+  int moved = 0;
+  longlong2 a01[2], a23[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const longlong2* q = (const longlong2*)(acc + 4 * (size_t)p[k]);
+    a01[k] = q[0];
+    a23[k] = q[1];
+  }
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    // without contacts the factor is 0 and the slot keeps its values exactly (a finite
+    // fixed-point sum times 0 adds a zero)
+    Slot<T>& L = k ? P.B : P.A;
+    const bool on = (L.f & F_VALID) && n[k] != 0;
+    const double inv = on ? 1.0 / (double)n[k] : 0.0;
+    L.x0 = (T)((double)L.x0 + inv * ((double)a01[k].x * 0x1p-44));
+    L.x1 = (T)((double)L.x1 + inv * ((double)a01[k].y * 0x1p-44));
+    L.x2 = (T)((double)L.x2 + inv * ((double)a23[k].x * 0x1p-44));
+    L.s = (T)((double)L.s + inv * ((double)a23[k].y * 0x1p-44));
+    if (on) {
+      longlong2* q = (longlong2*)(acc + 4 * (size_t)p[k]);
+      q[0] = make_longlong2(0, 0);
+      q[1] = make_longlong2(0, 0);
+      acnt[p[k]] = 0;
+      moved |= 1 << k;
+    }
+  }
+  return moved;
 }
 
 // ITERATION mode, stage 1: prediction of every pill and edge, saving the substep-start
@@ -83,9 +139,10 @@ template <class T>
 __global__ void __launch_bounds__(256) predict_kernel(const Dev<T>* __restrict__ D, const Blk* __restrict__ tab, T h) {
   Lane2<T> P;
   int pA, pB;
-  const Dev<T>* dp = lane_setup1(D, tab, P, pA, pB);
-  if (!dp) return;
-  const Dev<T>& d = *dp;
+  const Blk b = tab[blockIdx.x >> 2];
+  const Dev<T> d = D[b.scene];
+  asm volatile("" ::"s"(d.gx), "s"(d.gy), "s"(d.gz), "s"(h));
+  stage_setup(d, b, P, pA, pB);
   load_state(d, P.A, pA);
   load_state(d, P.B, pB);
   P.A.w = d.winv[pA]; P.A.inert = d.inert[pA];
@@ -213,26 +270,33 @@ __device__ __forceinline__ void jacobi_lane(Lane2<T>& P) {
   jacobi_apply(P.B, aB);
 }
 
-template <class T, bool X, bool EVEN>
+// C: the scenes have contacts (CD holds their buffers).
+template <class T, bool X, bool EVEN, bool C>
 __global__ void __launch_bounds__(256) rod_iteration_kernel(const Dev<T>* __restrict__ D, const Blk* __restrict__ tab,
                                                             T h, const ContactDev* __restrict__ CD) {
   Lane2<T> P;
   int pA, pB;
-  const Dev<T>* dp = lane_setup1(D, tab, P, pA, pB);
-  if (!dp) return;
-  const Dev<T>& d = *dp;
+  const Blk b = tab[blockIdx.x >> 2];
+  const Dev<T> d = D[b.scene];
+  int32_t* acnt = nullptr;
+  unsigned long long* acc = nullptr;
+  if constexpr (C) {
+    acnt = CD[b.scene].acnt;
+    acc = CD[b.scene].acc;
+  }
+  // the scalars read after the state are requested with the pointers (an empty statement
+  // that takes them as operands), not in a round trip of their own later
+  asm volatile("" ::"s"(d.floor_on), "s"(d.jacobi), "s"(h));
+  stage_setup(d, b, P, pA, pB);
   load_iter<T, X>(d, P.A, pA);
   load_iter<T, X>(d, P.B, pB);
-  if (CD) {   // the previous contact pass's corrections come first
-    const ContactDev& c = CD[dp - D];
-    if (P.A.f & F_VALID) contact_apply(c, pA, P.A.x0, P.A.x1, P.A.x2, P.A.s);
-    if (P.B.f & F_VALID) contact_apply(c, pB, P.B.x0, P.B.x1, P.B.x2, P.B.s);
-  }
+  load_lane_consts<T, X>(d, P, pA, pB, rcp(h * h));
+  // the previous contact pass's corrections come first
+  if constexpr (C) contact_apply_lane(acnt, acc, P, pA, pB);
   if (d.floor_on) {   // then the half-plane floor, at the start of the iteration
     if (P.A.f & F_VALID) floor_apply(d, pA, P.A.x0, P.A.x1, P.A.x2, P.A.s);
     if (P.B.f & F_VALID) floor_apply(d, pB, P.B.x0, P.B.x1, P.B.x2, P.B.s);
   }
-  load_lane_consts<T, X>(d, P, pA, pB, rcp(h * h));
   P.I1N = dn(P.A.I1);
   if (d.jacobi) jacobi_lane<T, X>(P);       // wave-uniform: one scene per block
   else iteration_lane<T, X, EVEN>(P);
@@ -242,34 +306,49 @@ __global__ void __launch_bounds__(256) rod_iteration_kernel(const Dev<T>* __rest
 
 // ITERATION mode, stage 3: velocity update.
 template <class T>
-__device__ __forceinline__ void velocity_store(const Dev<T>& d, Slot<T>& L, int p, T ih, const ContactDev* c) {
-  if (!(L.f & F_VALID)) return;
+__device__ __forceinline__ void velocity_load(const Dev<T>& d, Slot<T>& L, int p) {
   L.x0 = d.px[p]; L.x1 = d.py[p]; L.x2 = d.pz[p]; L.s = d.s[p];
-  if (c && contact_apply(*c, p, L.x0, L.x1, L.x2, L.s)) {   // the last contact pass's corrections
-    d.px[p] = L.x0; d.py[p] = L.x1; d.pz[p] = L.x2; d.s[p] = L.s;
-  }
   L.q0 = d.qx[p]; L.q1 = d.qy[p]; L.q2 = d.qz[p]; L.q3 = d.qw[p];
   L.xp0 = d.xpx[p]; L.xp1 = d.xpy[p]; L.xp2 = d.xpz[p]; L.sp = d.spv[p];
   L.qp0 = d.qpx[p]; L.qp1 = d.qpy[p]; L.qp2 = d.qpz[p]; L.qp3 = d.qpw[p];
   L.w = d.winv[p];
+}
+
+// moved: the last contact pass's corrections changed the slot's position and scale, which
+// are stored back with the velocities
+template <class T>
+__device__ __forceinline__ void velocity_store(const Dev<T>& d, Slot<T>& L, int p, T ih, bool moved) {
+  if (!(L.f & F_VALID)) return;
+  if (moved) { d.px[p] = L.x0; d.py[p] = L.x1; d.pz[p] = L.x2; d.s[p] = L.s; }
   velocity_slot(L, ih);
   d.vx[p] = L.v0; d.vy[p] = L.v1; d.vz[p] = L.v2; d.sd[p] = L.sd;
   if (L.f & F_EDGE) { d.ox[p] = L.o0; d.oy[p] = L.o1; d.oz[p] = L.o2; }
   check_finite(d, L);
 }
 
-template <class T>
+// C: the scenes have contacts, whose last pass's corrections are applied first.
+template <class T, bool C>
 __global__ void __launch_bounds__(256) velocity_kernel(const Dev<T>* __restrict__ D, const Blk* __restrict__ tab, T h,
                                                        const ContactDev* __restrict__ CD) {
   Lane2<T> P;
   int pA, pB;
-  const Dev<T>* dp = lane_setup1(D, tab, P, pA, pB);
-  if (!dp) return;
-  const Dev<T>& d = *dp;
+  const Blk b = tab[blockIdx.x >> 2];
+  const Dev<T> d = D[b.scene];
+  int32_t* acnt = nullptr;
+  unsigned long long* acc = nullptr;
+  if constexpr (C) {
+    acnt = CD[b.scene].acnt;
+    acc = CD[b.scene].acc;
+  }
+  asm volatile("" ::"s"(h));
+  stage_setup(d, b, P, pA, pB);
+  velocity_load(d, P.A, pA);
+  velocity_load(d, P.B, pB);
+  int moved = 0;
+  if constexpr (C) moved = contact_apply_lane(acnt, acc, P, pA, pB);
   const T ih = T(1) / h;
-  const ContactDev* c = CD ? CD + (dp - D) : nullptr;
-  velocity_store(d, P.A, pA, ih, c);
-  velocity_store(d, P.B, pB, ih, c);
+  velocity_store(d, P.A, pA, ih, (moved & 1) != 0);
+  velocity_store(d, P.B, pB, ih, (moved & 2) != 0);
 }
 
 // Field gather/scatter between the SoA layout and a pill-major array.
@@ -415,8 +494,12 @@ template <class T> hipError_t launch_predict(const BatchDev& b, double h, hipStr
 }
 template <class T, bool X, bool EVEN>
 void launch_rod_iteration_as(const BatchDev& b, double h, const ContactDev* cd, hipStream_t st) {
-  hipLaunchKernelGGL((rod_iteration_kernel<T, X, EVEN>), dim3(4 * b.nblk[TB_WAVES]), dim3(64), 0, st, (const Dev<T>*)b.dev,
-                     b.tab[TB_WAVES], (T)h, cd);
+  if (cd)
+    hipLaunchKernelGGL((rod_iteration_kernel<T, X, EVEN, true>), dim3(4 * b.nblk[TB_WAVES]), dim3(64), 0, st,
+                       (const Dev<T>*)b.dev, b.tab[TB_WAVES], (T)h, cd);
+  else
+    hipLaunchKernelGGL((rod_iteration_kernel<T, X, EVEN, false>), dim3(4 * b.nblk[TB_WAVES]), dim3(64), 0, st,
+                       (const Dev<T>*)b.dev, b.tab[TB_WAVES], (T)h, cd);
 }
 template <class T> hipError_t launch_rod_iteration(const BatchDev& b, double h, const ContactDev* cd, hipStream_t st) {
   if (b.nblk[TB_WAVES] == 0) return hipSuccess;
@@ -431,8 +514,12 @@ template <class T> hipError_t launch_rod_iteration(const BatchDev& b, double h, 
 }
 template <class T> hipError_t launch_velocity(const BatchDev& b, double h, const ContactDev* cd, hipStream_t st) {
   if (b.nblk[TB_WAVES] == 0) return hipSuccess;
-  hipLaunchKernelGGL(velocity_kernel<T>, dim3(4 * b.nblk[TB_WAVES]), dim3(64), 0, st, (const Dev<T>*)b.dev,
-                     b.tab[TB_WAVES], (T)h, cd);
+  if (cd)
+    hipLaunchKernelGGL((velocity_kernel<T, true>), dim3(4 * b.nblk[TB_WAVES]), dim3(64), 0, st, (const Dev<T>*)b.dev,
+                       b.tab[TB_WAVES], (T)h, cd);
+  else
+    hipLaunchKernelGGL((velocity_kernel<T, false>), dim3(4 * b.nblk[TB_WAVES]), dim3(64), 0, st, (const Dev<T>*)b.dev,
+                       b.tab[TB_WAVES], (T)h, cd);
   return hipGetLastError();
 }
 template <class T> hipError_t launch_gather_field(const Dev<T>& d, int which, T* out, hipStream_t st) {
