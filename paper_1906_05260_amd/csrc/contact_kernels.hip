@@ -143,94 +143,75 @@ __device__ __forceinline__ void acc_add(unsigned long long* a, double v) {
   (void)d; (void)c;
 
 // ---- exclusive scans (out[n] = total), 1024 items per block, one array per scene:
-// WHICH = 0: hash-cell counts, 1: candidate counts per capsule.  The selection is a
+// WHICH = 0: hash-cell counts, 1: candidate counts per (capsule, column).  The selection is a
 // template parameter: each scan kernel is compiled for one array, so no kernel selects
-// its pointers through a runtime branch.
+// its pointers through a runtime branch.  The kernels that produce the counts also add them
+// into per-chunk totals (a chunk is the 1024 items of one scan block; the totals are cleared
+// by det_kernel), so a scan is one launch with no wait between blocks: block b scans its
+// chunk and adds the totals of the chunks before it.
 template <int WHICH>
 __device__ __forceinline__ void scan_arrays(const ContactDev& c, const int32_t*& in, int32_t*& out, int& n) {
   static_assert(WHICH == 0 || WHICH == 1, "scan array");
   if constexpr (WHICH == 0) { in = c.cell_cnt; out = c.cell_start; n = c.T; }
   else { in = c.pcount; out = c.poff; n = kSearchSub * c.E; }
 }
+// Chunk totals: the cell counts' first, in kCellTotalCopies copies (every capsule adds one
+// to its bucket's chunk; the copies spread those adds over more addresses, since adds to
+// one address from the whole chip queue behind each other), the candidate counts' after them.
+constexpr int kCellTotalCopies = 32;
+__host__ __device__ __forceinline__ int cell_chunks(int T) { return (T + 1023) / 1024; }
+__host__ __device__ __forceinline__ int chunk_total_words(int T, int E) {
+  return kCellTotalCopies * cell_chunks(T) + (kSearchSub * E + 1023) / 1024;
+}
+__device__ __forceinline__ int32_t* chunk_totals(const ContactDev& c, int which) {
+  return which == 0 ? c.bsum : c.bsum + kCellTotalCopies * cell_chunks(c.T);
+}
 
 template <int WHICH>
-__global__ void __launch_bounds__(256) scan_block_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
-  __shared__ int32_t sh[256];
+__global__ void __launch_bounds__(256) scan_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
+  __shared__ int32_t s_sum[4], s_pre[4];
   const Blk b = tab[blockIdx.x];
   const ContactDev& c = CD[b.scene];
   const int32_t* in;
   int32_t* out;
   int n;
   scan_arrays<WHICH>(c, in, out, n);
-  const int t = (int)threadIdx.x;
+  const int32_t* tot = chunk_totals(c, WHICH);
+  const int t = (int)threadIdx.x, lane = t & 63, wv = t >> 6;
+  int pre = 0;                          // totals of the chunks before this block's
+  if constexpr (WHICH == 0) {
+    const int nch = cell_chunks(c.T), m = kCellTotalCopies * (b.base >> 10);
+    for (int k = t; k < m; k += 256) pre += tot[(k % kCellTotalCopies) * nch + k / kCellTotalCopies];
+  } else {
+    for (int k = t; k < (b.base >> 10); k += 256) pre += tot[k];
+  }
   const int base = b.base + 4 * t;
   int v[4];
-  int s = 0;
+  int sv = 0;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) { v[k] = (base + k < n) ? in[base + k] : 0; s += v[k]; }
-  sh[t] = s;
-  __syncthreads();
-  for (int o = 1; o < 256; o <<= 1) {
-    const int x = (t >= o) ? sh[t - o] : 0;
-    __syncthreads();
-    sh[t] += x;
-    __syncthreads();
+  for (int k = 0; k < 4; ++k) {
+    v[k] = (base + k < n) ? in[base + k] : 0;
+    sv += v[k];
   }
-  int run = sh[t] - s;
+  int incl = sv;                        // wavefront inclusive scan of the thread sums
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int x = __shfl_up(incl, o);
+    if (lane >= o) incl += x;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) pre += __shfl_xor(pre, o);
+  if (lane == 63) s_sum[wv] = incl;
+  if (lane == 0) s_pre[wv] = pre;
+  __syncthreads();
+  int run = s_pre[0] + s_pre[1] + s_pre[2] + s_pre[3] + incl - sv;
+  for (int k = 0; k < wv; ++k) run += s_sum[k];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     if (base + k < n) out[base + k] = run;
     run += v[k];
   }
-  if (t == 255) c.bsum[b.base / 1024] = sh[255];
-}
-
-// One block per scene: exclusive scan of its block sums; writes the total to out[n].
-template <int WHICH>
-__global__ void __launch_bounds__(1024) scan_sums_kernel(const ContactDev* __restrict__ CD) {
-  __shared__ int32_t sh[1024];
-  __shared__ int32_t carry;
-  const ContactDev& c = CD[blockIdx.x];
-  const int32_t* in;
-  int32_t* out;
-  int n;
-  scan_arrays<WHICH>(c, in, out, n);
-  const int nb = (n + 1023) / 1024;
-  const int t = (int)threadIdx.x;
-  if (t == 0) carry = 0;
-  __syncthreads();
-  for (int base = 0; base < nb; base += 1024) {
-    const int idx = base + t;
-    const int v = (idx < nb) ? c.bsum[idx] : 0;
-    sh[t] = v;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-      const int x = (t >= o) ? sh[t - o] : 0;
-      __syncthreads();
-      sh[t] += x;
-      __syncthreads();
-    }
-    if (idx < nb) c.bsum[idx] = carry + sh[t] - v;
-    __syncthreads();
-    if (t == 1023) carry += sh[1023];
-    __syncthreads();
-  }
-  if (t == 0) out[n] = carry;
-}
-
-template <int WHICH>
-__global__ void __launch_bounds__(256) scan_add_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
-  const Blk b = tab[blockIdx.x];
-  const ContactDev& c = CD[b.scene];
-  const int32_t* in;
-  int32_t* out;
-  int n;
-  scan_arrays<WHICH>(c, in, out, n);
-  const int base = b.base + 4 * (int)threadIdx.x;
-  const int add = c.bsum[b.base / 1024];
-#pragma unroll
-  for (int k = 0; k < 4; ++k)
-    if (base + k < n) out[base + k] += add;
+  if (base < n && n <= base + 4) out[n] = run;   // the thread holding the last item: the total
 }
 
 // ---- detection
@@ -261,6 +242,7 @@ __global__ void __launch_bounds__(256) det_kernel(const Dev<T>* __restrict__ D, 
     if (threadIdx.x == 0) c.dcnt[0] = 0;
     c.walk[threadIdx.x] = 0ull;
   }
+  if (i < chunk_total_words(c.T, c.E)) c.bsum[i] = 0;   // the scans' chunk totals
   for (int k = (int)threadIdx.x; k <= kRadBins; k += 256) {
     sh[k] = 0;
     if (k < kRadBins) shm[k] = 0ull;
@@ -420,6 +402,8 @@ __global__ void __launch_bounds__(256) key_kernel(const ContactDev* __restrict__
   const uint32_t h = bucket_of(K, c.T);
   c.key[i] = (int32_t)h;
   atomicAdd(&c.cell_cnt[h], 1);
+  // the cell scan's chunk total, in the copy of this block
+  atomicAdd(&c.bsum[(blockIdx.x % kCellTotalCopies) * cell_chunks(c.T) + (h >> 10)], 1);
   atomicMin(&c.cgmin[h], c.cap_grp[i]);
   atomicMax(&c.cgmax[h], c.cap_grp[i]);
 }
@@ -647,7 +631,11 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
   }
   __syncthreads();
   if (!EMIT) {
-    if (live) c.pcount[col] = s_cnt[wv][lane];
+    if (live) {
+      const int cnt = s_cnt[wv][lane];
+      c.pcount[col] = cnt;
+      if (cnt) atomicAdd(chunk_totals(c, 1) + (col >> 10), cnt);   // the candidate scan's chunk total
+    }
     return;
   }
   // Sort each capsule's segment by b and store capsule ids (first pill of each capsule).
@@ -1069,7 +1057,7 @@ ContactOffsets contact_layout(size_t start, bool on, int P, int E, int cpc, bool
   const int T = contact_table_size(E);
   const size_t cap = (size_t)cpc * (size_t)E;
   const size_t ts = f64 ? 8 : 4;
-  const int nb = (std::max(std::max(T, kSearchSub * E), P) + 1023) / 1024 + 1;
+  const int nb = chunk_total_words(T, E);   // scan chunk totals
   o.cap_ids = take(4 * (size_t)E);
   o.cap_rod = take(4 * (size_t)E);
   o.cap_grp = take(4 * (size_t)E);
@@ -1180,12 +1168,8 @@ viper_status contact_init(ContactDev& c, char* ws, const ContactOffsets& o, cons
 namespace {
 template <int WHICH>
 hipError_t scan(const BatchDev& b, int tabid, hipStream_t st) {
-  const ContactDev* CD = b.cd;
   if (b.nblk[tabid] > 0)
-    hipLaunchKernelGGL(scan_block_kernel<WHICH>, dim3(b.nblk[tabid]), dim3(256), 0, st, CD, b.tab[tabid]);
-  hipLaunchKernelGGL(scan_sums_kernel<WHICH>, dim3(b.nscenes), dim3(1024), 0, st, CD);
-  if (b.nblk[tabid] > 0)
-    hipLaunchKernelGGL(scan_add_kernel<WHICH>, dim3(b.nblk[tabid]), dim3(256), 0, st, CD, b.tab[tabid]);
+    hipLaunchKernelGGL(scan_kernel<WHICH>, dim3(b.nblk[tabid]), dim3(256), 0, st, b.cd, b.tab[tabid]);
   return hipGetLastError();
 }
 }  // namespace
