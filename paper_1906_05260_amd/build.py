@@ -14,6 +14,10 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
     # packed FP32 VALU ops are kept off on purpose
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # the first kernel arguments arrive in scalar registers at wave start (no load of the
+    # argument block before the first dependent read; the code keeps its own loads for
+    # hardware without the feature)
+    "-mllvm", "-amdgpu-kernarg-preload-count=16",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
 
