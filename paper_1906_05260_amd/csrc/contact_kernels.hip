@@ -346,6 +346,20 @@ __device__ GridLevels grid_levels_wave(const int32_t* h, const unsigned long lon
   return g;
 }
 
+// A block's distinct hash buckets, so that the block adds into each bucket once (capsules of
+// consecutive indices share cells: one muscle's neighbouring rods): open addressing over
+// kBlockSlots slots (at most 256 keys, so every probe sequence ends), cleared by the caller.
+constexpr int kBlockSlots = 512;
+__device__ __forceinline__ int block_slot(int* keys, int h) {
+  int s = h & (kBlockSlots - 1);
+  for (int n = 0; n < kBlockSlots; ++n) {
+    const int prev = atomicCAS(&keys[s], -1, h);
+    if (prev == -1 || prev == h) return s;
+    s = (s + 1) & (kBlockSlots - 1);
+  }
+  return -1;   // not reached: fewer keys than slots
+}
+
 // Cell keys: a capsule in a bin up to the fine bin goes to its fine-grid cell, one up to the
 // cell bin to its coarse-grid cell, a larger one to the oversized list, a non-finite one (or
 // every capsule of a skipped scene) nowhere; the candidate counts of capsules that are not
@@ -353,8 +367,25 @@ __device__ GridLevels grid_levels_wave(const int32_t* h, const unsigned long lon
 __global__ void __launch_bounds__(256) key_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
   __shared__ int s_cb, s_bf;
   __shared__ double s_rc, s_rf;
+  __shared__ int s_key[kBlockSlots], s_cnt[kBlockSlots], s_gmin[kBlockSlots], s_gmax[kBlockSlots];
   const Blk b = tab[blockIdx.x];
   const ContactDev& c = CD[b.scene];
+  for (int k = (int)threadIdx.x; k < kBlockSlots; k += 256) {
+    s_key[k] = -1;
+    s_cnt[k] = 0;
+    s_gmin[k] = 0x7fffffff;
+    s_gmax[k] = -0x7fffffff - 1;
+  }
+  // the capsule's bin and sphere are read before the block waits for its grid levels
+  const int i = b.base + (int)threadIdx.x;
+  const bool mine = i < c.E;
+  const int bin = mine ? c.key[i] : kRadBins;
+  const int grp = mine ? c.cap_grp[i] : 0;
+  double m[3] = {0.0, 0.0, 0.0};
+  if (mine) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) m[k] = c.sph[4 * (size_t)i + k];
+  }
   if (threadIdx.x < 64) {
     const int lane = (int)threadIdx.x;
     const GridLevels g = grid_levels_wave(c.hist, c.binmax, lane);
@@ -379,52 +410,84 @@ __global__ void __launch_bounds__(256) key_kernel(const ContactDev* __restrict__
     }
   }
   __syncthreads();
-  const int i = b.base + (int)threadIdx.x;
-  if (i >= c.E) return;
   const int cb = s_cb, bf = s_bf;
   const double rc = s_rc, rf = s_rf;
-  const int bin = c.key[i];
-  if (!(rc <= c.rlim) || bin == kRadBins) {
-    c.key[i] = -1;
+  if (mine) {
+    if (!(rc <= c.rlim) || bin == kRadBins) {
+      c.key[i] = -1;
 #pragma unroll
-    for (int k = 0; k < kSearchSub; ++k) c.pcount[kSearchSub * (size_t)i + k] = 0;
-    return;
+      for (int k = 0; k < kSearchSub; ++k) c.pcount[kSearchSub * (size_t)i + k] = 0;
+    } else if (bin > cb) {             // oversized: position in the list after the grid's entries
+      c.key[i] = -2 - atomicAdd(&c.dcnt[0], 1);
+    } else {
+      const int level = bin > bf;
+      const double cw = level ? cell_width_of(rc + rf) : cell_width_of(rf);
+      const long long K = pack_key(cell_of(m[0], cw), cell_of(m[1], cw), cell_of(m[2], cw), level);
+      c.pkey[i] = K;
+      const int h = (int)bucket_of(K, c.T);
+      c.key[i] = h;
+      const int sl = block_slot(s_key, h);
+      atomicAdd(&s_cnt[sl], 1);
+      atomicMin(&s_gmin[sl], grp);
+      atomicMax(&s_gmax[sl], grp);
+    }
   }
-  if (bin > cb) {                      // oversized: position in the list after the grid's entries
-    c.key[i] = -2 - atomicAdd(&c.dcnt[0], 1);
-    return;
+  __syncthreads();
+  // one add per distinct bucket of the block: its count, its group range, and the cell scan's
+  // chunk total (in the copy of this block)
+  for (int k = (int)threadIdx.x; k < kBlockSlots; k += 256) {
+    const int h = s_key[k];
+    if (h < 0) continue;
+    atomicAdd(&c.cell_cnt[h], s_cnt[k]);
+    atomicAdd(&c.bsum[(blockIdx.x % kCellTotalCopies) * cell_chunks(c.T) + (h >> 10)], s_cnt[k]);
+    atomicMin(&c.cgmin[h], s_gmin[k]);
+    atomicMax(&c.cgmax[h], s_gmax[k]);
   }
-  const int level = bin > bf;
-  const double cw = level ? cell_width_of(rc + rf) : cell_width_of(rf);
-  const long long K = pack_key(cell_of(c.sph[4 * (size_t)i], cw), cell_of(c.sph[4 * (size_t)i + 1], cw),
-                               cell_of(c.sph[4 * (size_t)i + 2], cw), level);
-  c.pkey[i] = K;
-  const uint32_t h = bucket_of(K, c.T);
-  c.key[i] = (int32_t)h;
-  atomicAdd(&c.cell_cnt[h], 1);
-  // the cell scan's chunk total, in the copy of this block
-  atomicAdd(&c.bsum[(blockIdx.x % kCellTotalCopies) * cell_chunks(c.T) + (h >> 10)], 1);
-  atomicMin(&c.cgmin[h], c.cap_grp[i]);
-  atomicMax(&c.cgmax[h], c.cap_grp[i]);
 }
 
 __global__ void __launch_bounds__(256) bucket_scatter_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
+  __shared__ int s_key[kBlockSlots], s_cnt[kBlockSlots], s_base[kBlockSlots];
   const Blk b = tab[blockIdx.x];
   const ContactDev& c = CD[b.scene];
+  for (int k = (int)threadIdx.x; k < kBlockSlots; k += 256) {
+    s_key[k] = -1;
+    s_cnt[k] = 0;
+  }
   const int i = b.base + (int)threadIdx.x;
-  if (i >= c.E) return;
-  const int h = c.key[i];
-  if (h == -1) return;                 // not placed in this detection
-  // grid capsules go to their bucket, oversized ones after every bucket (cell_start[T] is the
-  // number of grid capsules)
-  const int pos = h >= 0 ? c.cell_start[h] + atomicAdd(&c.cell_cur[h], 1) : c.cell_start[c.T] + (-2 - h);
-  // the capsule's search data goes straight to its slot: sphere, cell key, rod, group
+  const bool mine = i < c.E;
+  const int h = mine ? c.key[i] : -1;
+  // the capsule's search data (sphere, cell key, rod, group) is read while its slot is taken
+  double sp[4] = {0.0, 0.0, 0.0, 0.0};
+  long long K = -1;
+  int rod = 0, grp = 0;
+  if (mine) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sp[k] = c.sph[4 * (size_t)i + k];
+    K = c.pkey[i];
+    rod = c.cap_rod[i];
+    grp = c.cap_grp[i];
+  }
+  __syncthreads();
+  // grid capsules go to their bucket: the block takes one range of each of its buckets (one
+  // global add per distinct bucket) and its capsules are ranked inside it
+  int sl = -1, rank = 0;
+  if (h >= 0) {
+    sl = block_slot(s_key, h);
+    rank = atomicAdd(&s_cnt[sl], 1);
+  }
+  __syncthreads();
+  for (int k = (int)threadIdx.x; k < kBlockSlots; k += 256)
+    if (s_key[k] >= 0) s_base[k] = c.cell_start[s_key[k]] + atomicAdd(&c.cell_cur[s_key[k]], s_cnt[k]);
+  __syncthreads();
+  if (h == -1) return;                 // not placed in this detection (or past the scene's capsules)
+  // oversized capsules go after every bucket (cell_start[T] is the number of grid capsules)
+  const int pos = h >= 0 ? s_base[sl] + rank : c.cell_start[c.T] + (-2 - h);
   c.sorted[pos] = i;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) c.ssph[4 * (size_t)pos + k] = c.sph[4 * (size_t)i + k];
-  c.skey[pos] = h >= 0 ? c.pkey[i] : -1ll;
-  c.srg[2 * (size_t)pos] = c.cap_rod[i];
-  c.srg[2 * (size_t)pos + 1] = c.cap_grp[i];
+  for (int k = 0; k < 4; ++k) c.ssph[4 * (size_t)pos + k] = sp[k];
+  c.skey[pos] = h >= 0 ? K : -1ll;
+  c.srg[2 * (size_t)pos] = rod;
+  c.srg[2 * (size_t)pos + 1] = grp;
 }
 
 
