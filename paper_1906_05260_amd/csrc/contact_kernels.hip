@@ -525,12 +525,20 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
   const int q = wv * kCapsPerWave + lane / kSearchSub, sub = lane % kSearchSub;
   const int nwave = kWaves * ((c.E + kSearchCaps - 1) / kSearchCaps);
   const int jh = blk.base / kCapsPerWave + wv + nwave * (lane / kSearchSub);   // home capsule's bucket position
+  // the home capsule's bucket entry is read before the number of placed capsules is known
+  // (the position clamped into the scene: an unplaced position reads a stale entry, unused)
+  const int jc = min(jh, c.E - 1);
+  const int a0 = c.sorted[jc];
+  const long long K0 = c.skey[jc];
+  const double2 sa01 = ((const double2*)c.ssph)[2 * (size_t)jc], sa23 = ((const double2*)c.ssph)[2 * (size_t)jc + 1];
+  const int2 rg0 = ((const int2*)c.srg)[jc];
   const int ngrid = c.cell_start[c.T];                 // grid capsules; the oversized list follows
   const int nplaced = ngrid + c.dcnt[0];
+  asm volatile("" ::"v"(a0), "v"(K0), "v"(sa01.x), "v"(sa01.y), "v"(sa23.x), "v"(sa23.y), "v"(rg0.x), "v"(rg0.y));
   const bool live = lane < kCapsPerWave * kSearchSub && jh < nplaced;
   int a = 0, have = 0;
   if (live) {
-    a = c.sorted[jh];
+    a = a0;
     if (EMIT) have = c.pcount[kSearchSub * (size_t)a + sub];
   }
   const int col = kSearchSub * a + sub;             // this lane's (capsule, column) slot
@@ -566,10 +574,9 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
     const bool over = jh >= ngrid;
     double sa[4] = {0.0, 0.0, 0.0, 0.0};
     if (live && (!EMIT || have > kStage)) {
-      const long long K = c.skey[jh];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) sa[k] = c.ssph[4 * (size_t)jh + k];
-      ra = c.srg[2 * (size_t)jh]; ga = c.srg[2 * (size_t)jh + 1];
+      const long long K = K0;
+      sa[0] = sa01.x; sa[1] = sa01.y; sa[2] = sa23.x; sa[3] = sa23.y;
+      ra = rg0.x; ga = rg0.y;
       if (!over) {
         const int level = (int)(K >> 62);
         const int x = (int)(K & kM21), y = (int)((K >> 21) & kM21), z = (int)((K >> 42) & kM20);
@@ -637,9 +644,14 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
   if (lane == 63) s_off[wv][64] = incl;
   __syncthreads();
   const int W = s_off[wv][64];
-  // walk length for the detection record: one add per wavefront, spread over kWalkCounters
-  // addresses so that the adds of a scene's wavefronts do not queue on one
-  if (!EMIT && lane == 0 && W > 0) atomicAdd(c.walk + ((blockIdx.x * kWaves + wv) & (kWalkCounters - 1)), (unsigned long long)W);
+  // walk length for the detection record: one add per block, spread over kWalkCounters
+  // addresses so that the adds of a scene's blocks do not queue on one
+  if (!EMIT && threadIdx.x == 0) {
+    unsigned long long wb = 0;
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) wb += (unsigned long long)s_off[k][64];
+    if (wb) atomicAdd(c.walk + (blockIdx.x & (kWalkCounters - 1)), wb);
+  }
   for (int g0 = 0; g0 < W; g0 += 64 * kWalkItems) {
     int own[kWalkItems], jj[kWalkItems], dd[kWalkItems], bb[kWalkItems], rr[kWalkItems], gg[kWalkItems];
     long long kk[kWalkItems];
