@@ -537,15 +537,23 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
   asm volatile("" ::"v"(a0), "v"(K0), "v"(sa01.x), "v"(sa01.y), "v"(sa23.x), "v"(sa23.y), "v"(rg0.x), "v"(rg0.y));
   const bool live = lane < kCapsPerWave * kSearchSub && jh < nplaced;
   int a = 0, have = 0;
+  // emit pass: the capsule's segment bounds and id are read with its column's count
+  int seg0 = 0, seg1 = 0, ida = 0, pcol = 0;
   if (live) {
     a = a0;
-    if (EMIT) have = c.pcount[kSearchSub * (size_t)a + sub];
+    if (EMIT) {
+      have = c.pcount[kSearchSub * (size_t)a + sub];
+      pcol = c.poff[kSearchSub * (size_t)a + sub];
+      seg0 = c.poff[kSearchSub * (size_t)a];
+      seg1 = c.poff[kSearchSub * (size_t)a + kSearchSub];
+      ida = c.cap_ids[a];
+    }
   }
   const int col = kSearchSub * a + sub;             // this lane's (capsule, column) slot
   if (EMIT && live && have <= kStage) {
     // the count pass kept every candidate of this column: copy them
     const int32_t* stg = c.stage + (size_t)kStage * col;
-    const int base = c.poff[col];
+    const int base = pcol;
     for (int k = 0; k < have; ++k)
       if (base + k < c.cap) c.pairs[2 * (size_t)(base + k) + 1] = stg[k];
   }
@@ -624,7 +632,7 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
     sc[0] = js[0]; sc[1] = js[1]; sc[2] = js[2]; sc[3] = js[3];
     sc[4] = ln[0]; sc[5] = ln[0] + ln[1]; sc[6] = ln[0] + ln[1] + ln[2];
     sc[7] = gt; sc[8] = a; sc[9] = ra; sc[10] = ga;
-    sc[11] = EMIT ? (live ? c.poff[col] : 0) : col;
+    sc[11] = EMIT ? pcol : col;
     s_key[wv][lane][0] = k0;
     s_key[wv][lane][1] = k3;
 #pragma unroll
@@ -720,14 +728,13 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
   __syncthreads();                        // every column of the block's capsules has emitted
   int s0 = 0, n = 0;
   if (live) {
-    s0 = min(c.poff[kSearchSub * (size_t)a], c.cap);
-    n = min(c.poff[kSearchSub * (size_t)a + kSearchSub], c.cap) - s0;
+    s0 = min(seg0, c.cap);
+    n = min(seg1, c.cap) - s0;
     if (n <= kSortMax)
       for (int i = sub; i < n; i += kSearchSub) seg[q][i] = c.pairs[2 * (size_t)(s0 + i) + 1];
   }
   __syncthreads();
   if (!live) return;
-  const int ida = c.cap_ids[a];
   if (n <= kSortMax) {
     for (int i = sub; i < n; i += kSearchSub) {
       const int v = seg[q][i];
