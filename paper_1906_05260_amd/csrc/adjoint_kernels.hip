@@ -14,6 +14,7 @@
 // and chained to rest radii and activations on the host.
 
 #include "rod_device.h"
+#include "stage_setup.h"
 
 namespace viper {
 
@@ -864,9 +865,10 @@ __global__ void __launch_bounds__(64) rod_backward_kernel(const Dev<T>* __restri
   int pA, pB;
   const Blk blk = tab[bi >> 2];
   const int wave = blk.base + (bi & 3);
-  const Dev<T>* dp = lane_setup_wave(D, blk, wave, P, pA, pB);
-  if (!dp) return;
-  const Dev<T>& d = *dp;
+  const Dev<T> d = D[blk.scene];
+  asm volatile("" ::"s"(d.gx), "s"(d.gy), "s"(d.gz), "s"(h));
+  stage_setup(d, wave, P, pA, pB);
+  if (wave >= d.W) return;             // wave-uniform: a block past the scene's last wavefront
   const size_t NL = (size_t)d.W * 64;
   const size_t region = ((size_t)iters * kSnapPerIter + kSnapEnd) * NL;
   const size_t lg = (size_t)wave * 64 + (threadIdx.x & 63);

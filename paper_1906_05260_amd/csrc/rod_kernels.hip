@@ -23,6 +23,7 @@
 //      J_q1 = -J_q0 = (s1 c / 2)(r_w I - [r_v]x) R0^T, solved as a symmetric 3x3 in frame 0.
 
 #include "rod_device.h"
+#include "stage_setup.h"
 
 namespace viper {
 
@@ -55,33 +56,6 @@ __global__ void __launch_bounds__(256) rod_frame_kernel(const Dev<T>* __restrict
   store_state(d, P.B, pB);
   check_finite(d, P.A);
   check_finite(d, P.B);
-}
-
-// The per-stage kernels run one wavefront per block (block b: wavefront tab[b / 4].base +
-// b % 4), so that a scene of a few hundred wavefronts spreads over every compute unit.  A
-// launch of a contact substep is mostly the chain of dependent reads a wavefront waits for
-// before its work, so their start is laid out for few round trips to memory: the caller
-// copies the scene's fields into registers in one go (they sit behind the block table) and
-// names the scalars it reads later in an empty statement, so that they come with them; the
-// start has no branch (a wavefront past the scene's last reads that wave's range and gets no
-// valid slot); the slot flags are read unconditionally (an empty slot reads its wave's first
-// pill, which exists), and the per-pill reads that follow depend on the wave's range only.
-template <class T>
-__device__ __forceinline__ void stage_setup(const Dev<T>& d, const Blk b, Lane2<T>& P, int& pA, int& pB) {
-  const int wave = b.base + (int)(blockIdx.x & 3);
-  const bool live = wave < d.W;        // a dead wavefront (last block of a scene) gets no valid slot
-  const int w = live ? wave : d.W - 1;
-  const int lane = (int)(threadIdx.x & 63);
-  const int p0 = d.wave_start[w];
-  const int n = live ? d.wave_start[w + 1] - p0 : 0;
-  const bool vA = 2 * lane < n, vB = 2 * lane + 1 < n;
-  pA = p0 + (vA ? 2 * lane : 0);
-  pB = p0 + (vB ? 2 * lane + 1 : 0);
-  const uint32_t fA = d.flags[pA], fB = d.flags[pB];
-  P.A.f = vA ? fA : 0u;
-  P.B.f = vB ? fB : 0u;
-  P.sb = __any(((P.A.f | P.B.f) & F_SB) != 0u) != 0;
-  P.vb = __any(((P.A.f | P.B.f) & F_VB) != 0u) != 0;
 }
 
 // The previous contact pass's averaged corrections for both slots of a lane (the
@@ -142,7 +116,7 @@ __global__ void __launch_bounds__(256) predict_kernel(const Dev<T>* __restrict__
   const Blk b = tab[blockIdx.x >> 2];
   const Dev<T> d = D[b.scene];
   asm volatile("" ::"s"(d.gx), "s"(d.gy), "s"(d.gz), "s"(h));
-  stage_setup(d, b, P, pA, pB);
+  stage_setup(d, b.base + (int)(blockIdx.x & 3), P, pA, pB);
   load_state(d, P.A, pA);
   load_state(d, P.B, pB);
   P.A.w = d.winv[pA]; P.A.inert = d.inert[pA];
@@ -287,7 +261,7 @@ __global__ void __launch_bounds__(256) rod_iteration_kernel(const Dev<T>* __rest
   // the scalars read after the state are requested with the pointers (an empty statement
   // that takes them as operands), not in a round trip of their own later
   asm volatile("" ::"s"(d.floor_on), "s"(d.jacobi), "s"(h));
-  stage_setup(d, b, P, pA, pB);
+  stage_setup(d, b.base + (int)(blockIdx.x & 3), P, pA, pB);
   load_iter<T, X>(d, P.A, pA);
   load_iter<T, X>(d, P.B, pB);
   load_lane_consts<T, X>(d, P, pA, pB, rcp(h * h));
@@ -341,7 +315,7 @@ __global__ void __launch_bounds__(256) velocity_kernel(const Dev<T>* __restrict_
     acc = CD[b.scene].acc;
   }
   asm volatile("" ::"s"(h));
-  stage_setup(d, b, P, pA, pB);
+  stage_setup(d, b.base + (int)(blockIdx.x & 3), P, pA, pB);
   velocity_load(d, P.A, pA);
   velocity_load(d, P.B, pB);
   int moved = 0;
