@@ -360,10 +360,11 @@ def contact_skin_timing(torch, viper, scenes, dev, frames=10):
             "contact_pairs_last_substep": int(len(sc.contacts())), "frame_ms": frame_ms,
             "frame_ms_eager_launches": eager_ms, "frame_ms_wall_graph": wall_graph,
             "pill_substeps_per_s": desc.num_pills * sub / (frame_ms * 1e-3),
-            # per substep: prediction and velocity, 7 detection launches (detection start, cell
-            # keys, cell scan, bucket scatter, count pass, candidate scan, emit pass), and a rod
-            # iteration and a contact pass per iteration
-            "launches_per_frame": sub * (2 + 7 + 2 * iters),
+            # per substep: the velocity update (which predicts the next substep), 7 detection
+            # launches (detection start, cell keys, cell scan, bucket scatter, count pass,
+            # candidate scan, emit pass), and a rod iteration and a contact pass per iteration;
+            # one prediction for the first substep
+            "launches_per_frame": 1 + sub * (1 + 7 + 2 * iters),
             "skin_vertices": V, "skin_ms": skin_ms, "skin_weights_ms": weights_ms,
             "skin_algorithmic_GB_per_s": skin_bytes / (skin_ms * 1e-3) / 1e9,
             "skin_large": {"vertices": VL, "ms": skin_l_ms, "algorithmic_bytes": skin_l_bytes,

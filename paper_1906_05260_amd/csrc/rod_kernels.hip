@@ -300,8 +300,11 @@ __device__ __forceinline__ void velocity_store(const Dev<T>& d, Slot<T>& L, int 
   check_finite(d, L);
 }
 
-// C: the scenes have contacts, whose last pass's corrections are applied first.
-template <class T, bool C>
+// C: the scenes have contacts, whose last pass's corrections are applied first.  NEXT: the
+// next substep's prediction follows in the same launch, from the state in registers (the
+// values the prediction stage would read back: positions, scales and rotations as stored,
+// the velocities just formed).
+template <class T, bool C, bool NEXT>
 __global__ void __launch_bounds__(256) velocity_kernel(const Dev<T>* __restrict__ D, const Blk* __restrict__ tab, T h,
                                                        const ContactDev* __restrict__ CD) {
   Lane2<T> P;
@@ -314,15 +317,29 @@ __global__ void __launch_bounds__(256) velocity_kernel(const Dev<T>* __restrict_
     acnt = CD[b.scene].acnt;
     acc = CD[b.scene].acc;
   }
-  asm volatile("" ::"s"(h));
+  if constexpr (NEXT) asm volatile("" ::"s"(h), "s"(d.gx), "s"(d.gy), "s"(d.gz));
+  else asm volatile("" ::"s"(h));
   stage_setup(d, b.base + (int)(blockIdx.x & 3), P, pA, pB);
   velocity_load(d, P.A, pA);
   velocity_load(d, P.B, pB);
+  if constexpr (NEXT) {
+    P.A.inert = d.inert[pA];
+    P.B.inert = d.inert[pB];
+  }
   int moved = 0;
   if constexpr (C) moved = contact_apply_lane(acnt, acc, P, pA, pB);
   const T ih = T(1) / h;
   velocity_store(d, P.A, pA, ih, (moved & 1) != 0);
   velocity_store(d, P.B, pB, ih, (moved & 2) != 0);
+  if constexpr (NEXT) {
+    // an empty slot's values are left as they are: it stores nothing, and no valid slot
+    // reads it (a slot's inertia takes the next pill only when its own edge exists)
+    predict_slot(P.A, h, d.gx, d.gy, d.gz);
+    predict_slot(P.B, h, d.gx, d.gy, d.gz);
+    inertia_lane(P);
+    store_predicted(d, P.A, pA);
+    store_predicted(d, P.B, pB);
+  }
 }
 
 // Field gather/scatter between the SoA layout and a pill-major array.
@@ -486,14 +503,21 @@ template <class T> hipError_t launch_rod_iteration(const BatchDev& b, double h, 
   }
   return hipGetLastError();
 }
-template <class T> hipError_t launch_velocity(const BatchDev& b, double h, const ContactDev* cd, hipStream_t st) {
+template <class T, bool C, bool NEXT>
+void launch_velocity_as(const BatchDev& b, double h, const ContactDev* cd, hipStream_t st) {
+  hipLaunchKernelGGL((velocity_kernel<T, C, NEXT>), dim3(4 * b.nblk[TB_WAVES]), dim3(64), 0, st, (const Dev<T>*)b.dev,
+                     b.tab[TB_WAVES], (T)h, cd);
+}
+template <class T>
+hipError_t launch_velocity(const BatchDev& b, double h, const ContactDev* cd, bool predict_next, hipStream_t st) {
   if (b.nblk[TB_WAVES] == 0) return hipSuccess;
-  if (cd)
-    hipLaunchKernelGGL((velocity_kernel<T, true>), dim3(4 * b.nblk[TB_WAVES]), dim3(64), 0, st, (const Dev<T>*)b.dev,
-                       b.tab[TB_WAVES], (T)h, cd);
-  else
-    hipLaunchKernelGGL((velocity_kernel<T, false>), dim3(4 * b.nblk[TB_WAVES]), dim3(64), 0, st, (const Dev<T>*)b.dev,
-                       b.tab[TB_WAVES], (T)h, cd);
+  if (cd) {
+    if (predict_next) launch_velocity_as<T, true, true>(b, h, cd, st);
+    else launch_velocity_as<T, true, false>(b, h, cd, st);
+  } else {
+    if (predict_next) launch_velocity_as<T, false, true>(b, h, cd, st);
+    else launch_velocity_as<T, false, false>(b, h, cd, st);
+  }
   return hipGetLastError();
 }
 template <class T> hipError_t launch_gather_field(const Dev<T>& d, int which, T* out, hipStream_t st) {
@@ -519,7 +543,7 @@ template <class T> hipError_t launch_skin(const Dev<T>& d, int V, const float* r
   template hipError_t launch_rod_frame<T>(const BatchDev&, int, double, int, hipStream_t);                   \
   template hipError_t launch_predict<T>(const BatchDev&, double, hipStream_t);                               \
   template hipError_t launch_rod_iteration<T>(const BatchDev&, double, const ContactDev*, hipStream_t);      \
-  template hipError_t launch_velocity<T>(const BatchDev&, double, const ContactDev*, hipStream_t);           \
+  template hipError_t launch_velocity<T>(const BatchDev&, double, const ContactDev*, bool, hipStream_t);           \
   template hipError_t launch_gather_field<T>(const Dev<T>&, int, T*, hipStream_t);                           \
   template hipError_t launch_scatter_field<T>(const Dev<T>&, int, const T*, hipStream_t);                    \
   template hipError_t launch_skin<T>(const Dev<T>&, int, const float*, const int32_t*, const float*, float*, \

@@ -643,7 +643,8 @@ viper_status batch_step(const BatchDev& b, bool collisions, bool iteration_only,
     for (int i = 0; i < sub; ++i) HIP_TRY(launch_rod_frame<T>(b, 1, h, iters, st));
   } else if (mode == VIPER_MODE_ITERATION) {
     for (int i = 0; i < sub; ++i) {
-      HIP_TRY(launch_predict<T>(b, h, st));
+      // the first substep's prediction; the later ones come with the previous velocity update
+      if (i == 0) HIP_TRY(launch_predict<T>(b, h, st));
       if (collisions) HIP_TRY(launch_contact_detect<T>(b, st));
       const ContactDev* cd = collisions ? b.cd : nullptr;
       for (int it = 0; it < iters; ++it) {
@@ -654,7 +655,7 @@ viper_status batch_step(const BatchDev& b, bool collisions, bool iteration_only,
         if (collisions) HIP_TRY(launch_contact_flush<T>(b, st));
         HIP_TRY(launch_bundle<T>(b, st));
       }
-      HIP_TRY(launch_velocity<T>(b, h, cd, st));
+      HIP_TRY(launch_velocity<T>(b, h, cd, i + 1 < sub, st));
     }
   } else {
     return fail(VIPER_ERR_INVALID, "unknown mode");

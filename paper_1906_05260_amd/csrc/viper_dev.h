@@ -194,7 +194,10 @@ template <class T> hipError_t launch_predict(const BatchDev& b, double h, hipStr
 // With contacts (cd non-null) the rod iteration and the velocity update first apply each
 // pill's averaged corrections of the preceding contact pass (contact_apply).
 template <class T> hipError_t launch_rod_iteration(const BatchDev& b, double h, const ContactDev* cd, hipStream_t st);
-template <class T> hipError_t launch_velocity(const BatchDev& b, double h, const ContactDev* cd, hipStream_t st);
+// `predict_next`: the same launch then predicts the next substep (of the same step h) from the
+// state it has just formed, in place of a separate launch_predict.
+template <class T>
+hipError_t launch_velocity(const BatchDev& b, double h, const ContactDev* cd, bool predict_next, hipStream_t st);
 template <class T> hipError_t launch_contact_detect(const BatchDev& b, hipStream_t st);
 template <class T> hipError_t launch_contact_project(const BatchDev& b, hipStream_t st);
 // Apply the last contact pass's averaged corrections now (before a bundling projection).
