@@ -100,13 +100,15 @@ __device__ __forceinline__ void world_pos(const Dev<T>& d, int p, double* w) {
   w[2] = an[2] + (double)d.pz[p];
 }
 
-// Bounding sphere of capsule p in FP64: centre = midpoint, radius = half length + larger end radius.
+// Bounding sphere of capsule p in FP64 from the detection copy of the state (world positions and
+// scales of the predicted substep start): centre = midpoint, radius = half length + larger
+// end radius.
 template <class T>
-__device__ void capsule_sphere(const Dev<T>& d, int p, double* out) {
+__device__ void capsule_sphere(const Dev<T>& d, const ContactDev& c, int p, double* out) {
 #pragma clang fp contract(off)
-  double w0[3], w1[3];
-  world_pos(d, p, w0);
-  world_pos(d, p + 1, w1);
+  const double* w0 = c.xdet + 3 * (size_t)p;
+  const double* w1 = w0 + 3;
+  const T* sd = (const T*)c.sdet;
   const double x0 = w0[0], y0 = w0[1], z0 = w0[2];
   const double x1 = w1[0], y1 = w1[1], z1 = w1[2];
   out[0] = 0.5 * (x0 + x1);
@@ -114,8 +116,8 @@ __device__ void capsule_sphere(const Dev<T>& d, int p, double* out) {
   out[2] = 0.5 * (z0 + z1);
   const double dx = x1 - x0, dy = y1 - y0, dz = z1 - z0;
   const double len = __builtin_sqrt((dx * dx + dy * dy) + dz * dz);
-  const double ra = (double)d.s[p] * (double)d.rbar[p];
-  const double rb = (double)d.s[p + 1] * (double)d.rbar[p + 1];
+  const double ra = (double)sd[p] * (double)d.rbar[p];
+  const double rb = (double)sd[p + 1] * (double)d.rbar[p + 1];
   out[3] = 0.5 * len + ((ra < rb) ? rb : ra);
 }
 
@@ -228,9 +230,10 @@ __device__ __forceinline__ int radius_bin(double R) {
 // empty scene, gets a unit cell).
 __device__ __forceinline__ double cell_width_of(double rc) { return rc > 0.0 ? 2.0 * rc * (1.0 + 1e-6) : 1.0; }
 
-// Start of detection, one launch over max(pills, cells, capsules) items of each scene:
-// copy the detection state, reset the hash buckets, form every capsule's bounding sphere
-// and histogram the radii (per block in LDS, then one global add per non-empty bin).
+// Start of detection, one launch over max(pills, cells, capsules) items of each scene: reset
+// the hash buckets, form every capsule's bounding sphere from the detection copy of the state
+// (written by the prediction) and histogram the radii (per block in LDS, then one global add
+// per non-empty bin).
 template <class T>
 __global__ void __launch_bounds__(256) det_kernel(const Dev<T>* __restrict__ D, const ContactDev* __restrict__ CD,
                                                   const Blk* __restrict__ tab) {
@@ -248,10 +251,6 @@ __global__ void __launch_bounds__(256) det_kernel(const Dev<T>* __restrict__ D, 
     if (k < kRadBins) shm[k] = 0ull;
   }
   __syncthreads();
-  if (i < d.P) {                       // detection state: FP64 world positions, scales
-    world_pos(d, i, c.xdet + 3 * (size_t)i);
-    ((T*)c.sdet)[i] = d.s[i];
-  }
   if (i < c.T) {                       // per-substep hash-bucket counters and group ranges
     c.cell_cnt[i] = 0;
     c.cell_cur[i] = 0;
@@ -260,7 +259,7 @@ __global__ void __launch_bounds__(256) det_kernel(const Dev<T>* __restrict__ D, 
   }
   if (i < c.E) {                       // bounding sphere of each capsule
     double sp[4];
-    capsule_sphere(d, c.cap_ids[i], sp);
+    capsule_sphere(d, c, c.cap_ids[i], sp);
     c.sph[4 * (size_t)i + 0] = sp[0];
     c.sph[4 * (size_t)i + 1] = sp[1];
     c.sph[4 * (size_t)i + 2] = sp[2];
@@ -271,7 +270,7 @@ __global__ void __launch_bounds__(256) det_kernel(const Dev<T>* __restrict__ D, 
     int bin = kRadBins;
     const int p = c.cap_ids[i];
     if (!(isfinite(sp[0]) && isfinite(sp[1]) && isfinite(sp[2]) && isfinite(sp[3]))) c.status[ST_NAN] = 1;
-    else if (d.s[p] > T(0) && d.s[p + 1] > T(0)) bin = radius_bin(sp[3]);
+    else if (((const T*)c.sdet)[p] > T(0) && ((const T*)c.sdet)[p + 1] > T(0)) bin = radius_bin(sp[3]);
     c.key[i] = bin;
     atomicAdd(&sh[bin], 1);
     // largest radius of the bin (a positive double orders as its bit pattern)

@@ -109,23 +109,63 @@ __device__ __forceinline__ void store_predicted(const Dev<T>& d, const Slot<T>& 
   for (int i = 0; i < 12; ++i) d.lam[(size_t)i * d.P + p] = T(0);
 }
 
+// The detection copy of a predicted slot (contact scenes): its FP64 world position (rod anchor
+// + stored position, as the contact pass forms it) and its scale.  The detection reads this
+// copy, not the state, which the substep's first constraint iteration may already have moved.
 template <class T>
-__global__ void __launch_bounds__(256) predict_kernel(const Dev<T>* __restrict__ D, const Blk* __restrict__ tab, T h) {
+__device__ __forceinline__ void det_copy(const Dev<T>& d, double* xdet, T* sdet, const Slot<T>& L, int p, int rod) {
+  if (!(L.f & F_VALID)) return;
+  const double* an = d.anchor + 3 * (size_t)rod;
+  xdet[3 * (size_t)p] = an[0] + (double)L.x0;
+  xdet[3 * (size_t)p + 1] = an[1] + (double)L.x1;
+  xdet[3 * (size_t)p + 2] = an[2] + (double)L.x2;
+  sdet[p] = L.s;
+}
+
+// C: the scenes have contacts (the prediction writes their detection copy).
+template <class T, bool C>
+__global__ void __launch_bounds__(256) predict_kernel(const Dev<T>* __restrict__ D, const Blk* __restrict__ tab, T h,
+                                                      const ContactDev* __restrict__ CD) {
   Lane2<T> P;
   int pA, pB;
   const Blk b = tab[blockIdx.x >> 2];
   const Dev<T> d = D[b.scene];
+  double* xdet = nullptr;
+  T* sdet = nullptr;
+  if constexpr (C) {
+    xdet = CD[b.scene].xdet;
+    sdet = (T*)CD[b.scene].sdet;
+  }
   asm volatile("" ::"s"(d.gx), "s"(d.gy), "s"(d.gz), "s"(h));
   stage_setup(d, b.base + (int)(blockIdx.x & 3), P, pA, pB);
   load_state(d, P.A, pA);
   load_state(d, P.B, pB);
   P.A.w = d.winv[pA]; P.A.inert = d.inert[pA];
   P.B.w = d.winv[pB]; P.B.inert = d.inert[pB];
+  int rA = 0, rB = 0;
+  if constexpr (C) {
+    rA = d.rod_of[pA];
+    rB = d.rod_of[pB];
+  }
   predict_slot(P.A, h, d.gx, d.gy, d.gz);
   predict_slot(P.B, h, d.gx, d.gy, d.gz);
   inertia_lane(P);
   store_predicted(d, P.A, pA);
   store_predicted(d, P.B, pB);
+  if constexpr (C) {
+    det_copy(d, xdet, sdet, P.A, pA, rA);
+    det_copy(d, xdet, sdet, P.B, pB, rB);
+  }
+}
+
+// Substep start without the multipliers' reset (the first iteration that follows in the same
+// launch writes them).
+template <class T>
+__device__ __forceinline__ void store_substep_start(const Dev<T>& d, const Slot<T>& L, int p) {
+  if (!(L.f & F_VALID)) return;
+  d.xpx[p] = L.xp0; d.xpy[p] = L.xp1; d.xpz[p] = L.xp2; d.spv[p] = L.sp;
+  d.qpx[p] = L.qp0; d.qpy[p] = L.qp1; d.qpz[p] = L.qp2; d.qpw[p] = L.qp3;
+  d.i1[p] = L.I1;
 }
 
 // ITERATION mode, stage 2: one constraint iteration (four colour passes) with the
@@ -300,11 +340,14 @@ __device__ __forceinline__ void velocity_store(const Dev<T>& d, Slot<T>& L, int 
   check_finite(d, L);
 }
 
-// C: the scenes have contacts, whose last pass's corrections are applied first.  NEXT: the
-// next substep's prediction follows in the same launch, from the state in registers (the
-// values the prediction stage would read back: positions, scales and rotations as stored,
-// the velocities just formed).
-template <class T, bool C, bool NEXT>
+// C: the scenes have contacts, whose last pass's corrections are applied first.  NEXT: what
+// follows in the same launch, from the state in registers (the values the next stage would
+// read back: positions, scales and rotations as stored, the velocities just formed):
+// 0 nothing; 1 the next substep's prediction; 2 the prediction and that substep's first
+// constraint iteration (X, EVEN as for rod_iteration_kernel), which needs nothing from other
+// wavefronts: a rod lies in one wavefront, and no contact correction is pending before the
+// first iteration (this launch has just applied and cleared the last ones).
+template <class T, bool C, int NEXT, bool X, bool EVEN>
 __global__ void __launch_bounds__(256) velocity_kernel(const Dev<T>* __restrict__ D, const Blk* __restrict__ tab, T h,
                                                        const ContactDev* __restrict__ CD) {
   Lane2<T> P;
@@ -313,32 +356,62 @@ __global__ void __launch_bounds__(256) velocity_kernel(const Dev<T>* __restrict_
   const Dev<T> d = D[b.scene];
   int32_t* acnt = nullptr;
   unsigned long long* acc = nullptr;
+  double* xdet = nullptr;
+  T* sdet = nullptr;
   if constexpr (C) {
     acnt = CD[b.scene].acnt;
     acc = CD[b.scene].acc;
+    xdet = CD[b.scene].xdet;
+    sdet = (T*)CD[b.scene].sdet;
   }
-  if constexpr (NEXT) asm volatile("" ::"s"(h), "s"(d.gx), "s"(d.gy), "s"(d.gz));
+  if constexpr (NEXT == 2) asm volatile("" ::"s"(h), "s"(d.gx), "s"(d.gy), "s"(d.gz), "s"(d.floor_on), "s"(d.jacobi));
+  else if constexpr (NEXT == 1) asm volatile("" ::"s"(h), "s"(d.gx), "s"(d.gy), "s"(d.gz));
   else asm volatile("" ::"s"(h));
   stage_setup(d, b.base + (int)(blockIdx.x & 3), P, pA, pB);
   velocity_load(d, P.A, pA);
   velocity_load(d, P.B, pB);
-  if constexpr (NEXT) {
+  int rA = 0, rB = 0;
+  if constexpr (NEXT > 0) {
     P.A.inert = d.inert[pA];
     P.B.inert = d.inert[pB];
+    if constexpr (C) {
+      rA = d.rod_of[pA];
+      rB = d.rod_of[pB];
+    }
   }
+  if constexpr (NEXT == 2) load_lane_consts<T, X>(d, P, pA, pB, rcp(h * h));
   int moved = 0;
   if constexpr (C) moved = contact_apply_lane(acnt, acc, P, pA, pB);
   const T ih = T(1) / h;
   velocity_store(d, P.A, pA, ih, (moved & 1) != 0);
   velocity_store(d, P.B, pB, ih, (moved & 2) != 0);
-  if constexpr (NEXT) {
+  if constexpr (NEXT > 0) {
     // an empty slot's values are left as they are: it stores nothing, and no valid slot
     // reads it (a slot's inertia takes the next pill only when its own edge exists)
     predict_slot(P.A, h, d.gx, d.gy, d.gz);
     predict_slot(P.B, h, d.gx, d.gy, d.gz);
     inertia_lane(P);
+    if constexpr (C) {
+      det_copy(d, xdet, sdet, P.A, pA, rA);
+      det_copy(d, xdet, sdet, P.B, pB, rB);
+    }
+  }
+  if constexpr (NEXT == 1) {
     store_predicted(d, P.A, pA);
     store_predicted(d, P.B, pB);
+  }
+  if constexpr (NEXT == 2) {
+    store_substep_start(d, P.A, pA);
+    store_substep_start(d, P.B, pB);
+    if (d.floor_on) {   // the half-plane floor, at the start of the iteration
+      if (P.A.f & F_VALID) floor_apply(d, pA, P.A.x0, P.A.x1, P.A.x2, P.A.s);
+      if (P.B.f & F_VALID) floor_apply(d, pB, P.B.x0, P.B.x1, P.B.x2, P.B.s);
+    }
+    P.I1N = dn(P.A.I1);
+    if (d.jacobi) jacobi_lane<T, X>(P);       // wave-uniform: one scene per block
+    else iteration_lane<T, X, EVEN>(P);
+    store_iter<T, X>(d, P.A, pA);
+    store_iter<T, X>(d, P.B, pB);
   }
 }
 
@@ -477,10 +550,14 @@ template <class T> hipError_t launch_rod_frame(const BatchDev& b, int nsub, doub
   }
   return hipGetLastError();
 }
-template <class T> hipError_t launch_predict(const BatchDev& b, double h, hipStream_t st) {
+template <class T> hipError_t launch_predict(const BatchDev& b, double h, const ContactDev* cd, hipStream_t st) {
   if (b.nblk[TB_WAVES] == 0) return hipSuccess;
-  hipLaunchKernelGGL(predict_kernel<T>, dim3(4 * b.nblk[TB_WAVES]), dim3(64), 0, st, (const Dev<T>*)b.dev,
-                     b.tab[TB_WAVES], (T)h);
+  if (cd)
+    hipLaunchKernelGGL((predict_kernel<T, true>), dim3(4 * b.nblk[TB_WAVES]), dim3(64), 0, st, (const Dev<T>*)b.dev,
+                       b.tab[TB_WAVES], (T)h, cd);
+  else
+    hipLaunchKernelGGL((predict_kernel<T, false>), dim3(4 * b.nblk[TB_WAVES]), dim3(64), 0, st, (const Dev<T>*)b.dev,
+                       b.tab[TB_WAVES], (T)h, cd);
   return hipGetLastError();
 }
 template <class T, bool X, bool EVEN>
@@ -503,21 +580,29 @@ template <class T> hipError_t launch_rod_iteration(const BatchDev& b, double h, 
   }
   return hipGetLastError();
 }
-template <class T, bool C, bool NEXT>
+template <class T, bool C, int NEXT, bool X, bool EVEN>
 void launch_velocity_as(const BatchDev& b, double h, const ContactDev* cd, hipStream_t st) {
-  hipLaunchKernelGGL((velocity_kernel<T, C, NEXT>), dim3(4 * b.nblk[TB_WAVES]), dim3(64), 0, st, (const Dev<T>*)b.dev,
-                     b.tab[TB_WAVES], (T)h, cd);
+  hipLaunchKernelGGL((velocity_kernel<T, C, NEXT, X, EVEN>), dim3(4 * b.nblk[TB_WAVES]), dim3(64), 0, st,
+                     (const Dev<T>*)b.dev, b.tab[TB_WAVES], (T)h, cd);
+}
+template <class T, bool C>
+void launch_velocity_c(const BatchDev& b, double h, const ContactDev* cd, int next, hipStream_t st) {
+  if (next == 0) launch_velocity_as<T, C, 0, false, false>(b, h, cd, st);
+  else if (next == 1) launch_velocity_as<T, C, 1, false, false>(b, h, cd, st);
+  else if (b.extras) {
+    if (b.even) launch_velocity_as<T, C, 2, true, true>(b, h, cd, st);
+    else launch_velocity_as<T, C, 2, true, false>(b, h, cd, st);
+  } else {
+    if (b.even) launch_velocity_as<T, C, 2, false, true>(b, h, cd, st);
+    else launch_velocity_as<T, C, 2, false, false>(b, h, cd, st);
+  }
 }
 template <class T>
-hipError_t launch_velocity(const BatchDev& b, double h, const ContactDev* cd, bool predict_next, hipStream_t st) {
+hipError_t launch_velocity(const BatchDev& b, double h, const ContactDev* cd, int next, hipStream_t st) {
   if (b.nblk[TB_WAVES] == 0) return hipSuccess;
-  if (cd) {
-    if (predict_next) launch_velocity_as<T, true, true>(b, h, cd, st);
-    else launch_velocity_as<T, true, false>(b, h, cd, st);
-  } else {
-    if (predict_next) launch_velocity_as<T, false, true>(b, h, cd, st);
-    else launch_velocity_as<T, false, false>(b, h, cd, st);
-  }
+  if (next < 0 || next > 2) return hipErrorInvalidValue;
+  if (cd) launch_velocity_c<T, true>(b, h, cd, next, st);
+  else launch_velocity_c<T, false>(b, h, cd, next, st);
   return hipGetLastError();
 }
 template <class T> hipError_t launch_gather_field(const Dev<T>& d, int which, T* out, hipStream_t st) {
@@ -541,9 +626,9 @@ template <class T> hipError_t launch_skin(const Dev<T>& d, int V, const float* r
 
 #define VIPER_INST(T)                                                                                         \
   template hipError_t launch_rod_frame<T>(const BatchDev&, int, double, int, hipStream_t);                   \
-  template hipError_t launch_predict<T>(const BatchDev&, double, hipStream_t);                               \
+  template hipError_t launch_predict<T>(const BatchDev&, double, const ContactDev*, hipStream_t);            \
   template hipError_t launch_rod_iteration<T>(const BatchDev&, double, const ContactDev*, hipStream_t);      \
-  template hipError_t launch_velocity<T>(const BatchDev&, double, const ContactDev*, bool, hipStream_t);           \
+  template hipError_t launch_velocity<T>(const BatchDev&, double, const ContactDev*, int, hipStream_t);           \
   template hipError_t launch_gather_field<T>(const Dev<T>&, int, T*, hipStream_t);                           \
   template hipError_t launch_scatter_field<T>(const Dev<T>&, int, const T*, hipStream_t);                    \
   template hipError_t launch_skin<T>(const Dev<T>&, int, const float*, const int32_t*, const float*, float*, \

@@ -642,20 +642,21 @@ viper_status batch_step(const BatchDev& b, bool collisions, bool iteration_only,
   } else if (mode == VIPER_MODE_SUBSTEP) {
     for (int i = 0; i < sub; ++i) HIP_TRY(launch_rod_frame<T>(b, 1, h, iters, st));
   } else if (mode == VIPER_MODE_ITERATION) {
+    const ContactDev* cd = collisions ? b.cd : nullptr;
     for (int i = 0; i < sub; ++i) {
-      // the first substep's prediction; the later ones come with the previous velocity update
-      if (i == 0) HIP_TRY(launch_predict<T>(b, h, st));
+      // the first substep's prediction; a later substep's prediction and first iteration come
+      // with the previous substep's velocity update
+      if (i == 0) HIP_TRY(launch_predict<T>(b, h, cd, st));
       if (collisions) HIP_TRY(launch_contact_detect<T>(b, st));
-      const ContactDev* cd = collisions ? b.cd : nullptr;
       for (int it = 0; it < iters; ++it) {
-        HIP_TRY(launch_rod_iteration<T>(b, h, cd, st));
+        if (i == 0 || it > 0) HIP_TRY(launch_rod_iteration<T>(b, h, cd, st));
         if (collisions) HIP_TRY(launch_contact_project<T>(b, st));
       }
       if (bundled) {      // shape matching of the cross-sections (Sec. 7.3) after the iterations
         if (collisions) HIP_TRY(launch_contact_flush<T>(b, st));
         HIP_TRY(launch_bundle<T>(b, st));
       }
-      HIP_TRY(launch_velocity<T>(b, h, cd, i + 1 < sub, st));
+      HIP_TRY(launch_velocity<T>(b, h, cd, i + 1 < sub ? (iters > 0 ? 2 : 1) : 0, st));
     }
   } else {
     return fail(VIPER_ERR_INVALID, "unknown mode");

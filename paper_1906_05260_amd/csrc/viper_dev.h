@@ -190,14 +190,17 @@ struct BatchDev {
 
 // Launchers over a batch (enqueue on `stream`, return hipError_t of the launches).
 template <class T> hipError_t launch_rod_frame(const BatchDev& b, int nsub, double h, int iters, hipStream_t st);
-template <class T> hipError_t launch_predict(const BatchDev& b, double h, hipStream_t st);
+// With contacts (cd non-null) the prediction also writes the detection copy of the state.
+template <class T> hipError_t launch_predict(const BatchDev& b, double h, const ContactDev* cd, hipStream_t st);
 // With contacts (cd non-null) the rod iteration and the velocity update first apply each
 // pill's averaged corrections of the preceding contact pass (contact_apply).
 template <class T> hipError_t launch_rod_iteration(const BatchDev& b, double h, const ContactDev* cd, hipStream_t st);
-// `predict_next`: the same launch then predicts the next substep (of the same step h) from the
-// state it has just formed, in place of a separate launch_predict.
+// `next`: what the same launch does after the velocity update, from the state it has just
+// formed: 0 nothing, 1 the next substep's prediction (of the same step h, in place of a
+// separate launch_predict), 2 that prediction and the next substep's first iteration (in
+// place of its first launch_rod_iteration).
 template <class T>
-hipError_t launch_velocity(const BatchDev& b, double h, const ContactDev* cd, bool predict_next, hipStream_t st);
+hipError_t launch_velocity(const BatchDev& b, double h, const ContactDev* cd, int next, hipStream_t st);
 template <class T> hipError_t launch_contact_detect(const BatchDev& b, hipStream_t st);
 template <class T> hipError_t launch_contact_project(const BatchDev& b, hipStream_t st);
 // Apply the last contact pass's averaged corrections now (before a bundling projection).
