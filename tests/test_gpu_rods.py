@@ -379,6 +379,48 @@ def test_modes_agree():
         assert np.array_equal(res[2][k], res[3][k]), k
 
 
+# rounding-level bounds between two launch sequences of the same arithmetic (a field's
+# derivative-like rates carry the 1/h of the substep)
+SEQ_TOL = {"f32": {"x": 1e-6, "s": 1e-6, "q": 1e-5, "v": 1e-3, "sd": 1e-3, "om": 1e-3},
+           "f64": {"x": 1e-14, "s": 1e-14, "q": 1e-13, "v": 1e-11, "sd": 1e-11, "om": 1e-11}}
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("kind", ["helix", "muscles"])
+@pytest.mark.parametrize("iters", [0, 3])
+def test_substeps_in_one_step_equal_single_substep_steps(prec, kind, iters):
+    """Per-stage launches: a step of 3 substeps, where each velocity update also predicts the
+    next substep (and runs its first iteration when there are iterations) from the state in its
+    registers, against 3 steps of one substep each, launched stage by stage.  The arithmetic is
+    the same; the compiler may round a product into a sum differently once the stages share a
+    kernel, so the two agree to the rounding level (positions and scales exactly when there is
+    no iteration), and with contacts the candidate pairs are the same (the detection reads the
+    predicted copy written by that same launch)."""
+    if kind == "helix":
+        desc = scenes.helix_rods(16, 48, seed=11)
+    else:
+        desc, _ = scenes.muscle_scene(num_muscles=4, seed=12, target_pills=None, mesh_vertices=0)
+    say("case:", kind, prec, "iterations", iters)
+    a = viper.Scene(desc, prec)
+    b = viper.Scene(desc, prec)
+    h = 1 / 60
+    for _ in range(2):
+        a.step(h, 3, iters, mode=viper.MODE_ITERATION)
+        for _ in range(3):
+            b.step(h / 3, 1, iters, mode=viper.MODE_ITERATION)
+    a.sync()
+    b.sync()
+    sa, sb = a.state(), b.state()
+    for k in sa:
+        d = float(np.abs(sa[k] - sb[k]).max())
+        say(k, "max difference", d)
+        assert d <= SEQ_TOL[prec][k], k
+        if iters == 0 and k in ("x", "s"):
+            assert d == 0.0, k
+    if kind == "muscles" and iters == 0:
+        assert np.array_equal(a.contacts(), b.contacts())
+
+
 def test_deterministic_and_state_roundtrip():
     desc = scenes.helix_rods(128, 64, seed=6)
     a = viper.Scene(desc, "f32")
