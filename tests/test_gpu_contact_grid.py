@@ -5,6 +5,9 @@ searched from a list), capsules with larger radii than most go to a coarse grid 
 that shortens the search, capsules whose bounding sphere is not finite are left out, and a
 scene whose cells would exceed 4x its largest rest bounding radius is reported as diverged
 with its detection skipped.  Checked here:
+- seeded clouds of free capsules with mixed bounding radii (small, a few percent several
+  times larger, and some far larger than the rest): whatever split of fine level, coarse
+  level and list the histogram picks, the candidate set equals the oracle's brute force;
 - many moderately stretched capsules (more than the list holds): they form a coarse level,
   the fine cell width stays that of the intact scene, the walk stays below what one grid
   sized by the stretched capsules would examine, and the candidate set equals the oracle's
@@ -128,6 +131,43 @@ def test_many_stretched_capsules_form_a_coarse_level(prec):
     involved = int(np.isin(ref, np.concatenate([moved - 1, moved])).any(1).sum())
     say("pairs", len(got), len(ref), "with the stretched capsules", involved)
     assert involved > 0
+    assert np.array_equal(got, ref)
+    sc.sync()
+
+
+def capsule_cloud(seed, rods=1500):
+    """Free 2-pill rods (one capsule each) in a 0.6 m box: end radii U[2, 7] mm and lengths
+    U[0.5, 1.5] cm, a few percent stretched 2-4x, a handful 10-50 cm long; 6 groups."""
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(-0.3, 0.3, (rods, 3)) + rng.uniform(-5.0, 5.0, 3)
+    L = rng.uniform(0.005, 0.015, rods)
+    L[rng.random(rods) < rng.uniform(0.02, 0.1)] *= rng.uniform(2.0, 4.0)
+    big = rng.integers(0, rods, int(rng.integers(0, 40)))
+    L[big] = rng.uniform(0.1, 0.5, len(big))
+    d = rng.normal(size=(rods, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    x = np.empty((2 * rods, 3))
+    x[0::2] = c - 0.5 * L[:, None] * d
+    x[1::2] = c + 0.5 * L[:, None] * d
+    r = rng.uniform(0.002, 0.007, 2 * rods)
+    return scenes.SceneDesc(np.arange(0, 2 * rods + 1, 2, dtype=np.int32), x, r, np.zeros(2 * rods, np.uint8),
+                            np.ones(rods), np.full((rods, 4), 1e-6), rng.integers(0, 6, rods).astype(np.int32),
+                            collisions=True, name="capsule_cloud")
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_capsule_clouds_with_mixed_radii(prec, seed):
+    desc = capsule_cloud(seed)
+    sc = viper.Scene(desc, prec)
+    sc.step(1e-5, 1, 0)
+    st = sc.contact_stats()
+    say(prec, "seed", seed, st)
+    assert st["skipped"] == 0 and st["excluded"] == 0
+    got = sc.contacts()
+    ref = oracle_pairs(desc, sc)
+    say("pairs", len(got), len(ref))
+    assert len(ref) > 0
     assert np.array_equal(got, ref)
     sc.sync()
 
