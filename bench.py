@@ -360,12 +360,12 @@ def contact_skin_timing(torch, viper, scenes, dev, frames=10):
             "contact_pairs_last_substep": int(len(sc.contacts())), "frame_ms": frame_ms,
             "frame_ms_eager_launches": eager_ms, "frame_ms_wall_graph": wall_graph,
             "pill_substeps_per_s": desc.num_pills * sub / (frame_ms * 1e-3),
-            # per substep: the velocity update (which also predicts the next substep and runs
-            # its first rod iteration), 7 detection launches (detection start, cell keys, cell
+            # per substep: the velocity update (which also predicts the next substep, starts its
+            # detection and runs its first rod iteration), 6 detection launches (cell keys, cell
             # scan, bucket scatter, count pass, candidate scan, emit pass), a contact pass per
             # iteration and a rod iteration per iteration but the first; the first substep's
             # prediction and first rod iteration
-            "launches_per_frame": 2 + sub * (1 + 7 + iters + (iters - 1)),
+            "launches_per_frame": 2 + sub * (1 + 6 + iters + (iters - 1)),
             "skin_vertices": V, "skin_ms": skin_ms, "skin_weights_ms": weights_ms,
             "skin_algorithmic_GB_per_s": skin_bytes / (skin_ms * 1e-3) / 1e9,
             "skin_large": {"vertices": VL, "ms": skin_l_ms, "algorithmic_bytes": skin_l_bytes,

@@ -37,6 +37,7 @@
 // not depend on the order in which pairs arrive and the result is deterministic.
 
 #include "contact.h"
+#include "detect_device.h"
 
 #include <algorithm>
 #include <cmath>
@@ -47,9 +48,8 @@ namespace viper {
 
 namespace {
 
-// Neighbour search: 9 threads per capsule, one per (dz, dy) column of its 27 neighbour
-// cells; 28 capsules (252 threads) per block.
-constexpr int kSearchSub = 9;
+// Neighbour search: kSearchSub = 9 threads per capsule, one per (dz, dy) column of its
+// neighbour cells; 28 capsules (252 threads) per block.
 constexpr int kSearchCaps = 28;
 constexpr int kStage = 4;       // candidates per (capsule, column) kept by the count pass
 constexpr int kSortMax = 64;    // longest per-capsule candidate segment sorted in LDS
@@ -100,27 +100,6 @@ __device__ __forceinline__ void world_pos(const Dev<T>& d, int p, double* w) {
   w[2] = an[2] + (double)d.pz[p];
 }
 
-// Bounding sphere of capsule p in FP64 from the detection copy of the state (world positions and
-// scales of the predicted substep start): centre = midpoint, radius = half length + larger
-// end radius.
-template <class T>
-__device__ void capsule_sphere(const Dev<T>& d, const ContactDev& c, int p, double* out) {
-#pragma clang fp contract(off)
-  const double* w0 = c.xdet + 3 * (size_t)p;
-  const double* w1 = w0 + 3;
-  const T* sd = (const T*)c.sdet;
-  const double x0 = w0[0], y0 = w0[1], z0 = w0[2];
-  const double x1 = w1[0], y1 = w1[1], z1 = w1[2];
-  out[0] = 0.5 * (x0 + x1);
-  out[1] = 0.5 * (y0 + y1);
-  out[2] = 0.5 * (z0 + z1);
-  const double dx = x1 - x0, dy = y1 - y0, dz = z1 - z0;
-  const double len = __builtin_sqrt((dx * dx + dy * dy) + dz * dz);
-  const double ra = (double)sd[p] * (double)d.rbar[p];
-  const double rb = (double)sd[p + 1] * (double)d.rbar[p + 1];
-  out[3] = 0.5 * len + ((ra < rb) ? rb : ra);
-}
-
 __device__ bool spheres_overlap(const double* a, const double* b) {
 #pragma clang fp contract(off)
   const double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
@@ -149,21 +128,13 @@ __device__ __forceinline__ void acc_add(unsigned long long* a, double v) {
 // template parameter: each scan kernel is compiled for one array, so no kernel selects
 // its pointers through a runtime branch.  The kernels that produce the counts also add them
 // into per-chunk totals (a chunk is the 1024 items of one scan block; the totals are cleared
-// by det_kernel), so a scan is one launch with no wait between blocks: block b scans its
+// by the prediction launch), so a scan is one launch with no wait between blocks: block b scans its
 // chunk and adds the totals of the chunks before it.
 template <int WHICH>
 __device__ __forceinline__ void scan_arrays(const ContactDev& c, const int32_t*& in, int32_t*& out, int& n) {
   static_assert(WHICH == 0 || WHICH == 1, "scan array");
   if constexpr (WHICH == 0) { in = c.cell_cnt; out = c.cell_start; n = c.T; }
   else { in = c.pcount; out = c.poff; n = kSearchSub * c.E; }
-}
-// Chunk totals: the cell counts' first, in kCellTotalCopies copies (every capsule adds one
-// to its bucket's chunk; the copies spread those adds over more addresses, since adds to
-// one address from the whole chip queue behind each other), the candidate counts' after them.
-constexpr int kCellTotalCopies = 32;
-__host__ __device__ __forceinline__ int cell_chunks(int T) { return (T + 1023) / 1024; }
-__host__ __device__ __forceinline__ int chunk_total_words(int T, int E) {
-  return kCellTotalCopies * cell_chunks(T) + (kSearchSub * E + 1023) / 1024;
 }
 __device__ __forceinline__ int32_t* chunk_totals(const ContactDev& c, int which) {
   return which == 0 ? c.bsum : c.bsum + kCellTotalCopies * cell_chunks(c.T);
@@ -218,71 +189,9 @@ __global__ void __launch_bounds__(256) scan_kernel(const ContactDev* __restrict_
 
 // ---- detection
 
-// Histogram bin of a bounding radius R (finite, m): 4 bins per octave, bin 96 starts at 1 m,
-// clamped to [0, kRadBins - 1]; bin b holds [2^((b-96)/4), 2^((b-95)/4)).
-__device__ __forceinline__ int radius_bin(double R) {
-  if (!(R > 0x1p-24)) return 0;
-  const double f = floor(4.0 * log2(R)) + 96.0;
-  return f < 0.0 ? 0 : (f > kRadBins - 1 ? kRadBins - 1 : (int)f);
-}
-
 // Cell width for cell radius rc (> every grid capsule's bounding radius; a zero radius, an
 // empty scene, gets a unit cell).
 __device__ __forceinline__ double cell_width_of(double rc) { return rc > 0.0 ? 2.0 * rc * (1.0 + 1e-6) : 1.0; }
-
-// Start of detection, one launch over max(pills, cells, capsules) items of each scene: reset
-// the hash buckets, form every capsule's bounding sphere from the detection copy of the state
-// (written by the prediction) and histogram the radii (per block in LDS, then one global add
-// per non-empty bin).
-template <class T>
-__global__ void __launch_bounds__(256) det_kernel(const Dev<T>* __restrict__ D, const ContactDev* __restrict__ CD,
-                                                  const Blk* __restrict__ tab) {
-  __shared__ int sh[kRadBins + 1];
-  __shared__ unsigned long long shm[kRadBins];
-  BLOCK_SCENE(tab, D, CD)
-  const int i = blk_.base + (int)threadIdx.x;
-  if (blk_.base == 0 && threadIdx.x < kWalkCounters) {   // counters of this detection (last read by the previous one)
-    if (threadIdx.x == 0) c.dcnt[0] = 0;
-    c.walk[threadIdx.x] = 0ull;
-  }
-  if (i < chunk_total_words(c.T, c.E)) c.bsum[i] = 0;   // the scans' chunk totals
-  for (int k = (int)threadIdx.x; k <= kRadBins; k += 256) {
-    sh[k] = 0;
-    if (k < kRadBins) shm[k] = 0ull;
-  }
-  __syncthreads();
-  if (i < c.T) {                       // per-substep hash-bucket counters and group ranges
-    c.cell_cnt[i] = 0;
-    c.cell_cur[i] = 0;
-    c.cgmin[i] = 0x7fffffff;
-    c.cgmax[i] = -0x7fffffff - 1;
-  }
-  if (i < c.E) {                       // bounding sphere of each capsule
-    double sp[4];
-    capsule_sphere(d, c, c.cap_ids[i], sp);
-    c.sph[4 * (size_t)i + 0] = sp[0];
-    c.sph[4 * (size_t)i + 1] = sp[1];
-    c.sph[4 * (size_t)i + 2] = sp[2];
-    c.sph[4 * (size_t)i + 3] = sp[3];
-    // left out of this detection: a sphere that is not finite (non-finite state, reported),
-    // or an end radius s r that is not positive (a capsule without surface while a scale
-    // passes through zero: no contact, as in the oracle's candidate set)
-    int bin = kRadBins;
-    const int p = c.cap_ids[i];
-    if (!(isfinite(sp[0]) && isfinite(sp[1]) && isfinite(sp[2]) && isfinite(sp[3]))) c.status[ST_NAN] = 1;
-    else if (((const T*)c.sdet)[p] > T(0) && ((const T*)c.sdet)[p + 1] > T(0)) bin = radius_bin(sp[3]);
-    c.key[i] = bin;
-    atomicAdd(&sh[bin], 1);
-    // largest radius of the bin (a positive double orders as its bit pattern)
-    if (bin < kRadBins) atomicMax(&shm[bin], (unsigned long long)__double_as_longlong(fmax(sp[3], 0.0)));
-  }
-  __syncthreads();
-  for (int k = (int)threadIdx.x; k <= kRadBins; k += 256)
-    if (sh[k]) {
-      atomicAdd(&c.hist[k], sh[k]);
-      if (k < kRadBins) atomicMax(&c.binmax[k], shm[k]);
-    }
-}
 
 // Grid levels from the histogram, by the first wavefront (64 lanes, two bins each).
 // The cell bin cb holds the (kOversized+1)-th largest radius: the highest bin whose suffix
@@ -301,8 +210,16 @@ struct GridLevels {
 };
 __device__ GridLevels grid_levels_wave(const int32_t* h, const unsigned long long* bm, int lane) {
   static_assert(kRadBins == 128, "two bins per lane");
-  const int h0 = h[2 * lane], h1 = h[2 * lane + 1];
-  const double m0 = __longlong_as_double((long long)bm[2 * lane]), m1 = __longlong_as_double((long long)bm[2 * lane + 1]);
+  int h0 = 0, h1 = 0;                   // the histogram's copies summed
+  unsigned long long b0 = 0ull, b1 = 0ull;
+#pragma unroll
+  for (int k = 0; k < kHistCopies; ++k) {
+    h0 += h[k * (kRadBins + 1) + 2 * lane];
+    h1 += h[k * (kRadBins + 1) + 2 * lane + 1];
+    b0 = max(b0, bm[k * kRadBins + 2 * lane]);
+    b1 = max(b1, bm[k * kRadBins + 2 * lane + 1]);
+  }
+  const double m0 = __longlong_as_double((long long)b0), m1 = __longlong_as_double((long long)b1);
   int t = h0 + h1;                      // suffix sum over lanes >= this one
   int p = h0 + h1;                      // prefix sum over lanes <= this one
 #pragma unroll
@@ -398,7 +315,10 @@ __global__ void __launch_bounds__(256) key_kernel(const ContactDev* __restrict__
         const bool skip = !(rc <= c.rlim);
         const bool two = !skip && g.bf < g.cb;
         c.dcnt[1] = skip;
-        c.dcnt[2] = c.hist[kRadBins];
+        int excl = 0;
+#pragma unroll
+        for (int k = 0; k < kHistCopies; ++k) excl += c.hist[k * (kRadBins + 1) + kRadBins];
+        c.dcnt[2] = excl;
         c.dcnt[3] = g.bf;
         c.dcnt[4] = two ? g.cb : -1;
         c.dcnt[5] = two ? g.ncoarse : 0;
@@ -511,9 +431,9 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
       c.npairs[0] = min(total, c.cap);
       if (total > c.cap) c.status[ST_OVERFLOW] = 1;
     }
-    for (int k = (int)threadIdx.x; k <= kRadBins; k += 256) {
+    for (int k = (int)threadIdx.x; k < kHistCopies * (kRadBins + 1); k += 256) {
       c.hist[k] = 0;
-      if (k < kRadBins) c.binmax[k] = 0ull;
+      if (k < kHistCopies * kRadBins) c.binmax[k] = 0ull;
     }
   }
   // Each wavefront holds 7 whole capsules x 9 columns (lane 63 idles): a capsule's columns
@@ -1143,8 +1063,8 @@ ContactOffsets contact_layout(size_t start, bool on, int P, int E, int cpc, bool
   o.cap_rod = take(4 * (size_t)E);
   o.cap_grp = take(4 * (size_t)E);
   o.sph = take(8 * 4 * (size_t)E);
-  o.hist = take(4 * (size_t)(kRadBins + 1));
-  o.binmax = take(8 * (size_t)kRadBins);
+  o.hist = take(4 * (size_t)kHistCopies * (kRadBins + 1));
+  o.binmax = take(8 * (size_t)kHistCopies * kRadBins);
   o.dcnt = take(4 * 8);
   o.walk = take(8 * kWalkCounters);
   o.cw = take(8 * 2);
@@ -1236,8 +1156,8 @@ viper_status contact_init(ContactDev& c, char* ws, const ContactOffsets& o, cons
       hipMemcpyAsync(c.cap_rod, rod.data(), 4 * rod.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(c.cap_grp, grp.data(), 4 * grp.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemsetAsync(c.npairs, 0, 4, st) != hipSuccess ||
-      hipMemsetAsync(c.hist, 0, 4 * (size_t)(kRadBins + 1), st) != hipSuccess ||
-      hipMemsetAsync(c.binmax, 0, 8 * (size_t)kRadBins, st) != hipSuccess ||
+      hipMemsetAsync(c.hist, 0, 4 * (size_t)kHistCopies * (kRadBins + 1), st) != hipSuccess ||
+      hipMemsetAsync(c.binmax, 0, 8 * (size_t)kHistCopies * kRadBins, st) != hipSuccess ||
       hipMemsetAsync(c.dcnt, 0, 4 * 8, st) != hipSuccess || hipMemsetAsync(c.walk, 0, 8 * kWalkCounters, st) != hipSuccess ||
       hipMemsetAsync(c.cw, 0, 8 * 2, st) != hipSuccess ||
       hipMemsetAsync(c.acc, 0, 8 * 4 * (size_t)c.P, st) != hipSuccess ||
@@ -1261,7 +1181,9 @@ hipError_t launch_contact_detect(const BatchDev& b, hipStream_t st) {
   const Dev<T>* D = (const Dev<T>*)b.dev;
   const ContactDev* CD = b.cd;
   const dim3 blk(256);
-  hipLaunchKernelGGL(det_kernel<T>, dim3(b.nblk[TB_DET]), blk, 0, st, D, CD, b.tab[TB_DET]);
+  // the detection record of every capsule (sphere, radius bin, histogram) and the resets were
+  // formed by the prediction launch (launch_predict / launch_velocity with a next substep)
+  (void)D;
   hipLaunchKernelGGL(key_kernel, dim3(b.nblk[TB_CAPS]), blk, 0, st, CD, b.tab[TB_CAPS]);
   hipError_t e = scan<0>(b, TB_SCAN_T, st);
   if (e != hipSuccess) return e;

@@ -24,6 +24,7 @@
 
 #include "rod_device.h"
 #include "stage_setup.h"
+#include "detect_device.h"
 
 namespace viper {
 
@@ -109,20 +110,67 @@ __device__ __forceinline__ void store_predicted(const Dev<T>& d, const Slot<T>& 
   for (int i = 0; i < 12; ++i) d.lam[(size_t)i * d.P + p] = T(0);
 }
 
-// The detection copy of a predicted slot (contact scenes): its FP64 world position (rod anchor
-// + stored position, as the contact pass forms it) and its scale.  The detection reads this
-// copy, not the state, which the substep's first constraint iteration may already have moved.
+// Start of a contact detection, by the wavefront that has just predicted its pills (the
+// prediction launch of a contact scene): the detection copy of its state (FP64 world positions
+// -- rod anchor + stored position, as the contact pass forms them -- and scales), which the
+// detection reads instead of the state (the substep's first constraint iteration may already
+// have moved it); the bounding sphere and radius bin of every capsule that starts on one of
+// its pills (a capsule's pills lie in one wavefront: slot A's capsule ends on slot B, slot
+// B's on the next lane's slot A); the wavefront's radius histogram, added into one of
+// kHistCopies copies; and the scene's per-detection resets, shared over its threads.
+// s_hist [kRadBins + 1] and s_hmax [kRadBins] are the block's LDS (one wavefront per block).
 template <class T>
-__device__ __forceinline__ void det_copy(const Dev<T>& d, double* xdet, T* sdet, const Slot<T>& L, int p, int rod) {
-  if (!(L.f & F_VALID)) return;
-  const double* an = d.anchor + 3 * (size_t)rod;
-  xdet[3 * (size_t)p] = an[0] + (double)L.x0;
-  xdet[3 * (size_t)p + 1] = an[1] + (double)L.x1;
-  xdet[3 * (size_t)p + 2] = an[2] + (double)L.x2;
-  sdet[p] = L.s;
+__device__ __forceinline__ void detect_start_wave(const Dev<T>& d, const ContactDev& c, const Lane2<T>& P, int pA, int pB,
+                                                  int rA, int rB, T rbA, T rbB, int wave, int* s_hist,
+                                                  unsigned long long* s_hmax) {
+  const int lane = (int)(threadIdx.x & 63);
+  for (int k = lane; k <= kRadBins; k += 64) {
+    s_hist[k] = 0;
+    if (k < kRadBins) s_hmax[k] = 0ull;
+  }
+  detect_reset(c, wave * 64 + lane, d.W * 64);
+  double wA[3], wB[3];
+  {
+    const double* an = d.anchor + 3 * (size_t)rA;
+    wA[0] = an[0] + (double)P.A.x0; wA[1] = an[1] + (double)P.A.x1; wA[2] = an[2] + (double)P.A.x2;
+    const double* bn = d.anchor + 3 * (size_t)rB;
+    wB[0] = bn[0] + (double)P.B.x0; wB[1] = bn[1] + (double)P.B.x1; wB[2] = bn[2] + (double)P.B.x2;
+  }
+  T* sdet = (T*)c.sdet;
+  if (P.A.f & F_VALID) {
+    c.xdet[3 * (size_t)pA] = wA[0]; c.xdet[3 * (size_t)pA + 1] = wA[1]; c.xdet[3 * (size_t)pA + 2] = wA[2];
+    sdet[pA] = P.A.s;
+  }
+  if (P.B.f & F_VALID) {
+    c.xdet[3 * (size_t)pB] = wB[0]; c.xdet[3 * (size_t)pB + 1] = wB[1]; c.xdet[3 * (size_t)pB + 2] = wB[2];
+    sdet[pB] = P.B.s;
+  }
+  // the next lane's slot A: the far end of slot B's capsule
+  const double wN[3] = {dn(wA[0]), dn(wA[1]), dn(wA[2])};
+  const T sN = dn(P.A.s), rbN = dn(rbA);
+  __syncthreads();   // the block is this wavefront: its histogram is cleared
+  double sp[4];
+  if (P.A.f & F_EDGE) {
+    const int bin = capsule_record(c, pA - rA, wA, wB, P.A.s, P.B.s, rbA, rbB, sp);
+    atomicAdd(&s_hist[bin], 1);
+    if (bin < kRadBins) atomicMax(&s_hmax[bin], (unsigned long long)__double_as_longlong(fmax(sp[3], 0.0)));
+  }
+  if (P.B.f & F_EDGE) {
+    const int bin = capsule_record(c, pB - rB, wB, wN, P.B.s, sN, rbB, rbN, sp);
+    atomicAdd(&s_hist[bin], 1);
+    if (bin < kRadBins) atomicMax(&s_hmax[bin], (unsigned long long)__double_as_longlong(fmax(sp[3], 0.0)));
+  }
+  __syncthreads();
+  int32_t* hist = c.hist + (size_t)(wave & (kHistCopies - 1)) * (kRadBins + 1);
+  unsigned long long* hmax = c.binmax + (size_t)(wave & (kHistCopies - 1)) * kRadBins;
+  for (int k = lane; k <= kRadBins; k += 64)
+    if (s_hist[k]) {
+      atomicAdd(&hist[k], s_hist[k]);
+      if (k < kRadBins) atomicMax(&hmax[k], s_hmax[k]);
+    }
 }
 
-// C: the scenes have contacts (the prediction writes their detection copy).
+// C: the scenes have contacts (the prediction starts their detection).
 template <class T, bool C>
 __global__ void __launch_bounds__(256) predict_kernel(const Dev<T>* __restrict__ D, const Blk* __restrict__ tab, T h,
                                                       const ContactDev* __restrict__ CD) {
@@ -130,32 +178,29 @@ __global__ void __launch_bounds__(256) predict_kernel(const Dev<T>* __restrict__
   int pA, pB;
   const Blk b = tab[blockIdx.x >> 2];
   const Dev<T> d = D[b.scene];
-  double* xdet = nullptr;
-  T* sdet = nullptr;
-  if constexpr (C) {
-    xdet = CD[b.scene].xdet;
-    sdet = (T*)CD[b.scene].sdet;
-  }
+  __shared__ int s_hist[kRadBins + 1];
+  __shared__ unsigned long long s_hmax[kRadBins];
   asm volatile("" ::"s"(d.gx), "s"(d.gy), "s"(d.gz), "s"(h));
-  stage_setup(d, b.base + (int)(blockIdx.x & 3), P, pA, pB);
+  const int wave = b.base + (int)(blockIdx.x & 3);
+  stage_setup(d, wave, P, pA, pB);
   load_state(d, P.A, pA);
   load_state(d, P.B, pB);
   P.A.w = d.winv[pA]; P.A.inert = d.inert[pA];
   P.B.w = d.winv[pB]; P.B.inert = d.inert[pB];
   int rA = 0, rB = 0;
+  T rbA = T(0), rbB = T(0);
   if constexpr (C) {
     rA = d.rod_of[pA];
     rB = d.rod_of[pB];
+    rbA = d.rbar[pA];
+    rbB = d.rbar[pB];
   }
   predict_slot(P.A, h, d.gx, d.gy, d.gz);
   predict_slot(P.B, h, d.gx, d.gy, d.gz);
   inertia_lane(P);
   store_predicted(d, P.A, pA);
   store_predicted(d, P.B, pB);
-  if constexpr (C) {
-    det_copy(d, xdet, sdet, P.A, pA, rA);
-    det_copy(d, xdet, sdet, P.B, pB, rB);
-  }
+  if constexpr (C) detect_start_wave(d, CD[b.scene], P, pA, pB, rA, rB, rbA, rbB, wave, s_hist, s_hmax);
 }
 
 // Substep start without the multipliers' reset (the first iteration that follows in the same
@@ -356,27 +401,29 @@ __global__ void __launch_bounds__(256) velocity_kernel(const Dev<T>* __restrict_
   const Dev<T> d = D[b.scene];
   int32_t* acnt = nullptr;
   unsigned long long* acc = nullptr;
-  double* xdet = nullptr;
-  T* sdet = nullptr;
   if constexpr (C) {
     acnt = CD[b.scene].acnt;
     acc = CD[b.scene].acc;
-    xdet = CD[b.scene].xdet;
-    sdet = (T*)CD[b.scene].sdet;
   }
+  __shared__ int s_hist[kRadBins + 1];
+  __shared__ unsigned long long s_hmax[kRadBins];
   if constexpr (NEXT == 2) asm volatile("" ::"s"(h), "s"(d.gx), "s"(d.gy), "s"(d.gz), "s"(d.floor_on), "s"(d.jacobi));
   else if constexpr (NEXT == 1) asm volatile("" ::"s"(h), "s"(d.gx), "s"(d.gy), "s"(d.gz));
   else asm volatile("" ::"s"(h));
-  stage_setup(d, b.base + (int)(blockIdx.x & 3), P, pA, pB);
+  const int wave = b.base + (int)(blockIdx.x & 3);
+  stage_setup(d, wave, P, pA, pB);
   velocity_load(d, P.A, pA);
   velocity_load(d, P.B, pB);
   int rA = 0, rB = 0;
+  T rbA = T(0), rbB = T(0);
   if constexpr (NEXT > 0) {
     P.A.inert = d.inert[pA];
     P.B.inert = d.inert[pB];
     if constexpr (C) {
       rA = d.rod_of[pA];
       rB = d.rod_of[pB];
+      rbA = d.rbar[pA];
+      rbB = d.rbar[pB];
     }
   }
   if constexpr (NEXT == 2) load_lane_consts<T, X>(d, P, pA, pB, rcp(h * h));
@@ -391,10 +438,7 @@ __global__ void __launch_bounds__(256) velocity_kernel(const Dev<T>* __restrict_
     predict_slot(P.A, h, d.gx, d.gy, d.gz);
     predict_slot(P.B, h, d.gx, d.gy, d.gz);
     inertia_lane(P);
-    if constexpr (C) {
-      det_copy(d, xdet, sdet, P.A, pA, rA);
-      det_copy(d, xdet, sdet, P.B, pB, rB);
-    }
+    if constexpr (C) detect_start_wave(d, CD[b.scene], P, pA, pB, rA, rB, rbA, rbB, wave, s_hist, s_hmax);
   }
   if constexpr (NEXT == 1) {
     store_predicted(d, P.A, pA);
