@@ -50,7 +50,6 @@ namespace {
 
 // Neighbour search: kSearchSub = 9 threads per capsule, one per (dz, dy) column of its
 // neighbour cells; 28 capsules (252 threads) per block.
-constexpr int kSearchCaps = 28;
 constexpr int kStage = 4;       // candidates per (capsule, column) kept by the count pass
 constexpr int kSortMax = 64;    // longest per-capsule candidate segment sorted in LDS
 constexpr int kWalkItems = 4;   // bucket entries per lane whose loads are issued together
@@ -123,41 +122,23 @@ __device__ __forceinline__ void acc_add(unsigned long long* a, double v) {
   const ContactDev& c = (CD)[blk_.scene];       \
   (void)d; (void)c;
 
-// ---- exclusive scans (out[n] = total), 1024 items per block, one array per scene:
-// WHICH = 0: hash-cell counts, 1: candidate counts per (capsule, column).  The selection is a
-// template parameter: each scan kernel is compiled for one array, so no kernel selects
-// its pointers through a runtime branch.  The kernels that produce the counts also add them
-// into per-chunk totals (a chunk is the 1024 items of one scan block; the totals are cleared
-// by the prediction launch), so a scan is one launch with no wait between blocks: block b scans its
-// chunk and adds the totals of the chunks before it.
-template <int WHICH>
-__device__ __forceinline__ void scan_arrays(const ContactDev& c, const int32_t*& in, int32_t*& out, int& n) {
-  static_assert(WHICH == 0 || WHICH == 1, "scan array");
-  if constexpr (WHICH == 0) { in = c.cell_cnt; out = c.cell_start; n = c.T; }
-  else { in = c.pcount; out = c.poff; n = kSearchSub * c.E; }
-}
-__device__ __forceinline__ int32_t* chunk_totals(const ContactDev& c, int which) {
-  return which == 0 ? c.bsum : c.bsum + kCellTotalCopies * cell_chunks(c.T);
-}
-
-template <int WHICH>
+// ---- exclusive scan of the hash-cell counts (cell_start[T] = total), 1024 cells per block.
+// The key kernel that produces the counts also adds them into per-chunk totals (a chunk is the
+// 1024 cells of one scan block; the totals are cleared by the prediction launch), so the scan
+// is one launch with no wait between blocks: block b scans its chunk and adds the totals of
+// the chunks before it.
 __global__ void __launch_bounds__(256) scan_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
   __shared__ int32_t s_sum[4], s_pre[4];
   const Blk b = tab[blockIdx.x];
   const ContactDev& c = CD[b.scene];
-  const int32_t* in;
-  int32_t* out;
-  int n;
-  scan_arrays<WHICH>(c, in, out, n);
-  const int32_t* tot = chunk_totals(c, WHICH);
+  const int32_t* in = c.cell_cnt;
+  int32_t* out = c.cell_start;
+  const int n = c.T;
+  const int32_t* tot = c.bsum;
   const int t = (int)threadIdx.x, lane = t & 63, wv = t >> 6;
   int pre = 0;                          // totals of the chunks before this block's
-  if constexpr (WHICH == 0) {
-    const int nch = cell_chunks(c.T), m = kCellTotalCopies * (b.base >> 10);
-    for (int k = t; k < m; k += 256) pre += tot[(k % kCellTotalCopies) * nch + k / kCellTotalCopies];
-  } else {
-    for (int k = t; k < (b.base >> 10); k += 256) pre += tot[k];
-  }
+  const int nch = cell_chunks(c.T), m = kCellTotalCopies * (b.base >> 10);
+  for (int k = t; k < m; k += 256) pre += tot[(k % kCellTotalCopies) * nch + k / kCellTotalCopies];
   const int base = b.base + 4 * t;
   int v[4];
   int sv = 0;
@@ -334,8 +315,6 @@ __global__ void __launch_bounds__(256) key_kernel(const ContactDev* __restrict__
   if (mine) {
     if (!(rc <= c.rlim) || bin == kRadBins) {
       c.key[i] = -1;
-#pragma unroll
-      for (int k = 0; k < kSearchSub; ++k) c.pcount[kSearchSub * (size_t)i + k] = 0;
     } else if (bin > cb) {             // oversized: position in the list after the grid's entries
       c.key[i] = -2 - atomicAdd(&c.dcnt[0], 1);
     } else {
@@ -409,12 +388,16 @@ __global__ void __launch_bounds__(256) bucket_scatter_kernel(const ContactDev* _
   c.srg[2 * (size_t)pos + 1] = grp;
 }
 
+// The search blocks' candidate totals follow the cell scan's chunk totals.
+__device__ __forceinline__ int32_t* search_totals(const ContactDev& c) { return c.bsum + kCellTotalCopies * cell_chunks(c.T); }
 
 // Count (EMIT = false) or emit (EMIT = true) the candidates that capsule a's walk finds
 // (see the slots below).  Threads follow bucket order, so the lanes of a wave mostly share
 // a home cell and walk the same neighbour entries (their loads coalesce); each of a
-// capsule's 9 threads covers one (dz, dy) column.  Counts are per (capsule, column) so that
-// an exclusive scan gives every thread its output offset.  The count pass keeps a column's
+// capsule's 9 threads covers one (dz, dy) column.  The count pass stores every thread's count
+// (in thread order: coalesced, no atomics) and its block's total; the emit pass takes the
+// totals of the scene's blocks before its own and scans its block's counts, which gives every
+// thread its output offset with no scan launch between the passes.  The count pass keeps a column's
 // first 4 candidates, so the emit pass re-walks only the columns that had more.  After the
 // emit pass the capsule's threads sort the capsule's segment by b and store capsule ids.  A
 // bucket whose entries all share the capsule's collision group (the interior of a muscle)
@@ -424,13 +407,17 @@ template <bool EMIT>
 __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
   const Blk blk = tab[blockIdx.x];
   const ContactDev& c = CD[blk.scene];
+  const int lb = blk.base / kSearchCaps;                  // the block's index in its scene
+  const int slot = 256 * lb + (int)threadIdx.x;           // the thread's count and staging slot
+  // emit pass: the thread's count, and the totals of the scene's blocks before this one
+  int have = 0, pre = 0;
+  if (EMIT) {
+    have = c.pcount[slot];
+    const int32_t* bt = search_totals(c);
+    for (int k = (int)threadIdx.x; k < lb; k += 256) pre += bt[k];
+  }
   if (EMIT && blk.base == 0) {
-    // the scene's pair count and overflow flag; the radius histogram has had its last reader
-    if (threadIdx.x == 0) {
-      const int total = c.poff[kSearchSub * (size_t)c.E];
-      c.npairs[0] = min(total, c.cap);
-      if (total > c.cap) c.status[ST_OVERFLOW] = 1;
-    }
+    // the radius histogram has had its last reader
     for (int k = (int)threadIdx.x; k < kHistCopies * (kRadBins + 1); k += 256) {
       c.hist[k] = 0;
       if (k < kHistCopies * kRadBins) c.binmax[k] = 0ull;
@@ -442,7 +429,7 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
   // crowded cell, adjacent in bucket order, land in different wavefronts.
   const int wv = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
   const int q = wv * kCapsPerWave + lane / kSearchSub, sub = lane % kSearchSub;
-  const int nwave = kWaves * ((c.E + kSearchCaps - 1) / kSearchCaps);
+  const int nwave = kWaves * search_blocks(c.E);
   const int jh = blk.base / kCapsPerWave + wv + nwave * (lane / kSearchSub);   // home capsule's bucket position
   // the home capsule's bucket entry is read before the number of placed capsules is known
   // (the position clamped into the scene: an unplaced position reads a stale entry, unused)
@@ -455,23 +442,43 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
   const int nplaced = ngrid + c.dcnt[0];
   asm volatile("" ::"v"(a0), "v"(K0), "v"(sa01.x), "v"(sa01.y), "v"(sa23.x), "v"(sa23.y), "v"(rg0.x), "v"(rg0.y));
   const bool live = lane < kCapsPerWave * kSearchSub && jh < nplaced;
-  int a = 0, have = 0;
-  // emit pass: the capsule's segment bounds and id are read with its column's count
+  const int a = live ? a0 : 0;
+  // emit pass: the offset of the thread's candidates in the scene's list (the blocks' totals
+  // before this one, then an exclusive scan of the block's counts in thread order) and its
+  // capsule's segment, the offsets of its first column and of the next capsule's (the 9
+  // columns of a capsule are adjacent lanes; lane 63 has no column and closes the last)
+  __shared__ int s_pre[kWaves], s_tot[kWaves];
   int seg0 = 0, seg1 = 0, ida = 0, pcol = 0;
-  if (live) {
-    a = a0;
-    if (EMIT) {
-      have = c.pcount[kSearchSub * (size_t)a + sub];
-      pcol = c.poff[kSearchSub * (size_t)a + sub];
-      seg0 = c.poff[kSearchSub * (size_t)a];
-      seg1 = c.poff[kSearchSub * (size_t)a + kSearchSub];
-      ida = c.cap_ids[a];
+  if (EMIT) {
+    int incl = have;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(incl, o);
+      if (lane >= o) incl += t;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) pre += __shfl_xor(pre, o);
+    if (lane == 63) s_tot[wv] = incl;
+    if (lane == 0) s_pre[wv] = pre;
+    __syncthreads();
+    const int before = s_pre[0] + s_pre[1] + s_pre[2] + s_pre[3];
+    int run = before;
+    for (int k = 0; k < wv; ++k) run += s_tot[k];
+    pcol = run + incl - have;
+    const int first = kSearchSub * (lane / kSearchSub);
+    seg0 = __shfl(pcol, min(first, 63));
+    seg1 = __shfl(pcol, min(first + kSearchSub, 63));
+    if (live) ida = c.cap_ids[a];
+    if (threadIdx.x == 0 && lb == search_blocks(c.E) - 1) {
+      // the scene's pair count and overflow flag
+      const int total = before + s_tot[0] + s_tot[1] + s_tot[2] + s_tot[3];
+      c.npairs[0] = min(total, c.cap);
+      if (total > c.cap) c.status[ST_OVERFLOW] = 1;
     }
   }
-  const int col = kSearchSub * a + sub;             // this lane's (capsule, column) slot
   if (EMIT && live && have <= kStage) {
     // the count pass kept every candidate of this column: copy them
-    const int32_t* stg = c.stage + (size_t)kStage * col;
+    const int32_t* stg = c.stage + (size_t)kStage * slot;
     const int base = pcol;
     for (int k = 0; k < have; ++k)
       if (base + k < c.cap) c.pairs[2 * (size_t)(base + k) + 1] = stg[k];
@@ -551,7 +558,7 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
     sc[0] = js[0]; sc[1] = js[1]; sc[2] = js[2]; sc[3] = js[3];
     sc[4] = ln[0]; sc[5] = ln[0] + ln[1]; sc[6] = ln[0] + ln[1] + ln[2];
     sc[7] = gt; sc[8] = a; sc[9] = ra; sc[10] = ga;
-    sc[11] = EMIT ? pcol : col;
+    sc[11] = EMIT ? pcol : slot;
     s_key[wv][lane][0] = k0;
     s_key[wv][lane][1] = k3;
 #pragma unroll
@@ -633,11 +640,15 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
   }
   __syncthreads();
   if (!EMIT) {
-    if (live) {
-      const int cnt = s_cnt[wv][lane];
-      c.pcount[col] = cnt;
-      if (cnt) atomicAdd(chunk_totals(c, 1) + (col >> 10), cnt);   // the candidate scan's chunk total
-    }
+    // every slot's count (0 without a column) and the block's total, plain stores
+    const int cnt = s_cnt[wv][lane];
+    c.pcount[slot] = cnt;
+    int t = cnt;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+    if (lane == 0) s_tot[wv] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) search_totals(c)[lb] = s_tot[0] + s_tot[1] + s_tot[2] + s_tot[3];
     return;
   }
   // Sort each capsule's segment by b and store capsule ids (first pill of each capsule).
@@ -1058,7 +1069,7 @@ ContactOffsets contact_layout(size_t start, bool on, int P, int E, int cpc, bool
   const int T = contact_table_size(E);
   const size_t cap = (size_t)cpc * (size_t)E;
   const size_t ts = f64 ? 8 : 4;
-  const int nb = chunk_total_words(T, E);   // scan chunk totals
+  const int nb = chunk_total_words(T, E);   // cell scan chunk totals, search block totals
   o.cap_ids = take(4 * (size_t)E);
   o.cap_rod = take(4 * (size_t)E);
   o.cap_grp = take(4 * (size_t)E);
@@ -1076,9 +1087,8 @@ ContactOffsets contact_layout(size_t start, bool on, int P, int E, int cpc, bool
   o.sorted = take(4 * (size_t)E);
   o.cgmin = take(4 * (size_t)T);
   o.cgmax = take(4 * (size_t)T);
-  o.pcount = take(4 * (size_t)kSearchSub * E);
-  o.poff = take(4 * ((size_t)kSearchSub * E + 1));
-  o.stage = take(4 * (size_t)kStage * kSearchSub * E);
+  o.pcount = take(4 * (size_t)256 * search_blocks(E));
+  o.stage = take(4 * (size_t)kStage * 256 * search_blocks(E));
   o.pairs = take(8 * cap);
   o.npairs = take(4);
   o.ssph = take(8 * 4 * (size_t)E);
@@ -1139,7 +1149,6 @@ viper_status contact_init(ContactDev& c, char* ws, const ContactOffsets& o, cons
   c.cgmin = (int32_t*)(ws + o.cgmin);
   c.cgmax = (int32_t*)(ws + o.cgmax);
   c.pcount = (int32_t*)(ws + o.pcount);
-  c.poff = (int32_t*)(ws + o.poff);
   c.stage = (int32_t*)(ws + o.stage);
   c.pairs = (int32_t*)(ws + o.pairs);
   c.npairs = (int32_t*)(ws + o.npairs);
@@ -1166,15 +1175,6 @@ viper_status contact_init(ContactDev& c, char* ws, const ContactOffsets& o, cons
   return VIPER_OK;
 }
 
-namespace {
-template <int WHICH>
-hipError_t scan(const BatchDev& b, int tabid, hipStream_t st) {
-  if (b.nblk[tabid] > 0)
-    hipLaunchKernelGGL(scan_kernel<WHICH>, dim3(b.nblk[tabid]), dim3(256), 0, st, b.cd, b.tab[tabid]);
-  return hipGetLastError();
-}
-}  // namespace
-
 template <class T>
 hipError_t launch_contact_detect(const BatchDev& b, hipStream_t st) {
   if (b.nscenes == 0) return hipSuccess;
@@ -1185,12 +1185,9 @@ hipError_t launch_contact_detect(const BatchDev& b, hipStream_t st) {
   // formed by the prediction launch (launch_predict / launch_velocity with a next substep)
   (void)D;
   hipLaunchKernelGGL(key_kernel, dim3(b.nblk[TB_CAPS]), blk, 0, st, CD, b.tab[TB_CAPS]);
-  hipError_t e = scan<0>(b, TB_SCAN_T, st);
-  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(scan_kernel, dim3(b.nblk[TB_SCAN_T]), blk, 0, st, CD, b.tab[TB_SCAN_T]);
   hipLaunchKernelGGL(bucket_scatter_kernel, dim3(b.nblk[TB_CAPS]), blk, 0, st, CD, b.tab[TB_CAPS]);
   hipLaunchKernelGGL(pair_kernel<false>, dim3(b.nblk[TB_SEARCH]), blk, 0, st, CD, b.tab[TB_SEARCH]);
-  e = scan<1>(b, TB_SCAN_E, st);
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(pair_kernel<true>, dim3(b.nblk[TB_SEARCH]), blk, 0, st, CD, b.tab[TB_SEARCH]);
   return hipGetLastError();
 }

@@ -14,14 +14,18 @@ constexpr int kSearchSub = 9;
 // addresses; its readers sum the copies.
 constexpr int kHistCopies = 8;
 
-// Chunk totals of the scans: the cell counts' first, in kCellTotalCopies copies (every capsule
-// adds one to its bucket's chunk; the copies spread those adds over more addresses, since
-// adds to one address from the whole chip queue behind each other), the candidate counts'
-// after them.  A chunk is the 1024 items of one scan block.
+// Neighbour search blocks: 28 capsules (252 threads of 256) each.
+constexpr int kSearchCaps = 28;
+__host__ __device__ __forceinline__ int search_blocks(int E) { return (E + kSearchCaps - 1) / kSearchCaps; }
+
+// Chunk totals of the cell scan, in kCellTotalCopies copies (every capsule adds one to its
+// bucket's chunk; the copies spread those adds over more addresses, since adds to one address
+// from the whole chip queue behind each other; a chunk is the 1024 items of one scan block),
+// then the candidate total of each search block (a plain store per block).
 constexpr int kCellTotalCopies = 32;
 __host__ __device__ __forceinline__ int cell_chunks(int T) { return (T + 1023) / 1024; }
 __host__ __device__ __forceinline__ int chunk_total_words(int T, int E) {
-  return kCellTotalCopies * cell_chunks(T) + (kSearchSub * E + 1023) / 1024;
+  return kCellTotalCopies * cell_chunks(T) + search_blocks(E);
 }
 
 // Histogram bin of a bounding radius R (finite, m): 4 bins per octave, bin 96 starts at 1 m,
@@ -67,7 +71,7 @@ __device__ __forceinline__ int capsule_record(const ContactDev& c, int i, const 
 }
 
 // The per-detection resets a scene's threads share (thread tid of nth): hash-bucket counts,
-// cursors and group ranges, the scans' chunk totals, the walk record and the oversized count.
+// cursors and group ranges, the cell scan's chunk totals, the walk record and the oversized count.
 __device__ __forceinline__ void detect_reset(const ContactDev& c, int tid, int nth) {
   for (int k = tid; k < c.T; k += nth) {
     c.cell_cnt[k] = 0;
@@ -75,7 +79,7 @@ __device__ __forceinline__ void detect_reset(const ContactDev& c, int tid, int n
     c.cgmin[k] = 0x7fffffff;
     c.cgmax[k] = -0x7fffffff - 1;
   }
-  const int nw = chunk_total_words(c.T, c.E);
+  const int nw = kCellTotalCopies * cell_chunks(c.T);   // the search blocks store their totals
   for (int k = tid; k < nw; k += nth) c.bsum[k] = 0;
   for (int k = tid; k < kWalkCounters; k += nth) c.walk[k] = 0ull;
   if (tid == 0) c.dcnt[0] = 0;

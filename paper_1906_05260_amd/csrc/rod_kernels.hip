@@ -172,17 +172,17 @@ __device__ __forceinline__ void detect_start_wave(const Dev<T>& d, const Contact
 
 // C: the scenes have contacts (the prediction starts their detection).
 template <class T, bool C>
-__global__ void __launch_bounds__(256) predict_kernel(const Dev<T>* __restrict__ D, const Blk* __restrict__ tab, T h,
+__global__ void __launch_bounds__(256) predict_kernel(const Dev<T>* __restrict__ D, const WaveBlk* __restrict__ wtab, T h,
                                                       const ContactDev* __restrict__ CD) {
   Lane2<T> P;
   int pA, pB;
-  const Blk b = tab[blockIdx.x >> 2];
+  const WaveBlk b = wtab[blockIdx.x];
   const Dev<T> d = D[b.scene];
   __shared__ int s_hist[kRadBins + 1];
   __shared__ unsigned long long s_hmax[kRadBins];
   asm volatile("" ::"s"(d.gx), "s"(d.gy), "s"(d.gz), "s"(h));
-  const int wave = b.base + (int)(blockIdx.x & 3);
-  stage_setup(d, wave, P, pA, pB);
+  const int wave = b.wave;
+  stage_setup(d, b, P, pA, pB);
   load_state(d, P.A, pA);
   load_state(d, P.B, pB);
   P.A.w = d.winv[pA]; P.A.inert = d.inert[pA];
@@ -331,11 +331,11 @@ __device__ __forceinline__ void jacobi_lane(Lane2<T>& P) {
 
 // C: the scenes have contacts (CD holds their buffers).
 template <class T, bool X, bool EVEN, bool C>
-__global__ void __launch_bounds__(256) rod_iteration_kernel(const Dev<T>* __restrict__ D, const Blk* __restrict__ tab,
+__global__ void __launch_bounds__(256) rod_iteration_kernel(const Dev<T>* __restrict__ D, const WaveBlk* __restrict__ wtab,
                                                             T h, const ContactDev* __restrict__ CD) {
   Lane2<T> P;
   int pA, pB;
-  const Blk b = tab[blockIdx.x >> 2];
+  const WaveBlk b = wtab[blockIdx.x];
   const Dev<T> d = D[b.scene];
   int32_t* acnt = nullptr;
   unsigned long long* acc = nullptr;
@@ -346,7 +346,7 @@ __global__ void __launch_bounds__(256) rod_iteration_kernel(const Dev<T>* __rest
   // the scalars read after the state are requested with the pointers (an empty statement
   // that takes them as operands), not in a round trip of their own later
   asm volatile("" ::"s"(d.floor_on), "s"(d.jacobi), "s"(h));
-  stage_setup(d, b.base + (int)(blockIdx.x & 3), P, pA, pB);
+  stage_setup(d, b, P, pA, pB);
   load_iter<T, X>(d, P.A, pA);
   load_iter<T, X>(d, P.B, pB);
   load_lane_consts<T, X>(d, P, pA, pB, rcp(h * h));
@@ -393,11 +393,11 @@ __device__ __forceinline__ void velocity_store(const Dev<T>& d, Slot<T>& L, int 
 // wavefronts: a rod lies in one wavefront, and no contact correction is pending before the
 // first iteration (this launch has just applied and cleared the last ones).
 template <class T, bool C, int NEXT, bool X, bool EVEN>
-__global__ void __launch_bounds__(256) velocity_kernel(const Dev<T>* __restrict__ D, const Blk* __restrict__ tab, T h,
+__global__ void __launch_bounds__(256) velocity_kernel(const Dev<T>* __restrict__ D, const WaveBlk* __restrict__ wtab, T h,
                                                        const ContactDev* __restrict__ CD) {
   Lane2<T> P;
   int pA, pB;
-  const Blk b = tab[blockIdx.x >> 2];
+  const WaveBlk b = wtab[blockIdx.x];
   const Dev<T> d = D[b.scene];
   int32_t* acnt = nullptr;
   unsigned long long* acc = nullptr;
@@ -410,8 +410,8 @@ __global__ void __launch_bounds__(256) velocity_kernel(const Dev<T>* __restrict_
   if constexpr (NEXT == 2) asm volatile("" ::"s"(h), "s"(d.gx), "s"(d.gy), "s"(d.gz), "s"(d.floor_on), "s"(d.jacobi));
   else if constexpr (NEXT == 1) asm volatile("" ::"s"(h), "s"(d.gx), "s"(d.gy), "s"(d.gz));
   else asm volatile("" ::"s"(h));
-  const int wave = b.base + (int)(blockIdx.x & 3);
-  stage_setup(d, wave, P, pA, pB);
+  const int wave = b.wave;
+  stage_setup(d, b, P, pA, pB);
   velocity_load(d, P.A, pA);
   velocity_load(d, P.B, pB);
   int rA = 0, rB = 0;
@@ -597,21 +597,21 @@ template <class T> hipError_t launch_rod_frame(const BatchDev& b, int nsub, doub
 template <class T> hipError_t launch_predict(const BatchDev& b, double h, const ContactDev* cd, hipStream_t st) {
   if (b.nblk[TB_WAVES] == 0) return hipSuccess;
   if (cd)
-    hipLaunchKernelGGL((predict_kernel<T, true>), dim3(4 * b.nblk[TB_WAVES]), dim3(64), 0, st, (const Dev<T>*)b.dev,
-                       b.tab[TB_WAVES], (T)h, cd);
+    hipLaunchKernelGGL((predict_kernel<T, true>), dim3(b.nwaves), dim3(64), 0, st, (const Dev<T>*)b.dev, b.wtab, (T)h,
+                       cd);
   else
-    hipLaunchKernelGGL((predict_kernel<T, false>), dim3(4 * b.nblk[TB_WAVES]), dim3(64), 0, st, (const Dev<T>*)b.dev,
-                       b.tab[TB_WAVES], (T)h, cd);
+    hipLaunchKernelGGL((predict_kernel<T, false>), dim3(b.nwaves), dim3(64), 0, st, (const Dev<T>*)b.dev, b.wtab, (T)h,
+                       cd);
   return hipGetLastError();
 }
 template <class T, bool X, bool EVEN>
 void launch_rod_iteration_as(const BatchDev& b, double h, const ContactDev* cd, hipStream_t st) {
   if (cd)
-    hipLaunchKernelGGL((rod_iteration_kernel<T, X, EVEN, true>), dim3(4 * b.nblk[TB_WAVES]), dim3(64), 0, st,
-                       (const Dev<T>*)b.dev, b.tab[TB_WAVES], (T)h, cd);
+    hipLaunchKernelGGL((rod_iteration_kernel<T, X, EVEN, true>), dim3(b.nwaves), dim3(64), 0, st, (const Dev<T>*)b.dev,
+                       b.wtab, (T)h, cd);
   else
-    hipLaunchKernelGGL((rod_iteration_kernel<T, X, EVEN, false>), dim3(4 * b.nblk[TB_WAVES]), dim3(64), 0, st,
-                       (const Dev<T>*)b.dev, b.tab[TB_WAVES], (T)h, cd);
+    hipLaunchKernelGGL((rod_iteration_kernel<T, X, EVEN, false>), dim3(b.nwaves), dim3(64), 0, st, (const Dev<T>*)b.dev,
+                       b.wtab, (T)h, cd);
 }
 template <class T> hipError_t launch_rod_iteration(const BatchDev& b, double h, const ContactDev* cd, hipStream_t st) {
   if (b.nblk[TB_WAVES] == 0) return hipSuccess;
@@ -626,8 +626,8 @@ template <class T> hipError_t launch_rod_iteration(const BatchDev& b, double h, 
 }
 template <class T, bool C, int NEXT, bool X, bool EVEN>
 void launch_velocity_as(const BatchDev& b, double h, const ContactDev* cd, hipStream_t st) {
-  hipLaunchKernelGGL((velocity_kernel<T, C, NEXT, X, EVEN>), dim3(4 * b.nblk[TB_WAVES]), dim3(64), 0, st,
-                     (const Dev<T>*)b.dev, b.tab[TB_WAVES], (T)h, cd);
+  hipLaunchKernelGGL((velocity_kernel<T, C, NEXT, X, EVEN>), dim3(b.nwaves), dim3(64), 0, st, (const Dev<T>*)b.dev, b.wtab,
+                     (T)h, cd);
 }
 template <class T, bool C>
 void launch_velocity_c(const BatchDev& b, double h, const ContactDev* cd, int next, hipStream_t st) {

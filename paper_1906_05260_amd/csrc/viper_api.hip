@@ -218,9 +218,10 @@ int pack_waves(const viper_scene_desc* d, std::vector<int32_t>& ws, bool& even) 
 struct Counts {
   int W = 0, P = 0, E = 0, T = 0, cap = 0, S = 0, N = 0;   // ... bundling sections and entries
   bool contacts = false;
+  const std::vector<int32_t>* wave_start = nullptr;      // [W+1] first pill of each wave (host)
 };
 
-const int kStageItems[TB_COUNT] = {4, 256, 28, 256, 1024, 1024, 256, 4, 256};
+const int kStageItems[TB_COUNT] = {4, 256, 28, 256, 1024, 256, 4, 256};
 
 int stage_items(const Counts& c, int stage) {
   switch (stage) {
@@ -228,7 +229,6 @@ int stage_items(const Counts& c, int stage) {
     case TB_CAPS: return c.contacts ? c.E : 0;
     case TB_SEARCH: return c.contacts ? c.E : 0;
     case TB_PAIRS: return c.contacts ? 2 * pair_span(c.cap) : 0;
-    case TB_SCAN_E: return c.contacts ? 9 * c.E : 0;
     case TB_SCAN_T: return c.contacts ? c.T : 0;
     case TB_DET: return c.contacts ? std::max(c.P, std::max(c.T, c.E)) : 0;
     case TB_SECT: return c.S;
@@ -247,6 +247,9 @@ size_t header_bytes(const std::vector<Counts>& v, size_t dev_size) {
     for (const Counts& c : v) e += (size_t)((stage_items(c, t) + kStageItems[t] - 1) / kStageItems[t]);
     n += align256(e * sizeof(Blk));
   }
+  size_t w = 0;
+  for (const Counts& c : v) w += (size_t)c.W;
+  n += align256(w * sizeof(WaveBlk));
   return n;
 }
 
@@ -271,6 +274,15 @@ void build_header(std::vector<char>& buf, const std::vector<const void*>& devs, 
     b.nblk[t] = (int)tab.size();
     off += align256(tab.size() * sizeof(Blk));
   }
+  std::vector<WaveBlk> wt;
+  for (size_t s = 0; s < v.size(); ++s) {
+    const std::vector<int32_t>& ws = *v[s].wave_start;
+    for (int w = 0; w < v[s].W; ++w) wt.push_back(WaveBlk{(int32_t)s, w, ws[w], ws[w + 1] - ws[w]});
+  }
+  std::memcpy(buf.data() + off, wt.data(), wt.size() * sizeof(WaveBlk));
+  b.wtab = (const WaveBlk*)(dev_base + off);
+  b.nwaves = (int)wt.size();
+  off += align256(wt.size() * sizeof(WaveBlk));
   b.nscenes = (int)v.size();
 }
 
@@ -516,6 +528,7 @@ struct viper_scene_s {
   std::vector<char> header;   // host image of the batch header
   std::vector<Skin> skins;
   std::vector<int32_t> off;  // rod offsets (host copy)
+  std::vector<int32_t> wave_start;   // first pill of each wave (host copy)
   double density = 1000.0;
   // GRAPH mode: one captured frame, valid for (h, substeps, iterations) of its capture
   hipStream_t capture = nullptr;
@@ -717,6 +730,7 @@ Counts scene_counts(const viper_scene_s* S) {
   c.cap = S->collisions ? S->cd.cap : S->cap * S->E;
   c.contacts = S->collisions != 0;
   c.S = S->nsec; c.N = S->nsecp;
+  c.wave_start = &S->wave_start;
   return c;
 }
 
@@ -780,6 +794,7 @@ viper_status viper_create_scene(const viper_scene_desc* desc, void* workspace, s
   S->bytes = bytes;
   S->o = o;
   S->off = H.off;
+  S->wave_start = H.wave_start;
   S->density = desc->density;
   hipStream_t st = (hipStream_t)stream;
   viper_status r;

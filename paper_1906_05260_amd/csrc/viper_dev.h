@@ -102,8 +102,8 @@ struct ContactDev {
   long long* pkey = nullptr;          // [E] cell key (wrapped cell coordinates and grid level)
   int32_t *cell_cnt = nullptr, *cell_start = nullptr, *cell_cur = nullptr, *sorted = nullptr;
   int32_t *cgmin = nullptr, *cgmax = nullptr;  // [T] smallest / largest group id in each bucket
-  int32_t *pcount = nullptr, *poff = nullptr;  // [9E], [9E+1] candidates per (capsule, column)
-  int32_t* stage = nullptr;           // [9E*4] first candidates of each (capsule, column)
+  int32_t* pcount = nullptr;          // [256 search_blocks(E)] candidates per search thread (capsule column)
+  int32_t* stage = nullptr;           // [4 * 256 search_blocks(E)] first candidates of each search thread
   int32_t *pairs = nullptr, *npairs = nullptr;
   double* ssph = nullptr;             // [E*4] spheres in bucket (cell) order
   long long* skey = nullptr;          // [E] cell keys in bucket order (-1: oversized list)
@@ -112,7 +112,7 @@ struct ContactDev {
   int32_t* acnt = nullptr;            // [P] active contacts per pill this pass
   double* xdet = nullptr;             // [3P] FP64 world positions at detection
   void* sdet = nullptr;               // [P] scales at detection (scene precision)
-  int32_t* bsum = nullptr;            // scan block sums
+  int32_t* bsum = nullptr;            // cell scan chunk totals, then each search block's candidate total
   int32_t* status = nullptr;          // the scene's status words
 };
 
@@ -157,14 +157,20 @@ struct Blk {
   int32_t scene, base;
 };
 
+// One wavefront of a scene, for the kernels that run one wavefront per block: its scene, its
+// index in the scene, its first pill and its pill count (the wave's range, so that a launch
+// starts without reading it from the scene's wave table).
+struct WaveBlk {
+  int32_t scene, wave, p0, n;
+};
+
 enum Stage {
   TB_WAVES = 0,   // 4 wavefronts (<= 512 pill slots) per block: rod kernels
   TB_CAPS,        // 256 capsules per block
   TB_SEARCH,      // 28 capsules per block, 9 threads each: neighbour search
   TB_PAIRS,       // 256 lanes per block, two per candidate pair, 2 pair_span(cap) lanes per scene
-  TB_SCAN_E,      // 1024 (capsule, neighbour column) counts per block (scans)
-  TB_SCAN_T,      // 1024 cells per block
-  TB_DET,         // 256 of max(pills, cells, capsules) per block: start of contact detection
+  TB_SCAN_T,      // 1024 cells per block (cell scan)
+  TB_DET,         // 256 of max(pills, cells, capsules) per block: contact flush
   TB_SECT,        // 4 bundling sections per block (one wavefront each)
   TB_SECP,        // 256 bundling section entries per block
   TB_COUNT
@@ -182,6 +188,8 @@ struct BatchDev {
   const ContactDev* cd = nullptr;     // ContactDev[nscenes] in device memory (contact batches)
   const Blk* tab[TB_COUNT] = {};
   int nblk[TB_COUNT] = {};
+  const WaveBlk* wtab = nullptr;      // every wavefront of every scene, in scene order
+  int nwaves = 0;
   bool extras = false;                // some scene uses an optional constraint term (the rod
                                       // kernels' instantiation with them compiled in)
   bool even = false;                  // every rod of every scene starts on an even slot of its
