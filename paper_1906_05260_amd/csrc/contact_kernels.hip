@@ -22,9 +22,10 @@
 // Cells are hashed into a table and filled by a counting sort; every capsule then
 // counts its candidates in its cells, an exclusive scan turns the
 // counts into offsets, and a second pass emits the candidate list in parallel
-// (the parallel count-then-list construction of Sec. 7.1).  Each capsule sorts its
-// own segment, so the list does not depend on the order the atomics left inside a
-// bucket.  The overlap predicate runs in FP64 with no contraction, so it
+// (the parallel count-then-list construction of Sec. 7.1).  The set of pairs is exact; their
+// order inside a capsule's segment follows the order of the atomics and is not kept: the
+// handling sums its corrections in fixed point, so its result does not depend on it, and the
+// host sorts a list it hands out.  The overlap predicate runs in FP64 with no contraction, so it
 // decides exactly as a serial FP64 evaluation of the same stored values.
 //
 // Handling (Sec. 7.2, App. D): per candidate pair, a 10-step dichotomous search of
@@ -51,7 +52,6 @@ namespace {
 // Neighbour search: kSearchSub = 9 threads per capsule, one per (dz, dy) column of its
 // neighbour cells; 28 capsules (252 threads) per block.
 constexpr int kStage = 4;       // candidates per (capsule, column) kept by the count pass
-constexpr int kSortMax = 64;    // longest per-capsule candidate segment sorted in LDS
 constexpr int kWalkItems = 4;   // bucket entries per lane whose loads are issued together
 constexpr int kWaves = 4;       // wavefronts per search block
 constexpr int kCapsPerWave = 7; // capsules per wavefront (7 x 9 columns = 63 lanes)
@@ -357,13 +357,14 @@ __global__ void __launch_bounds__(256) bucket_scatter_kernel(const ContactDev* _
   // the capsule's search data (sphere, cell key, rod, group) is read while its slot is taken
   double sp[4] = {0.0, 0.0, 0.0, 0.0};
   long long K = -1;
-  int rod = 0, grp = 0;
+  int rod = 0, grp = 0, id = 0;
   if (mine) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) sp[k] = c.sph[4 * (size_t)i + k];
     K = c.pkey[i];
     rod = c.cap_rod[i];
     grp = c.cap_grp[i];
+    id = c.cap_ids[i];
   }
   __syncthreads();
   // grid capsules go to their bucket: the block takes one range of each of its buckets (one
@@ -380,7 +381,7 @@ __global__ void __launch_bounds__(256) bucket_scatter_kernel(const ContactDev* _
   if (h == -1) return;                 // not placed in this detection (or past the scene's capsules)
   // oversized capsules go after every bucket (cell_start[T] is the number of grid capsules)
   const int pos = h >= 0 ? s_base[sl] + rank : c.cell_start[c.T] + (-2 - h);
-  c.sorted[pos] = i;
+  c.sorted[pos] = id;
 #pragma unroll
   for (int k = 0; k < 4; ++k) c.ssph[4 * (size_t)pos + k] = sp[k];
   c.skey[pos] = h >= 0 ? K : -1ll;
@@ -398,11 +399,12 @@ __device__ __forceinline__ int32_t* search_totals(const ContactDev& c) { return 
 // (in thread order: coalesced, no atomics) and its block's total; the emit pass takes the
 // totals of the scene's blocks before its own and scans its block's counts, which gives every
 // thread its output offset with no scan launch between the passes.  The count pass keeps a column's
-// first 4 candidates, so the emit pass re-walks only the columns that had more.  After the
-// emit pass the capsule's threads sort the capsule's segment by b and store capsule ids.  A
+// first 4 candidates, so the emit pass re-walks only the columns that had more.  A
 // bucket whose entries all share the capsule's collision group (the interior of a muscle)
-// is skipped unread.  A pair is stored as (lower, higher) capsule id in the segment of the
-// capsule whose walk found it.
+// is skipped unread.  Bucket entries carry capsule ids (the first pill of a capsule, which
+// grows with the capsule index, so comparisons of ids order capsules as their indices do); a
+// pair is stored as (lower, higher) capsule id in the segment of the capsule whose walk found
+// it.
 template <bool EMIT>
 __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
   const Blk blk = tab[blockIdx.x];
@@ -428,7 +430,7 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
   // bucket positions w, w + n, ..., w + 6n (n = the scene's wavefronts): capsules of one
   // crowded cell, adjacent in bucket order, land in different wavefronts.
   const int wv = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
-  const int q = wv * kCapsPerWave + lane / kSearchSub, sub = lane % kSearchSub;
+  const int sub = lane % kSearchSub;
   const int nwave = kWaves * search_blocks(c.E);
   const int jh = blk.base / kCapsPerWave + wv + nwave * (lane / kSearchSub);   // home capsule's bucket position
   // the home capsule's bucket entry is read before the number of placed capsules is known
@@ -444,11 +446,9 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
   const bool live = lane < kCapsPerWave * kSearchSub && jh < nplaced;
   const int a = live ? a0 : 0;
   // emit pass: the offset of the thread's candidates in the scene's list (the blocks' totals
-  // before this one, then an exclusive scan of the block's counts in thread order) and its
-  // capsule's segment, the offsets of its first column and of the next capsule's (the 9
-  // columns of a capsule are adjacent lanes; lane 63 has no column and closes the last)
+  // before this one, then an exclusive scan of the block's counts in thread order)
   __shared__ int s_pre[kWaves], s_tot[kWaves];
-  int seg0 = 0, seg1 = 0, ida = 0, pcol = 0;
+  int pcol = 0;
   if (EMIT) {
     int incl = have;
 #pragma unroll
@@ -465,10 +465,6 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
     int run = before;
     for (int k = 0; k < wv; ++k) run += s_tot[k];
     pcol = run + incl - have;
-    const int first = kSearchSub * (lane / kSearchSub);
-    seg0 = __shfl(pcol, min(first, 63));
-    seg1 = __shfl(pcol, min(first + kSearchSub, 63));
-    if (live) ida = c.cap_ids[a];
     if (threadIdx.x == 0 && lb == search_blocks(c.E) - 1) {
       // the scene's pair count and overflow flag
       const int total = before + s_tot[0] + s_tot[1] + s_tot[2] + s_tot[3];
@@ -481,7 +477,7 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
     const int32_t* stg = c.stage + (size_t)kStage * slot;
     const int base = pcol;
     for (int k = 0; k < have; ++k)
-      if (base + k < c.cap) c.pairs[2 * (size_t)(base + k) + 1] = stg[k];
+      if (base + k < c.cap) ((int2*)c.pairs)[base + k] = make_int2(min(a, stg[k]), max(a, stg[k]));
   }
   // Columns to walk: all of them in the count pass, those with more than kStage candidates
   // in the emit pass.  A lane lists up to 4 slots (a run of bucket entries, the key they
@@ -632,15 +628,15 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
       const int pos = atomicAdd(&s_cnt[wv][o], 1);
       if (EMIT) {
         const int idx = sc[11] + pos;
-        if (idx < c.cap) c.pairs[2 * (size_t)idx + 1] = b;   // capsule index for now
+        if (idx < c.cap) ((int2*)c.pairs)[idx] = make_int2(min(sc[8], b), max(sc[8], b));
       } else if (pos < kStage) {
         c.stage[(size_t)kStage * sc[11] + pos] = b;
       }
     }
   }
-  __syncthreads();
-  if (!EMIT) {
+  if constexpr (!EMIT) {
     // every slot's count (0 without a column) and the block's total, plain stores
+    __syncthreads();
     const int cnt = s_cnt[wv][lane];
     c.pcount[slot] = cnt;
     int t = cnt;
@@ -649,49 +645,6 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
     if (lane == 0) s_tot[wv] = t;
     __syncthreads();
     if (threadIdx.x == 0) search_totals(c)[lb] = s_tot[0] + s_tot[1] + s_tot[2] + s_tot[3];
-    return;
-  }
-  // Sort each capsule's segment by b and store capsule ids (first pill of each capsule).
-  // A segment of up to kSortMax entries is ranked in LDS by the capsule's 9 threads: its
-  // entries are distinct capsules, so rank = number of smaller entries is a permutation.
-  __shared__ int seg[kSearchCaps][kSortMax];
-  __syncthreads();                        // every column of the block's capsules has emitted
-  int s0 = 0, n = 0;
-  if (live) {
-    s0 = min(seg0, c.cap);
-    n = min(seg1, c.cap) - s0;
-    if (n <= kSortMax)
-      for (int i = sub; i < n; i += kSearchSub) seg[q][i] = c.pairs[2 * (size_t)(s0 + i) + 1];
-  }
-  __syncthreads();
-  if (!live) return;
-  if (n <= kSortMax) {
-    for (int i = sub; i < n; i += kSearchSub) {
-      const int v = seg[q][i];
-      int r = 0;
-      for (int k = 0; k < n; ++k) r += seg[q][k] < v;
-      const int idb = c.cap_ids[v];
-      c.pairs[2 * (size_t)(s0 + r)] = min(ida, idb);
-      c.pairs[2 * (size_t)(s0 + r) + 1] = max(ida, idb);
-    }
-    return;
-  }
-  if (sub != 0) return;
-  // longer segments (rare): one thread, insertion sort in place
-  const int s1 = s0 + n;
-  for (int i = s0 + 1; i < s1; ++i) {
-    const int v = c.pairs[2 * (size_t)i + 1];
-    int j = i - 1;
-    while (j >= s0 && c.pairs[2 * (size_t)j + 1] > v) {
-      c.pairs[2 * (size_t)(j + 1) + 1] = c.pairs[2 * (size_t)j + 1];
-      --j;
-    }
-    c.pairs[2 * (size_t)(j + 1) + 1] = v;
-  }
-  for (int i = s0; i < s1; ++i) {
-    const int idb = c.cap_ids[c.pairs[2 * (size_t)i + 1]];
-    c.pairs[2 * (size_t)i] = min(ida, idb);
-    c.pairs[2 * (size_t)i + 1] = max(ida, idb);
   }
 }
 
@@ -1263,8 +1216,8 @@ viper_status contact_get_pairs(const ContactDev& c, int32_t* pairs, int32_t cap,
   if (h > cap) return VIPER_ERR_NO_CAPACITY;
   if (h > 0) {
     if (!pairs) return VIPER_ERR_INVALID;
-    // the device list is ordered by the capsule whose walk found the pair (the lower id in a
-    // home cell, otherwise either), so the canonical (a, b) order is restored here
+    // the device list holds each pair once as (lower, higher) capsule id, grouped by the
+    // capsule whose walk found it and in the order of the atomics: sorted here
     std::vector<int64_t> v((size_t)h);
     if (hipMemcpyAsync(v.data(), c.pairs, 8 * (size_t)h, hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)

@@ -100,7 +100,8 @@ struct ContactDev {
   double rlim = 0.0;                  // largest admitted cell radius (4x the largest at rest)
   int32_t* key = nullptr;             // [E] radius bin, then hash bucket
   long long* pkey = nullptr;          // [E] cell key (wrapped cell coordinates and grid level)
-  int32_t *cell_cnt = nullptr, *cell_start = nullptr, *cell_cur = nullptr, *sorted = nullptr;
+  int32_t *cell_cnt = nullptr, *cell_start = nullptr, *cell_cur = nullptr;
+  int32_t* sorted = nullptr;          // [E] capsule ids (first pill) in bucket order
   int32_t *cgmin = nullptr, *cgmax = nullptr;  // [T] smallest / largest group id in each bucket
   int32_t* pcount = nullptr;          // [256 search_blocks(E)] candidates per search thread (capsule column)
   int32_t* stage = nullptr;           // [4 * 256 search_blocks(E)] first candidates of each search thread
