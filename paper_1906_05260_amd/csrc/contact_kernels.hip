@@ -51,7 +51,7 @@ namespace {
 
 // Neighbour search: kSearchSub = 9 threads per capsule, one per (dz, dy) column of its
 // neighbour cells; 28 capsules (252 threads) per block.
-constexpr int kStage = 4;       // candidates per (capsule, column) kept by the count pass
+constexpr int kStage = 8;       // candidates per (capsule, column) kept by the count pass
 constexpr int kWalkItems = 4;   // bucket entries per lane whose loads are issued together
 constexpr int kWaves = 4;       // wavefronts per search block
 constexpr int kCapsPerWave = 7; // capsules per wavefront (7 x 9 columns = 63 lanes)
@@ -399,7 +399,7 @@ __device__ __forceinline__ int32_t* search_totals(const ContactDev& c) { return 
 // (in thread order: coalesced, no atomics) and its block's total; the emit pass takes the
 // totals of the scene's blocks before its own and scans its block's counts, which gives every
 // thread its output offset with no scan launch between the passes.  The count pass keeps a column's
-// first 4 candidates, so the emit pass re-walks only the columns that had more.  A
+// first 8 candidates, so the emit pass re-walks only the columns that had more.  A
 // bucket whose entries all share the capsule's collision group (the interior of a muscle)
 // is skipped unread.  Bucket entries carry capsule ids (the first pill of a capsule, which
 // grows with the capsule index, so comparisons of ids order capsules as their indices do); a

@@ -104,7 +104,7 @@ struct ContactDev {
   int32_t* sorted = nullptr;          // [E] capsule ids (first pill) in bucket order
   int32_t *cgmin = nullptr, *cgmax = nullptr;  // [T] smallest / largest group id in each bucket
   int32_t* pcount = nullptr;          // [256 search_blocks(E)] candidates per search thread (capsule column)
-  int32_t* stage = nullptr;           // [4 * 256 search_blocks(E)] first candidates of each search thread
+  int32_t* stage = nullptr;           // [8 * 256 search_blocks(E)] first candidates of each search thread
   int32_t *pairs = nullptr, *npairs = nullptr;
   double* ssph = nullptr;             // [E*4] spheres in bucket (cell) order
   long long* skey = nullptr;          // [E] cell keys in bucket order (-1: oversized list)
