@@ -365,7 +365,7 @@ def contact_skin_timing(torch, viper, scenes, dev, frames=10):
             # scan, bucket scatter, count pass, candidate scan, emit pass), a contact pass per
             # iteration and a rod iteration per iteration but the first; the first substep's
             # prediction and first rod iteration
-            "launches_per_frame": 2 + sub * (1 + 5 + iters + (iters - 1)),
+            "launches_per_frame": 2 + sub * (1 + 4 + iters + (iters - 1)),
             "skin_vertices": V, "skin_ms": skin_ms, "skin_weights_ms": weights_ms,
             "skin_algorithmic_GB_per_s": skin_bytes / (skin_ms * 1e-3) / 1e9,
             "skin_large": {"vertices": VL, "ms": skin_l_ms, "algorithmic_bytes": skin_l_bytes,

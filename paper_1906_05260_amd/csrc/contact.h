@@ -14,7 +14,7 @@ namespace viper {
 struct ContactOffsets {
   bool on = false;
   size_t cap_ids, cap_rod, cap_grp, sph, hist, binmax, dcnt, walk, cw, key, pkey, cell_cnt, cell_start, cell_cur, sorted, cgmin, cgmax;
-  size_t pcount, stage, pairs, npairs, ssph, skey, srg, acc, acnt;
+  size_t stage, pairs, npairs, ssph, skey, srg, acc, acnt;
   size_t xdet, sdet, bsum;
   size_t end;
 };

@@ -20,9 +20,9 @@
 // its largest bounding radius at rest has diverged: its detection is skipped (no
 // candidates) and its status says so.
 // Cells are hashed into a table and filled by a counting sort; every capsule then
-// counts its candidates in its cells, an exclusive scan turns the
-// counts into offsets, and a second pass emits the candidate list in parallel
-// (the parallel count-then-list construction of Sec. 7.1).  The set of pairs is exact; their
+// counts its candidates in its cells, an exclusive scan turns the counts into offsets
+// (in each search block, whose range of the list comes from one add), and the candidates
+// are listed in parallel (the parallel count-then-list construction of Sec. 7.1).  The set of pairs is exact; their
 // order inside a capsule's segment follows the order of the atomics and is not kept: the
 // handling sums its corrections in fixed point, so its result does not depend on it, and the
 // host sorts a list it hands out.  The overlap predicate runs in FP64 with no contraction, so it
@@ -44,6 +44,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <type_traits>
 
 namespace viper {
 
@@ -389,36 +390,24 @@ __global__ void __launch_bounds__(256) bucket_scatter_kernel(const ContactDev* _
   c.srg[2 * (size_t)pos + 1] = grp;
 }
 
-// The search blocks' candidate totals follow the cell scan's chunk totals.
-__device__ __forceinline__ int32_t* search_totals(const ContactDev& c) { return c.bsum + kCellTotalCopies * cell_chunks(c.T); }
-
-// Count (EMIT = false) or emit (EMIT = true) the candidates that capsule a's walk finds
-// (see the slots below).  Threads follow bucket order, so the lanes of a wave mostly share
-// a home cell and walk the same neighbour entries (their loads coalesce); each of a
-// capsule's 9 threads covers one (dz, dy) column.  The count pass stores every thread's count
-// (in thread order: coalesced, no atomics) and its block's total; the emit pass takes the
-// totals of the scene's blocks before its own and scans its block's counts, which gives every
-// thread its output offset with no scan launch between the passes.  The count pass keeps a column's
-// first 8 candidates, so the emit pass re-walks only the columns that had more.  A
-// bucket whose entries all share the capsule's collision group (the interior of a muscle)
-// is skipped unread.  Bucket entries carry capsule ids (the first pill of a capsule, which
-// grows with the capsule index, so comparisons of ids order capsules as their indices do); a
-// pair is stored as (lower, higher) capsule id in the segment of the capsule whose walk found
-// it.
-template <bool EMIT>
+// Find and list the candidates of capsule a's walk (see the slots below).  Threads follow
+// bucket order, so the lanes of a wave mostly share a home cell and walk the same neighbour
+// entries (their loads coalesce); each of a capsule's 9 threads covers one (dz, dy) column.
+// The first walk counts every column's candidates and keeps its first kStage in the thread's
+// staging slot; the block then takes the range of its candidates in the scene's list with one
+// add to the scene's pair count (every thread's offset follows from an exclusive scan of the
+// block's counts), copies the staged candidates and walks again the columns that had more,
+// listing them.  A bucket whose entries all share the capsule's collision group (the interior
+// of a muscle) is skipped unread.  Bucket entries carry capsule ids (the first pill of a
+// capsule, which grows with the capsule index, so comparisons of ids order capsules as their
+// indices do); a pair is stored as (lower, higher) capsule id.  The blocks' ranges follow the
+// order of their adds, which is not kept (see the handling below).
 __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
   const Blk blk = tab[blockIdx.x];
   const ContactDev& c = CD[blk.scene];
   const int lb = blk.base / kSearchCaps;                  // the block's index in its scene
-  const int slot = 256 * lb + (int)threadIdx.x;           // the thread's count and staging slot
-  // emit pass: the thread's count, and the totals of the scene's blocks before this one
-  int have = 0, pre = 0;
-  if (EMIT) {
-    have = c.pcount[slot];
-    const int32_t* bt = search_totals(c);
-    for (int k = (int)threadIdx.x; k < lb; k += 256) pre += bt[k];
-  }
-  if (EMIT && blk.base == 0) {
+  const int slot = 256 * lb + (int)threadIdx.x;           // the thread's staging slot
+  if (blk.base == 0) {
     // the radius histogram has had its last reader
     for (int k = (int)threadIdx.x; k < kHistCopies * (kRadBins + 1); k += 256) {
       c.hist[k] = 0;
@@ -445,43 +434,8 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
   asm volatile("" ::"v"(a0), "v"(K0), "v"(sa01.x), "v"(sa01.y), "v"(sa23.x), "v"(sa23.y), "v"(rg0.x), "v"(rg0.y));
   const bool live = lane < kCapsPerWave * kSearchSub && jh < nplaced;
   const int a = live ? a0 : 0;
-  // emit pass: the offset of the thread's candidates in the scene's list (the blocks' totals
-  // before this one, then an exclusive scan of the block's counts in thread order)
-  __shared__ int s_pre[kWaves], s_tot[kWaves];
-  int pcol = 0;
-  if (EMIT) {
-    int incl = have;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int t = __shfl_up(incl, o);
-      if (lane >= o) incl += t;
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) pre += __shfl_xor(pre, o);
-    if (lane == 63) s_tot[wv] = incl;
-    if (lane == 0) s_pre[wv] = pre;
-    __syncthreads();
-    const int before = s_pre[0] + s_pre[1] + s_pre[2] + s_pre[3];
-    int run = before;
-    for (int k = 0; k < wv; ++k) run += s_tot[k];
-    pcol = run + incl - have;
-    if (threadIdx.x == 0 && lb == search_blocks(c.E) - 1) {
-      // the scene's pair count and overflow flag
-      const int total = before + s_tot[0] + s_tot[1] + s_tot[2] + s_tot[3];
-      c.npairs[0] = min(total, c.cap);
-      if (total > c.cap) c.status[ST_OVERFLOW] = 1;
-    }
-  }
-  if (EMIT && live && have <= kStage) {
-    // the count pass kept every candidate of this column: copy them
-    const int32_t* stg = c.stage + (size_t)kStage * slot;
-    const int base = pcol;
-    for (int k = 0; k < have; ++k)
-      if (base + k < c.cap) ((int2*)c.pairs)[base + k] = make_int2(min(a, stg[k]), max(a, stg[k]));
-  }
-  // Columns to walk: all of them in the count pass, those with more than kStage candidates
-  // in the emit pass.  A lane lists up to 4 slots (a run of bucket entries, the key they
-  // must carry, whether b > a is required) ...
+  // A lane lists up to 4 slots (a run of bucket entries, the key they must carry, whether
+  // b > a is required) ...
   //  - slots 0..2, the cells dx = -1, 0, +1 of its (dz, dy) column in its capsule's own
   //    level, half shell: a cell after the home cell in (dz, dy, dx) order gives every
   //    partner, the home cell those above a, a cell before it none (the partner's own walk
@@ -497,13 +451,14 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
   __shared__ int s_col[kWaves][64][12];   // js0..js3, cum1 cum2 cum3, b > a mask, a ra ga, out
   __shared__ long long s_key[kWaves][64][2];   // key of the column's dx = -1 cell, key of slot 3
   __shared__ double s_sph[kWaves][64][4];
+  __shared__ int s_tot[kWaves], s_base;
   int w = 0;
   {
     int js[4] = {0, 0, 0, 0}, ln[4] = {0, 0, 0, 0}, ra = 0, ga = 0, gt = 0;
     long long k0 = -1, k3 = -1;
     const bool over = jh >= ngrid;
     double sa[4] = {0.0, 0.0, 0.0, 0.0};
-    if (live && (!EMIT || have > kStage)) {
+    if (live) {
       const long long K = K0;
       sa[0] = sa01.x; sa[1] = sa01.y; sa[2] = sa23.x; sa[3] = sa23.y;
       ra = rg0.x; ga = rg0.y;
@@ -554,98 +509,125 @@ __global__ void __launch_bounds__(256) pair_kernel(const ContactDev* __restrict_
     sc[0] = js[0]; sc[1] = js[1]; sc[2] = js[2]; sc[3] = js[3];
     sc[4] = ln[0]; sc[5] = ln[0] + ln[1]; sc[6] = ln[0] + ln[1] + ln[2];
     sc[7] = gt; sc[8] = a; sc[9] = ra; sc[10] = ga;
-    sc[11] = EMIT ? pcol : slot;
+    sc[11] = slot;
     s_key[wv][lane][0] = k0;
     s_key[wv][lane][1] = k3;
 #pragma unroll
     for (int k = 0; k < 4; ++k) s_sph[wv][lane][k] = sa[k];
     s_cnt[wv][lane] = 0;
   }
-  // ... and the wavefront walks the concatenation of its lanes' lists 64 entries at a time
-  // (a lane finds the column of its entry by binary search over the exclusive prefix sums),
-  // so that lanes stay busy however unevenly the entries fall on columns.
-  int incl = w;
+  // ... and the wavefront walks the concatenation of its lanes' lists (w entries on this lane)
+  // 64 entries at a time (a lane finds the column of its entry by binary search over the
+  // exclusive prefix sums), so that lanes stay busy however unevenly the entries fall on
+  // columns.  A found candidate is counted in its column; the first walk stages it (up to
+  // kStage per column), the second lists it at its column's offset (s_col out).
+  auto walk = [&](auto listing) {
+    constexpr bool kList = decltype(listing)::value;
+    int incl = w;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(incl, o);
+      if (lane >= o) incl += t;
+    }
+    s_off[wv][lane] = incl - w;
+    if (lane == 63) s_off[wv][64] = incl;
+    __syncthreads();
+    const int W = s_off[wv][64];
+    // walk length for the detection record: one add per block, spread over kWalkCounters
+    // addresses so that the adds of a scene's blocks do not queue on one
+    if (!kList && threadIdx.x == 0) {
+      unsigned long long wb = 0;
+#pragma unroll
+      for (int k = 0; k < kWaves; ++k) wb += (unsigned long long)s_off[k][64];
+      if (wb) atomicAdd(c.walk + (blockIdx.x & (kWalkCounters - 1)), wb);
+    }
+    for (int g0 = 0; g0 < W; g0 += 64 * kWalkItems) {
+      int own[kWalkItems], jj[kWalkItems], dd[kWalkItems], bb[kWalkItems], rr[kWalkItems], gg[kWalkItems];
+      long long kk[kWalkItems];
+      double2 s01[kWalkItems], s23[kWalkItems];
+#pragma unroll
+      for (int u = 0; u < kWalkItems; ++u) {
+        const int g = g0 + 64 * u + lane;
+        int lo = 0, hi = 64;
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (s_off[wv][mid] <= g) lo = mid; else hi = mid;
+        }
+        const int* sc = s_col[wv][lo];
+        const int k = g - s_off[wv][lo];
+        own[u] = g < W ? lo : -1;
+        dd[u] = k < sc[4] ? 0 : (k < sc[5] ? 1 : (k < sc[6] ? 2 : 3));
+        jj[u] = sc[dd[u]] + k - (dd[u] == 0 ? 0 : sc[3 + dd[u]]);
+        if (g >= W) jj[u] = 0;          // past the end: a harmless in-bounds read, masked below
+      }
+#pragma unroll
+      for (int u = 0; u < kWalkItems; ++u) {
+        const size_t j = (size_t)jj[u];
+        bb[u] = c.sorted[j];
+        kk[u] = c.skey[j];
+        const int2 rg = ((const int2*)c.srg)[j];
+        rr[u] = rg.x; gg[u] = rg.y;
+        s01[u] = ((const double2*)c.ssph)[2 * j];
+        s23[u] = ((const double2*)c.ssph)[2 * j + 1];
+      }
+#pragma unroll
+      for (int u = 0; u < kWalkItems; ++u) {
+        const int o = own[u];
+        if (o < 0) continue;
+        const int* sc = s_col[wv][o];
+        const int b = bb[u];
+        const int d = dd[u];
+        const long long k0 = s_key[wv][o][0];
+        const long long want = d < 3 ? ((k0 & ~kM21) | ((k0 + d) & kM21)) : s_key[wv][o][1];
+        if (kk[u] != want) continue;                         // another cell or level (hash collision)
+        if (((sc[7] >> d) & 1) && b <= sc[8]) continue;      // the home cell / an oversized capsule's list
+        if (rr[u] == sc[9] || gg[u] == sc[10]) continue;
+        const double sb[4] = {s01[u].x, s01[u].y, s23[u].x, s23[u].y};
+        if (!spheres_overlap(s_sph[wv][o], sb)) continue;
+        const int pos = atomicAdd(&s_cnt[wv][o], 1);
+        if (kList) {
+          const int idx = sc[11] + pos;
+          if (idx < c.cap) ((int2*)c.pairs)[idx] = make_int2(min(sc[8], b), max(sc[8], b));
+        } else if (pos < kStage) {
+          c.stage[(size_t)kStage * sc[11] + pos] = b;
+        }
+      }
+    }
+  };
+  walk(std::false_type{});
+  // the block's range: its columns' counts scanned in thread order, one add for the block
+  __syncthreads();                        // every count is final and every staged entry written
+  const int cnt = s_cnt[wv][lane];
+  const int w1 = s_off[wv][lane + 1] - s_off[wv][lane];   // the lane's entries (kept in LDS over the walk)
+  const int ida = s_col[wv][lane][8];
+  int incl = cnt;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
     const int t = __shfl_up(incl, o);
     if (lane >= o) incl += t;
   }
-  s_off[wv][lane] = incl - w;
-  if (lane == 63) s_off[wv][64] = incl;
+  if (lane == 63) s_tot[wv] = incl;
   __syncthreads();
-  const int W = s_off[wv][64];
-  // walk length for the detection record: one add per block, spread over kWalkCounters
-  // addresses so that the adds of a scene's blocks do not queue on one
-  if (!EMIT && threadIdx.x == 0) {
-    unsigned long long wb = 0;
-#pragma unroll
-    for (int k = 0; k < kWaves; ++k) wb += (unsigned long long)s_off[k][64];
-    if (wb) atomicAdd(c.walk + (blockIdx.x & (kWalkCounters - 1)), wb);
+  if (threadIdx.x == 0) {
+    const int total = s_tot[0] + s_tot[1] + s_tot[2] + s_tot[3];
+    const int base = total > 0 ? atomicAdd(c.npairs, total) : 0;
+    if (total > c.cap - base) c.status[ST_OVERFLOW] = 1;   // the list keeps its first cap pairs
+    s_base = base;
   }
-  for (int g0 = 0; g0 < W; g0 += 64 * kWalkItems) {
-    int own[kWalkItems], jj[kWalkItems], dd[kWalkItems], bb[kWalkItems], rr[kWalkItems], gg[kWalkItems];
-    long long kk[kWalkItems];
-    double2 s01[kWalkItems], s23[kWalkItems];
-#pragma unroll
-    for (int u = 0; u < kWalkItems; ++u) {
-      const int g = g0 + 64 * u + lane;
-      int lo = 0, hi = 64;
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (s_off[wv][mid] <= g) lo = mid; else hi = mid;
-      }
-      const int* sc = s_col[wv][lo];
-      const int k = g - s_off[wv][lo];
-      own[u] = g < W ? lo : -1;
-      dd[u] = k < sc[4] ? 0 : (k < sc[5] ? 1 : (k < sc[6] ? 2 : 3));
-      jj[u] = sc[dd[u]] + k - (dd[u] == 0 ? 0 : sc[3 + dd[u]]);
-      if (g >= W) jj[u] = 0;          // past the end: a harmless in-bounds read, masked below
-    }
-#pragma unroll
-    for (int u = 0; u < kWalkItems; ++u) {
-      const size_t j = (size_t)jj[u];
-      bb[u] = c.sorted[j];
-      kk[u] = c.skey[j];
-      const int2 rg = ((const int2*)c.srg)[j];
-      rr[u] = rg.x; gg[u] = rg.y;
-      s01[u] = ((const double2*)c.ssph)[2 * j];
-      s23[u] = ((const double2*)c.ssph)[2 * j + 1];
-    }
-#pragma unroll
-    for (int u = 0; u < kWalkItems; ++u) {
-      const int o = own[u];
-      if (o < 0) continue;
-      const int* sc = s_col[wv][o];
-      const int b = bb[u];
-      const int d = dd[u];
-      const long long k0 = s_key[wv][o][0];
-      const long long want = d < 3 ? ((k0 & ~kM21) | ((k0 + d) & kM21)) : s_key[wv][o][1];
-      if (kk[u] != want) continue;                         // another cell or level (hash collision)
-      if (((sc[7] >> d) & 1) && b <= sc[8]) continue;      // the home cell / an oversized capsule's list
-      if (rr[u] == sc[9] || gg[u] == sc[10]) continue;
-      const double sb[4] = {s01[u].x, s01[u].y, s23[u].x, s23[u].y};
-      if (!spheres_overlap(s_sph[wv][o], sb)) continue;
-      const int pos = atomicAdd(&s_cnt[wv][o], 1);
-      if (EMIT) {
-        const int idx = sc[11] + pos;
-        if (idx < c.cap) ((int2*)c.pairs)[idx] = make_int2(min(sc[8], b), max(sc[8], b));
-      } else if (pos < kStage) {
-        c.stage[(size_t)kStage * sc[11] + pos] = b;
-      }
-    }
+  __syncthreads();
+  int out = s_base + incl - cnt;
+  for (int k = 0; k < wv; ++k) out += s_tot[k];
+  if (cnt <= kStage) {
+    // the first walk kept every candidate of this column: copy them
+    const int32_t* stg = c.stage + (size_t)kStage * (256 * lb + (int)threadIdx.x);
+    for (int k = 0; k < cnt; ++k)
+      if (out + k < c.cap) ((int2*)c.pairs)[out + k] = make_int2(min(ida, stg[k]), max(ida, stg[k]));
   }
-  if constexpr (!EMIT) {
-    // every slot's count (0 without a column) and the block's total, plain stores
-    __syncthreads();
-    const int cnt = s_cnt[wv][lane];
-    c.pcount[slot] = cnt;
-    int t = cnt;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
-    if (lane == 0) s_tot[wv] = t;
-    __syncthreads();
-    if (threadIdx.x == 0) search_totals(c)[lb] = s_tot[0] + s_tot[1] + s_tot[2] + s_tot[3];
-  }
+  // the columns with more are walked again, listing
+  w = cnt > kStage ? w1 : 0;
+  s_cnt[wv][lane] = 0;
+  s_col[wv][lane][11] = out;
+  walk(std::true_type{});
 }
 
 // ---- handling (FP64 arithmetic)
@@ -755,7 +737,7 @@ __global__ void __launch_bounds__(256) contact_pair_kernel(const Dev<T>* __restr
   asm volatile("" ::"s"(d.px), "s"(d.py), "s"(d.pz), "s"(d.s), "s"(d.rbar), "s"(d.winv), "s"(d.wsinv), "s"(d.rod_of),
                "s"(d.anchor), "s"(c.acc), "s"(c.acnt), "s"(c.search_iters), "s"(c.delta), "s"(c.pairs), "s"(c.npairs));
   int2 ab = ((const int2*)c.pairs)[min(i, c.cap - 1)];
-  const int np = c.npairs[0];
+  const int np = min(c.npairs[0], c.cap);
   asm volatile("" ::"v"(ab.x), "v"(ab.y));
   while (i < np) {   // the same trip count on both lanes of a pair
     const int pid[4] = {ab.x, ab.x + 1, ab.y, ab.y + 1};
@@ -1022,7 +1004,7 @@ ContactOffsets contact_layout(size_t start, bool on, int P, int E, int cpc, bool
   const int T = contact_table_size(E);
   const size_t cap = (size_t)cpc * (size_t)E;
   const size_t ts = f64 ? 8 : 4;
-  const int nb = chunk_total_words(T, E);   // cell scan chunk totals, search block totals
+  const int nb = chunk_total_words(T);      // cell scan chunk totals
   o.cap_ids = take(4 * (size_t)E);
   o.cap_rod = take(4 * (size_t)E);
   o.cap_grp = take(4 * (size_t)E);
@@ -1040,7 +1022,6 @@ ContactOffsets contact_layout(size_t start, bool on, int P, int E, int cpc, bool
   o.sorted = take(4 * (size_t)E);
   o.cgmin = take(4 * (size_t)T);
   o.cgmax = take(4 * (size_t)T);
-  o.pcount = take(4 * (size_t)256 * search_blocks(E));
   o.stage = take(4 * (size_t)kStage * 256 * search_blocks(E));
   o.pairs = take(8 * cap);
   o.npairs = take(4);
@@ -1101,7 +1082,6 @@ viper_status contact_init(ContactDev& c, char* ws, const ContactOffsets& o, cons
   c.sorted = (int32_t*)(ws + o.sorted);
   c.cgmin = (int32_t*)(ws + o.cgmin);
   c.cgmax = (int32_t*)(ws + o.cgmax);
-  c.pcount = (int32_t*)(ws + o.pcount);
   c.stage = (int32_t*)(ws + o.stage);
   c.pairs = (int32_t*)(ws + o.pairs);
   c.npairs = (int32_t*)(ws + o.npairs);
@@ -1140,8 +1120,7 @@ hipError_t launch_contact_detect(const BatchDev& b, hipStream_t st) {
   hipLaunchKernelGGL(key_kernel, dim3(b.nblk[TB_CAPS]), blk, 0, st, CD, b.tab[TB_CAPS]);
   hipLaunchKernelGGL(scan_kernel, dim3(b.nblk[TB_SCAN_T]), blk, 0, st, CD, b.tab[TB_SCAN_T]);
   hipLaunchKernelGGL(bucket_scatter_kernel, dim3(b.nblk[TB_CAPS]), blk, 0, st, CD, b.tab[TB_CAPS]);
-  hipLaunchKernelGGL(pair_kernel<false>, dim3(b.nblk[TB_SEARCH]), blk, 0, st, CD, b.tab[TB_SEARCH]);
-  hipLaunchKernelGGL(pair_kernel<true>, dim3(b.nblk[TB_SEARCH]), blk, 0, st, CD, b.tab[TB_SEARCH]);
+  hipLaunchKernelGGL(pair_kernel, dim3(b.nblk[TB_SEARCH]), blk, 0, st, CD, b.tab[TB_SEARCH]);
   return hipGetLastError();
 }
 
@@ -1212,6 +1191,7 @@ viper_status contact_get_pairs(const ContactDev& c, int32_t* pairs, int32_t cap,
   int32_t h = 0;
   if (hipMemcpyAsync(&h, c.npairs, 4, hipMemcpyDeviceToHost, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
     return VIPER_ERR_DEVICE;
+  h = std::min(h, c.cap);               // an overflowing detection keeps its first cap pairs
   *n = h;
   if (h > cap) return VIPER_ERR_NO_CAPACITY;
   if (h > 0) {

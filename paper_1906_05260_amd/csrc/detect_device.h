@@ -20,13 +20,10 @@ __host__ __device__ __forceinline__ int search_blocks(int E) { return (E + kSear
 
 // Chunk totals of the cell scan, in kCellTotalCopies copies (every capsule adds one to its
 // bucket's chunk; the copies spread those adds over more addresses, since adds to one address
-// from the whole chip queue behind each other; a chunk is the 1024 items of one scan block),
-// then the candidate total of each search block (a plain store per block).
+// from the whole chip queue behind each other; a chunk is the 1024 items of one scan block).
 constexpr int kCellTotalCopies = 32;
 __host__ __device__ __forceinline__ int cell_chunks(int T) { return (T + 1023) / 1024; }
-__host__ __device__ __forceinline__ int chunk_total_words(int T, int E) {
-  return kCellTotalCopies * cell_chunks(T) + search_blocks(E);
-}
+__host__ __device__ __forceinline__ int chunk_total_words(int T) { return kCellTotalCopies * cell_chunks(T); }
 
 // Histogram bin of a bounding radius R (finite, m): 4 bins per octave, bin 96 starts at 1 m,
 // clamped to [0, kRadBins - 1]; bin b holds [2^((b-96)/4), 2^((b-95)/4)).
@@ -71,7 +68,8 @@ __device__ __forceinline__ int capsule_record(const ContactDev& c, int i, const 
 }
 
 // The per-detection resets a scene's threads share (thread tid of nth): hash-bucket counts,
-// cursors and group ranges, the cell scan's chunk totals, the walk record and the oversized count.
+// cursors and group ranges, the cell scan's chunk totals, the walk record, the oversized count and
+// the pair count.
 __device__ __forceinline__ void detect_reset(const ContactDev& c, int tid, int nth) {
   for (int k = tid; k < c.T; k += nth) {
     c.cell_cnt[k] = 0;
@@ -79,10 +77,13 @@ __device__ __forceinline__ void detect_reset(const ContactDev& c, int tid, int n
     c.cgmin[k] = 0x7fffffff;
     c.cgmax[k] = -0x7fffffff - 1;
   }
-  const int nw = kCellTotalCopies * cell_chunks(c.T);   // the search blocks store their totals
+  const int nw = chunk_total_words(c.T);
   for (int k = tid; k < nw; k += nth) c.bsum[k] = 0;
   for (int k = tid; k < kWalkCounters; k += nth) c.walk[k] = 0ull;
-  if (tid == 0) c.dcnt[0] = 0;
+  if (tid == 0) {
+    c.dcnt[0] = 0;
+    c.npairs[0] = 0;
+  }
 }
 
 }  // namespace viper

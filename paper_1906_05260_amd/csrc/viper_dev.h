@@ -103,9 +103,9 @@ struct ContactDev {
   int32_t *cell_cnt = nullptr, *cell_start = nullptr, *cell_cur = nullptr;
   int32_t* sorted = nullptr;          // [E] capsule ids (first pill) in bucket order
   int32_t *cgmin = nullptr, *cgmax = nullptr;  // [T] smallest / largest group id in each bucket
-  int32_t* pcount = nullptr;          // [256 search_blocks(E)] candidates per search thread (capsule column)
   int32_t* stage = nullptr;           // [8 * 256 search_blocks(E)] first candidates of each search thread
-  int32_t *pairs = nullptr, *npairs = nullptr;
+  int32_t* pairs = nullptr;           // [cap] candidate pairs (lower, higher capsule id)
+  int32_t* npairs = nullptr;          // pairs found (the list keeps the first cap of them)
   double* ssph = nullptr;             // [E*4] spheres in bucket (cell) order
   long long* skey = nullptr;          // [E] cell keys in bucket order (-1: oversized list)
   int32_t* srg = nullptr;             // [E*2] rod, group in bucket order
@@ -113,7 +113,7 @@ struct ContactDev {
   int32_t* acnt = nullptr;            // [P] active contacts per pill this pass
   double* xdet = nullptr;             // [3P] FP64 world positions at detection
   void* sdet = nullptr;               // [P] scales at detection (scene precision)
-  int32_t* bsum = nullptr;            // cell scan chunk totals, then each search block's candidate total
+  int32_t* bsum = nullptr;            // cell scan chunk totals
   int32_t* status = nullptr;          // the scene's status words
 };
 
