@@ -53,7 +53,7 @@ namespace {
 // Neighbour search: kSearchSub = 9 threads per capsule, one per (dz, dy) column of its
 // neighbour cells; 28 capsules (252 threads) per block.
 constexpr int kStage = 8;       // candidates per (capsule, column) kept by the count pass
-constexpr int kWalkItems = 4;   // bucket entries per lane whose loads are issued together
+constexpr int kWalkItems = 3;   // bucket entries per lane whose loads are issued together
 constexpr int kWaves = 4;       // wavefronts per search block
 constexpr int kCapsPerWave = 7; // capsules per wavefront (7 x 9 columns = 63 lanes)
 static_assert(kWaves * kCapsPerWave == kSearchCaps, "search block layout");
