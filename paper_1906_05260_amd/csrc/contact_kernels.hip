@@ -723,7 +723,7 @@ __device__ __forceinline__ double pair_swap(double v) {
 // lower lane accumulates the corrections of the first capsule's pills, the upper lane those
 // of the second's.  A scene's blocks cover pair_span(cap) pairs per round.
 template <class T>
-__global__ void __launch_bounds__(256) contact_pair_kernel(const Dev<T>* __restrict__ D, const ContactDev* __restrict__ CD,
+__global__ void __launch_bounds__(64) contact_pair_kernel(const Dev<T>* __restrict__ D, const ContactDev* __restrict__ CD,
                                                            const Blk* __restrict__ tab) {
   BLOCK_SCENE(tab, D, CD)
   const int lane2 = blk_.base + (int)threadIdx.x;
@@ -1128,7 +1128,7 @@ template <class T>
 hipError_t launch_contact_project(const BatchDev& b, hipStream_t st) {
   if (b.nscenes == 0) return hipSuccess;
   const Dev<T>* D = (const Dev<T>*)b.dev;
-  hipLaunchKernelGGL(contact_pair_kernel<T>, dim3(b.nblk[TB_PAIRS]), dim3(256), 0, st, D, b.cd, b.tab[TB_PAIRS]);
+  hipLaunchKernelGGL(contact_pair_kernel<T>, dim3(b.nblk[TB_PAIRS]), dim3(64), 0, st, D, b.cd, b.tab[TB_PAIRS]);
   return hipGetLastError();
 }
 

@@ -221,7 +221,7 @@ struct Counts {
   const std::vector<int32_t>* wave_start = nullptr;      // [W+1] first pill of each wave (host)
 };
 
-const int kStageItems[TB_COUNT] = {4, 256, 28, 256, 1024, 256, 4, 256};
+const int kStageItems[TB_COUNT] = {4, 256, 28, 64, 1024, 256, 4, 256};
 
 int stage_items(const Counts& c, int stage) {
   switch (stage) {
