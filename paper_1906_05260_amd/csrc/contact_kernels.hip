@@ -244,10 +244,12 @@ __device__ GridLevels grid_levels_wave(const int32_t* h, const unsigned long lon
   return g;
 }
 
+// The cell-key and bucket-scatter kernels take kCapsBlock capsules per block (one thread each).
+constexpr int kCapsBlock = 256;
 // A block's distinct hash buckets, so that the block adds into each bucket once (capsules of
 // consecutive indices share cells: one muscle's neighbouring rods): open addressing over
-// kBlockSlots slots (at most 256 keys, so every probe sequence ends), cleared by the caller.
-constexpr int kBlockSlots = 512;
+// kBlockSlots slots (at most kCapsBlock keys, so every probe sequence ends), cleared by the caller.
+constexpr int kBlockSlots = 2 * kCapsBlock;
 __device__ __forceinline__ int block_slot(int* keys, int h) {
   int s = h & (kBlockSlots - 1);
   for (int n = 0; n < kBlockSlots; ++n) {
@@ -260,15 +262,14 @@ __device__ __forceinline__ int block_slot(int* keys, int h) {
 
 // Cell keys: a capsule in a bin up to the fine bin goes to its fine-grid cell, one up to the
 // cell bin to its coarse-grid cell, a larger one to the oversized list, a non-finite one (or
-// every capsule of a skipped scene) nowhere; the candidate counts of capsules that are not
-// placed are cleared here, since no search thread visits them.
-__global__ void __launch_bounds__(256) key_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
+// every capsule of a skipped scene) nowhere.
+__global__ void __launch_bounds__(kCapsBlock) key_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
   __shared__ int s_cb, s_bf;
   __shared__ double s_rc, s_rf;
   __shared__ int s_key[kBlockSlots], s_cnt[kBlockSlots], s_gmin[kBlockSlots], s_gmax[kBlockSlots];
   const Blk b = tab[blockIdx.x];
   const ContactDev& c = CD[b.scene];
-  for (int k = (int)threadIdx.x; k < kBlockSlots; k += 256) {
+  for (int k = (int)threadIdx.x; k < kBlockSlots; k += kCapsBlock) {
     s_key[k] = -1;
     s_cnt[k] = 0;
     s_gmin[k] = 0x7fffffff;
@@ -334,7 +335,7 @@ __global__ void __launch_bounds__(256) key_kernel(const ContactDev* __restrict__
   __syncthreads();
   // one add per distinct bucket of the block: its count, its group range, and the cell scan's
   // chunk total (in the copy of this block)
-  for (int k = (int)threadIdx.x; k < kBlockSlots; k += 256) {
+  for (int k = (int)threadIdx.x; k < kBlockSlots; k += kCapsBlock) {
     const int h = s_key[k];
     if (h < 0) continue;
     atomicAdd(&c.cell_cnt[h], s_cnt[k]);
@@ -344,11 +345,11 @@ __global__ void __launch_bounds__(256) key_kernel(const ContactDev* __restrict__
   }
 }
 
-__global__ void __launch_bounds__(256) bucket_scatter_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
+__global__ void __launch_bounds__(kCapsBlock) bucket_scatter_kernel(const ContactDev* __restrict__ CD, const Blk* __restrict__ tab) {
   __shared__ int s_key[kBlockSlots], s_cnt[kBlockSlots], s_base[kBlockSlots];
   const Blk b = tab[blockIdx.x];
   const ContactDev& c = CD[b.scene];
-  for (int k = (int)threadIdx.x; k < kBlockSlots; k += 256) {
+  for (int k = (int)threadIdx.x; k < kBlockSlots; k += kCapsBlock) {
     s_key[k] = -1;
     s_cnt[k] = 0;
   }
@@ -376,7 +377,7 @@ __global__ void __launch_bounds__(256) bucket_scatter_kernel(const ContactDev* _
     rank = atomicAdd(&s_cnt[sl], 1);
   }
   __syncthreads();
-  for (int k = (int)threadIdx.x; k < kBlockSlots; k += 256)
+  for (int k = (int)threadIdx.x; k < kBlockSlots; k += kCapsBlock)
     if (s_key[k] >= 0) s_base[k] = c.cell_start[s_key[k]] + atomicAdd(&c.cell_cur[s_key[k]], s_cnt[k]);
   __syncthreads();
   if (h == -1) return;                 // not placed in this detection (or past the scene's capsules)
@@ -1117,9 +1118,9 @@ hipError_t launch_contact_detect(const BatchDev& b, hipStream_t st) {
   // the detection record of every capsule (sphere, radius bin, histogram) and the resets were
   // formed by the prediction launch (launch_predict / launch_velocity with a next substep)
   (void)D;
-  hipLaunchKernelGGL(key_kernel, dim3(b.nblk[TB_CAPS]), blk, 0, st, CD, b.tab[TB_CAPS]);
+  hipLaunchKernelGGL(key_kernel, dim3(b.nblk[TB_CAPS]), dim3(kCapsBlock), 0, st, CD, b.tab[TB_CAPS]);
   hipLaunchKernelGGL(scan_kernel, dim3(b.nblk[TB_SCAN_T]), blk, 0, st, CD, b.tab[TB_SCAN_T]);
-  hipLaunchKernelGGL(bucket_scatter_kernel, dim3(b.nblk[TB_CAPS]), blk, 0, st, CD, b.tab[TB_CAPS]);
+  hipLaunchKernelGGL(bucket_scatter_kernel, dim3(b.nblk[TB_CAPS]), dim3(kCapsBlock), 0, st, CD, b.tab[TB_CAPS]);
   hipLaunchKernelGGL(pair_kernel, dim3(b.nblk[TB_SEARCH]), blk, 0, st, CD, b.tab[TB_SEARCH]);
   return hipGetLastError();
 }
