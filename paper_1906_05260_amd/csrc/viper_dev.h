@@ -169,7 +169,7 @@ enum Stage {
   TB_WAVES = 0,   // 4 wavefronts (<= 512 pill slots) per block: rod kernels
   TB_CAPS,        // 256 capsules per block
   TB_SEARCH,      // 28 capsules per block, 9 threads each: neighbour search
-  TB_PAIRS,       // 256 lanes per block, two per candidate pair, 2 pair_span(cap) lanes per scene
+  TB_PAIRS,       // 64 lanes per block, two per candidate pair, 2 pair_span(cap) lanes per scene
   TB_SCAN_T,      // 1024 cells per block (cell scan)
   TB_DET,         // 256 of max(pills, cells, capsules) per block: contact flush
   TB_SECT,        // 4 bundling sections per block (one wavefront each)
