@@ -186,7 +186,9 @@ viper_status viper_set_state(viper_scene scene, int32_t which, const void* src, 
 
 /* Candidate contact pairs of the last substep's detection (Sec. 7.1): sorted (a, b),
  * a < b, capsule ids; written to device or host `pairs` [cap*2]; *n receives the count
- * (synchronises `stream`).  VIPER_ERR_NO_CAPACITY if n > cap (nothing written). */
+ * (synchronises `stream`).  VIPER_ERR_NO_CAPACITY if n > cap (nothing written).  After a
+ * detection that overflowed the scene's pair capacity (reported by viper_sync) the list
+ * holds capacity-many of the candidates, which ones depending on the order of the search. */
 viper_status viper_get_contacts(viper_scene scene, int32_t* pairs, int32_t cap, int32_t* n, void* stream);
 
 /* Record of the last contact detection of a scene (Sec. 7.1 uniform grid, in two levels).

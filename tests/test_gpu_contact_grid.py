@@ -8,6 +8,9 @@ with its detection skipped.  Checked here:
 - seeded clouds of free capsules with mixed bounding radii (small, a few percent several
   times larger, and some far larger than the rest): whatever split of fine level, coarse
   level and list the histogram picks, the candidate set equals the oracle's brute force;
+- a cloud packed so tightly that it has more candidates than capsules: with room for them the
+  list equals the brute force; with room for one per capsule the detection reports the
+  overflow and keeps that many true candidates, each once;
 - many moderately stretched capsules (more than the list holds): they form a coarse level,
   the fine cell width stays that of the intact scene, the walk stays below what one grid
   sized by the stretched capsules would examine, and the candidate set equals the oracle's
@@ -170,6 +173,37 @@ def test_capsule_clouds_with_mixed_radii(prec, seed):
     assert len(ref) > 0
     assert np.array_equal(got, ref)
     sc.sync()
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_overflowing_pair_list_keeps_true_candidates(prec):
+    """A capsule cloud packed 4x tighter than the one above has several candidates per capsule:
+    with room for 16 per capsule the list equals the brute force; with room for one per capsule
+    the detection overflows, viper_sync reports it, and the list holds exactly that many
+    candidates, each a true one, each once (which ones depends on the order of the search)."""
+    desc = capsule_cloud(7)
+    c = desc.rest_pos.mean(axis=0)
+    desc.rest_pos[:] = c + 0.25 * (desc.rest_pos - c)
+    roomy = viper.Scene(desc, prec)
+    roomy.step(1e-5, 1, 0)
+    roomy.sync()
+    ref = oracle_pairs(desc, roomy)
+    E = desc.num_pills - desc.num_rods
+    say(prec, "packed cloud:", E, "capsules", len(ref), "pairs")
+    assert E < len(ref) <= 16 * E
+    assert np.array_equal(roomy.contacts(), ref)
+    tight = viper.Scene(desc, prec, capacity=1)
+    tight.step(1e-5, 1, 0)
+    with pytest.raises(viper.ViperError) as ei:
+        tight.sync()
+    assert ei.value.status == viper.ERR_CAPACITY
+    kept = tight.contacts()
+    full = oracle_pairs(desc, tight)
+    say("kept", len(kept), "of", len(full))
+    assert len(kept) == E
+    kept_set = {tuple(r) for r in kept.tolist()}
+    assert len(kept_set) == E
+    assert kept_set <= {tuple(r) for r in full.tolist()}
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
