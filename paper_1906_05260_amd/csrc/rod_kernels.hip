@@ -172,12 +172,13 @@ __device__ __forceinline__ void detect_start_wave(const Dev<T>& d, const Contact
 
 // C: the scenes have contacts (the prediction starts their detection).
 template <class T, bool C>
-__global__ void __launch_bounds__(256) predict_kernel(const Dev<T>* __restrict__ D, const WaveBlk* __restrict__ wtab, T h,
+__global__ void __launch_bounds__(256) predict_kernel(const char* __restrict__ wrec, int stride, T h,
                                                       const ContactDev* __restrict__ CD) {
   Lane2<T> P;
   int pA, pB;
-  const WaveBlk b = wtab[blockIdx.x];
-  const Dev<T> d = D[b.scene];
+  const char* rec = wrec + (size_t)blockIdx.x * stride;
+  const WaveBlk b = ((const WaveRec*)rec)->b;
+  const Dev<T> d = *(const Dev<T>*)(rec + sizeof(WaveRec));
   __shared__ int s_hist[kRadBins + 1];
   __shared__ unsigned long long s_hmax[kRadBins];
   asm volatile("" ::"s"(d.gx), "s"(d.gy), "s"(d.gz), "s"(h));
@@ -331,17 +332,19 @@ __device__ __forceinline__ void jacobi_lane(Lane2<T>& P) {
 
 // C: the scenes have contacts (CD holds their buffers).
 template <class T, bool X, bool EVEN, bool C>
-__global__ void __launch_bounds__(256) rod_iteration_kernel(const Dev<T>* __restrict__ D, const WaveBlk* __restrict__ wtab,
-                                                            T h, const ContactDev* __restrict__ CD) {
+__global__ void __launch_bounds__(256) rod_iteration_kernel(const char* __restrict__ wrec, int stride, T h,
+                                                            const ContactDev* __restrict__ CD) {
   Lane2<T> P;
   int pA, pB;
-  const WaveBlk b = wtab[blockIdx.x];
-  const Dev<T> d = D[b.scene];
+  const char* rec = wrec + (size_t)blockIdx.x * stride;
+  const WaveRec wr = *(const WaveRec*)rec;
+  const WaveBlk b = wr.b;
+  const Dev<T> d = *(const Dev<T>*)(rec + sizeof(WaveRec));
   int32_t* acnt = nullptr;
   unsigned long long* acc = nullptr;
   if constexpr (C) {
-    acnt = CD[b.scene].acnt;
-    acc = CD[b.scene].acc;
+    acnt = wr.acnt;
+    acc = wr.acc;
   }
   // the scalars read after the state are requested with the pointers (an empty statement
   // that takes them as operands), not in a round trip of their own later
@@ -393,17 +396,19 @@ __device__ __forceinline__ void velocity_store(const Dev<T>& d, Slot<T>& L, int 
 // wavefronts: a rod lies in one wavefront, and no contact correction is pending before the
 // first iteration (this launch has just applied and cleared the last ones).
 template <class T, bool C, int NEXT, bool X, bool EVEN>
-__global__ void __launch_bounds__(256) velocity_kernel(const Dev<T>* __restrict__ D, const WaveBlk* __restrict__ wtab, T h,
+__global__ void __launch_bounds__(256) velocity_kernel(const char* __restrict__ wrec, int stride, T h,
                                                        const ContactDev* __restrict__ CD) {
   Lane2<T> P;
   int pA, pB;
-  const WaveBlk b = wtab[blockIdx.x];
-  const Dev<T> d = D[b.scene];
+  const char* rec = wrec + (size_t)blockIdx.x * stride;
+  const WaveRec wr = *(const WaveRec*)rec;
+  const WaveBlk b = wr.b;
+  const Dev<T> d = *(const Dev<T>*)(rec + sizeof(WaveRec));
   int32_t* acnt = nullptr;
   unsigned long long* acc = nullptr;
   if constexpr (C) {
-    acnt = CD[b.scene].acnt;
-    acc = CD[b.scene].acc;
+    acnt = wr.acnt;
+    acc = wr.acc;
   }
   __shared__ int s_hist[kRadBins + 1];
   __shared__ unsigned long long s_hmax[kRadBins];
@@ -597,21 +602,21 @@ template <class T> hipError_t launch_rod_frame(const BatchDev& b, int nsub, doub
 template <class T> hipError_t launch_predict(const BatchDev& b, double h, const ContactDev* cd, hipStream_t st) {
   if (b.nblk[TB_WAVES] == 0) return hipSuccess;
   if (cd)
-    hipLaunchKernelGGL((predict_kernel<T, true>), dim3(b.nwaves), dim3(64), 0, st, (const Dev<T>*)b.dev, b.wtab, (T)h,
+    hipLaunchKernelGGL((predict_kernel<T, true>), dim3(b.nwaves), dim3(64), 0, st, b.wrec, b.wrec_stride, (T)h,
                        cd);
   else
-    hipLaunchKernelGGL((predict_kernel<T, false>), dim3(b.nwaves), dim3(64), 0, st, (const Dev<T>*)b.dev, b.wtab, (T)h,
+    hipLaunchKernelGGL((predict_kernel<T, false>), dim3(b.nwaves), dim3(64), 0, st, b.wrec, b.wrec_stride, (T)h,
                        cd);
   return hipGetLastError();
 }
 template <class T, bool X, bool EVEN>
 void launch_rod_iteration_as(const BatchDev& b, double h, const ContactDev* cd, hipStream_t st) {
   if (cd)
-    hipLaunchKernelGGL((rod_iteration_kernel<T, X, EVEN, true>), dim3(b.nwaves), dim3(64), 0, st, (const Dev<T>*)b.dev,
-                       b.wtab, (T)h, cd);
+    hipLaunchKernelGGL((rod_iteration_kernel<T, X, EVEN, true>), dim3(b.nwaves), dim3(64), 0, st, b.wrec,
+                       b.wrec_stride, (T)h, cd);
   else
-    hipLaunchKernelGGL((rod_iteration_kernel<T, X, EVEN, false>), dim3(b.nwaves), dim3(64), 0, st, (const Dev<T>*)b.dev,
-                       b.wtab, (T)h, cd);
+    hipLaunchKernelGGL((rod_iteration_kernel<T, X, EVEN, false>), dim3(b.nwaves), dim3(64), 0, st, b.wrec,
+                       b.wrec_stride, (T)h, cd);
 }
 template <class T> hipError_t launch_rod_iteration(const BatchDev& b, double h, const ContactDev* cd, hipStream_t st) {
   if (b.nblk[TB_WAVES] == 0) return hipSuccess;
@@ -626,7 +631,7 @@ template <class T> hipError_t launch_rod_iteration(const BatchDev& b, double h, 
 }
 template <class T, bool C, int NEXT, bool X, bool EVEN>
 void launch_velocity_as(const BatchDev& b, double h, const ContactDev* cd, hipStream_t st) {
-  hipLaunchKernelGGL((velocity_kernel<T, C, NEXT, X, EVEN>), dim3(b.nwaves), dim3(64), 0, st, (const Dev<T>*)b.dev, b.wtab,
+  hipLaunchKernelGGL((velocity_kernel<T, C, NEXT, X, EVEN>), dim3(b.nwaves), dim3(64), 0, st, b.wrec, b.wrec_stride,
                      (T)h, cd);
 }
 template <class T, bool C>

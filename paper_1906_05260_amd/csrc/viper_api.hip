@@ -238,6 +238,8 @@ int stage_items(const Counts& c, int stage) {
 }
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+// Bytes of one wavefront launch record: WaveRec, then the scene's Dev, in whole cache lines.
+size_t wave_rec_bytes(size_t dev_size) { return (sizeof(WaveRec) + dev_size + 63) & ~size_t(63); }
 
 // Bytes of the device header of a batch: Dev structs, ContactDev structs, block tables.
 size_t header_bytes(const std::vector<Counts>& v, size_t dev_size) {
@@ -249,7 +251,7 @@ size_t header_bytes(const std::vector<Counts>& v, size_t dev_size) {
   }
   size_t w = 0;
   for (const Counts& c : v) w += (size_t)c.W;
-  n += align256(w * sizeof(WaveBlk));
+  n += align256(w * wave_rec_bytes(dev_size));
   return n;
 }
 
@@ -274,15 +276,23 @@ void build_header(std::vector<char>& buf, const std::vector<const void*>& devs, 
     b.nblk[t] = (int)tab.size();
     off += align256(tab.size() * sizeof(Blk));
   }
-  std::vector<WaveBlk> wt;
+  const size_t rs = wave_rec_bytes(dev_size);
+  size_t k = 0;
   for (size_t s = 0; s < v.size(); ++s) {
     const std::vector<int32_t>& ws = *v[s].wave_start;
-    for (int w = 0; w < v[s].W; ++w) wt.push_back(WaveBlk{(int32_t)s, w, ws[w], ws[w + 1] - ws[w]});
+    for (int w = 0; w < v[s].W; ++w, ++k) {
+      WaveRec r{};
+      r.b = WaveBlk{(int32_t)s, w, ws[w], ws[w + 1] - ws[w]};
+      r.acc = s < cds.size() ? cds[s].acc : nullptr;
+      r.acnt = s < cds.size() ? cds[s].acnt : nullptr;
+      std::memcpy(buf.data() + off + k * rs, &r, sizeof(WaveRec));
+      std::memcpy(buf.data() + off + k * rs + sizeof(WaveRec), devs[s], dev_size);
+    }
   }
-  std::memcpy(buf.data() + off, wt.data(), wt.size() * sizeof(WaveBlk));
-  b.wtab = (const WaveBlk*)(dev_base + off);
-  b.nwaves = (int)wt.size();
-  off += align256(wt.size() * sizeof(WaveBlk));
+  b.wrec = dev_base + off;
+  b.wrec_stride = (int)rs;
+  b.nwaves = (int)k;
+  off += align256(k * rs);
   b.nscenes = (int)v.size();
 }
 
@@ -1018,7 +1028,7 @@ viper_status viper_set_floor(viper_scene S, const double* normal, double offset,
   const double l = std::sqrt(normal[0] * normal[0] + normal[1] * normal[1] + normal[2] * normal[2]);
   for (int i = 0; i < 3; ++i) S->floor_n[i] = normal[i] / l;
   S->floor_d = offset / l;
-  // the scene record lives at the start of the device header: update it there, in stream order
+  // the scene record lives at the start of the device header: update it there, in stream order ...
   size_t dsz;
   if (S->precision == VIPER_F64) {
     S->dd.fnx = S->floor_n[0]; S->dd.fny = S->floor_n[1]; S->dd.fnz = S->floor_n[2]; S->dd.fd = S->floor_d;
@@ -1029,7 +1039,12 @@ viper_status viper_set_floor(viper_scene S, const double* normal, double offset,
     dsz = sizeof(Dev<float>);
     std::memcpy(S->header.data(), &S->df, dsz);
   }
-  HIP_TRY(hipMemcpyAsync(S->ws + S->o.header, S->header.data(), dsz, hipMemcpyHostToDevice, (hipStream_t)stream));
+  // ... and in every wavefront's launch record, which carries a copy of it
+  const size_t rec0 = (size_t)(S->batch.wrec - (S->ws + S->o.header));
+  for (int k = 0; k < S->batch.nwaves; ++k)
+    std::memcpy(S->header.data() + rec0 + (size_t)k * S->batch.wrec_stride + sizeof(WaveRec), S->header.data(), dsz);
+  HIP_TRY(hipMemcpyAsync(S->ws + S->o.header, S->header.data(), S->header.size(), hipMemcpyHostToDevice,
+                         (hipStream_t)stream));
   return VIPER_OK;
 }
 

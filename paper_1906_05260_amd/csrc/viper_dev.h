@@ -165,6 +165,15 @@ struct WaveBlk {
   int32_t scene, wave, p0, n;
 };
 
+// The launch record of such a wavefront: its WaveBlk and its scene's contact sums (null without
+// contacts), followed in memory by a copy of its scene's Dev (in the batch's precision), so that
+// a block starts with reads that depend on nothing but its index.
+struct WaveRec {
+  WaveBlk b;
+  unsigned long long* acc;
+  int32_t* acnt;
+};
+
 enum Stage {
   TB_WAVES = 0,   // 4 wavefronts (<= 512 pill slots) per block: rod kernels
   TB_CAPS,        // 256 capsules per block
@@ -189,7 +198,8 @@ struct BatchDev {
   const ContactDev* cd = nullptr;     // ContactDev[nscenes] in device memory (contact batches)
   const Blk* tab[TB_COUNT] = {};
   int nblk[TB_COUNT] = {};
-  const WaveBlk* wtab = nullptr;      // every wavefront of every scene, in scene order
+  const char* wrec = nullptr;         // WaveRec + Dev of every wavefront of every scene, in scene order
+  int wrec_stride = 0;                // bytes per record
   int nwaves = 0;
   bool extras = false;                // some scene uses an optional constraint term (the rod
                                       // kernels' instantiation with them compiled in)
