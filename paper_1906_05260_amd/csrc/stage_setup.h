@@ -8,9 +8,9 @@ namespace viper {
 // The per-stage kernels run one wavefront per block, so that a scene of a few hundred
 // wavefronts spreads over every compute unit.  Such a launch is mostly the chain of dependent
 // reads a wavefront waits for before its work, so its start is laid out for few round trips to
-// memory: the caller copies the scene's fields into registers in one go (they sit behind the
-// block's table entry) and names the scalars it reads later in an empty statement, so that they
-// come with them; the start has no branch; the slot flags are read unconditionally (an empty
+// memory: the caller copies the scene's fields into registers in one go (a copy of them sits in
+// the wavefront's launch record, or behind the block's table entry) and names the scalars it
+// reads later in an empty statement, so that they come with them; the start has no branch; the slot flags are read unconditionally (an empty
 // slot reads its wave's first pill, which exists), and the per-pill reads that follow depend on
 // the wave's range only.  This form takes the wave index of a 4-wavefront block table entry
 // (block b: wavefront tab[b / 4].base + b % 4; a wavefront past the scene's last reads that
@@ -32,8 +32,8 @@ __device__ __forceinline__ void stage_setup(const Dev<T>& d, int wave, Lane2<T>&
   P.vb = __any(((P.A.f | P.B.f) & F_VB) != 0u) != 0;
 }
 
-// The same start from the wavefront's entry of the batch's wave table (its pill range comes
-// with it: no read of the scene's wave table before the per-pill reads).
+// The same start from the wavefront's launch record (its pill range comes with it: no read of
+// the scene's wave table before the per-pill reads).
 template <class T>
 __device__ __forceinline__ void stage_setup(const Dev<T>& d, const WaveBlk& wb, Lane2<T>& P, int& pA, int& pB) {
   const int lane = (int)(threadIdx.x & 63);
